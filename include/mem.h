@@ -1,0 +1,276 @@
+/*
+ * mem.h - C ABI of the MI355X multi-modal elevation map update.
+ *
+ * The library implements the per-frame map update of "MEM: Multi-Modal
+ * Elevation Mapping for Robotics and Learning" (Erni et al., 2023):
+ *   - a robot-centric 2.5D grid (abstract; Sec. II-B) that follows the robot,
+ *   - point clouds associated to cells by their horizontal coordinates and
+ *     fused into the height/variance layers (Sec. III-B), with the
+ *     "height update & ray cast" stage of Table I clearing cells that a
+ *     sensor ray passes below,
+ *   - the extra point fields and the channels of camera images fused into
+ *     task-agnostic layers with one of four rules (Sec. III-C, Eq. (1)-(12)),
+ *   - images associated by projecting every cell into the camera with a
+ *     Bresenham occlusion test against the map heights (Sec. III-B, Fig. 3).
+ *
+ * Conventions shared by every entry point
+ *   - Every call is asynchronous on the HIP stream passed as `stream`
+ *     (a hipStream_t; NULL is the null stream).  Apart from mem_create,
+ *     mem_destroy, mem_get_stats and mem_profile_read the library never
+ *     synchronises the host with the device.
+ *   - Array arguments named "device" are caller-owned device memory (for
+ *     example the data_ptr() of a torch tensor).  They are read or written
+ *     only by work enqueued on `stream`; the caller keeps them alive until
+ *     that work has completed.  The library keeps no pointer after a call
+ *     returns.  Arguments named "host" are read during the call only.
+ *   - Poses are row-major 3x4 float matrices [R | t] (12 floats, host) that
+ *     map a point from the sensor (or camera) frame into the map frame:
+ *     p_map = R p_sensor + t.  R must be orthonormal to 1e-4.
+ *   - The map frame is the world frame, z up.  The grid is axis-aligned and
+ *     only translates (robot-centric map).  Cell (ix, iy) of a W x H grid with
+ *     centre cell (cx, cy) covers x in [(cx - W/2 + ix) res, (cx - W/2 + ix + 1) res),
+ *     likewise in y; W/2 is integer division.  Layer read-outs are
+ *     row-major [H][W][C] with row iy and column ix.
+ *   - Errors: every argument is validated on the host before anything is
+ *     enqueued, so a call that returns an error leaves the map untouched.
+ *     A HIP launch or runtime error returns MEM_E_HIP and is sticky: every
+ *     later call on the same map returns MEM_E_STATE.  mem_last_error()
+ *     returns a message for the calling thread's last failure.
+ *   - A map handle is not thread-safe; distinct handles are independent.
+ *
+ * Decisions (which cell a point falls in, which cells a ray crosses, the
+ * visibility and pixel of a cell) are evaluated in binary32 with a fixed
+ * operation order and no fused multiply-add; the exact formulas are written
+ * next to each entry point.  Values (heights, variances, layer contents) are
+ * binary32 with binary32 accumulation unless a layer's storage says otherwise.
+ */
+#ifndef MEM_H
+#define MEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mem_map mem_map; /* opaque, library-owned */
+typedef int32_t mem_status;
+
+enum {
+    MEM_OK = 0,
+    MEM_E_ARG = -1,         /* invalid argument; nothing was enqueued          */
+    MEM_E_NOMEM = -2,       /* device allocation failed                         */
+    MEM_E_HIP = -3,         /* a HIP call failed; the map is now unusable       */
+    MEM_E_STATE = -4,       /* the map saw an earlier MEM_E_HIP                 */
+    MEM_E_UNSUPPORTED = -5  /* a valid request this build does not implement   */
+};
+
+/* Fusion rules, Sec. III-C.  `param` of the layer descriptor means:
+ *   MEM_LATEST     (Sec. III-C.2, Eq. (1)): unused.
+ *   MEM_EXPAVG     (Sec. III-C.3, Eq. (2)): the weight w in (0, 1].
+ *   MEM_GAUSS      (Sec. III-C.4, Eq. (6)-(7)): the measurement variance
+ *                  sigma_f^2 > 0, one value for every dimension.
+ *   MEM_DIRICHLET  (Sec. III-C.5, Eq. (11)-(12)): the initial concentration
+ *                  alpha_0 > 0 of every class. */
+enum { MEM_LATEST = 0, MEM_EXPAVG = 1, MEM_GAUSS = 2, MEM_DIRICHLET = 3 };
+
+/* Element types.  Layer storage may be MEM_F32, MEM_BF16 or MEM_FP8_E4M3
+ * (LATEST, EXPAVG and GAUSS layers); images may be MEM_F32 or MEM_U8
+ * (u8 values are divided by 255). */
+enum { MEM_F32 = 0, MEM_BF16 = 1, MEM_FP8_E4M3 = 2, MEM_U8 = 3 };
+
+/* Layer ids.  User layers are numbered MEM_LAYER_USER0 + k in the order of
+ * mem_params.layers. */
+enum {
+    MEM_LAYER_ELEVATION = 0, /* h; NaN where the cell holds no height        */
+    MEM_LAYER_VARIANCE = 1,  /* v of the height estimate; NaN where invalid   */
+    MEM_LAYER_VALID = 2,     /* 1 where the cell holds a height, else 0      */
+    MEM_LAYER_HITS = 3,      /* points fused into the cell by the last cloud  */
+    MEM_LAYER_CLEAR = 4,     /* clearing votes cast by the last cloud's rays  */
+    MEM_LAYER_USER0 = 8
+};
+
+/* Views of a layer for mem_get_layer / mem_set_layer. */
+enum {
+    MEM_VIEW_VALUE = 0,  /* theta (LATEST, EXPAVG; NaN = never observed), mu
+                            (GAUSS; NaN = never observed), alpha / sum(alpha)
+                            (DIRICHLET, Eq. (11)), or the built-in layer    */
+    MEM_VIEW_AUX = 1,    /* sigma^2 (GAUSS, one per cell; +inf = never
+                            observed) or alpha (DIRICHLET)                   */
+    MEM_VIEW_ARGMAX = 2  /* DIRICHLET: index of the largest alpha, the lowest
+                            index on ties (read-only)                        */
+};
+
+typedef struct mem_layer_desc {
+    int32_t channels;       /* C >= 1 (classes K for DIRICHLET, dimension d for GAUSS) */
+    int32_t rule;           /* MEM_LATEST .. MEM_DIRICHLET                      */
+    int32_t storage;        /* MEM_F32, MEM_BF16 or MEM_FP8_E4M3                */
+    float param;            /* see the rule enum                                */
+    const float* ch_scale;  /* host, C floats or NULL: FP8 per-channel amax
+                               (code = value / (amax / 448)); NULL means 1.0   */
+} mem_layer_desc;
+
+typedef struct mem_params {
+    int32_t width, height;   /* W, H cells, 1 .. 16384 each                      */
+    float resolution;        /* cell side in metres, > 0                          */
+    float noise_c0, noise_c1;/* point noise: sigma = c0 + c1 r^2, v = sigma^2,
+                                r the range in the sensor frame                   */
+    float max_range;         /* points with r^2 > max_range^2 are dropped         */
+    float clear_margin;      /* delta of the clearing test, metres                */
+    int32_t clear_min_count; /* votes a cell needs to be cleared; 0 disables rays */
+    float min_depth;         /* a cell is in a camera's view only if Z > this     */
+    int32_t n_layers;        /* user layers, 0 .. 32                              */
+    const mem_layer_desc* layers; /* host, n_layers entries                       */
+} mem_params;
+
+/* Binds input channels [ch_first, ch_first + ch_count) of a point cloud or an
+ * image to a user layer with exactly ch_count channels (Sec. III-C: the user
+ * chooses the target layer of every input source). */
+typedef struct mem_binding {
+    int32_t layer;    /* MEM_LAYER_USER0 + k */
+    int32_t ch_first;
+    int32_t ch_count;
+} mem_binding;
+
+/* Counters accumulated by the device since the last mem_reset_stats. */
+typedef struct mem_stats {
+    int64_t points_in;          /* points passed to mem_input_pointcloud        */
+    int64_t points_accepted;    /* fused into a cell                             */
+    int64_t dropped_nonfinite;  /* a coordinate was NaN or infinite              */
+    int64_t dropped_range;      /* r^2 > max_range^2                             */
+    int64_t dropped_outside;    /* fell outside the grid                         */
+    int64_t cells_touched;      /* (cell, cloud) pairs with at least one point   */
+    int64_t cells_cleared;      /* cells invalidated by clearing votes           */
+    int64_t ray_cells;          /* cells visited by clearing rays                */
+    int64_t cells_in_view;      /* (cell, image) pairs inside the camera frustum */
+    int64_t pairs_visible;      /* (cell, image) pairs fused (not occluded)      */
+    int64_t occl_cells;         /* cells visited by occlusion rays               */
+} mem_stats;
+
+/* Creates a map centred on cell (0, 0) with every cell empty: no height,
+ * LATEST/EXPAVG/GAUSS layers never observed, DIRICHLET alpha = alpha_0.
+ * Allocates the map state on the current HIP device.  `layers` and
+ * `ch_scale` are copied.  Synchronises `stream` before returning. */
+mem_status mem_create(const mem_params* params, void* stream, mem_map** out);
+
+/* Frees the map after synchronising `stream`.  NULL is a no-op. */
+mem_status mem_destroy(mem_map* map, void* stream);
+
+/* Re-centres the robot-centric grid on the robot at (x, y) (abstract: the map
+ * follows the robot).  The new centre cell is (floor(x * inv_res),
+ * floor(y * inv_res)) in binary32 with inv_res = (float)(1.0 / (double)res);
+ * content moves by whole cells and cells that enter the grid are reset to
+ * empty.  The device does O(cells entering the grid) work. */
+mem_status mem_move(mem_map* map, float x, float y, void* stream);
+
+/* Fuses one point cloud (Sec. III-B, first paragraph; Sec. III-C; Table I
+ * rows "point trsf." and "height update & ray cast").
+ *   xyz    device, n x 3 float, row-major, sensor frame.
+ *   n      number of points, >= 0 (0 is a no-op apart from clearing the
+ *          hits/clear layers).
+ *   ch     device, n x c float, row-major, or NULL if c == 0.
+ *   bind   host, n_bind bindings of point channels to user layers.
+ *   T_map_sensor  host, 12 floats.
+ * Per point, in binary32 (R = rotation, t = translation of T_map_sensor):
+ *   dropped if x, y or z is not finite;
+ *   r2 = (x*x + y*y) + z*z, dropped if r2 > max_range * max_range;
+ *   p = ((R[k][0]*x + R[k][1]*y) + R[k][2]*z) + t[k];
+ *   gx = floor(p.x * inv_res), dropped unless cx - W/2 <= gx < cx - W/2 + W
+ *   (same for y); variance v = (c0 + c1 r2)^2.
+ * Per cell j with N_j accepted points, information-form Gaussian fusion:
+ *   valid prior:  v' = 1 / (1/v + sum 1/v_i),  h' = v' (h/v + sum z_i/v_i);
+ *   empty prior:  N_j == 1 -> (h', v') = (z_i, v_i) exactly,
+ *                 else     -> v' = 1 / sum 1/v_i, h' = v' sum z_i/v_i.
+ * Clearing (if clear_min_count > 0): the ray of every accepted point runs
+ * from the sensor's cell to the point's cell along Bresenham's line; each
+ * cell strictly between them that held a height before this call receives a
+ * vote when h_k > z_ray + clear_margin, z_ray = s_z + (p_z - s_z) t_k and
+ * t_k = (centre_k - s) * (1 / (p - s)) along the line's major axis.  A cell
+ * with no point in this call and at least clear_min_count votes loses its
+ * height.
+ * Bound channels: per cell the mean a = (1/N_j) sum m_i (Eq. (1)) is fused by
+ * LATEST, EXPAVG (Eq. (2); the first observation sets theta = a) and GAUSS
+ * (Eq. (6)-(7) with N = N_j); DIRICHLET adds sum m_i to alpha (Eq. (12)).
+ * GAUSS and DIRICHLET layers fed by point clouds must use MEM_F32 storage. */
+mem_status mem_input_pointcloud(mem_map* map, const float* xyz, int64_t n,
+                                const float* ch, int32_t c,
+                                const mem_binding* bind, int32_t n_bind,
+                                const float T_map_sensor[12], void* stream);
+
+/* Fuses one multi-modal image (Sec. III-B, second paragraph; Fig. 3).
+ *   img      device, element (row, col, k) at img[row*strides[0] +
+ *            col*strides[1] + k*strides[2]] (strides in elements, >= 0).
+ *   dtype    MEM_F32 or MEM_U8.
+ *   h, w, c  image size and channel count.
+ *   K        host, {fx, fy, cx, cy} of a pinhole camera whose pixel centres
+ *            sit at integer coordinates.
+ *   T_map_cam host, 12 floats; camera axes x right, y down, z forward.
+ * For every cell holding a height, in binary32 with (R, t) = T_map_cam:
+ *   centre xc = ((float)(cx - W/2 + ix) + 0.5f) * res (same for yc),
+ *   d = (xc - t.x, yc - t.y, h - t.z),
+ *   X = (R[0][0] d.x + R[1][0] d.y) + R[2][0] d.z, likewise Y, Z (R^T d),
+ *   in view iff Z > min_depth and 0 <= floor(u + 0.5) < w, 0 <= floor(v + 0.5) < h,
+ *   u = (fx * X) / Z + cx, v = (fy * Y) / Z + cy;
+ *   visible iff every cell strictly between the camera's cell and the cell
+ *   on Bresenham's line that holds a height is below the ray:
+ *   h_k < t.z + (h - t.z) t_k (strict, as in Sec. III-B).
+ * A visible cell fuses the pixel's bound channels with its layer's rule and
+ * N_j = 1. */
+mem_status mem_input_image(mem_map* map, const void* img, int32_t dtype,
+                           int32_t h, int32_t w, int32_t c,
+                           const int64_t strides[3], const float K[4],
+                           const float T_map_cam[12],
+                           const mem_binding* bind, int32_t n_bind,
+                           void* stream);
+
+/* Writes a layer view to `out` (device, H x W x C float, C = 1 for the
+ * built-in layers and for MEM_VIEW_ARGMAX).  See the view enum. */
+mem_status mem_get_layer(const mem_map* map, int32_t layer, int32_t view,
+                         float* out, void* stream);
+
+/* Overwrites a layer view from `in` (device, same layout as mem_get_layer).
+ * Settable: ELEVATION/VALUE (NaN = no height), VARIANCE/VALUE, user
+ * LATEST/EXPAVG/GAUSS VALUE, GAUSS AUX and DIRICHLET AUX.  Used to restore a
+ * saved map and by tests. */
+mem_status mem_set_layer(mem_map* map, int32_t layer, int32_t view,
+                         const float* in, void* stream);
+
+/* Current centre cell of the grid (host values; no device work). */
+mem_status mem_get_center(const mem_map* map, int32_t* cx, int32_t* cy);
+
+/* Debug exports, same decisions as the update.
+ * mem_debug_point_cells: out (device, n int32) = iy*W + ix of each point's
+ *   cell, or -1 non-finite, -2 out of range, -3 outside the grid.
+ * mem_debug_cell_pixels: out (device, H*W int32, logical cell order) =
+ *   row*w + col of each cell's pixel, -1 no height, -2 outside the view,
+ *   -3 occluded. */
+mem_status mem_debug_point_cells(const mem_map* map, const float* xyz, int64_t n,
+                                 const float T_map_sensor[12], int32_t* out,
+                                 void* stream);
+mem_status mem_debug_cell_pixels(const mem_map* map, int32_t h, int32_t w,
+                                 const float K[4], const float T_map_cam[12],
+                                 int32_t* out, void* stream);
+
+/* Statistics (synchronises `stream`). */
+mem_status mem_get_stats(mem_map* map, mem_stats* out, void* stream);
+mem_status mem_reset_stats(mem_map* map, void* stream);
+
+/* Per-kernel timing with HIP events recorded on `stream` around every launch
+ * while enabled.  mem_profile_read synchronises and returns, per kernel
+ * name, the number of launches and the summed milliseconds. */
+typedef struct mem_kernel_time {
+    char name[32];
+    int64_t launches;
+    double total_ms;
+} mem_kernel_time;
+mem_status mem_profile_enable(mem_map* map, int32_t on);
+mem_status mem_profile_read(mem_map* map, mem_kernel_time* out, int32_t max,
+                            int32_t* count);
+
+/* Message of the calling thread's last failure ("" if none). */
+const char* mem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MEM_H */

@@ -1,0 +1,419 @@
+"""Seeded synthetic terrain and sensor data.
+
+This module only simulates the world and the sensors: a height field, a
+robot walking over it, LiDAR / depth-camera point clouds and camera images.
+It holds none of the map update's arithmetic (no cell association, no
+fusion) and is shared by the tests, the benchmark and the smoke check.
+
+Workloads (sizes follow the paper's scales: a ~10 m robot-centric grid at
+4 cm, hundreds of thousands of points per cloud, Table I and Table II):
+
+* ``small``  - 200x200 cells at 0.04 m, 10 frames, one 20k-point cloud per
+  frame sampled on the terrain within 4 m (4 Dirichlet(1) class channels per
+  point), one 320x240 camera with an RGB u8 image and an 8-class image.
+* ``full``   - 500x500 cells at 0.04 m, a 128x2048 LiDAR and four 640x480
+  depth cameras per frame (~1.49M points), four RGB cameras each with an RGB
+  u8 image, a 160x120x64 unit-norm feature image and a 20-class image.
+
+Terrain: a sum of 8 random sinusoids (amplitudes summing to 0.3 m,
+wavelengths 1-8 m) plus 5 boxes 0.2-1.0 m wide and 0.05-0.5 m tall.  The
+robot takes steps of at most 0.1 m and 5 degrees.  Point noise is added along
+world z with sigma = 0.01 + 0.001 r^2 (r the range to the sensor).  All
+random numbers come from numpy PCG64 seeded per workload; ray casting of the
+terrain may run on a torch device but draws no random numbers.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+try:  # torch is optional here: ray casting falls back to numpy
+    import torch
+except Exception:  # pragma: no cover
+    torch = None
+
+
+# --------------------------------------------------------------------------
+# Terrain
+# --------------------------------------------------------------------------
+
+@dataclass
+class Terrain:
+    amp: np.ndarray      # (8,)
+    lam: np.ndarray      # (8,)
+    phi: np.ndarray      # (8,)
+    psi: np.ndarray      # (8,)
+    boxes: np.ndarray    # (nb, 5): centre x, centre y, half-width x, half-width y, height
+    _cache: dict = field(default_factory=dict, repr=False)
+
+    @property
+    def zmax(self) -> float:
+        """Upper bound of the height field."""
+        return float(np.sum(np.abs(self.amp)) + (self.boxes[:, 4].max() if len(self.boxes) else 0.0))
+
+    # -- numpy -------------------------------------------------------------
+    def height(self, x, y):
+        x = np.asarray(x, np.float64)
+        y = np.asarray(y, np.float64)
+        h = np.zeros(np.broadcast(x, y).shape)
+        for a, l, f, p in zip(self.amp, self.lam, self.phi, self.psi):
+            h += a * np.sin(2 * np.pi * (x * np.cos(f) + y * np.sin(f)) / l + p)
+        for bx, by, hx, hy, bh in self.boxes:
+            inside = (np.abs(x - bx) <= hx) & (np.abs(y - by) <= hy)
+            h = np.where(inside, h + bh, h)
+        return h
+
+    def albedo(self, x, y):
+        """RGB in [0, 1]: grass/soil stripes, each box its own colour."""
+        x = np.asarray(x, np.float64)
+        y = np.asarray(y, np.float64)
+        g = 0.5 + 0.25 * np.sin(1.7 * x + 0.3) * np.cos(1.3 * y - 0.2)
+        rgb = np.stack([0.35 + 0.3 * g, 0.45 + 0.35 * (1 - g), 0.2 + 0.1 * g], -1)
+        for k, (bx, by, hx, hy, _) in enumerate(self.boxes):
+            inside = (np.abs(x - bx) <= hx) & (np.abs(y - by) <= hy)
+            col = np.array([0.8 * ((k + 1) % 2), 0.2 + 0.15 * k, 0.9 * (k % 3 == 0)])
+            rgb = np.where(inside[..., None], col, rgb)
+        return np.clip(rgb, 0, 1)
+
+    # -- torch -------------------------------------------------------------
+    def height_t(self, x, y):
+        key = (x.device, x.dtype)
+        if key not in self._cache:
+            t = lambda a: torch.as_tensor(np.asarray(a), device=x.device, dtype=x.dtype)
+            self._cache[key] = (t(self.amp), t(2 * np.pi * np.cos(self.phi) / self.lam),
+                                t(2 * np.pi * np.sin(self.phi) / self.lam), t(self.psi), t(self.boxes))
+        amp, kx, ky, psi, boxes = self._cache[key]
+        h = torch.zeros_like(x)
+        for k in range(amp.shape[0]):
+            h = h + amp[k] * torch.sin(x * kx[k] + y * ky[k] + psi[k])
+        for b in range(boxes.shape[0]):
+            bx, by, hx, hy, bh = boxes[b]
+            inside = ((x - bx).abs() <= hx) & ((y - by).abs() <= hy)
+            h = h + inside.to(x.dtype) * bh
+        return h
+
+
+def make_terrain(rng: np.random.Generator, extent: float, n_waves: int = 8,
+                 n_boxes: int = 5, amplitude: float = 0.3) -> Terrain:
+    a = rng.uniform(0, 1, n_waves)
+    a = amplitude * a / a.sum()
+    lam = rng.uniform(1.0, 8.0, n_waves)
+    phi = rng.uniform(0, 2 * np.pi, n_waves)
+    psi = rng.uniform(0, 2 * np.pi, n_waves)
+    boxes = []
+    while len(boxes) < n_boxes:
+        side = rng.uniform(0.2, 1.0, 2)
+        c = rng.uniform(-extent / 2, extent / 2, 2)
+        if np.hypot(*c) < 0.5 + side.max():  # keep the start clear
+            continue
+        boxes.append([c[0], c[1], side[0] / 2, side[1] / 2, rng.uniform(0.05, 0.5)])
+    return Terrain(a, lam, phi, psi, np.array(boxes).reshape(-1, 5))
+
+
+# --------------------------------------------------------------------------
+# Poses
+# --------------------------------------------------------------------------
+
+def rot_z(yaw: float) -> np.ndarray:
+    c, s = math.cos(yaw), math.sin(yaw)
+    return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+
+
+def camera_rotation(yaw: float, pitch_down: float) -> np.ndarray:
+    """Camera -> map rotation; camera x right, y down, z forward."""
+    cp, sp = math.cos(pitch_down), math.sin(pitch_down)
+    cy, sy = math.cos(yaw), math.sin(yaw)
+    z = np.array([cy * cp, sy * cp, -sp])
+    x = np.array([sy, -cy, 0.0])
+    y = np.cross(z, x)
+    return np.stack([x, y, z], 1)
+
+
+def pose_matrix(R: np.ndarray, t) -> np.ndarray:
+    T = np.zeros((3, 4), np.float32)
+    T[:, :3] = R
+    T[:, 3] = t
+    return T
+
+
+def pose_walk(rng: np.random.Generator, n: int, step: float = 0.1,
+              dyaw_deg: float = 5.0):
+    """Random walk from (0, 0, yaw 0): each step moves up to `step` metres
+    (uniform in a disc) and turns up to `dyaw_deg` degrees."""
+    x = y = yaw = 0.0
+    out = []
+    for i in range(n):
+        if i > 0:
+            r = step * math.sqrt(rng.uniform())
+            a = rng.uniform(0, 2 * np.pi)
+            x += r * math.cos(a)
+            y += r * math.sin(a)
+            yaw += math.radians(rng.uniform(-dyaw_deg, dyaw_deg))
+        out.append((x, y, yaw))
+    return out
+
+
+# --------------------------------------------------------------------------
+# Ray casting the terrain
+# --------------------------------------------------------------------------
+
+def raycast(ter: Terrain, o, d, tmax: float, step: float = 0.04, tmin: float = 0.05,
+            refine: int = 12, device=None):
+    """First hit of rays o + t d (|d| = 1) with the height field, t <= tmax.
+    Returns t (NaN for a miss).  Runs on torch `device` if given."""
+    zmax = ter.zmax
+    if device is not None and torch is not None:
+        dt = torch.float32 if str(device).startswith("cuda") else torch.float64
+        O = torch.as_tensor(np.array(o), device=device, dtype=dt)
+        D = torch.as_tensor(np.array(d), device=device, dtype=dt)
+        f = lambda t: O[:, 2] + t * D[:, 2] - ter.height_t(O[:, 0] + t * D[:, 0], O[:, 1] + t * D[:, 1])
+        lo = torch.full(O.shape[:1], tmin, device=device, dtype=dt)
+        hit = torch.full_like(lo, float("nan"))
+        hi_t = torch.full_like(lo, float("nan"))
+        t = tmin
+        prev_above = f(lo) > 0
+        while t < tmax:
+            t2 = min(t + step, tmax)
+            val = f(torch.full_like(lo, t2))
+            cross = prev_above & (val <= 0) & torch.isnan(hi_t)
+            lo = torch.where(cross, torch.full_like(lo, t), lo)
+            hi_t = torch.where(cross, torch.full_like(lo, t2), hi_t)
+            escaped = (D[:, 2] >= 0) & (O[:, 2] + t2 * D[:, 2] > zmax)
+            prev_above = prev_above & ~cross & ~escaped
+            if not bool(prev_above.any()):
+                break
+            t = t2
+        m = ~torch.isnan(hi_t)
+        a, b = lo[m], hi_t[m]
+        Om, Dm = O[m], D[m]
+        fm = lambda tt: Om[:, 2] + tt * Dm[:, 2] - ter.height_t(Om[:, 0] + tt * Dm[:, 0], Om[:, 1] + tt * Dm[:, 1])
+        for _ in range(refine):
+            c = 0.5 * (a + b)
+            above = fm(c) > 0
+            a = torch.where(above, c, a)
+            b = torch.where(above, b, c)
+        hit[m] = 0.5 * (a + b)
+        return hit.cpu().numpy().astype(np.float64)
+    o = np.asarray(o, np.float64)
+    d = np.asarray(d, np.float64)
+    f = lambda t, idx=slice(None): o[idx, 2] + t * d[idx, 2] - ter.height(o[idx, 0] + t * d[idx, 0], o[idx, 1] + t * d[idx, 1])
+    n = o.shape[0]
+    lo = np.full(n, tmin)
+    hi = np.full(n, np.nan)
+    active = f(lo) > 0
+    t = tmin
+    while t < tmax and active.any():
+        t2 = min(t + step, tmax)
+        idx = np.nonzero(active)[0]
+        val = f(t2, idx)
+        cr = val <= 0
+        lo[idx[cr]] = t
+        hi[idx[cr]] = t2
+        active[idx[cr]] = False
+        gone = (d[idx, 2] >= 0) & (o[idx, 2] + t2 * d[idx, 2] > zmax)
+        active[idx[gone]] = False
+        t = t2
+    m = ~np.isnan(hi)
+    idx = np.nonzero(m)[0]
+    a, b = lo[idx], hi[idx]
+    for _ in range(refine):
+        c = 0.5 * (a + b)
+        above = f(c, idx) > 0
+        a = np.where(above, c, a)
+        b = np.where(above, b, c)
+    out = np.full(n, np.nan)
+    out[idx] = 0.5 * (a + b)
+    return out
+
+
+def segment_clear(ter: Terrain, o, p, samples: int = 32, eps: float = 1e-3) -> np.ndarray:
+    """True where the straight segment from o to each p stays above the
+    terrain (the point is visible from o)."""
+    o = np.asarray(o, np.float64).reshape(1, 3)
+    p = np.asarray(p, np.float64)
+    t = (np.arange(1, samples) / samples).reshape(1, -1)
+    x = o[:, 0:1] + t * (p[:, 0:1] - o[:, 0:1])
+    y = o[:, 1:2] + t * (p[:, 1:2] - o[:, 1:2])
+    z = o[:, 2:3] + t * (p[:, 2:3] - o[:, 2:3])
+    return np.all(ter.height(x, y) < z - eps, axis=1)
+
+
+def add_noise(rng: np.random.Generator, p: np.ndarray, origin, c0=0.01, c1=0.001) -> np.ndarray:
+    r2 = np.sum((p - np.asarray(origin).reshape(1, 3)) ** 2, 1)
+    q = p.copy()
+    q[:, 2] += rng.standard_normal(p.shape[0]) * (c0 + c1 * r2)
+    return q
+
+
+def to_sensor(p_map: np.ndarray, T: np.ndarray) -> np.ndarray:
+    R = T[:, :3].astype(np.float64)
+    t = T[:, 3].astype(np.float64)
+    return ((p_map - t) @ R).astype(np.float32)
+
+
+# --------------------------------------------------------------------------
+# Sensors
+# --------------------------------------------------------------------------
+
+def disc_cloud(rng, ter: Terrain, sensor_xyz, yaw: float, n: int, radius: float = 4.0):
+    """n visible terrain points uniform in a disc around the sensor, with
+    noise; returns (points in the sensor frame, T_map_sensor)."""
+    T = pose_matrix(rot_z(yaw), sensor_xyz)
+    pts = []
+    got = 0
+    while got < n:
+        m = int((n - got) * 1.4) + 64
+        r = radius * np.sqrt(rng.uniform(size=m))
+        a = rng.uniform(0, 2 * np.pi, m)
+        x = sensor_xyz[0] + r * np.cos(a)
+        y = sensor_xyz[1] + r * np.sin(a)
+        p = np.stack([x, y, ter.height(x, y)], 1)
+        p = p[segment_clear(ter, sensor_xyz, p)]
+        pts.append(p)
+        got += p.shape[0]
+    p = np.concatenate(pts)[:n]
+    p = add_noise(rng, p, sensor_xyz)
+    return to_sensor(p, T), T
+
+
+def depth_camera_cloud(rng, ter, T_cam: np.ndarray, K, h: int, w: int, tmax: float, device=None):
+    """Back-projected depth image (row-major pixel order), misses dropped."""
+    fx, fy, cx, cy = K
+    v, u = np.meshgrid(np.arange(h), np.arange(w), indexing="ij")
+    d = np.stack([(u - cx) / fx, (v - cy) / fy, np.ones_like(u, dtype=np.float64)], -1).reshape(-1, 3)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    R = T_cam[:, :3].astype(np.float64)
+    o = T_cam[:, 3].astype(np.float64)
+    dm = d @ R.T
+    t = raycast(ter, np.broadcast_to(o, dm.shape), dm, tmax, device=device)
+    ok = ~np.isnan(t)
+    p = o + t[ok, None] * dm[ok]
+    p = add_noise(rng, p, o)
+    return to_sensor(p, T_cam)
+
+
+def lidar_cloud(rng, ter, T_lidar: np.ndarray, beams: int, azimuths: int,
+                el_min_deg: float, el_max_deg: float, tmax: float, device=None):
+    """Spinning LiDAR, azimuth-major order (all beams of one firing, then the
+    next azimuth); misses dropped."""
+    el = np.radians(np.linspace(el_min_deg, el_max_deg, beams))
+    az = np.arange(azimuths) * (2 * np.pi / azimuths)
+    A, E = np.meshgrid(az, el, indexing="ij")
+    d = np.stack([np.cos(E) * np.cos(A), np.cos(E) * np.sin(A), np.sin(E)], -1).reshape(-1, 3)
+    R = T_lidar[:, :3].astype(np.float64)
+    o = T_lidar[:, 3].astype(np.float64)
+    dm = d @ R.T
+    t = raycast(ter, np.broadcast_to(o, dm.shape), dm, tmax, device=device)
+    ok = ~np.isnan(t)
+    p = o + t[ok, None] * dm[ok]
+    p = add_noise(rng, p, o)
+    return to_sensor(p, T_lidar)
+
+
+def render_rgb(ter: Terrain, T_cam, K, h: int, w: int, tmax: float, device=None,
+               step: float = 0.06) -> np.ndarray:
+    fx, fy, cx, cy = K
+    v, u = np.meshgrid(np.arange(h), np.arange(w), indexing="ij")
+    d = np.stack([(u - cx) / fx, (v - cy) / fy, np.ones_like(u, dtype=np.float64)], -1).reshape(-1, 3)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    R = T_cam[:, :3].astype(np.float64)
+    o = T_cam[:, 3].astype(np.float64)
+    dm = d @ R.T
+    t = raycast(ter, np.broadcast_to(o, dm.shape), dm, tmax, step=step, refine=8, device=device)
+    rgb = np.tile(np.array([0.53, 0.81, 0.92]), (h * w, 1))  # sky
+    ok = ~np.isnan(t)
+    p = o + t[ok, None] * dm[ok]
+    rgb[ok] = ter.albedo(p[:, 0], p[:, 1])
+    return np.round(rgb * 255).astype(np.uint8).reshape(h, w, 3)
+
+
+def class_image(rng, h: int, w: int, k: int) -> np.ndarray:
+    """Per-pixel Dirichlet(1) class probabilities (normalised Exp(1))."""
+    e = rng.standard_exponential((h, w, k), dtype=np.float32)
+    return (e / e.sum(-1, keepdims=True)).astype(np.float32)
+
+
+def feature_image(rng, h: int, w: int, c: int) -> np.ndarray:
+    """Per-pixel N(0, I) features normalised to unit length."""
+    f = rng.standard_normal((h, w, c), dtype=np.float32)
+    return (f / np.linalg.norm(f, axis=-1, keepdims=True)).astype(np.float32)
+
+
+def scaled_intrinsics(K, s: float):
+    """Intrinsics of the same camera at s times the resolution (pixel
+    centres at integers)."""
+    fx, fy, cx, cy = K
+    return (fx * s, fy * s, (cx + 0.5) * s - 0.5, (cy + 0.5) * s - 0.5)
+
+
+# --------------------------------------------------------------------------
+# Workloads
+# --------------------------------------------------------------------------
+
+SMALL_MAP = dict(width=200, height=200, resolution=0.04, noise_c0=0.01, noise_c1=0.001,
+                 max_range=10.0, clear_margin=0.05, clear_min_count=1, min_depth=0.1)
+# layers: point classes (Dirichlet K=4), RGB (exp. averaging w=0.5), image classes (Dirichlet K=8)
+SMALL_LAYERS = [(4, 3, 1.0), (3, 1, 0.5), (8, 3, 1.0)]
+
+FULL_MAP = dict(width=500, height=500, resolution=0.04, noise_c0=0.01, noise_c1=0.001,
+                max_range=15.0, clear_margin=0.05, clear_min_count=1, min_depth=0.1)
+# layers: RGB (exp. averaging), 64-d features (Gaussian, sigma_f^2 = 1), 20 classes (Dirichlet)
+FULL_LAYERS = [(3, 1, 0.5), (64, 2, 1.0), (20, 3, 1.0)]
+
+
+def small_frames(seed: int = 0, n_frames: int = 10, n_points: int = 20000,
+                 cam_hw=(240, 320), device=None):
+    """The small workload: list of frames, each a dict with
+    pose (x, y, yaw), cloud (xyz, ch, T), camera (K, T, rgb, classes)."""
+    ss = np.random.SeedSequence(seed)
+    rng_t, rng_p, rng_f = [np.random.Generator(np.random.PCG64(s)) for s in ss.spawn(3)]
+    ter = make_terrain(rng_t, extent=8.0)
+    poses = pose_walk(rng_p, n_frames)
+    frames = []
+    h, w = cam_hw
+    K = (200.0, 200.0, (w - 1) / 2.0, (h - 1) / 2.0)
+    for (x, y, yaw) in poses:
+        zg = float(ter.height(x, y))
+        s = np.array([x, y, zg + 0.6])
+        xyz, T = disc_cloud(rng_f, ter, s, yaw, n_points)
+        ch = class_image(rng_f, 1, n_points, 4).reshape(n_points, 4)
+        Tc = pose_matrix(camera_rotation(yaw, math.radians(20)), s)
+        rgb = render_rgb(ter, Tc, K, h, w, tmax=8.0, device=device)
+        cls = class_image(rng_f, h, w, 8)
+        frames.append(dict(pose=(x, y, yaw), cloud=dict(xyz=xyz, ch=ch, T=T),
+                           camera=dict(K=K, T=Tc, rgb=rgb, classes=cls)))
+    return ter, frames
+
+
+def full_frames(seed: int = 1, n_frames: int = 2, device=None, lidar=(128, 2048),
+                depth_hw=(480, 640), rgb_hw=(480, 640), feat_hw=(120, 160), n_feat=64,
+                n_cls=20):
+    """The full-rate single-robot workload (see module docstring)."""
+    ss = np.random.SeedSequence(seed)
+    rng_t, rng_p, rng_f = [np.random.Generator(np.random.PCG64(s)) for s in ss.spawn(3)]
+    ter = make_terrain(rng_t, extent=20.0)
+    poses = pose_walk(rng_p, n_frames)
+    dh, dw = depth_hw
+    Kd = (400.0, 400.0, (dw - 1) / 2.0, (dh - 1) / 2.0)
+    rh, rw = rgb_hw
+    Kr = (400.0, 400.0, (rw - 1) / 2.0, (rh - 1) / 2.0)
+    Kf = scaled_intrinsics(Kr, feat_hw[1] / rw)
+    frames = []
+    for (x, y, yaw) in poses:
+        zg = float(ter.height(x, y))
+        base = np.array([x, y, zg])
+        clouds = []
+        Tl = pose_matrix(rot_z(yaw), base + [0, 0, 0.8])
+        clouds.append(dict(xyz=lidar_cloud(rng_f, ter, Tl, lidar[0], lidar[1], -25.0, -1.0, 14.1,
+                                           device=device), T=Tl))
+        cams = []
+        for k in range(4):
+            Tc = pose_matrix(camera_rotation(yaw + k * np.pi / 2, math.radians(25)), base + [0, 0, 0.6])
+            clouds.append(dict(xyz=depth_camera_cloud(rng_f, ter, Tc, Kd, dh, dw, 10.0, device=device), T=Tc))
+            cams.append(dict(T=Tc, K=Kr, rgb=render_rgb(ter, Tc, Kr, rh, rw, 10.0, device=device),
+                             classes=class_image(rng_f, rh, rw, n_cls),
+                             K_feat=Kf, features=feature_image(rng_f, feat_hw[0], feat_hw[1], n_feat)))
+        frames.append(dict(pose=(x, y, yaw), clouds=clouds, cameras=cams))
+    return ter, frames
