@@ -1,0 +1,219 @@
+"""Benchmark of the per-frame map update on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+One step is one frame of the full-rate single-robot workload: re-centre the
+500x500 grid (0.04 m), fuse a 128x2048 LiDAR cloud and four 640x480
+depth-camera clouds (height update and clearing ray cast), then fuse four
+RGB cameras, each as an RGB u8 image, a 160x120x64 unit-norm feature image
+(Gaussian layer) and a 640x480 20-class image (Dirichlet layer).  Inputs are
+synthetic, generated before timing and resident in HBM.
+
+Prints one JSON line: fused points/s over the whole update (value), the
+per-frame latency, per-kernel times from HIP events recorded on the
+library's stream during the timed region, the roofline of the dominant
+kernel, and the oracle's throughput on the host CPU for a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fused points/s + map-update latency (ms), plain vs batched/learned, at tolerance"
+HBM_PEAK_GBS = 8000.0
+# Vector ALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 4 cycles/wave-instr...
+# expressed as lane-instructions/s: 256 CU * 128 lanes/clk * 2.4 GHz.
+ALU_PEAK_LANE_OPS = 256 * 128 * 2.4e9
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-frames", type=int, default=10)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--profile-events", type=int, default=1,
+                    help="record HIP events around every launch in the timed region")
+    return ap.parse_args()
+
+
+def gen_frames(n, seed, device):
+    from paper_2309_16818_amd import synth
+    t0 = time.time()
+    frames = []
+    for k, (_, f) in enumerate(synth.iter_full_frames(seed=seed, n_frames=n, device=device)):
+        frames.append(f)
+        print(f"# frame {k + 1}/{n} generated ({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
+    return frames, time.time() - t0
+
+
+def upload(frames):
+    import torch
+    dev = []
+    for f in frames:
+        d = dict(pose=f["pose"], clouds=[], cameras=[])
+        for c in f["clouds"]:
+            d["clouds"].append(dict(xyz=torch.from_numpy(np.ascontiguousarray(c["xyz"])).cuda(), T=c["T"]))
+        for c in f["cameras"]:
+            d["cameras"].append(dict(T=c["T"], K=c["K"], K_feat=c["K_feat"],
+                                     rgb=torch.from_numpy(c["rgb"]).cuda(),
+                                     classes=torch.from_numpy(c["classes"]).cuda(),
+                                     features=torch.from_numpy(c["features"]).cuda()))
+        dev.append(d)
+    return dev
+
+
+def run_frame(m, f):
+    x, y, _ = f["pose"]
+    m.move(x, y)
+    for c in f["clouds"]:
+        m.input_pointcloud(c["xyz"], c["T"])
+    for c in f["cameras"]:
+        m.input_image(c["rgb"], c["K"], c["T"], bind=[(8, 0, 3)])
+        m.input_image(c["features"], c["K_feat"], c["T"], bind=[(9, 0, 64)])
+        m.input_image(c["classes"], c["K"], c["T"], bind=[(10, 0, 20)])
+
+
+def make_map():
+    from paper_2309_16818_amd import mem, synth
+    p = dict(synth.FULL_MAP)
+    layers = [mem.Layer(c, r, q) for (c, r, q) in synth.FULL_LAYERS]
+    return mem.Map(mem.MapParams(p.pop("width"), p.pop("height"), p.pop("resolution"), layers=layers, **p))
+
+
+def kernel_bytes(name, st, launches):
+    """Algorithmic HBM bytes of a kernel over the timed region, from the
+    per-call counters (units and per-unit bytes as documented in the design doc)."""
+    cells = 500 * 500
+    if name == "ingest":       # 12 B per input point; 12 B of sums per touched cell
+        return 12 * st["points_in"] + 12 * st["cells_touched"]
+    if name == "finalize":     # dense n + clr reads; touched: W,S,h,v read, h,v write
+        return 8 * cells * launches + 24 * st["cells_touched"]
+    if name == "zero_accum":   # n, W, S, clr cleared
+        return 16 * cells * launches
+    if name == "gather_fuse":  # pixel + state RMW per visible pair, per layer
+        per_pair = (3 + 2 * 3 * 4) + (64 * 4 + 2 * 64 * 4 + 8) + (20 * 4 + 2 * 20 * 4)
+        return per_pair * st["pairs_visible"] // 3 + 8 * st["pairs_visible"]
+    if name == "project":      # h per cell
+        return 4 * cells * launches
+    if name == "clear_march":  # xyz re-read
+        return 12 * st["points_in"]
+    return 0
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_2309_16818_amd import mem
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    n_frames = args.warmup + args.steps
+    frames, gen_s = gen_frames(n_frames, args.seed, "cuda")
+    print(f"# generated {n_frames} frames in {gen_s:.1f}s", file=sys.stderr, flush=True)
+    dframes = upload(frames)
+    torch.cuda.synchronize()
+
+    m = make_map()
+    for f in dframes[:args.warmup]:
+        run_frame(m, f)
+    torch.cuda.synchronize()
+    m.reset_stats()
+    if args.profile_events:
+        m.profile_enable(True)
+    m.profile_read()  # clears totals
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k, f in enumerate(dframes[args.warmup:]):
+        ev[k][0].record()
+        run_frame(m, f)
+        ev[k][1].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = m.profile_read() if args.profile_events else {}
+    m.profile_enable(False)
+    st = m.stats()
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    wall_ms = (t1 - t0) * 1e3 / args.steps
+    pts_s = st["points_accepted"] / ((t1 - t0))
+
+    kernels = {}
+    for name, (launches, ms) in kern.items():
+        b = kernel_bytes(name, st, launches)
+        kernels[name] = dict(launches=launches, total_ms=round(ms, 4), avg_us=round(1e3 * ms / max(launches, 1), 3),
+                             alg_gbs=round(b / (ms * 1e-3) / 1e9, 1) if b and ms > 0 else None)
+    dom = max(kernels, key=lambda k: kernels[k]["total_ms"]) if kernels else None
+    roof = None
+    if dom:
+        kd = kernels[dom]
+        b = kernel_bytes(dom, st, kd["launches"])
+        if b and dom not in ("clear_march", "project"):
+            ach = b / (kd["total_ms"] * 1e-3) / 1e9
+            roof = dict(kernel=dom, bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(ach / HBM_PEAK_GBS, 4), traffic=None)
+        else:  # ray walks: ALU / L2 bound; achieved in ray-cell visits
+            visits = st["ray_cells"] if dom == "clear_march" else st["occl_cells"]
+            rate = visits / (kd["total_ms"] * 1e-3)
+            roof = dict(kernel=dom, bound="alu", achieved=round(rate / 1e9, 3), unit="Gcell-visits/s",
+                        peak=None, frac=None, traffic=None)
+    out = {
+        "metric": METRIC, "value": round(pts_s, 1), "unit": "points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall_ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "full-rate single robot: 500x500 grid at 0.04 m; per frame 1 LiDAR 128x2048 "
+                               "+ 4 depth cameras 640x480 (~1.4M points), 4 RGB cameras x (RGB 640x480 u8, "
+                               "features 160x120x64 f32 Gaussian, classes 640x480x20 f32 Dirichlet)",
+                   "frames": n_frames, "points_per_frame": round(st["points_in"] / args.steps)},
+        "latency_ms": {"mean": round(float(lat.mean()), 4), "std": round(float(lat.std()), 4),
+                       "median": round(float(np.median(lat)), 4), "p90": round(float(np.percentile(lat, 90)), 4)},
+        "stats": st, "kernels": kernels, "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(frames[:args.cpu_frames])
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(frames):
+    """The oracle (plain C, one thread) on the first frames of the same
+    workload, from an empty map."""
+    import oracle as O
+    from paper_2309_16818_amd import synth
+    p = dict(synth.FULL_MAP)
+    o = O.OracleMap(p.pop("width"), p.pop("height"), p.pop("resolution"), layers=synth.FULL_LAYERS, **p)
+    acc = 0
+    t0 = time.perf_counter()
+    for f in frames:
+        x, y, _ = f["pose"]
+        o.move(x, y)
+        for c in f["clouds"]:
+            cells = o.input_pointcloud(c["xyz"], c["T"])
+            acc += int((cells >= 0).sum())
+        for c in f["cameras"]:
+            o.input_image(c["rgb"], c["K"], c["T"], bind=[(8, 0, 3)])
+            o.input_image(c["features"], c["K_feat"], c["T"], bind=[(9, 0, 64)])
+            o.input_image(c["classes"], c["K"], c["T"], bind=[(10, 0, 20)])
+    dt = time.perf_counter() - t0
+    return {"value": round(acc / dt, 1), "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(frames)} frame(s) of the same workload from an empty map "
+                      f"({acc} accepted points, {dt:.1f} s)"}
+
+
+if __name__ == "__main__":
+    main()

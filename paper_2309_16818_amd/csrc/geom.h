@@ -1,0 +1,124 @@
+// geom.h - binary32 decision formulas of the map update (device side).
+//
+// Every function here decides an integer (a cell, a pixel, a vote) and must
+// evaluate exactly as specified in include/mem.h: binary32, the written
+// operation order, no fused multiply-add (the library is compiled with
+// -ffp-contract=off and correctly rounded division).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "mem_internal.h"
+
+namespace memk {
+
+// Storage index of logical cell (ix, iy), both inside the grid.
+__device__ __forceinline__ int storage_index(const Grid& g, int ix, int iy)
+{
+    int sx = ix + g.rx;
+    sx -= (sx >= g.W) ? g.W : 0;
+    int sy = iy + g.ry;
+    sy -= (sy >= g.H) ? g.H : 0;
+    return sy * g.W + sx;
+}
+
+// Logical cell of a storage index.
+__device__ __forceinline__ void logical_index(const Grid& g, int st, int& ix, int& iy)
+{
+    int sy = st / g.W;
+    int sx = st - sy * g.W;
+    ix = sx - g.rx;
+    ix += (ix < 0) ? g.W : 0;
+    iy = sy - g.ry;
+    iy += (iy < 0) ? g.H : 0;
+}
+
+// Sensor-frame point -> map frame and grid cell (Sec. III-B association by
+// horizontal coordinates).  Returns 0 (accepted) or -1 non-finite, -2 out of
+// range, -3 outside the grid.  r2 receives the sensor-frame range squared.
+__device__ __forceinline__ int point_cell(const Grid& g, const Pose& T, float mr2, float x,
+                                          float y, float z, float& px, float& py, float& pz,
+                                          float& r2, int& ix, int& iy)
+{
+    if (!(isfinite(x) && isfinite(y) && isfinite(z))) return -1;
+    float xx = x * x, yy = y * y, zz = z * z;
+    r2 = xx + yy;
+    r2 = r2 + zz;
+    if (r2 > mr2) return -2;
+    const float* m = T.m;
+    float a, b, c;
+    a = m[0] * x; b = m[1] * y; c = m[2] * z;
+    px = ((a + b) + c) + m[3];
+    a = m[4] * x; b = m[5] * y; c = m[6] * z;
+    py = ((a + b) + c) + m[7];
+    a = m[8] * x; b = m[9] * y; c = m[10] * z;
+    pz = ((a + b) + c) + m[11];
+    if (!(isfinite(px) && isfinite(py) && isfinite(pz))) return -3;
+    float gx = floorf(px * g.inv_res);
+    float gy = floorf(py * g.inv_res);
+    if (!(gx >= (float)g.ox && gx < (float)(g.ox + g.W))) return -3;
+    if (!(gy >= (float)g.oy && gy < (float)(g.oy + g.H))) return -3;
+    ix = (int)gx - g.ox;
+    iy = (int)gy - g.oy;
+    return 0;
+}
+
+// Logical lattice cell of a position (may lie outside the grid).
+__device__ __forceinline__ void lattice_cell(const Grid& g, float x, float y, int& ix, int& iy)
+{
+    ix = (int)floorf(x * g.inv_res) - g.ox;
+    iy = (int)floorf(y * g.inv_res) - g.oy;
+}
+
+// Incremental Bresenham walk from (ax, ay) towards (bx, by).  step() moves
+// to the next cell; the minor coordinate advances only when D > 0.
+struct LineWalk {
+    int x, y, sx, sy, dmaj2, dmin2, D, steps;
+    bool xmajor;
+    __device__ __forceinline__ LineWalk(int ax, int ay, int bx, int by)
+    {
+        int dx = abs(bx - ax), dy = abs(by - ay);
+        sx = (bx >= ax) ? 1 : -1;
+        sy = (by >= ay) ? 1 : -1;
+        x = ax;
+        y = ay;
+        xmajor = dx >= dy;
+        if (xmajor) {
+            D = 2 * dy - dx;
+            dmaj2 = 2 * dx;
+            dmin2 = 2 * dy;
+            steps = dx;
+        } else {
+            D = 2 * dx - dy;
+            dmaj2 = 2 * dy;
+            dmin2 = 2 * dx;
+            steps = dy;
+        }
+    }
+    __device__ __forceinline__ void step()
+    {
+        if (xmajor) {
+            if (D > 0) { y += sy; D -= dmaj2; }
+            D += dmin2;
+            x += sx;
+        } else {
+            if (D > 0) { x += sx; D -= dmaj2; }
+            D += dmin2;
+            y += sy;
+        }
+    }
+};
+
+// Height of the ray s -> p above the cell whose absolute major-axis lattice
+// index is k: the ray parameter is taken at that cell's centre.
+// inv_d = 1 / (p_major - s_major), dz = p_z - s_z.
+__device__ __forceinline__ float ray_height(int k_abs, float res, float s_major, float inv_d,
+                                            float s_z, float dz)
+{
+    float c = (float)k_abs + 0.5f;
+    c = c * res;
+    float t = (c - s_major) * inv_d;
+    return s_z + dz * t;
+}
+
+}  // namespace memk

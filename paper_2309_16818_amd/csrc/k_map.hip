@@ -1,0 +1,159 @@
+// k_map.hip - grid maintenance: resetting cells that enter the moving grid,
+// and the layer read-out / write-in views.
+#include "codec.h"
+#include "geom.h"
+#include "mem_internal.h"
+
+namespace memk {
+
+namespace {
+
+constexpr float kNaN = __builtin_nanf("");
+constexpr float kInf = __builtin_inff();
+
+struct LayerSet {
+    LayerDev L[32];
+    int n;
+};
+
+// Empty cell: no height, never observed layers, Dirichlet alpha_0.
+__global__ __launch_bounds__(256) void k_reset_rect(Grid g, int x0, int x1, int y0, int y1,
+                                                    float* __restrict__ h, float* __restrict__ v,
+                                                    int* __restrict__ cnt, int* __restrict__ clr,
+                                                    LayerSet ls)
+{
+    const int w = x1 - x0;
+    const int64_t total = (int64_t)w * (y1 - y0);
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        int ix = x0 + (int)(k % w), iy = y0 + (int)(k / w);
+        int st = storage_index(g, ix, iy);
+        h[st] = kNaN;
+        v[st] = kInf;
+        cnt[st] = 0;
+        clr[st] = 0;
+        for (int l = 0; l < ls.n; l++) {
+            const LayerDev& L = ls.L[l];
+            float init = (L.rule == MEM_DIRICHLET) ? L.param : kNaN;
+            for (int q = 0; q < L.C; q++) layer_store(L.val, L.storage, L.scale, (int64_t)st * L.C + q, q, init);
+            if (L.rule == MEM_GAUSS) L.var[st] = kInf;
+        }
+    }
+}
+
+// out[(iy*W + ix)*C + q], logical order.  layer < 8: built-in layers.
+__global__ __launch_bounds__(256) void k_readout(Grid g, int layer, int view,
+                                                 const float* __restrict__ h,
+                                                 const float* __restrict__ v,
+                                                 const int* __restrict__ cnt,
+                                                 const int* __restrict__ clr, LayerDev L,
+                                                 float* __restrict__ out)
+{
+    const int HW = g.W * g.H;
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= HW) return;
+    int ix = j % g.W, iy = j / g.W;
+    int st = storage_index(g, ix, iy);
+    if (layer < 8) {
+        float o;
+        float hv = h[st];
+        switch (layer) {
+        case MEM_LAYER_ELEVATION: o = hv; break;
+        case MEM_LAYER_VARIANCE: o = isnan(hv) ? kNaN : v[st]; break;
+        case MEM_LAYER_VALID: o = isnan(hv) ? 0.0f : 1.0f; break;
+        case MEM_LAYER_HITS: o = (float)cnt[st]; break;
+        default: o = (float)clr[st]; break;
+        }
+        out[j] = o;
+        return;
+    }
+    const int C = L.C;
+    if (view == MEM_VIEW_AUX && L.rule == MEM_GAUSS) {
+        out[j] = L.var[st];
+        return;
+    }
+    if (view == MEM_VIEW_ARGMAX) {  // lowest index on ties
+        int best = 0;
+        float bv = layer_load(L.val, L.storage, L.scale, (int64_t)st * C, 0);
+        for (int q = 1; q < C; q++) {
+            float x = layer_load(L.val, L.storage, L.scale, (int64_t)st * C + q, q);
+            if (x > bv) {
+                bv = x;
+                best = q;
+            }
+        }
+        out[j] = (float)best;
+        return;
+    }
+    if (view == MEM_VIEW_VALUE && L.rule == MEM_DIRICHLET) {  // Eq. (11)
+        float s = 0.0f;
+        for (int q = 0; q < C; q++) s += layer_load(L.val, L.storage, L.scale, (int64_t)st * C + q, q);
+        for (int q = 0; q < C; q++)
+            out[(int64_t)j * C + q] = layer_load(L.val, L.storage, L.scale, (int64_t)st * C + q, q) / s;
+        return;
+    }
+    for (int q = 0; q < C; q++)
+        out[(int64_t)j * C + q] = layer_load(L.val, L.storage, L.scale, (int64_t)st * C + q, q);
+}
+
+__global__ __launch_bounds__(256) void k_setlayer(Grid g, int layer, int view,
+                                                  float* __restrict__ h, float* __restrict__ v,
+                                                  LayerDev L, const float* __restrict__ in)
+{
+    const int HW = g.W * g.H;
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= HW) return;
+    int ix = j % g.W, iy = j / g.W;
+    int st = storage_index(g, ix, iy);
+    if (layer == MEM_LAYER_ELEVATION) {
+        h[st] = in[j];
+        return;
+    }
+    if (layer == MEM_LAYER_VARIANCE) {
+        if (!isnan(in[j])) v[st] = in[j];
+        return;
+    }
+    if (view == MEM_VIEW_AUX && L.rule == MEM_GAUSS) {
+        L.var[st] = in[j];
+        return;
+    }
+    for (int q = 0; q < L.C; q++)
+        layer_store(L.val, L.storage, L.scale, (int64_t)st * L.C + q, q, in[(int64_t)j * L.C + q]);
+}
+
+}  // namespace
+
+void launch_reset_rect(hipStream_t s, const Grid& g, int x0, int x1, int y0, int y1, float* h,
+                       float* v, int* cnt, int* clr, const LayerDev* L, int nL)
+{
+    if (x1 <= x0 || y1 <= y0) return;
+    LayerSet ls;
+    ls.n = nL;
+    for (int l = 0; l < nL; l++) ls.L[l] = L[l];
+    int64_t total = (int64_t)(x1 - x0) * (y1 - y0);
+    int64_t b = (total + 255) / 256;
+    if (b > 4096) b = 4096;
+    hipLaunchKernelGGL(k_reset_rect, dim3((unsigned)b), dim3(256), 0, s, g, x0, x1, y0, y1, h, v, cnt,
+                       clr, ls);
+}
+
+void launch_readout(hipStream_t s, const Grid& g, int layer, int view, const float* h,
+                    const float* v, const int* cnt, const int* clr, const LayerDev* L, float* out)
+{
+    int HW = g.W * g.H;
+    LayerDev l{};
+    if (L) l = *L;
+    hipLaunchKernelGGL(k_readout, dim3((HW + 255) / 256), dim3(256), 0, s, g, layer, view, h, v, cnt,
+                       clr, l, out);
+}
+
+void launch_setlayer(hipStream_t s, const Grid& g, int layer, int view, float* h, float* v,
+                     const LayerDev* L, const float* in)
+{
+    int HW = g.W * g.H;
+    LayerDev l{};
+    if (L) l = *L;
+    hipLaunchKernelGGL(k_setlayer, dim3((HW + 255) / 256), dim3(256), 0, s, g, layer, view, h, v, l, in);
+}
+
+}  // namespace memk

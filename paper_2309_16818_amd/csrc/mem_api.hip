@@ -1,0 +1,667 @@
+// mem_api.hip - host side of the C ABI declared in include/mem.h.
+//
+// Every entry point validates its arguments before it enqueues anything,
+// then enqueues kernels on the caller's stream and returns without waiting.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "mem_internal.h"
+
+using namespace memk;
+
+namespace {
+
+thread_local std::string g_err;
+
+mem_status fail(mem_status code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+struct Layer {
+    int C, rule, storage;
+    float param;
+    void* val = nullptr;
+    float* var = nullptr;
+    float* scale = nullptr;
+    LayerDev dev() const
+    {
+        LayerDev d;
+        d.val = val;
+        d.var = var;
+        d.scale = scale;
+        d.C = C;
+        d.rule = rule;
+        d.storage = storage;
+        d.param = param;
+        return d;
+    }
+};
+
+struct ProfRec {
+    const char* name;
+    hipEvent_t a, b;
+};
+
+size_t elem_size(int storage)
+{
+    return storage == MEM_BF16 ? 2 : storage == MEM_FP8_E4M3 ? 1 : 4;
+}
+
+}  // namespace
+
+struct mem_map {
+    int W = 0, H = 0;
+    float res = 0, inv_res = 0;
+    float c0 = 0, c1 = 0, max_range = 0, mr2 = 0, clear_margin = 0, min_depth = 0;
+    int clear_min = 0;
+    int cx = 0, cy = 0, rx = 0, ry = 0;
+    int device = 0;
+    int max_lds = 65536;  // LDS bytes a workgroup may use on this device
+    bool broken = false;
+
+    float* h = nullptr;
+    float* v = nullptr;
+    int* cnt = nullptr;
+    int* clr = nullptr;
+    float* wsum = nullptr;
+    float* ssum = nullptr;
+    float2* stash = nullptr;
+    int2* pairs = nullptr;
+    int* pair_count = nullptr;
+    unsigned long long* stats = nullptr;
+    float* chsum = nullptr;
+    int chsum_planes = 0;
+    std::vector<Layer> layers;
+
+    bool prof = false;
+    std::vector<ProfRec> pending;
+    std::vector<hipEvent_t> pool;
+    std::map<std::string, std::pair<int64_t, double>> totals;
+
+    Grid grid() const
+    {
+        Grid g;
+        g.W = W;
+        g.H = H;
+        g.ox = cx - W / 2;
+        g.oy = cy - H / 2;
+        g.rx = rx;
+        g.ry = ry;
+        g.res = res;
+        g.inv_res = inv_res;
+        return g;
+    }
+    int64_t cells() const { return (int64_t)W * H; }
+};
+
+namespace {
+
+mem_status hip_fail(mem_map* m, hipError_t e, const char* what)
+{
+    if (m) m->broken = true;
+    return fail(MEM_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(m, call)                                          \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) return hip_fail((m), e_, #call);    \
+    } while (0)
+
+mem_status check_launch(mem_map* m, const char* what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(m, e, what);
+    return MEM_OK;
+}
+
+hipEvent_t pool_get(mem_map* m)
+{
+    if (!m->pool.empty()) {
+        hipEvent_t e = m->pool.back();
+        m->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+void prof_drain(mem_map* m)
+{
+    if (m->pending.empty()) return;
+    (void)hipEventSynchronize(m->pending.back().b);
+    for (auto& r : m->pending) {
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, r.a, r.b);
+        auto& t = m->totals[r.name];
+        t.first += 1;
+        t.second += ms;
+        m->pool.push_back(r.a);
+        m->pool.push_back(r.b);
+    }
+    m->pending.clear();
+}
+
+// Runs a launcher, bracketed by events on `s` while profiling is on.
+template <class F>
+void timed(mem_map* m, hipStream_t s, const char* name, F&& f)
+{
+    if (!m->prof) {
+        f();
+        return;
+    }
+    hipEvent_t a = pool_get(m), b = pool_get(m);
+    (void)hipEventRecord(a, s);
+    f();
+    (void)hipEventRecord(b, s);
+    m->pending.push_back({name, a, b});
+    if (m->pending.size() >= 8192) prof_drain(m);
+}
+
+mem_status usable(const mem_map* m)
+{
+    if (!m) return fail(MEM_E_ARG, "map is NULL");
+    if (m->broken) return fail(MEM_E_STATE, "map is unusable after an earlier HIP error");
+    return MEM_OK;
+}
+
+// Finite pose with an orthonormal rotation and a translation whose lattice
+// coordinates stay far inside int32.
+mem_status check_pose(const mem_map* m, const float* T, const char* what)
+{
+    if (!T) return fail(MEM_E_ARG, "%s is NULL", what);
+    for (int k = 0; k < 12; k++)
+        if (!std::isfinite(T[k])) return fail(MEM_E_ARG, "%s has a non-finite entry", what);
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) {
+            double d = 0;
+            for (int k = 0; k < 3; k++) d += (double)T[4 * a + k] * T[4 * b + k];
+            if (std::fabs(d - (a == b ? 1.0 : 0.0)) > 1e-4)
+                return fail(MEM_E_ARG, "%s rotation is not orthonormal", what);
+        }
+    const double lim = 4194304.0;  // 2^22 cells
+    if (std::fabs((double)T[3] * m->inv_res) > lim || std::fabs((double)T[7] * m->inv_res) > lim)
+        return fail(MEM_E_ARG, "%s translation is too far from the origin", what);
+    // Rays start at the sensor: keep it within a few grid widths of the grid
+    // so that every ray walk is short.
+    const double reach = 4.0 * (m->W > m->H ? m->W : m->H) + 2.0;
+    if (std::fabs(std::floor((double)(T[3] * m->inv_res)) - m->cx) > reach ||
+        std::fabs(std::floor((double)(T[7] * m->inv_res)) - m->cy) > reach)
+        return fail(MEM_E_ARG, "%s lies more than 4 grid widths from the grid", what);
+    return MEM_OK;
+}
+
+mem_status resolve_layer(const mem_map* m, int layer, const Layer** out)
+{
+    int l = layer - MEM_LAYER_USER0;
+    if (l < 0 || l >= (int)m->layers.size()) return fail(MEM_E_ARG, "no user layer %d", layer);
+    *out = &m->layers[l];
+    return MEM_OK;
+}
+
+template <class T>
+mem_status dev_alloc(mem_map* m, T** p, size_t count)
+{
+    hipError_t e = hipMalloc((void**)p, sizeof(T) * (count ? count : 1));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(MEM_E_NOMEM, "hipMalloc of %zu bytes failed: %s", sizeof(T) * count,
+                    hipGetErrorString(e));
+    }
+    (void)m;
+    return MEM_OK;
+}
+
+void free_map(mem_map* m)
+{
+    (void)hipFree(m->h);
+    (void)hipFree(m->v);
+    (void)hipFree(m->cnt);
+    (void)hipFree(m->clr);
+    (void)hipFree(m->wsum);
+    (void)hipFree(m->ssum);
+    (void)hipFree(m->stash);
+    (void)hipFree(m->pairs);
+    (void)hipFree(m->pair_count);
+    (void)hipFree(m->stats);
+    (void)hipFree(m->chsum);
+    for (auto& L : m->layers) {
+        (void)hipFree(L.val);
+        (void)hipFree(L.var);
+        (void)hipFree(L.scale);
+    }
+    for (auto& r : m->pending) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : m->pool) (void)hipEventDestroy(e);
+    delete m;
+}
+
+std::vector<LayerDev> layer_devs(const mem_map* m)
+{
+    std::vector<LayerDev> d;
+    for (auto& L : m->layers) d.push_back(L.dev());
+    return d;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mem_last_error(void)
+{
+    return g_err.c_str();
+}
+
+mem_status mem_create(const mem_params* p, void* stream, mem_map** out)
+{
+    if (!p || !out) return fail(MEM_E_ARG, "params and out must not be NULL");
+    *out = nullptr;
+    if (p->width < 1 || p->width > 16384 || p->height < 1 || p->height > 16384)
+        return fail(MEM_E_ARG, "grid %dx%d outside 1..16384", p->width, p->height);
+    if (!(p->resolution > 0.0f) || !std::isfinite(p->resolution))
+        return fail(MEM_E_ARG, "resolution must be positive");
+    if (!std::isfinite(p->noise_c0) || !std::isfinite(p->noise_c1) || p->noise_c0 < 0 || p->noise_c1 < 0 ||
+        (p->noise_c0 == 0 && p->noise_c1 == 0))
+        return fail(MEM_E_ARG, "noise model needs c0, c1 >= 0, not both zero");
+    if (!(p->max_range > 0.0f)) return fail(MEM_E_ARG, "max_range must be positive");
+    if (!std::isfinite(p->clear_margin) || p->clear_min_count < 0)
+        return fail(MEM_E_ARG, "bad clearing parameters");
+    if (!std::isfinite(p->min_depth)) return fail(MEM_E_ARG, "min_depth must be finite");
+    if (p->n_layers < 0 || p->n_layers > 32 || (p->n_layers > 0 && !p->layers))
+        return fail(MEM_E_ARG, "n_layers must be 0..32 with a layer array");
+    for (int l = 0; l < p->n_layers; l++) {
+        const mem_layer_desc& d = p->layers[l];
+        if (d.channels < 1 || d.channels > 4096) return fail(MEM_E_ARG, "layer %d: channels", l);
+        if (d.rule < MEM_LATEST || d.rule > MEM_DIRICHLET) return fail(MEM_E_ARG, "layer %d: rule", l);
+        if (d.storage != MEM_F32 && d.storage != MEM_BF16 && d.storage != MEM_FP8_E4M3)
+            return fail(MEM_E_ARG, "layer %d: storage", l);
+        if (d.rule == MEM_DIRICHLET && d.storage != MEM_F32)
+            return fail(MEM_E_ARG, "layer %d: Dirichlet layers are stored in f32", l);
+        if (d.rule == MEM_EXPAVG && !(d.param > 0.0f && d.param <= 1.0f))
+            return fail(MEM_E_ARG, "layer %d: exponential averaging weight must be in (0, 1]", l);
+        if ((d.rule == MEM_GAUSS || d.rule == MEM_DIRICHLET) && !(d.param > 0.0f && std::isfinite(d.param)))
+            return fail(MEM_E_ARG, "layer %d: parameter must be positive", l);
+        if (d.ch_scale)
+            for (int q = 0; q < d.channels; q++)
+                if (!(d.ch_scale[q] > 0.0f) || !std::isfinite(d.ch_scale[q]))
+                    return fail(MEM_E_ARG, "layer %d: ch_scale must be positive", l);
+    }
+
+    hipStream_t s = (hipStream_t)stream;
+    mem_map* m = new mem_map;
+    m->W = p->width;
+    m->H = p->height;
+    m->res = p->resolution;
+    m->inv_res = (float)(1.0 / (double)p->resolution);
+    m->c0 = p->noise_c0;
+    m->c1 = p->noise_c1;
+    m->max_range = p->max_range;
+    m->mr2 = p->max_range * p->max_range;
+    m->clear_margin = p->clear_margin;
+    m->clear_min = p->clear_min_count;
+    m->min_depth = p->min_depth;
+    (void)hipGetDevice(&m->device);
+    {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, m->device) == hipSuccess && v > 0)
+            m->max_lds = v;
+        (void)hipGetLastError();
+    }
+    const int64_t HW = m->cells();
+    mem_status st = MEM_OK;
+    if ((st = dev_alloc(m, &m->h, HW)) || (st = dev_alloc(m, &m->v, HW)) ||
+        (st = dev_alloc(m, &m->cnt, HW)) || (st = dev_alloc(m, &m->clr, HW)) ||
+        (st = dev_alloc(m, &m->wsum, HW)) || (st = dev_alloc(m, &m->ssum, HW)) ||
+        (st = dev_alloc(m, &m->stash, HW)) || (st = dev_alloc(m, &m->pairs, HW)) ||
+        (st = dev_alloc(m, &m->pair_count, 1)) || (st = dev_alloc(m, &m->stats, kStats))) {
+        free_map(m);
+        return st;
+    }
+    for (int l = 0; l < p->n_layers; l++) {
+        const mem_layer_desc& d = p->layers[l];
+        Layer L;
+        L.C = d.channels;
+        L.rule = d.rule;
+        L.storage = d.storage;
+        L.param = d.param;
+        m->layers.push_back(L);
+        Layer& M = m->layers.back();
+        if ((st = dev_alloc(m, (uint8_t**)&M.val, HW * d.channels * elem_size(d.storage))) ||
+            (d.rule == MEM_GAUSS && (st = dev_alloc(m, &M.var, HW))) ||
+            (st = dev_alloc(m, &M.scale, d.channels))) {
+            free_map(m);
+            return st;
+        }
+        std::vector<float> sc(d.channels, 1.0f / 448.0f);
+        if (d.ch_scale)
+            for (int q = 0; q < d.channels; q++) sc[q] = d.ch_scale[q] / 448.0f;
+        hipError_t e = hipMemcpy(M.scale, sc.data(), sizeof(float) * d.channels, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            free_map(m);
+            return fail(MEM_E_HIP, "hipMemcpy: %s", hipGetErrorString(e));
+        }
+    }
+    Grid g = m->grid();
+    auto devs = layer_devs(m);
+    launch_reset_rect(s, g, 0, m->W, 0, m->H, m->h, m->v, m->cnt, m->clr, devs.data(), (int)devs.size());
+    launch_zero_accum(s, g, m->cnt, m->wsum, m->ssum, m->clr, nullptr, 0);
+    launch_zero_int(s, (int*)m->stats, 2 * kStats);
+    launch_zero_int(s, m->pair_count, 1);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        free_map(m);
+        return fail(MEM_E_HIP, "initialising the map: %s", hipGetErrorString(e));
+    }
+    *out = m;
+    return MEM_OK;
+}
+
+mem_status mem_destroy(mem_map* m, void* stream)
+{
+    if (!m) return MEM_OK;
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    free_map(m);
+    return MEM_OK;
+}
+
+mem_status mem_get_center(const mem_map* m, int32_t* cx, int32_t* cy)
+{
+    if (!m || !cx || !cy) return fail(MEM_E_ARG, "NULL argument");
+    *cx = m->cx;
+    *cy = m->cy;
+    return MEM_OK;
+}
+
+mem_status mem_move(mem_map* m, float x, float y, void* stream)
+{
+    if (mem_status st = usable(m)) return st;
+    if (!std::isfinite(x) || !std::isfinite(y)) return fail(MEM_E_ARG, "position must be finite");
+    const double lim = 4194304.0;
+    if (std::fabs((double)x * m->inv_res) > lim || std::fabs((double)y * m->inv_res) > lim)
+        return fail(MEM_E_ARG, "position is too far from the origin");
+    hipStream_t s = (hipStream_t)stream;
+    float gx = floorf(x * m->inv_res);
+    float gy = floorf(y * m->inv_res);
+    int ncx = (int)gx, ncy = (int)gy;
+    int sx = ncx - m->cx, sy = ncy - m->cy;
+    if (sx == 0 && sy == 0) return MEM_OK;
+    m->cx = ncx;
+    m->cy = ncy;
+    auto devs = layer_devs(m);
+    timed(m, s, "reset_rect", [&] {
+        if (std::abs(sx) >= m->W || std::abs(sy) >= m->H) {
+            m->rx = 0;
+            m->ry = 0;
+            launch_reset_rect(s, m->grid(), 0, m->W, 0, m->H, m->h, m->v, m->cnt, m->clr, devs.data(),
+                              (int)devs.size());
+            return;
+        }
+        m->rx = ((m->rx + sx) % m->W + m->W) % m->W;
+        m->ry = ((m->ry + sy) % m->H + m->H) % m->H;
+        Grid g = m->grid();
+        if (sx > 0)
+            launch_reset_rect(s, g, m->W - sx, m->W, 0, m->H, m->h, m->v, m->cnt, m->clr, devs.data(), (int)devs.size());
+        else if (sx < 0)
+            launch_reset_rect(s, g, 0, -sx, 0, m->H, m->h, m->v, m->cnt, m->clr, devs.data(), (int)devs.size());
+        if (sy > 0)
+            launch_reset_rect(s, g, 0, m->W, m->H - sy, m->H, m->h, m->v, m->cnt, m->clr, devs.data(), (int)devs.size());
+        else if (sy < 0)
+            launch_reset_rect(s, g, 0, m->W, 0, -sy, m->h, m->v, m->cnt, m->clr, devs.data(), (int)devs.size());
+    });
+    return check_launch(m, "mem_move");
+}
+
+mem_status mem_input_pointcloud(mem_map* m, const float* xyz, int64_t n, const float* ch, int32_t c,
+                                const mem_binding* bind, int32_t n_bind, const float T_map_sensor[12],
+                                void* stream)
+{
+    if (mem_status st = usable(m)) return st;
+    if (n < 0) return fail(MEM_E_ARG, "n must be >= 0");
+    if (n > 0 && !xyz) return fail(MEM_E_ARG, "xyz is NULL");
+    if (c < 0 || (c > 0 && n > 0 && !ch)) return fail(MEM_E_ARG, "channels given without data");
+    if (n_bind < 0 || n_bind > kMaxBind || (n_bind > 0 && !bind))
+        return fail(MEM_E_ARG, "n_bind must be 0..%d with a binding array", kMaxBind);
+    if (mem_status st = check_pose(m, T_map_sensor, "T_map_sensor")) return st;
+    PointBinds pb{};
+    pb.n = n_bind;
+    pb.c_in = c;
+    for (int b = 0; b < n_bind; b++) {
+        const Layer* L = nullptr;
+        if (mem_status st = resolve_layer(m, bind[b].layer, &L)) return st;
+        if (bind[b].ch_first < 0 || bind[b].ch_count != L->C || bind[b].ch_first + bind[b].ch_count > c)
+            return fail(MEM_E_ARG, "binding %d: channels [%d, %d) do not fit %d inputs / layer of %d",
+                        b, bind[b].ch_first, bind[b].ch_first + bind[b].ch_count, c, L->C);
+        pb.b[b].layer = bind[b].layer - MEM_LAYER_USER0;
+        pb.b[b].ch_first = bind[b].ch_first;
+        pb.b[b].C = L->C;
+        pb.b[b].sum_off = pb.Cb;
+        pb.L[b] = L->dev();
+        pb.Cb += L->C;
+    }
+    pb.lds_ch = (pb.Cb > 0 && ingest_lds_bytes(pb.Cb) <= (size_t)m->max_lds) ? 1 : 0;
+    hipStream_t s = (hipStream_t)stream;
+    if (pb.Cb > m->chsum_planes) {
+        // Stream-ordered growth: wait for earlier users of the old buffer.
+        HIP_TRY(m, hipStreamSynchronize(s));
+        (void)hipFree(m->chsum);
+        m->chsum = nullptr;
+        m->chsum_planes = 0;
+        if (mem_status st = dev_alloc(m, &m->chsum, (size_t)pb.Cb * m->cells())) return st;
+        m->chsum_planes = pb.Cb;
+    }
+    Grid g = m->grid();
+    timed(m, s, "zero_accum", [&] { launch_zero_accum(s, g, m->cnt, m->wsum, m->ssum, m->clr, m->chsum, pb.Cb); });
+    Pose T;
+    memcpy(T.m, T_map_sensor, sizeof(T.m));
+    timed(m, s, "ingest", [&] {
+        launch_ingest(s, g, xyz, n, ch, T, m->c0, m->c1, m->mr2, pb, m->cnt, m->wsum, m->ssum, m->stash,
+                      m->chsum, m->stats);
+    });
+    if (m->clear_min > 0)
+        timed(m, s, "clear_march", [&] {
+            launch_clear_march(s, g, xyz, n, T, m->mr2, m->clear_margin, m->h, m->clr, m->stats);
+        });
+    timed(m, s, "finalize", [&] {
+        launch_finalize(s, g, m->cnt, m->wsum, m->ssum, m->stash, m->clr, m->clear_min, m->h, m->v,
+                        m->chsum, pb, m->stats);
+    });
+    return check_launch(m, "mem_input_pointcloud");
+}
+
+static mem_status check_camera(const mem_map* m, int32_t h, int32_t w, const float K[4],
+                               const float T[12], Camera* cam)
+{
+    if (h < 1 || w < 1 || (int64_t)h * w > (1ll << 30)) return fail(MEM_E_ARG, "image size %dx%d", w, h);
+    if (!K) return fail(MEM_E_ARG, "K is NULL");
+    for (int k = 0; k < 4; k++)
+        if (!std::isfinite(K[k])) return fail(MEM_E_ARG, "K must be finite");
+    if (!(K[0] > 0.0f) || !(K[1] > 0.0f)) return fail(MEM_E_ARG, "fx and fy must be positive");
+    if (mem_status st = check_pose(m, T, "T_map_cam")) return st;
+    memcpy(cam->T.m, T, sizeof(cam->T.m));
+    cam->fx = K[0];
+    cam->fy = K[1];
+    cam->cx = K[2];
+    cam->cy = K[3];
+    cam->h = h;
+    cam->w = w;
+    cam->min_depth = m->min_depth;
+    return MEM_OK;
+}
+
+mem_status mem_input_image(mem_map* m, const void* img, int32_t dtype, int32_t h, int32_t w, int32_t c,
+                           const int64_t strides[3], const float K[4], const float T_map_cam[12],
+                           const mem_binding* bind, int32_t n_bind, void* stream)
+{
+    if (mem_status st = usable(m)) return st;
+    if (!img) return fail(MEM_E_ARG, "img is NULL");
+    if (dtype != MEM_F32 && dtype != MEM_U8) return fail(MEM_E_ARG, "image dtype must be MEM_F32 or MEM_U8");
+    if (c < 1) return fail(MEM_E_ARG, "image needs at least one channel");
+    if (!strides || strides[0] < 0 || strides[1] < 0 || strides[2] < 0)
+        return fail(MEM_E_ARG, "strides must be non-negative");
+    if (n_bind < 0 || n_bind > kMaxBind || (n_bind > 0 && !bind))
+        return fail(MEM_E_ARG, "n_bind must be 0..%d with a binding array", kMaxBind);
+    Camera cam;
+    if (mem_status st = check_camera(m, h, w, K, T_map_cam, &cam)) return st;
+    for (int b = 0; b < n_bind; b++) {
+        const Layer* L = nullptr;
+        if (mem_status st = resolve_layer(m, bind[b].layer, &L)) return st;
+        if (bind[b].ch_first < 0 || bind[b].ch_count != L->C || bind[b].ch_first + bind[b].ch_count > c)
+            return fail(MEM_E_ARG, "binding %d does not fit the image / layer", b);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    Grid g = m->grid();
+    timed(m, s, "zero_count", [&] { launch_zero_int(s, m->pair_count, 1); });
+    timed(m, s, "project", [&] { launch_project(s, g, cam, m->h, m->pairs, m->pair_count, nullptr, m->stats); });
+    for (int b = 0; b < n_bind; b++) {
+        const Layer* L = nullptr;
+        resolve_layer(m, bind[b].layer, &L);
+        LayerDev d = L->dev();
+        timed(m, s, "gather_fuse", [&] {
+            launch_gather_fuse(s, m->pairs, m->pair_count, (int)m->cells(), img, dtype, strides[0],
+                               strides[1], strides[2], w, bind[b].ch_first, d);
+        });
+    }
+    return check_launch(m, "mem_input_image");
+}
+
+mem_status mem_get_layer(const mem_map* mc, int32_t layer, int32_t view, float* out, void* stream)
+{
+    mem_map* m = const_cast<mem_map*>(mc);
+    if (mem_status st = usable(m)) return st;
+    if (!out) return fail(MEM_E_ARG, "out is NULL");
+    LayerDev d{};
+    if (layer >= 0 && layer <= MEM_LAYER_CLEAR) {
+        if (view != MEM_VIEW_VALUE) return fail(MEM_E_ARG, "built-in layers have only the value view");
+    } else {
+        const Layer* L = nullptr;
+        if (mem_status st = resolve_layer(m, layer, &L)) return st;
+        bool ok = view == MEM_VIEW_VALUE || (view == MEM_VIEW_AUX && (L->rule == MEM_GAUSS || L->rule == MEM_DIRICHLET)) ||
+                  (view == MEM_VIEW_ARGMAX && L->rule == MEM_DIRICHLET);
+        if (!ok) return fail(MEM_E_ARG, "layer %d has no view %d", layer, view);
+        d = L->dev();
+    }
+    hipStream_t s = (hipStream_t)stream;
+    timed(m, s, "readout", [&] {
+        launch_readout(s, m->grid(), layer, view, m->h, m->v, m->cnt, m->clr, layer >= MEM_LAYER_USER0 ? &d : nullptr, out);
+    });
+    return check_launch(m, "mem_get_layer");
+}
+
+mem_status mem_set_layer(mem_map* m, int32_t layer, int32_t view, const float* in, void* stream)
+{
+    if (mem_status st = usable(m)) return st;
+    if (!in) return fail(MEM_E_ARG, "in is NULL");
+    LayerDev d{};
+    if (layer == MEM_LAYER_ELEVATION || layer == MEM_LAYER_VARIANCE) {
+        if (view != MEM_VIEW_VALUE) return fail(MEM_E_ARG, "built-in layers have only the value view");
+    } else if (layer >= 0 && layer < MEM_LAYER_USER0) {
+        return fail(MEM_E_ARG, "layer %d is not settable", layer);
+    } else {
+        const Layer* L = nullptr;
+        if (mem_status st = resolve_layer(m, layer, &L)) return st;
+        bool ok = (view == MEM_VIEW_VALUE && L->rule != MEM_DIRICHLET) ||
+                  (view == MEM_VIEW_AUX && (L->rule == MEM_GAUSS || L->rule == MEM_DIRICHLET));
+        if (!ok) return fail(MEM_E_ARG, "view %d of layer %d is not settable", view, layer);
+        d = L->dev();
+    }
+    hipStream_t s = (hipStream_t)stream;
+    timed(m, s, "setlayer", [&] {
+        launch_setlayer(s, m->grid(), layer, view, m->h, m->v, layer >= MEM_LAYER_USER0 ? &d : nullptr, in);
+    });
+    return check_launch(m, "mem_set_layer");
+}
+
+mem_status mem_debug_point_cells(const mem_map* mc, const float* xyz, int64_t n, const float T[12],
+                                 int32_t* out, void* stream)
+{
+    mem_map* m = const_cast<mem_map*>(mc);
+    if (mem_status st = usable(m)) return st;
+    if (n < 0 || (n > 0 && (!xyz || !out))) return fail(MEM_E_ARG, "bad points / output");
+    if (mem_status st = check_pose(m, T, "T_map_sensor")) return st;
+    Pose P;
+    memcpy(P.m, T, sizeof(P.m));
+    launch_point_cells((hipStream_t)stream, m->grid(), xyz, n, P, m->mr2, out);
+    return check_launch(m, "mem_debug_point_cells");
+}
+
+mem_status mem_debug_cell_pixels(const mem_map* mc, int32_t h, int32_t w, const float K[4],
+                                 const float T[12], int32_t* out, void* stream)
+{
+    mem_map* m = const_cast<mem_map*>(mc);
+    if (mem_status st = usable(m)) return st;
+    if (!out) return fail(MEM_E_ARG, "out is NULL");
+    Camera cam;
+    if (mem_status st = check_camera(m, h, w, K, T, &cam)) return st;
+    hipStream_t s = (hipStream_t)stream;
+    launch_zero_int(s, m->pair_count, 1);
+    launch_project(s, m->grid(), cam, m->h, m->pairs, m->pair_count, out, m->stats);
+    return check_launch(m, "mem_debug_cell_pixels");
+}
+
+mem_status mem_get_stats(mem_map* m, mem_stats* out, void* stream)
+{
+    if (mem_status st = usable(m)) return st;
+    if (!out) return fail(MEM_E_ARG, "out is NULL");
+    unsigned long long buf[kStats];
+    HIP_TRY(m, hipMemcpyAsync(buf, m->stats, sizeof buf, hipMemcpyDeviceToHost, (hipStream_t)stream));
+    HIP_TRY(m, hipStreamSynchronize((hipStream_t)stream));
+    int64_t* o = (int64_t*)out;
+    for (int k = 0; k < kStats; k++) o[k] = (int64_t)buf[k];
+    return MEM_OK;
+}
+
+mem_status mem_reset_stats(mem_map* m, void* stream)
+{
+    if (mem_status st = usable(m)) return st;
+    launch_zero_int((hipStream_t)stream, (int*)m->stats, 2 * kStats);
+    return check_launch(m, "mem_reset_stats");
+}
+
+mem_status mem_profile_enable(mem_map* m, int32_t on)
+{
+    if (mem_status st = usable(m)) return st;
+    if (!on) prof_drain(m);
+    m->prof = on != 0;
+    return MEM_OK;
+}
+
+mem_status mem_profile_read(mem_map* m, mem_kernel_time* out, int32_t max, int32_t* count)
+{
+    if (mem_status st = usable(m)) return st;
+    if (!count || (max > 0 && !out)) return fail(MEM_E_ARG, "NULL output");
+    prof_drain(m);
+    int k = 0;
+    for (auto& kv : m->totals) {
+        if (k < max) {
+            memset(out[k].name, 0, sizeof out[k].name);
+            strncpy(out[k].name, kv.first.c_str(), sizeof out[k].name - 1);
+            out[k].launches = kv.second.first;
+            out[k].total_ms = kv.second.second;
+        }
+        k++;
+    }
+    *count = k;
+    m->totals.clear();
+    return MEM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,289 @@
+"""Python binding of libmem.so (include/mem.h): argument marshalling only.
+
+Every computation runs in the HIP kernels of libmem.so.  torch supplies
+device memory (tensor data pointers) and the stream
+(``torch.cuda.current_stream().cuda_stream``).  There is no fallback: if the
+library is missing, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import torch  # imported first so that libmem.so binds to torch's HIP runtime
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmem.so")
+
+MEM_OK, MEM_E_ARG, MEM_E_NOMEM, MEM_E_HIP, MEM_E_STATE, MEM_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+MEM_LATEST, MEM_EXPAVG, MEM_GAUSS, MEM_DIRICHLET = 0, 1, 2, 3
+MEM_F32, MEM_BF16, MEM_FP8_E4M3, MEM_U8 = 0, 1, 2, 3
+MEM_LAYER_ELEVATION, MEM_LAYER_VARIANCE, MEM_LAYER_VALID, MEM_LAYER_HITS, MEM_LAYER_CLEAR = 0, 1, 2, 3, 4
+MEM_LAYER_USER0 = 8
+MEM_VIEW_VALUE, MEM_VIEW_AUX, MEM_VIEW_ARGMAX = 0, 1, 2
+
+STAT_FIELDS = ("points_in", "points_accepted", "dropped_nonfinite", "dropped_range", "dropped_outside",
+               "cells_touched", "cells_cleared", "ray_cells", "cells_in_view", "pairs_visible",
+               "occl_cells")
+
+# Exported symbols of include/mem.h.
+SYMBOLS = ("mem_create", "mem_destroy", "mem_move", "mem_input_pointcloud", "mem_input_image",
+           "mem_get_layer", "mem_set_layer", "mem_get_center", "mem_debug_point_cells",
+           "mem_debug_cell_pixels", "mem_get_stats", "mem_reset_stats", "mem_profile_enable",
+           "mem_profile_read", "mem_last_error")
+
+
+class mem_layer_desc(C.Structure):
+    _fields_ = [("channels", C.c_int32), ("rule", C.c_int32), ("storage", C.c_int32),
+                ("param", C.c_float), ("ch_scale", C.c_void_p)]
+
+
+class mem_params(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("resolution", C.c_float),
+                ("noise_c0", C.c_float), ("noise_c1", C.c_float), ("max_range", C.c_float),
+                ("clear_margin", C.c_float), ("clear_min_count", C.c_int32),
+                ("min_depth", C.c_float), ("n_layers", C.c_int32),
+                ("layers", C.POINTER(mem_layer_desc))]
+
+
+class mem_binding(C.Structure):
+    _fields_ = [("layer", C.c_int32), ("ch_first", C.c_int32), ("ch_count", C.c_int32)]
+
+
+class mem_stats(C.Structure):
+    _fields_ = [(f, C.c_int64) for f in STAT_FIELDS]
+
+
+class mem_kernel_time(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("total_ms", C.c_double)]
+
+
+class MemError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mem error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    """Loads libmem.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2309_16818_amd.build`")
+    L = C.CDLL(path)
+    P, I32, I64, F = C.c_void_p, C.c_int32, C.c_int64, C.c_float
+    sig = {
+        "mem_create": [C.POINTER(mem_params), P, C.POINTER(P)],
+        "mem_destroy": [P, P],
+        "mem_move": [P, F, F, P],
+        "mem_input_pointcloud": [P, P, I64, P, I32, C.POINTER(mem_binding), I32, P, P],
+        "mem_input_image": [P, P, I32, I32, I32, I32, P, P, P, C.POINTER(mem_binding), I32, P],
+        "mem_get_layer": [P, I32, I32, P, P],
+        "mem_set_layer": [P, I32, I32, P, P],
+        "mem_get_center": [P, C.POINTER(I32), C.POINTER(I32)],
+        "mem_debug_point_cells": [P, P, I64, P, P, P],
+        "mem_debug_cell_pixels": [P, I32, I32, P, P, P, P],
+        "mem_get_stats": [P, C.POINTER(mem_stats), P],
+        "mem_reset_stats": [P, P],
+        "mem_profile_enable": [P, I32],
+        "mem_profile_read": [P, C.POINTER(mem_kernel_time), I32, C.POINTER(I32)],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = C.c_int32
+    L.mem_last_error.restype = C.c_char_p
+    L.mem_last_error.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(code: int):
+    if code != MEM_OK:
+        raise MemError(code, load().mem_last_error().decode())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _floats(vals, n):
+    a = (C.c_float * n)(*[float(v) for v in vals])
+    return a
+
+
+def _pose(T):
+    t = torch.as_tensor(T, dtype=torch.float32).reshape(-1).tolist()
+    if len(t) != 12:
+        raise ValueError("pose must be 3x4")
+    return _floats(t, 12)
+
+
+def _bindings(bind):
+    bind = list(bind or [])
+    arr = (mem_binding * max(1, len(bind)))()
+    for i, (layer, f, cnt) in enumerate(bind):
+        arr[i] = mem_binding(int(layer), int(f), int(cnt))
+    return arr, len(bind)
+
+
+def _dev_ptr(t: torch.Tensor, what: str):
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a device tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+@dataclass
+class Layer:
+    channels: int
+    rule: int
+    param: float
+    storage: int = MEM_F32
+    ch_scale: list | None = None
+
+
+@dataclass
+class MapParams:
+    width: int
+    height: int
+    resolution: float
+    noise_c0: float = 0.01
+    noise_c1: float = 0.001
+    max_range: float = 100.0
+    clear_margin: float = 0.05
+    clear_min_count: int = 1
+    min_depth: float = 0.1
+    layers: list = field(default_factory=list)
+
+
+class Map:
+    """A map on the current HIP device (wraps mem_create ... mem_destroy)."""
+
+    def __init__(self, params: MapParams, stream=None):
+        L = load()
+        self.params = params
+        self.W, self.H = params.width, params.height
+        self.layers = [l if isinstance(l, Layer) else Layer(*l) for l in params.layers]
+        descs = (mem_layer_desc * max(1, len(self.layers)))()
+        self._scales = []
+        for i, l in enumerate(self.layers):
+            sc = None
+            if l.ch_scale is not None:
+                sc = _floats(l.ch_scale, l.channels)
+                self._scales.append(sc)
+            descs[i] = mem_layer_desc(l.channels, l.rule, l.storage, l.param,
+                                      C.cast(sc, C.c_void_p) if sc is not None else None)
+        p = mem_params(params.width, params.height, params.resolution, params.noise_c0,
+                       params.noise_c1, params.max_range, params.clear_margin,
+                       params.clear_min_count, params.min_depth, len(self.layers), descs)
+        h = C.c_void_p()
+        _check(L.mem_create(C.byref(p), _stream(stream), C.byref(h)))
+        self._h = h
+
+    def close(self, stream=None):
+        if getattr(self, "_h", None):
+            load().mem_destroy(self._h, _stream(stream))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- update ---------------------------------------------------------------
+    def move(self, x, y, stream=None):
+        _check(load().mem_move(self._h, float(x), float(y), _stream(stream)))
+
+    def input_pointcloud(self, xyz: torch.Tensor, T, ch: torch.Tensor | None = None, bind=(),
+                         stream=None):
+        if xyz.dtype != torch.float32 or xyz.dim() != 2 or xyz.shape[1] != 3 or not xyz.is_contiguous():
+            raise ValueError("xyz must be a contiguous float32 [n, 3] tensor")
+        n = xyz.shape[0]
+        c, chp = 0, None
+        if ch is not None:
+            if ch.dtype != torch.float32 or ch.dim() != 2 or ch.shape[0] != n or not ch.is_contiguous():
+                raise ValueError("ch must be a contiguous float32 [n, c] tensor")
+            c, chp = ch.shape[1], _dev_ptr(ch, "ch")
+        b, nb = _bindings(bind)
+        _check(load().mem_input_pointcloud(self._h, _dev_ptr(xyz, "xyz"), n, chp, c, b, nb,
+                                           _pose(T), _stream(stream)))
+
+    def input_image(self, img: torch.Tensor, K, T, bind=(), stream=None):
+        if img.dim() != 3:
+            raise ValueError("img must be [h, w, c] (any strides)")
+        if img.dtype == torch.uint8:
+            dt = MEM_U8
+        elif img.dtype == torch.float32:
+            dt = MEM_F32
+        else:
+            raise ValueError("img must be uint8 or float32")
+        h, w, c = img.shape
+        st = (C.c_int64 * 3)(*img.stride())
+        b, nb = _bindings(bind)
+        _check(load().mem_input_image(self._h, _dev_ptr(img, "img"), dt, h, w, c, st,
+                                      _floats(K, 4), _pose(T), b, nb, _stream(stream)))
+
+    # -- read-out -------------------------------------------------------------
+    def channels(self, layer: int, view: int = MEM_VIEW_VALUE) -> int:
+        if layer < MEM_LAYER_USER0:
+            return 1
+        l = self.layers[layer - MEM_LAYER_USER0]
+        if view == MEM_VIEW_ARGMAX or (view == MEM_VIEW_AUX and l.rule == MEM_GAUSS):
+            return 1
+        return l.channels
+
+    def get_layer(self, layer: int, view: int = MEM_VIEW_VALUE, out: torch.Tensor | None = None,
+                  stream=None) -> torch.Tensor:
+        Cn = self.channels(layer, view)
+        if out is None:
+            out = torch.empty((self.H, self.W, Cn), dtype=torch.float32, device="cuda")
+        _check(load().mem_get_layer(self._h, layer, view, _dev_ptr(out, "out"), _stream(stream)))
+        return out if layer >= MEM_LAYER_USER0 else out.reshape(self.H, self.W)
+
+    def set_layer(self, layer: int, view: int, values: torch.Tensor, stream=None):
+        v = values.to(device="cuda", dtype=torch.float32).contiguous()
+        if v.numel() != self.H * self.W * self.channels(layer, view):
+            raise ValueError("values have the wrong size")
+        _check(load().mem_set_layer(self._h, layer, view, _dev_ptr(v, "values"), _stream(stream)))
+        torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+
+    def center(self):
+        cx, cy = C.c_int32(), C.c_int32()
+        _check(load().mem_get_center(self._h, C.byref(cx), C.byref(cy)))
+        return cx.value, cy.value
+
+    def debug_point_cells(self, xyz: torch.Tensor, T, stream=None) -> torch.Tensor:
+        out = torch.empty(xyz.shape[0], dtype=torch.int32, device="cuda")
+        _check(load().mem_debug_point_cells(self._h, _dev_ptr(xyz.contiguous(), "xyz"), xyz.shape[0],
+                                            _pose(T), _dev_ptr(out, "out"), _stream(stream)))
+        return out
+
+    def debug_cell_pixels(self, h: int, w: int, K, T, stream=None) -> torch.Tensor:
+        out = torch.empty((self.H, self.W), dtype=torch.int32, device="cuda")
+        _check(load().mem_debug_cell_pixels(self._h, h, w, _floats(K, 4), _pose(T),
+                                            _dev_ptr(out, "out"), _stream(stream)))
+        return out
+
+    def stats(self, stream=None) -> dict:
+        s = mem_stats()
+        _check(load().mem_get_stats(self._h, C.byref(s), _stream(stream)))
+        return {f: getattr(s, f) for f in STAT_FIELDS}
+
+    def reset_stats(self, stream=None):
+        _check(load().mem_reset_stats(self._h, _stream(stream)))
+
+    def profile_enable(self, on: bool = True):
+        _check(load().mem_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        arr = (mem_kernel_time * 64)()
+        n = C.c_int32()
+        _check(load().mem_profile_read(self._h, arr, 64, C.byref(n)))
+        return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(min(n.value, 64))}

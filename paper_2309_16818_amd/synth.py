@@ -387,10 +387,17 @@ def small_frames(seed: int = 0, n_frames: int = 10, n_points: int = 20000,
     return ter, frames
 
 
-def full_frames(seed: int = 1, n_frames: int = 2, device=None, lidar=(128, 2048),
-                depth_hw=(480, 640), rgb_hw=(480, 640), feat_hw=(120, 160), n_feat=64,
-                n_cls=20):
+def full_frames(seed: int = 1, n_frames: int = 2, device=None, **kw):
     """The full-rate single-robot workload (see module docstring)."""
+    frames = list(iter_full_frames(seed, n_frames, device, **kw))
+    return frames[0][0] if frames else None, [f for _, f in frames]
+
+
+def iter_full_frames(seed: int = 1, n_frames: int = 2, device=None, lidar=(128, 2048),
+                     depth_hw=(480, 640), rgb_hw=(480, 640), feat_hw=(120, 160), n_feat=64,
+                     n_cls=20):
+    """Yields (terrain, frame) of the full-rate single-robot workload one
+    frame at a time."""
     ss = np.random.SeedSequence(seed)
     rng_t, rng_p, rng_f = [np.random.Generator(np.random.PCG64(s)) for s in ss.spawn(3)]
     ter = make_terrain(rng_t, extent=20.0)
@@ -400,7 +407,6 @@ def full_frames(seed: int = 1, n_frames: int = 2, device=None, lidar=(128, 2048)
     rh, rw = rgb_hw
     Kr = (400.0, 400.0, (rw - 1) / 2.0, (rh - 1) / 2.0)
     Kf = scaled_intrinsics(Kr, feat_hw[1] / rw)
-    frames = []
     for (x, y, yaw) in poses:
         zg = float(ter.height(x, y))
         base = np.array([x, y, zg])
@@ -415,5 +421,4 @@ def full_frames(seed: int = 1, n_frames: int = 2, device=None, lidar=(128, 2048)
             cams.append(dict(T=Tc, K=Kr, rgb=render_rgb(ter, Tc, Kr, rh, rw, 10.0, device=device),
                              classes=class_image(rng_f, rh, rw, n_cls),
                              K_feat=Kf, features=feature_image(rng_f, feat_hw[0], feat_hw[1], n_feat)))
-        frames.append(dict(pose=(x, y, yaw), clouds=clouds, cameras=cams))
-    return ter, frames
+        yield ter, dict(pose=(x, y, yaw), clouds=clouds, cameras=cams)
