@@ -79,10 +79,9 @@ def run_frame(m, f):
     m.move(x, y)
     for c in f["clouds"]:
         m.input_pointcloud(c["xyz"], c["T"])
-    for c in f["cameras"]:
-        m.input_image(c["rgb"], c["K"], c["T"], bind=[(8, 0, 3)])
-        m.input_image(c["features"], c["K_feat"], c["T"], bind=[(9, 0, 64)])
-        m.input_image(c["classes"], c["K"], c["T"], bind=[(10, 0, 20)])
+    for c in f["cameras"]:  # RGB, features and classes share the camera pose
+        m.input_images([(c["rgb"], c["K"], [(8, 0, 3)]), (c["features"], c["K_feat"], [(9, 0, 64)]),
+                        (c["classes"], c["K"], [(10, 0, 20)])], c["T"])
 
 
 def make_map():

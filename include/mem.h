@@ -223,6 +223,26 @@ mem_status mem_input_image(mem_map* map, const void* img, int32_t dtype,
                            const mem_binding* bind, int32_t n_bind,
                            void* stream);
 
+/* One image of a mem_input_images call (same meaning as the arguments of
+ * mem_input_image). */
+typedef struct mem_image {
+    const void* data;       /* device */
+    int32_t dtype, h, w, c;
+    int64_t strides[3];
+    float K[4];             /* fx, fy, cx, cy of this image's resolution */
+    const mem_binding* bind;/* host */
+    int32_t n_bind;
+} mem_image;
+
+/* Fuses up to 4 images taken from one camera pose (Sec. III-B), e.g. an RGB
+ * image and the feature and class maps computed from it at other
+ * resolutions.  The result equals calling mem_input_image for each image in
+ * order: fusing an image does not change heights, so the occlusion walk of a
+ * cell is shared by all images and evaluated once; each image applies its
+ * own frustum test and pixel. */
+mem_status mem_input_images(mem_map* map, const mem_image* images, int32_t n_images,
+                            const float T_map_cam[12], void* stream);
+
 /* Writes a layer view to `out` (device, H x W x C float, C = 1 for the
  * built-in layers and for MEM_VIEW_ARGMAX).  See the view enum. */
 mem_status mem_get_layer(const mem_map* map, int32_t layer, int32_t view,
@@ -266,6 +286,81 @@ typedef struct mem_kernel_time {
 mem_status mem_profile_enable(mem_map* map, int32_t on);
 mem_status mem_profile_read(mem_map* map, mem_kernel_time* out, int32_t max,
                             int32_t* count);
+
+/* ---------------------------------------------------------------------- */
+/* Batches of independent maps                                             */
+/* ---------------------------------------------------------------------- */
+
+/* Many independent robot-centric maps (for example one per simulated robot
+ * in a learning task, Sec. I) of different sizes, updated together.  One
+ * step of a batch applies, to every map m, exactly the single-map update
+ *   mem_move(robot_xy[m]); mem_input_pointcloud(map m's points, no channels);
+ *   mem_input_image(map m's image)          (if the batch has cameras)
+ * with the same decisions and arithmetic as mem_*; maps share no state.
+ * The step is one launch of a captured HIP graph whose stages are persistent
+ * work-stealing kernels over (map, chunk) and (map, tile) items of every
+ * map at once; chunk, tile and grid sizes come from mem_batch_tune. */
+typedef struct mem_batch mem_batch;
+
+typedef struct mem_batch_params {
+    int32_t n_maps;           /* 1 .. 65536                                      */
+    const int32_t* width;     /* host, n_maps grid widths (1 .. 16384)           */
+    const int32_t* height;    /* host, n_maps grid heights                       */
+    float resolution, noise_c0, noise_c1, max_range, clear_margin;
+    int32_t clear_min_count;
+    float min_depth;
+    int32_t n_layers;         /* the same user layers in every map               */
+    const mem_layer_desc* layers;
+    int64_t max_points;       /* most points a step may pass over all maps       */
+    int32_t cam_h, cam_w, cam_c; /* every map's image size, or 0 0 0: no cameras */
+    int32_t cam_dtype;        /* MEM_F32 or MEM_U8                               */
+    int32_t n_img_bind;       /* image channel bindings shared by all maps       */
+    const mem_binding* img_bind;
+} mem_batch_params;
+
+typedef struct mem_batch_input {
+    const float* robot_xy;    /* host, n_maps x 2                                */
+    const float* xyz;         /* device, all maps' points, n x 3 (sensor frames) */
+    const int64_t* offsets;   /* host, n_maps + 1: map m owns points
+                                 [offsets[m], offsets[m + 1]), offsets[0] = 0     */
+    const float* T_map_sensor;/* host, n_maps x 12                               */
+    const void* images;       /* device, n_maps x cam_h x cam_w x cam_c (HWC), or NULL */
+    const float* K;           /* host, n_maps x 4                                */
+    const float* T_map_cam;   /* host, n_maps x 12                               */
+} mem_batch_input;
+
+/* Sizes the autotuner chooses (read back with mem_batch_get_tuning). */
+typedef struct mem_batch_tuning {
+    int32_t chunk;            /* points per ingest / clearing work item          */
+    int32_t wg_per_cu;        /* persistent workgroups per compute unit          */
+    int32_t tile;             /* side of the square cell tiles of projection     */
+    int32_t graph;            /* 1: the step runs as a captured HIP graph        */
+    double step_ms;           /* measured time of the chosen configuration       */
+} mem_batch_tuning;
+
+mem_status mem_batch_create(const mem_batch_params* params, void* stream, mem_batch** out);
+mem_status mem_batch_destroy(mem_batch* batch, void* stream);
+
+/* One update of every map.  Host arrays are read during the call; device
+ * arrays must stay valid until the step completes on `stream`. */
+mem_status mem_batch_step(mem_batch* batch, const mem_batch_input* in, void* stream);
+
+/* Times candidate (chunk, wg_per_cu, tile) settings on `in` (each runs a few
+ * steps; the maps are restored afterwards) and keeps the fastest.  The
+ * choice never changes integer results. */
+mem_status mem_batch_tune(mem_batch* batch, const mem_batch_input* in, void* stream);
+mem_status mem_batch_set_tuning(mem_batch* batch, const mem_batch_tuning* t);
+mem_status mem_batch_get_tuning(const mem_batch* batch, mem_batch_tuning* out);
+
+/* Per-map views, same meaning and layout as mem_get_layer / mem_set_layer /
+ * mem_get_center for map `map`. */
+mem_status mem_batch_get_layer(const mem_batch* batch, int32_t map, int32_t layer, int32_t view,
+                               float* out, void* stream);
+mem_status mem_batch_set_layer(mem_batch* batch, int32_t map, int32_t layer, int32_t view,
+                               const float* in, void* stream);
+mem_status mem_batch_get_center(const mem_batch* batch, int32_t map, int32_t* cx, int32_t* cy);
+mem_status mem_batch_get_stats(mem_batch* batch, mem_stats* out, void* stream);
+mem_status mem_batch_reset_stats(mem_batch* batch, void* stream);
 
 /* Message of the calling thread's last failure ("" if none). */
 const char* mem_last_error(void);

@@ -698,6 +698,11 @@ int orc_set_layer(orc_map* m, int layer, int view, const double* in)
             if (!isnan(in[j])) m->v[j] = in[j];
         return 0;
     }
+    if ((layer == ORC_LAYER_HITS || layer == ORC_LAYER_CLEAR) && view == ORC_VIEW_VALUE) {
+        int32_t* dst = (layer == ORC_LAYER_HITS) ? m->hits : m->clear;
+        for (long j = 0; j < HW; j++) dst[j] = (int32_t)in[j];
+        return 0;
+    }
     int l = layer - ORC_LAYER_USER0;
     if (l < 0 || l >= m->nL) return -1;
     orc_layer* L = &m->L[l];

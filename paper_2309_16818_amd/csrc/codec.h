@@ -11,6 +11,7 @@
 #include <cstdint>
 
 #include "../../include/mem.h"
+#include "mem_internal.h"
 
 namespace memk {
 
@@ -124,12 +125,26 @@ __device__ __forceinline__ void layer_store(void* val, int storage, const float*
     }
 }
 
-// Adds v of every lane of the wave into *g with one atomic per wave.  All
-// lanes of the wave must call it.
-__device__ __forceinline__ void wave_stat_add(unsigned long long* g, int v)
+// Sums v[k] over the workgroup and adds each sum to counter id[k] with one
+// atomic per workgroup.  Every thread of the workgroup must call it.
+template <int N>
+__device__ __forceinline__ void block_stats(unsigned long long* stats, const int (&id)[N], int (&v)[N])
 {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if (__lane_id() == 0 && v != 0) atomicAdd(g, (unsigned long long)v);
+    __shared__ int s[N];
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    if (tid < N) s[tid] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        int x = v[k];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        if (__lane_id() == 0 && x != 0) atomicAdd(&s[k], x);
+    }
+    __syncthreads();
+    if (tid < N && s[tid] != 0) {
+        int slot = (int)((blockIdx.x + gridDim.x * blockIdx.y) % kStatSlots);
+        atomicAdd(&stats[id[tid] * kStatSlots + slot], (unsigned long long)s[tid]);
+    }
 }
 
 }  // namespace memk

@@ -121,4 +121,71 @@ __device__ __forceinline__ float ray_height(int k_abs, float res, float s_major,
     return s_z + dz * t;
 }
 
+// A ray from s (map frame) to p over the Bresenham cells between the
+// sensor's cell and the target cell.
+struct Ray {
+    LineWalk L;
+    int o_major;       // absolute lattice index of logical 0 along the major axis
+    float s_major, inv_d, s_z, dz;
+    bool all_inside;   // both ends inside the grid, so every cell between is
+    __device__ __forceinline__ Ray(const Grid& g, int ax, int ay, int bx, int by, float sx,
+                                   float sy, float sz, float px, float py, float pz)
+        : L(ax, ay, bx, by)
+    {
+        o_major = L.xmajor ? g.ox : g.oy;
+        s_major = L.xmajor ? sx : sy;
+        const float p_major = L.xmajor ? px : py;
+        inv_d = 1.0f / (p_major - s_major);
+        s_z = sz;
+        dz = pz - sz;
+        all_inside = ax >= 0 && ax < g.W && ay >= 0 && ay < g.H;
+    }
+};
+
+// Visits the cells strictly between the ray's end cells, in order, U at a
+// time: the U cells' heights are loaded together before any of them is
+// tested, so a lane keeps U loads in flight.  visit(st, h, z_ray) returns
+// true to stop the walk.  Cells outside the grid are skipped.  Returns the
+// number of in-grid cells loaded.
+template <int U, class Visit>
+__device__ __forceinline__ int walk_cells(const Grid& g, Ray& r, const float* __restrict__ h,
+                                          Visit&& visit)
+{
+    int rem = r.L.steps - 1;
+    int loaded = 0;
+    while (rem > 0) {
+        int st[U];
+        float zr[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            st[u] = -1;
+            zr[u] = 0.0f;
+            if (u < rem) {
+                r.L.step();
+                const bool in = r.all_inside ||
+                                (r.L.x >= 0 && r.L.x < g.W && r.L.y >= 0 && r.L.y < g.H);
+                if (in) {
+                    st[u] = storage_index(g, r.L.x, r.L.y);
+                    zr[u] = ray_height(r.o_major + (r.L.xmajor ? r.L.x : r.L.y), g.res, r.s_major,
+                                       r.inv_d, r.s_z, r.dz);
+                }
+            }
+        }
+        float hk[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) hk[u] = st[u] >= 0 ? h[st[u]] : __builtin_nanf("");
+        bool stop = false;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            if (st[u] >= 0) {
+                loaded++;
+                if (!stop && visit(st[u], hk[u], zr[u])) stop = true;
+            }
+        }
+        if (stop) break;
+        rem -= U;
+    }
+    return loaded;
+}
+
 }  // namespace memk

@@ -1,17 +1,15 @@
-// k_image.hip - image path of the map update (Sec. III-B, Fig. 3).
+// k_image.hip - image path of the map update (Sec. III-B, Fig. 3), one map.
 //
 //   k_project      one lane per cell (16x16 cell tiles, so neighbouring rays
-//                  share the cells they walk): frustum test, pin-hole pixel,
-//                  Bresenham occlusion walk against the map heights, and a
-//                  wave-aggregated append of visible (cell, pixel) pairs.
-//   k_gather_fuse  grid-stride over the visible pairs; a group of lanes
-//                  (a power of two >= the layer's channels, at most 64) reads
-//                  one pixel's channels and read-modify-writes the cell's
-//                  channel-contiguous layer row with the layer's rule.
-#include "codec.h"
-#include "fuse.h"
-#include "geom.h"
-#include "mem_internal.h"
+//                  share the cells they walk): frustum test and pin-hole pixel
+//                  of every image of one camera pose, one Bresenham occlusion
+//                  walk against the map heights, and a wave-aggregated append
+//                  of visible (cell, pixel) pairs per image.
+//   k_gather_fuse  grid-stride over one image's visible pairs; a group of
+//                  lanes (a power of two >= the layer's channels, at most 64)
+//                  reads one pixel's channels and read-modify-writes the
+//                  cell's channel-contiguous layer row with the layer's rule.
+#include "update.h"
 
 namespace memk {
 
@@ -19,93 +17,33 @@ namespace {
 
 constexpr int kTile = 16;
 
+// Image k's visible pairs go to pairs[k * cap ...] and their number to
+// count[k].  dbg (optional) receives image 0's code per logical cell.
 __global__ __launch_bounds__(256) void k_project(Grid g, Camera cam, const float* __restrict__ h,
-                                                 int2* __restrict__ pairs, int* __restrict__ count,
-                                                 int32_t* __restrict__ dbg,
+                                                 int2* __restrict__ pairs, int cap,
+                                                 int* __restrict__ count, int32_t* __restrict__ dbg,
                                                  unsigned long long* __restrict__ stats)
 {
     const int ix = blockIdx.x * kTile + threadIdx.x;
     const int iy = blockIdx.y * kTile + threadIdx.y;
-    const float* T = cam.T.m;
-    int code = -1, st = 0, visited = 0, in_view = 0;
+    int code[kMaxImages];
+#pragma unroll
+    for (int k = 0; k < kMaxImages; k++) code[k] = -1;
+    int st = 0, visited = 0, in_view = 0, n_vis = 0;
     if (ix < g.W && iy < g.H) {
         st = storage_index(g, ix, iy);
-        float hj = h[st];
-        if (!isnan(hj)) {
-            float xc = ((float)(g.ox + ix) + 0.5f) * g.res;
-            float yc = ((float)(g.oy + iy) + 0.5f) * g.res;
-            float dx = xc - T[3], dy = yc - T[7], dz = hj - T[11];
-            float P[3];
+        visited = project_cell(g, cam, h, ix, iy, st, code, in_view);
+    }
 #pragma unroll
-            for (int k = 0; k < 3; k++) {  // R^T d
-                float a = T[0 + k] * dx;
-                float b = T[4 + k] * dy;
-                float c = T[8 + k] * dz;
-                float s = a + b;
-                P[k] = s + c;
-            }
-            code = -2;
-            if (P[2] > cam.min_depth) {
-                float u = cam.fx * P[0];
-                u = u / P[2];
-                u = u + cam.cx;
-                float v = cam.fy * P[1];
-                v = v / P[2];
-                v = v + cam.cy;
-                float uf = floorf(u + 0.5f);
-                float vf = floorf(v + 0.5f);
-                if (uf >= 0.0f && uf < (float)cam.w && vf >= 0.0f && vf < (float)cam.h) {
-                    in_view = 1;
-                    int ax, ay;
-                    lattice_cell(g, T[3], T[7], ax, ay);
-                    LineWalk L(ax, ay, ix, iy);
-                    const float s_major = L.xmajor ? T[3] : T[7];
-                    const float p_major = L.xmajor ? xc : yc;
-                    const int o_major = L.xmajor ? g.ox : g.oy;
-                    const float inv_d = 1.0f / (p_major - s_major);
-                    const float dzr = hj - T[11];
-                    bool occluded = false;
-                    for (int s = 1; s < L.steps; s++) {
-                        L.step();
-                        if (L.x < 0 || L.x >= g.W || L.y < 0 || L.y >= g.H) continue;
-                        visited++;
-                        float hk = h[storage_index(g, L.x, L.y)];
-                        float zr = ray_height(o_major + (L.xmajor ? L.x : L.y), g.res, s_major,
-                                              inv_d, T[11], dzr);
-                        if (hk >= zr) {  // NaN (no height) never occludes
-                            occluded = true;
-                            break;
-                        }
-                    }
-                    code = occluded ? -3 : (int)vf * cam.w + (int)uf;
-                }
-            }
-        }
+    for (int k = 0; k < kMaxImages; k++) {
+        if (k >= cam.n) break;
+        n_vis += code[k] >= 0 ? 1 : 0;
+        append_pair(code[k] >= 0, st, code[k], pairs + (int64_t)k * cap, &count[k]);
     }
-    const bool vis = code >= 0;
-    unsigned long long mask = __ballot(vis);
-    if (mask) {
-        int lane = __lane_id();
-        int leader = __ffsll((long long)mask) - 1;
-        int base = 0;
-        if (lane == leader) base = atomicAdd(count, __popcll(mask));
-        base = __shfl(base, leader);
-        if (vis) {
-            int rank = __popcll(mask & ((1ull << lane) - 1ull));
-            pairs[base + rank] = make_int2(st, code);
-        }
-    }
-    if (dbg && ix < g.W && iy < g.H) dbg[iy * g.W + ix] = code;
-    wave_stat_add(&stats[ST_IN_VIEW], in_view);
-    wave_stat_add(&stats[ST_VISIBLE], vis ? 1 : 0);
-    wave_stat_add(&stats[ST_OCCL_CELLS], visited);
-}
-
-template <int IMG>
-__device__ __forceinline__ float pixel_value(const void* img, int64_t off)
-{
-    if (IMG == MEM_U8) return (float)((const uint8_t*)img)[off] / 255.0f;
-    return ((const float*)img)[off];
+    if (dbg && ix < g.W && iy < g.H) dbg[iy * g.W + ix] = code[0];
+    const int ids[3] = {ST_IN_VIEW, ST_VISIBLE, ST_OCCL_CELLS};
+    int vals[3] = {in_view, n_vis, visited};
+    block_stats(stats, ids, vals);
 }
 
 template <int IMG, int S>
@@ -123,24 +61,9 @@ __global__ __launch_bounds__(256) void k_gather_fuse(const int2* __restrict__ pa
     const int ppw = 64 >> lpp_log2;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const int C = L.C;
     for (int64_t pbase = wave * ppw; pbase < N; pbase += nwaves * ppw) {
-        int64_t p = pbase + sub;
-        if (p >= N) continue;
-        int2 pr = pairs[p];
-        const int st = pr.x;
-        const int row = pr.y / w, col = pr.y - (pr.y / w) * w;
-        const int64_t pix = (int64_t)row * s0 + (int64_t)col * s1 + (int64_t)ch_first * s2;
-        GaussCoef gc{0.0f, 1.0f, 0.0f, true};
-        if (L.rule == MEM_GAUSS) gc = gauss_coef(L.param, L.var[st], 1);
-        for (int q = q0; q < C; q += LPP) {
-            float m = pixel_value<IMG>(img, pix + (int64_t)q * s2);
-            int64_t idx = (int64_t)st * C + q;
-            float old = Store<S>::load(L.val, idx, S == MEM_FP8_E4M3 ? L.scale[q] : 1.0f);
-            float nv = fuse_value(L.rule, L.param, old, m, m, gc);
-            Store<S>::store(L.val, idx, nv, S == MEM_FP8_E4M3 ? L.scale[q] : 1.0f);
-        }
-        if (L.rule == MEM_GAUSS && q0 == 0) L.var[st] = gc.var;
+        const int64_t p = pbase + sub;
+        if (p < N) gather_pair<IMG, S>(pairs[p], img, s0, s1, s2, w, ch_first, L, q0, LPP);
     }
 }
 
@@ -158,10 +81,11 @@ void launch_zero_int(hipStream_t s, int* p, int n)
 }
 
 void launch_project(hipStream_t s, const Grid& g, const Camera& cam, const float* h, int2* pairs,
-                    int* count, int32_t* dbg, unsigned long long* stats)
+                    int cap, int* count, int32_t* dbg, unsigned long long* stats)
 {
     dim3 grid((g.W + kTile - 1) / kTile, (g.H + kTile - 1) / kTile);
-    hipLaunchKernelGGL(k_project, grid, dim3(kTile, kTile), 0, s, g, cam, h, pairs, count, dbg, stats);
+    hipLaunchKernelGGL(k_project, grid, dim3(kTile, kTile), 0, s, g, cam, h, pairs, cap, count, dbg,
+                       stats);
 }
 
 void launch_gather_fuse(hipStream_t s, const int2* pairs, const int* count, int max_pairs,

@@ -1,44 +1,28 @@
 // k_map.hip - grid maintenance: resetting cells that enter the moving grid,
 // and the layer read-out / write-in views.
-#include "codec.h"
-#include "geom.h"
-#include "mem_internal.h"
+#include "update.h"
 
 namespace memk {
 
 namespace {
 
 constexpr float kNaN = __builtin_nanf("");
-constexpr float kInf = __builtin_inff();
 
 struct LayerSet {
     LayerDev L[32];
     int n;
 };
 
-// Empty cell: no height, never observed layers, Dirichlet alpha_0.
+// Resets the logical rectangle [x0, x1) x [y0, y1): one thread per cell,
+// rows along blockIdx.y.
 __global__ __launch_bounds__(256) void k_reset_rect(Grid g, int x0, int x1, int y0, int y1,
                                                     float* __restrict__ h, float* __restrict__ v,
                                                     int* __restrict__ cnt, int* __restrict__ clr,
                                                     LayerSet ls)
 {
-    const int w = x1 - x0;
-    const int64_t total = (int64_t)w * (y1 - y0);
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        int ix = x0 + (int)(k % w), iy = y0 + (int)(k / w);
-        int st = storage_index(g, ix, iy);
-        h[st] = kNaN;
-        v[st] = kInf;
-        cnt[st] = 0;
-        clr[st] = 0;
-        for (int l = 0; l < ls.n; l++) {
-            const LayerDev& L = ls.L[l];
-            float init = (L.rule == MEM_DIRICHLET) ? L.param : kNaN;
-            for (int q = 0; q < L.C; q++) layer_store(L.val, L.storage, L.scale, (int64_t)st * L.C + q, q, init);
-            if (L.rule == MEM_GAUSS) L.var[st] = kInf;
-        }
-    }
+    const int ix = x0 + blockIdx.x * blockDim.x + threadIdx.x;
+    for (int iy = y0 + blockIdx.y; iy < y1; iy += gridDim.y)
+        if (ix < x1) reset_cell(storage_index(g, ix, iy), h, v, cnt, clr, ls.L, ls.n);
 }
 
 // out[(iy*W + ix)*C + q], logical order.  layer < 8: built-in layers.
@@ -130,11 +114,9 @@ void launch_reset_rect(hipStream_t s, const Grid& g, int x0, int x1, int y0, int
     LayerSet ls;
     ls.n = nL;
     for (int l = 0; l < nL; l++) ls.L[l] = L[l];
-    int64_t total = (int64_t)(x1 - x0) * (y1 - y0);
-    int64_t b = (total + 255) / 256;
-    if (b > 4096) b = 4096;
-    hipLaunchKernelGGL(k_reset_rect, dim3((unsigned)b), dim3(256), 0, s, g, x0, x1, y0, y1, h, v, cnt,
-                       clr, ls);
+    const int bx = 64;
+    dim3 grid((unsigned)((x1 - x0 + bx - 1) / bx), (unsigned)(y1 - y0 < 2048 ? y1 - y0 : 2048));
+    hipLaunchKernelGGL(k_reset_rect, grid, dim3(bx), 0, s, g, x0, x1, y0, y1, h, v, cnt, clr, ls);
 }
 
 void launch_readout(hipStream_t s, const Grid& g, int layer, int view, const float* h,

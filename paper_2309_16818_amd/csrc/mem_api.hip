@@ -330,8 +330,8 @@ mem_status mem_create(const mem_params* p, void* stream, mem_map** out)
     if ((st = dev_alloc(m, &m->h, HW)) || (st = dev_alloc(m, &m->v, HW)) ||
         (st = dev_alloc(m, &m->cnt, HW)) || (st = dev_alloc(m, &m->clr, HW)) ||
         (st = dev_alloc(m, &m->wsum, HW)) || (st = dev_alloc(m, &m->ssum, HW)) ||
-        (st = dev_alloc(m, &m->stash, HW)) || (st = dev_alloc(m, &m->pairs, HW)) ||
-        (st = dev_alloc(m, &m->pair_count, 1)) || (st = dev_alloc(m, &m->stats, kStats))) {
+        (st = dev_alloc(m, &m->stash, HW)) || (st = dev_alloc(m, &m->pairs, HW * kMaxImages)) ||
+        (st = dev_alloc(m, &m->pair_count, kMaxImages)) || (st = dev_alloc(m, &m->stats, kStats * kStatSlots))) {
         free_map(m);
         return st;
     }
@@ -363,8 +363,8 @@ mem_status mem_create(const mem_params* p, void* stream, mem_map** out)
     auto devs = layer_devs(m);
     launch_reset_rect(s, g, 0, m->W, 0, m->H, m->h, m->v, m->cnt, m->clr, devs.data(), (int)devs.size());
     launch_zero_accum(s, g, m->cnt, m->wsum, m->ssum, m->clr, nullptr, 0);
-    launch_zero_int(s, (int*)m->stats, 2 * kStats);
-    launch_zero_int(s, m->pair_count, 1);
+    launch_zero_int(s, (int*)m->stats, 2 * kStats * kStatSlots);
+    launch_zero_int(s, m->pair_count, kMaxImages);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
@@ -487,60 +487,96 @@ mem_status mem_input_pointcloud(mem_map* m, const float* xyz, int64_t n, const f
     return check_launch(m, "mem_input_pointcloud");
 }
 
-static mem_status check_camera(const mem_map* m, int32_t h, int32_t w, const float K[4],
-                               const float T[12], Camera* cam)
+// Adds image k's intrinsics and size to `cam`.
+static mem_status check_intrinsics(int32_t h, int32_t w, const float K[4], int k, Camera* cam)
 {
     if (h < 1 || w < 1 || (int64_t)h * w > (1ll << 30)) return fail(MEM_E_ARG, "image size %dx%d", w, h);
     if (!K) return fail(MEM_E_ARG, "K is NULL");
-    for (int k = 0; k < 4; k++)
-        if (!std::isfinite(K[k])) return fail(MEM_E_ARG, "K must be finite");
+    for (int q = 0; q < 4; q++)
+        if (!std::isfinite(K[q])) return fail(MEM_E_ARG, "K must be finite");
     if (!(K[0] > 0.0f) || !(K[1] > 0.0f)) return fail(MEM_E_ARG, "fx and fy must be positive");
-    if (mem_status st = check_pose(m, T, "T_map_cam")) return st;
-    memcpy(cam->T.m, T, sizeof(cam->T.m));
-    cam->fx = K[0];
-    cam->fy = K[1];
-    cam->cx = K[2];
-    cam->cy = K[3];
-    cam->h = h;
-    cam->w = w;
-    cam->min_depth = m->min_depth;
+    cam->fx[k] = K[0];
+    cam->fy[k] = K[1];
+    cam->cx[k] = K[2];
+    cam->cy[k] = K[3];
+    cam->h[k] = h;
+    cam->w[k] = w;
     return MEM_OK;
+}
+
+static mem_status check_image(const mem_map* m, const mem_image& im, int k, Camera* cam)
+{
+    if (!im.data) return fail(MEM_E_ARG, "image %d: data is NULL", k);
+    if (im.dtype != MEM_F32 && im.dtype != MEM_U8)
+        return fail(MEM_E_ARG, "image %d: dtype must be MEM_F32 or MEM_U8", k);
+    if (im.c < 1) return fail(MEM_E_ARG, "image %d needs at least one channel", k);
+    if (im.strides[0] < 0 || im.strides[1] < 0 || im.strides[2] < 0)
+        return fail(MEM_E_ARG, "image %d: strides must be non-negative", k);
+    if (im.n_bind < 0 || im.n_bind > kMaxBind || (im.n_bind > 0 && !im.bind))
+        return fail(MEM_E_ARG, "image %d: n_bind must be 0..%d with a binding array", k, kMaxBind);
+    if (mem_status st = check_intrinsics(im.h, im.w, im.K, k, cam)) return st;
+    for (int b = 0; b < im.n_bind; b++) {
+        const Layer* L = nullptr;
+        if (mem_status st = resolve_layer(m, im.bind[b].layer, &L)) return st;
+        if (im.bind[b].ch_first < 0 || im.bind[b].ch_count != L->C || im.bind[b].ch_first + im.bind[b].ch_count > im.c)
+            return fail(MEM_E_ARG, "image %d binding %d does not fit the image / layer", k, b);
+    }
+    return MEM_OK;
+}
+
+mem_status mem_input_images(mem_map* m, const mem_image* images, int32_t n_images,
+                            const float T_map_cam[12], void* stream)
+{
+    if (mem_status st = usable(m)) return st;
+    if (n_images < 1 || n_images > kMaxImages || !images)
+        return fail(MEM_E_ARG, "n_images must be 1..%d with an image array", kMaxImages);
+    Camera cam{};
+    if (mem_status st = check_pose(m, T_map_cam, "T_map_cam")) return st;
+    memcpy(cam.T.m, T_map_cam, sizeof(cam.T.m));
+    cam.n = n_images;
+    cam.min_depth = m->min_depth;
+    for (int k = 0; k < n_images; k++)
+        if (mem_status st = check_image(m, images[k], k, &cam)) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Grid g = m->grid();
+    const int cap = (int)m->cells();
+    timed(m, s, "zero_count", [&] { launch_zero_int(s, m->pair_count, kMaxImages); });
+    timed(m, s, "project", [&] {
+        launch_project(s, g, cam, m->h, m->pairs, cap, m->pair_count, nullptr, m->stats);
+    });
+    for (int k = 0; k < n_images; k++) {
+        const mem_image& im = images[k];
+        for (int b = 0; b < im.n_bind; b++) {
+            const Layer* L = nullptr;
+            resolve_layer(m, im.bind[b].layer, &L);
+            LayerDev d = L->dev();
+            timed(m, s, "gather_fuse", [&] {
+                launch_gather_fuse(s, m->pairs + (int64_t)k * cap, m->pair_count + k, cap, im.data,
+                                   im.dtype, im.strides[0], im.strides[1], im.strides[2], im.w,
+                                   im.bind[b].ch_first, d);
+            });
+        }
+    }
+    return check_launch(m, "mem_input_images");
 }
 
 mem_status mem_input_image(mem_map* m, const void* img, int32_t dtype, int32_t h, int32_t w, int32_t c,
                            const int64_t strides[3], const float K[4], const float T_map_cam[12],
                            const mem_binding* bind, int32_t n_bind, void* stream)
 {
-    if (mem_status st = usable(m)) return st;
-    if (!img) return fail(MEM_E_ARG, "img is NULL");
-    if (dtype != MEM_F32 && dtype != MEM_U8) return fail(MEM_E_ARG, "image dtype must be MEM_F32 or MEM_U8");
-    if (c < 1) return fail(MEM_E_ARG, "image needs at least one channel");
-    if (!strides || strides[0] < 0 || strides[1] < 0 || strides[2] < 0)
-        return fail(MEM_E_ARG, "strides must be non-negative");
-    if (n_bind < 0 || n_bind > kMaxBind || (n_bind > 0 && !bind))
-        return fail(MEM_E_ARG, "n_bind must be 0..%d with a binding array", kMaxBind);
-    Camera cam;
-    if (mem_status st = check_camera(m, h, w, K, T_map_cam, &cam)) return st;
-    for (int b = 0; b < n_bind; b++) {
-        const Layer* L = nullptr;
-        if (mem_status st = resolve_layer(m, bind[b].layer, &L)) return st;
-        if (bind[b].ch_first < 0 || bind[b].ch_count != L->C || bind[b].ch_first + bind[b].ch_count > c)
-            return fail(MEM_E_ARG, "binding %d does not fit the image / layer", b);
-    }
-    hipStream_t s = (hipStream_t)stream;
-    Grid g = m->grid();
-    timed(m, s, "zero_count", [&] { launch_zero_int(s, m->pair_count, 1); });
-    timed(m, s, "project", [&] { launch_project(s, g, cam, m->h, m->pairs, m->pair_count, nullptr, m->stats); });
-    for (int b = 0; b < n_bind; b++) {
-        const Layer* L = nullptr;
-        resolve_layer(m, bind[b].layer, &L);
-        LayerDev d = L->dev();
-        timed(m, s, "gather_fuse", [&] {
-            launch_gather_fuse(s, m->pairs, m->pair_count, (int)m->cells(), img, dtype, strides[0],
-                               strides[1], strides[2], w, bind[b].ch_first, d);
-        });
-    }
-    return check_launch(m, "mem_input_image");
+    if (!strides) return fail(MEM_E_ARG, "strides is NULL");
+    if (!K) return fail(MEM_E_ARG, "K is NULL");
+    mem_image im;
+    im.data = img;
+    im.dtype = dtype;
+    im.h = h;
+    im.w = w;
+    im.c = c;
+    memcpy(im.strides, strides, sizeof(im.strides));
+    memcpy(im.K, K, sizeof(im.K));
+    im.bind = bind;
+    im.n_bind = n_bind;
+    return mem_input_images(m, &im, 1, T_map_cam, stream);
 }
 
 mem_status mem_get_layer(const mem_map* mc, int32_t layer, int32_t view, float* out, void* stream)
@@ -609,11 +645,15 @@ mem_status mem_debug_cell_pixels(const mem_map* mc, int32_t h, int32_t w, const 
     mem_map* m = const_cast<mem_map*>(mc);
     if (mem_status st = usable(m)) return st;
     if (!out) return fail(MEM_E_ARG, "out is NULL");
-    Camera cam;
-    if (mem_status st = check_camera(m, h, w, K, T, &cam)) return st;
+    Camera cam{};
+    if (mem_status st = check_pose(m, T, "T_map_cam")) return st;
+    if (mem_status st = check_intrinsics(h, w, K, 0, &cam)) return st;
+    memcpy(cam.T.m, T, sizeof(cam.T.m));
+    cam.n = 1;
+    cam.min_depth = m->min_depth;
     hipStream_t s = (hipStream_t)stream;
-    launch_zero_int(s, m->pair_count, 1);
-    launch_project(s, m->grid(), cam, m->h, m->pairs, m->pair_count, out, m->stats);
+    launch_zero_int(s, m->pair_count, kMaxImages);
+    launch_project(s, m->grid(), cam, m->h, m->pairs, (int)m->cells(), m->pair_count, out, m->stats);
     return check_launch(m, "mem_debug_cell_pixels");
 }
 
@@ -621,18 +661,21 @@ mem_status mem_get_stats(mem_map* m, mem_stats* out, void* stream)
 {
     if (mem_status st = usable(m)) return st;
     if (!out) return fail(MEM_E_ARG, "out is NULL");
-    unsigned long long buf[kStats];
+    unsigned long long buf[kStats * kStatSlots];
     HIP_TRY(m, hipMemcpyAsync(buf, m->stats, sizeof buf, hipMemcpyDeviceToHost, (hipStream_t)stream));
     HIP_TRY(m, hipStreamSynchronize((hipStream_t)stream));
     int64_t* o = (int64_t*)out;
-    for (int k = 0; k < kStats; k++) o[k] = (int64_t)buf[k];
+    for (int k = 0; k < kStats; k++) {
+        o[k] = 0;
+        for (int j = 0; j < kStatSlots; j++) o[k] += (int64_t)buf[k * kStatSlots + j];
+    }
     return MEM_OK;
 }
 
 mem_status mem_reset_stats(mem_map* m, void* stream)
 {
     if (mem_status st = usable(m)) return st;
-    launch_zero_int((hipStream_t)stream, (int*)m->stats, 2 * kStats);
+    launch_zero_int((hipStream_t)stream, (int*)m->stats, 2 * kStats * kStatSlots);
     return check_launch(m, "mem_reset_stats");
 }
 

@@ -29,6 +29,10 @@ namespace memk {
 
 constexpr int kMaxBind = 8;
 constexpr int kStats = 11;  // device counters, order of mem_stats
+// Device counters are [kStats][kStatSlots]: a workgroup adds into slot
+// (block id mod kStatSlots), so no single address sees more than
+// 1/kStatSlots of the atomics.
+constexpr int kStatSlots = 64;
 
 enum Stat {
     ST_POINTS_IN = 0,
@@ -82,10 +86,14 @@ struct PointBinds {
     LayerDev L[kMaxBind];
 };
 
+constexpr int kMaxImages = 4;  // images sharing one camera pose per call
+
+// One camera pose and the intrinsics / sizes of the images taken from it.
 struct Camera {
     Pose T;
-    float fx, fy, cx, cy;
-    int h, w;
+    int n;
+    float fx[kMaxImages], fy[kMaxImages], cx[kMaxImages], cy[kMaxImages];
+    int h[kMaxImages], w[kMaxImages];
     float min_depth;
 };
 
@@ -110,10 +118,68 @@ void launch_point_cells(hipStream_t s, const Grid& g, const float* xyz, int64_t 
 
 void launch_zero_int(hipStream_t s, int* p, int n);
 void launch_project(hipStream_t s, const Grid& g, const Camera& cam, const float* h, int2* pairs,
-                    int* count, int32_t* dbg, unsigned long long* stats);
+                    int cap, int* count, int32_t* dbg, unsigned long long* stats);
 void launch_gather_fuse(hipStream_t s, const int2* pairs, const int* count, int max_pairs,
                         const void* img, int img_dtype, int64_t s0, int64_t s1, int64_t s2, int w,
                         int ch_first, const LayerDev& L);
+
+// ---- batches of maps ----
+
+// One map of a batch as the kernels see it during a step.
+struct BatchMap {
+    Grid g;
+    int64_t cell_off;       // first cell of the map in the concatenated arrays
+    int64_t pt_begin, pt_end;
+    int64_t img_off;        // first element of the map's image
+    Pose T;                 // sensor pose of this step
+    Camera cam;             // this step's camera (cam.n = 0: none)
+};
+
+struct BatchRect {          // cells of map `map` entering the grid this step
+    int map, x0, x1, y0, y1, pad0, pad1, pad2;
+};
+
+struct BatchItem {          // a work item: map plus two item-specific fields
+    int map, a, b, pad;
+};
+
+// Device pointers of a batch (concatenated over maps).
+struct BatchDev {
+    float* h;
+    float* v;
+    int* cnt;
+    int* clr;
+    float* wsum;
+    float* ssum;
+    float2* stash;
+    int2* pairs;            // per map at cell_off
+    int* pair_count;        // [n_maps]
+    int* qctr;              // work-queue counters, [kQueues]
+    int* n_items;           // [0] rects, [1] point chunks (this step)
+    const BatchMap* maps;
+    const BatchRect* rects;
+    const BatchItem* chunks; // (map, begin, end): global point indices
+    const BatchItem* tiles;  // (map, x0, y0): projection tiles
+    const BatchItem* gitems; // (map, first pair): gather items
+    int n_tiles, n_gitems, n_maps;
+    int64_t total_cells;
+    unsigned long long* stats;
+};
+
+constexpr int kQueues = 8;
+constexpr int kGatherItem = 4096;  // visible pairs per gather work item
+
+struct BatchLaunch {        // tuning of one step
+    int chunk;              // points per ingest / march item (power of two)
+    int grid;               // persistent workgroups per stage
+    int tile;               // projection tile side (8 or 16)
+};
+
+void launch_batch_step(hipStream_t s, const BatchDev& d, const BatchLaunch& bl, const float* xyz,
+                       float c0, float c1, float mr2, float margin, int clear_min,
+                       const LayerDev* L, int nL, const void* images, int img_dtype, int cam_c,
+                       int cam_w, const mem_binding* ib, int n_ib);
+size_t batch_ingest_lds_bytes(int chunk);
 
 void launch_reset_rect(hipStream_t s, const Grid& g, int x0, int x1, int y0, int y1, float* h,
                        float* v, int* cnt, int* clr, const LayerDev* L, int nL);

@@ -1,0 +1,324 @@
+// update.h - per-item bodies of the map update kernels (device side).
+//
+// The single-map kernels (k_points.hip, k_image.hip, k_map.hip) and the
+// batched persistent kernels (k_batch.hip) run exactly these functions, so a
+// map updated inside a batch makes the same decisions and the same
+// arithmetic as a map updated on its own.
+#pragma once
+
+#include "codec.h"
+#include "fuse.h"
+#include "geom.h"
+#include "mem_internal.h"
+
+namespace memk {
+
+// Per-cloud accumulators of one map (storage-indexed).
+struct Accum {
+    int* cnt;
+    float* wsum;
+    float* ssum;
+    float2* stash;
+    int* clr;
+    float* chsum;  // [Cb][HW]
+    int HW;
+};
+
+// LDS hash table of one ingest workgroup.
+struct IngestLds {
+    int* key;
+    int* cnt;
+    float* w;
+    float* s;
+    float2* first;
+    float* ch;  // [Cb][slots] or unused
+    int slots_log2;
+};
+
+struct PointCounts {
+    int acc = 0, nonfinite = 0, range = 0, outside = 0;
+};
+
+// Aggregates points [begin, end) of a cloud (at most 2^slots_log2 / 2
+// points) into the LDS table, then flushes one global atomic per (cell,
+// field).  Every thread of the workgroup must call it; it starts and ends
+// with a workgroup barrier.
+__device__ __forceinline__ void ingest_range(const Grid& g, const float* __restrict__ xyz,
+                                             int64_t begin, int64_t end,
+                                             const float* __restrict__ ch, const Pose& T, float c0,
+                                             float c1, float mr2, const PointBinds& pb,
+                                             const Accum& acc, const IngestLds& lds,
+                                             PointCounts& pc)
+{
+    const int slots = 1 << lds.slots_log2;
+    const int nthr = blockDim.x;
+    const bool lds_ch = pb.lds_ch != 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < slots; i += nthr) {
+        lds.key[i] = -1;
+        lds.cnt[i] = 0;
+        lds.w[i] = 0.0f;
+        lds.s[i] = 0.0f;
+    }
+    if (lds_ch)
+        for (int i = threadIdx.x; i < slots * pb.Cb; i += nthr) lds.ch[i] = 0.0f;
+    __syncthreads();
+
+    for (int64_t i = begin + threadIdx.x; i < end; i += nthr) {
+        float px, py, pz, r2;
+        int ix, iy;
+        int r = point_cell(g, T, mr2, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], px, py, pz, r2, ix, iy);
+        if (r != 0) {
+            pc.nonfinite += (r == -1);
+            pc.range += (r == -2);
+            pc.outside += (r == -3);
+            continue;
+        }
+        pc.acc++;
+        const int st = storage_index(g, ix, iy);
+        const float sig = c0 + c1 * r2;
+        const float var = sig * sig;
+        const float w = 1.0f / var;
+        int slot = (int)(((unsigned)st * 2654435761u) >> (32 - lds.slots_log2));
+        for (;;) {
+            int old = atomicCAS(&lds.key[slot], -1, st);
+            if (old == -1) {
+                lds.first[slot] = make_float2(pz, var);
+                break;
+            }
+            if (old == st) break;
+            slot = (slot + 1) & (slots - 1);
+        }
+        atomicAdd(&lds.cnt[slot], 1);
+        atomicAdd(&lds.w[slot], w);
+        atomicAdd(&lds.s[slot], pz * w);
+        for (int b = 0; b < pb.n; b++) {
+            const float* src = ch + i * pb.c_in + pb.b[b].ch_first;
+            for (int q = 0; q < pb.b[b].C; q++) {
+                const int plane = pb.b[b].sum_off + q;
+                if (lds_ch)
+                    atomicAdd(&lds.ch[plane * slots + slot], src[q]);
+                else
+                    unsafeAtomicAdd(&acc.chsum[(int64_t)plane * acc.HW + st], src[q]);
+            }
+        }
+    }
+    __syncthreads();
+
+    // Flush: one global atomic per (cell, field) seen by this workgroup.
+    for (int slot = threadIdx.x; slot < slots; slot += nthr) {
+        const int st = lds.key[slot];
+        if (st < 0) continue;
+        const int c = lds.cnt[slot];
+        atomicAdd(&acc.cnt[st], c);
+        unsafeAtomicAdd(&acc.wsum[st], lds.w[slot]);
+        unsafeAtomicAdd(&acc.ssum[st], lds.s[slot]);
+        // A cell whose only point in the whole cloud is this one takes
+        // (z, v) verbatim; any other writer implies a count above one.
+        if (c == 1) acc.stash[st] = lds.first[slot];
+        if (lds_ch)
+            for (int q = 0; q < pb.Cb; q++)
+                unsafeAtomicAdd(&acc.chsum[(int64_t)q * acc.HW + st], lds.ch[q * slots + slot]);
+    }
+    __syncthreads();
+}
+
+// Clearing walk of point i of a cloud (Table I's ray cast).  Returns the
+// number of in-grid cells it loaded.
+__device__ __forceinline__ int march_point(const Grid& g, const float* __restrict__ xyz, int64_t i,
+                                           const Pose& T, float mr2, float margin,
+                                           const float* __restrict__ h, int* __restrict__ clr)
+{
+    float px, py, pz, r2;
+    int ix, iy;
+    int r = point_cell(g, T, mr2, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], px, py, pz, r2, ix, iy);
+    if (r != 0) return 0;
+    const float sx = T.m[3], sy = T.m[7], sz = T.m[11];
+    int ax, ay;
+    lattice_cell(g, sx, sy, ax, ay);
+    Ray ray(g, ax, ay, ix, iy, sx, sy, sz, px, py, pz);
+    return walk_cells<8>(g, ray, h, [&](int st, float hk, float zr) {
+        float thr = zr + margin;
+        if (hk > thr) atomicAdd(&clr[st], 1);  // NaN (no height) never votes
+        return false;
+    });
+}
+
+// Height fusion, clearing and bound point channels of storage cell st.
+// Returns 1 if the cell received points, 2 if it was cleared, else 0.
+__device__ __forceinline__ int finalize_cell(int st, const Accum& acc, int clear_min,
+                                             float* __restrict__ h, float* __restrict__ v,
+                                             const PointBinds& pb)
+{
+    const int N = acc.cnt[st];
+    if (N == 0) {
+        if (clear_min > 0 && acc.clr[st] >= clear_min && !isnan(h[st])) {
+            h[st] = __uint_as_float(0x7fc00000u);
+            return 2;
+        }
+        return 0;
+    }
+    const float hv = h[st];
+    float hn, vn;
+    if (!isnan(hv)) {  // prior plus the cloud, information form
+        const float vv = v[st];
+        vn = 1.0f / (1.0f / vv + acc.wsum[st]);
+        hn = vn * (hv / vv + acc.ssum[st]);
+    } else if (N == 1) {  // a single point sets an empty cell exactly
+        const float2 zv = acc.stash[st];
+        hn = zv.x;
+        vn = zv.y;
+    } else {
+        vn = 1.0f / acc.wsum[st];
+        hn = acc.ssum[st] * vn;
+    }
+    h[st] = hn;
+    v[st] = vn;
+    for (int b = 0; b < pb.n; b++) {
+        const LayerDev& L = pb.L[b];
+        const int C = pb.b[b].C, off = pb.b[b].sum_off;
+        GaussCoef gc{0.0f, 1.0f, 0.0f, true};
+        if (L.rule == MEM_GAUSS) gc = gauss_coef(L.param, L.var[st], N);
+        for (int q = 0; q < C; q++) {
+            const float sum = acc.chsum[(int64_t)(off + q) * acc.HW + st];
+            const float a = sum / (float)N;
+            const int64_t idx = (int64_t)st * C + q;
+            const float old = layer_load(L.val, L.storage, L.scale, idx, q);
+            layer_store(L.val, L.storage, L.scale, idx, q, fuse_value(L.rule, L.param, old, a, sum, gc));
+        }
+        if (L.rule == MEM_GAUSS) L.var[st] = gc.var;
+    }
+    return 1;
+}
+
+// Association of logical cell (ix, iy) with every image of one camera pose
+// (Sec. III-B, Fig. 3).  code[k] = pixel, or -1 no height, -2 outside image
+// k's view, -3 occluded.  Returns the number of in-grid cells the occlusion
+// walk loaded; in_view counts the images whose view holds the cell.
+__device__ __forceinline__ int project_cell(const Grid& g, const Camera& cam,
+                                            const float* __restrict__ h, int ix, int iy, int st,
+                                            int (&code)[kMaxImages], int& in_view)
+{
+#pragma unroll
+    for (int k = 0; k < kMaxImages; k++) code[k] = -1;
+    in_view = 0;
+    const float hj = h[st];
+    if (isnan(hj)) return 0;
+    const float* T = cam.T.m;
+    const float xc = ((float)(g.ox + ix) + 0.5f) * g.res;
+    const float yc = ((float)(g.oy + iy) + 0.5f) * g.res;
+    const float dx = xc - T[3], dy = yc - T[7], dz = hj - T[11];
+    float P[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) {  // R^T d
+        float a = T[0 + k] * dx;
+        float b = T[4 + k] * dy;
+        float c = T[8 + k] * dz;
+        float s = a + b;
+        P[k] = s + c;
+    }
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < kMaxImages; k++) {
+        if (k >= cam.n) break;
+        code[k] = -2;
+        if (P[2] > cam.min_depth) {
+            float u = cam.fx[k] * P[0];
+            u = u / P[2];
+            u = u + cam.cx[k];
+            float v = cam.fy[k] * P[1];
+            v = v / P[2];
+            v = v + cam.cy[k];
+            const float uf = floorf(u + 0.5f);
+            const float vf = floorf(v + 0.5f);
+            if (uf >= 0.0f && uf < (float)cam.w[k] && vf >= 0.0f && vf < (float)cam.h[k]) {
+                code[k] = (int)vf * cam.w[k] + (int)uf;
+                in_view++;
+                any = true;
+            }
+        }
+    }
+    if (!any) return 0;
+    // One occlusion walk serves every image of this pose.
+    int ax, ay;
+    lattice_cell(g, T[3], T[7], ax, ay);
+    Ray ray(g, ax, ay, ix, iy, T[3], T[7], T[11], xc, yc, hj);
+    bool occluded = false;
+    const int visited = walk_cells<8>(g, ray, h, [&](int, float hk, float zr) {
+        if (hk >= zr) occluded = true;  // NaN (no height) never occludes
+        return occluded;
+    });
+    if (occluded)
+#pragma unroll
+        for (int k = 0; k < kMaxImages; k++)
+            if (code[k] >= 0) code[k] = -3;
+    return visited;
+}
+
+// Wave-aggregated append of (st, code) for the lanes with code >= 0.  All
+// lanes of the wave must call it.
+__device__ __forceinline__ void append_pair(bool vis, int st, int code, int2* __restrict__ list,
+                                            int* __restrict__ count)
+{
+    const unsigned long long mask = __ballot(vis);
+    if (!mask) return;
+    const int lane = __lane_id();
+    const int leader = __ffsll((long long)mask) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(count, __popcll(mask));
+    base = __shfl(base, leader);
+    if (vis) {
+        const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+        list[base + rank] = make_int2(st, code);
+    }
+}
+
+template <int IMG>
+__device__ __forceinline__ float pixel_value(const void* img, int64_t off)
+{
+    if (IMG == MEM_U8) return (float)((const uint8_t*)img)[off] / 255.0f;
+    return ((const float*)img)[off];
+}
+
+// Fuses channels q0, q0 + LPP, ... of one visible pair's pixel into layer L
+// (N = 1).  The LPP lanes of a pair call it together; lane q0 == 0 writes
+// the Gaussian variance.
+template <int IMG, int S>
+__device__ __forceinline__ void gather_pair(int2 pr, const void* __restrict__ img, int64_t s0,
+                                            int64_t s1, int64_t s2, int w, int ch_first,
+                                            const LayerDev& L, int q0, int LPP)
+{
+    const int st = pr.x;
+    const int row = pr.y / w, col = pr.y - (pr.y / w) * w;
+    const int64_t pix = (int64_t)row * s0 + (int64_t)col * s1 + (int64_t)ch_first * s2;
+    GaussCoef gc{0.0f, 1.0f, 0.0f, true};
+    if (L.rule == MEM_GAUSS) gc = gauss_coef(L.param, L.var[st], 1);
+    const int C = L.C;
+    for (int q = q0; q < C; q += LPP) {
+        const float m = pixel_value<IMG>(img, pix + (int64_t)q * s2);
+        const int64_t idx = (int64_t)st * C + q;
+        const float sc = S == MEM_FP8_E4M3 ? L.scale[q] : 1.0f;
+        const float old = Store<S>::load(L.val, idx, sc);
+        Store<S>::store(L.val, idx, fuse_value(L.rule, L.param, old, m, m, gc), sc);
+    }
+    if (L.rule == MEM_GAUSS && q0 == 0) L.var[st] = gc.var;
+}
+
+// An empty cell: no height, never observed layers, Dirichlet alpha_0.
+__device__ __forceinline__ void reset_cell(int st, float* __restrict__ h, float* __restrict__ v,
+                                           int* __restrict__ cnt, int* __restrict__ clr,
+                                           const LayerDev* L, int nL)
+{
+    h[st] = __builtin_nanf("");
+    v[st] = __builtin_inff();
+    cnt[st] = 0;
+    clr[st] = 0;
+    for (int l = 0; l < nL; l++) {
+        const float init = (L[l].rule == MEM_DIRICHLET) ? L[l].param : __builtin_nanf("");
+        for (int q = 0; q < L[l].C; q++)
+            layer_store(L[l].val, L[l].storage, L[l].scale, (int64_t)st * L[l].C + q, q, init);
+        if (L[l].rule == MEM_GAUSS) L[l].var[st] = __builtin_inff();
+    }
+}
+
+}  // namespace memk

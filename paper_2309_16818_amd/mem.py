@@ -29,7 +29,7 @@ STAT_FIELDS = ("points_in", "points_accepted", "dropped_nonfinite", "dropped_ran
 
 # Exported symbols of include/mem.h.
 SYMBOLS = ("mem_create", "mem_destroy", "mem_move", "mem_input_pointcloud", "mem_input_image",
-           "mem_get_layer", "mem_set_layer", "mem_get_center", "mem_debug_point_cells",
+           "mem_input_images", "mem_get_layer", "mem_set_layer", "mem_get_center", "mem_debug_point_cells",
            "mem_debug_cell_pixels", "mem_get_stats", "mem_reset_stats", "mem_profile_enable",
            "mem_profile_read", "mem_last_error")
 
@@ -49,6 +49,12 @@ class mem_params(C.Structure):
 
 class mem_binding(C.Structure):
     _fields_ = [("layer", C.c_int32), ("ch_first", C.c_int32), ("ch_count", C.c_int32)]
+
+
+class mem_image(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("dtype", C.c_int32), ("h", C.c_int32), ("w", C.c_int32),
+                ("c", C.c_int32), ("strides", C.c_int64 * 3), ("K", C.c_float * 4),
+                ("bind", C.POINTER(mem_binding)), ("n_bind", C.c_int32)]
 
 
 class mem_stats(C.Structure):
@@ -83,6 +89,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "mem_move": [P, F, F, P],
         "mem_input_pointcloud": [P, P, I64, P, I32, C.POINTER(mem_binding), I32, P, P],
         "mem_input_image": [P, P, I32, I32, I32, I32, P, P, P, C.POINTER(mem_binding), I32, P],
+        "mem_input_images": [P, C.POINTER(mem_image), I32, P, P],
         "mem_get_layer": [P, I32, I32, P, P],
         "mem_set_layer": [P, I32, I32, P, P],
         "mem_get_center": [P, C.POINTER(I32), C.POINTER(I32)],
@@ -230,10 +237,25 @@ class Map:
         _check(load().mem_input_image(self._h, _dev_ptr(img, "img"), dt, h, w, c, st,
                                       _floats(K, 4), _pose(T), b, nb, _stream(stream)))
 
+    def input_images(self, images, T, stream=None):
+        """images: sequence of (img [h, w, c] tensor, K, bind) taken from one
+        camera pose T; equals input_image for each in order."""
+        arr = (mem_image * max(1, len(images)))()
+        keep = []
+        for k, (img, K, bind) in enumerate(images):
+            if img.dim() != 3 or img.dtype not in (torch.uint8, torch.float32):
+                raise ValueError("images must be uint8 or float32 [h, w, c] tensors")
+            b, nb = _bindings(bind)
+            keep.append(b)
+            h, w, c = img.shape
+            arr[k] = mem_image(_dev_ptr(img, "img"), MEM_U8 if img.dtype == torch.uint8 else MEM_F32,
+                               h, w, c, (C.c_int64 * 3)(*img.stride()), _floats(K, 4), b, nb)
+        _check(load().mem_input_images(self._h, arr, len(images), _pose(T), _stream(stream)))
+
     # -- read-out -------------------------------------------------------------
     def channels(self, layer: int, view: int = MEM_VIEW_VALUE) -> int:
-        if layer < MEM_LAYER_USER0:
-            return 1
+        if layer < MEM_LAYER_USER0 or layer - MEM_LAYER_USER0 >= len(self.layers):
+            return 1  # the library rejects unknown layers
         l = self.layers[layer - MEM_LAYER_USER0]
         if view == MEM_VIEW_ARGMAX or (view == MEM_VIEW_AUX and l.rule == MEM_GAUSS):
             return 1
@@ -252,7 +274,8 @@ class Map:
         if v.numel() != self.H * self.W * self.channels(layer, view):
             raise ValueError("values have the wrong size")
         _check(load().mem_set_layer(self._h, layer, view, _dev_ptr(v, "values"), _stream(stream)))
-        torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+        # `v` may be a temporary copy: keep it alive until the kernel has read it
+        (stream or torch.cuda.current_stream()).synchronize()
 
     def center(self):
         cx, cy = C.c_int32(), C.c_int32()

@@ -46,6 +46,8 @@ def sync_oracle(g: mem.Map, o: O.OracleMap):
     o.set_center(cx, cy)
     o.set_layer(O.LAYER_ELEVATION, 0, gpu_layer(g, mem.MEM_LAYER_ELEVATION))
     o.set_layer(O.LAYER_VARIANCE, 0, gpu_layer(g, mem.MEM_LAYER_VARIANCE))
+    o.set_layer(O.LAYER_HITS, 0, gpu_layer(g, mem.MEM_LAYER_HITS))
+    o.set_layer(O.LAYER_CLEAR, 0, gpu_layer(g, mem.MEM_LAYER_CLEAR))
     for k, l in enumerate(g.layers):
         lid = mem.MEM_LAYER_USER0 + k
         if l.rule == mem.MEM_DIRICHLET:

@@ -39,6 +39,8 @@ def test_struct_layouts_match_the_header():
     assert C.sizeof(mem.mem_binding) == 12
     assert C.sizeof(mem.mem_stats) == 8 * len(mem.STAT_FIELDS)
     assert C.sizeof(mem.mem_kernel_time) == 48
+    assert C.sizeof(mem.mem_image) == 80
+    assert mem.mem_image.strides.offset == 24 and mem.mem_image.bind.offset == 64
 
 
 def _params(**kw):

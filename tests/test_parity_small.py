@@ -176,7 +176,32 @@ def test_image_channel_rules(dtype, layout):
         compare(g, o, counts=False, what=f"image {dtype} {layout} it={it}")
 
 
-@pytest.mark.parametrize("moves", [[(0.13, 0.0), (0.5, 0.27), (-0.31, 0.9), (-0.31, 0.9), (5.0, -5.0), (0.0, 0.0)]])
+def test_images_of_one_pose_equal_sequential_single_images():
+    """mem_input_images (shared occlusion walk) against the oracle fusing the
+    images one after another; two images bind the same exp.-averaging layer
+    so their order matters."""
+    rng = np.random.default_rng(17)
+    layers = [(3, mem.MEM_EXPAVG, 0.5), (8, mem.MEM_GAUSS, 1.0), (5, mem.MEM_DIRICHLET, 1.0)]
+    g, o = make_pair(64, 48, 0.05, layers=layers)
+    rand_map_state(g, o, rng, valid_frac=0.9, hscale=0.08)
+    for it in range(3):
+        R = synth.camera_rotation(rng.uniform(0, 2 * np.pi), math.radians(35)).astype(np.float32)
+        T = pose((rng.uniform(-0.3, 0.3), rng.uniform(-0.3, 0.3), 0.9), R)
+        K = (80.0, 80.0, 63.5, 47.5)
+        Kq = synth.scaled_intrinsics(K, 0.25)
+        rgb = rng.integers(0, 256, (96, 128, 3), dtype=np.uint8)
+        rgb2 = rng.integers(0, 256, (96, 128, 3), dtype=np.uint8)
+        feat = synth.feature_image(rng, 24, 32, 8)
+        cls = synth.class_image(rng, 96, 128, 5)
+        ims = [(rgb, K, [(8, 0, 3)]), (feat, Kq, [(9, 0, 8)]), (cls, K, [(10, 0, 5)]), (rgb2, K, [(8, 0, 3)])]
+        sync_oracle(g, o)
+        g.input_images([(to_dev(a), k, b) for a, k, b in ims], T)
+        for a, k, b in ims:
+            o.input_image(a, k, T, bind=b)
+        compare(g, o, counts=False, what=f"images it={it}")
+
+
+@pytest.mark.parametrize("moves",[[(0.13, 0.0), (0.5, 0.27), (-0.31, 0.9), (-0.31, 0.9), (5.0, -5.0), (0.0, 0.0)]])
 def test_move_matches_oracle_bitwise(moves):
     rng = np.random.default_rng(3)
     layers = [(3, mem.MEM_EXPAVG, 0.5), (2, mem.MEM_GAUSS, 1.0), (4, mem.MEM_DIRICHLET, 1.0)]

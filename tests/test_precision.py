@@ -1,0 +1,88 @@
+"""Reduced-precision layer storage (BF16, FP8 E4M3 with per-channel scales):
+codecs against torch's own conversions, every E4M3 code round-trips, and a
+fused update stays within one storage rounding of the binary64 oracle."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from lockstep import gpu_layer, make_pair, sync_oracle, to_dev
+from paper_2309_16818_amd import mem, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def roundtrip(storage, values, scale=None):
+    C = values.shape[-1]
+    g = mem.Map(mem.MapParams(values.shape[1], values.shape[0], 0.1,
+                              layers=[mem.Layer(C, mem.MEM_LATEST, 0.0, storage, scale)]))
+    g.set_layer(8, 0, torch.tensor(values, dtype=torch.float32))
+    out = gpu_layer(g, 8, 0)
+    g.close()
+    return out
+
+
+def test_bf16_storage_rounds_to_nearest_even_like_torch():
+    rng = np.random.default_rng(0)
+    v = (rng.standard_normal((16, 16, 8)) * np.exp(rng.uniform(-20, 20, (16, 16, 8)))).astype(np.float32)
+    v[0, 0, :4] = [0.0, -0.0, np.inf, -np.inf]
+    want = torch.tensor(v).to(torch.bfloat16).float().numpy()
+    got = roundtrip(mem.MEM_BF16, v)
+    assert np.array_equal(got, want)
+
+
+def test_every_e4m3_code_round_trips():
+    codes = torch.arange(256, dtype=torch.uint8).view(torch.float8_e4m3fn).float().numpy()
+    v = codes.reshape(16, 16, 1).astype(np.float32)
+    got = roundtrip(mem.MEM_FP8_E4M3, v, scale=[448.0])  # amax 448 -> scale 1
+    assert np.array_equal(got, v, equal_nan=True)
+    assert np.isnan(got).sum() == 2  # 0x7F and 0xFF
+
+
+def test_fp8_storage_matches_torch_e4m3_with_saturation_and_scales():
+    rng = np.random.default_rng(1)
+    C = 6
+    amax = np.array([1.0, 0.5, 4.0, 100.0, 1e-3, 448.0], np.float32)
+    v = (rng.standard_normal((12, 10, C)) * amax * 0.6).astype(np.float32)
+    v[0, 0] = amax * 3.0   # saturates
+    v[0, 1] = -amax * 3.0
+    s = (amax / 448.0).astype(np.float32)
+    q = np.clip(v / s, -448, 448)
+    want = (torch.tensor(q).to(torch.float8_e4m3fn).float().numpy() * s).astype(np.float32)
+    got = roundtrip(mem.MEM_FP8_E4M3, v, scale=list(amax))
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("storage,rel", [(mem.MEM_F32, 1e-4), (mem.MEM_BF16, 2.0 ** -8), (mem.MEM_FP8_E4M3, 2.0 ** -3)])
+def test_feature_fusion_within_one_storage_rounding(storage, rel):
+    """One image update from the same state on both sides: the GPU result
+    differs from the binary64 oracle by at most the storage rounding (plus
+    binary32 arithmetic), per channel, relative to the layer's scale."""
+    rng = np.random.default_rng(2)
+    C = 48
+    layers = [(C, mem.MEM_GAUSS, 1.0, storage), (C, mem.MEM_EXPAVG, 0.5, storage)]
+    g, o = make_pair(48, 48, 0.05, layers=layers)
+    h = np.where(rng.uniform(size=(48, 48)) < 0.9, rng.normal(0, 0.05, (48, 48)), np.nan)
+    g.set_layer(0, 0, torch.tensor(h, dtype=torch.float32))
+    g.set_layer(1, 0, torch.full((48, 48), 1e-3))
+    K = (60.0, 60.0, 47.5, 35.5)
+    for it in range(4):
+        img = synth.feature_image(rng, 72, 96, 2 * C)
+        R = synth.camera_rotation(rng.uniform(0, 2 * np.pi), math.radians(40)).astype(np.float32)
+        T = np.zeros((3, 4), np.float32)
+        T[:, :3] = R
+        T[:, 3] = (rng.uniform(-0.2, 0.2), rng.uniform(-0.2, 0.2), 0.8)
+        sync_oracle(g, o)
+        g.input_image(to_dev(img), K, T, bind=[(8, 0, C), (9, C, C)])
+        o.input_image(img, K, T, bind=[(8, 0, C), (9, C, C)])
+        for lid in (8, 9):
+            a, b = gpu_layer(g, lid), o.get_layer(lid)
+            ok = ~np.isnan(b)
+            assert np.array_equal(np.isnan(a), np.isnan(b))
+            # unit-norm features: channel values are O(1/sqrt(C)); bound the
+            # error by the storage rounding of the value plus the FP8
+            # subnormal quantum of the default scale (1/448 * 2^-9)
+            err = np.abs(a[ok] - b[ok])
+            bound = rel * np.abs(b[ok]) + (1e-6 if storage != mem.MEM_FP8_E4M3 else 2.0 ** -9 / 448 + 1e-6)
+            assert (err <= bound).all(), (storage, lid, float((err - bound).max()))
