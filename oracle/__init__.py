@@ -180,3 +180,60 @@ class OracleMap:
         r = lib().orc_set_layer(self._m, layer, view, _ptr(v))
         if r != 0:
             raise ValueError(f"oracle: view {view} of layer {layer} is not settable")
+
+
+# ---------------------------------------------------------------------------
+# Learned completion network (unet_oracle.c)
+# ---------------------------------------------------------------------------
+
+def _unet_sigs(L):
+    if getattr(L, "_unet_ready", False):
+        return
+    P, I = C.c_void_p, C.c_int
+    L.orc_unet_num_params.restype = C.c_int64
+    L.orc_unet_num_params.argtypes = [I, I, I]
+    L.orc_unet_layer_offsets.argtypes = [I, I, I, P]
+    L.orc_unet_forward.argtypes = [I, I, I, P, P, I, I, P]
+    L.orc_unet_loss_grad.restype = C.c_double
+    L.orc_unet_loss_grad.argtypes = [I, I, P, P, P, P, I, I, P]
+    L._unet_ready = True
+
+
+def unet_num_params(base, in_ch=3, out_ch=2):
+    L = lib()
+    _unet_sigs(L)
+    return int(L.orc_unet_num_params(base, in_ch, out_ch))
+
+
+def unet_layer_offsets(base, in_ch=3, out_ch=2):
+    L = lib()
+    _unet_sigs(L)
+    off = np.zeros(18, np.int64)
+    L.orc_unet_layer_offsets(base, in_ch, out_ch, _ptr(off))
+    return off
+
+
+def unet_forward(params, x, base, out_ch=2):
+    """x: [B, S, S, Cin] binary64 NHWC; returns [B, S, S, out_ch]."""
+    L = lib()
+    _unet_sigs(L)
+    x = np.ascontiguousarray(x, np.float64)
+    B, S, _, cin = x.shape
+    p = np.ascontiguousarray(params, np.float64)
+    out = np.zeros((B, S, S, out_ch))
+    L.orc_unet_forward(base, cin, out_ch, _ptr(p), _ptr(x), B, S, _ptr(out))
+    return out
+
+
+def unet_loss_grad(params, x, target, mask, base):
+    """Gaussian NLL (mean over mask > 0) and its gradient."""
+    L = lib()
+    _unet_sigs(L)
+    x = np.ascontiguousarray(x, np.float64)
+    B, S, _, cin = x.shape
+    p = np.ascontiguousarray(params, np.float64)
+    t = np.ascontiguousarray(target, np.float64)
+    m = np.ascontiguousarray(mask, np.float64)
+    g = np.zeros_like(p)
+    loss = L.orc_unet_loss_grad(base, cin, _ptr(p), _ptr(x), _ptr(t), _ptr(m), B, S, _ptr(g))
+    return loss, g

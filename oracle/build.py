@@ -15,9 +15,9 @@ LIB = os.path.join(HERE, "liborc.so")
 
 
 def build(verbose: bool = False) -> str:
-    src = os.path.join(HERE, "mem_oracle.c")
+    srcs = [os.path.join(HERE, f) for f in ("mem_oracle.c", "unet_oracle.c")]
     cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-           "-fPIC", "-shared", "-Wall", "-Wextra", "-o", LIB + ".tmp", src, "-lm"]
+           "-fPIC", "-shared", "-Wall", "-Wextra", "-o", LIB + ".tmp", *srcs, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

@@ -1,0 +1,133 @@
+"""Pins of the U-Net oracle (learned completion): forward and gradient
+against torch's own binary64 convolution / pooling / transposed convolution
+with autograd (an independent implementation), and central finite
+differences.  CPU only."""
+import numpy as np
+import pytest
+import torch
+import torch.nn.functional as F
+
+import oracle as O
+
+SPEC = None
+
+
+def spec(base, cin=3, cout=2):
+    c = [base, 2 * base, 4 * base, 8 * base]
+    L, prev = [], cin
+    for l in range(4):
+        L += [(9, prev, c[l]), (9, c[l], c[l])]
+        prev = c[l]
+    for l in (2, 1, 0):
+        L += [(4, c[l + 1], c[l]), (9, 2 * c[l], c[l]), (9, c[l], c[l])]
+    L.append((1, base, cout))
+    return L
+
+
+def torch_unet(p, x, base):
+    """The same network with torch.nn.functional (NCHW inside)."""
+    L = spec(base)
+    offs = O.unet_layer_offsets(base)
+    assert len(offs) == len(L)
+
+    def wb(i):
+        taps, ci, co = L[i]
+        o = int(offs[i])
+        w = p[o:o + taps * ci * co].view(taps, ci, co)
+        b = p[o + taps * ci * co:o + taps * ci * co + co]
+        return w, b
+
+    def conv3(i, a):
+        w, b = wb(i)
+        ci, co = w.shape[1], w.shape[2]
+        return F.conv2d(a, w.view(3, 3, ci, co).permute(3, 2, 0, 1), b, padding=1)
+
+    def up(i, a):
+        w, b = wb(i)
+        ci, co = w.shape[1], w.shape[2]
+        return F.conv_transpose2d(a, w.view(2, 2, ci, co).permute(2, 3, 0, 1), b, stride=2)
+
+    a = x.permute(0, 3, 1, 2)
+    enc = []
+    for l in range(4):
+        a = F.relu(conv3(2 * l + 1, F.relu(conv3(2 * l, a))))
+        enc.append(a)
+        if l < 3:
+            a = F.max_pool2d(a, 2)
+    d = enc[3]
+    for j, l in enumerate((2, 1, 0)):
+        k = 8 + 3 * j
+        d = torch.cat([up(k, d), enc[l]], 1)
+        d = F.relu(conv3(k + 2, F.relu(conv3(k + 1, d))))
+    w, b = wb(17)
+    out = F.conv2d(d, w.view(w.shape[1], w.shape[2]).t()[:, :, None, None], b)
+    return out.permute(0, 2, 3, 1)
+
+
+def nll(out, t, m):
+    h, s = out[..., 0], out[..., 1]
+    msk = m > 0
+    cnt = max(int(msk.sum()), 1)
+    return (0.5 * (s + (t - h) ** 2 * torch.exp(-s)))[msk].sum() / cnt
+
+
+def sample(base, B, S, seed):
+    rng = np.random.default_rng(seed)
+    n = O.unet_num_params(base)
+    p = rng.normal(0, 0.3, n)
+    offs = list(O.unet_layer_offsets(base)) + [n]
+    for i, (taps, ci, co) in enumerate(spec(base)):  # fan-in scaling keeps activations O(1)
+        p[offs[i]:offs[i + 1]] *= np.sqrt(2.0 / (taps * ci)) / 0.3
+    x = rng.normal(0, 1, (B, S, S, 3))
+    t = rng.normal(0, 1, (B, S, S))
+    m = (rng.uniform(size=(B, S, S)) < 0.7).astype(np.float64)
+    return p, x, t, m
+
+
+def test_parameter_count_of_the_four_level_unet():
+    # 3x3 convs, 2x2 transposed convs and the 1x1 head, base width 32
+    assert O.unet_num_params(32) == 1925634
+    assert O.unet_num_params(4) == sum(t * ci * co + co for t, ci, co in spec(4))
+
+
+@pytest.mark.parametrize("base,B,S", [(2, 2, 16), (4, 1, 32)])
+def test_forward_and_gradient_match_torch_autograd(base, B, S):
+    p, x, t, m = sample(base, B, S, base + S)
+    out = O.unet_forward(p, x, base)
+    pt = torch.tensor(p, requires_grad=True)
+    ot = torch_unet(pt, torch.tensor(x), base)
+    assert np.allclose(out, ot.detach().numpy(), rtol=1e-11, atol=1e-11)
+    loss, g = O.unet_loss_grad(p, x, t, m, base)
+    lt = nll(ot, torch.tensor(t), torch.tensor(m))
+    lt.backward()
+    assert abs(loss - lt.item()) <= 1e-12 * max(1.0, abs(loss))
+    gt = pt.grad.numpy()
+    assert np.allclose(g, gt, rtol=1e-9, atol=1e-12 * np.abs(gt).max())
+
+
+def test_gradient_matches_central_differences():
+    base, B, S = 2, 2, 16
+    p, x, t, m = sample(base, B, S, 5)
+    _, g = O.unet_loss_grad(p, x, t, m, base)
+    rng = np.random.default_rng(6)
+    offs = list(O.unet_layer_offsets(base)) + [len(p)]
+    idx = np.concatenate([rng.integers(offs[i], offs[i + 1], 12) for i in range(18)])
+    h = 1e-6
+    ok = 0
+    for i in idx:
+        pp, pm = p.copy(), p.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (O.unet_loss_grad(pp, x, t, m, base)[0] - O.unet_loss_grad(pm, x, t, m, base)[0]) / (2 * h)
+        ok += abs(fd - g[i]) <= 1e-6 * max(abs(g[i]), 1e-3 * np.abs(g).max())
+    assert ok >= 0.98 * len(idx)  # ReLU / max-pool kinks may catch a few
+
+
+def test_loss_special_cases():
+    base, B, S = 2, 1, 16
+    p, x, t, m = sample(base, B, S, 7)
+    loss, g = O.unet_loss_grad(p, x, t, np.zeros_like(m), base)
+    assert loss == 0.0 and not g.any()
+    out = O.unet_forward(p, x, base)
+    loss, _ = O.unet_loss_grad(p, x, out[..., 0], m, base)  # perfect mean: loss = mean(s / 2)
+    assert abs(loss - 0.5 * out[..., 1][m > 0].mean()) < 1e-12
