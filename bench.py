@@ -45,7 +45,94 @@ def parse():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--profile-events", type=int, default=1,
                     help="record HIP events around every launch in the timed region")
+    ap.add_argument("--workload", choices=["full", "batch"], default="full",
+                    help="full: one robot at full rate; batch: 1024 uneven maps per step")
+    ap.add_argument("--maps", type=int, default=1024)
+    ap.add_argument("--plain-steps", type=int, default=2,
+                    help="batch workload: steps of the per-map call sequence timed beside it")
     return ap.parse_args()
+
+
+def run_batch(args):
+    """1024 independent maps (sides 64-256 cells at 0.05 m, 4k-60k points and
+    one 128x96x16 feature camera each) per step: the batched graph step
+    against the same step as per-map call sequences on one stream."""
+    import torch
+    from paper_2309_16818_amd import mem, synth
+    t0 = time.time()
+    world = synth.BatchWorld(n=args.maps, seed=3, device="cuda")
+    steps = [world.step(k) for k in range(args.warmup + args.steps)]
+    imgs = [world.images(11), world.images(12)]
+    torch.cuda.synchronize()
+    print(f"# generated {len(steps)} batch steps in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    side = [int(s) for s in world.side]
+    cam = synth.BATCH_CAM
+    layers = [mem.Layer(cam["c"], mem.MEM_GAUSS, 1.0)]
+    max_pts = max(int(s["offsets"][-1]) for s in steps)
+    B = mem.Batch(side, side, synth.BATCH_RES, layers=layers, max_points=max_pts,
+                  cam=(cam["h"], cam["w"], cam["c"], mem.MEM_F32), img_bind=[(8, 0, cam["c"])],
+                  max_range=100.0)
+
+    def bstep(k):
+        s = steps[k]
+        B.step(s["robot_xy"], s["xyz"], s["offsets"], s["T"], images=imgs[k % 2], K=s["K"], T_cam=s["T_cam"])
+
+    s0 = steps[0]
+    tuning = B.tune(s0["robot_xy"], s0["xyz"], s0["offsets"], s0["T"], images=imgs[0], K=s0["K"], T_cam=s0["T_cam"])
+    print(f"# tuned: {tuning}", file=sys.stderr, flush=True)
+    for k in range(args.warmup):
+        bstep(k)
+    torch.cuda.synchronize()
+    B.reset_stats()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t1 = time.perf_counter()
+    for j in range(args.steps):
+        ev[j][0].record()
+        bstep(args.warmup + j)
+        ev[j][1].record()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    st = B.stats()
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    batched_pts = st["points_accepted"] / (t2 - t1)
+
+    # the same steps as per-map call sequences (mem_move, mem_input_pointcloud, mem_input_image)
+    plain = [mem.Map(mem.MapParams(s_, s_, synth.BATCH_RES, max_range=100.0, layers=layers)) for s_ in side]
+    def pstep(k):
+        s = steps[k]
+        o = s["offsets"]
+        for m, mp in enumerate(plain):
+            mp.move(*s["robot_xy"][m])
+            mp.input_pointcloud(s["xyz"][o[m]:o[m + 1]], s["T"][m])
+            mp.input_image(imgs[k % 2][m], s["K"][m], s["T_cam"][m], bind=[(8, 0, cam["c"])])
+    pstep(0)
+    torch.cuda.synchronize()
+    for mp in plain:
+        mp.reset_stats()
+    t3 = time.perf_counter()
+    for j in range(args.plain_steps):
+        pstep(1 + j)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    p_acc = sum(mp.stats()["points_accepted"] for mp in plain)
+    plain_pts = p_acc / (t4 - t3)
+    out = {
+        "metric": METRIC, "value": round(batched_pts, 1), "unit": "points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round((t2 - t1) * 1e3 / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batched: {args.maps} maps, sides 64-256 cells at 0.05 m, 4k-60k points and "
+                               f"one 128x96x16 feature camera per map per step, one graph launch per step",
+                   "cells": int(sum(s_ * s_ for s_ in side)),
+                   "points_per_step": round(st["points_in"] / args.steps)},
+        "latency_ms": {"mean": round(float(lat.mean()), 4), "std": round(float(lat.std()), 4),
+                       "median": round(float(np.median(lat)), 4), "p90": round(float(np.percentile(lat, 90)), 4)},
+        "tuning": tuning,
+        "plain": {"value": round(plain_pts, 1), "unit": "points/s",
+                  "ms_per_step": round((t4 - t3) * 1e3 / args.plain_steps, 3), "steps": args.plain_steps},
+        "batched_over_plain": round(batched_pts / plain_pts, 2),
+        "stats": st,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def gen_frames(n, seed, device):
@@ -117,6 +204,8 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.workload == "batch":
+        return run_batch(args)
     import torch
     from paper_2309_16818_amd import mem
 

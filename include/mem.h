@@ -362,6 +362,86 @@ mem_status mem_batch_get_center(const mem_batch* batch, int32_t map, int32_t* cx
 mem_status mem_batch_get_stats(mem_batch* batch, mem_stats* out, void* stream);
 mem_status mem_batch_reset_stats(mem_batch* batch, void* stream);
 
+/* ---------------------------------------------------------------------- */
+/* Learned completion of the height layers                                 */
+/* ---------------------------------------------------------------------- */
+
+/* A network that takes map layers and produces a new one (the plugin slot
+ * of Sec. III-D): a 4-level U-Net that predicts, for every cell of a
+ * size x size window, a height and a log variance from three input channels
+ *   x[b][i][j][0] = h - z_ref   (0 where the cell has no height)
+ *   x[b][i][j][1] = log v       (0 where the cell has no height)
+ *   x[b][i][j][2] = 1 if the cell has a height, else 0
+ * (NHWC FP32, b < batch, row i = logical grid row).  Level l (l = 0..3) works
+ * at size / 2^l with base * 2^l channels: two 3x3 convolutions with ReLU,
+ * then 2x2 max pooling; the way up is a 2x2 stride-2 transposed convolution,
+ * concatenation [up, skip] and two 3x3 convolutions with ReLU; a 1x1 head
+ * gives out[b][i][j][0] = predicted h - z_ref, [1] = predicted log sigma^2.
+ *
+ * Parameters are one flat FP32 array, layer by layer in the order
+ *   enc0a enc0b enc1a enc1b enc2a enc2b enc3a enc3b
+ *   up2 dec2a dec2b  up1 dec1a dec1b  up0 dec0a dec0b  head
+ * each as weights [taps][c_in][c_out] (taps 9 row-major for 3x3, 4 for the
+ * transposed 2x2 with tap = 2 dy + dx, 1 for the head) followed by the bias
+ * [c_out]; dec*a takes c_in = [up channels, skip channels].  Products run on
+ * BF16 operands (activations and a BF16 copy of the weights) with FP32
+ * accumulation; the master weights and Adam moments are FP32.
+ *
+ * Training loss over cells with mask > 0, for out = (m, s):
+ *   L = inv_count * sum 0.5 (s + (t - m)^2 exp(-s))
+ * the Gaussian negative log-likelihood of the target height t. */
+typedef struct mem_unet mem_unet;
+
+/* Number of parameters for a base width (1 .. 256), or -1. */
+int64_t mem_unet_num_params(int32_t base);
+
+/* Allocates a network for batches of up to max_batch windows of size x size
+ * (size a multiple of 8, 8 .. 4096) with He-normal weights drawn from `seed`
+ * (deterministic) and zero biases.  MEM_E_ARG on bad sizes, MEM_E_NOMEM. */
+mem_status mem_unet_create(int32_t base, int32_t max_batch, int32_t size, uint64_t seed, void* stream,
+                           mem_unet** out);
+mem_status mem_unet_destroy(mem_unet* net, void* stream);
+
+/* Copies the flat parameters in (device, mem_unet_num_params floats; resets
+ * the Adam state) or out. */
+mem_status mem_unet_set_params(mem_unet* net, const float* params, void* stream);
+mem_status mem_unet_get_params(const mem_unet* net, float* params, void* stream);
+
+/* Writes / reads the parameters as a file: the 8 bytes "MEMUNET1", int32
+ * base, int64 count, then count little-endian FP32 values.  Synchronises
+ * `stream`.  MEM_E_ARG if the file does not match the network. */
+mem_status mem_unet_save(const mem_unet* net, const char* path, void* stream);
+mem_status mem_unet_load(mem_unet* net, const char* path, void* stream);
+
+/* out (device, batch x size x size x 2) = network(x) for batch windows x
+ * (device, batch x size x size x 3). */
+mem_status mem_unet_forward(mem_unet* net, const float* x, int32_t batch, float* out, void* stream);
+
+/* Loss and its gradient with respect to every parameter (flat layout) for
+ * targets t and masks (device, batch x size x size each); grad and loss are
+ * device pointers and may be NULL.  inv_count > 0, normally 1 / (number of
+ * cells with mask > 0). */
+mem_status mem_unet_loss_grad(mem_unet* net, const float* x, const float* target, const float* mask,
+                              int32_t batch, float inv_count, float* grad, float* loss, void* stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the
+ * gradient of mem_unet_loss_grad at learning rate lr; loss (device) may be
+ * NULL. */
+mem_status mem_unet_train_step(mem_unet* net, const float* x, const float* target, const float* mask,
+                               int32_t batch, float inv_count, float lr, float* loss, void* stream);
+
+/* Completion of a map's height layer: runs the network on the whole map
+ * (width = height = the network's size, input built from the map's
+ * elevation and variance around z_ref) and writes, for every cell in
+ * logical row-major order (device, W x H each),
+ *   observed cell:                 out_h = h,        out_sigma = sqrt(v)
+ *   unobserved, predicted sigma < sigma_max:
+ *                                  out_h = network,  out_sigma = predicted
+ *   otherwise:                     NaN, NaN.
+ * The classical layers are not modified. */
+mem_status mem_complete(const mem_map* map, mem_unet* net, float z_ref, float sigma_max, float* out_h,
+                        float* out_sigma, void* stream);
+
 /* Message of the calling thread's last failure ("" if none). */
 const char* mem_last_error(void);
 

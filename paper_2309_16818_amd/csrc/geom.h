@@ -95,6 +95,26 @@ struct LineWalk {
             steps = dy;
         }
     }
+    // Moves from the start cell directly to the cell after i steps.  With
+    // dmaj = |major extent| and dmin = |minor extent|, the minor offset after
+    // i steps is m = floor((2 i dmin + dmaj - 1) / (2 dmaj)) (the nearest
+    // lattice point to the ideal line, ties toward the start) and the error
+    // term is D = 2 dmin (i + 1) - dmaj - 2 dmaj m, exactly what i calls of
+    // step() produce.
+    __device__ __forceinline__ void jump_from_start(int i)
+    {
+        const int64_t dmaj = dmaj2 >> 1, dmin = dmin2 >> 1;
+        if (i <= 0 || dmaj == 0) return;
+        const int64_t m = (2 * (int64_t)i * dmin + dmaj - 1) / (2 * dmaj);
+        D = (int)(2 * dmin * ((int64_t)i + 1) - dmaj - 2 * dmaj * m);
+        if (xmajor) {
+            x += sx * i;
+            y += sy * (int)m;
+        } else {
+            y += sy * i;
+            x += sx * (int)m;
+        }
+    }
     __device__ __forceinline__ void step()
     {
         if (xmajor) {
@@ -186,6 +206,20 @@ __device__ __forceinline__ int walk_cells(const Grid& g, Ray& r, const float* __
         rem -= U;
     }
     return loaded;
+}
+
+// Visits `count` cells of the ray starting with intermediate cell `first`
+// (1 = the cell after the start cell), U at a time, like walk_cells.
+template <int U, class Visit>
+__device__ __forceinline__ int walk_range(const Grid& g, Ray& r, const float* __restrict__ h,
+                                          int first, int count, Visit&& visit)
+{
+    r.L.jump_from_start(first - 1);
+    const int steps = r.L.steps;
+    r.L.steps = count + 1;  // walk_cells visits steps - 1 cells
+    const int n = walk_cells<U>(g, r, h, visit);
+    r.L.steps = steps;
+    return n;
 }
 
 }  // namespace memk

@@ -46,6 +46,119 @@ __global__ __launch_bounds__(256) void k_project(Grid g, Camera cam, const float
     block_stats(stats, ids, vals);
 }
 
+// Pass 1 of the two-pass projection: frustum test and pixel of every image
+// per cell; cells inside at least one view are appended to vlist
+// (st, ix, iy, intermediate cells of the occlusion line) and their codes to
+// vcode[k * cap + position].
+__global__ __launch_bounds__(256) void k_view(Grid g, Camera cam, const float* __restrict__ h,
+                                              int4* __restrict__ vlist, int* __restrict__ vcode, int cap,
+                                              int* __restrict__ vcount, int32_t* __restrict__ dbg,
+                                              unsigned long long* __restrict__ stats)
+{
+    const int ix = blockIdx.x * kTile + threadIdx.x;
+    const int iy = blockIdx.y * kTile + threadIdx.y;
+    int code[kMaxImages];
+#pragma unroll
+    for (int k = 0; k < kMaxImages; k++) code[k] = -1;
+    int st = 0, in_view = 0, steps = 0;
+    if (ix < g.W && iy < g.H) {
+        st = storage_index(g, ix, iy);
+        in_view = view_cell(g, cam, h, ix, iy, st, code);
+        if (in_view) {
+            int ax, ay;
+            lattice_cell(g, cam.T.m[3], cam.T.m[7], ax, ay);
+            steps = max(abs(ix - ax), abs(iy - ay)) - 1;
+        }
+    }
+    const bool any = in_view > 0;
+    const unsigned long long mask = __ballot(any);
+    if (mask) {
+        const int lane = __lane_id();
+        const int leader = __ffsll((long long)mask) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(vcount, __popcll(mask));
+        base = __shfl(base, leader);
+        if (any) {
+            const int pos = base + __popcll(mask & ((1ull << lane) - 1ull));
+            vlist[pos] = make_int4(st, ix, iy, steps > 0 ? steps : 0);
+#pragma unroll
+            for (int k = 0; k < kMaxImages; k++)
+                if (k < cam.n) vcode[(int64_t)k * cap + pos] = code[k];
+        }
+    }
+    if (dbg && ix < g.W && iy < g.H && !any) dbg[iy * g.W + ix] = code[0];
+    const int ids[1] = {ST_IN_VIEW};
+    int vals[1] = {in_view};
+    block_stats(stats, ids, vals);
+}
+
+// Pass 2: kOccLanes lanes per in-view cell split its occlusion line into
+// equal runs of cells; the cell is visible iff no lane finds an occluder.
+// The first lane of the group appends the cell's pixel to every image's
+// pair list in which it lies inside the view.
+constexpr int kOccLanes = 8;
+
+__global__ __launch_bounds__(256) void k_occlude(Grid g, Camera cam, const float* __restrict__ h,
+                                                 const int4* __restrict__ vlist,
+                                                 const int* __restrict__ vcode, int cap,
+                                                 const int* __restrict__ vcount,
+                                                 int2* __restrict__ pairs, int* __restrict__ count,
+                                                 int32_t* __restrict__ dbg,
+                                                 unsigned long long* __restrict__ stats)
+{
+    const int N = *vcount;
+    const int lane = __lane_id();
+    const int sub = lane % kOccLanes;        // lane within the cell's group
+    const int grp = lane / kOccLanes;        // group within the wave
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int per_wave = 64 / kOccLanes;
+    const float* T = cam.T.m;
+    int visited = 0, n_vis = 0;
+    for (int64_t base = wave * per_wave; base < N; base += nwaves * per_wave) {
+        const int64_t pos = base + grp;
+        bool occ = false;
+        int4 e = make_int4(0, 0, 0, 0);
+        if (pos < N) {
+            e = vlist[pos];
+            const int total = e.w;  // intermediate cells of the line
+            const int run = (total + kOccLanes - 1) / kOccLanes;
+            const int first = 1 + sub * run;
+            const int cnt = min(run, total - sub * run);
+            if (cnt > 0) {
+                const float hj = h[e.x];
+                const float xc = ((float)(g.ox + e.y) + 0.5f) * g.res;
+                const float yc = ((float)(g.oy + e.z) + 0.5f) * g.res;
+                int ax, ay;
+                lattice_cell(g, T[3], T[7], ax, ay);
+                Ray ray(g, ax, ay, e.y, e.z, T[3], T[7], T[11], xc, yc, hj);
+                visited += walk_range<8>(g, ray, h, first, cnt, [&](int, float hk, float zr) {
+                    if (hk >= zr) occ = true;  // NaN (no height) never occludes
+                    return occ;
+                });
+            }
+        }
+        const unsigned long long om = __ballot(occ);
+        const bool occluded = ((om >> (grp * kOccLanes)) & ((1ull << kOccLanes) - 1ull)) != 0;
+        const bool lead = sub == 0 && pos < N;
+#pragma unroll
+        for (int k = 0; k < kMaxImages; k++) {
+            if (k >= cam.n) break;
+            const int code = lead ? vcode[(int64_t)k * cap + pos] : -1;
+            const bool vis = lead && !occluded && code >= 0;
+            n_vis += vis ? 1 : 0;
+            append_pair(vis, e.x, code, pairs + (int64_t)k * cap, &count[k]);
+        }
+        if (dbg && lead) {
+            const int c0 = vcode[pos];
+            dbg[e.z * g.W + e.y] = (c0 >= 0 && occluded) ? -3 : c0;
+        }
+    }
+    const int ids[2] = {ST_VISIBLE, ST_OCCL_CELLS};
+    int vals[2] = {n_vis, visited};
+    block_stats(stats, ids, vals);
+}
+
 template <int IMG, int S>
 __global__ __launch_bounds__(256) void k_gather_fuse(const int2* __restrict__ pairs,
                                                      const int* __restrict__ count,
@@ -81,11 +194,17 @@ void launch_zero_int(hipStream_t s, int* p, int n)
 }
 
 void launch_project(hipStream_t s, const Grid& g, const Camera& cam, const float* h, int2* pairs,
-                    int cap, int* count, int32_t* dbg, unsigned long long* stats)
+                    int cap, int* count, int4* vlist, int* vcode, int32_t* dbg,
+                    unsigned long long* stats)
 {
     dim3 grid((g.W + kTile - 1) / kTile, (g.H + kTile - 1) / kTile);
-    hipLaunchKernelGGL(k_project, grid, dim3(kTile, kTile), 0, s, g, cam, h, pairs, cap, count, dbg,
-                       stats);
+    hipLaunchKernelGGL(k_view, grid, dim3(kTile, kTile), 0, s, g, cam, h, vlist, vcode, cap,
+                       count + kMaxImages, dbg, stats);
+    int64_t blocks = ((int64_t)cap * kOccLanes + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_occlude, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, h, vlist, vcode, cap,
+                       count + kMaxImages, pairs, count, dbg, stats);
 }
 
 void launch_gather_fuse(hipStream_t s, const int2* pairs, const int* count, int max_pairs,

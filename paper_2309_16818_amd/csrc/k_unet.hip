@@ -1,0 +1,558 @@
+// k_unet.hip - kernels of the completion U-Net (forward, backward, Adam).
+//
+// Every 3x3 convolution, transposed convolution and their gradients is a
+// BF16 matrix product on the MFMA units (v_mfma_f32_16x16x32_bf16, FP32
+// accumulation):
+//   gemm_nt  C[m][n] = sum_k A[m][k] B[n][k]      A, B K-contiguous (im2col
+//            rows x weight rows); epilogue: bias, ReLU or ReLU-mask, BF16/FP32
+//            store, or the 2x2 scatter of a transposed convolution.
+//   gemm_tn  C[m][n] += sum_p A[p][m] B[p][n]     reduction over pixels for
+//            weight gradients, split over pixel ranges with FP32 atomics.
+// Activations are NHWC BF16; a convolution's input is unfolded (im2col)
+// into a K-padded BF16 matrix first.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "codec.h"
+#include "unet_internal.h"
+
+namespace memk {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 64, BN = 64, BK = 32;
+constexpr int LDSK = BK + 8;  // padded row (bf16) against bank conflicts
+
+__device__ __forceinline__ uint16_t bf(float f) { return f32_to_bf16(f); }
+__device__ __forceinline__ float fb(uint16_t b) { return bf16_to_f32(b); }
+
+// Loads 8 consecutive bf16 of row r (K-contiguous, row stride ld) starting
+// at column k0, zero-filling outside [0, rows) x [0, K).
+__device__ __forceinline__ uint4 load8(const uint16_t* __restrict__ p, int64_t ld, int r, int rows, int k0,
+                                       int K)
+{
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (r >= rows) return v;
+    const uint16_t* q = p + (int64_t)r * ld + k0;
+    if (k0 + 8 <= K && ((((uintptr_t)q) & 15) == 0)) return *(const uint4*)q;
+    uint16_t t[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) t[j] = (k0 + j < K) ? q[j] : (uint16_t)0;
+    v.x = t[0] | ((uint32_t)t[1] << 16);
+    v.y = t[2] | ((uint32_t)t[3] << 16);
+    v.z = t[4] | ((uint32_t)t[5] << 16);
+    v.w = t[6] | ((uint32_t)t[7] << 16);
+    return v;
+}
+
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v)
+{
+    bf16x8 r;
+    __builtin_memcpy(&r, &v, 16);
+    return r;
+}
+
+// C = A B^T on a 64x64 tile; 4 waves, each a 32x32 quadrant of 2x2 MFMA
+// 16x16x32 blocks.  Lane l of an MFMA block supplies A[l % 16][8 (l / 16) ..
+// + 7] and B[l % 16][8 (l / 16) .. + 7] and receives D[4 (l / 16) + j][l % 16].
+template <int EPI>
+__global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A, int64_t lda,
+                                                 const uint16_t* __restrict__ B, int64_t ldb, int M,
+                                                 int N, int K, Epilogue ep)
+{
+    __shared__ uint16_t sA[BM * LDSK];
+    __shared__ uint16_t sB[BN * LDSK];
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int lr = tid >> 2, lk = (tid & 3) * 8;  // 64 rows x 4 chunks of 8
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        const uint4 va = load8(A, lda, m0 + lr, M, k0 + lk, K);
+        const uint4 vb = load8(B, ldb, n0 + lr, N, k0 + lk, K);
+        __syncthreads();
+        *(uint4*)&sA[lr * LDSK + lk] = va;
+        *(uint4*)&sB[lr * LDSK + lk] = vb;
+        __syncthreads();
+        const int fr = lane & 15, fk = (lane >> 4) * 8;
+#pragma unroll
+        for (int i = 0; i < 2; i++) {
+            const bf16x8 a = as_bf16x8(*(const uint4*)&sA[(wm + 16 * i + fr) * LDSK + fk]);
+#pragma unroll
+            for (int j = 0; j < 2; j++) {
+                const bf16x8 b = as_bf16x8(*(const uint4*)&sB[(wn + 16 * j + fr) * LDSK + fk]);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+                const int n = n0 + wn + 16 * j + (lane & 15);
+                if (m < M && n < N) epilogue<EPI>(ep, m, n, acc[i][j][r]);
+            }
+}
+
+// C[m][n] += sum_p A[p][m] B[p][n] over the pixel range of this block
+// (blockIdx.z of gridDim.z equal slices).
+__global__ __launch_bounds__(256) void k_gemm_tn(const uint16_t* __restrict__ A, int64_t lda,
+                                                 const uint16_t* __restrict__ B, int64_t ldb, int P,
+                                                 int M, int N, float* __restrict__ C, int64_t ldc)
+{
+    __shared__ uint16_t sA[BM * LDSK];  // [m][p]
+    __shared__ uint16_t sB[BN * LDSK];  // [n][p]
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    const int slice = (P + gridDim.z - 1) / gridDim.z;
+    const int p_begin = blockIdx.z * slice;
+    const int p_end = min(P, p_begin + slice);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int lp = tid >> 3, lc = (tid & 7) * 8;  // 32 pixels x 8 chunks of 8 columns
+    for (int p0 = p_begin; p0 < p_end; p0 += BK) {
+        const uint4 va = load8(A, lda, p0 + lp, p_end, m0 + lc, M);
+        const uint4 vb = load8(B, ldb, p0 + lp, p_end, n0 + lc, N);
+        __syncthreads();
+        const uint16_t* ta = (const uint16_t*)&va;
+        const uint16_t* tb = (const uint16_t*)&vb;
+#pragma unroll
+        for (int j = 0; j < 8; j++) {  // transpose into [column][pixel]
+            sA[(lc + j) * LDSK + lp] = ta[j];
+            sB[(lc + j) * LDSK + lp] = tb[j];
+        }
+        __syncthreads();
+        const int fr = lane & 15, fk = (lane >> 4) * 8;
+#pragma unroll
+        for (int i = 0; i < 2; i++) {
+            const bf16x8 a = as_bf16x8(*(const uint4*)&sA[(wm + 16 * i + fr) * LDSK + fk]);
+#pragma unroll
+            for (int j = 0; j < 2; j++) {
+                const bf16x8 b = as_bf16x8(*(const uint4*)&sB[(wn + 16 * j + fr) * LDSK + fk]);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+                const int n = n0 + wn + 16 * j + (lane & 15);
+                if (m < M && n < N) unsafeAtomicAdd(&C[(int64_t)m * ldc + n], acc[i][j][r]);
+            }
+}
+
+// Unfolds 3x3 neighbourhoods (zero padding): col[p][t * ci + c] =
+// x[n][y + ty - 1][x + tx - 1][c] (channel stride xs, offset xo), K padded
+// with zeros to kpad.
+__global__ void k_im2col3(const uint16_t* __restrict__ x, int xs, int xo, int B, int S, int ci,
+                          uint16_t* __restrict__ col, int kpad)
+{
+    const int64_t total = (int64_t)B * S * S * kpad;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int k = (int)(e % kpad);
+        const int64_t p = e / kpad;
+        uint16_t v = 0;
+        if (k < 9 * ci) {
+            const int t = k / ci, c = k - t * ci;
+            const int q = (int)(p % S), r = (int)((p / S) % S);
+            const int64_t n = p / ((int64_t)S * S);
+            const int rr = r + t / 3 - 1, qq = q + t % 3 - 1;
+            if (rr >= 0 && rr < S && qq >= 0 && qq < S) v = x[((n * S + rr) * S + qq) * xs + xo + c];
+        }
+        col[e] = v;
+    }
+}
+
+// Gathers the 2x2 children of every coarse pixel: g[p][t * c + o] =
+// dy[n][2 r + t / 2][2 q + t % 2][o] (channel stride ys, offset yo).
+__global__ void k_gather_children(const uint16_t* __restrict__ dy, int ys, int yo, int B, int S, int c,
+                                  uint16_t* __restrict__ g)
+{
+    const int64_t total = (int64_t)B * S * S * 4 * c;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int k = (int)(e % (4 * c));
+        const int64_t p = e / (4 * c);
+        const int t = k / c, o = k - t * c;
+        const int q = (int)(p % S), r = (int)((p / S) % S);
+        const int64_t n = p / ((int64_t)S * S);
+        const int S2 = 2 * S;
+        g[e] = dy[((n * S2 + 2 * r + t / 2) * S2 + 2 * q + t % 2) * ys + yo + o];
+    }
+}
+
+// 2x2 max pool (ties: first in row-major order) of x (stride xs), keeping the
+// winner's index for the backward pass.
+__global__ void k_maxpool(const uint16_t* __restrict__ x, int xs, int B, int S, int c,
+                          uint16_t* __restrict__ y, uint8_t* __restrict__ arg)
+{
+    const int H = S / 2;
+    const int64_t total = (int64_t)B * H * H * c;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int o = (int)(e % c);
+        const int64_t p = e / c;
+        const int q = (int)(p % H), r = (int)((p / H) % H);
+        const int64_t n = p / ((int64_t)H * H);
+        float bv = 0.f;
+        int best = 0;
+        for (int t = 0; t < 4; t++) {
+            const float v = fb(x[((n * S + 2 * r + t / 2) * S + 2 * q + t % 2) * xs + o]);
+            if (t == 0 || v > bv) {
+                bv = v;
+                best = t;
+            }
+        }
+        y[e] = bf(bv);
+        arg[e] = (uint8_t)best;
+    }
+}
+
+// dx[winner] += dy (both FP32; dx stride dxs).
+__global__ void k_maxpool_bwd(const float* __restrict__ dy, const uint8_t* __restrict__ arg, int B, int S,
+                              int c, float* __restrict__ dx, int dxs)
+{
+    const int H = S / 2;
+    const int64_t total = (int64_t)B * H * H * c;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int o = (int)(e % c);
+        const int64_t p = e / c;
+        const int q = (int)(p % H), r = (int)((p / H) % H);
+        const int64_t n = p / ((int64_t)H * H);
+        const int t = arg[e];
+        dx[((n * S + 2 * r + t / 2) * S + 2 * q + t % 2) * dxs + o] += dy[e];
+    }
+}
+
+// g (BF16 out) = (acc + add) * (y > 0), over n x c elements with strides.
+__global__ void k_relu_mask_add(const float* __restrict__ acc, int as, const float* __restrict__ add, int ads,
+                                const uint16_t* __restrict__ y, int ysd, int64_t rows, int c,
+                                uint16_t* __restrict__ g, int gs)
+{
+    const int64_t total = rows * c;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int o = (int)(e % c);
+        const int64_t p = e / c;
+        float v = acc[p * as + o] + (add ? add[p * ads + o] : 0.f);
+        if (y && !(fb(y[p * ysd + o]) > 0.f)) v = 0.f;  // no y: no ReLU mask
+        g[p * gs + o] = bf(v);
+    }
+}
+
+// Column sums: db[o] += sum_p g[p][o] (BF16 g, stride gs).
+__global__ void k_colsum(const uint16_t* __restrict__ g, int gs, int64_t rows, int c, float* __restrict__ db)
+{
+    const int o = blockIdx.y * blockDim.x + threadIdx.x;
+    if (o >= c) return;
+    float s = 0.f;
+    for (int64_t p = blockIdx.x; p < rows; p += gridDim.x) s += fb(g[p * gs + o]);
+    unsafeAtomicAdd(&db[o], s);
+}
+
+// Head (1x1 convolution, 2 outputs, FP32 weights) and the Gaussian NLL over
+// mask > 0; writes out (optional), dout-derived head gradients and the
+// gradient with respect to d0 (BF16, ReLU-masked by d0).
+__global__ void k_head_loss(const uint16_t* __restrict__ d0, int c, int64_t P, const float* __restrict__ w,
+                            const float* __restrict__ b, const float* __restrict__ target,
+                            const float* __restrict__ mask, float inv_count, float* __restrict__ out,
+                            float* __restrict__ loss, float* __restrict__ gw, float* __restrict__ gb,
+                            uint16_t* __restrict__ gd0)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+        float o0 = b[0], o1 = b[1];
+        for (int i = 0; i < c; i++) {
+            const float a = fb(d0[p * c + i]);
+            o0 += a * w[2 * i];
+            o1 += a * w[2 * i + 1];
+        }
+        if (out) {
+            out[2 * p] = o0;
+            out[2 * p + 1] = o1;
+        }
+        if (!target) continue;
+        float g0 = 0.f, g1 = 0.f;
+        if (mask[p] > 0.f) {
+            const float r = target[p] - o0, e = expf(-o1);
+            unsafeAtomicAdd(loss, 0.5f * (o1 + r * r * e) * inv_count);
+            g0 = -r * e * inv_count;
+            g1 = 0.5f * (1.f - r * r * e) * inv_count;
+        }
+        if (g0 != 0.f || g1 != 0.f) {
+            unsafeAtomicAdd(&gb[0], g0);
+            unsafeAtomicAdd(&gb[1], g1);
+        }
+        for (int i = 0; i < c; i++) {
+            const float a = fb(d0[p * c + i]);
+            if (g0 != 0.f || g1 != 0.f) {
+                unsafeAtomicAdd(&gw[2 * i], g0 * a);
+                unsafeAtomicAdd(&gw[2 * i + 1], g1 * a);
+            }
+            const float gd = (a > 0.f) ? g0 * w[2 * i] + g1 * w[2 * i + 1] : 0.f;
+            gd0[p * c + i] = bf(gd);
+        }
+    }
+}
+
+// dst[p][o] += src[p][o] (FP32, strides ds / ss).
+__global__ void k_add_f32(float* __restrict__ dst, int ds, const float* __restrict__ src, int ss, int64_t rows, int c)
+{
+    const int64_t total = rows * c;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int o = (int)(e % c);
+        const int64_t p = e / c;
+        dst[p * ds + o] += src[p * ss + o];
+    }
+}
+
+__global__ void k_cast_bf16(const float* __restrict__ x, int64_t n, uint16_t* __restrict__ y)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = bf(x[i]);
+}
+
+__global__ void k_fill(float* __restrict__ x, int64_t n, float v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = v;
+}
+
+// Weight layouts.  Master weights are the flat FP32 array (per layer
+// [taps][ci][co] then bias).  Forward operand of a 3x3 conv: wf[co][t ci + c]
+// (K padded to kpad); its input-gradient operand (flipped taps):
+// wd[c][t' co + o] = W[8 - t'][c][o]; transposed conv forward operand
+// wu[t co + o][c] = U[t][c][o]; its input-gradient operand
+// wub[c][t co + o] = U[t][c][o].
+__global__ void k_relayout(const float* __restrict__ w, int taps, int ci, int co, int kind, int kpad,
+                           uint16_t* __restrict__ dst)
+{
+    const int64_t total = (int64_t)taps * ci * co;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int o = (int)(e % co);
+        const int c = (int)((e / co) % ci);
+        const int t = (int)(e / ((int64_t)co * ci));
+        const uint16_t v = bf(w[e]);
+        switch (kind) {
+        case 0: dst[(int64_t)o * kpad + t * ci + c] = v; break;                    // conv fwd
+        case 1: dst[(int64_t)c * kpad + (taps - 1 - t) * co + o] = v; break;       // conv dgrad
+        case 2: dst[((int64_t)t * co + o) * ci + c] = v; break;                    // convT fwd
+        default: dst[(int64_t)c * (taps * co) + t * co + o] = v; break;            // convT dgrad
+        }
+    }
+}
+
+// Back to the flat layout: conv gradient g[co][t ci + c] (ld kpad) or convT
+// gradient g[t co + o][c] -> flat[t][c][o] (added).
+__global__ void k_grad_to_flat(const float* __restrict__ g, int taps, int ci, int co, int kind, int kpad,
+                               float* __restrict__ flat)
+{
+    const int64_t total = (int64_t)taps * ci * co;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int o = (int)(e % co);
+        const int c = (int)((e / co) % ci);
+        const int t = (int)(e / ((int64_t)co * ci));
+        flat[e] = (kind == 0) ? g[(int64_t)o * kpad + t * ci + c] : g[((int64_t)t * co + o) * ci + c];
+    }
+}
+
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float c1,
+                       float c2)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+// Network input from a map: (h - z_ref, log v, mask) with 0 where invalid.
+__global__ void k_map_input(const float* __restrict__ h, const float* __restrict__ v, Grid g, float z_ref,
+                            float* __restrict__ x)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= g.W * g.H) return;
+    const int ix = j % g.W, iy = j / g.W;
+    int sx = ix + g.rx;
+    sx -= (sx >= g.W) ? g.W : 0;
+    int sy = iy + g.ry;
+    sy -= (sy >= g.H) ? g.H : 0;
+    const int st = sy * g.W + sx;
+    const float hv = h[st];
+    const bool ok = !isnan(hv);
+    x[3 * j] = ok ? hv - z_ref : 0.f;
+    x[3 * j + 1] = ok ? logf(v[st]) : 0.f;
+    x[3 * j + 2] = ok ? 1.f : 0.f;
+}
+
+// Gate: a cell without a classical height takes the network's height where
+// its predicted standard deviation is below sigma_max.
+__global__ void k_gate(const float* __restrict__ x, const float* __restrict__ out, int64_t P, float z_ref,
+                       float sigma_max, float* __restrict__ out_h, float* __restrict__ out_sigma)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+        const bool observed = x[3 * p + 2] > 0.f;
+        const float sig = expf(0.5f * out[2 * p + 1]);
+        if (observed) {
+            out_h[p] = x[3 * p] + z_ref;
+            out_sigma[p] = expf(0.5f * x[3 * p + 1]);
+        } else if (sig < sigma_max) {
+            out_h[p] = out[2 * p] + z_ref;
+            out_sigma[p] = sig;
+        } else {
+            out_h[p] = __builtin_nanf("");
+            out_sigma[p] = __builtin_nanf("");
+        }
+    }
+}
+
+inline unsigned grid_for(int64_t n)
+{
+    int64_t b = (n + 255) / 256;
+    return (unsigned)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
+}
+
+}  // namespace
+
+void unet_gemm_nt(hipStream_t s, int epi, const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, int M,
+                  int N, int K, const Epilogue& ep)
+{
+    dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN);
+    switch (epi) {
+    case EPI_STORE: hipLaunchKernelGGL(k_gemm_nt<EPI_STORE>, grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, ep); break;
+    case EPI_CONVT: hipLaunchKernelGGL(k_gemm_nt<EPI_CONVT>, grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, ep); break;
+    default: hipLaunchKernelGGL(k_gemm_nt<EPI_F32>, grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, ep); break;
+    }
+}
+
+void unet_gemm_tn(hipStream_t s, const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, int P, int M,
+                  int N, float* C, int64_t ldc, int n_cu)
+{
+    const int tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+    int split = (4 * n_cu + tiles - 1) / tiles;
+    const int max_split = (P + 255) / 256;
+    if (split > max_split) split = max_split;
+    if (split < 1) split = 1;
+    dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN, split);
+    hipLaunchKernelGGL(k_gemm_tn, grid, dim3(256), 0, s, A, lda, B, ldb, P, M, N, C, ldc);
+}
+
+void unet_im2col3(hipStream_t s, const uint16_t* x, int xs, int xo, int B, int S, int ci, uint16_t* col, int kpad)
+{
+    hipLaunchKernelGGL(k_im2col3, dim3(grid_for((int64_t)B * S * S * kpad)), dim3(256), 0, s, x, xs, xo, B, S, ci,
+                       col, kpad);
+}
+
+void unet_gather_children(hipStream_t s, const uint16_t* dy, int ys, int yo, int B, int S, int c, uint16_t* g)
+{
+    hipLaunchKernelGGL(k_gather_children, dim3(grid_for((int64_t)B * S * S * 4 * c)), dim3(256), 0, s, dy, ys, yo,
+                       B, S, c, g);
+}
+
+void unet_maxpool(hipStream_t s, const uint16_t* x, int xs, int B, int S, int c, uint16_t* y, uint8_t* arg)
+{
+    hipLaunchKernelGGL(k_maxpool, dim3(grid_for((int64_t)B * (S / 2) * (S / 2) * c)), dim3(256), 0, s, x, xs, B, S,
+                       c, y, arg);
+}
+
+void unet_maxpool_bwd(hipStream_t s, const float* dy, const uint8_t* arg, int B, int S, int c, float* dx,
+                      int dxs)
+{
+    hipLaunchKernelGGL(k_maxpool_bwd, dim3(grid_for((int64_t)B * (S / 2) * (S / 2) * c)), dim3(256), 0, s, dy,
+                       arg, B, S, c, dx, dxs);
+}
+
+void unet_relu_mask_add(hipStream_t s, const float* acc, int as, const float* add, int ads, const uint16_t* y,
+                        int ys, int64_t rows, int c, uint16_t* g, int gs)
+{
+    hipLaunchKernelGGL(k_relu_mask_add, dim3(grid_for(rows * c)), dim3(256), 0, s, acc, as, add, ads, y, ys, rows,
+                       c, g, gs);
+}
+
+void unet_colsum(hipStream_t s, const uint16_t* g, int gs, int64_t rows, int c, float* db)
+{
+    int64_t gx = rows < 1024 ? rows : 1024;
+    dim3 grid((unsigned)(gx < 1 ? 1 : gx), (unsigned)((c + 63) / 64));
+    hipLaunchKernelGGL(k_colsum, grid, dim3(64), 0, s, g, gs, rows, c, db);
+}
+
+void unet_head_loss(hipStream_t s, const uint16_t* d0, int c, int64_t P, const float* w, const float* b,
+                    const float* target, const float* mask, float inv_count, float* out, float* loss, float* gw,
+                    float* gb, uint16_t* gd0)
+{
+    hipLaunchKernelGGL(k_head_loss, dim3(grid_for(P)), dim3(256), 0, s, d0, c, P, w, b, target, mask, inv_count,
+                       out, loss, gw, gb, gd0);
+}
+
+void unet_add_f32(hipStream_t s, float* dst, int ds, const float* src, int ss, int64_t rows, int c)
+{
+    hipLaunchKernelGGL(k_add_f32, dim3(grid_for(rows * c)), dim3(256), 0, s, dst, ds, src, ss, rows, c);
+}
+
+void unet_cast_bf16(hipStream_t s, const float* x, int64_t n, uint16_t* y)
+{
+    hipLaunchKernelGGL(k_cast_bf16, dim3(grid_for(n)), dim3(256), 0, s, x, n, y);
+}
+
+void unet_fill(hipStream_t s, float* x, int64_t n, float v)
+{
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(256), 0, s, x, n, v);
+}
+
+void unet_relayout(hipStream_t s, const float* w, int taps, int ci, int co, int kind, int kpad, uint16_t* dst)
+{
+    hipLaunchKernelGGL(k_relayout, dim3(grid_for((int64_t)taps * ci * co)), dim3(256), 0, s, w, taps, ci, co, kind,
+                       kpad, dst);
+}
+
+void unet_grad_to_flat(hipStream_t s, const float* g, int taps, int ci, int co, int kind, int kpad, float* flat)
+{
+    hipLaunchKernelGGL(k_grad_to_flat, dim3(grid_for((int64_t)taps * ci * co)), dim3(256), 0, s, g, taps, ci, co,
+                       kind, kpad, flat);
+}
+
+void unet_adam(hipStream_t s, float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+               float eps, float c1, float c2)
+{
+    hipLaunchKernelGGL(k_adam, dim3(grid_for(n)), dim3(256), 0, s, w, g, m, v, n, lr, b1, b2, eps, c1, c2);
+}
+
+void unet_map_input(hipStream_t s, const float* h, const float* v, const Grid& g, float z_ref, float* x)
+{
+    hipLaunchKernelGGL(k_map_input, dim3((g.W * g.H + 255) / 256), dim3(256), 0, s, h, v, g, z_ref, x);
+}
+
+void unet_gate(hipStream_t s, const float* x, const float* out, int64_t P, float z_ref, float sigma_max,
+               float* out_h, float* out_sigma)
+{
+    hipLaunchKernelGGL(k_gate, dim3(grid_for(P)), dim3(256), 0, s, x, out, P, z_ref, sigma_max, out_h, out_sigma);
+}
+
+}  // namespace memk

@@ -31,6 +31,24 @@ mem_status fail(mem_status code, const char* fmt, ...)
     return code;
 }
 
+}  // namespace
+
+namespace memk {
+// Error reporting shared with the batch entry points (batch_api.hip).
+mem_status api_fail(mem_status code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+}  // namespace memk
+
+namespace {
+
 struct Layer {
     int C, rule, storage;
     float param;
@@ -81,7 +99,9 @@ struct mem_map {
     float* ssum = nullptr;
     float2* stash = nullptr;
     int2* pairs = nullptr;
-    int* pair_count = nullptr;
+    int* pair_count = nullptr;  // [kMaxImages] pair counts, then the in-view count
+    int4* vlist = nullptr;      // cells inside a camera's view
+    int* vcode = nullptr;       // their pixel per image
     unsigned long long* stats = nullptr;
     float* chsum = nullptr;
     int chsum_planes = 0;
@@ -239,6 +259,8 @@ void free_map(mem_map* m)
     (void)hipFree(m->stash);
     (void)hipFree(m->pairs);
     (void)hipFree(m->pair_count);
+    (void)hipFree(m->vlist);
+    (void)hipFree(m->vcode);
     (void)hipFree(m->stats);
     (void)hipFree(m->chsum);
     for (auto& L : m->layers) {
@@ -331,7 +353,9 @@ mem_status mem_create(const mem_params* p, void* stream, mem_map** out)
         (st = dev_alloc(m, &m->cnt, HW)) || (st = dev_alloc(m, &m->clr, HW)) ||
         (st = dev_alloc(m, &m->wsum, HW)) || (st = dev_alloc(m, &m->ssum, HW)) ||
         (st = dev_alloc(m, &m->stash, HW)) || (st = dev_alloc(m, &m->pairs, HW * kMaxImages)) ||
-        (st = dev_alloc(m, &m->pair_count, kMaxImages)) || (st = dev_alloc(m, &m->stats, kStats * kStatSlots))) {
+        (st = dev_alloc(m, &m->vlist, HW)) || (st = dev_alloc(m, &m->vcode, HW * kMaxImages)) ||
+        (st = dev_alloc(m, &m->pair_count, kMaxImages + 1)) ||
+        (st = dev_alloc(m, &m->stats, kStats * kStatSlots))) {
         free_map(m);
         return st;
     }
@@ -364,7 +388,7 @@ mem_status mem_create(const mem_params* p, void* stream, mem_map** out)
     launch_reset_rect(s, g, 0, m->W, 0, m->H, m->h, m->v, m->cnt, m->clr, devs.data(), (int)devs.size());
     launch_zero_accum(s, g, m->cnt, m->wsum, m->ssum, m->clr, nullptr, 0);
     launch_zero_int(s, (int*)m->stats, 2 * kStats * kStatSlots);
-    launch_zero_int(s, m->pair_count, kMaxImages);
+    launch_zero_int(s, m->pair_count, kMaxImages + 1);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
@@ -540,9 +564,10 @@ mem_status mem_input_images(mem_map* m, const mem_image* images, int32_t n_image
     hipStream_t s = (hipStream_t)stream;
     Grid g = m->grid();
     const int cap = (int)m->cells();
-    timed(m, s, "zero_count", [&] { launch_zero_int(s, m->pair_count, kMaxImages); });
+    timed(m, s, "zero_count", [&] { launch_zero_int(s, m->pair_count, kMaxImages + 1); });
     timed(m, s, "project", [&] {
-        launch_project(s, g, cam, m->h, m->pairs, cap, m->pair_count, nullptr, m->stats);
+        launch_project(s, g, cam, m->h, m->pairs, cap, m->pair_count, m->vlist, m->vcode, nullptr,
+                       m->stats);
     });
     for (int k = 0; k < n_images; k++) {
         const mem_image& im = images[k];
@@ -652,8 +677,9 @@ mem_status mem_debug_cell_pixels(const mem_map* mc, int32_t h, int32_t w, const 
     cam.n = 1;
     cam.min_depth = m->min_depth;
     hipStream_t s = (hipStream_t)stream;
-    launch_zero_int(s, m->pair_count, kMaxImages);
-    launch_project(s, m->grid(), cam, m->h, m->pairs, (int)m->cells(), m->pair_count, out, m->stats);
+    launch_zero_int(s, m->pair_count, kMaxImages + 1);
+    launch_project(s, m->grid(), cam, m->h, m->pairs, (int)m->cells(), m->pair_count, m->vlist,
+                   m->vcode, out, m->stats);
     return check_launch(m, "mem_debug_cell_pixels");
 }
 
@@ -708,3 +734,19 @@ mem_status mem_profile_read(mem_map* m, mem_kernel_time* out, int32_t max, int32
 }
 
 }  // extern "C"
+
+namespace memk {
+
+// The current height and variance layers of a map, for the completion network.
+mem_status map_height_view(const mem_map* m, const float** h, const float** v, Grid* g)
+{
+    if (!m) return api_fail(MEM_E_ARG, "map is NULL");
+    if (m->broken) return api_fail(MEM_E_STATE, "map is unusable after an earlier HIP error");
+    *h = m->h;
+    *v = m->v;
+    *g = m->grid();
+    return MEM_OK;
+}
+
+}  // namespace memk
+

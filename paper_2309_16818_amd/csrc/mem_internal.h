@@ -117,8 +117,13 @@ void launch_point_cells(hipStream_t s, const Grid& g, const float* xyz, int64_t 
                         float mr2, int32_t* out);
 
 void launch_zero_int(hipStream_t s, int* p, int n);
+// Two passes: k_view compacts the cells inside any image's view into vlist
+// (cap entries) and vcode (kMaxImages x cap), k_occlude walks their
+// occlusion lines and appends visible pairs.  count: [kMaxImages] pair
+// counts followed by the in-view count, all zero on entry.
 void launch_project(hipStream_t s, const Grid& g, const Camera& cam, const float* h, int2* pairs,
-                    int cap, int* count, int32_t* dbg, unsigned long long* stats);
+                    int cap, int* count, int4* vlist, int* vcode, int32_t* dbg,
+                    unsigned long long* stats);
 void launch_gather_fuse(hipStream_t s, const int2* pairs, const int* count, int max_pairs,
                         const void* img, int img_dtype, int64_t s0, int64_t s1, int64_t s2, int w,
                         int ch_first, const LayerDev& L);
@@ -158,10 +163,10 @@ struct BatchDev {
     int* n_items;           // [0] rects, [1] point chunks (this step)
     const BatchMap* maps;
     const BatchRect* rects;
-    const BatchItem* chunks; // (map, begin, end): global point indices
+    const int* chunk_start;  // [n_maps + 1]: first point-chunk item of each map
     const BatchItem* tiles;  // (map, x0, y0): projection tiles
     const BatchItem* gitems; // (map, first pair): gather items
-    int n_tiles, n_gitems, n_maps;
+    int n_tiles, n_gitems, n_maps, chunk;
     int64_t total_cells;
     unsigned long long* stats;
 };

@@ -195,6 +195,54 @@ __device__ __forceinline__ int finalize_cell(int st, const Accum& acc, int clear
 // (Sec. III-B, Fig. 3).  code[k] = pixel, or -1 no height, -2 outside image
 // k's view, -3 occluded.  Returns the number of in-grid cells the occlusion
 // walk loaded; in_view counts the images whose view holds the cell.
+// Frustum test and pixel of logical cell (ix, iy) in every image of one
+// camera pose, without the occlusion walk.  code[k] = pixel, or -1 no
+// height, -2 outside image k's view.  Returns the number of images whose
+// view holds the cell.
+__device__ __forceinline__ int view_cell(const Grid& g, const Camera& cam,
+                                         const float* __restrict__ h, int ix, int iy, int st,
+                                         int (&code)[kMaxImages])
+{
+#pragma unroll
+    for (int k = 0; k < kMaxImages; k++) code[k] = -1;
+    const float hj = h[st];
+    if (isnan(hj)) return 0;
+    const float* T = cam.T.m;
+    const float xc = ((float)(g.ox + ix) + 0.5f) * g.res;
+    const float yc = ((float)(g.oy + iy) + 0.5f) * g.res;
+    const float dx = xc - T[3], dy = yc - T[7], dz = hj - T[11];
+    float P[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) {  // R^T d
+        float a = T[0 + k] * dx;
+        float b = T[4 + k] * dy;
+        float c = T[8 + k] * dz;
+        float s = a + b;
+        P[k] = s + c;
+    }
+    int in_view = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxImages; k++) {
+        if (k >= cam.n) break;
+        code[k] = -2;
+        if (P[2] > cam.min_depth) {
+            float u = cam.fx[k] * P[0];
+            u = u / P[2];
+            u = u + cam.cx[k];
+            float v = cam.fy[k] * P[1];
+            v = v / P[2];
+            v = v + cam.cy[k];
+            const float uf = floorf(u + 0.5f);
+            const float vf = floorf(v + 0.5f);
+            if (uf >= 0.0f && uf < (float)cam.w[k] && vf >= 0.0f && vf < (float)cam.h[k]) {
+                code[k] = (int)vf * cam.w[k] + (int)uf;
+                in_view++;
+            }
+        }
+    }
+    return in_view;
+}
+
 __device__ __forceinline__ int project_cell(const Grid& g, const Camera& cam,
                                             const float* __restrict__ h, int ix, int iy, int st,
                                             int (&code)[kMaxImages], int& in_view)

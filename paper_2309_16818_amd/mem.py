@@ -310,3 +310,303 @@ class Map:
         n = C.c_int32()
         _check(load().mem_profile_read(self._h, arr, 64, C.byref(n)))
         return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(min(n.value, 64))}
+
+
+# ---------------------------------------------------------------------------
+# Batches of maps (mem_batch_*)
+# ---------------------------------------------------------------------------
+
+class mem_batch_params(C.Structure):
+    _fields_ = [("n_maps", C.c_int32), ("width", C.POINTER(C.c_int32)), ("height", C.POINTER(C.c_int32)),
+                ("resolution", C.c_float), ("noise_c0", C.c_float), ("noise_c1", C.c_float),
+                ("max_range", C.c_float), ("clear_margin", C.c_float), ("clear_min_count", C.c_int32),
+                ("min_depth", C.c_float), ("n_layers", C.c_int32), ("layers", C.POINTER(mem_layer_desc)),
+                ("max_points", C.c_int64), ("cam_h", C.c_int32), ("cam_w", C.c_int32), ("cam_c", C.c_int32),
+                ("cam_dtype", C.c_int32), ("n_img_bind", C.c_int32), ("img_bind", C.POINTER(mem_binding))]
+
+
+class mem_batch_input(C.Structure):
+    _fields_ = [("robot_xy", C.c_void_p), ("xyz", C.c_void_p), ("offsets", C.c_void_p),
+                ("T_map_sensor", C.c_void_p), ("images", C.c_void_p), ("K", C.c_void_p),
+                ("T_map_cam", C.c_void_p)]
+
+
+class mem_batch_tuning(C.Structure):
+    _fields_ = [("chunk", C.c_int32), ("wg_per_cu", C.c_int32), ("tile", C.c_int32), ("graph", C.c_int32),
+                ("step_ms", C.c_double)]
+
+
+BATCH_SYMBOLS = ("mem_batch_create", "mem_batch_destroy", "mem_batch_step", "mem_batch_tune",
+                 "mem_batch_set_tuning", "mem_batch_get_tuning", "mem_batch_get_layer",
+                 "mem_batch_set_layer", "mem_batch_get_center", "mem_batch_get_stats",
+                 "mem_batch_reset_stats")
+
+
+def _load_batch():
+    L = load()
+    if getattr(L, "_batch_ready", False):
+        return L
+    P, I32 = C.c_void_p, C.c_int32
+    sig = {
+        "mem_batch_create": [C.POINTER(mem_batch_params), P, C.POINTER(P)],
+        "mem_batch_destroy": [P, P],
+        "mem_batch_step": [P, C.POINTER(mem_batch_input), P],
+        "mem_batch_tune": [P, C.POINTER(mem_batch_input), P],
+        "mem_batch_set_tuning": [P, C.POINTER(mem_batch_tuning)],
+        "mem_batch_get_tuning": [P, C.POINTER(mem_batch_tuning)],
+        "mem_batch_get_layer": [P, I32, I32, I32, P, P],
+        "mem_batch_set_layer": [P, I32, I32, I32, P, P],
+        "mem_batch_get_center": [P, I32, C.POINTER(I32), C.POINTER(I32)],
+        "mem_batch_get_stats": [P, C.POINTER(mem_stats), P],
+        "mem_batch_reset_stats": [P, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = C.c_int32
+    L._batch_ready = True
+    return L
+
+
+def _host_f32(a, n):
+    import numpy as np
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float32).reshape(-1))
+    if a.size != n:
+        raise ValueError(f"expected {n} floats, got {a.size}")
+    return a
+
+
+class Batch:
+    """Independent maps of different sizes updated together (mem_batch_*)."""
+
+    def __init__(self, widths, heights, resolution, layers=(), max_points=0, cam=None, img_bind=(),
+                 noise_c0=0.01, noise_c1=0.001, max_range=100.0, clear_margin=0.05, clear_min_count=1,
+                 min_depth=0.1, stream=None):
+        L = _load_batch()
+        self.n = len(widths)
+        self.W = [int(w) for w in widths]
+        self.H = [int(h) for h in heights]
+        self.layers = [l if isinstance(l, Layer) else Layer(*l) for l in layers]
+        self._w = (C.c_int32 * self.n)(*self.W)
+        self._h = (C.c_int32 * self.n)(*self.H)
+        descs = (mem_layer_desc * max(1, len(self.layers)))()
+        for i, l in enumerate(self.layers):
+            descs[i] = mem_layer_desc(l.channels, l.rule, l.storage, l.param, None)
+        ib, nib = _bindings(img_bind)
+        ch, cw, cc, cd = cam if cam is not None else (0, 0, 0, MEM_F32)
+        self.cam = cam
+        p = mem_batch_params(self.n, self._w, self._h, resolution, noise_c0, noise_c1, max_range, clear_margin,
+                             clear_min_count, min_depth, len(self.layers), descs, int(max_points), ch, cw, cc, cd,
+                             nib, ib)
+        self._keep = (descs, ib)
+        h = C.c_void_p()
+        _check(L.mem_batch_create(C.byref(p), _stream(stream), C.byref(h)))
+        self._b = h
+
+    def close(self, stream=None):
+        if getattr(self, "_b", None):
+            _load_batch().mem_batch_destroy(self._b, _stream(stream))
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _input(self, robot_xy, xyz, offsets, T, images=None, K=None, T_cam=None):
+        import numpy as np
+        n = self.n
+        self._in_keep = [
+            _host_f32(robot_xy, 2 * n),
+            np.ascontiguousarray(np.asarray(offsets, dtype=np.int64).reshape(-1)),
+            _host_f32(T, 12 * n),
+        ]
+        if self._in_keep[1].size != n + 1:
+            raise ValueError("offsets must have n_maps + 1 entries")
+        if xyz.dtype != torch.float32 or not xyz.is_contiguous() or xyz.dim() != 2 or xyz.shape[1] != 3:
+            raise ValueError("xyz must be a contiguous float32 [n, 3] device tensor")
+        img_p = None
+        if images is not None:
+            if not images.is_contiguous():
+                raise ValueError("images must be contiguous [n_maps, h, w, c]")
+            img_p = _dev_ptr(images, "images").value
+            self._in_keep += [_host_f32(K, 4 * n), _host_f32(T_cam, 12 * n)]
+        k = self._in_keep
+        ptr = lambda a: a.ctypes.data_as(C.c_void_p).value
+        return mem_batch_input(ptr(k[0]), _dev_ptr(xyz, "xyz").value if xyz.numel() else None, ptr(k[1]),
+                               ptr(k[2]), img_p, ptr(k[3]) if images is not None else None,
+                               ptr(k[4]) if images is not None else None)
+
+    def step(self, robot_xy, xyz, offsets, T, images=None, K=None, T_cam=None, stream=None):
+        inp = self._input(robot_xy, xyz, offsets, T, images, K, T_cam)
+        _check(_load_batch().mem_batch_step(self._b, C.byref(inp), _stream(stream)))
+
+    def tune(self, robot_xy, xyz, offsets, T, images=None, K=None, T_cam=None, stream=None):
+        inp = self._input(robot_xy, xyz, offsets, T, images, K, T_cam)
+        _check(_load_batch().mem_batch_tune(self._b, C.byref(inp), _stream(stream)))
+        return self.tuning()
+
+    def tuning(self) -> dict:
+        t = mem_batch_tuning()
+        _check(_load_batch().mem_batch_get_tuning(self._b, C.byref(t)))
+        return {f: getattr(t, f) for f, _ in mem_batch_tuning._fields_}
+
+    def set_tuning(self, chunk, wg_per_cu, tile, graph=1):
+        t = mem_batch_tuning(chunk, wg_per_cu, tile, graph, 0.0)
+        _check(_load_batch().mem_batch_set_tuning(self._b, C.byref(t)))
+
+    def channels(self, layer, view=MEM_VIEW_VALUE):
+        if layer < MEM_LAYER_USER0 or layer - MEM_LAYER_USER0 >= len(self.layers):
+            return 1
+        l = self.layers[layer - MEM_LAYER_USER0]
+        if view == MEM_VIEW_ARGMAX or (view == MEM_VIEW_AUX and l.rule == MEM_GAUSS):
+            return 1
+        return l.channels
+
+    def get_layer(self, m, layer, view=MEM_VIEW_VALUE, stream=None):
+        Cn = self.channels(layer, view)
+        out = torch.empty((self.H[m], self.W[m], Cn), dtype=torch.float32, device="cuda")
+        _check(_load_batch().mem_batch_get_layer(self._b, m, layer, view, _dev_ptr(out, "out"), _stream(stream)))
+        return out if layer >= MEM_LAYER_USER0 else out.reshape(self.H[m], self.W[m])
+
+    def set_layer(self, m, layer, view, values, stream=None):
+        v = values.to(device="cuda", dtype=torch.float32).contiguous()
+        _check(_load_batch().mem_batch_set_layer(self._b, m, layer, view, _dev_ptr(v, "values"), _stream(stream)))
+        (stream or torch.cuda.current_stream()).synchronize()
+
+    def center(self, m):
+        cx, cy = C.c_int32(), C.c_int32()
+        _check(_load_batch().mem_batch_get_center(self._b, m, C.byref(cx), C.byref(cy)))
+        return cx.value, cy.value
+
+    def stats(self, stream=None) -> dict:
+        s = mem_stats()
+        _check(_load_batch().mem_batch_get_stats(self._b, C.byref(s), _stream(stream)))
+        return {f: getattr(s, f) for f in STAT_FIELDS}
+
+    def reset_stats(self, stream=None):
+        _check(_load_batch().mem_batch_reset_stats(self._b, _stream(stream)))
+
+
+UNET_SYMBOLS = ("mem_unet_num_params", "mem_unet_create", "mem_unet_destroy", "mem_unet_set_params",
+                "mem_unet_get_params", "mem_unet_save", "mem_unet_load", "mem_unet_forward",
+                "mem_unet_loss_grad", "mem_unet_train_step", "mem_complete")
+
+
+def _load_unet():
+    L = load()
+    if getattr(L, "_unet_ready", False):
+        return L
+    P, I32, F = C.c_void_p, C.c_int32, C.c_float
+    sig = {
+        "mem_unet_create": [I32, I32, I32, C.c_uint64, P, C.POINTER(P)],
+        "mem_unet_destroy": [P, P],
+        "mem_unet_set_params": [P, P, P],
+        "mem_unet_get_params": [P, P, P],
+        "mem_unet_save": [P, C.c_char_p, P],
+        "mem_unet_load": [P, C.c_char_p, P],
+        "mem_unet_forward": [P, P, I32, P, P],
+        "mem_unet_loss_grad": [P, P, P, P, I32, F, P, P, P],
+        "mem_unet_train_step": [P, P, P, P, I32, F, F, P, P],
+        "mem_complete": [P, P, F, F, P, P, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = C.c_int32
+    L.mem_unet_num_params.argtypes = [I32]
+    L.mem_unet_num_params.restype = C.c_int64
+    L._unet_ready = True
+    return L
+
+
+def unet_num_params(base: int) -> int:
+    return int(_load_unet().mem_unet_num_params(int(base)))
+
+
+class UNet:
+    """The completion network (mem_unet_*): NHWC FP32 device tensors in and out."""
+
+    def __init__(self, base=32, max_batch=1, size=256, seed=0, stream=None):
+        L = _load_unet()
+        self.base, self.max_batch, self.size = int(base), int(max_batch), int(size)
+        self.n_params = unet_num_params(base)
+        h = C.c_void_p()
+        _check(L.mem_unet_create(self.base, self.max_batch, self.size, int(seed), _stream(stream), C.byref(h)))
+        self._u = h
+
+    def close(self, stream=None):
+        if getattr(self, "_u", None):
+            _load_unet().mem_unet_destroy(self._u, _stream(stream))
+            self._u = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _x(self, x, ch, what):
+        if (x.dtype != torch.float32 or not x.is_contiguous() or x.dim() != 4 or x.shape[1] != self.size
+                or x.shape[2] != self.size or x.shape[3] != ch):
+            raise ValueError(f"{what} must be a contiguous float32 [B, {self.size}, {self.size}, {ch}] tensor")
+        return _dev_ptr(x, what)
+
+    def _tm(self, t, B, what):
+        if t.dtype != torch.float32 or not t.is_contiguous() or tuple(t.shape) != (B, self.size, self.size):
+            raise ValueError(f"{what} must be a contiguous float32 [B, size, size] tensor")
+        return _dev_ptr(t, what)
+
+    def params(self, stream=None) -> torch.Tensor:
+        out = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        _check(_load_unet().mem_unet_get_params(self._u, _dev_ptr(out, "params"), _stream(stream)))
+        return out
+
+    def set_params(self, p, stream=None):
+        p = p.to(device="cuda", dtype=torch.float32).contiguous().reshape(-1)
+        if p.numel() != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters")
+        _check(_load_unet().mem_unet_set_params(self._u, _dev_ptr(p, "params"), _stream(stream)))
+        (stream or torch.cuda.current_stream()).synchronize()
+
+    def save(self, path, stream=None):
+        _check(_load_unet().mem_unet_save(self._u, os.fsencode(path), _stream(stream)))
+
+    def load(self, path, stream=None):
+        _check(_load_unet().mem_unet_load(self._u, os.fsencode(path), _stream(stream)))
+
+    def forward(self, x, stream=None) -> torch.Tensor:
+        B = x.shape[0]
+        out = torch.empty((B, self.size, self.size, 2), dtype=torch.float32, device="cuda")
+        _check(_load_unet().mem_unet_forward(self._u, self._x(x, 3, "x"), B, _dev_ptr(out, "out"),
+                                             _stream(stream)))
+        return out
+
+    @staticmethod
+    def _inv_count(mask):
+        return 1.0 / max(int((mask > 0).sum().item()), 1)
+
+    def loss_grad(self, x, target, mask, stream=None):
+        B = x.shape[0]
+        grad = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        _check(_load_unet().mem_unet_loss_grad(self._u, self._x(x, 3, "x"), self._tm(target, B, "target"),
+                                               self._tm(mask, B, "mask"), B, self._inv_count(mask),
+                                               _dev_ptr(grad, "grad"), _dev_ptr(loss, "loss"), _stream(stream)))
+        return loss, grad
+
+    def train_step(self, x, target, mask, lr, loss_out=None, stream=None):
+        B = x.shape[0]
+        lp = _dev_ptr(loss_out, "loss") if loss_out is not None else None
+        _check(_load_unet().mem_unet_train_step(self._u, self._x(x, 3, "x"), self._tm(target, B, "target"),
+                                                self._tm(mask, B, "mask"), B, self._inv_count(mask), float(lr),
+                                                lp, _stream(stream)))
+
+    def complete(self, m: "Map", z_ref, sigma_max, stream=None):
+        """(height, sigma) [H, W] of the map completed by the network (mem_complete)."""
+        out_h = torch.empty((m.H, m.W), dtype=torch.float32, device="cuda")
+        out_s = torch.empty((m.H, m.W), dtype=torch.float32, device="cuda")
+        _check(_load_unet().mem_complete(m._h, self._u, float(z_ref), float(sigma_max), _dev_ptr(out_h, "out_h"),
+                                         _dev_ptr(out_s, "out_sigma"), _stream(stream)))
+        return out_h, out_s

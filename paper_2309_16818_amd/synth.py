@@ -422,3 +422,108 @@ def iter_full_frames(seed: int = 1, n_frames: int = 2, device=None, lidar=(128, 
                              classes=class_image(rng_f, rh, rw, n_cls),
                              K_feat=Kf, features=feature_image(rng_f, feat_hw[0], feat_hw[1], n_feat)))
         yield ter, dict(pose=(x, y, yaw), clouds=clouds, cameras=cams)
+
+
+# --------------------------------------------------------------------------
+# Batched workload: many robots, each with its own terrain and map
+# --------------------------------------------------------------------------
+
+BATCH_RES = 0.05
+BATCH_CAM = dict(h=96, w=128, fx=80.0, fy=80.0, cx=63.5, cy=47.5, c=16)
+
+
+class BatchWorld:
+    """n robots on n seeded terrains (8 sinusoids with amplitudes summing to
+    0.3 m, wavelengths 1-8 m, plus 5 boxes each), map sides uniform in
+    [side_lo, side_hi] cells at 0.05 m, point counts per step uniform in
+    [pts_lo, pts_hi], sampled in a disc of radius min(4 m, half the map)
+    around the sensor (0.6 m up) on the terrain, with z-noise
+    0.01 + 0.001 r^2; one 128x96 camera per robot (fx 80, pitched 30 deg
+    down, 0.7 m up) with 16 unit-norm Gaussian feature channels.  Points are
+    not tested for occlusion (every sample is taken as seen).  Generation
+    runs on a torch device."""
+
+    def __init__(self, n=1024, seed=3, side_lo=64, side_hi=256, pts_lo=4000, pts_hi=60000, device="cuda"):
+        self.n, self.device = n, device
+        ss = np.random.SeedSequence(seed)
+        self.rng = np.random.Generator(np.random.PCG64(ss.spawn(1)[0]))
+        r = self.rng
+        self.side = r.integers(side_lo, side_hi + 1, n)
+        self.pts_lo, self.pts_hi = pts_lo, pts_hi
+        a = r.uniform(0, 1, (n, 8))
+        a = 0.3 * a / a.sum(1, keepdims=True)
+        lam = r.uniform(1, 8, (n, 8))
+        phi = r.uniform(0, 2 * np.pi, (n, 8))
+        t = lambda v: torch.as_tensor(v, dtype=torch.float32, device=device)
+        self.amp, self.psi = t(a), t(r.uniform(0, 2 * np.pi, (n, 8)))
+        self.kx, self.ky = t(2 * np.pi * np.cos(phi) / lam), t(2 * np.pi * np.sin(phi) / lam)
+        ext = self.side * BATCH_RES
+        bc = r.uniform(-0.5, 0.5, (n, 5, 2)) * ext[:, None, None]
+        bh = r.uniform(0.1, 0.5, (n, 5, 2))
+        self.box = t(np.concatenate([bc, bh, r.uniform(0.05, 0.5, (n, 5, 1))], -1))  # cx cy hx hy h
+        self.pose = np.zeros((n, 3))
+        self.pose[:, 2] = r.uniform(0, 2 * np.pi, n)
+
+    def height(self, mid, x, y):
+        h = torch.zeros_like(x)
+        for k in range(8):
+            h = h + self.amp[mid, k] * torch.sin(x * self.kx[mid, k] + y * self.ky[mid, k] + self.psi[mid, k])
+        for b in range(5):
+            B = self.box[mid, b]
+            inside = ((x - B[:, 0]).abs() <= B[:, 2]) & ((y - B[:, 1]).abs() <= B[:, 3])
+            h = h + inside.float() * B[:, 4]
+        return h
+
+    def step(self, k):
+        """Advances every robot and returns one step's inputs (device xyz,
+        host offsets / poses / cameras)."""
+        r = self.rng
+        n = self.n
+        if k > 0:
+            d = 0.1 * np.sqrt(r.uniform(size=n))
+            a = r.uniform(0, 2 * np.pi, n)
+            self.pose[:, 0] += d * np.cos(a)
+            self.pose[:, 1] += d * np.sin(a)
+            self.pose[:, 2] += np.radians(r.uniform(-5, 5, n))
+        cnt = r.integers(self.pts_lo, self.pts_hi + 1, n)
+        offs = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int64)
+        dev = self.device
+        mid = torch.repeat_interleave(torch.arange(n, device=dev), torch.as_tensor(cnt, device=dev))
+        radius = torch.as_tensor(np.minimum(4.0, 0.5 * self.side * BATCH_RES), dtype=torch.float32, device=dev)
+        g = torch.Generator(device=dev)
+        g.manual_seed(int(r.integers(0, 2**62)))
+        u = torch.rand(int(offs[-1]), 4, device=dev, generator=g)
+        px0 = torch.as_tensor(self.pose[:, 0], dtype=torch.float32, device=dev)[mid]
+        py0 = torch.as_tensor(self.pose[:, 1], dtype=torch.float32, device=dev)[mid]
+        rr = radius[mid] * u[:, 0].sqrt()
+        ang = u[:, 1] * (2 * np.pi)
+        x = px0 + rr * torch.cos(ang)
+        y = py0 + rr * torch.sin(ang)
+        ground0 = self.height(torch.arange(n, device=dev), torch.as_tensor(self.pose[:, 0], dtype=torch.float32, device=dev),
+                              torch.as_tensor(self.pose[:, 1], dtype=torch.float32, device=dev))
+        sz = ground0 + 0.6
+        z = self.height(mid, x, y)
+        rng3 = torch.sqrt((x - px0) ** 2 + (y - py0) ** 2 + (z - sz[mid]) ** 2)
+        z = z + torch.randn(z.shape, device=dev, generator=g) * (0.01 + 0.001 * rng3 ** 2)
+        yaw = torch.as_tensor(self.pose[:, 2], dtype=torch.float32, device=dev)[mid]
+        dx, dy, dz = x - px0, y - py0, z - sz[mid]
+        c, s = torch.cos(yaw), torch.sin(yaw)
+        xyz = torch.stack([c * dx + s * dy, -s * dx + c * dy, dz], 1).contiguous()
+        g0 = ground0.cpu().numpy()
+        T = np.zeros((n, 3, 4), np.float32)
+        Tc = np.zeros((n, 3, 4), np.float32)
+        for m in range(n):
+            T[m] = pose_matrix(rot_z(self.pose[m, 2]), (self.pose[m, 0], self.pose[m, 1], g0[m] + 0.6))
+            Tc[m] = pose_matrix(camera_rotation(self.pose[m, 2], math.radians(30)),
+                                (self.pose[m, 0], self.pose[m, 1], g0[m] + 0.7))
+        cam = BATCH_CAM
+        K = np.tile(np.array([cam["fx"], cam["fy"], cam["cx"], cam["cy"]], np.float32), (n, 1))
+        return dict(xyz=xyz, offsets=offs, T=T, T_cam=Tc, K=K,
+                    robot_xy=self.pose[:, :2].astype(np.float32).copy())
+
+    def images(self, seed):
+        cam = BATCH_CAM
+        g = torch.Generator(device=self.device)
+        g.manual_seed(seed)
+        f = torch.randn(self.n, cam["h"], cam["w"], cam["c"], device=self.device, generator=g)
+        return (f / f.norm(dim=-1, keepdim=True)).contiguous()

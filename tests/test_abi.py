@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def declared_symbols():
     text = open(os.path.join(ROOT, "include", "mem.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:mem_status|const char\*)\s+(mem_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:mem_status|const char\*|int64_t)\s+(mem_\w+)\s*\(", text, re.M)))
 
 
 def test_header_declares_the_boundary():
@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     lib = mem.load()
     for s in declared_symbols():
         assert hasattr(lib, s), s
-    assert sorted(mem.SYMBOLS) == declared_symbols()
+    assert sorted(mem.SYMBOLS + mem.BATCH_SYMBOLS + mem.UNET_SYMBOLS) == declared_symbols()
 
 
 def test_struct_layouts_match_the_header():
@@ -40,6 +40,8 @@ def test_struct_layouts_match_the_header():
     assert C.sizeof(mem.mem_stats) == 8 * len(mem.STAT_FIELDS)
     assert C.sizeof(mem.mem_kernel_time) == 48
     assert C.sizeof(mem.mem_image) == 80
+    assert C.sizeof(mem.mem_batch_params) == 104 and mem.mem_batch_params.max_points.offset == 64
+    assert C.sizeof(mem.mem_batch_input) == 56 and C.sizeof(mem.mem_batch_tuning) == 24
     assert mem.mem_image.strides.offset == 24 and mem.mem_image.bind.offset == 64
 
 
@@ -89,6 +91,25 @@ def test_null_handles_are_rejected():
     assert lib.mem_input_pointcloud(None, None, 0, None, 0, None, 0, T, None) == mem.MEM_E_ARG
     assert lib.mem_get_layer(None, 0, 0, None, None) == mem.MEM_E_ARG
     assert lib.mem_destroy(None, None) == mem.MEM_OK
+
+
+def test_unet_host_checks():
+    """Parameter count agrees with the oracle's layout; bad sizes and NULL
+    handles are rejected before any device work."""
+    import oracle as O
+    from paper_2309_16818_amd import mem
+    lib = mem._load_unet()
+    for base in (1, 2, 4, 32):
+        assert lib.mem_unet_num_params(base) == O.unet_num_params(base)
+    assert lib.mem_unet_num_params(0) == -1
+    h = C.c_void_p()
+    for args in ((0, 1, 16), (32, 0, 256), (32, 1, 12), (32, 1, 4), (32, 1, 8192), (257, 1, 16)):
+        assert lib.mem_unet_create(*args, 0, None, C.byref(h)) == mem.MEM_E_ARG, args
+        assert not h.value
+    assert lib.mem_unet_forward(None, None, 1, None, None) == mem.MEM_E_ARG
+    assert lib.mem_unet_train_step(None, None, None, None, 1, 1.0, 1e-3, None, None) == mem.MEM_E_ARG
+    assert lib.mem_complete(None, None, 0.0, 0.05, None, None, None) == mem.MEM_E_ARG
+    assert lib.mem_unet_destroy(None, None) == mem.MEM_OK
 
 
 def test_oracle_and_gpu_path_share_no_source():

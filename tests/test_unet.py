@@ -1,0 +1,252 @@
+"""GPU parity of the completion U-Net (mem_unet_*) against the binary64 oracle.
+
+Both sides get the same BF16-representable weights and inputs, so the only
+differences are the BF16 storage of activations and gradients on the GPU and
+its FP32 accumulation.  Bars: forward within 1e-2 norm-wise relative, loss
+within 1e-2 relative, parameter gradient with cosine >= 0.999 and norm-wise
+relative error <= 2e-2 (one BF16 rounding, 2^-9 relative, per stored tensor,
+accumulated over the deepest path of about 20 stored tensors)."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+def bf16(a):
+    return torch.tensor(np.asarray(a), dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def spec(base):
+    c = [base, 2 * base, 4 * base, 8 * base]
+    L, prev = [], 3
+    for l in range(4):
+        L += [(9, prev, c[l]), (9, c[l], c[l])]
+        prev = c[l]
+    for l in (2, 1, 0):
+        L += [(4, c[l + 1], c[l]), (9, 2 * c[l], c[l]), (9, c[l], c[l])]
+    L.append((1, base, 2))
+    return L
+
+
+def sample(base, B, S, seed):
+    """He-scaled weights, small random biases, standard-normal inputs, a 70 %
+    mask (all BF16-representable)."""
+    rng = np.random.default_rng(seed)
+    n = O.unet_num_params(base)
+    p = np.zeros(n)
+    offs = list(O.unet_layer_offsets(base)) + [n]
+    for i, (taps, ci, co) in enumerate(spec(base)):
+        nw = taps * ci * co
+        p[offs[i]:offs[i] + nw] = rng.normal(0, np.sqrt(2.0 / (taps * ci)), nw)
+        p[offs[i] + nw:offs[i + 1]] = rng.normal(0, 0.05, co)
+    x = rng.normal(0, 1, (B, S, S, 3))
+    x[..., 2] = rng.uniform(size=(B, S, S)) < 0.5
+    t = rng.normal(0, 1, (B, S, S))
+    m = (rng.uniform(size=(B, S, S)) < 0.7).astype(np.float64)
+    return bf16(p), bf16(x), bf16(t), m
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def make(base, B, S, p):
+    from paper_2309_16818_amd import mem
+    net = mem.UNet(base=base, max_batch=B, size=S, seed=1)
+    net.set_params(dev(p))
+    return net
+
+
+# (base, batch, size): several MFMA tiles per product, ragged channel counts
+# (base 2 and 6 give K and N that are not multiples of the tile), and the
+# full width at a reduced window.
+CASES = [(2, 2, 16), (4, 2, 32), (6, 1, 24), (32, 1, 32), (32, 2, 64)]
+
+
+@pytest.mark.parametrize("base,B,S", CASES)
+def test_forward_matches_oracle(base, B, S):
+    p, x, _, _ = sample(base, B, S, 11 * base + S)
+    net = make(base, B, S, p)
+    out = net.forward(dev(x)).cpu().double().numpy()
+    ref = O.unet_forward(p, x, base)
+    assert np.isfinite(out).all()
+    e = relerr(out, ref)
+    print(f"base {base} B {B} S {S}: forward rel err {e:.2e}")
+    assert e <= 1e-2
+    net.close()
+
+
+@pytest.mark.parametrize("base,B,S", CASES)
+def test_loss_and_gradient_match_oracle(base, B, S):
+    p, x, t, m = sample(base, B, S, 13 * base + S)
+    net = make(base, B, S, p)
+    loss, g = net.loss_grad(dev(x), dev(t), dev(m))
+    g = g.cpu().double().numpy()
+    loss = float(loss.item())
+    rl, rg = O.unet_loss_grad(p, x, t, m, base)
+    cos = float(g @ rg / (np.linalg.norm(g) * np.linalg.norm(rg)))
+    e = relerr(g, rg)
+    print(f"base {base} B {B} S {S}: loss {loss:.6f} vs {rl:.6f}, grad cos {cos:.6f} rel {e:.2e}")
+    assert abs(loss - rl) <= 1e-2 * max(abs(rl), 1e-3)
+    assert cos >= 0.999 and e <= 2e-2
+    # per layer: no layer's gradient is lost in the sum
+    offs = list(O.unet_layer_offsets(base)) + [len(p)]
+    for i in range(18):
+        a, b = g[offs[i]:offs[i + 1]], rg[offs[i]:offs[i + 1]]
+        if np.linalg.norm(b) > 1e-6 * np.linalg.norm(rg):
+            assert relerr(a, b) <= 5e-2, (i, relerr(a, b))
+    net.close()
+
+
+def test_empty_mask_gives_zero_loss_and_gradient():
+    base, B, S = 4, 1, 16
+    p, x, t, m = sample(base, B, S, 3)
+    net = make(base, B, S, p)
+    from paper_2309_16818_amd import mem
+    loss = torch.zeros(1, device="cuda")
+    grad = torch.zeros(net.n_params, device="cuda")
+    lib = mem._load_unet()
+    import ctypes as C
+    z = dev(np.zeros((B, S, S)))
+    mem._check(lib.mem_unet_loss_grad(net._u, C.c_void_p(dev(x).data_ptr()), C.c_void_p(dev(t).data_ptr()),
+                                      C.c_void_p(z.data_ptr()), B, 1.0, C.c_void_p(grad.data_ptr()),
+                                      C.c_void_p(loss.data_ptr()), mem._stream()))
+    torch.cuda.synchronize()
+    assert loss.item() == 0.0 and not grad.any()
+    net.close()
+
+
+def test_adam_step_follows_its_definition():
+    """One train step from fresh moments: w - lr * m_hat / (sqrt(v_hat) + eps)
+    with m_hat = g, v_hat = g^2 on the network's own gradient."""
+    base, B, S = 4, 2, 32
+    p, x, t, m = sample(base, B, S, 5)
+    net = make(base, B, S, p)
+    _, g = net.loss_grad(dev(x), dev(t), dev(m))
+    g = g.cpu().double().numpy()
+    lr = 1e-3
+    net.train_step(dev(x), dev(t), dev(m), lr)
+    w1 = net.params().cpu().double().numpy()
+    # The step recomputes the gradient; its atomic sums may differ in the last
+    # bits, which can flip the sign of a gradient that cancels to ~0, so the
+    # exact step is checked where |g| is well above that noise.
+    step = w1 - p
+    big = np.abs(g) > 1e-3 * np.sqrt(np.mean(g * g))
+    assert big.mean() > 0.5
+    want = -lr * g / (np.abs(g) + 1e-8)
+    assert np.allclose(step[big], want[big], rtol=1e-4, atol=1e-9)
+    assert (np.abs(step) <= lr * (1 + 1e-4)).all()
+    net.close()
+
+
+def test_training_reduces_the_loss():
+    base, B, S = 8, 2, 32
+    p, x, t, m = sample(base, B, S, 9)
+    t = bf16(np.tanh(x[..., 0]) * 0.5)  # a learnable target
+    net = make(base, B, S, p)
+    X, T, M = dev(x), dev(t), dev(m)
+    l0 = net.loss_grad(X, T, M)[0].item()
+    for _ in range(60):
+        net.train_step(X, T, M, 2e-3)
+    l1 = net.loss_grad(X, T, M)[0].item()
+    print(f"loss {l0:.4f} -> {l1:.4f}")
+    assert l1 < l0 - 0.5
+    net.close()
+
+
+def test_params_roundtrip_and_file(tmp_path):
+    base, B, S = 4, 1, 16
+    from paper_2309_16818_amd import mem
+    net = mem.UNet(base=base, max_batch=B, size=S, seed=7)
+    p0 = net.params().cpu()
+    assert p0.numel() == O.unet_num_params(base)
+    # He-normal weights, zero biases
+    offs = list(O.unet_layer_offsets(base)) + [p0.numel()]
+    for i, (taps, ci, co) in enumerate(spec(base)):
+        w = p0[offs[i]:offs[i] + taps * ci * co]
+        assert not p0[offs[i] + taps * ci * co:offs[i + 1]].any()
+        if w.numel() > 500:
+            assert abs(float(w.std()) / np.sqrt(2.0 / (taps * ci)) - 1) < 0.15
+    net2 = mem.UNet(base=base, max_batch=B, size=S, seed=7)
+    assert torch.equal(net2.params().cpu(), p0)  # deterministic initialisation
+    path = os.path.join(tmp_path, "w.bin")
+    net.save(path)
+    net3 = mem.UNet(base=base, max_batch=B, size=S, seed=8)
+    assert not torch.equal(net3.params().cpu(), p0)
+    net3.load(path)
+    assert torch.equal(net3.params().cpu(), p0)
+    x = dev(np.random.default_rng(0).normal(size=(B, S, S, 3)))
+    assert torch.equal(net.forward(x), net3.forward(x))
+    wrong = mem.UNet(base=2, max_batch=1, size=S, seed=0)
+    with pytest.raises(mem.MemError):
+        wrong.load(path)
+    for n in (net, net2, net3, wrong):
+        n.close()
+
+
+def test_bad_batch_and_shapes_are_rejected():
+    from paper_2309_16818_amd import mem
+    net = mem.UNet(base=2, max_batch=1, size=16, seed=0)
+    with pytest.raises(mem.MemError):
+        net.forward(dev(np.zeros((2, 16, 16, 3))))
+    with pytest.raises(ValueError):
+        net.forward(dev(np.zeros((1, 8, 8, 3))))
+    net.close()
+
+
+def test_complete_gates_the_network_output():
+    """mem_complete on a moved map (toroidal offset): observed cells keep the
+    classical height and sqrt(variance); unobserved cells take the network's
+    height where its predicted sigma is below the bound, else NaN.  The
+    network's part is checked against mem_unet_forward on the input built
+    here from the map's layers."""
+    from paper_2309_16818_amd import mem
+    S, res = 32, 0.1
+    m = mem.Map(mem.MapParams(S, S, res))
+    m.move(0.73, -0.41)  # shifts the ring offsets
+    rng = np.random.default_rng(4)
+    n = 400
+    xy = rng.uniform(-1.2, 1.2, (n, 2))
+    z = 0.3 * np.sin(xy[:, 0] * 2) + 0.1
+    pts = dev(np.column_stack([xy + [0.73, -0.41], z]))
+    m.input_pointcloud(pts, np.hstack([np.eye(3), np.zeros((3, 1))]))
+    h = m.get_layer(mem.MEM_LAYER_ELEVATION).cpu().double().numpy()
+    v = m.get_layer(mem.MEM_LAYER_VARIANCE).cpu().double().numpy()
+    obs = np.isfinite(h)
+    assert 0 < obs.sum() < S * S
+    net = mem.UNet(base=4, max_batch=1, size=S, seed=3)
+    z_ref = 0.1
+    x = np.zeros((1, S, S, 3))
+    x[0, ..., 0] = np.where(obs, h - z_ref, 0)
+    x[0, ..., 1] = np.where(obs, np.log(np.where(obs, v, 1)), 0)
+    x[0, ..., 2] = obs
+    out = net.forward(dev(x))[0].cpu().double().numpy()
+    sig = np.exp(0.5 * out[..., 1])
+    smax = float(np.median(sig[~obs]))  # about half of the unobserved cells pass
+    ch, cs = net.complete(m, z_ref, smax)
+    ch, cs = ch.cpu().double().numpy(), cs.cpu().double().numpy()
+    assert np.array_equal(ch[obs], h[obs])
+    assert np.allclose(cs[obs], np.sqrt(v[obs]), rtol=1e-6)
+    clear = ~obs & (np.abs(sig - smax) > 1e-3 * smax)
+    take = clear & (sig < smax)
+    drop = clear & (sig >= smax)
+    assert take.sum() > 0 and drop.sum() > 0
+    assert np.allclose(ch[take], out[..., 0][take] + z_ref, rtol=1e-4, atol=1e-4)
+    assert np.allclose(cs[take], sig[take], rtol=1e-4)
+    assert np.isnan(ch[drop]).all() and np.isnan(cs[drop]).all()
+    # the classical layers are untouched
+    assert np.array_equal(m.get_layer(mem.MEM_LAYER_ELEVATION).cpu().double().numpy(), h, equal_nan=True)
+    big = mem.UNet(base=2, max_batch=1, size=64, seed=0)
+    with pytest.raises(mem.MemError):
+        big.complete(m, 0.0, 0.05)
+    for o in (net, big, m):
+        o.close()
