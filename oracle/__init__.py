@@ -193,9 +193,11 @@ def _unet_sigs(L):
     L.orc_unet_num_params.restype = C.c_int64
     L.orc_unet_num_params.argtypes = [I, I, I]
     L.orc_unet_layer_offsets.argtypes = [I, I, I, P]
-    L.orc_unet_forward.argtypes = [I, I, I, P, P, I, I, P]
+    L.orc_unet_forward.argtypes = [I, I, I, P, P, I, I, P, I]
     L.orc_unet_loss_grad.restype = C.c_double
-    L.orc_unet_loss_grad.argtypes = [I, I, P, P, P, P, I, I, P]
+    L.orc_unet_loss_grad.argtypes = [I, I, P, P, P, P, I, I, P, I]
+    L.orc_round_bf16.restype = C.c_double
+    L.orc_round_bf16.argtypes = [C.c_double]
     L._unet_ready = True
 
 
@@ -213,19 +215,20 @@ def unet_layer_offsets(base, in_ch=3, out_ch=2):
     return off
 
 
-def unet_forward(params, x, base, out_ch=2):
-    """x: [B, S, S, Cin] binary64 NHWC; returns [B, S, S, out_ch]."""
+def unet_forward(params, x, base, out_ch=2, bf16=False):
+    """x: [B, S, S, Cin] NHWC; returns [B, S, S, out_ch].  bf16: the
+    network's BF16 storage format (see unet_oracle.c), else binary64."""
     L = lib()
     _unet_sigs(L)
     x = np.ascontiguousarray(x, np.float64)
     B, S, _, cin = x.shape
     p = np.ascontiguousarray(params, np.float64)
     out = np.zeros((B, S, S, out_ch))
-    L.orc_unet_forward(base, cin, out_ch, _ptr(p), _ptr(x), B, S, _ptr(out))
+    L.orc_unet_forward(base, cin, out_ch, _ptr(p), _ptr(x), B, S, _ptr(out), int(bool(bf16)))
     return out
 
 
-def unet_loss_grad(params, x, target, mask, base):
+def unet_loss_grad(params, x, target, mask, base, bf16=False):
     """Gaussian NLL (mean over mask > 0) and its gradient."""
     L = lib()
     _unet_sigs(L)
@@ -235,5 +238,13 @@ def unet_loss_grad(params, x, target, mask, base):
     t = np.ascontiguousarray(target, np.float64)
     m = np.ascontiguousarray(mask, np.float64)
     g = np.zeros_like(p)
-    loss = L.orc_unet_loss_grad(base, cin, _ptr(p), _ptr(x), _ptr(t), _ptr(m), B, S, _ptr(g))
+    loss = L.orc_unet_loss_grad(base, cin, _ptr(p), _ptr(x), _ptr(t), _ptr(m), B, S, _ptr(g), int(bool(bf16)))
     return loss, g
+
+
+def round_bf16(v):
+    """Nearest BF16 of each value (through binary32, ties to even)."""
+    L = lib()
+    _unet_sigs(L)
+    f = np.vectorize(L.orc_round_bf16, otypes=[np.float64])
+    return f(np.asarray(v, np.float64))

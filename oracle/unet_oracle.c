@@ -22,6 +22,18 @@
  * array; each layer stores its weights [taps][Cin][Cout] then its bias
  * [Cout], in the order enc0a enc0b enc1a enc1b enc2a enc2b enc3a enc3b
  * up2 dec2a dec2b up1 dec1a dec1b up0 dec0a dec0b head.
+ *
+ * Two number formats:
+ *   binary64  every value and sum in binary64;
+ *   bf16      the network's storage format: the convolution and transposed
+ *             convolution weights, the input, every stored activation
+ *             (each convolution output after its ReLU, each transposed
+ *             convolution output) and every gradient with respect to a
+ *             convolution or transposed convolution output (after the ReLU
+ *             mask) are rounded to BF16 (round to binary32, then to the
+ *             nearest BF16, ties to even); biases and the head are binary32
+ *             values; sums stay binary64.  ReLU masks and max-pool winners
+ *             are then decided on the stored BF16 values.
  */
 #include <math.h>
 #include <stdint.h>
@@ -71,6 +83,31 @@ void orc_unet_layer_offsets(int base, int in_ch, int out_ch, int64_t* off)
     layer_t L[NL];
     layout(base, in_ch, out_ch, L);
     for (int i = 0; i < NL; i++) off[i] = L[i].off;
+}
+
+/* Nearest BF16 (ties to even) of v rounded to binary32 first. */
+double orc_round_bf16(double v)
+{
+    float f = (float)v;
+    if (f != f) return v;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    u &= 0xffff0000u;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+static void round_all(double* a, int64_t n)
+{
+    for (int64_t i = 0; i < n; i++) a[i] = orc_round_bf16(a[i]);
+}
+
+/* channels [0, c) of each of n rows of stride rs */
+static void round_rows(double* a, int64_t n, int rs, int c)
+{
+    for (int64_t j = 0; j < n; j++)
+        for (int i = 0; i < c; i++) a[j * rs + i] = orc_round_bf16(a[j * rs + i]);
 }
 
 /* ---------------- building blocks ---------------- */
@@ -212,7 +249,7 @@ static void relu_bwd(const double* y, double* dy, int64_t n)
 /* ---------------- network ---------------- */
 
 typedef struct {
-    int B, S, base, in_ch, out_ch;
+    int B, S, base, in_ch, out_ch, bf16;
     layer_t L[NL];
     double *a[4], *e[4];      /* enc: first conv output, block output (e_l) */
     double *p[3];             /* pooled inputs of levels 1..3 */
@@ -223,8 +260,9 @@ typedef struct {
 
 static int64_t sz(const net_t* N, int l, int c) { return (int64_t)N->B * (N->S >> l) * (N->S >> l) * c; }
 
-static void net_alloc(net_t* N, int B, int S, int base, int in_ch, int out_ch)
+static void net_alloc(net_t* N, int B, int S, int base, int in_ch, int out_ch, int bf16)
 {
+    N->bf16 = bf16;
     N->B = B;
     N->S = S;
     N->base = base;
@@ -275,8 +313,10 @@ static void forward(net_t* N, const double* P, const double* x)
         int c = N->base << l, Sl = S >> l;
         conv3(in, ci, B, Sl, ci, W(P, 2 * l), BIAS(P, 2 * l), c, N->a[l]);
         relu(N->a[l], sz(N, l, c));
+        if (N->bf16) round_all(N->a[l], sz(N, l, c));
         conv3(N->a[l], c, B, Sl, c, W(P, 2 * l + 1), BIAS(P, 2 * l + 1), c, N->e[l]);
         relu(N->e[l], sz(N, l, c));
+        if (N->bf16) round_all(N->e[l], sz(N, l, c));
         if (l < 3) {
             maxpool2(N->e[l], c, B, Sl, c, N->p[l], N->arg[l]);
             in = N->p[l];
@@ -288,12 +328,15 @@ static void forward(net_t* N, const double* P, const double* x)
         int c = N->base << l, Sl = S >> l, k = 8 + 3 * (2 - l);
         /* concat: channels [0, c) = up-sampled, [c, 2c) = skip */
         convT2(below, B, Sl / 2, 2 * c, W(P, k), BIAS(P, k), c, N->cat[l], 2 * c);
+        if (N->bf16) round_rows(N->cat[l], (int64_t)B * Sl * Sl, 2 * c, c);
         for (int64_t j = 0; j < (int64_t)B * Sl * Sl; j++)
             memcpy(N->cat[l] + j * 2 * c + c, N->e[l] + j * c, sizeof(double) * c);
         conv3(N->cat[l], 2 * c, B, Sl, 2 * c, W(P, k + 1), BIAS(P, k + 1), c, N->m[l]);
         relu(N->m[l], sz(N, l, c));
+        if (N->bf16) round_all(N->m[l], sz(N, l, c));
         conv3(N->m[l], c, B, Sl, c, W(P, k + 2), BIAS(P, k + 2), c, N->d[l]);
         relu(N->d[l], sz(N, l, c));
+        if (N->bf16) round_all(N->d[l], sz(N, l, c));
         below = N->d[l];
     }
     /* head: 1x1 */
@@ -327,13 +370,16 @@ static void backward(net_t* N, const double* P, const double* x, const double* d
     for (int l = 0; l <= 2; l++) {
         int c = N->base << l, Sl = S >> l, k = 8 + 3 * (2 - l);
         relu_bwd(N->d[l], dd, sz(N, l, c));
+        if (N->bf16) round_all(dd, sz(N, l, c));
         double* dm = calloc(sz(N, l, c), sizeof(double));
         conv3_bwd(N->m[l], c, B, Sl, c, W(P, k + 2), c, dd, dm, c, W(G, k + 2), BIAS(G, k + 2));
         relu_bwd(N->m[l], dm, sz(N, l, c));
+        if (N->bf16) round_all(dm, sz(N, l, c));
         double* dcat = calloc(sz(N, l, 2 * c), sizeof(double));
         conv3_bwd(N->cat[l], 2 * c, B, Sl, 2 * c, W(P, k + 1), c, dm, dcat, 2 * c, W(G, k + 1), BIAS(G, k + 1));
         for (int64_t j = 0; j < (int64_t)B * Sl * Sl; j++)
             for (int i = 0; i < c; i++) de[l][j * c + i] += dcat[j * 2 * c + c + i];
+        if (N->bf16) round_rows(dcat, (int64_t)B * Sl * Sl, 2 * c, c);
         const double* below = (l == 2) ? N->e[3] : N->d[l + 1];
         double* dbelow = calloc(sz(N, l + 1, 2 * c), sizeof(double));
         convT2_bwd(below, B, Sl / 2, 2 * c, W(P, k), c, dcat, 2 * c, dbelow, W(G, k), BIAS(G, k));
@@ -354,9 +400,11 @@ static void backward(net_t* N, const double* P, const double* x, const double* d
         int ci = (l == 0) ? N->in_ch : (c / 2);
         const double* in = (l == 0) ? x : N->p[l - 1];
         relu_bwd(N->e[l], de[l], sz(N, l, c));
+        if (N->bf16) round_all(de[l], sz(N, l, c));
         double* da = calloc(sz(N, l, c), sizeof(double));
         conv3_bwd(N->a[l], c, B, Sl, c, W(P, 2 * l + 1), c, de[l], da, c, W(G, 2 * l + 1), BIAS(G, 2 * l + 1));
         relu_bwd(N->a[l], da, sz(N, l, c));
+        if (N->bf16) round_all(da, sz(N, l, c));
         double* din = (l == 0) ? NULL : calloc(sz(N, l, ci), sizeof(double));
         conv3_bwd(in, ci, B, Sl, ci, W(P, 2 * l), c, da, din, ci, W(G, 2 * l), BIAS(G, 2 * l));
         if (l > 0) maxpool2_bwd(din, N->arg[l - 1], B, S >> (l - 1), ci, de[l - 1], ci);
@@ -366,25 +414,61 @@ static void backward(net_t* N, const double* P, const double* x, const double* d
     for (int l = 0; l < 4; l++) free(de[l]);
 }
 
-/* Forward pass: out [B][S][S][out_ch]. */
+/* The parameters and input as the chosen number format stores them:
+ * returns the arrays to use (copies in bf16 format, to be freed with
+ * release()). */
+static const double* fmt_params(const net_t* N, const double* params, int fmt)
+{
+    if (!fmt) return params;
+    int64_t n = orc_unet_num_params(N->base, N->in_ch, N->out_ch);
+    double* q = malloc(sizeof(double) * n);
+    for (int64_t j = 0; j < n; j++) q[j] = (float)params[j];
+    for (int i = 0; i < NL - 1; i++)
+        round_all(q + N->L[i].off, (int64_t)N->L[i].taps * N->L[i].cin * N->L[i].cout);
+    return q;
+}
+
+static const double* fmt_input(const net_t* N, const double* x, int fmt)
+{
+    if (!fmt) return x;
+    int64_t n = sz(N, 0, N->in_ch);
+    double* q = malloc(sizeof(double) * n);
+    memcpy(q, x, sizeof(double) * n);
+    round_all(q, n);
+    return q;
+}
+
+static void release(const double* copy, const double* orig)
+{
+    if (copy != orig) free((void*)copy);
+}
+
+/* Forward pass: out [B][S][S][out_ch]; fmt 0 = binary64, 1 = bf16. */
 void orc_unet_forward(int base, int in_ch, int out_ch, const double* params, const double* x, int B, int S,
-                      double* out)
+                      double* out, int fmt)
 {
     net_t N;
-    net_alloc(&N, B, S, base, in_ch, out_ch);
-    forward(&N, params, x);
+    net_alloc(&N, B, S, base, in_ch, out_ch, fmt);
+    const double* P = fmt_params(&N, params, fmt);
+    const double* X = fmt_input(&N, x, fmt);
+    forward(&N, P, X);
     memcpy(out, N.out, sizeof(double) * sz(&N, 0, out_ch));
+    release(P, params);
+    release(X, x);
     net_free(&N);
 }
 
 /* Gaussian negative log-likelihood over cells with mask > 0 (mean) and its
  * gradient with respect to every parameter.  Returns the loss. */
 double orc_unet_loss_grad(int base, int in_ch, const double* params, const double* x, const double* target,
-                          const double* mask, int B, int S, double* grad)
+                          const double* mask, int B, int S, double* grad, int fmt)
 {
+    if (B < 1 || S < 1) return 0.0;
     net_t N;
-    net_alloc(&N, B, S, base, in_ch, 2);
-    forward(&N, params, x);
+    net_alloc(&N, B, S, base, in_ch, 2, fmt);
+    const double* Pm = fmt_params(&N, params, fmt);
+    const double* X = fmt_input(&N, x, fmt);
+    forward(&N, Pm, X);
     int64_t P = (int64_t)B * S * S;
     double cnt = 0;
     for (int64_t j = 0; j < P; j++) cnt += mask[j] > 0;
@@ -398,8 +482,10 @@ double orc_unet_loss_grad(int base, int in_ch, const double* params, const doubl
         dout[2 * j] = -r * e / denom;
         dout[2 * j + 1] = 0.5 * (1.0 - r * r * e) / denom;
     }
-    if (grad) backward(&N, params, x, dout, grad);
+    if (grad) backward(&N, Pm, X, dout, grad);
     free(dout);
+    release(Pm, params);
+    release(X, x);
     net_free(&N);
     return loss / denom;
 }

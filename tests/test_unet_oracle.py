@@ -131,3 +131,104 @@ def test_loss_special_cases():
     out = O.unet_forward(p, x, base)
     loss, _ = O.unet_loss_grad(p, x, out[..., 0], m, base)  # perfect mean: loss = mean(s / 2)
     assert abs(loss - 0.5 * out[..., 1][m > 0].mean()) < 1e-12
+
+
+def test_bf16_rounding_matches_torch():
+    """The oracle's BF16 rounding (through binary32, ties to even) against
+    torch's float32 -> bfloat16 conversion, including exact ties, values
+    just beside them, subnormals, overflow to infinity and signed zeros."""
+    rng = np.random.default_rng(0)
+    v = np.concatenate([rng.normal(0, 1, 2000) * 10.0 ** rng.integers(-40, 39, 2000),
+                        [0.0, -0.0, 1.0, -1.0, 3.4e38, -3.4e38, 1e-45, np.inf, -np.inf]])
+    f32 = v.astype(np.float32)
+    bits = f32[np.isfinite(f32)].view(np.uint32)
+    ties = ((bits & 0xFFFF0000) | 0x8000).view(np.float32)
+    ties = ties[np.isfinite(ties)].astype(np.float64)  # exactly half-way
+    v = np.concatenate([v, ties, np.nextafter(ties, np.inf), np.nextafter(ties, -np.inf)])
+    want = torch.tensor(v).float().to(torch.bfloat16).double().numpy()
+    got = O.round_bf16(v)
+    assert np.array_equal(got, want, equal_nan=True)
+    assert np.signbit(O.round_bf16(-0.0))
+
+
+class _Rf(torch.autograd.Function):  # forward-only BF16 rounding
+    @staticmethod
+    def forward(ctx, x):
+        return x.float().to(torch.bfloat16).double()
+
+    @staticmethod
+    def backward(ctx, g):
+        return g
+
+
+class _Rb(torch.autograd.Function):  # gradient-only BF16 rounding
+    @staticmethod
+    def forward(ctx, x):
+        return x.clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        return g.float().to(torch.bfloat16).double()
+
+
+def torch_unet_bf16(p, x, base):
+    """torch_unet with the BF16 storage format: BF16 input and convolution
+    weights, binary32 biases and head; every convolution / transposed
+    convolution output stored in BF16, and the gradient with respect to it
+    (after the ReLU mask) rounded to BF16."""
+    L = spec(base)
+    offs = O.unet_layer_offsets(base)
+    rf, rb = _Rf.apply, _Rb.apply
+
+    def wb(i):
+        taps, ci, co = L[i]
+        o = int(offs[i])
+        w = p[o:o + taps * ci * co].view(taps, ci, co)
+        b = p[o + taps * ci * co:o + taps * ci * co + co]
+        w = w.float().double() if i == 17 else rf(w)
+        return w, b.float().double()
+
+    def conv3(i, a):
+        w, b = wb(i)
+        ci, co = w.shape[1], w.shape[2]
+        return F.conv2d(a, w.view(3, 3, ci, co).permute(3, 2, 0, 1), b, padding=1)
+
+    def up(i, a):
+        w, b = wb(i)
+        ci, co = w.shape[1], w.shape[2]
+        return F.conv_transpose2d(a, w.view(2, 2, ci, co).permute(2, 3, 0, 1), b, stride=2)
+
+    block = lambda i, a: rf(F.relu(rb(conv3(i, a))))
+    a = rf(x.permute(0, 3, 1, 2))
+    enc = []
+    for l in range(4):
+        a = block(2 * l + 1, block(2 * l, a))
+        enc.append(a)
+        if l < 3:
+            a = F.max_pool2d(a, 2)
+    d = enc[3]
+    for j, l in enumerate((2, 1, 0)):
+        k = 8 + 3 * j
+        d = torch.cat([rf(rb(up(k, d))), enc[l]], 1)
+        d = block(k + 2, block(k + 1, d))
+    w, b = wb(17)
+    out = F.conv2d(d, w.view(w.shape[1], w.shape[2]).t()[:, :, None, None], b)
+    return out.permute(0, 2, 3, 1)
+
+
+@pytest.mark.parametrize("base,B,S", [(2, 2, 16), (4, 1, 32)])
+def test_bf16_format_matches_torch_autograd_with_the_same_roundings(base, B, S):
+    p, x, t, m = sample(base, B, S, 3 * base + S)
+    out = O.unet_forward(p, x, base, bf16=True)
+    pt = torch.tensor(p, requires_grad=True)
+    ot = torch_unet_bf16(pt, torch.tensor(x), base)
+    # same stored values up to the order of binary64 sums
+    assert np.allclose(out, ot.detach().numpy(), rtol=1e-9, atol=1e-9)
+    loss, g = O.unet_loss_grad(p, x, t, m, base, bf16=True)
+    lt = nll(ot, torch.tensor(t), torch.tensor(m))
+    lt.backward()
+    assert abs(loss - lt.item()) <= 1e-9 * max(1.0, abs(loss))
+    gt = pt.grad.numpy()
+    assert np.linalg.norm(g - gt) <= 1e-7 * np.linalg.norm(gt)
+    # and the format really differs from binary64
+    assert not np.allclose(out, O.unet_forward(p, x, base), rtol=1e-6, atol=0)
