@@ -369,8 +369,8 @@ mem_status mem_batch_reset_stats(mem_batch* batch, void* stream);
 /* A network that takes map layers and produces a new one (the plugin slot
  * of Sec. III-D): a 4-level U-Net that predicts, for every cell of a
  * size x size window, a height and a log variance from three input channels
- *   x[b][i][j][0] = h - z_ref   (0 where the cell has no height)
- *   x[b][i][j][1] = log v       (0 where the cell has no height)
+ *   x[b][i][j][0] = h - z_ref               (0 where the cell has no height)
+ *   x[b][i][j][1] = ln(sqrt(v) / 0.01 m)    (0 where the cell has no height)
  *   x[b][i][j][2] = 1 if the cell has a height, else 0
  * (NHWC FP32, b < batch, row i = logical grid row).  Level l (l = 0..3) works
  * at size / 2^l with base * 2^l channels: two 3x3 convolutions with ReLU,
@@ -396,10 +396,14 @@ typedef struct mem_unet mem_unet;
 int64_t mem_unet_num_params(int32_t base);
 
 /* Allocates a network for batches of up to max_batch windows of size x size
- * (size a multiple of 8, 8 .. 4096) with He-normal weights drawn from `seed`
- * (deterministic) and zero biases.  MEM_E_ARG on bad sizes, MEM_E_NOMEM. */
-mem_status mem_unet_create(int32_t base, int32_t max_batch, int32_t size, uint64_t seed, void* stream,
-                           mem_unet** out);
+ * (size a multiple of 8, 8 .. 4096).  Convolution weights are He-normal
+ * (standard deviation sqrt(2 / fan_in)) drawn from `seed` (deterministic),
+ * their biases zero; the head starts at zero weights with bias
+ * (0, 2 ln sigma0), so the untrained network predicts h = z_ref with
+ * standard deviation sigma0 > 0 (metres, the height scale of the terrain).
+ * MEM_E_ARG on bad sizes, MEM_E_NOMEM. */
+mem_status mem_unet_create(int32_t base, int32_t max_batch, int32_t size, uint64_t seed, float sigma0,
+                           void* stream, mem_unet** out);
 mem_status mem_unet_destroy(mem_unet* net, void* stream);
 
 /* Copies the flat parameters in (device, mem_unet_num_params floats; resets
@@ -429,6 +433,21 @@ mem_status mem_unet_loss_grad(mem_unet* net, const float* x, const float* target
  * NULL. */
 mem_status mem_unet_train_step(mem_unet* net, const float* x, const float* target, const float* mask,
                                int32_t batch, float inv_count, float lr, float* loss, void* stream);
+
+/* The network input x (device, height x width x 3, NHWC) of one window
+ * from its height and variance layers h, v (device, height x width, logical
+ * row-major order as mem_get_layer / mem_batch_get_layer return them; NaN
+ * height = no height), channels as described above. */
+mem_status mem_unet_input(const float* h, const float* v, int32_t width, int32_t height, float z_ref, float* x,
+                          void* stream);
+
+/* Gated completion of batch prepared windows x (device, batch x size x
+ * size x 3): out_h / out_sigma (device, batch x size x size) follow the rule
+ * of mem_complete below, with an observed cell's values rebuilt from its
+ * input (x0 + z_ref, 0.01 exp(x1); the height exact for z_ref = 0) and a
+ * predicted height reported as (network output + z_ref). */
+mem_status mem_unet_complete(mem_unet* net, const float* x, int32_t batch, float z_ref, float sigma_max,
+                             float* out_h, float* out_sigma, void* stream);
 
 /* Completion of a map's height layer: runs the network on the whole map
  * (width = height = the network's size, input built from the map's

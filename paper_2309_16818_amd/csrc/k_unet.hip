@@ -25,6 +25,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 64, BN = 64, BK = 32;
+constexpr float kLogSigmaRef = -4.60517019f;  // ln(0.01 m), the input's standard-deviation unit
 constexpr int LDSK = BK + 8;  // padded row (bf16) against bank conflicts
 
 __device__ __forceinline__ uint16_t bf(float f) { return f32_to_bf16(f); }
@@ -393,7 +394,8 @@ __global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float
     }
 }
 
-// Network input from a map: (h - z_ref, log v, mask) with 0 where invalid.
+// Network input from a map: (h - z_ref, ln(sqrt(v) / 0.01), mask), all 0
+// where the cell has no height.
 __global__ void k_map_input(const float* __restrict__ h, const float* __restrict__ v, Grid g, float z_ref,
                             float* __restrict__ x)
 {
@@ -408,27 +410,37 @@ __global__ void k_map_input(const float* __restrict__ h, const float* __restrict
     const float hv = h[st];
     const bool ok = !isnan(hv);
     x[3 * j] = ok ? hv - z_ref : 0.f;
-    x[3 * j + 1] = ok ? logf(v[st]) : 0.f;
+    x[3 * j + 1] = ok ? 0.5f * logf(v[st]) - kLogSigmaRef : 0.f;
     x[3 * j + 2] = ok ? 1.f : 0.f;
 }
 
-// Gate: a cell without a classical height takes the network's height where
-// its predicted standard deviation is below sigma_max.
+// Gate: a cell with a classical height keeps it (read from the map's own
+// layers when h is given, so it is returned unchanged; else rebuilt from the
+// window input); a cell without one takes the network's height where its
+// predicted standard deviation is below sigma_max, else NaN.
 __global__ void k_gate(const float* __restrict__ x, const float* __restrict__ out, int64_t P, float z_ref,
-                       float sigma_max, float* __restrict__ out_h, float* __restrict__ out_sigma)
+                       float sigma_max, const float* __restrict__ h, const float* __restrict__ v, Grid g,
+                       float* __restrict__ out_h, float* __restrict__ out_sigma)
 {
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
         const bool observed = x[3 * p + 2] > 0.f;
-        const float sig = expf(0.5f * out[2 * p + 1]);
-        if (observed) {
+        if (observed && h) {
+            const int ix = (int)(p % g.W), iy = (int)(p / g.W);
+            int sx = ix + g.rx;
+            sx -= (sx >= g.W) ? g.W : 0;
+            int sy = iy + g.ry;
+            sy -= (sy >= g.H) ? g.H : 0;
+            const int st = sy * g.W + sx;
+            out_h[p] = h[st];
+            out_sigma[p] = sqrtf(v[st]);
+        } else if (observed) {
             out_h[p] = x[3 * p] + z_ref;
-            out_sigma[p] = expf(0.5f * x[3 * p + 1]);
-        } else if (sig < sigma_max) {
-            out_h[p] = out[2 * p] + z_ref;
-            out_sigma[p] = sig;
+            out_sigma[p] = expf(x[3 * p + 1] + kLogSigmaRef);
         } else {
-            out_h[p] = __builtin_nanf("");
-            out_sigma[p] = __builtin_nanf("");
+            const float sig = expf(0.5f * out[2 * p + 1]);
+            const bool take = sig < sigma_max;
+            out_h[p] = take ? out[2 * p] + z_ref : __builtin_nanf("");
+            out_sigma[p] = take ? sig : __builtin_nanf("");
         }
     }
 }
@@ -550,9 +562,10 @@ void unet_map_input(hipStream_t s, const float* h, const float* v, const Grid& g
 }
 
 void unet_gate(hipStream_t s, const float* x, const float* out, int64_t P, float z_ref, float sigma_max,
-               float* out_h, float* out_sigma)
+               const float* h, const float* v, const Grid& g, float* out_h, float* out_sigma)
 {
-    hipLaunchKernelGGL(k_gate, dim3(grid_for(P)), dim3(256), 0, s, x, out, P, z_ref, sigma_max, out_h, out_sigma);
+    hipLaunchKernelGGL(k_gate, dim3(grid_for(P)), dim3(256), 0, s, x, out, P, z_ref, sigma_max, h, v, g, out_h,
+                       out_sigma);
 }
 
 }  // namespace memk

@@ -318,11 +318,12 @@ int64_t mem_unet_num_params(int32_t base)
     return u.n_params;
 }
 
-mem_status mem_unet_create(int32_t base, int32_t max_batch, int32_t size, uint64_t seed, void* stream,
-                           mem_unet** out)
+mem_status mem_unet_create(int32_t base, int32_t max_batch, int32_t size, uint64_t seed, float sigma0,
+                           void* stream, mem_unet** out)
 {
     if (!out) return api_fail(MEM_E_ARG, "out is NULL");
     *out = nullptr;
+    if (!(sigma0 > 0.f) || !std::isfinite(sigma0)) return api_fail(MEM_E_ARG, "sigma0 must be positive");
     if (base < 1 || base > 256 || max_batch < 1 || size < 8 || size % 8 != 0 || size > 4096)
         return api_fail(MEM_E_ARG, "base 1..256, max_batch >= 1, size a multiple of 8 in 8..4096");
     if ((int64_t)max_batch * size * size * 2 * base >= (int64_t)1 << 31)
@@ -373,10 +374,11 @@ mem_status mem_unet_create(int32_t base, int32_t max_batch, int32_t size, uint64
         free_unet(u);
         return api_fail(MEM_E_NOMEM, "network buffers");
     }
-    // He-normal weights (std sqrt(2 / fan_in)), zero biases, zero moments
+    // He-normal convolution weights (std sqrt(2 / fan_in)), zero biases, a
+    // zero head predicting (0, 2 ln sigma0), zero moments
     std::vector<float> w(u->n_params, 0.f);
     uint64_t st = seed;
-    for (int i = 0; i < NLAY; i++) {
+    for (int i = 0; i < NLAY - 1; i++) {
         const ULayer& Y = u->L[i];
         const int64_t nw = (int64_t)Y.taps * Y.ci * Y.co;
         const double sd = std::sqrt(2.0 / ((double)Y.taps * Y.ci));
@@ -386,6 +388,7 @@ mem_status mem_unet_create(int32_t base, int32_t max_batch, int32_t size, uint64
             w[Y.off + k] = (float)(sd * std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2));
         }
     }
+    w[u->n_params - 1] = 2.f * std::log(sigma0);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMemcpy(u->w, w.data(), sizeof(float) * u->n_params, hipMemcpyHostToDevice);
     if (e == hipSuccess) {
@@ -523,6 +526,34 @@ mem_status mem_unet_load(mem_unet* u, const char* path, void* stream)
 
 }  // extern "C"
 
+extern "C" mem_status mem_unet_input(const float* h, const float* v, int32_t width, int32_t height, float z_ref,
+                                     float* x, void* stream)
+{
+    if (!h || !v || !x) return api_fail(MEM_E_ARG, "NULL argument");
+    if (width < 1 || height < 1 || (int64_t)width * height > ((int64_t)1 << 28))
+        return api_fail(MEM_E_ARG, "bad size %d x %d", width, height);
+    if (!std::isfinite(z_ref)) return api_fail(MEM_E_ARG, "z_ref must be finite");
+    Grid g{};
+    g.W = width;
+    g.H = height;
+    unet_map_input((hipStream_t)stream, h, v, g, z_ref, x);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return api_fail(MEM_E_HIP, "mem_unet_input: %s", hipGetErrorString(e));
+    return MEM_OK;
+}
+
+extern "C" mem_status mem_unet_complete(mem_unet* u, const float* x, int32_t batch, float z_ref, float sigma_max,
+                                        float* out_h, float* out_sigma, void* stream)
+{
+    if (mem_status st = check_batch(u, batch)) return st;
+    if (!x || !out_h || !out_sigma) return api_fail(MEM_E_ARG, "NULL argument");
+    if (!std::isfinite(z_ref) || !(sigma_max > 0.f)) return api_fail(MEM_E_ARG, "bad z_ref or sigma_max");
+    if (mem_status st = mem_unet_forward(u, x, batch, u->out, stream)) return st;
+    unet_gate((hipStream_t)stream, x, u->out, P_at(u, batch, 0), z_ref, sigma_max, nullptr, nullptr, Grid{}, out_h,
+              out_sigma);
+    return finish(u, "mem_unet_complete");
+}
+
 // mem_complete needs the map's internals (mem_api.hip).
 namespace memk {
 mem_status map_height_view(const mem_map* m, const float** h, const float** v, Grid* g);
@@ -538,9 +569,8 @@ extern "C" mem_status mem_complete(const mem_map* map, mem_unet* u, float z_ref,
     Grid g;
     if (mem_status st = map_height_view(map, &h, &v, &g)) return st;
     if (g.W != u->S || g.H != u->S) return api_fail(MEM_E_ARG, "the network was built for %dx%d maps", u->S, u->S);
-    hipStream_t s = (hipStream_t)stream;
-    unet_map_input(s, h, v, g, z_ref, u->xin);
+    unet_map_input((hipStream_t)stream, h, v, g, z_ref, u->xin);
     if (mem_status st = mem_unet_forward(u, u->xin, 1, u->out, stream)) return st;
-    unet_gate(s, u->xin, u->out, (int64_t)u->S * u->S, z_ref, sigma_max, out_h, out_sigma);
+    unet_gate((hipStream_t)stream, u->xin, u->out, (int64_t)g.W * g.H, z_ref, sigma_max, h, v, g, out_h, out_sigma);
     return finish(u, "mem_complete");
 }

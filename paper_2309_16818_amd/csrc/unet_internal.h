@@ -72,6 +72,6 @@ void unet_adam(hipStream_t s, float* w, const float* g, float* m, float* v, int6
                float eps, float c1, float c2);
 void unet_map_input(hipStream_t s, const float* h, const float* v, const Grid& g, float z_ref, float* x);
 void unet_gate(hipStream_t s, const float* x, const float* out, int64_t P, float z_ref, float sigma_max,
-               float* out_h, float* out_sigma);
+               const float* h, const float* v, const Grid& g, float* out_h, float* out_sigma);
 
 }  // namespace memk

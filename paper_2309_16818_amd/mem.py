@@ -491,7 +491,8 @@ class Batch:
 
 UNET_SYMBOLS = ("mem_unet_num_params", "mem_unet_create", "mem_unet_destroy", "mem_unet_set_params",
                 "mem_unet_get_params", "mem_unet_save", "mem_unet_load", "mem_unet_forward",
-                "mem_unet_loss_grad", "mem_unet_train_step", "mem_complete")
+                "mem_unet_loss_grad", "mem_unet_train_step", "mem_unet_input", "mem_unet_complete",
+                "mem_complete")
 
 
 def _load_unet():
@@ -500,7 +501,7 @@ def _load_unet():
         return L
     P, I32, F = C.c_void_p, C.c_int32, C.c_float
     sig = {
-        "mem_unet_create": [I32, I32, I32, C.c_uint64, P, C.POINTER(P)],
+        "mem_unet_create": [I32, I32, I32, C.c_uint64, F, P, C.POINTER(P)],
         "mem_unet_destroy": [P, P],
         "mem_unet_set_params": [P, P, P],
         "mem_unet_get_params": [P, P, P],
@@ -509,6 +510,8 @@ def _load_unet():
         "mem_unet_forward": [P, P, I32, P, P],
         "mem_unet_loss_grad": [P, P, P, P, I32, F, P, P, P],
         "mem_unet_train_step": [P, P, P, P, I32, F, F, P, P],
+        "mem_unet_input": [P, P, I32, I32, F, P, P],
+        "mem_unet_complete": [P, P, I32, F, F, P, P, P],
         "mem_complete": [P, P, F, F, P, P, P],
     }
     for name, args in sig.items():
@@ -528,12 +531,13 @@ def unet_num_params(base: int) -> int:
 class UNet:
     """The completion network (mem_unet_*): NHWC FP32 device tensors in and out."""
 
-    def __init__(self, base=32, max_batch=1, size=256, seed=0, stream=None):
+    def __init__(self, base=32, max_batch=1, size=256, seed=0, sigma0=0.3, stream=None):
         L = _load_unet()
         self.base, self.max_batch, self.size = int(base), int(max_batch), int(size)
         self.n_params = unet_num_params(base)
         h = C.c_void_p()
-        _check(L.mem_unet_create(self.base, self.max_batch, self.size, int(seed), _stream(stream), C.byref(h)))
+        _check(L.mem_unet_create(self.base, self.max_batch, self.size, int(seed), float(sigma0), _stream(stream),
+                                 C.byref(h)))
         self._u = h
 
     def close(self, stream=None):
@@ -603,6 +607,16 @@ class UNet:
                                                 self._tm(mask, B, "mask"), B, self._inv_count(mask), float(lr),
                                                 lp, _stream(stream)))
 
+    def complete_windows(self, x, z_ref, sigma_max, stream=None):
+        """(height, sigma) [B, size, size] of prepared windows x (mem_unet_complete)."""
+        B = x.shape[0]
+        out_h = torch.empty((B, self.size, self.size), dtype=torch.float32, device="cuda")
+        out_s = torch.empty_like(out_h)
+        _check(_load_unet().mem_unet_complete(self._u, self._x(x, 3, "x"), B, float(z_ref), float(sigma_max),
+                                              _dev_ptr(out_h, "out_h"), _dev_ptr(out_s, "out_sigma"),
+                                              _stream(stream)))
+        return out_h, out_s
+
     def complete(self, m: "Map", z_ref, sigma_max, stream=None):
         """(height, sigma) [H, W] of the map completed by the network (mem_complete)."""
         out_h = torch.empty((m.H, m.W), dtype=torch.float32, device="cuda")
@@ -610,3 +624,19 @@ class UNet:
         _check(_load_unet().mem_complete(m._h, self._u, float(z_ref), float(sigma_max), _dev_ptr(out_h, "out_h"),
                                          _dev_ptr(out_s, "out_sigma"), _stream(stream)))
         return out_h, out_s
+
+
+def unet_input(h: torch.Tensor, v: torch.Tensor, z_ref, out: torch.Tensor | None = None, stream=None):
+    """Network input [H, W, 3] of one window from its height / variance layers
+    (mem_unet_input)."""
+    if h.shape != v.shape or h.dim() != 2 or h.dtype != torch.float32 or v.dtype != torch.float32:
+        raise ValueError("h and v must be float32 [H, W] tensors of one shape")
+    h, v = h.contiguous(), v.contiguous()
+    H, W = h.shape
+    if out is None:
+        out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    if tuple(out.shape) != (H, W, 3) or not out.is_contiguous():
+        raise ValueError("out must be a contiguous [H, W, 3] tensor")
+    _check(_load_unet().mem_unet_input(_dev_ptr(h, "h"), _dev_ptr(v, "v"), W, H, float(z_ref), _dev_ptr(out, "x"),
+                                       _stream(stream)))
+    return out

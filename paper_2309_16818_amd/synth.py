@@ -527,3 +527,153 @@ class BatchWorld:
         g.manual_seed(seed)
         f = torch.randn(self.n, cam["h"], cam["w"], cam["c"], device=self.device, generator=g)
         return (f / f.norm(dim=-1, keepdim=True)).contiguous()
+
+
+# --------------------------------------------------------------------------
+# Completion pairs: dense 360-degree sweeps against one forward sensor
+# --------------------------------------------------------------------------
+
+class CompletionWorld:
+    """n windows of `size` cells at `res` metres, each on its own seeded
+    terrain (8 sinusoids with amplitudes summing to 0.3 m, wavelengths 1-8 m,
+    and 5 boxes 0.2-1.0 m wide, 0.05-0.5 m tall inside the window), with the
+    robot at the window centre (the origin) under a random yaw, its sensors
+    0.6 m above the ground there.
+
+    * ``dense_step(v)`` (v = 0..4): a 360-degree sweep from viewpoint v (the
+      centre, then four points at +-0.3 of the window side in x and y):
+      1.5 points per cell drawn uniformly over the window, kept if within
+      0.6 window sides of the viewpoint and visible from it (the straight
+      segment stays above the terrain at 15 samples).
+    * ``sparse_step()``: one forward sensor at the centre, a 90-degree
+      sector around the yaw, ranges 0.3 m to 0.45 window sides, the same
+      density, visible points only, minus the shadows of 2-5 random vertical
+      cylinders (radius 0.1-0.4 m, 1-4 m ahead inside the sector), which
+      stand in for transient obstacles and are not part of the terrain.
+
+    Points get z-noise 0.01 + 0.001 r^2 for range r to their sensor and are
+    returned in that sensor's frame.  All random numbers come from numpy
+    PCG64 (terrain, poses, occluders) and a seeded torch generator on the
+    device (point samples, noise)."""
+
+    VIEW = ((0.0, 0.0), (0.3, 0.0), (-0.3, 0.0), (0.0, 0.3), (0.0, -0.3))
+
+    def __init__(self, n, size=256, res=0.04, seed=0, device="cuda"):
+        self.n, self.size, self.res, self.device = n, size, res, device
+        self.ext = size * res
+        r = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, n, size])))
+        self.rng = r
+        a = r.uniform(0, 1, (n, 8))
+        a = 0.3 * a / a.sum(1, keepdims=True)
+        lam = r.uniform(1, 8, (n, 8))
+        phi = r.uniform(0, 2 * np.pi, (n, 8))
+        t = lambda v: torch.as_tensor(v, dtype=torch.float32, device=device)
+        self.amp, self.psi = t(a), t(r.uniform(0, 2 * np.pi, (n, 8)))
+        self.kx, self.ky = t(2 * np.pi * np.cos(phi) / lam), t(2 * np.pi * np.sin(phi) / lam)
+        bc = r.uniform(-0.45, 0.45, (n, 5, 2)) * self.ext
+        bh = r.uniform(0.1, 0.5, (n, 5, 2))
+        self.box = t(np.concatenate([bc, bh, r.uniform(0.05, 0.5, (n, 5, 1))], -1))
+        self.yaw = r.uniform(0, 2 * np.pi, n)
+        ids = torch.arange(n, device=device)
+        zero = torch.zeros(n, device=device)
+        self.ground = self.height(ids, zero, zero).cpu().numpy().astype(np.float64)
+        self.gen = torch.Generator(device=device)
+        self.gen.manual_seed(int(r.integers(0, 2**62)))
+
+    def height(self, mid, x, y):
+        h = torch.zeros_like(x)
+        for k in range(8):
+            h = h + self.amp[mid, k] * torch.sin(x * self.kx[mid, k] + y * self.ky[mid, k] + self.psi[mid, k])
+        for b in range(5):
+            B = self.box[mid, b]
+            inside = ((x - B[:, 0]).abs() <= B[:, 2]) & ((y - B[:, 1]).abs() <= B[:, 3])
+            h = h + inside.float() * B[:, 4]
+        return h
+
+    def _visible(self, mid, ox, oy, oz, x, y, z, samples=15, chunk=1 << 21):
+        keep = torch.empty(x.shape, dtype=torch.bool, device=self.device)
+        for s0 in range(0, x.shape[0], chunk):
+            sl = slice(s0, s0 + chunk)
+            ok = torch.ones(x[sl].shape, dtype=torch.bool, device=self.device)
+            for k in range(1, samples + 1):
+                f = k / (samples + 1)
+                xs = ox[sl] + f * (x[sl] - ox[sl])
+                ys = oy[sl] + f * (y[sl] - oy[sl])
+                zs = oz[sl] + f * (z[sl] - oz[sl])
+                ok &= self.height(mid[sl], xs, ys) < zs - 1e-3
+            keep[sl] = ok
+        return keep
+
+    def _cloud(self, mid, x, y, ox, oy, oz, yaw):
+        """Noisy visible points (sensor frame) and per-map offsets."""
+        z = self.height(mid, x, y)
+        vis = self._visible(mid, ox[mid], oy[mid], oz[mid], x, y, z)
+        mid, x, y, z = mid[vis], x[vis], y[vis], z[vis]
+        dx, dy, dz = x - ox[mid], y - oy[mid], z - oz[mid]
+        r2 = dx * dx + dy * dy + dz * dz
+        dz = dz + torch.randn(dz.shape, device=self.device, generator=self.gen) * (0.01 + 0.001 * r2)
+        c, s = torch.cos(yaw)[mid], torch.sin(yaw)[mid]
+        xyz = torch.stack([c * dx + s * dy, -s * dx + c * dy, dz], 1).contiguous()
+        cnt = torch.bincount(mid, minlength=self.n).cpu().numpy()
+        offs = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int64)
+        return xyz, offs
+
+    def _poses(self, ox, oy, oz):
+        T = np.zeros((self.n, 3, 4), np.float32)
+        for m in range(self.n):
+            T[m] = pose_matrix(rot_z(self.yaw[m]), (ox[m], oy[m], oz[m]))
+        return T
+
+    def _common(self, per_cell):
+        n, dev = self.n, self.device
+        cnt = int(per_cell * self.size * self.size)
+        mid = torch.arange(n, device=dev).repeat_interleave(cnt)
+        u = torch.rand(n * cnt, 2, device=dev, generator=self.gen)
+        return mid, (u[:, 0] - 0.5) * self.ext, (u[:, 1] - 0.5) * self.ext
+
+    def dense_step(self, v):
+        """One viewpoint's sweep for every window: dict(xyz, offsets, T, robot_xy)."""
+        dev = self.device
+        fx, fy = self.VIEW[v]
+        vx = np.full(self.n, fx * self.ext)
+        vy = np.full(self.n, fy * self.ext)
+        ids = torch.arange(self.n, device=dev)
+        tv = lambda a: torch.as_tensor(a, dtype=torch.float32, device=dev)
+        vz = self.height(ids, tv(vx), tv(vy)).cpu().numpy() + 0.6
+        mid, x, y = self._common(1.5)
+        ox, oy, oz = tv(vx), tv(vy), tv(vz)
+        near = (x - ox[mid]) ** 2 + (y - oy[mid]) ** 2 <= (0.6 * self.ext) ** 2
+        xyz, offs = self._cloud(mid[near], x[near], y[near], ox, oy, oz, tv(self.yaw))
+        return dict(xyz=xyz, offsets=offs, T=self._poses(vx, vy, vz),
+                    robot_xy=np.zeros((self.n, 2), np.float32))
+
+    def sparse_step(self):
+        """The forward sensor's cloud for every window (same keys)."""
+        dev, n, r = self.device, self.n, self.rng
+        tv = lambda a: torch.as_tensor(a, dtype=torch.float32, device=dev)
+        oz = self.ground + 0.6
+        rmax = 0.45 * self.ext
+        mid, x, y = self._common(1.5)
+        yaw = tv(self.yaw)
+        ang = torch.atan2(y, x) - yaw[mid]
+        ang = torch.remainder(ang + np.pi, 2 * np.pi) - np.pi
+        rr = torch.sqrt(x * x + y * y)
+        keep = (ang.abs() <= np.pi / 4) & (rr >= 0.3) & (rr <= rmax)
+        # occluders: k cylinders per window
+        k = r.integers(2, 6, n)
+        oc = np.zeros((n, 5, 3))  # x, y, radius (radius 0 = none)
+        for m in range(n):
+            for j in range(k[m]):
+                d, a = r.uniform(1.0, 4.0), self.yaw[m] + r.uniform(-np.pi / 4, np.pi / 4)
+                oc[m, j] = (d * np.cos(a), d * np.sin(a), r.uniform(0.1, 0.4))
+        oc = tv(oc)
+        for j in range(5):
+            cx, cy, cr = oc[mid, j, 0], oc[mid, j, 1], oc[mid, j, 2]
+            # closest approach of the segment origin -> point to the cylinder axis
+            tt = torch.clamp((cx * x + cy * y) / torch.clamp(rr * rr, min=1e-9), 0, 1)
+            dist2 = (tt * x - cx) ** 2 + (tt * y - cy) ** 2
+            keep &= ~((cr > 0) & (dist2 <= cr * cr))
+        zero = np.zeros(n)
+        xyz, offs = self._cloud(mid[keep], x[keep], y[keep], tv(zero), tv(zero), tv(oz), yaw)
+        return dict(xyz=xyz, offsets=offs, T=self._poses(zero, zero, oz),
+                    robot_xy=np.zeros((n, 2), np.float32))

@@ -103,8 +103,9 @@ def test_unet_host_checks():
         assert lib.mem_unet_num_params(base) == O.unet_num_params(base)
     assert lib.mem_unet_num_params(0) == -1
     h = C.c_void_p()
-    for args in ((0, 1, 16), (32, 0, 256), (32, 1, 12), (32, 1, 4), (32, 1, 8192), (257, 1, 16)):
-        assert lib.mem_unet_create(*args, 0, None, C.byref(h)) == mem.MEM_E_ARG, args
+    for args in ((0, 1, 16, 0.3), (32, 0, 256, 0.3), (32, 1, 12, 0.3), (32, 1, 4, 0.3), (32, 1, 8192, 0.3),
+                 (257, 1, 16, 0.3), (4, 1, 16, 0.0), (4, 1, 16, float("nan"))):
+        assert lib.mem_unet_create(*args[:3], 0, args[3], None, C.byref(h)) == mem.MEM_E_ARG, args
         assert not h.value
     assert lib.mem_unet_forward(None, None, 1, None, None) == mem.MEM_E_ARG
     assert lib.mem_unet_train_step(None, None, None, None, 1, 1.0, 1e-3, None, None) == mem.MEM_E_ARG

@@ -1,11 +1,26 @@
-"""GPU parity of the completion U-Net (mem_unet_*) against the binary64 oracle.
+"""GPU parity of the completion U-Net (mem_unet_*) against the oracle.
 
-Both sides get the same BF16-representable weights and inputs, so the only
-differences are the BF16 storage of activations and gradients on the GPU and
-its FP32 accumulation.  Bars: forward within 1e-2 norm-wise relative, loss
-within 1e-2 relative, parameter gradient with cosine >= 0.999 and norm-wise
-relative error <= 2e-2 (one BF16 rounding, 2^-9 relative, per stored tensor,
-accumulated over the deepest path of about 20 stored tensors)."""
+The network's number format is BF16 storage with FP32 accumulation: inputs,
+convolution weights, stored activations and the gradients at convolution
+outputs are BF16, so ReLU masks and max-pool winners are decided on BF16
+values.  The oracle has the same format in binary64 arithmetic (its "bf16"
+mode), and the GPU is compared against it; the only difference left is FP32
+against binary64 sums.  That difference moves a stored value to the
+neighbouring BF16 value only when the two sums fall on either side of a
+rounding boundary.
+
+* Narrow networks (base <= 6, sums of at most a few hundred terms): no
+  stored value lands on the other side, and the GPU reproduces the format to
+  FP32 rounding.  Bars: forward and gradient 1e-4 norm-wise relative, every
+  layer 1e-3, loss 1e-5 relative.
+* The real width (base 32, sums of up to 2304 terms with random signs): FP32
+  sums are off by ~1e-4 relative, a few percent of the stored values round
+  the other way and the ReLU / max-pool decisions downstream of them
+  diverge.  Any FP32-accumulating implementation of the format differs from
+  the binary64 one by the same amount (torch's own FP32 convolutions in the
+  same format differ by 4e-3 forward).  Bars against both oracles, the
+  format's own error budget: forward 1e-2, gradient cosine >= 0.999 and
+  norm-wise 2e-2, every layer 0.15, loss 1e-3."""
 import os
 
 import numpy as np
@@ -72,16 +87,22 @@ def make(base, B, S, p):
 CASES = [(2, 2, 16), (4, 2, 32), (6, 1, 24), (32, 1, 32), (32, 2, 64)]
 
 
+def _bars(base):
+    """(forward, gradient, per-layer) norm-wise bars against the bf16 oracle."""
+    return (1e-4, 1e-4, 1e-3) if base <= 6 else (1e-2, 2e-2, 0.15)
+
+
 @pytest.mark.parametrize("base,B,S", CASES)
 def test_forward_matches_oracle(base, B, S):
     p, x, _, _ = sample(base, B, S, 11 * base + S)
     net = make(base, B, S, p)
     out = net.forward(dev(x)).cpu().double().numpy()
-    ref = O.unet_forward(p, x, base)
     assert np.isfinite(out).all()
-    e = relerr(out, ref)
-    print(f"base {base} B {B} S {S}: forward rel err {e:.2e}")
-    assert e <= 1e-2
+    e = relerr(out, O.unet_forward(p, x, base, bf16=True))
+    e64 = relerr(out, O.unet_forward(p, x, base))
+    print(f"base {base} B {B} S {S}: forward rel err {e:.2e} (bf16 oracle), {e64:.2e} (binary64)")
+    assert e <= _bars(base)[0]
+    assert e64 <= 1e-2
     net.close()
 
 
@@ -92,18 +113,22 @@ def test_loss_and_gradient_match_oracle(base, B, S):
     loss, g = net.loss_grad(dev(x), dev(t), dev(m))
     g = g.cpu().double().numpy()
     loss = float(loss.item())
-    rl, rg = O.unet_loss_grad(p, x, t, m, base)
+    rl, rg = O.unet_loss_grad(p, x, t, m, base, bf16=True)
     cos = float(g @ rg / (np.linalg.norm(g) * np.linalg.norm(rg)))
     e = relerr(g, rg)
-    print(f"base {base} B {B} S {S}: loss {loss:.6f} vs {rl:.6f}, grad cos {cos:.6f} rel {e:.2e}")
-    assert abs(loss - rl) <= 1e-2 * max(abs(rl), 1e-3)
-    assert cos >= 0.999 and e <= 2e-2
-    # per layer: no layer's gradient is lost in the sum
     offs = list(O.unet_layer_offsets(base)) + [len(p)]
-    for i in range(18):
-        a, b = g[offs[i]:offs[i + 1]], rg[offs[i]:offs[i + 1]]
-        if np.linalg.norm(b) > 1e-6 * np.linalg.norm(rg):
-            assert relerr(a, b) <= 5e-2, (i, relerr(a, b))
+    per = [relerr(g[offs[i]:offs[i + 1]], rg[offs[i]:offs[i + 1]]) for i in range(18)]
+    print(f"base {base} B {B} S {S}: loss {loss:.6f} vs {rl:.6f}, grad cos {cos:.7f} rel {e:.2e}, "
+          f"worst layer {int(np.argmax(per))} {max(per):.2e}")
+    _, bg, bl = _bars(base)
+    assert abs(loss - rl) <= (1e-5 if base <= 6 else 1e-3) * max(abs(rl), 1e-3)
+    assert cos >= 0.999 and e <= bg
+    assert max(per) <= bl
+    if base == 32:
+        _, g64 = O.unet_loss_grad(p, x, t, m, base)
+        cos64 = float(g @ g64 / (np.linalg.norm(g) * np.linalg.norm(g64)))
+        print(f"   binary64: cos {cos64:.6f} rel {relerr(g, g64):.2e}")
+        assert cos64 >= 0.999 and relerr(g, g64) <= 2e-2
     net.close()
 
 
@@ -169,13 +194,16 @@ def test_params_roundtrip_and_file(tmp_path):
     net = mem.UNet(base=base, max_batch=B, size=S, seed=7)
     p0 = net.params().cpu()
     assert p0.numel() == O.unet_num_params(base)
-    # He-normal weights, zero biases
+    # He-normal convolution weights, zero biases, a zero head predicting
+    # (0, 2 ln sigma0) with the default sigma0 = 0.3 m
     offs = list(O.unet_layer_offsets(base)) + [p0.numel()]
-    for i, (taps, ci, co) in enumerate(spec(base)):
+    for i, (taps, ci, co) in enumerate(spec(base)[:-1]):
         w = p0[offs[i]:offs[i] + taps * ci * co]
         assert not p0[offs[i] + taps * ci * co:offs[i + 1]].any()
         if w.numel() > 500:
             assert abs(float(w.std()) / np.sqrt(2.0 / (taps * ci)) - 1) < 0.15
+    assert not p0[offs[17]:-1].any()
+    assert p0[-1].item() == np.float32(2 * np.log(np.float32(0.3)))
     net2 = mem.UNet(base=base, max_batch=B, size=S, seed=7)
     assert torch.equal(net2.params().cpu(), p0)  # deterministic initialisation
     path = os.path.join(tmp_path, "w.bin")
@@ -224,15 +252,21 @@ def test_complete_gates_the_network_output():
     obs = np.isfinite(h)
     assert 0 < obs.sum() < S * S
     net = mem.UNet(base=4, max_batch=1, size=S, seed=3)
+    p = net.params()  # a head with random weights, so the predicted sigma varies
+    p[-(2 * 4 + 2):-2] = torch.randn(2 * 4, device="cuda", generator=torch.Generator("cuda").manual_seed(0))
+    net.set_params(p)
     z_ref = 0.1
     x = np.zeros((1, S, S, 3))
     x[0, ..., 0] = np.where(obs, h - z_ref, 0)
-    x[0, ..., 1] = np.where(obs, np.log(np.where(obs, v, 1)), 0)
+    x[0, ..., 1] = np.where(obs, 0.5 * np.log(np.where(obs, v, 1)) - np.log(0.01), 0)
     x[0, ..., 2] = obs
     out = net.forward(dev(x))[0].cpu().double().numpy()
     sig = np.exp(0.5 * out[..., 1])
     smax = float(np.median(sig[~obs]))  # about half of the unobserved cells pass
     ch, cs = net.complete(m, z_ref, smax)
+    # the input mem_complete builds is the one rebuilt here
+    xi = mem.unet_input(m.get_layer(mem.MEM_LAYER_ELEVATION), m.get_layer(mem.MEM_LAYER_VARIANCE), z_ref)
+    assert np.allclose(xi.cpu().double().numpy(), x[0], rtol=1e-6, atol=1e-6)
     ch, cs = ch.cpu().double().numpy(), cs.cpu().double().numpy()
     assert np.array_equal(ch[obs], h[obs])
     assert np.allclose(cs[obs], np.sqrt(v[obs]), rtol=1e-6)
