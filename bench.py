@@ -45,8 +45,13 @@ def parse():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--profile-events", type=int, default=1,
                     help="record HIP events around every launch in the timed region")
-    ap.add_argument("--workload", choices=["full", "batch"], default="full",
-                    help="full: one robot at full rate; batch: 1024 uneven maps per step")
+    ap.add_argument("--workload", choices=["full", "batch", "learned"], default="full",
+                    help="full: one robot at full rate; batch: 1024 uneven maps per step; "
+                         "learned: the completion network's training and inference at 256x256")
+    ap.add_argument("--pairs", type=int, default=288, help="learned: generated (input, target) windows")
+    ap.add_argument("--train-steps", type=int, default=1500,
+                    help="learned: total training steps before the quality evaluation")
+    ap.add_argument("--train-batch", type=int, default=8)
     ap.add_argument("--maps", type=int, default=1024)
     ap.add_argument("--plain-steps", type=int, default=2,
                     help="batch workload: steps of the per-map call sequence timed beside it")
@@ -135,6 +140,138 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+MFMA_BF16_PEAK_TFS = 2500.0  # dense BF16 matrix peak of the MI355X
+
+
+def unet_gemm_flops(base, size, batch):
+    """Algorithmic FLOPs of one training step's matrix products per kind
+    (2 M N K with the unpadded K of each product)."""
+    c = [base << l for l in range(4)]
+    P = [batch * (size >> l) ** 2 for l in range(4)]
+    conv = []  # (level, ci, co)
+    prev = 3
+    for l in range(4):
+        conv += [(l, prev, c[l]), (l, c[l], c[l])]
+        prev = c[l]
+    up = []
+    for l in (2, 1, 0):
+        up.append((l, c[l + 1], c[l]))
+        conv += [(l, 2 * c[l], c[l]), (l, c[l], c[l])]
+    f = dict(gemm_fwd=0, gemm_up=0, gemm_dgrad=0, gemm_wgrad=0)
+    for i, (l, ci, co) in enumerate(conv):
+        f["gemm_fwd"] += 2 * P[l] * 9 * ci * co
+        f["gemm_wgrad"] += 2 * P[l] * 9 * ci * co
+        if i > 0:  # the first layer needs no input gradient
+            f["gemm_dgrad"] += 2 * P[l] * 9 * ci * co
+    for l, ci, co in up:
+        f["gemm_up"] += 2 * P[l + 1] * ci * 4 * co
+        f["gemm_wgrad"] += 2 * P[l + 1] * ci * 4 * co
+        f["gemm_dgrad"] += 2 * P[l + 1] * ci * 4 * co
+    return f
+
+
+def run_learned(args):
+    """The completion network at its full size (base 32, 256x256 windows of a
+    0.04 m map): pairs from the batched map update, timed training steps
+    (forward, backward and Adam on batches of 8), inference latency of
+    mem_complete on one map, and the completion's quality on held-out pairs
+    after training."""
+    import torch
+    from paper_2309_16818_amd import completion, mem, synth
+    torch.cuda.set_device(0)
+    S, res, base, bs = 256, 0.04, 32, args.train_batch
+    t0 = time.time()
+    pairs = completion.make_pairs(args.pairs, size=S, res=res, seed=args.seed)
+    n_hold = min(32, args.pairs // 4)
+    train = pairs.subset(range(args.pairs - n_hold))
+    held = pairs.subset(range(args.pairs - n_hold, args.pairs))
+    print(f"# generated {args.pairs} pairs in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    net = mem.UNet(base=base, max_batch=bs, size=S, seed=0)
+    completion.train(net, train, steps=args.warmup, batch=bs, lr=1e-3, seed=0, lr_final=1e-3)
+    torch.cuda.synchronize()
+    net.profile_enable(True)
+    net.profile_read()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t1 = time.perf_counter()
+    e0.record()
+    completion.train(net, train, steps=args.steps, batch=bs, lr=1e-3, seed=1, lr_final=1e-3)
+    e1.record()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    kern = net.profile_read()
+    net.profile_enable(False)
+    step_ms = (t2 - t1) * 1e3 / args.steps
+    flops = unet_gemm_flops(base, S, bs)
+    kernels = {}
+    for name, (launches, ms) in kern.items():
+        per_step = launches / args.steps
+        k = dict(launches=launches, total_ms=round(ms, 4), avg_us=round(1e3 * ms / max(launches, 1), 3),
+                 ms_per_step=round(ms / args.steps, 4))
+        if name in flops:
+            k["tflops"] = round(flops[name] * args.steps / (ms * 1e-3) / 1e12, 2)
+            k["gflop_per_launch"] = round(flops[name] / per_step / 1e9, 3)
+        kernels[name] = k
+    gemm = [k for k in kernels if k in flops]
+    dom = max(gemm, key=lambda k: kernels[k]["total_ms"])
+    ach = kernels[dom]["tflops"]
+    all_gemm = sum(flops.values()) * args.steps / (sum(kernels[k]["total_ms"] for k in gemm) * 1e-3) / 1e12
+    # the rest of the training, then quality on held-out windows
+    rest = max(0, args.train_steps - args.warmup - args.steps)
+    t3 = time.time()
+    completion.train(net, train, steps=rest, batch=bs, lr=1e-3, seed=2)
+    torch.cuda.synchronize()
+    print(f"# trained {rest} more steps in {time.time() - t3:.1f}s", file=sys.stderr, flush=True)
+    q = completion.evaluate(net, held, 0.05)
+    # inference: mem_complete on one map holding a sparse fusion
+    w = synth.CompletionWorld(1, size=S, res=res, seed=args.seed + 99)
+    st = w.sparse_step()
+    m = mem.Map(mem.MapParams(S, S, res, max_range=20.0))
+    m.input_pointcloud(st["xyz"], st["T"][0])
+    z = float(w.ground[0])
+    for _ in range(3):
+        net.complete(m, z, 0.05)
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(20):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        net.complete(m, z, 0.05)
+        b.record()
+        torch.cuda.synchronize()
+        lat.append(a.elapsed_time(b))
+    lat = np.array(lat)
+    # batched inference throughput (windows of the held-out set)
+    xb = held.x[:bs].contiguous()
+    net.complete_windows(xb, 0.0, 0.05)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    for _ in range(10):
+        net.complete_windows(xb, 0.0, 0.05)
+    torch.cuda.synchronize()
+    inf_cells = 10 * bs * S * S / (time.perf_counter() - t4)
+    out = {
+        "metric": METRIC, "value": round(inf_cells, 1), "unit": "cells/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(step_ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"learned completion: 4-level U-Net, base 32 ({net.n_params} parameters), "
+                               f"{S}x{S} windows at {res} m, trained on pairs of the batched map update "
+                               f"(dense 360-degree sweeps vs one forward sensor with occluders), batch {bs}",
+                   "pairs": args.pairs, "train_steps": args.train_steps},
+        "value_is": "completion inference: gated cells per second on batches of windows",
+        "train": {"samples_per_s": round(bs / (step_ms * 1e-3), 1), "ms_per_step": round(step_ms, 3),
+                  "gemm_tflops_all": round(all_gemm, 2)},
+        "latency_ms": {"what": "mem_complete on one 256x256 map", "mean": round(float(lat.mean()), 4),
+                       "std": round(float(lat.std()), 4), "median": round(float(np.median(lat)), 4),
+                       "p90": round(float(np.percentile(lat, 90)), 4)},
+        "quality": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in q.items()},
+        "kernels": kernels,
+        "roofline": {"kernel": dom, "bound": "mfma", "achieved": ach, "peak": MFMA_BF16_PEAK_TFS,
+                     "unit": "TFLOP/s", "frac": round(ach / MFMA_BF16_PEAK_TFS, 4), "traffic": None},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def gen_frames(n, seed, device):
     from paper_2309_16818_amd import synth
     t0 = time.time()
@@ -206,6 +343,8 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         return run_batch(args)
+    if args.workload == "learned":
+        return run_learned(args)
     import torch
     from paper_2309_16818_amd import mem
 

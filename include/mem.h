@@ -141,10 +141,14 @@ typedef struct mem_stats {
     int64_t dropped_outside;    /* fell outside the grid                         */
     int64_t cells_touched;      /* (cell, cloud) pairs with at least one point   */
     int64_t cells_cleared;      /* cells invalidated by clearing votes           */
-    int64_t ray_cells;          /* cells visited by clearing rays                */
+    int64_t ray_cells;          /* cell heights loaded by clearing rays          */
     int64_t cells_in_view;      /* (cell, image) pairs inside the camera frustum */
     int64_t pairs_visible;      /* (cell, image) pairs fused (not occluded)      */
-    int64_t occl_cells;         /* cells visited by occlusion rays               */
+    int64_t occl_cells;         /* cell heights loaded by occlusion rays         */
+    int64_t ray_steps;          /* cells between the ends of every clearing ray
+                                   (ray_cells is smaller where runs of cells are
+                                   ruled out by their block maxima)              */
+    int64_t occl_steps;         /* likewise for the occlusion rays               */
 } mem_stats;
 
 /* Creates a map centred on cell (0, 0) with every cell empty: no height,
@@ -410,6 +414,14 @@ mem_status mem_unet_destroy(mem_unet* net, void* stream);
  * the Adam state) or out. */
 mem_status mem_unet_set_params(mem_unet* net, const float* params, void* stream);
 mem_status mem_unet_get_params(const mem_unet* net, float* params, void* stream);
+
+/* Per-kernel event timing of the network's launches, as mem_profile_enable /
+ * mem_profile_read for a map.  Names: gemm_fwd (3x3 convolutions),
+ * gemm_up (transposed convolutions), gemm_dgrad (input gradients),
+ * gemm_wgrad (weight gradients), im2col, head, pool, eltwise, colsum, fill,
+ * relayout, adam. */
+mem_status mem_unet_profile_enable(mem_unet* net, int32_t on);
+mem_status mem_unet_profile_read(mem_unet* net, mem_kernel_time* out, int32_t max, int32_t* count);
 
 /* Writes / reads the parameters as a file: the 8 bytes "MEMUNET1", int32
  * base, int64 count, then count little-endian FP32 values.  Synchronises

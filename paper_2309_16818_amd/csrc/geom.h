@@ -71,29 +71,29 @@ __device__ __forceinline__ void lattice_cell(const Grid& g, float x, float y, in
 }
 
 // Incremental Bresenham walk from (ax, ay) towards (bx, by).  step() moves
-// to the next cell; the minor coordinate advances only when D > 0.
+// to the next cell: one cell along the major axis, plus one along the minor
+// axis when the error term D > 0.  The two moves are kept as increments
+// (mx, my) and (nx, ny) so a step has no branch on the line's octant.
 struct LineWalk {
-    int x, y, sx, sy, dmaj2, dmin2, D, steps;
+    int x, y, mx, my, nx, ny, dmaj2, dmin2, D, steps;
     bool xmajor;
     __device__ __forceinline__ LineWalk(int ax, int ay, int bx, int by)
     {
-        int dx = abs(bx - ax), dy = abs(by - ay);
-        sx = (bx >= ax) ? 1 : -1;
-        sy = (by >= ay) ? 1 : -1;
+        const int dx = abs(bx - ax), dy = abs(by - ay);
+        const int sx = (bx >= ax) ? 1 : -1;
+        const int sy = (by >= ay) ? 1 : -1;
         x = ax;
         y = ay;
         xmajor = dx >= dy;
-        if (xmajor) {
-            D = 2 * dy - dx;
-            dmaj2 = 2 * dx;
-            dmin2 = 2 * dy;
-            steps = dx;
-        } else {
-            D = 2 * dx - dy;
-            dmaj2 = 2 * dy;
-            dmin2 = 2 * dx;
-            steps = dy;
-        }
+        const int dmaj = xmajor ? dx : dy, dmin = xmajor ? dy : dx;
+        D = 2 * dmin - dmaj;
+        dmaj2 = 2 * dmaj;
+        dmin2 = 2 * dmin;
+        steps = dmaj;
+        mx = xmajor ? sx : 0;
+        my = xmajor ? 0 : sy;
+        nx = xmajor ? 0 : sx;
+        ny = xmajor ? sy : 0;
     }
     // Moves from the start cell directly to the cell after i steps.  With
     // dmaj = |major extent| and dmin = |minor extent|, the minor offset after
@@ -107,26 +107,17 @@ struct LineWalk {
         if (i <= 0 || dmaj == 0) return;
         const int64_t m = (2 * (int64_t)i * dmin + dmaj - 1) / (2 * dmaj);
         D = (int)(2 * dmin * ((int64_t)i + 1) - dmaj - 2 * dmaj * m);
-        if (xmajor) {
-            x += sx * i;
-            y += sy * (int)m;
-        } else {
-            y += sy * i;
-            x += sx * (int)m;
-        }
+        x += mx * i + nx * (int)m;
+        y += my * i + ny * (int)m;
     }
     __device__ __forceinline__ void step()
     {
-        if (xmajor) {
-            if (D > 0) { y += sy; D -= dmaj2; }
-            D += dmin2;
-            x += sx;
-        } else {
-            if (D > 0) { x += sx; D -= dmaj2; }
-            D += dmin2;
-            y += sy;
-        }
+        const bool c = D > 0;
+        x += mx + (c ? nx : 0);
+        y += my + (c ? ny : 0);
+        D += dmin2 - (c ? dmaj2 : 0);
     }
+    __device__ __forceinline__ int major() const { return xmajor ? x : y; }
 };
 
 // Height of the ray s -> p above the cell whose absolute major-axis lattice
@@ -186,8 +177,7 @@ __device__ __forceinline__ int walk_cells(const Grid& g, Ray& r, const float* __
                                 (r.L.x >= 0 && r.L.x < g.W && r.L.y >= 0 && r.L.y < g.H);
                 if (in) {
                     st[u] = storage_index(g, r.L.x, r.L.y);
-                    zr[u] = ray_height(r.o_major + (r.L.xmajor ? r.L.x : r.L.y), g.res, r.s_major,
-                                       r.inv_d, r.s_z, r.dz);
+                    zr[u] = ray_height(r.o_major + r.L.major(), g.res, r.s_major, r.inv_d, r.s_z, r.dz);
                 }
             }
         }
@@ -220,6 +210,105 @@ __device__ __forceinline__ int walk_range(const Grid& g, Ray& r, const float* __
     const int n = walk_cells<U>(g, r, h, visit);
     r.L.steps = steps;
     return n;
+}
+
+// Largest entry of a block-max table (blocks of side 1 << shift) over the
+// blocks that the logical cells between (x0, y0) and (x1, y1) (inclusive,
+// either order, clamped to the grid) fall in; -inf if none is inside.
+__device__ __forceinline__ float box_max(const Grid& g, const float* __restrict__ t, int tw, int shift, int x0,
+                                         int y0, int x1, int y1)
+{
+    const int xa = max(min(x0, x1), 0), xb = min(max(x0, x1), g.W - 1);
+    const int ya = max(min(y0, y1), 0), yb = min(max(y0, y1), g.H - 1);
+    float m = -__builtin_inff();
+    if (xa > xb || ya > yb) return m;
+    for (int ty = ya >> shift; ty <= (yb >> shift); ty++)
+        for (int tx = xa >> shift; tx <= (xb >> shift); tx++) m = fmaxf(m, t[ty * tw + tx]);
+    return m;
+}
+
+// Ray height above the cell the walk stands on.
+__device__ __forceinline__ float walk_height(const Grid& g, const Ray& r, const LineWalk& L)
+{
+    return ray_height(r.o_major + L.major(), g.res, r.s_major, r.inv_d, r.s_z, r.dz);
+}
+
+// walk_range with exact skipping.  The ray height is a composition of
+// monotone binary32 operations of the cell's major index, so along any run
+// of cells its smallest value is the one at an end of the run; a run whose
+// cells' largest height `hmax` (from the block maxima) cannot meet the
+// visit's condition at the lower of the two end heights is skipped without
+// loading a cell: skip(hmax, z_first, z_last) must return true only if no
+// cell with height <= hmax and ray height >= min(z_first, z_last) can make
+// visit act.  Runs are 64 cells (checked against blocks of 64) and then 8
+// cells (blocks of 8); the remaining cells are visited as walk_range does.
+// `r` must be at the start cell.  Returns the number of cells loaded.
+template <class Skip, class Visit>
+__device__ __forceinline__ int walk_range_skip(const Grid& g, const Ray& r, const float* __restrict__ h,
+                                               const TileMax& tm, int first, int count, Skip&& skip,
+                                               Visit&& visit)
+{
+    constexpr int U = 8;
+    const int end = first + count;  // one past the last intermediate cell
+    int i = first;
+    LineWalk L = r.L;
+    L.jump_from_start(i - 1);  // on the cell before `i`
+    int loaded = 0;
+    while (i < end) {
+        if (end - i >= 64) {
+            LineWalk A = L;
+            A.step();
+            LineWalk E = r.L;
+            E.jump_from_start(i + 63);
+            const float hm = box_max(g, tm.t64, tm.tw64, 6, A.x, A.y, E.x, E.y);
+            if (skip(hm, walk_height(g, r, A), walk_height(g, r, E))) {
+                L = E;
+                i += 64;
+                continue;
+            }
+        }
+        // up to U cells: positions and ray heights first, loads only if the
+        // run may matter
+        const int n = min(U, end - i);
+        int st[U];
+        float zr[U];
+        int x0 = 0, y0 = 0, x1 = 0, y1 = 0;
+        float z0 = 0.0f, z1 = 0.0f;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            st[u] = -1;
+            zr[u] = 0.0f;
+            if (u < n) {
+                L.step();
+                zr[u] = walk_height(g, r, L);
+                if (u == 0) {
+                    x0 = L.x;
+                    y0 = L.y;
+                    z0 = zr[u];
+                }
+                x1 = L.x;
+                y1 = L.y;
+                z1 = zr[u];
+                const bool in = r.all_inside || (L.x >= 0 && L.x < g.W && L.y >= 0 && L.y < g.H);
+                if (in) st[u] = storage_index(g, L.x, L.y);
+            }
+        }
+        i += n;
+        if (skip(box_max(g, tm.t8, tm.tw8, 3, x0, y0, x1, y1), z0, z1)) continue;
+        float hk[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) hk[u] = st[u] >= 0 ? h[st[u]] : __builtin_nanf("");
+        bool stop = false;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            if (st[u] >= 0) {
+                loaded++;
+                if (!stop && visit(st[u], hk[u], zr[u])) stop = true;
+            }
+        }
+        if (stop) break;
+    }
+    return loaded;
 }
 
 }  // namespace memk

@@ -132,8 +132,8 @@ __global__ __launch_bounds__(kBatchWG) void k_b_march(BatchDev d, const float* _
         for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x)
             visited += march_point(m.g, xyz, i, m.T, mr2, margin, d.h + m.cell_off, d.clr + m.cell_off);
     }
-    const int ids[1] = {ST_RAY_CELLS};
-    int vals[1] = {visited};
+    const int ids[2] = {ST_RAY_CELLS, ST_RAY_STEPS};  // every cell of a ray is loaded here
+    int vals[2] = {visited, visited};
     block_stats(d.stats, ids, vals);
 }
 
@@ -189,8 +189,8 @@ __global__ __launch_bounds__(kBatchWG) void k_b_project(BatchDev d, int tile)
         const int64_t off = d.maps[map].cell_off;
         append_pair(vis, (int)off + st, code[0], d.pairs + off, &d.pair_count[map]);
     }
-    const int ids[3] = {ST_IN_VIEW, ST_VISIBLE, ST_OCCL_CELLS};
-    int vals[3] = {in_view_all, vis_all, visited};
+    const int ids[4] = {ST_IN_VIEW, ST_VISIBLE, ST_OCCL_CELLS, ST_OCCL_STEPS};
+    int vals[4] = {in_view_all, vis_all, visited, visited};
     block_stats(d.stats, ids, vals);
 }
 

@@ -1,14 +1,19 @@
 // k_image.hip - image path of the map update (Sec. III-B, Fig. 3), one map.
 //
-//   k_project      one lane per cell (16x16 cell tiles, so neighbouring rays
-//                  share the cells they walk): frustum test and pin-hole pixel
-//                  of every image of one camera pose, one Bresenham occlusion
-//                  walk against the map heights, and a wave-aggregated append
-//                  of visible (cell, pixel) pairs per image.
-//   k_gather_fuse  grid-stride over one image's visible pairs; a group of
-//                  lanes (a power of two >= the layer's channels, at most 64)
-//                  reads one pixel's channels and read-modify-writes the
-//                  cell's channel-contiguous layer row with the layer's rule.
+//   k_view         one lane per cell (16x16 cell tiles): frustum test and
+//                  pin-hole pixel of every image of one camera pose; cells
+//                  inside any view are compacted into a list with one
+//                  wave-aggregated append.
+//   k_occlude      kOccLanes lanes per listed cell split its Bresenham
+//                  occlusion line; runs of cells that the block maxima of the
+//                  heights rule out are skipped without loading them, the
+//                  others are tested cell by cell; an occluded cell's pixel
+//                  codes are overwritten with -1 in place (no atomics).
+//   k_gather_fuse  grid-stride over the listed cells; for those visible in
+//                  the image a group of lanes (a power of two >= the layer's
+//                  channels, at most 64) reads the pixel's channels and
+//                  read-modify-writes the cell's channel-contiguous layer row
+//                  with the layer's rule.
 #include "update.h"
 
 namespace memk {
@@ -16,35 +21,6 @@ namespace memk {
 namespace {
 
 constexpr int kTile = 16;
-
-// Image k's visible pairs go to pairs[k * cap ...] and their number to
-// count[k].  dbg (optional) receives image 0's code per logical cell.
-__global__ __launch_bounds__(256) void k_project(Grid g, Camera cam, const float* __restrict__ h,
-                                                 int2* __restrict__ pairs, int cap,
-                                                 int* __restrict__ count, int32_t* __restrict__ dbg,
-                                                 unsigned long long* __restrict__ stats)
-{
-    const int ix = blockIdx.x * kTile + threadIdx.x;
-    const int iy = blockIdx.y * kTile + threadIdx.y;
-    int code[kMaxImages];
-#pragma unroll
-    for (int k = 0; k < kMaxImages; k++) code[k] = -1;
-    int st = 0, visited = 0, in_view = 0, n_vis = 0;
-    if (ix < g.W && iy < g.H) {
-        st = storage_index(g, ix, iy);
-        visited = project_cell(g, cam, h, ix, iy, st, code, in_view);
-    }
-#pragma unroll
-    for (int k = 0; k < kMaxImages; k++) {
-        if (k >= cam.n) break;
-        n_vis += code[k] >= 0 ? 1 : 0;
-        append_pair(code[k] >= 0, st, code[k], pairs + (int64_t)k * cap, &count[k]);
-    }
-    if (dbg && ix < g.W && iy < g.H) dbg[iy * g.W + ix] = code[0];
-    const int ids[3] = {ST_IN_VIEW, ST_VISIBLE, ST_OCCL_CELLS};
-    int vals[3] = {in_view, n_vis, visited};
-    block_stats(stats, ids, vals);
-}
 
 // Pass 1 of the two-pass projection: frustum test and pixel of every image
 // per cell; cells inside at least one view are appended to vlist
@@ -70,21 +46,27 @@ __global__ __launch_bounds__(256) void k_view(Grid g, Camera cam, const float* _
             steps = max(abs(ix - ax), abs(iy - ay)) - 1;
         }
     }
+    // one global atomic per workgroup: lanes rank within the wave, waves
+    // within the workgroup (LDS), the workgroup within the list
+    __shared__ int s_cnt, s_base;
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    if (tid == 0) s_cnt = 0;
+    __syncthreads();
     const bool any = in_view > 0;
     const unsigned long long mask = __ballot(any);
-    if (mask) {
-        const int lane = __lane_id();
-        const int leader = __ffsll((long long)mask) - 1;
-        int base = 0;
-        if (lane == leader) base = atomicAdd(vcount, __popcll(mask));
-        base = __shfl(base, leader);
-        if (any) {
-            const int pos = base + __popcll(mask & ((1ull << lane) - 1ull));
-            vlist[pos] = make_int4(st, ix, iy, steps > 0 ? steps : 0);
+    const int lane = __lane_id();
+    int woff = 0;
+    if (lane == 0 && mask) woff = atomicAdd(&s_cnt, __popcll(mask));
+    woff = __shfl(woff, 0);
+    __syncthreads();
+    if (tid == 0) s_base = s_cnt ? atomicAdd(vcount, s_cnt) : 0;
+    __syncthreads();
+    if (any) {
+        const int pos = s_base + woff + __popcll(mask & ((1ull << lane) - 1ull));
+        vlist[pos] = make_int4(st, ix, iy, steps > 0 ? steps : 0);
 #pragma unroll
-            for (int k = 0; k < kMaxImages; k++)
-                if (k < cam.n) vcode[(int64_t)k * cap + pos] = code[k];
-        }
+        for (int k = 0; k < kMaxImages; k++)
+            if (k < cam.n) vcode[(int64_t)k * cap + pos] = code[k];
     }
     if (dbg && ix < g.W && iy < g.H && !any) dbg[iy * g.W + ix] = code[0];
     const int ids[1] = {ST_IN_VIEW};
@@ -98,11 +80,10 @@ __global__ __launch_bounds__(256) void k_view(Grid g, Camera cam, const float* _
 // pair list in which it lies inside the view.
 constexpr int kOccLanes = 8;
 
-__global__ __launch_bounds__(256) void k_occlude(Grid g, Camera cam, const float* __restrict__ h,
+__global__ __launch_bounds__(256) void k_occlude(Grid g, Camera cam, const float* __restrict__ h, TileMax tm,
                                                  const int4* __restrict__ vlist,
-                                                 const int* __restrict__ vcode, int cap,
+                                                 int* __restrict__ vcode, int cap,
                                                  const int* __restrict__ vcount,
-                                                 int2* __restrict__ pairs, int* __restrict__ count,
                                                  int32_t* __restrict__ dbg,
                                                  unsigned long long* __restrict__ stats)
 {
@@ -114,7 +95,7 @@ __global__ __launch_bounds__(256) void k_occlude(Grid g, Camera cam, const float
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const int per_wave = 64 / kOccLanes;
     const float* T = cam.T.m;
-    int visited = 0, n_vis = 0;
+    int visited = 0, n_vis = 0, steps = 0;
     for (int64_t base = wave * per_wave; base < N; base += nwaves * per_wave) {
         const int64_t pos = base + grp;
         bool occ = false;
@@ -131,36 +112,43 @@ __global__ __launch_bounds__(256) void k_occlude(Grid g, Camera cam, const float
                 const float yc = ((float)(g.oy + e.z) + 0.5f) * g.res;
                 int ax, ay;
                 lattice_cell(g, T[3], T[7], ax, ay);
-                Ray ray(g, ax, ay, e.y, e.z, T[3], T[7], T[11], xc, yc, hj);
-                visited += walk_range<8>(g, ray, h, first, cnt, [&](int, float hk, float zr) {
-                    if (hk >= zr) occ = true;  // NaN (no height) never occludes
-                    return occ;
-                });
+                const Ray ray(g, ax, ay, e.y, e.z, T[3], T[7], T[11], xc, yc, hj);
+                steps += cnt;
+                visited += walk_range_skip(
+                    g, ray, h, tm, first, cnt, [&](float hm, float z0, float z1) { return hm < fminf(z0, z1); },
+                    [&](int, float hk, float zr) {
+                        if (hk >= zr) occ = true;  // NaN (no height) never occludes
+                        return occ;
+                    });
             }
         }
         const unsigned long long om = __ballot(occ);
         const bool occluded = ((om >> (grp * kOccLanes)) & ((1ull << kOccLanes) - 1ull)) != 0;
         const bool lead = sub == 0 && pos < N;
-#pragma unroll
-        for (int k = 0; k < kMaxImages; k++) {
-            if (k >= cam.n) break;
-            const int code = lead ? vcode[(int64_t)k * cap + pos] : -1;
-            const bool vis = lead && !occluded && code >= 0;
-            n_vis += vis ? 1 : 0;
-            append_pair(vis, e.x, code, pairs + (int64_t)k * cap, &count[k]);
-        }
-        if (dbg && lead) {
+        if (lead) {
             const int c0 = vcode[pos];
-            dbg[e.z * g.W + e.y] = (c0 >= 0 && occluded) ? -3 : c0;
+#pragma unroll
+            for (int k = 0; k < kMaxImages; k++) {
+                if (k >= cam.n) break;
+                const int64_t q = (int64_t)k * cap + pos;
+                const int code = k == 0 ? c0 : vcode[q];
+                if (code < 0) continue;
+                if (occluded)
+                    vcode[q] = -1;
+                else
+                    n_vis++;
+            }
+            if (dbg) dbg[e.z * g.W + e.y] = (c0 >= 0 && occluded) ? -3 : c0;
         }
     }
-    const int ids[2] = {ST_VISIBLE, ST_OCCL_CELLS};
-    int vals[2] = {n_vis, visited};
+    const int ids[3] = {ST_VISIBLE, ST_OCCL_CELLS, ST_OCCL_STEPS};
+    int vals[3] = {n_vis, visited, steps};
     block_stats(stats, ids, vals);
 }
 
 template <int IMG, int S>
-__global__ __launch_bounds__(256) void k_gather_fuse(const int2* __restrict__ pairs,
+__global__ __launch_bounds__(256) void k_gather_fuse(const int4* __restrict__ vlist,
+                                                     const int* __restrict__ vcode,
                                                      const int* __restrict__ count,
                                                      const void* __restrict__ img, int64_t s0,
                                                      int64_t s1, int64_t s2, int w, int ch_first,
@@ -176,7 +164,8 @@ __global__ __launch_bounds__(256) void k_gather_fuse(const int2* __restrict__ pa
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t pbase = wave * ppw; pbase < N; pbase += nwaves * ppw) {
         const int64_t p = pbase + sub;
-        if (p < N) gather_pair<IMG, S>(pairs[p], img, s0, s1, s2, w, ch_first, L, q0, LPP);
+        const int code = p < N ? vcode[p] : -1;
+        if (code >= 0) gather_pair<IMG, S>(make_int2(vlist[p].x, code), img, s0, s1, s2, w, ch_first, L, q0, LPP);
     }
 }
 
@@ -193,21 +182,20 @@ void launch_zero_int(hipStream_t s, int* p, int n)
     hipLaunchKernelGGL(k_zero_int, dim3((n + 63) / 64), dim3(64), 0, s, p, n);
 }
 
-void launch_project(hipStream_t s, const Grid& g, const Camera& cam, const float* h, int2* pairs,
-                    int cap, int* count, int4* vlist, int* vcode, int32_t* dbg,
-                    unsigned long long* stats)
+void launch_project(hipStream_t s, const Grid& g, const Camera& cam, const float* h, const TileMax& tm, int cap,
+                    int* vcount, int4* vlist, int* vcode, int32_t* dbg, unsigned long long* stats)
 {
     dim3 grid((g.W + kTile - 1) / kTile, (g.H + kTile - 1) / kTile);
-    hipLaunchKernelGGL(k_view, grid, dim3(kTile, kTile), 0, s, g, cam, h, vlist, vcode, cap,
-                       count + kMaxImages, dbg, stats);
+    hipLaunchKernelGGL(k_view, grid, dim3(kTile, kTile), 0, s, g, cam, h, vlist, vcode, cap, vcount, dbg,
+                       stats);
     int64_t blocks = ((int64_t)cap * kOccLanes + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_occlude, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, h, vlist, vcode, cap,
-                       count + kMaxImages, pairs, count, dbg, stats);
+    hipLaunchKernelGGL(k_occlude, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, h, tm, vlist, vcode, cap,
+                       vcount, dbg, stats);
 }
 
-void launch_gather_fuse(hipStream_t s, const int2* pairs, const int* count, int max_pairs,
+void launch_gather_fuse(hipStream_t s, const int4* vlist, const int* vcode, const int* count, int max_pairs,
                         const void* img, int img_dtype, int64_t s0, int64_t s1, int64_t s2, int w,
                         int ch_first, const LayerDev& L)
 {
@@ -220,7 +208,8 @@ void launch_gather_fuse(hipStream_t s, const int2* pairs, const int* count, int 
     if (blocks < 1) blocks = 1;
     dim3 gr((unsigned)blocks), bl(256);
 #define MEM_GF(IMG, S) \
-    hipLaunchKernelGGL((k_gather_fuse<IMG, S>), gr, bl, 0, s, pairs, count, img, s0, s1, s2, w, ch_first, L, lpp_log2)
+    hipLaunchKernelGGL((k_gather_fuse<IMG, S>), gr, bl, 0, s, vlist, vcode, count, img, s0, s1, s2, w, ch_first, \
+                       L, lpp_log2)
     if (img_dtype == MEM_U8) {
         if (L.storage == MEM_BF16) MEM_GF(MEM_U8, MEM_BF16);
         else if (L.storage == MEM_FP8_E4M3) MEM_GF(MEM_U8, MEM_FP8_E4M3);

@@ -66,17 +66,94 @@ __global__ __launch_bounds__(kWG) void k_ingest(Grid g, const float* __restrict_
     block_stats(stats, ids, vals);
 }
 
+// One ray per lane.  Scan order puts rays of very different lengths side by
+// side (the beams of one LiDAR firing), and a wave runs as long as its
+// longest ray, so the workgroup first sorts its 256 rays by length (bitonic
+// sort in LDS) and each wave walks 64 rays of similar length; neighbouring
+// points stay in one workgroup, so the walks still share cache lines.
 __global__ __launch_bounds__(256) void k_clear_march(Grid g, const float* __restrict__ xyz,
                                                      int64_t n, Pose T, float mr2, float margin,
                                                      const float* __restrict__ h,
                                                      int* __restrict__ clr,
                                                      unsigned long long* __restrict__ stats)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int visited = (i < n) ? march_point(g, xyz, i, T, mr2, margin, h, clr) : 0;
-    const int ids[1] = {ST_RAY_CELLS};
-    int vals[1] = {visited};
+    __shared__ uint32_t s_key[256];  // (intermediate cells << 8) | thread
+    __shared__ float4 s_pt[256];
+    __shared__ int2 s_cell[256];
+    const int t = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * 256 + t;
+    float px = 0.f, py = 0.f, pz = 0.f, r2;
+    int ix = 0, iy = 0, steps = 0;
+    const float sx = T.m[3], sy = T.m[7], sz = T.m[11];
+    int ax, ay;
+    lattice_cell(g, sx, sy, ax, ay);
+    if (i < n && point_cell(g, T, mr2, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], px, py, pz, r2, ix, iy) == 0)
+        steps = max(max(abs(ix - ax), abs(iy - ay)) - 1, 0);
+    s_key[t] = ((uint32_t)min(steps, 0xffffff) << 8) | (uint32_t)t;
+    s_pt[t] = make_float4(px, py, pz, 0.f);
+    s_cell[t] = make_int2(ix, iy);
+    __syncthreads();
+    for (int k = 2; k <= 256; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const int o = t ^ j;
+            if (o > t) {
+                const uint32_t a = s_key[t], b = s_key[o];
+                if ((a > b) == ((t & k) == 0)) {
+                    s_key[t] = b;
+                    s_key[o] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const int src = (int)(s_key[t] & 255u);
+    const int my_steps = (int)(s_key[t] >> 8);
+    int visited = 0;
+    if (my_steps > 0) {
+        const float4 p = s_pt[src];
+        const int2 c = s_cell[src];
+        Ray ray(g, ax, ay, c.x, c.y, sx, sy, sz, p.x, p.y, p.z);
+        visited = walk_cells<8>(g, ray, h, [&](int st, float hk, float zr) {
+            float thr = zr + margin;
+            if (hk > thr) atomicAdd(&clr[st], 1);  // NaN (no height) never votes
+            return false;
+        });
+    }
+    const int ids[2] = {ST_RAY_CELLS, ST_RAY_STEPS};
+    int vals[2] = {visited, steps};
     block_stats(stats, ids, vals);
+}
+
+// Block maxima of the height layer over logical cells: one wave per 8x8
+// block (lane = cell), then one wave per 64x64 block over its 8x8 maxima.
+__global__ __launch_bounds__(256) void k_tile_max8(Grid g, const float* __restrict__ h, float* __restrict__ t8,
+                                                   int tw, int th)
+{
+    const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (tile >= tw * th) return;  // whole waves leave together
+    const int tx = tile % tw, ty = tile / tw;
+    const int x = tx * 8 + (lane & 7), y = ty * 8 + (lane >> 3);
+    float v = -__builtin_inff();
+    if (x < g.W && y < g.H) v = fmaxf(v, h[storage_index(g, x, y)]);  // NaN (no height) drops out
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    if (lane == 0) t8[tile] = v;
+}
+
+__global__ __launch_bounds__(256) void k_tile_max64(const float* __restrict__ t8, int tw8, int th8,
+                                                    float* __restrict__ t64, int tw, int th)
+{
+    const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (tile >= tw * th) return;
+    const int tx = tile % tw, ty = tile / tw;
+    const int x = tx * 8 + (lane & 7), y = ty * 8 + (lane >> 3);
+    float v = -__builtin_inff();
+    if (x < tw8 && y < th8) v = t8[y * tw8 + x];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    if (lane == 0) t64[tile] = v;
 }
 
 __global__ __launch_bounds__(256) void k_finalize(Grid g, Accum acc, int clear_min,
@@ -137,12 +214,32 @@ void launch_ingest(hipStream_t s, const Grid& g, const float* xyz, int64_t n, co
 }
 
 void launch_clear_march(hipStream_t s, const Grid& g, const float* xyz, int64_t n, const Pose& T,
-                        float mr2, float margin, const float* h, int* clr,
-                        unsigned long long* stats)
+                        float mr2, float margin, const float* h, int* clr, unsigned long long* stats)
 {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_clear_march, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, xyz, n, T, mr2,
-                       margin, h, clr, stats);
+    hipLaunchKernelGGL(k_clear_march, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, xyz, n, T, mr2, margin, h,
+                       clr, stats);
+}
+
+TileMax tile_max_dims(const Grid& g, const float* t8, const float* t64)
+{
+    TileMax tm;
+    tm.t8 = t8;
+    tm.t64 = t64;
+    tm.tw8 = (g.W + 7) / 8;
+    tm.th8 = (g.H + 7) / 8;
+    tm.tw64 = (g.W + 63) / 64;
+    tm.th64 = (g.H + 63) / 64;
+    return tm;
+}
+
+void launch_tile_max(hipStream_t s, const Grid& g, const float* h, float* t8, float* t64)
+{
+    const TileMax tm = tile_max_dims(g, t8, t64);
+    const int n8 = tm.tw8 * tm.th8, n64 = tm.tw64 * tm.th64;
+    hipLaunchKernelGGL(k_tile_max8, dim3((n8 + 3) / 4), dim3(256), 0, s, g, h, t8, tm.tw8, tm.th8);
+    hipLaunchKernelGGL(k_tile_max64, dim3((n64 + 3) / 4), dim3(256), 0, s, t8, tm.tw8, tm.th8, t64, tm.tw64,
+                       tm.th64);
 }
 
 void launch_finalize(hipStream_t s, const Grid& g, const int* cnt, const float* wsum,

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "mem_internal.h"
+#include "prof.h"
 
 using namespace memk;
 
@@ -69,10 +70,6 @@ struct Layer {
     }
 };
 
-struct ProfRec {
-    const char* name;
-    hipEvent_t a, b;
-};
 
 size_t elem_size(int storage)
 {
@@ -98,19 +95,30 @@ struct mem_map {
     float* wsum = nullptr;
     float* ssum = nullptr;
     float2* stash = nullptr;
-    int2* pairs = nullptr;
-    int* pair_count = nullptr;  // [kMaxImages] pair counts, then the in-view count
+    int* vcount = nullptr;      // cells listed in vlist
     int4* vlist = nullptr;      // cells inside a camera's view
+    float* tmax = nullptr;      // block maxima of h: side 8, then side 64
     int* vcode = nullptr;       // their pixel per image
     unsigned long long* stats = nullptr;
     float* chsum = nullptr;
     int chsum_planes = 0;
     std::vector<Layer> layers;
 
-    bool prof = false;
-    std::vector<ProfRec> pending;
-    std::vector<hipEvent_t> pool;
-    std::map<std::string, std::pair<int64_t, double>> totals;
+    Profiler prof;
+
+    // Block maxima of the heights for the exact skipping of ray walks.
+    int64_t tmax_size() const
+    {
+        const int64_t n8 = (int64_t)((W + 7) / 8) * ((H + 7) / 8);
+        return n8 + (int64_t)((W + 63) / 64) * ((H + 63) / 64);
+    }
+    TileMax tiles(hipStream_t s) const
+    {
+        const Grid g = grid();
+        const int64_t n8 = (int64_t)((W + 7) / 8) * ((H + 7) / 8);
+        launch_tile_max(s, g, h, tmax, tmax + n8);
+        return tile_max_dims(g, tmax, tmax + n8);
+    }
 
     Grid grid() const
     {
@@ -149,48 +157,11 @@ mem_status check_launch(mem_map* m, const char* what)
     return MEM_OK;
 }
 
-hipEvent_t pool_get(mem_map* m)
-{
-    if (!m->pool.empty()) {
-        hipEvent_t e = m->pool.back();
-        m->pool.pop_back();
-        return e;
-    }
-    hipEvent_t e = nullptr;
-    (void)hipEventCreate(&e);
-    return e;
-}
-
-void prof_drain(mem_map* m)
-{
-    if (m->pending.empty()) return;
-    (void)hipEventSynchronize(m->pending.back().b);
-    for (auto& r : m->pending) {
-        float ms = 0.0f;
-        (void)hipEventElapsedTime(&ms, r.a, r.b);
-        auto& t = m->totals[r.name];
-        t.first += 1;
-        t.second += ms;
-        m->pool.push_back(r.a);
-        m->pool.push_back(r.b);
-    }
-    m->pending.clear();
-}
-
 // Runs a launcher, bracketed by events on `s` while profiling is on.
 template <class F>
 void timed(mem_map* m, hipStream_t s, const char* name, F&& f)
 {
-    if (!m->prof) {
-        f();
-        return;
-    }
-    hipEvent_t a = pool_get(m), b = pool_get(m);
-    (void)hipEventRecord(a, s);
-    f();
-    (void)hipEventRecord(b, s);
-    m->pending.push_back({name, a, b});
-    if (m->pending.size() >= 8192) prof_drain(m);
+    m->prof.timed(s, name, f);
 }
 
 mem_status usable(const mem_map* m)
@@ -257,10 +228,10 @@ void free_map(mem_map* m)
     (void)hipFree(m->wsum);
     (void)hipFree(m->ssum);
     (void)hipFree(m->stash);
-    (void)hipFree(m->pairs);
-    (void)hipFree(m->pair_count);
+    (void)hipFree(m->vcount);
     (void)hipFree(m->vlist);
     (void)hipFree(m->vcode);
+    (void)hipFree(m->tmax);
     (void)hipFree(m->stats);
     (void)hipFree(m->chsum);
     for (auto& L : m->layers) {
@@ -268,11 +239,7 @@ void free_map(mem_map* m)
         (void)hipFree(L.var);
         (void)hipFree(L.scale);
     }
-    for (auto& r : m->pending) {
-        (void)hipEventDestroy(r.a);
-        (void)hipEventDestroy(r.b);
-    }
-    for (auto e : m->pool) (void)hipEventDestroy(e);
+    m->prof.release();
     delete m;
 }
 
@@ -352,9 +319,9 @@ mem_status mem_create(const mem_params* p, void* stream, mem_map** out)
     if ((st = dev_alloc(m, &m->h, HW)) || (st = dev_alloc(m, &m->v, HW)) ||
         (st = dev_alloc(m, &m->cnt, HW)) || (st = dev_alloc(m, &m->clr, HW)) ||
         (st = dev_alloc(m, &m->wsum, HW)) || (st = dev_alloc(m, &m->ssum, HW)) ||
-        (st = dev_alloc(m, &m->stash, HW)) || (st = dev_alloc(m, &m->pairs, HW * kMaxImages)) ||
+        (st = dev_alloc(m, &m->stash, HW)) ||
         (st = dev_alloc(m, &m->vlist, HW)) || (st = dev_alloc(m, &m->vcode, HW * kMaxImages)) ||
-        (st = dev_alloc(m, &m->pair_count, kMaxImages + 1)) ||
+        (st = dev_alloc(m, &m->vcount, 1)) || (st = dev_alloc(m, &m->tmax, m->tmax_size())) ||
         (st = dev_alloc(m, &m->stats, kStats * kStatSlots))) {
         free_map(m);
         return st;
@@ -388,7 +355,7 @@ mem_status mem_create(const mem_params* p, void* stream, mem_map** out)
     launch_reset_rect(s, g, 0, m->W, 0, m->H, m->h, m->v, m->cnt, m->clr, devs.data(), (int)devs.size());
     launch_zero_accum(s, g, m->cnt, m->wsum, m->ssum, m->clr, nullptr, 0);
     launch_zero_int(s, (int*)m->stats, 2 * kStats * kStatSlots);
-    launch_zero_int(s, m->pair_count, kMaxImages + 1);
+    launch_zero_int(s, m->vcount, 1);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
@@ -500,7 +467,7 @@ mem_status mem_input_pointcloud(mem_map* m, const float* xyz, int64_t n, const f
         launch_ingest(s, g, xyz, n, ch, T, m->c0, m->c1, m->mr2, pb, m->cnt, m->wsum, m->ssum, m->stash,
                       m->chsum, m->stats);
     });
-    if (m->clear_min > 0)
+    if (m->clear_min > 0 && n > 0)
         timed(m, s, "clear_march", [&] {
             launch_clear_march(s, g, xyz, n, T, m->mr2, m->clear_margin, m->h, m->clr, m->stats);
         });
@@ -564,10 +531,11 @@ mem_status mem_input_images(mem_map* m, const mem_image* images, int32_t n_image
     hipStream_t s = (hipStream_t)stream;
     Grid g = m->grid();
     const int cap = (int)m->cells();
-    timed(m, s, "zero_count", [&] { launch_zero_int(s, m->pair_count, kMaxImages + 1); });
+    timed(m, s, "zero_count", [&] { launch_zero_int(s, m->vcount, 1); });
+    TileMax tm;
+    timed(m, s, "tile_max", [&] { tm = m->tiles(s); });
     timed(m, s, "project", [&] {
-        launch_project(s, g, cam, m->h, m->pairs, cap, m->pair_count, m->vlist, m->vcode, nullptr,
-                       m->stats);
+        launch_project(s, g, cam, m->h, tm, cap, m->vcount, m->vlist, m->vcode, nullptr, m->stats);
     });
     for (int k = 0; k < n_images; k++) {
         const mem_image& im = images[k];
@@ -576,7 +544,7 @@ mem_status mem_input_images(mem_map* m, const mem_image* images, int32_t n_image
             resolve_layer(m, im.bind[b].layer, &L);
             LayerDev d = L->dev();
             timed(m, s, "gather_fuse", [&] {
-                launch_gather_fuse(s, m->pairs + (int64_t)k * cap, m->pair_count + k, cap, im.data,
+                launch_gather_fuse(s, m->vlist, m->vcode + (int64_t)k * cap, m->vcount, cap, im.data,
                                    im.dtype, im.strides[0], im.strides[1], im.strides[2], im.w,
                                    im.bind[b].ch_first, d);
             });
@@ -677,9 +645,9 @@ mem_status mem_debug_cell_pixels(const mem_map* mc, int32_t h, int32_t w, const 
     cam.n = 1;
     cam.min_depth = m->min_depth;
     hipStream_t s = (hipStream_t)stream;
-    launch_zero_int(s, m->pair_count, kMaxImages + 1);
-    launch_project(s, m->grid(), cam, m->h, m->pairs, (int)m->cells(), m->pair_count, m->vlist,
-                   m->vcode, out, m->stats);
+    launch_zero_int(s, m->vcount, 1);
+    const TileMax tm = m->tiles(s);
+    launch_project(s, m->grid(), cam, m->h, tm, (int)m->cells(), m->vcount, m->vlist, m->vcode, out, m->stats);
     return check_launch(m, "mem_debug_cell_pixels");
 }
 
@@ -708,8 +676,7 @@ mem_status mem_reset_stats(mem_map* m, void* stream)
 mem_status mem_profile_enable(mem_map* m, int32_t on)
 {
     if (mem_status st = usable(m)) return st;
-    if (!on) prof_drain(m);
-    m->prof = on != 0;
+    m->prof.enable(on != 0);
     return MEM_OK;
 }
 
@@ -717,19 +684,7 @@ mem_status mem_profile_read(mem_map* m, mem_kernel_time* out, int32_t max, int32
 {
     if (mem_status st = usable(m)) return st;
     if (!count || (max > 0 && !out)) return fail(MEM_E_ARG, "NULL output");
-    prof_drain(m);
-    int k = 0;
-    for (auto& kv : m->totals) {
-        if (k < max) {
-            memset(out[k].name, 0, sizeof out[k].name);
-            strncpy(out[k].name, kv.first.c_str(), sizeof out[k].name - 1);
-            out[k].launches = kv.second.first;
-            out[k].total_ms = kv.second.second;
-        }
-        k++;
-    }
-    *count = k;
-    m->totals.clear();
+    *count = m->prof.read(out, max);
     return MEM_OK;
 }
 

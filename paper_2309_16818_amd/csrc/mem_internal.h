@@ -28,7 +28,7 @@
 namespace memk {
 
 constexpr int kMaxBind = 8;
-constexpr int kStats = 11;  // device counters, order of mem_stats
+constexpr int kStats = 13;  // device counters, order of mem_stats
 // Device counters are [kStats][kStatSlots]: a workgroup adds into slot
 // (block id mod kStatSlots), so no single address sees more than
 // 1/kStatSlots of the atomics.
@@ -45,7 +45,9 @@ enum Stat {
     ST_RAY_CELLS,
     ST_IN_VIEW,
     ST_VISIBLE,
-    ST_OCCL_CELLS
+    ST_OCCL_CELLS,
+    ST_RAY_STEPS,
+    ST_OCCL_STEPS
 };
 
 // Grid geometry handed to every kernel.
@@ -54,6 +56,14 @@ struct Grid {
     int ox, oy;  // absolute lattice index of logical cell (0, 0)
     int rx, ry;  // toroidal offsets
     float res, inv_res;
+};
+
+// Largest height over square blocks of logical cells (-inf where no cell of
+// the block holds a height): side 8 in t8 ([th8][tw8]) and side 64 in t64.
+struct TileMax {
+    const float* t8;
+    const float* t64;
+    int tw8, th8, tw64, th64;
 };
 
 struct Pose {
@@ -107,8 +117,7 @@ void launch_ingest(hipStream_t s, const Grid& g, const float* xyz, int64_t n, co
                    float* wsum, float* ssum, float2* stash, float* chsum,
                    unsigned long long* stats);
 void launch_clear_march(hipStream_t s, const Grid& g, const float* xyz, int64_t n, const Pose& T,
-                        float mr2, float margin, const float* h, int* clr,
-                        unsigned long long* stats);
+                        float mr2, float margin, const float* h, int* clr, unsigned long long* stats);
 void launch_finalize(hipStream_t s, const Grid& g, const int* cnt, const float* wsum,
                      const float* ssum, const float2* stash, const int* clr, int clear_min,
                      float* h, float* v, const float* chsum, const PointBinds& pb,
@@ -117,14 +126,20 @@ void launch_point_cells(hipStream_t s, const Grid& g, const float* xyz, int64_t 
                         float mr2, int32_t* out);
 
 void launch_zero_int(hipStream_t s, int* p, int n);
-// Two passes: k_view compacts the cells inside any image's view into vlist
-// (cap entries) and vcode (kMaxImages x cap), k_occlude walks their
-// occlusion lines and appends visible pairs.  count: [kMaxImages] pair
-// counts followed by the in-view count, all zero on entry.
-void launch_project(hipStream_t s, const Grid& g, const Camera& cam, const float* h, int2* pairs,
-                    int cap, int* count, int4* vlist, int* vcode, int32_t* dbg,
-                    unsigned long long* stats);
-void launch_gather_fuse(hipStream_t s, const int2* pairs, const int* count, int max_pairs,
+// Block maxima of h (sizes from tile_max_dims: ceil(W/8) x ceil(H/8) and
+// ceil(W/64) x ceil(H/64) floats).
+TileMax tile_max_dims(const Grid& g, const float* t8, const float* t64);
+void launch_tile_max(hipStream_t s, const Grid& g, const float* h, float* t8, float* t64);
+// Two passes: k_view lists the cells inside any image's view in vlist
+// (st, ix, iy, intermediate cells of the occlusion line; *vcount entries, at
+// most cap) with their pixel codes in vcode[k * cap + position] (-1 outside
+// image k), k_occlude overwrites the codes of occluded cells with -1.
+// *vcount must be zero on entry.
+void launch_project(hipStream_t s, const Grid& g, const Camera& cam, const float* h, const TileMax& tm, int cap,
+                    int* vcount, int4* vlist, int* vcode, int32_t* dbg, unsigned long long* stats);
+// Fuses image channels into layer L for the listed cells whose code (image's
+// row of vcode) is >= 0.
+void launch_gather_fuse(hipStream_t s, const int4* vlist, const int* vcode, const int* count, int max_pairs,
                         const void* img, int img_dtype, int64_t s0, int64_t s1, int64_t s2, int w,
                         int ch_first, const LayerDev& L);
 

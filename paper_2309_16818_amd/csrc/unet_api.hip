@@ -17,6 +17,7 @@
 #include <cstring>
 #include <vector>
 
+#include "prof.h"
 #include "unet_internal.h"
 
 using namespace memk;
@@ -59,6 +60,7 @@ struct mem_unet {
     uint16_t *col = nullptr, *g1 = nullptr, *g2 = nullptr, *gch = nullptr;
     float *tmpf = nullptr, *de[4] = {}, *loss = nullptr;
     float* xin = nullptr;  // mem_complete input
+    memk::Profiler prof;
 };
 
 namespace {
@@ -120,6 +122,7 @@ bool ualloc(T** p, size_t n)
 
 void free_unet(mem_unet* u)
 {
+    u->prof.release();
     for (auto& Y : u->L) {
         (void)hipFree(Y.wf);
         (void)hipFree(Y.wd);
@@ -152,11 +155,11 @@ void relayout_all(mem_unet* u, hipStream_t s)
         if (Y.kind == 0) {
             (void)hipMemsetAsync(Y.wf, 0, sizeof(uint16_t) * (size_t)Y.co * Y.kf, s);
             (void)hipMemsetAsync(Y.wd, 0, sizeof(uint16_t) * (size_t)Y.ci * Y.kd, s);
-            unet_relayout(s, W, Y.taps, Y.ci, Y.co, 0, Y.kf, Y.wf);
-            unet_relayout(s, W, Y.taps, Y.ci, Y.co, 1, Y.kd, Y.wd);
+            u->prof.timed(s, "relayout", [&] { unet_relayout(s, W, Y.taps, Y.ci, Y.co, 0, Y.kf, Y.wf); });
+            u->prof.timed(s, "relayout", [&] { unet_relayout(s, W, Y.taps, Y.ci, Y.co, 1, Y.kd, Y.wd); });
         } else {
-            unet_relayout(s, W, Y.taps, Y.ci, Y.co, 2, 0, Y.wf);
-            unet_relayout(s, W, Y.taps, Y.ci, Y.co, 3, 0, Y.wd);
+            u->prof.timed(s, "relayout", [&] { unet_relayout(s, W, Y.taps, Y.ci, Y.co, 2, 0, Y.wf); });
+            u->prof.timed(s, "relayout", [&] { unet_relayout(s, W, Y.taps, Y.ci, Y.co, 3, 0, Y.wd); });
         }
     }
 }
@@ -167,9 +170,11 @@ void conv_fwd(mem_unet* u, hipStream_t s, int i, const uint16_t* x, int xs, int 
 {
     const ULayer& Y = u->L[i];
     const int S = u->S >> l;
-    unet_im2col3(s, x, xs, 0, B, S, Y.ci, u->col, Y.kf);
+    u->prof.timed(s, "im2col", [&] { unet_im2col3(s, x, xs, 0, B, S, Y.ci, u->col, Y.kf); });
     Epilogue ep{bias(u, u->w, i), 1, out, ldo, off, nullptr, 0, 0, 0};
-    unet_gemm_nt(s, EPI_STORE, u->col, Y.kf, Y.wf, Y.kf, (int)P_at(u, B, l), Y.co, Y.kf, ep);
+    u->prof.timed(s, "gemm_fwd", [&] {
+        unet_gemm_nt(s, EPI_STORE, u->col, Y.kf, Y.wf, Y.kf, (int)P_at(u, B, l), Y.co, Y.kf, ep);
+    });
 }
 
 void forward(mem_unet* u, hipStream_t s, int B)
@@ -182,7 +187,9 @@ void forward(mem_unet* u, hipStream_t s, int B)
         conv_fwd(u, s, 2 * l, in, ci_stride, B, l, u->a[l], c, 0);
         conv_fwd(u, s, 2 * l + 1, u->a[l], c, B, l, e_ptr(u, l), e_stride(u, l), 0);
         if (l < 3) {
-            unet_maxpool(s, e_ptr(u, l), e_stride(u, l), B, u->S >> l, c, u->p[l], u->arg[l]);
+            u->prof.timed(s, "pool", [&] {
+                unet_maxpool(s, e_ptr(u, l), e_stride(u, l), B, u->S >> l, c, u->p[l], u->arg[l]);
+            });
             in = u->p[l];
             ci_stride = c;
         }
@@ -192,7 +199,9 @@ void forward(mem_unet* u, hipStream_t s, int B)
         const int c = b << l, k = 8 + 3 * (2 - l);
         const ULayer& U = u->L[k];
         Epilogue ep{bias(u, u->w, k), 0, u->cat[l], 2 * c, 0, nullptr, 0, u->S >> (l + 1), c};
-        unet_gemm_nt(s, EPI_CONVT, below, U.ci, U.wf, U.ci, (int)P_at(u, B, l + 1), 4 * c, U.ci, ep);
+        u->prof.timed(s, "gemm_up", [&] {
+            unet_gemm_nt(s, EPI_CONVT, below, U.ci, U.wf, U.ci, (int)P_at(u, B, l + 1), 4 * c, U.ci, ep);
+        });
         conv_fwd(u, s, k + 1, u->cat[l], 2 * c, B, l, u->m[l], c, 0);
         conv_fwd(u, s, k + 2, u->m[l], c, B, l, u->d[l], c, 0);
         below = u->d[l];
@@ -209,13 +218,15 @@ void conv_bwd(mem_unet* u, hipStream_t s, int i, const uint16_t* x, int xs, int 
     const ULayer& Y = u->L[i];
     const int S = u->S >> l;
     const int P = (int)P_at(u, B, l);
-    unet_im2col3(s, x, xs, 0, B, S, Y.ci, u->col, Y.kf);
-    unet_gemm_tn(s, gy, Y.co, u->col, Y.kf, P, Y.co, Y.kf, Y.gbuf, Y.kf, u->n_cu);
-    unet_colsum(s, gy, Y.co, P, Y.co, bias(u, u->g, i));
+    u->prof.timed(s, "im2col", [&] { unet_im2col3(s, x, xs, 0, B, S, Y.ci, u->col, Y.kf); });
+    u->prof.timed(s, "gemm_wgrad", [&] {
+        unet_gemm_tn(s, gy, Y.co, u->col, Y.kf, P, Y.co, Y.kf, Y.gbuf, Y.kf, u->n_cu);
+    });
+    u->prof.timed(s, "colsum", [&] { unet_colsum(s, gy, Y.co, P, Y.co, bias(u, u->g, i)); });
     if (!dx) return;
-    unet_im2col3(s, gy, Y.co, 0, B, S, Y.co, u->col, Y.kd);
+    u->prof.timed(s, "im2col", [&] { unet_im2col3(s, gy, Y.co, 0, B, S, Y.co, u->col, Y.kd); });
     Epilogue ep{nullptr, 0, nullptr, 0, 0, dx, Y.ci, 0, 0};
-    unet_gemm_nt(s, EPI_F32, u->col, Y.kd, Y.wd, Y.kd, P, Y.ci, Y.kd, ep);
+    u->prof.timed(s, "gemm_dgrad", [&] { unet_gemm_nt(s, EPI_F32, u->col, Y.kd, Y.wd, Y.kd, P, Y.ci, Y.kd, ep); });
 }
 
 // Loss gradient of every parameter into u->g (flat), loss into u->loss.
@@ -224,16 +235,19 @@ void backward(mem_unet* u, hipStream_t s, int B, const float* target, const floa
     const int b = u->base;
     for (int i = 0; i < NLAY; i++) {
         const ULayer& Y = u->L[i];
-        if (Y.kind == 0) unet_fill(s, Y.gbuf, (int64_t)Y.co * Y.kf, 0.f);
-        if (Y.kind == 2) unet_fill(s, Y.gbuf, (int64_t)4 * Y.co * Y.ci, 0.f);
+        if (Y.kind == 0) u->prof.timed(s, "fill", [&] { unet_fill(s, Y.gbuf, (int64_t)Y.co * Y.kf, 0.f); });
+        if (Y.kind == 2) u->prof.timed(s, "fill", [&] { unet_fill(s, Y.gbuf, (int64_t)4 * Y.co * Y.ci, 0.f); });
     }
-    unet_fill(s, u->g, u->n_params, 0.f);
-    for (int l = 0; l < 4; l++) unet_fill(s, u->de[l], P_at(u, B, l) * (b << l), 0.f);
-    unet_fill(s, u->loss, 1, 0.f);
+    u->prof.timed(s, "fill", [&] { unet_fill(s, u->g, u->n_params, 0.f); });
+    for (int l = 0; l < 4; l++)
+        u->prof.timed(s, "fill", [&] { unet_fill(s, u->de[l], P_at(u, B, l) * (b << l), 0.f); });
+    u->prof.timed(s, "fill", [&] { unet_fill(s, u->loss, 1, 0.f); });
     const int H = NLAY - 1;
     const int64_t P0 = P_at(u, B, 0);
-    unet_head_loss(s, u->d[0], b, P0, u->w + u->L[H].off, bias(u, u->w, H), target, mask, inv_count, u->out,
-                   u->loss, u->g + u->L[H].off, bias(u, u->g, H), u->g1);
+    u->prof.timed(s, "head", [&] {
+        unet_head_loss(s, u->d[0], b, P0, u->w + u->L[H].off, bias(u, u->w, H), target, mask, inv_count, u->out,
+                       u->loss, u->g + u->L[H].off, bias(u, u->g, H), u->g1);
+    });
     uint16_t* gd = u->g1;  // gradient of d_l's pre-activation
     uint16_t* gt = u->g2;
     for (int l = 0; l <= 2; l++) {
@@ -241,42 +255,56 @@ void backward(mem_unet* u, hipStream_t s, int B, const float* target, const floa
         const int64_t P = P_at(u, B, l);
         // d_l = relu(conv3(m_l))
         conv_bwd(u, s, k + 2, u->m[l], c, B, l, gd, u->tmpf);
-        unet_relu_mask_add(s, u->tmpf, c, nullptr, 0, u->m[l], c, P, c, gt, c);
+        u->prof.timed(s, "eltwise", [&] { unet_relu_mask_add(s, u->tmpf, c, nullptr, 0, u->m[l], c, P, c, gt, c); });
         std::swap(gd, gt);  // gd: gradient of m_l's pre-activation
         // m_l = relu(conv3([u_l, e_l]))
         conv_bwd(u, s, k + 1, u->cat[l], 2 * c, B, l, gd, u->tmpf);
-        unet_add_f32(s, u->de[l], c, u->tmpf + c, 2 * c, P, c);                       // skip -> e_l
-        unet_relu_mask_add(s, u->tmpf, 2 * c, nullptr, 0, nullptr, 0, P, c, gt, c);  // -> u_l (no ReLU)
+        u->prof.timed(s, "eltwise", [&] { unet_add_f32(s, u->de[l], c, u->tmpf + c, 2 * c, P, c); });  // skip -> e_l
+        u->prof.timed(s, "eltwise", [&] {
+            unet_relu_mask_add(s, u->tmpf, 2 * c, nullptr, 0, nullptr, 0, P, c, gt, c);  // -> u_l (no ReLU)
+        });
         // u_l = convT2(below) + b
         const ULayer& U = u->L[k];
         const int64_t Pb = P_at(u, B, l + 1);
-        unet_gather_children(s, gt, c, 0, B, u->S >> (l + 1), c, u->gch);
+        u->prof.timed(s, "eltwise", [&] { unet_gather_children(s, gt, c, 0, B, u->S >> (l + 1), c, u->gch); });
         const uint16_t* below = (l == 2) ? u->e3 : u->d[l + 1];
-        unet_gemm_tn(s, u->gch, 4 * c, below, U.ci, (int)Pb, 4 * c, U.ci, U.gbuf, U.ci, u->n_cu);
-        unet_colsum(s, gt, c, P, c, bias(u, u->g, k));
+        u->prof.timed(s, "gemm_wgrad", [&] {
+            unet_gemm_tn(s, u->gch, 4 * c, below, U.ci, (int)Pb, 4 * c, U.ci, U.gbuf, U.ci, u->n_cu);
+        });
+        u->prof.timed(s, "colsum", [&] { unet_colsum(s, gt, c, P, c, bias(u, u->g, k)); });
         Epilogue ep{nullptr, 0, nullptr, 0, 0, u->tmpf, U.ci, 0, 0};
-        unet_gemm_nt(s, EPI_F32, u->gch, 4 * c, U.wd, 4 * c, (int)Pb, U.ci, 4 * c, ep);
+        u->prof.timed(s, "gemm_dgrad", [&] {
+            unet_gemm_nt(s, EPI_F32, u->gch, 4 * c, U.wd, 4 * c, (int)Pb, U.ci, 4 * c, ep);
+        });
         if (l < 2) {
-            unet_relu_mask_add(s, u->tmpf, U.ci, nullptr, 0, u->d[l + 1], U.ci, Pb, U.ci, gd, U.ci);
+            u->prof.timed(s, "eltwise", [&] {
+                unet_relu_mask_add(s, u->tmpf, U.ci, nullptr, 0, u->d[l + 1], U.ci, Pb, U.ci, gd, U.ci);
+            });
         } else {
-            unet_add_f32(s, u->de[3], U.ci, u->tmpf, U.ci, Pb, U.ci);
+            u->prof.timed(s, "eltwise", [&] { unet_add_f32(s, u->de[3], U.ci, u->tmpf, U.ci, Pb, U.ci); });
         }
     }
     for (int l = 3; l >= 0; l--) {
         const int c = b << l;
         const int64_t P = P_at(u, B, l);
-        unet_relu_mask_add(s, u->de[l], c, nullptr, 0, e_ptr(u, l), e_stride(u, l), P, c, gd, c);
+        u->prof.timed(s, "eltwise", [&] {
+            unet_relu_mask_add(s, u->de[l], c, nullptr, 0, e_ptr(u, l), e_stride(u, l), P, c, gd, c);
+        });
         conv_bwd(u, s, 2 * l + 1, u->a[l], c, B, l, gd, u->tmpf);
-        unet_relu_mask_add(s, u->tmpf, c, nullptr, 0, u->a[l], c, P, c, gt, c);
+        u->prof.timed(s, "eltwise", [&] { unet_relu_mask_add(s, u->tmpf, c, nullptr, 0, u->a[l], c, P, c, gt, c); });
         const uint16_t* in = (l == 0) ? u->x : u->p[l - 1];
         const int ci = (l == 0) ? 3 : c / 2;
         conv_bwd(u, s, 2 * l, in, ci, B, l, gt, l > 0 ? u->tmpf : nullptr);
-        if (l > 0) unet_maxpool_bwd(s, u->tmpf, u->arg[l - 1], B, u->S >> (l - 1), ci, u->de[l - 1], ci);
+        if (l > 0) u->prof.timed(s, "pool", [&] {
+            unet_maxpool_bwd(s, u->tmpf, u->arg[l - 1], B, u->S >> (l - 1), ci, u->de[l - 1], ci);
+        });
     }
     for (int i = 0; i < NLAY; i++) {
         const ULayer& Y = u->L[i];
         if (Y.kind == 4) continue;
-        unet_grad_to_flat(s, Y.gbuf, Y.taps, Y.ci, Y.co, Y.kind, Y.kf, u->g + Y.off);
+        u->prof.timed(s, "eltwise", [&] {
+            unet_grad_to_flat(s, Y.gbuf, Y.taps, Y.ci, Y.co, Y.kind, Y.kf, u->g + Y.off);
+        });
     }
 }
 
@@ -392,8 +420,8 @@ mem_status mem_unet_create(int32_t base, int32_t max_batch, int32_t size, uint64
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMemcpy(u->w, w.data(), sizeof(float) * u->n_params, hipMemcpyHostToDevice);
     if (e == hipSuccess) {
-        unet_fill(s, u->am, u->n_params, 0.f);
-        unet_fill(s, u->av, u->n_params, 0.f);
+        u->prof.timed(s, "fill", [&] { unet_fill(s, u->am, u->n_params, 0.f); });
+        u->prof.timed(s, "fill", [&] { unet_fill(s, u->av, u->n_params, 0.f); });
         relayout_all(u, s);
         e = hipGetLastError();
     }
@@ -421,8 +449,8 @@ mem_status mem_unet_set_params(mem_unet* u, const float* params, void* stream)
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(u->w, params, sizeof(float) * u->n_params, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return ufail(u, e, "mem_unet_set_params");
-    unet_fill(s, u->am, u->n_params, 0.f);
-    unet_fill(s, u->av, u->n_params, 0.f);
+    u->prof.timed(s, "fill", [&] { unet_fill(s, u->am, u->n_params, 0.f); });
+    u->prof.timed(s, "fill", [&] { unet_fill(s, u->av, u->n_params, 0.f); });
     u->step = 0;
     relayout_all(u, s);
     return finish(u, "mem_unet_set_params");
@@ -444,12 +472,14 @@ mem_status mem_unet_forward(mem_unet* u, const float* x, int32_t batch, float* o
     if (!x || !out) return api_fail(MEM_E_ARG, "x and out must not be NULL");
     hipStream_t s = (hipStream_t)stream;
     const int64_t P0 = P_at(u, batch, 0);
-    unet_cast_bf16(s, x, P0 * 3, u->x);
+    u->prof.timed(s, "eltwise", [&] { unet_cast_bf16(s, x, P0 * 3, u->x); });
     forward(u, s, batch);
     // the head alone (no loss)
     const int H = NLAY - 1;
-    unet_head_loss(s, u->d[0], u->base, P0, u->w + u->L[H].off, bias(u, u->w, H), nullptr, nullptr, 0.f, out,
-                   nullptr, nullptr, nullptr, nullptr);
+    u->prof.timed(s, "head", [&] {
+        unet_head_loss(s, u->d[0], u->base, P0, u->w + u->L[H].off, bias(u, u->w, H), nullptr, nullptr, 0.f, out,
+                       nullptr, nullptr, nullptr, nullptr);
+    });
     return finish(u, "mem_unet_forward");
 }
 
@@ -460,7 +490,7 @@ mem_status mem_unet_loss_grad(mem_unet* u, const float* x, const float* target, 
     if (!x || !target || !mask) return api_fail(MEM_E_ARG, "x, target and mask must not be NULL");
     if (!(inv_count > 0.f)) return api_fail(MEM_E_ARG, "inv_count must be positive (1 / masked cells)");
     hipStream_t s = (hipStream_t)stream;
-    unet_cast_bf16(s, x, P_at(u, batch, 0) * 3, u->x);
+    u->prof.timed(s, "eltwise", [&] { unet_cast_bf16(s, x, P_at(u, batch, 0) * 3, u->x); });
     forward(u, s, batch);
     backward(u, s, batch, target, mask, inv_count);
     if (grad) (void)hipMemcpyAsync(grad, u->g, sizeof(float) * u->n_params, hipMemcpyDeviceToDevice, s);
@@ -477,9 +507,24 @@ mem_status mem_unet_train_step(mem_unet* u, const float* x, const float* target,
     u->step++;
     const float b1 = 0.9f, b2 = 0.999f;
     const float c1 = 1.f - std::pow(b1, (float)u->step), c2 = 1.f - std::pow(b2, (float)u->step);
-    unet_adam(s, u->w, u->g, u->am, u->av, u->n_params, lr, b1, b2, 1e-8f, c1, c2);
+    u->prof.timed(s, "adam", [&] { unet_adam(s, u->w, u->g, u->am, u->av, u->n_params, lr, b1, b2, 1e-8f, c1, c2); });
     relayout_all(u, s);
     return finish(u, "mem_unet_train_step");
+}
+
+mem_status mem_unet_profile_enable(mem_unet* u, int32_t on)
+{
+    if (!u) return api_fail(MEM_E_ARG, "network is NULL");
+    u->prof.enable(on != 0);
+    return MEM_OK;
+}
+
+mem_status mem_unet_profile_read(mem_unet* u, mem_kernel_time* out, int32_t max, int32_t* count)
+{
+    if (!u) return api_fail(MEM_E_ARG, "network is NULL");
+    if (!count || (max > 0 && !out)) return api_fail(MEM_E_ARG, "NULL output");
+    *count = u->prof.read(out, max);
+    return MEM_OK;
 }
 
 mem_status mem_unet_save(const mem_unet* uc, const char* path, void* stream)

@@ -127,7 +127,8 @@ __device__ __forceinline__ void ingest_range(const Grid& g, const float* __restr
 // number of in-grid cells it loaded.
 __device__ __forceinline__ int march_point(const Grid& g, const float* __restrict__ xyz, int64_t i,
                                            const Pose& T, float mr2, float margin,
-                                           const float* __restrict__ h, int* __restrict__ clr)
+                                           const float* __restrict__ h, int* __restrict__ clr,
+                                           int* steps = nullptr)
 {
     float px, py, pz, r2;
     int ix, iy;
@@ -137,6 +138,7 @@ __device__ __forceinline__ int march_point(const Grid& g, const float* __restric
     int ax, ay;
     lattice_cell(g, sx, sy, ax, ay);
     Ray ray(g, ax, ay, ix, iy, sx, sy, sz, px, py, pz);
+    if (steps) *steps = max(ray.L.steps - 1, 0);
     return walk_cells<8>(g, ray, h, [&](int st, float hk, float zr) {
         float thr = zr + margin;
         if (hk > thr) atomicAdd(&clr[st], 1);  // NaN (no height) never votes

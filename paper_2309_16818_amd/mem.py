@@ -25,7 +25,7 @@ MEM_VIEW_VALUE, MEM_VIEW_AUX, MEM_VIEW_ARGMAX = 0, 1, 2
 
 STAT_FIELDS = ("points_in", "points_accepted", "dropped_nonfinite", "dropped_range", "dropped_outside",
                "cells_touched", "cells_cleared", "ray_cells", "cells_in_view", "pairs_visible",
-               "occl_cells")
+               "occl_cells", "ray_steps", "occl_steps")
 
 # Exported symbols of include/mem.h.
 SYMBOLS = ("mem_create", "mem_destroy", "mem_move", "mem_input_pointcloud", "mem_input_image",
@@ -492,7 +492,7 @@ class Batch:
 UNET_SYMBOLS = ("mem_unet_num_params", "mem_unet_create", "mem_unet_destroy", "mem_unet_set_params",
                 "mem_unet_get_params", "mem_unet_save", "mem_unet_load", "mem_unet_forward",
                 "mem_unet_loss_grad", "mem_unet_train_step", "mem_unet_input", "mem_unet_complete",
-                "mem_complete")
+                "mem_unet_profile_enable", "mem_unet_profile_read", "mem_complete")
 
 
 def _load_unet():
@@ -513,6 +513,8 @@ def _load_unet():
         "mem_unet_input": [P, P, I32, I32, F, P, P],
         "mem_unet_complete": [P, P, I32, F, F, P, P, P],
         "mem_complete": [P, P, F, F, P, P, P],
+        "mem_unet_profile_enable": [P, I32],
+        "mem_unet_profile_read": [P, C.POINTER(mem_kernel_time), I32, C.POINTER(I32)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -573,6 +575,16 @@ class UNet:
             raise ValueError(f"expected {self.n_params} parameters")
         _check(_load_unet().mem_unet_set_params(self._u, _dev_ptr(p, "params"), _stream(stream)))
         (stream or torch.cuda.current_stream()).synchronize()
+
+    def profile_enable(self, on=True):
+        _check(_load_unet().mem_unet_profile_enable(self._u, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        """{name: (launches, total_ms)} since the last read."""
+        arr = (mem_kernel_time * 64)()
+        n = C.c_int32()
+        _check(_load_unet().mem_unet_profile_read(self._u, arr, 64, C.byref(n)))
+        return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(min(n.value, 64))}
 
     def save(self, path, stream=None):
         _check(_load_unet().mem_unet_save(self._u, os.fsencode(path), _stream(stream)))
