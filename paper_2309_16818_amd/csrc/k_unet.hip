@@ -50,6 +50,37 @@ __device__ __forceinline__ uint4 load8(const uint16_t* __restrict__ p, int64_t l
     return v;
 }
 
+// Position of one thread's 8-wide K slice inside the unfolded convolution
+// input: tap t and channel c of column k, advanced by whole K steps.
+struct ConvCursor {
+    int t, c;
+    __device__ __forceinline__ void start(int k, int ci)
+    {
+        t = k / ci;
+        c = k - t * ci;
+    }
+    __device__ __forceinline__ void advance(int dk, int ci)
+    {
+        c += dk;
+        while (c >= ci) {
+            c -= ci;
+            t++;
+        }
+    }
+};
+
+// 8 values of the unfolded input at pixel (n, r, q), slice (t, c); zero
+// outside the image or past tap 8.
+__device__ __forceinline__ uint4 load8_conv(const ConvSrc& cs, int64_t n, int r, int q, bool valid, const ConvCursor& cc)
+{
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (!valid || cc.t >= 9) return v;
+    const int ty = cc.t / 3;
+    const int rr = r + ty - 1, qq = q + (cc.t - 3 * ty) - 1;
+    if (rr < 0 || rr >= cs.S || qq < 0 || qq >= cs.S) return v;
+    return *(const uint4*)(cs.x + ((n * cs.S + rr) * cs.S + qq) * cs.xs + cc.c);
+}
+
 __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v)
 {
     bf16x8 r;
@@ -60,8 +91,8 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v)
 // C = A B^T on a 64x64 tile; 4 waves, each a 32x32 quadrant of 2x2 MFMA
 // 16x16x32 blocks.  Lane l of an MFMA block supplies A[l % 16][8 (l / 16) ..
 // + 7] and B[l % 16][8 (l / 16) .. + 7] and receives D[4 (l / 16) + j][l % 16].
-template <int EPI>
-__global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A, int64_t lda,
+template <int EPI, bool CONV>
+__global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A, int64_t lda, ConvSrc cs,
                                                  const uint16_t* __restrict__ B, int64_t ldb, int M,
                                                  int N, int K, Epilogue ep)
 {
@@ -76,8 +107,25 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A,
 #pragma unroll
         for (int j = 0; j < 2; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int lr = tid >> 2, lk = (tid & 3) * 8;  // 64 rows x 4 chunks of 8
+    // the pixel of this thread's A row (unfolded input)
+    int64_t pn = 0;
+    int pr = 0, pq = 0;
+    ConvCursor cc{0, 0};
+    if (CONV) {
+        const int m = m0 + lr;
+        pq = m % cs.S;
+        pr = (m / cs.S) % cs.S;
+        pn = m / (cs.S * cs.S);
+        cc.start(lk, cs.ci);
+    }
     for (int k0 = 0; k0 < K; k0 += BK) {
-        const uint4 va = load8(A, lda, m0 + lr, M, k0 + lk, K);
+        uint4 va;
+        if (CONV) {
+            va = load8_conv(cs, pn, pr, pq, m0 + lr < M, cc);
+            cc.advance(BK, cs.ci);
+        } else {
+            va = load8(A, lda, m0 + lr, M, k0 + lk, K);
+        }
         const uint4 vb = load8(B, ldb, n0 + lr, N, k0 + lk, K);
         __syncthreads();
         *(uint4*)&sA[lr * LDSK + lk] = va;
@@ -108,8 +156,9 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A,
 
 // C[m][n] += sum_p A[p][m] B[p][n] over the pixel range of this block
 // (blockIdx.z of gridDim.z equal slices).
+template <bool CONV>
 __global__ __launch_bounds__(256) void k_gemm_tn(const uint16_t* __restrict__ A, int64_t lda,
-                                                 const uint16_t* __restrict__ B, int64_t ldb, int P,
+                                                 const uint16_t* __restrict__ B, int64_t ldb, ConvSrc cs, int P,
                                                  int M, int N, float* __restrict__ C, int64_t ldc)
 {
     __shared__ uint16_t sA[BM * LDSK];  // [m][p]
@@ -126,9 +175,34 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const uint16_t* __restrict__ A,
 #pragma unroll
         for (int j = 0; j < 2; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int lp = tid >> 3, lc = (tid & 7) * 8;  // 32 pixels x 8 chunks of 8 columns
+    // this thread's B columns (unfolded input): fixed tap and channel, and
+    // the pixel of its row, advanced by BK pixels per step
+    ConvCursor cc{0, 0};
+    int64_t pn = 0;
+    int pr = 0, pq = 0;
+    if (CONV) {
+        cc.start(n0 + lc, cs.ci);
+        const int p = p_begin + lp;
+        pq = p % cs.S;
+        pr = (p / cs.S) % cs.S;
+        pn = p / (cs.S * cs.S);
+    }
     for (int p0 = p_begin; p0 < p_end; p0 += BK) {
         const uint4 va = load8(A, lda, p0 + lp, p_end, m0 + lc, M);
-        const uint4 vb = load8(B, ldb, p0 + lp, p_end, n0 + lc, N);
+        uint4 vb;
+        if (CONV) {
+            vb = load8_conv(cs, pn, pr, pq, p0 + lp < p_end && n0 + lc < N, cc);
+            pq += BK;
+            while (pq >= cs.S) {
+                pq -= cs.S;
+                if (++pr == cs.S) {
+                    pr = 0;
+                    pn++;
+                }
+            }
+        } else {
+            vb = load8(B, ldb, p0 + lp, p_end, n0 + lc, N);
+        }
         __syncthreads();
         const uint16_t* ta = (const uint16_t*)&va;
         const uint16_t* tb = (const uint16_t*)&vb;
@@ -262,25 +336,44 @@ __global__ void k_relu_mask_add(const float* __restrict__ acc, int as, const flo
     }
 }
 
-// Column sums: db[o] += sum_p g[p][o] (BF16 g, stride gs).
-__global__ void k_colsum(const uint16_t* __restrict__ g, int gs, int64_t rows, int c, float* __restrict__ db)
+// Column sums db[o] += sum_p g[p][o] (BF16 g, row stride gs): a workgroup
+// sums a contiguous range of rows for 64 columns at a time (4 row lanes per
+// column, coalesced 128-byte rows), then one atomic per (workgroup, column).
+__global__ __launch_bounds__(256) void k_colsum(const uint16_t* __restrict__ g, int gs, int64_t rows, int c,
+                                                float* __restrict__ db)
 {
-    const int o = blockIdx.y * blockDim.x + threadIdx.x;
-    if (o >= c) return;
-    float s = 0.f;
-    for (int64_t p = blockIdx.x; p < rows; p += gridDim.x) s += fb(g[p * gs + o]);
-    unsafeAtomicAdd(&db[o], s);
+    const int oc = threadIdx.x & 63, rl = threadIdx.x >> 6;
+    const int64_t per = (rows + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(rows, r0 + per);
+    __shared__ float red[4][64];
+    for (int c0 = 0; c0 < c; c0 += 64) {
+        const int o = c0 + oc;
+        float sum = 0.f;
+        if (o < c)
+            for (int64_t p = r0 + rl; p < r1; p += 4) sum += fb(g[p * gs + o]);
+        red[rl][oc] = sum;
+        __syncthreads();
+        if (rl == 0 && o < c) {
+            const float t = red[0][oc] + red[1][oc] + red[2][oc] + red[3][oc];
+            if (t != 0.f) unsafeAtomicAdd(&db[o], t);
+        }
+        __syncthreads();
+    }
 }
 
 // Head (1x1 convolution, 2 outputs, FP32 weights) and the Gaussian NLL over
-// mask > 0; writes out (optional), dout-derived head gradients and the
-// gradient with respect to d0 (BF16, ReLU-masked by d0).
-__global__ void k_head_loss(const uint16_t* __restrict__ d0, int c, int64_t P, const float* __restrict__ w,
-                            const float* __restrict__ b, const float* __restrict__ target,
-                            const float* __restrict__ mask, float inv_count, float* __restrict__ out,
-                            float* __restrict__ loss, float* __restrict__ gw, float* __restrict__ gb,
-                            uint16_t* __restrict__ gd0)
+// mask > 0: writes out (optional); with a target, the per-pixel output
+// gradient gout[p] = (dL/dm, dL/ds), the bias gradient and the loss
+// (reduced per workgroup, one atomic each), and the gradient with respect to
+// d0's pre-activation (BF16, ReLU-masked by d0).
+__global__ __launch_bounds__(256) void k_head(const uint16_t* __restrict__ d0, int c, int64_t P,
+                                              const float* __restrict__ w, const float* __restrict__ b,
+                                              const float* __restrict__ target, const float* __restrict__ mask,
+                                              float inv_count, float* __restrict__ out, float* __restrict__ loss,
+                                              float2* __restrict__ gout, float* __restrict__ gb,
+                                              uint16_t* __restrict__ gd0)
 {
+    float l_acc = 0.f, g0_acc = 0.f, g1_acc = 0.f;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
         float o0 = b[0], o1 = b[1];
         for (int i = 0; i < c; i++) {
@@ -296,23 +389,69 @@ __global__ void k_head_loss(const uint16_t* __restrict__ d0, int c, int64_t P, c
         float g0 = 0.f, g1 = 0.f;
         if (mask[p] > 0.f) {
             const float r = target[p] - o0, e = expf(-o1);
-            unsafeAtomicAdd(loss, 0.5f * (o1 + r * r * e) * inv_count);
+            l_acc += 0.5f * (o1 + r * r * e) * inv_count;
             g0 = -r * e * inv_count;
             g1 = 0.5f * (1.f - r * r * e) * inv_count;
         }
-        if (g0 != 0.f || g1 != 0.f) {
-            unsafeAtomicAdd(&gb[0], g0);
-            unsafeAtomicAdd(&gb[1], g1);
-        }
+        g0_acc += g0;
+        g1_acc += g1;
+        gout[p] = make_float2(g0, g1);
         for (int i = 0; i < c; i++) {
             const float a = fb(d0[p * c + i]);
-            if (g0 != 0.f || g1 != 0.f) {
-                unsafeAtomicAdd(&gw[2 * i], g0 * a);
-                unsafeAtomicAdd(&gw[2 * i + 1], g1 * a);
-            }
-            const float gd = (a > 0.f) ? g0 * w[2 * i] + g1 * w[2 * i + 1] : 0.f;
-            gd0[p * c + i] = bf(gd);
+            gd0[p * c + i] = bf((a > 0.f) ? g0 * w[2 * i] + g1 * w[2 * i + 1] : 0.f);
         }
+    }
+    if (!target) return;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        l_acc += __shfl_xor(l_acc, o);
+        g0_acc += __shfl_xor(g0_acc, o);
+        g1_acc += __shfl_xor(g1_acc, o);
+    }
+    __shared__ float red[3][4];
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][wave] = l_acc;
+        red[1][wave] = g0_acc;
+        red[2][wave] = g1_acc;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const float v = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
+        if (v != 0.f) unsafeAtomicAdd(threadIdx.x == 0 ? loss : &gb[threadIdx.x - 1], v);
+    }
+}
+
+// Head weight gradient gw[i][j] = sum_p d0[p][i] gout[p][j]: a workgroup
+// sums a range of pixels for 64 channels (4 pixel lanes per channel), then
+// one atomic per (workgroup, weight).
+__global__ __launch_bounds__(256) void k_head_wgrad(const uint16_t* __restrict__ d0, int c, int64_t P,
+                                                    const float2* __restrict__ gout, float* __restrict__ gw)
+{
+    const int oc = threadIdx.x & 63, pl = threadIdx.x >> 6;
+    const int64_t per = (P + gridDim.x - 1) / gridDim.x;
+    const int64_t p0 = (int64_t)blockIdx.x * per, p1 = min(P, p0 + per);
+    __shared__ float red[4][64][2];
+    for (int c0 = 0; c0 < c; c0 += 64) {
+        const int i = c0 + oc;
+        float s0 = 0.f, s1 = 0.f;
+        if (i < c)
+            for (int64_t p = p0 + pl; p < p1; p += 4) {
+                const float a = fb(d0[p * c + i]);
+                const float2 g = gout[p];
+                s0 += a * g.x;
+                s1 += a * g.y;
+            }
+        red[pl][oc][0] = s0;
+        red[pl][oc][1] = s1;
+        __syncthreads();
+        if (pl == 0 && i < c) {
+            const float t0 = red[0][oc][0] + red[1][oc][0] + red[2][oc][0] + red[3][oc][0];
+            const float t1 = red[0][oc][1] + red[1][oc][1] + red[2][oc][1] + red[3][oc][1];
+            if (t0 != 0.f) unsafeAtomicAdd(&gw[2 * i], t0);
+            if (t1 != 0.f) unsafeAtomicAdd(&gw[2 * i + 1], t1);
+        }
+        __syncthreads();
     }
 }
 
@@ -453,19 +592,30 @@ inline unsigned grid_for(int64_t n)
 
 }  // namespace
 
-void unet_gemm_nt(hipStream_t s, int epi, const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, int M,
-                  int N, int K, const Epilogue& ep)
+void unet_gemm_nt(hipStream_t s, int epi, const uint16_t* A, int64_t lda, const ConvSrc* conv, const uint16_t* B,
+                  int64_t ldb, int M, int N, int K, const Epilogue& ep)
 {
     dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN);
-    switch (epi) {
-    case EPI_STORE: hipLaunchKernelGGL(k_gemm_nt<EPI_STORE>, grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, ep); break;
-    case EPI_CONVT: hipLaunchKernelGGL(k_gemm_nt<EPI_CONVT>, grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, ep); break;
-    default: hipLaunchKernelGGL(k_gemm_nt<EPI_F32>, grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, ep); break;
+    const ConvSrc cs = conv ? *conv : ConvSrc{nullptr, 0, 1, 1};
+#define MEM_GNT(E, CV) hipLaunchKernelGGL((k_gemm_nt<E, CV>), grid, dim3(256), 0, s, A, lda, cs, B, ldb, M, N, K, ep)
+    if (conv) {
+        switch (epi) {
+        case EPI_STORE: MEM_GNT(EPI_STORE, true); break;
+        case EPI_CONVT: MEM_GNT(EPI_CONVT, true); break;
+        default: MEM_GNT(EPI_F32, true); break;
+        }
+    } else {
+        switch (epi) {
+        case EPI_STORE: MEM_GNT(EPI_STORE, false); break;
+        case EPI_CONVT: MEM_GNT(EPI_CONVT, false); break;
+        default: MEM_GNT(EPI_F32, false); break;
+        }
     }
+#undef MEM_GNT
 }
 
-void unet_gemm_tn(hipStream_t s, const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, int P, int M,
-                  int N, float* C, int64_t ldc, int n_cu)
+void unet_gemm_tn(hipStream_t s, const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, const ConvSrc* conv,
+                  int P, int M, int N, float* C, int64_t ldc, int n_cu)
 {
     const int tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
     int split = (4 * n_cu + tiles - 1) / tiles;
@@ -473,7 +623,11 @@ void unet_gemm_tn(hipStream_t s, const uint16_t* A, int64_t lda, const uint16_t*
     if (split > max_split) split = max_split;
     if (split < 1) split = 1;
     dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN, split);
-    hipLaunchKernelGGL(k_gemm_tn, grid, dim3(256), 0, s, A, lda, B, ldb, P, M, N, C, ldc);
+    if (conv)
+        hipLaunchKernelGGL(k_gemm_tn<true>, grid, dim3(256), 0, s, A, lda, B, ldb, *conv, P, M, N, C, ldc);
+    else
+        hipLaunchKernelGGL(k_gemm_tn<false>, grid, dim3(256), 0, s, A, lda, B, ldb, ConvSrc{nullptr, 0, 1, 1}, P, M,
+                           N, C, ldc);
 }
 
 void unet_im2col3(hipStream_t s, const uint16_t* x, int xs, int xo, int B, int S, int ci, uint16_t* col, int kpad)
@@ -510,17 +664,24 @@ void unet_relu_mask_add(hipStream_t s, const float* acc, int as, const float* ad
 
 void unet_colsum(hipStream_t s, const uint16_t* g, int gs, int64_t rows, int c, float* db)
 {
-    int64_t gx = rows < 1024 ? rows : 1024;
-    dim3 grid((unsigned)(gx < 1 ? 1 : gx), (unsigned)((c + 63) / 64));
-    hipLaunchKernelGGL(k_colsum, grid, dim3(64), 0, s, g, gs, rows, c, db);
+    int64_t blocks = (rows + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)blocks), dim3(256), 0, s, g, gs, rows, c, db);
 }
 
 void unet_head_loss(hipStream_t s, const uint16_t* d0, int c, int64_t P, const float* w, const float* b,
                     const float* target, const float* mask, float inv_count, float* out, float* loss, float* gw,
-                    float* gb, uint16_t* gd0)
+                    float* gb, uint16_t* gd0, float2* gout)
 {
-    hipLaunchKernelGGL(k_head_loss, dim3(grid_for(P)), dim3(256), 0, s, d0, c, P, w, b, target, mask, inv_count,
-                       out, loss, gw, gb, gd0);
+    int64_t blocks = (P + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(k_head, dim3((unsigned)(blocks < 1 ? 1 : blocks)), dim3(256), 0, s, d0, c, P, w, b, target,
+                       mask, inv_count, out, loss, gout, gb, gd0);
+    if (!target) return;
+    int64_t wb = (P + 1023) / 1024;
+    if (wb > 512) wb = 512;
+    hipLaunchKernelGGL(k_head_wgrad, dim3((unsigned)(wb < 1 ? 1 : wb)), dim3(256), 0, s, d0, c, P, gout, gw);
 }
 
 void unet_add_f32(hipStream_t s, float* dst, int ds, const float* src, int ss, int64_t rows, int c)

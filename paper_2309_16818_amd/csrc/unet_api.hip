@@ -164,16 +164,29 @@ void relayout_all(mem_unet* u, hipStream_t s)
     }
 }
 
+// A convolution input whose channels and stride are multiples of 8 is read
+// by the matrix products in place; others (the 3-channel network input,
+// narrow test networks) are unfolded into `col` first.
+bool implicit(int ci, int xs) { return ci % 8 == 0 && xs % 8 == 0; }
+
 // y = relu(conv3(x) + b) into out (stride ldo, channel offset off).
 void conv_fwd(mem_unet* u, hipStream_t s, int i, const uint16_t* x, int xs, int B, int l, uint16_t* out,
               int64_t ldo, int off)
 {
     const ULayer& Y = u->L[i];
     const int S = u->S >> l;
-    u->prof.timed(s, "im2col", [&] { unet_im2col3(s, x, xs, 0, B, S, Y.ci, u->col, Y.kf); });
     Epilogue ep{bias(u, u->w, i), 1, out, ldo, off, nullptr, 0, 0, 0};
+    const int P = (int)P_at(u, B, l);
+    if (implicit(Y.ci, xs)) {  // the GEMM reads the unfolded input in place
+        const ConvSrc cs{x, xs, Y.ci, S};
+        u->prof.timed(s, "gemm_fwd", [&] {
+            unet_gemm_nt(s, EPI_STORE, nullptr, 0, &cs, Y.wf, Y.kf, P, Y.co, 9 * Y.ci, ep);
+        });
+        return;
+    }
+    u->prof.timed(s, "im2col", [&] { unet_im2col3(s, x, xs, 0, B, S, Y.ci, u->col, Y.kf); });
     u->prof.timed(s, "gemm_fwd", [&] {
-        unet_gemm_nt(s, EPI_STORE, u->col, Y.kf, Y.wf, Y.kf, (int)P_at(u, B, l), Y.co, Y.kf, ep);
+        unet_gemm_nt(s, EPI_STORE, u->col, Y.kf, nullptr, Y.wf, Y.kf, P, Y.co, Y.kf, ep);
     });
 }
 
@@ -200,7 +213,7 @@ void forward(mem_unet* u, hipStream_t s, int B)
         const ULayer& U = u->L[k];
         Epilogue ep{bias(u, u->w, k), 0, u->cat[l], 2 * c, 0, nullptr, 0, u->S >> (l + 1), c};
         u->prof.timed(s, "gemm_up", [&] {
-            unet_gemm_nt(s, EPI_CONVT, below, U.ci, U.wf, U.ci, (int)P_at(u, B, l + 1), 4 * c, U.ci, ep);
+            unet_gemm_nt(s, EPI_CONVT, below, U.ci, nullptr, U.wf, U.ci, (int)P_at(u, B, l + 1), 4 * c, U.ci, ep);
         });
         conv_fwd(u, s, k + 1, u->cat[l], 2 * c, B, l, u->m[l], c, 0);
         conv_fwd(u, s, k + 2, u->m[l], c, B, l, u->d[l], c, 0);
@@ -218,15 +231,31 @@ void conv_bwd(mem_unet* u, hipStream_t s, int i, const uint16_t* x, int xs, int 
     const ULayer& Y = u->L[i];
     const int S = u->S >> l;
     const int P = (int)P_at(u, B, l);
-    u->prof.timed(s, "im2col", [&] { unet_im2col3(s, x, xs, 0, B, S, Y.ci, u->col, Y.kf); });
-    u->prof.timed(s, "gemm_wgrad", [&] {
-        unet_gemm_tn(s, gy, Y.co, u->col, Y.kf, P, Y.co, Y.kf, Y.gbuf, Y.kf, u->n_cu);
-    });
+    if (implicit(Y.ci, xs)) {
+        const ConvSrc cs{x, xs, Y.ci, S};
+        u->prof.timed(s, "gemm_wgrad", [&] {
+            unet_gemm_tn(s, gy, Y.co, nullptr, 0, &cs, P, Y.co, 9 * Y.ci, Y.gbuf, Y.kf, u->n_cu);
+        });
+    } else {
+        u->prof.timed(s, "im2col", [&] { unet_im2col3(s, x, xs, 0, B, S, Y.ci, u->col, Y.kf); });
+        u->prof.timed(s, "gemm_wgrad", [&] {
+            unet_gemm_tn(s, gy, Y.co, u->col, Y.kf, nullptr, P, Y.co, Y.kf, Y.gbuf, Y.kf, u->n_cu);
+        });
+    }
     u->prof.timed(s, "colsum", [&] { unet_colsum(s, gy, Y.co, P, Y.co, bias(u, u->g, i)); });
     if (!dx) return;
-    u->prof.timed(s, "im2col", [&] { unet_im2col3(s, gy, Y.co, 0, B, S, Y.co, u->col, Y.kd); });
     Epilogue ep{nullptr, 0, nullptr, 0, 0, dx, Y.ci, 0, 0};
-    u->prof.timed(s, "gemm_dgrad", [&] { unet_gemm_nt(s, EPI_F32, u->col, Y.kd, Y.wd, Y.kd, P, Y.ci, Y.kd, ep); });
+    if (implicit(Y.co, Y.co)) {
+        const ConvSrc cs{gy, Y.co, Y.co, S};
+        u->prof.timed(s, "gemm_dgrad", [&] {
+            unet_gemm_nt(s, EPI_F32, nullptr, 0, &cs, Y.wd, Y.kd, P, Y.ci, 9 * Y.co, ep);
+        });
+        return;
+    }
+    u->prof.timed(s, "im2col", [&] { unet_im2col3(s, gy, Y.co, 0, B, S, Y.co, u->col, Y.kd); });
+    u->prof.timed(s, "gemm_dgrad", [&] {
+        unet_gemm_nt(s, EPI_F32, u->col, Y.kd, nullptr, Y.wd, Y.kd, P, Y.ci, Y.kd, ep);
+    });
 }
 
 // Loss gradient of every parameter into u->g (flat), loss into u->loss.
@@ -246,7 +275,7 @@ void backward(mem_unet* u, hipStream_t s, int B, const float* target, const floa
     const int64_t P0 = P_at(u, B, 0);
     u->prof.timed(s, "head", [&] {
         unet_head_loss(s, u->d[0], b, P0, u->w + u->L[H].off, bias(u, u->w, H), target, mask, inv_count, u->out,
-                       u->loss, u->g + u->L[H].off, bias(u, u->g, H), u->g1);
+                       u->loss, u->g + u->L[H].off, bias(u, u->g, H), u->g1, (float2*)u->tmpf);
     });
     uint16_t* gd = u->g1;  // gradient of d_l's pre-activation
     uint16_t* gt = u->g2;
@@ -269,12 +298,12 @@ void backward(mem_unet* u, hipStream_t s, int B, const float* target, const floa
         u->prof.timed(s, "eltwise", [&] { unet_gather_children(s, gt, c, 0, B, u->S >> (l + 1), c, u->gch); });
         const uint16_t* below = (l == 2) ? u->e3 : u->d[l + 1];
         u->prof.timed(s, "gemm_wgrad", [&] {
-            unet_gemm_tn(s, u->gch, 4 * c, below, U.ci, (int)Pb, 4 * c, U.ci, U.gbuf, U.ci, u->n_cu);
+            unet_gemm_tn(s, u->gch, 4 * c, below, U.ci, nullptr, (int)Pb, 4 * c, U.ci, U.gbuf, U.ci, u->n_cu);
         });
         u->prof.timed(s, "colsum", [&] { unet_colsum(s, gt, c, P, c, bias(u, u->g, k)); });
         Epilogue ep{nullptr, 0, nullptr, 0, 0, u->tmpf, U.ci, 0, 0};
         u->prof.timed(s, "gemm_dgrad", [&] {
-            unet_gemm_nt(s, EPI_F32, u->gch, 4 * c, U.wd, 4 * c, (int)Pb, U.ci, 4 * c, ep);
+            unet_gemm_nt(s, EPI_F32, u->gch, 4 * c, nullptr, U.wd, 4 * c, (int)Pb, U.ci, 4 * c, ep);
         });
         if (l < 2) {
             u->prof.timed(s, "eltwise", [&] {
@@ -384,8 +413,8 @@ mem_status mem_unet_create(int32_t base, int32_t max_batch, int32_t size, uint64
         const ULayer& Y = u->L[i];
         if (Y.kind != 0) continue;
         const int l = (i < 8) ? i / 2 : 2 - (i - 8) / 3;
-        const size_t need = (size_t)P_at(u, B, l) * (size_t)std::max(Y.kf, Y.kd);
-        col = std::max(col, need);
+        const size_t kf = implicit(Y.ci, Y.ci) ? 0 : Y.kf, kd = implicit(Y.co, Y.co) ? 0 : Y.kd;
+        col = std::max(col, (size_t)P_at(u, B, l) * std::max(kf, kd));
     }
     const int64_t P0 = P_at(u, B, 0);
     ok = ok && ualloc(&u->x, P0 * 3) && ualloc(&u->out, P0 * 2) && ualloc(&u->col, col) &&
@@ -478,7 +507,7 @@ mem_status mem_unet_forward(mem_unet* u, const float* x, int32_t batch, float* o
     const int H = NLAY - 1;
     u->prof.timed(s, "head", [&] {
         unet_head_loss(s, u->d[0], u->base, P0, u->w + u->L[H].off, bias(u, u->w, H), nullptr, nullptr, 0.f, out,
-                       nullptr, nullptr, nullptr, nullptr);
+                       nullptr, nullptr, nullptr, nullptr, nullptr);
     });
     return finish(u, "mem_unet_forward");
 }

@@ -47,10 +47,23 @@ __device__ __forceinline__ void epilogue(const Epilogue& ep, int m, int n, float
     }
 }
 
-void unet_gemm_nt(hipStream_t s, int epi, const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, int M,
-                  int N, int K, const Epilogue& ep);
-void unet_gemm_tn(hipStream_t s, const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, int P, int M,
-                  int N, float* C, int64_t ldc, int n_cu);
+// The unfolded (im2col) matrix of a 3x3 zero-padded convolution input,
+// read in place: row = pixel of a B x S x S NHWC grid, column k = tap * ci +
+// channel, tap = 3 (dy + 1) + (dx + 1); channels at stride xs.  Usable when
+// ci and xs are multiples of 8 (a K slice of 8 stays inside one tap and is
+// one aligned 16-byte load).
+struct ConvSrc {
+    const uint16_t* x;
+    int xs, ci, S;
+};
+
+// A (M x K, row stride lda) is dense, or the unfolded input `conv` (then A
+// and lda are ignored and K = 9 ci).
+void unet_gemm_nt(hipStream_t s, int epi, const uint16_t* A, int64_t lda, const ConvSrc* conv, const uint16_t* B,
+                  int64_t ldb, int M, int N, int K, const Epilogue& ep);
+// B (P x N, row stride ldb) is dense, or the unfolded input `conv` (N = 9 ci).
+void unet_gemm_tn(hipStream_t s, const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, const ConvSrc* conv,
+                  int P, int M, int N, float* C, int64_t ldc, int n_cu);
 void unet_im2col3(hipStream_t s, const uint16_t* x, int xs, int xo, int B, int S, int ci, uint16_t* col,
                   int kpad);
 void unet_gather_children(hipStream_t s, const uint16_t* dy, int ys, int yo, int B, int S, int c, uint16_t* g);
@@ -61,9 +74,11 @@ void unet_add_f32(hipStream_t s, float* dst, int ds, const float* src, int ss, i
 void unet_relu_mask_add(hipStream_t s, const float* acc, int as, const float* add, int ads, const uint16_t* y,
                         int ys, int64_t rows, int c, uint16_t* g, int gs);
 void unet_colsum(hipStream_t s, const uint16_t* g, int gs, int64_t rows, int c, float* db);
+// Head output (out may be NULL) and, with a target, loss and head / d0
+// gradients; gout (P float2) is scratch.
 void unet_head_loss(hipStream_t s, const uint16_t* d0, int c, int64_t P, const float* w, const float* b,
                     const float* target, const float* mask, float inv_count, float* out, float* loss, float* gw,
-                    float* gb, uint16_t* gd0);
+                    float* gb, uint16_t* gd0, float2* gout);
 void unet_cast_bf16(hipStream_t s, const float* x, int64_t n, uint16_t* y);
 void unet_fill(hipStream_t s, float* x, int64_t n, float v);
 void unet_relayout(hipStream_t s, const float* w, int taps, int ci, int co, int kind, int kpad, uint16_t* dst);
