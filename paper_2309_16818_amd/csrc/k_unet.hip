@@ -88,59 +88,86 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v)
     return r;
 }
 
-// C = A B^T on a 64x64 tile; 4 waves, each a 32x32 quadrant of 2x2 MFMA
-// 16x16x32 blocks.  Lane l of an MFMA block supplies A[l % 16][8 (l / 16) ..
-// + 7] and B[l % 16][8 (l / 16) .. + 7] and receives D[4 (l / 16) + j][l % 16].
-template <int EPI, bool CONV>
+// C = A B^T on a (32 WM) x (32 WN) tile, WM WN = 4: four waves, each a
+// 32x32 quadrant of 2x2 MFMA 16x16x32 blocks.  Lane l of an MFMA block
+// supplies A[l % 16][8 (l / 16) .. + 7] and B[l % 16][8 (l / 16) .. + 7] and
+// receives D[4 (l / 16) + j][l % 16].  K advances in slices of 32 through two
+// LDS stages: the next slice's global loads are in flight while the MFMAs
+// consume the current one, with one barrier per slice.
+template <int EPI, bool CONV, int WM>
 __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A, int64_t lda, ConvSrc cs,
                                                  const uint16_t* __restrict__ B, int64_t ldb, int M,
                                                  int N, int K, Epilogue ep)
 {
-    __shared__ uint16_t sA[BM * LDSK];
-    __shared__ uint16_t sB[BN * LDSK];
-    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    constexpr int WN = 4 / WM, TM = 32 * WM, TN = 32 * WN;
+    constexpr int CA = TM * 4 / 256, CB = (TN * 4 + 255) / 256;  // 8-wide chunks per thread
+    __shared__ uint16_t sA[2][TM * LDSK];
+    __shared__ uint16_t sB[2][TN * LDSK];
+    const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int wm = (wave / WN) * 32, wn = (wave % WN) * 32;
     f32x4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; i++)
 #pragma unroll
         for (int j = 0; j < 2; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int lr = tid >> 2, lk = (tid & 3) * 8;  // 64 rows x 4 chunks of 8
-    // the pixel of this thread's A row (unfolded input)
-    int64_t pn = 0;
-    int pr = 0, pq = 0;
+    const int lk = (tid & 3) * 8;  // K offset of every chunk of this thread
+    int64_t pn[CA];
+    int pr[CA], pq[CA];
     ConvCursor cc{0, 0};
     if (CONV) {
-        const int m = m0 + lr;
-        pq = m % cs.S;
-        pr = (m / cs.S) % cs.S;
-        pn = m / (cs.S * cs.S);
+#pragma unroll
+        for (int u = 0; u < CA; u++) {
+            const int m = m0 + (tid >> 2) + 64 * u;
+            pq[u] = m % cs.S;
+            pr[u] = (m / cs.S) % cs.S;
+            pn[u] = m / (cs.S * cs.S);
+        }
         cc.start(lk, cs.ci);
     }
-    for (int k0 = 0; k0 < K; k0 += BK) {
-        uint4 va;
-        if (CONV) {
-            va = load8_conv(cs, pn, pr, pq, m0 + lr < M, cc);
-            cc.advance(BK, cs.ci);
-        } else {
-            va = load8(A, lda, m0 + lr, M, k0 + lk, K);
+    uint4 va[CA], vb[CB];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < CA; u++) {
+            const int r = (tid >> 2) + 64 * u;
+            va[u] = CONV ? load8_conv(cs, pn[u], pr[u], pq[u], m0 + r < M, cc) : load8(A, lda, m0 + r, M, k0 + lk, K);
         }
-        const uint4 vb = load8(B, ldb, n0 + lr, N, k0 + lk, K);
-        __syncthreads();
-        *(uint4*)&sA[lr * LDSK + lk] = va;
-        *(uint4*)&sB[lr * LDSK + lk] = vb;
-        __syncthreads();
-        const int fr = lane & 15, fk = (lane >> 4) * 8;
+        if (CONV) cc.advance(BK, cs.ci);
+#pragma unroll
+        for (int u = 0; u < CB; u++) {
+            const int r = (tid >> 2) + 64 * u;
+            vb[u] = (r < TN) ? load8(B, ldb, n0 + r, N, k0 + lk, K) : make_uint4(0, 0, 0, 0);
+        }
+    };
+    auto stash = [&](int st) {
+#pragma unroll
+        for (int u = 0; u < CA; u++) *(uint4*)&sA[st][((tid >> 2) + 64 * u) * LDSK + lk] = va[u];
+#pragma unroll
+        for (int u = 0; u < CB; u++) {
+            const int r = (tid >> 2) + 64 * u;
+            if (r < TN) *(uint4*)&sB[st][r * LDSK + lk] = vb[u];
+        }
+    };
+    load(0);
+    stash(0);
+    __syncthreads();
+    int cur = 0;
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        const bool more = k0 + BK < K;
+        if (more) load(k0 + BK);
 #pragma unroll
         for (int i = 0; i < 2; i++) {
-            const bf16x8 a = as_bf16x8(*(const uint4*)&sA[(wm + 16 * i + fr) * LDSK + fk]);
+            const bf16x8 a = as_bf16x8(*(const uint4*)&sA[cur][(wm + 16 * i + fr) * LDSK + fk]);
 #pragma unroll
             for (int j = 0; j < 2; j++) {
-                const bf16x8 b = as_bf16x8(*(const uint4*)&sB[(wn + 16 * j + fr) * LDSK + fk]);
+                const bf16x8 b = as_bf16x8(*(const uint4*)&sB[cur][(wn + 16 * j + fr) * LDSK + fk]);
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
             }
         }
+        if (more) stash(cur ^ 1);
+        __syncthreads();
+        cur ^= 1;
     }
 #pragma unroll
     for (int i = 0; i < 2; i++)
@@ -155,73 +182,119 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A,
 }
 
 // C[m][n] += sum_p A[p][m] B[p][n] over the pixel range of this block
-// (blockIdx.z of gridDim.z equal slices).
-template <bool CONV>
+// (blockIdx.z of gridDim.z equal slices), on a (32 WM) x (32 WN) tile.
+// Pixels advance in slices of 32 through two LDS stages holding the slices
+// transposed ([column][pixel]), the next slice's loads in flight during the
+// MFMAs.
+template <bool CONV, int WM>
 __global__ __launch_bounds__(256) void k_gemm_tn(const uint16_t* __restrict__ A, int64_t lda,
                                                  const uint16_t* __restrict__ B, int64_t ldb, ConvSrc cs, int P,
                                                  int M, int N, float* __restrict__ C, int64_t ldc)
 {
-    __shared__ uint16_t sA[BM * LDSK];  // [m][p]
-    __shared__ uint16_t sB[BN * LDSK];  // [n][p]
-    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    constexpr int WN = 4 / WM, TM = 32 * WM, TN = 32 * WN;
+    constexpr int CA = (TM * 4 + 255) / 256, CB = (TN * 4 + 255) / 256;
+    __shared__ uint16_t sA[2][TM * LDSK];  // [m][p]
+    __shared__ uint16_t sB[2][TN * LDSK];  // [n][p]
+    const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
     const int slice = (P + gridDim.z - 1) / gridDim.z;
     const int p_begin = blockIdx.z * slice;
     const int p_end = min(P, p_begin + slice);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int wm = (wave / WN) * 32, wn = (wave % WN) * 32;
     f32x4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; i++)
 #pragma unroll
         for (int j = 0; j < 2; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int lp = tid >> 3, lc = (tid & 7) * 8;  // 32 pixels x 8 chunks of 8 columns
-    // this thread's B columns (unfolded input): fixed tap and channel, and
-    // the pixel of its row, advanced by BK pixels per step
-    ConvCursor cc{0, 0};
-    int64_t pn = 0;
-    int pr = 0, pq = 0;
+    // chunk u of a thread: pixel lp = tid / (T / 8) within the slice, columns
+    // lc .. lc + 7; 32 pixels x T columns per operand
+    constexpr int APR = TM / 8, BPR = TN / 8;  // chunks per pixel row
+    ConvCursor cc[CB];
+    int64_t pn[CB];
+    int pr[CB], pq[CB];
     if (CONV) {
-        cc.start(n0 + lc, cs.ci);
-        const int p = p_begin + lp;
-        pq = p % cs.S;
-        pr = (p / cs.S) % cs.S;
-        pn = p / (cs.S * cs.S);
-    }
-    for (int p0 = p_begin; p0 < p_end; p0 += BK) {
-        const uint4 va = load8(A, lda, p0 + lp, p_end, m0 + lc, M);
-        uint4 vb;
-        if (CONV) {
-            vb = load8_conv(cs, pn, pr, pq, p0 + lp < p_end && n0 + lc < N, cc);
-            pq += BK;
-            while (pq >= cs.S) {
-                pq -= cs.S;
-                if (++pr == cs.S) {
-                    pr = 0;
-                    pn++;
-                }
-            }
-        } else {
-            vb = load8(B, ldb, p0 + lp, p_end, n0 + lc, N);
-        }
-        __syncthreads();
-        const uint16_t* ta = (const uint16_t*)&va;
-        const uint16_t* tb = (const uint16_t*)&vb;
 #pragma unroll
-        for (int j = 0; j < 8; j++) {  // transpose into [column][pixel]
-            sA[(lc + j) * LDSK + lp] = ta[j];
-            sB[(lc + j) * LDSK + lp] = tb[j];
+        for (int u = 0; u < CB; u++) {
+            const int ch = tid + 256 * u;
+            const int lp = ch / BPR, lc = (ch % BPR) * 8;
+            cc[u].start(n0 + lc, cs.ci);
+            const int p = p_begin + lp;
+            pq[u] = p % cs.S;
+            pr[u] = (p / cs.S) % cs.S;
+            pn[u] = p / (cs.S * cs.S);
         }
-        __syncthreads();
-        const int fr = lane & 15, fk = (lane >> 4) * 8;
+    }
+    uint4 va[CA], vb[CB];
+    auto load = [&](int p0) {
+#pragma unroll
+        for (int u = 0; u < CA; u++) {
+            const int ch = tid + 256 * u;
+            const int lp = ch / APR, lc = (ch % APR) * 8;
+            va[u] = (ch < 32 * APR) ? load8(A, lda, p0 + lp, p_end, m0 + lc, M) : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < CB; u++) {
+            const int ch = tid + 256 * u;
+            const int lp = ch / BPR, lc = (ch % BPR) * 8;
+            if (ch >= 32 * BPR) {
+                vb[u] = make_uint4(0, 0, 0, 0);
+            } else if (CONV) {
+                vb[u] = load8_conv(cs, pn[u], pr[u], pq[u], p0 + lp < p_end && n0 + lc < N, cc[u]);
+                pq[u] += BK;
+                while (pq[u] >= cs.S) {
+                    pq[u] -= cs.S;
+                    if (++pr[u] == cs.S) {
+                        pr[u] = 0;
+                        pn[u]++;
+                    }
+                }
+            } else {
+                vb[u] = load8(B, ldb, p0 + lp, p_end, n0 + lc, N);
+            }
+        }
+    };
+    auto stash = [&](int st) {
+#pragma unroll
+        for (int u = 0; u < CA; u++) {
+            const int ch = tid + 256 * u;
+            if (ch >= 32 * APR) continue;
+            const int lp = ch / APR, lc = (ch % APR) * 8;
+            const uint16_t* t = (const uint16_t*)&va[u];
+#pragma unroll
+            for (int j = 0; j < 8; j++) sA[st][(lc + j) * LDSK + lp] = t[j];
+        }
+#pragma unroll
+        for (int u = 0; u < CB; u++) {
+            const int ch = tid + 256 * u;
+            if (ch >= 32 * BPR) continue;
+            const int lp = ch / BPR, lc = (ch % BPR) * 8;
+            const uint16_t* t = (const uint16_t*)&vb[u];
+#pragma unroll
+            for (int j = 0; j < 8; j++) sB[st][(lc + j) * LDSK + lp] = t[j];
+        }
+    };
+    if (p_begin < p_end) {
+        load(p_begin);
+        stash(0);
+    }
+    __syncthreads();
+    int cur = 0;
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    for (int p0 = p_begin; p0 < p_end; p0 += BK) {
+        const bool more = p0 + BK < p_end;
+        if (more) load(p0 + BK);
 #pragma unroll
         for (int i = 0; i < 2; i++) {
-            const bf16x8 a = as_bf16x8(*(const uint4*)&sA[(wm + 16 * i + fr) * LDSK + fk]);
+            const bf16x8 a = as_bf16x8(*(const uint4*)&sA[cur][(wm + 16 * i + fr) * LDSK + fk]);
 #pragma unroll
             for (int j = 0; j < 2; j++) {
-                const bf16x8 b = as_bf16x8(*(const uint4*)&sB[(wn + 16 * j + fr) * LDSK + fk]);
+                const bf16x8 b = as_bf16x8(*(const uint4*)&sB[cur][(wn + 16 * j + fr) * LDSK + fk]);
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
             }
         }
+        if (more) stash(cur ^ 1);
+        __syncthreads();
+        cur ^= 1;
     }
 #pragma unroll
     for (int i = 0; i < 2; i++)
@@ -592,42 +665,56 @@ inline unsigned grid_for(int64_t n)
 
 }  // namespace
 
+// Narrow outputs (32 columns or fewer) take 128x32 tiles so no MFMA block
+// works on padding.
 void unet_gemm_nt(hipStream_t s, int epi, const uint16_t* A, int64_t lda, const ConvSrc* conv, const uint16_t* B,
                   int64_t ldb, int M, int N, int K, const Epilogue& ep)
 {
-    dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN);
     const ConvSrc cs = conv ? *conv : ConvSrc{nullptr, 0, 1, 1};
-#define MEM_GNT(E, CV) hipLaunchKernelGGL((k_gemm_nt<E, CV>), grid, dim3(256), 0, s, A, lda, cs, B, ldb, M, N, K, ep)
-    if (conv) {
-        switch (epi) {
-        case EPI_STORE: MEM_GNT(EPI_STORE, true); break;
-        case EPI_CONVT: MEM_GNT(EPI_CONVT, true); break;
-        default: MEM_GNT(EPI_F32, true); break;
-        }
-    } else {
-        switch (epi) {
-        case EPI_STORE: MEM_GNT(EPI_STORE, false); break;
-        case EPI_CONVT: MEM_GNT(EPI_CONVT, false); break;
-        default: MEM_GNT(EPI_F32, false); break;
-        }
+    const bool narrow = N <= 32;
+    const int TM = narrow ? 128 : 64, TN = narrow ? 32 : 64;
+    dim3 grid((M + TM - 1) / TM, (N + TN - 1) / TN);
+#define MEM_GNT(E, CV, W) \
+    hipLaunchKernelGGL((k_gemm_nt<E, CV, W>), grid, dim3(256), 0, s, A, lda, cs, B, ldb, M, N, K, ep)
+#define MEM_GNT_E(CV, W)                                   \
+    switch (epi) {                                         \
+    case EPI_STORE: MEM_GNT(EPI_STORE, CV, W); break;      \
+    case EPI_CONVT: MEM_GNT(EPI_CONVT, CV, W); break;      \
+    default: MEM_GNT(EPI_F32, CV, W); break;               \
     }
+    if (conv) {
+        if (narrow) { MEM_GNT_E(true, 4) } else { MEM_GNT_E(true, 2) }
+    } else {
+        if (narrow) { MEM_GNT_E(false, 4) } else { MEM_GNT_E(false, 2) }
+    }
+#undef MEM_GNT_E
 #undef MEM_GNT
 }
 
+// Narrow outputs (32 rows or fewer) take 32x128 tiles.
 void unet_gemm_tn(hipStream_t s, const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, const ConvSrc* conv,
                   int P, int M, int N, float* C, int64_t ldc, int n_cu)
 {
-    const int tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+    const bool narrow = M <= 32;
+    const int TM = narrow ? 32 : 64, TN = narrow ? 128 : 64;
+    const int tiles = ((M + TM - 1) / TM) * ((N + TN - 1) / TN);
     int split = (4 * n_cu + tiles - 1) / tiles;
     const int max_split = (P + 255) / 256;
     if (split > max_split) split = max_split;
     if (split < 1) split = 1;
-    dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN, split);
-    if (conv)
-        hipLaunchKernelGGL(k_gemm_tn<true>, grid, dim3(256), 0, s, A, lda, B, ldb, *conv, P, M, N, C, ldc);
-    else
-        hipLaunchKernelGGL(k_gemm_tn<false>, grid, dim3(256), 0, s, A, lda, B, ldb, ConvSrc{nullptr, 0, 1, 1}, P, M,
-                           N, C, ldc);
+    dim3 grid((M + TM - 1) / TM, (N + TN - 1) / TN, split);
+    const ConvSrc cs = conv ? *conv : ConvSrc{nullptr, 0, 1, 1};
+    if (conv) {
+        if (narrow)
+            hipLaunchKernelGGL((k_gemm_tn<true, 1>), grid, dim3(256), 0, s, A, lda, B, ldb, cs, P, M, N, C, ldc);
+        else
+            hipLaunchKernelGGL((k_gemm_tn<true, 2>), grid, dim3(256), 0, s, A, lda, B, ldb, cs, P, M, N, C, ldc);
+    } else {
+        if (narrow)
+            hipLaunchKernelGGL((k_gemm_tn<false, 1>), grid, dim3(256), 0, s, A, lda, B, ldb, cs, P, M, N, C, ldc);
+        else
+            hipLaunchKernelGGL((k_gemm_tn<false, 2>), grid, dim3(256), 0, s, A, lda, B, ldb, cs, P, M, N, C, ldc);
+    }
 }
 
 void unet_im2col3(hipStream_t s, const uint16_t* x, int xs, int xo, int B, int S, int ci, uint16_t* col, int kpad)
