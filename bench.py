@@ -30,9 +30,38 @@ sys.path.insert(0, ROOT)
 
 METRIC = "fused points/s + map-update latency (ms), plain vs batched/learned, at tolerance"
 HBM_PEAK_GBS = 8000.0
-# Vector ALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 4 cycles/wave-instr...
-# expressed as lane-instructions/s: 256 CU * 128 lanes/clk * 2.4 GHz.
-ALU_PEAK_LANE_OPS = 256 * 128 * 2.4e9
+# Vector ALU issue peak for integer / non-packed instructions: 256 CUs x 4
+# SIMDs x 16 lanes per clock x 2.4 GHz (the FP32 peak of 157.3 TFLOP/s counts
+# an FMA as two flops on 128 lanes).
+VALU_LANE_OPS = 256 * 64 * 2.4e9
+# VALU instructions a lane executes per cell of a Bresenham walk (step,
+# ray height, storage index, test), counted in the gfx950 ISA of the walk
+# loop of this build.
+WALK_VALU_PER_CELL = 40
+
+# HBM traffic of kernels from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled
+# by the same counters for a plain 256 MiB copy (profiles/), valid while the
+# kernel's sources hash to `sha`.
+TRAFFIC = {}
+
+
+def source_sha(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(ROOT, "paper_2309_16818_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+KERNEL_SOURCES = {"clear_march": ("k_points.hip", "update.h", "geom.h", "codec.h"),
+                  "project": ("k_image.hip", "update.h", "geom.h", "codec.h")}
+
+
+def traffic_bytes(kernel):
+    t = TRAFFIC.get(kernel)
+    if not t or t["sha"] != source_sha(KERNEL_SOURCES.get(kernel, ())):
+        return None
+    return t["bytes_per_launch"]
 
 
 def parse():
@@ -45,7 +74,9 @@ def parse():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--profile-events", type=int, default=1,
                     help="record HIP events around every launch in the timed region")
-    ap.add_argument("--workload", choices=["full", "batch", "learned"], default="full",
+    ap.add_argument("--frames-cache", default=None,
+                    help="full: .npz of generated frames to load (written first if missing)")
+    ap.add_argument("--workload", choices=["full", "batch", "learned", "copy"], default="full",
                     help="full: one robot at full rate; batch: 1024 uneven maps per step; "
                          "learned: the completion network's training and inference at 256x256")
     ap.add_argument("--pairs", type=int, default=288, help="learned: generated (input, target) windows")
@@ -272,13 +303,58 @@ def run_learned(args):
     print(json.dumps(out), flush=True)
 
 
-def gen_frames(n, seed, device):
+CAM_KEYS = ("T", "K", "K_feat", "rgb", "classes", "features")
+
+
+def run_copy(args):
+    """A plain device copy of 256 MiB (torch's copy kernel): the reference
+    for scaling rocprof's FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    n = 64 << 20
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(args.warmup + args.steps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": "copy", "bytes_read_per_launch": 4 * n, "bytes_written_per_launch": 4 * n,
+                      "launches": args.warmup + args.steps}), flush=True)
+
+
+def gen_frames(n, seed, device, cache=None):
+    """n frames of the full workload, generated (or loaded from / saved to
+    the .npz `cache`, so that a profiled run need not generate them)."""
     from paper_2309_16818_amd import synth
     t0 = time.time()
+    if cache and os.path.exists(cache):
+        z = np.load(cache)
+        if int(z["n"]) >= n and int(z["seed"]) == seed:
+            frames = []
+            for k in range(n):
+                f = dict(pose=z[f"pose{k}"], clouds=[], cameras=[])
+                j = 0
+                while f"c{k}_{j}_xyz" in z:
+                    f["clouds"].append(dict(xyz=z[f"c{k}_{j}_xyz"], T=z[f"c{k}_{j}_T"]))
+                    j += 1
+                j = 0
+                while f"m{k}_{j}_T" in z:
+                    f["cameras"].append({key: z[f"m{k}_{j}_{key}"] for key in CAM_KEYS})
+                    j += 1
+                frames.append(f)
+            return frames, time.time() - t0
     frames = []
     for k, (_, f) in enumerate(synth.iter_full_frames(seed=seed, n_frames=n, device=device)):
         frames.append(f)
         print(f"# frame {k + 1}/{n} generated ({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
+    if cache:
+        arrs = dict(n=n, seed=seed)
+        for k, f in enumerate(frames):
+            arrs[f"pose{k}"] = np.asarray(f["pose"])
+            for j, c in enumerate(f["clouds"]):
+                arrs[f"c{k}_{j}_xyz"], arrs[f"c{k}_{j}_T"] = c["xyz"], c["T"]
+            for j, c in enumerate(f["cameras"]):
+                for key in CAM_KEYS:
+                    arrs[f"m{k}_{j}_{key}"] = np.asarray(c[key])
+        np.savez(cache, **arrs)
     return frames, time.time() - t0
 
 
@@ -345,13 +421,15 @@ def main():
         return run_batch(args)
     if args.workload == "learned":
         return run_learned(args)
+    if args.workload == "copy":
+        return run_copy(args)
     import torch
     from paper_2309_16818_amd import mem
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
     n_frames = args.warmup + args.steps
-    frames, gen_s = gen_frames(n_frames, args.seed, "cuda")
+    frames, gen_s = gen_frames(n_frames, args.seed, "cuda", args.frames_cache)
     print(f"# generated {n_frames} frames in {gen_s:.1f}s", file=sys.stderr, flush=True)
     dframes = upload(frames)
     torch.cuda.synchronize()
@@ -394,11 +472,13 @@ def main():
             ach = b / (kd["total_ms"] * 1e-3) / 1e9
             roof = dict(kernel=dom, bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                         frac=round(ach / HBM_PEAK_GBS, 4), traffic=None)
-        else:  # ray walks: ALU / L2 bound; achieved in ray-cell visits
-            visits = st["ray_cells"] if dom == "clear_march" else st["occl_cells"]
-            rate = visits / (kd["total_ms"] * 1e-3)
-            roof = dict(kernel=dom, bound="alu", achieved=round(rate / 1e9, 3), unit="Gcell-visits/s",
-                        peak=None, frac=None, traffic=None)
+        else:  # ray walks: VALU bound; achieved in ray cells per second
+            cells = st["ray_steps"] if dom == "clear_march" else st["occl_steps"]
+            rate = cells / (kd["total_ms"] * 1e-3) / 1e9
+            peak = VALU_LANE_OPS / WALK_VALU_PER_CELL / 1e9
+            roof = dict(kernel=dom, bound="alu", achieved=round(rate, 2), unit="Gcell/s", peak=round(peak, 1),
+                        frac=round(rate / peak, 4), traffic=traffic_bytes(dom),
+                        cells_per_launch=round(cells / kd["launches"]), avg_us=kd["avg_us"])
     out = {
         "metric": METRIC, "value": round(pts_s, 1), "unit": "points/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall_ms, 4),
