@@ -42,7 +42,11 @@ WALK_VALU_PER_CELL = 40
 # HBM traffic of kernels from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled
 # by the same counters for a plain 256 MiB copy (profiles/), valid while the
 # kernel's sources hash to `sha`.
-TRAFFIC = {}
+TRAFFIC = {
+    # k_clear_march, full-rate workload: FETCH_SIZE 2146.9 KiB x 1.99985 (a
+    # 256 MiB copy reads FETCH_SIZE 131083.5 KiB) + WRITE_SIZE 461.1 KiB x 1.0
+    "clear_march": {"bytes_per_launch": 4868743, "sha": "6e58dfff130780b9"},
+}
 
 
 def source_sha(files):
@@ -76,7 +80,9 @@ def parse():
                     help="record HIP events around every launch in the timed region")
     ap.add_argument("--frames-cache", default=None,
                     help="full: .npz of generated frames to load (written first if missing)")
-    ap.add_argument("--workload", choices=["full", "batch", "learned", "copy"], default="full",
+    ap.add_argument("--precision-frames", type=int, default=8,
+                    help="precision: frames run by every storage type and by the binary64 oracle")
+    ap.add_argument("--workload", choices=["full", "batch", "learned", "copy", "precision"], default="full",
                     help="full: one robot at full rate; batch: 1024 uneven maps per step; "
                          "learned: the completion network's training and inference at 256x256")
     ap.add_argument("--pairs", type=int, default=288, help="learned: generated (input, target) windows")
@@ -306,6 +312,121 @@ def run_learned(args):
 CAM_KEYS = ("T", "K", "K_feat", "rgb", "classes", "features")
 
 
+def run_precision(args):
+    """Reduced-precision storage: the full-rate workload with a 384-channel
+    visual-feature layer (Gaussian rule) stored in FP32, BF16 and FP8 e4m3
+    with per-channel scales (accumulation in FP32 throughout; heights and
+    variances FP32).  Times a frame for every storage type, sweeps the
+    feature width 64 -> 384, and reports every layer's error against the
+    binary64 oracle run on the same frames from the same empty map."""
+    import torch
+    import oracle as O
+    from paper_2309_16818_amd import mem, synth
+    torch.cuda.set_device(0)
+    n = args.precision_frames
+    t0 = time.time()
+    frames = [f for _, f in synth.iter_full_frames(seed=args.seed, n_frames=n, device="cuda", n_feat=384)]
+    print(f"# generated {n} frames in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    dframes = upload(frames)
+    p = dict(synth.FULL_MAP)
+    W, H, res = p.pop("width"), p.pop("height"), p.pop("resolution")
+    feats = np.concatenate([c["features"].reshape(-1, 384) for f in frames for c in f["cameras"]])
+    amax = np.abs(feats).max(0).astype(np.float32)  # per-channel FP8 scale: amax / 448
+    storages = [("f32", mem.MEM_F32), ("bf16", mem.MEM_BF16), ("fp8_e4m3", mem.MEM_FP8_E4M3)]
+
+    def make(storage, C):
+        layers = [mem.Layer(3, mem.MEM_EXPAVG, 0.5), mem.Layer(C, mem.MEM_GAUSS, 1.0, storage,
+                                                               list(amax[:C]) if storage == mem.MEM_FP8_E4M3 else None),
+                  mem.Layer(20, mem.MEM_DIRICHLET, 1.0)]
+        return mem.Map(mem.MapParams(W, H, res, layers=layers, **p))
+
+    def frame(m, f, feat):
+        x, y, _ = f["pose"]
+        m.move(x, y)
+        for c in f["clouds"]:
+            m.input_pointcloud(c["xyz"], c["T"])
+        for c, ft in zip(f["cameras"], feat):
+            m.input_images([(c["rgb"], c["K"], [(8, 0, 3)]), (ft, c["K_feat"], [(9, 0, ft.shape[-1])]),
+                            (c["classes"], c["K"], [(10, 0, 20)])], c["T"])
+
+    def timed_run(storage, C, keep=False):
+        feat = [[c["features"][..., :C].contiguous() for c in f["cameras"]] for f in dframes]
+        m = make(storage, C)
+        m.reset_stats()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+        m.profile_enable(True)
+        m.profile_read()
+        for k, f in enumerate(dframes):
+            ev[k][0].record()
+            frame(m, f, feat[k])
+            ev[k][1].record()
+        torch.cuda.synchronize()
+        kern = m.profile_read()
+        lat = np.array([a.elapsed_time(b) for a, b in ev])[1:]  # first frame: empty map
+        st = m.stats()
+        out = dict(ms_per_frame=round(float(lat.mean()), 4), points_per_s=round(st["points_accepted"] / (lat.sum() * 1e-3 * n / (n - 1)), 1),
+                   gather_fuse_ms_per_frame=round(kern.get("gather_fuse", (0, 0.0))[1] / n, 4),
+                   state_mb=round(W * H * C * {mem.MEM_F32: 4, mem.MEM_BF16: 2, mem.MEM_FP8_E4M3: 1}[storage] / 2**20, 1))
+        if keep:
+            return out, m
+        m.close()
+        return out
+
+    runs, maps = {}, {}
+    for name, stg in storages:
+        runs[name], maps[name] = timed_run(stg, 384, keep=True)
+        print(f"# {name}: {runs[name]}", file=sys.stderr, flush=True)
+    sweep = {name: {C: timed_run(stg, C)["ms_per_frame"] for C in (64, 128, 256, 384)} for name, stg in storages}
+    print(f"# sweep {sweep}", file=sys.stderr, flush=True)
+    # binary64 oracle on the same frames
+    t1 = time.time()
+    o = O.OracleMap(W, H, res, layers=[(3, 1, 0.5), (384, 2, 1.0), (20, 3, 1.0)], **p)
+    for f in frames:
+        x, y, _ = f["pose"]
+        o.move(x, y)
+        for c in f["clouds"]:
+            o.input_pointcloud(c["xyz"], c["T"])
+        for c in f["cameras"]:
+            o.input_image(c["rgb"], c["K"], c["T"], bind=[(8, 0, 3)])
+            o.input_image(c["features"], c["K_feat"], c["T"], bind=[(9, 0, 384)])
+            o.input_image(c["classes"], c["K"], c["T"], bind=[(10, 0, 20)])
+    print(f"# oracle {n} frames in {time.time() - t1:.1f}s", file=sys.stderr, flush=True)
+
+    def err(g, r):
+        ok = np.isfinite(r).all(-1) & np.isfinite(g).all(-1)
+        g, r = g[ok].astype(np.float64), r[ok]
+        d = np.linalg.norm(g - r, axis=-1)
+        nr = np.maximum(np.linalg.norm(r, axis=-1), 1e-30)
+        cos = (g * r).sum(-1) / np.maximum(np.linalg.norm(g, axis=-1) * nr, 1e-30)
+        return dict(cells=int(ok.sum()), rel_rms=float(np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-30)),
+                    rel_max=float((d / nr).max()) if len(d) else 0.0, cos_mean=float(cos.mean()) if len(d) else 1.0)
+
+    ref = {"height": o.get_layer(0)[..., None], "variance": o.get_layer(1)[..., None], "rgb": o.get_layer(8),
+           "features_mu": o.get_layer(9), "features_var": o.get_layer(9, 1).reshape(H, W, 1),
+           "classes": o.get_layer(10)}
+    errors = {}
+    for name, m in maps.items():
+        got = {"height": m.get_layer(0).cpu().numpy()[..., None], "variance": m.get_layer(1).cpu().numpy()[..., None],
+               "rgb": m.get_layer(8).cpu().numpy(), "features_mu": m.get_layer(9).cpu().numpy(),
+               "features_var": m.get_layer(9, 1).cpu().numpy().reshape(H, W, 1),
+               "classes": m.get_layer(10).cpu().numpy()}
+        errors[name] = {k: {q: (round(v, 7) if isinstance(v, float) else v) for q, v in err(got[k], ref[k]).items()}
+                        for k in ref}
+        m.close()
+    out = {
+        "metric": METRIC, "value": runs["bf16"]["points_per_s"], "unit": "points/s", "n_gpus": 1,
+        "steps": n - 1, "warmup": 1, "ms_per_step": runs["bf16"]["ms_per_frame"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "precision: full-rate single robot with a 384-channel Gaussian feature layer "
+                               "stored in FP32 / BF16 / FP8 e4m3 (per-channel scales), FP32 accumulation; "
+                               "errors after all frames against the binary64 oracle from the same empty map",
+                   "frames": n},
+        "value_is": "fused points/s with the feature layer in BF16",
+        "storage": runs, "channel_sweep_ms_per_frame": sweep, "errors_vs_binary64": errors,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_copy(args):
     """A plain device copy of 256 MiB (torch's copy kernel): the reference
     for scaling rocprof's FETCH_SIZE / WRITE_SIZE counters to bytes."""
@@ -423,6 +544,8 @@ def main():
         return run_learned(args)
     if args.workload == "copy":
         return run_copy(args)
+    if args.workload == "precision":
+        return run_precision(args)
     import torch
     from paper_2309_16818_amd import mem
 
