@@ -335,7 +335,7 @@ typedef struct mem_batch_input {
 
 /* Sizes the autotuner chooses (read back with mem_batch_get_tuning). */
 typedef struct mem_batch_tuning {
-    int32_t chunk;            /* points per ingest / clearing work item          */
+    int32_t chunk;            /* points per clearing work item                   */
     int32_t wg_per_cu;        /* persistent workgroups per compute unit          */
     int32_t tile;             /* side of the square cell tiles of projection     */
     int32_t graph;            /* 1: the step runs as a captured HIP graph        */

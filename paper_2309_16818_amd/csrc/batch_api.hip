@@ -94,6 +94,12 @@ struct mem_batch {
     int n_tiles = 0, tiles_side = 0;
     BatchItem* gitems = nullptr;
     int n_gitems = 0;
+    BatchItem* itiles = nullptr;
+    int n_itiles = 0, itile_h = 64;
+    std::vector<int> itile_base, itiles_x;  // per map
+    float4* rec = nullptr;                  // binned points, max_points records
+    int* tile_start = nullptr;
+    int* tile_cnt = nullptr;
 
     Staging stg[2];
     int next_stg = 0;
@@ -143,6 +149,10 @@ void free_batch(mem_batch* b)
     (void)hipFree(b->tables);
     (void)hipFree(b->tiles);
     (void)hipFree(b->gitems);
+    (void)hipFree(b->itiles);
+    (void)hipFree(b->rec);
+    (void)hipFree(b->tile_start);
+    (void)hipFree(b->tile_cnt);
     for (auto& L : b->layers) (void)hipFree(L.scale);
     delete b;
 }
@@ -199,6 +209,27 @@ mem_status build_tiles(mem_batch* b, int side)
     return MEM_OK;
 }
 
+// Ingest tiles: kIngestTileW x itile_h blocks of every map's storage cells,
+// as tall as the device's LDS allows (64 or 32 rows).
+mem_status build_itiles(mem_batch* b)
+{
+    b->itile_h = batch_tile_ingest_lds_bytes(64) <= (size_t)b->max_lds ? 64 : 32;
+    std::vector<BatchItem> t;
+    for (int m = 0; m < b->n; m++) {
+        b->itile_base.push_back((int)t.size());
+        b->itiles_x.push_back((b->W[m] + kIngestTileW - 1) / kIngestTileW);
+        for (int y = 0; y < b->H[m]; y += b->itile_h)
+            for (int x = 0; x < b->W[m]; x += kIngestTileW) t.push_back(BatchItem{m, x, y, 0});
+    }
+    BTRY(b, hipMalloc((void**)&b->itiles, sizeof(BatchItem) * t.size()));
+    BTRY(b, hipMemcpy(b->itiles, t.data(), sizeof(BatchItem) * t.size(), hipMemcpyHostToDevice));
+    b->n_itiles = (int)t.size();
+    BTRY(b, hipMalloc((void**)&b->tile_start, sizeof(int) * t.size()));
+    BTRY(b, hipMalloc((void**)&b->tile_cnt, sizeof(int) * t.size()));
+    BTRY(b, hipMalloc((void**)&b->rec, sizeof(float4) * (size_t)std::max<int64_t>(b->max_points, 1)));
+    return MEM_OK;
+}
+
 void drop_graphs(mem_batch* b)
 {
     for (auto& s : b->stg) {
@@ -229,6 +260,12 @@ BatchDev device_view(const mem_batch* b)
     d.chunk = b->bl.chunk;
     d.tiles = b->tiles;
     d.gitems = b->gitems;
+    d.itiles = b->itiles;
+    d.n_itiles = b->n_itiles;
+    d.itile_h = b->itile_h;
+    d.rec = b->rec;
+    d.tile_start = b->tile_start;
+    d.tile_cnt = b->tile_cnt;
     d.n_tiles = b->n_tiles;
     d.n_gitems = b->n_gitems;
     d.n_maps = b->n;
@@ -314,6 +351,9 @@ mem_status prepare(mem_batch* b, const mem_batch_input* in, Staging& s, size_t* 
             M.cam.w[0] = b->cam_w;
             M.cam.min_depth = b->min_depth;
         }
+        M.itile_base = b->itile_base[m];
+        M.itiles_x = b->itiles_x[m];
+        M.pad0 = M.pad1 = 0;
         C[m] = (int)nc;
         nc += (M.pt_end - M.pt_begin + b->bl.chunk - 1) / b->bl.chunk;
     }
@@ -539,7 +579,7 @@ mem_status mem_batch_create(const mem_batch_params* p, void* stream, mem_batch**
         }
     }
     if (hipMemcpy(b->gitems, gi.data(), sizeof(BatchItem) * gi.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        build_tiles(b, 16) != MEM_OK) {
+        build_tiles(b, 16) != MEM_OK || build_itiles(b) != MEM_OK) {
         free_batch(b);
         return api_fail(MEM_E_HIP, "batch tables");
     }
@@ -584,9 +624,8 @@ mem_status mem_batch_set_tuning(mem_batch* b, const mem_batch_tuning* t)
 {
     if (mem_status st = busable(b)) return st;
     if (!t) return api_fail(MEM_E_ARG, "tuning is NULL");
-    if ((t->chunk != 512 && t->chunk != 1024 && t->chunk != 2048) ||
-        batch_ingest_lds_bytes(t->chunk) > (size_t)b->max_lds)
-        return api_fail(MEM_E_ARG, "chunk must be 512, 1024 or 2048 (and fit in LDS)");
+    if (t->chunk != 512 && t->chunk != 1024 && t->chunk != 2048)
+        return api_fail(MEM_E_ARG, "chunk must be 512, 1024 or 2048");
     if (t->wg_per_cu < 1 || t->wg_per_cu > 16) return api_fail(MEM_E_ARG, "wg_per_cu must be 1..16");
     if (t->tile != 8 && t->tile != 16) return api_fail(MEM_E_ARG, "tile must be 8 or 16");
     (void)hipDeviceSynchronize();
@@ -636,7 +675,6 @@ mem_status mem_batch_tune(mem_batch* b, const mem_batch_input* in, void* stream)
         for (int wi = 0; wi < 3 && !err; wi++)
             for (int ti = 0; ti < 2 && !err; ti++) {
                 mem_batch_tuning t{chunks[ci], wgs[wi], tiles[ti], 1, 0.0};
-                if (batch_ingest_lds_bytes(t.chunk) > (size_t)b->max_lds) continue;
                 if ((err = mem_batch_set_tuning(b, &t))) break;
                 // warm-up step builds the graph, then 3 timed steps
                 if ((err = run_step(b, in, s))) break;

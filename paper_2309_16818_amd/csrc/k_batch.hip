@@ -8,8 +8,11 @@
 //
 //   k_b_prep      zero the work-queue counters and per-map pair counts
 //   k_b_reset     cells entering each map's grid (robot motion)
-//   k_b_zero      per-cloud accumulators of every cell (dense)
-//   k_b_ingest    (map, point chunk) items: LDS-binned aggregation
+//   k_b_bin       map items: accepted points binned by ingest tile (counting
+//                 sort in LDS)
+//   k_b_tile_ingest (map, cell block) items: per-cloud sums of the block's
+//                 binned points in LDS, written with plain stores (no
+//                 zeroing pass, no global atomics)
 //   k_b_march     (map, point chunk) items: clearing walks
 //   k_b_finalize  every cell (dense): height fusion and clearing
 //   k_b_project   (map, tile) items: frustum, pixel, occlusion, pair lists
@@ -85,39 +88,167 @@ __global__ __launch_bounds__(kBatchWG) void k_b_reset(BatchDev d, BatchLayers ls
     }
 }
 
-__global__ __launch_bounds__(256) void k_b_zero(BatchDev d)
+// Map items: bins the map's accepted points by ingest tile (a counting
+// sort in LDS: histogram, scan, scatter), one point transform per point and
+// pass, so each tile's workgroup later reads only its own points.  Records
+// of map m fill [pt_begin, pt_begin + accepted) in tile order.  Counts the
+// map's points and drops.
+__global__ __launch_bounds__(kBatchWG) void k_b_bin(BatchDev d, const float* __restrict__ xyz, float c0, float c1,
+                                                    float mr2)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d.total_cells;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        d.cnt[i] = 0;
-        d.wsum[i] = 0.0f;
-        d.ssum[i] = 0.0f;
-        d.clr[i] = 0;
-    }
-}
-
-__global__ __launch_bounds__(kBatchWG) void k_b_ingest(BatchDev d, const float* __restrict__ xyz,
-                                                       float c0, float c1, float mr2,
-                                                       int slots_log2)
-{
-    extern __shared__ char s_raw[];
-    const int slots = 1 << slots_log2;
-    const IngestLds lds{(int*)s_raw, (int*)s_raw + slots, (float*)s_raw + 2 * slots,
-                        (float*)s_raw + 3 * slots, (float2*)((float*)s_raw + 4 * slots), nullptr,
-                        slots_log2};
+    __shared__ int s_hist[kBinTiles];
+    __shared__ int s_part[kBatchWG];
     __shared__ int s_item;
-    PointBinds pb{};
     PointCounts pc;
-    const int n = d.n_items[1];
-    for (int it = next_item(d.qctr, 1, n, &s_item); it >= 0; it = next_item(d.qctr, 1, n, &s_item)) {
-        int64_t b0, b1;
-        const BatchMap& m = d.maps[chunk_item(d, it, b0, b1)];
-        ingest_range(m.g, xyz, b0, b1, nullptr, m.T, c0, c1, mr2, pb, map_accum(d, m), lds, pc);
+    int points_in = 0;
+    const int sh = d.itile_h == 64 ? 6 : 5;
+    for (int it = next_item(d.qctr, 8, d.n_maps, &s_item); it >= 0; it = next_item(d.qctr, 8, d.n_maps, &s_item)) {
+        const BatchMap& m = d.maps[it];
+        const int W = m.g.W, H = m.g.H;
+        const int ntiles = m.itiles_x * ((H + d.itile_h - 1) >> sh);
+        int64_t base = m.pt_begin;
+        for (int r0 = 0; r0 < ntiles; r0 += kBinTiles) {
+            const int nr = min(kBinTiles, ntiles - r0);
+            for (int k = threadIdx.x; k < kBinTiles; k += blockDim.x) s_hist[k] = 0;
+            __syncthreads();
+            // pass 1 counts, pass 2 scatters; both transform every point
+            for (int pass = 0; pass < 2; pass++) {
+                constexpr int U = 8;
+                for (int64_t i0 = m.pt_begin + threadIdx.x; i0 < m.pt_end; i0 += (int64_t)U * blockDim.x) {
+                    float p3[U][3];
+#pragma unroll
+                    for (int u = 0; u < U; u++) {
+                        const int64_t i = i0 + (int64_t)u * blockDim.x;
+                        const bool in = i < m.pt_end;
+                        p3[u][0] = in ? xyz[3 * i] : 0.0f;
+                        p3[u][1] = in ? xyz[3 * i + 1] : 0.0f;
+                        p3[u][2] = in ? xyz[3 * i + 2] : 0.0f;
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; u++) {
+                        const bool in = i0 + (int64_t)u * blockDim.x < m.pt_end;
+                        float px, py, pz, r2;
+                        int ix, iy;
+                        const int r = in ? point_cell(m.g, m.T, mr2, p3[u][0], p3[u][1], p3[u][2], px, py, pz, r2,
+                                                      ix, iy)
+                                         : 1;  // 1: no point
+                        if (pass == 0 && r0 == 0 && in) {
+                            points_in++;
+                            pc.acc += (r == 0);
+                            pc.nonfinite += (r == -1);
+                            pc.range += (r == -2);
+                            pc.outside += (r == -3);
+                        }
+                        int t = -1, sx = 0, sy = 0;
+                        if (r == 0) {
+                            sx = ix + m.g.rx;
+                            sx -= (sx >= W) ? W : 0;
+                            sy = iy + m.g.ry;
+                            sy -= (sy >= H) ? H : 0;
+                            t = (sy >> sh) * m.itiles_x + (sx >> 6) - r0;
+                            if (t >= nr) t = -1;
+                        }
+                        if (t < 0) continue;
+                        const int pos = atomicAdd(&s_hist[t], 1);
+                        if (pass == 1) {
+                            const float sig = c0 + c1 * r2;
+                            d.rec[base + pos] = make_float4(__int_as_float(sx | (sy << 16)), pz, sig * sig, 0.0f);
+                        }
+                    }
+                }
+                __syncthreads();
+                if (pass == 0) {
+                    // exclusive scan of the counts: 16 per thread, then across threads
+                    constexpr int PER = kBinTiles / kBatchWG;
+                    int run = 0;
+                    for (int q = 0; q < PER; q++) run += s_hist[threadIdx.x * PER + q];
+                    s_part[threadIdx.x] = run;
+                    __syncthreads();
+                    if (threadIdx.x == 0) {
+                        int acc = 0;
+                        for (int q = 0; q < kBatchWG; q++) {
+                            const int v = s_part[q];
+                            s_part[q] = acc;
+                            acc += v;
+                        }
+                    }
+                    __syncthreads();
+                    int off = s_part[threadIdx.x];
+                    for (int q = 0; q < PER; q++) {
+                        const int k = threadIdx.x * PER + q;
+                        const int c = s_hist[k];
+                        if (k < nr) {
+                            d.tile_start[m.itile_base + r0 + k] = (int)(base + off);
+                            d.tile_cnt[m.itile_base + r0 + k] = c;
+                        }
+                        s_hist[k] = off;  // becomes the scatter cursor
+                        off += c;
+                    }
+                    __syncthreads();
+                }
+            }
+            // the next range's records follow this range's
+            if (threadIdx.x == 0) s_part[0] = s_hist[kBinTiles - 1];
+            __syncthreads();
+            base += s_part[0];
+            __syncthreads();
+        }
     }
     const int ids[5] = {ST_ACCEPTED, ST_NONFINITE, ST_RANGE, ST_OUTSIDE, ST_POINTS_IN};
-    int vals[5] = {pc.acc, pc.nonfinite, pc.range, pc.outside,
-                   pc.acc + pc.nonfinite + pc.range + pc.outside};
+    int vals[5] = {pc.acc, pc.nonfinite, pc.range, pc.outside, points_in};
     block_stats(d.stats, ids, vals);
+}
+
+// (map, tile) items: the workgroup owns a kIngestTileW x itile_h block of
+// its map's storage cells, sums the block's binned points in dense LDS
+// arrays (counts, 1/v, z/v and the (z, v) of the first point) and writes
+// every cell of the block with plain stores: per-cloud sums, the
+// single-point stash and a zero vote count.  No global atomics, and the
+// block is written whether or not it received points, so no separate
+// zeroing pass is needed.
+__global__ __launch_bounds__(kBatchWG) void k_b_tile_ingest(BatchDev d)
+{
+    extern __shared__ char s_raw[];
+    const int TH = d.itile_h, NC = kIngestTileW * TH;
+    int* s_cnt = (int*)s_raw;
+    float* s_w = (float*)(s_cnt + NC);
+    float* s_s = s_w + NC;
+    float2* s_first = (float2*)(s_s + NC);
+    __shared__ int s_item;
+    for (int it = next_item(d.qctr, 1, d.n_itiles, &s_item); it >= 0; it = next_item(d.qctr, 1, d.n_itiles, &s_item)) {
+        const BatchItem I = d.itiles[it];
+        const BatchMap& m = d.maps[I.map];
+        const int W = m.g.W, x0 = I.a, y0 = I.b;
+        for (int k = threadIdx.x; k < NC; k += blockDim.x) {
+            s_cnt[k] = 0;
+            s_w[k] = 0.0f;
+            s_s[k] = 0.0f;
+        }
+        __syncthreads();
+        const int r0 = d.tile_start[it], n = d.tile_cnt[it];
+        for (int j = threadIdx.x; j < n; j += blockDim.x) {
+            const float4 rc = d.rec[r0 + j];
+            const int c = __float_as_int(rc.x);
+            const int k = ((c >> 16) - y0) * kIngestTileW + (c & 0xffff) - x0;
+            const float w = 1.0f / rc.z;
+            if (atomicAdd(&s_cnt[k], 1) == 0) s_first[k] = make_float2(rc.y, rc.z);
+            atomicAdd(&s_w[k], w);
+            atomicAdd(&s_s[k], rc.y * w);
+        }
+        __syncthreads();
+        const int tw = min(kIngestTileW, W - x0), th = min(TH, m.g.H - y0);
+        for (int k = threadIdx.x; k < kIngestTileW * th; k += blockDim.x) {
+            const int lx = k % kIngestTileW, ly = k / kIngestTileW;
+            if (lx >= tw) continue;
+            const int64_t st = m.cell_off + (int64_t)(y0 + ly) * W + x0 + lx;
+            const int c = s_cnt[k];
+            d.cnt[st] = c;
+            d.wsum[st] = s_w[k];
+            d.ssum[st] = s_s[k];
+            d.clr[st] = 0;
+            if (c == 1) d.stash[st] = s_first[k];  // a single point sets an empty cell exactly
+        }
+    }
 }
 
 __global__ __launch_bounds__(kBatchWG) void k_b_march(BatchDev d, const float* __restrict__ xyz,
@@ -225,9 +356,9 @@ __global__ __launch_bounds__(kBatchWG) void k_b_gather(BatchDev d, int queue,
 
 }  // namespace
 
-size_t batch_ingest_lds_bytes(int chunk)
+size_t batch_tile_ingest_lds_bytes(int tile_h)
 {
-    return (size_t)2 * chunk * (4 + 4 + 4 + 4 + 8);
+    return (size_t)kIngestTileW * tile_h * (sizeof(int) + 2 * sizeof(float) + sizeof(float2));
 }
 
 void launch_batch_step(hipStream_t s, const BatchDev& d, const BatchLaunch& bl, const float* xyz,
@@ -243,11 +374,9 @@ void launch_batch_step(hipStream_t s, const BatchDev& d, const BatchLaunch& bl, 
     hipLaunchKernelGGL(k_b_reset, dim3(bl.grid), dim3(kBatchWG), 0, s, d, ls);
     int64_t zb = (d.total_cells + 255) / 256;
     if (zb > 8192) zb = 8192;
-    hipLaunchKernelGGL(k_b_zero, dim3((unsigned)zb), dim3(256), 0, s, d);
-    int slots_log2 = 0;
-    while ((1 << slots_log2) < 2 * bl.chunk) slots_log2++;
-    hipLaunchKernelGGL(k_b_ingest, dim3(bl.grid), dim3(kBatchWG), batch_ingest_lds_bytes(bl.chunk), s,
-                       d, xyz, c0, c1, mr2, slots_log2);
+    hipLaunchKernelGGL(k_b_bin, dim3(bl.grid), dim3(kBatchWG), 0, s, d, xyz, c0, c1, mr2);
+    hipLaunchKernelGGL(k_b_tile_ingest, dim3(bl.grid), dim3(kBatchWG), batch_tile_ingest_lds_bytes(d.itile_h), s,
+                       d);
     if (clear_min > 0)
         hipLaunchKernelGGL(k_b_march, dim3(bl.grid), dim3(kBatchWG), 0, s, d, xyz, mr2, margin);
     hipLaunchKernelGGL(k_b_finalize, dim3((unsigned)zb), dim3(256), 0, s, d, clear_min);

@@ -153,6 +153,9 @@ struct BatchMap {
     int64_t img_off;        // first element of the map's image
     Pose T;                 // sensor pose of this step
     Camera cam;             // this step's camera (cam.n = 0: none)
+    int itile_base;         // first ingest tile of the map
+    int itiles_x;           // ingest tiles per row of storage cells
+    int pad0, pad1;
 };
 
 struct BatchRect {          // cells of map `map` entering the grid this step
@@ -181,12 +184,18 @@ struct BatchDev {
     const int* chunk_start;  // [n_maps + 1]: first point-chunk item of each map
     const BatchItem* tiles;  // (map, x0, y0): projection tiles
     const BatchItem* gitems; // (map, first pair): gather items
+    const BatchItem* itiles; // (map, sx0, sy0): ingest tiles of storage cells
+    float4* rec;             // accepted points binned by ingest tile: (sx | sy << 16, z, v, -)
+    int* tile_start;         // [n_itiles] first record of each ingest tile
+    int* tile_cnt;           // [n_itiles] its records
     int n_tiles, n_gitems, n_maps, chunk;
+    int n_itiles, itile_h;   // ingest tiles are kIngestTileW x itile_h cells
     int64_t total_cells;
     unsigned long long* stats;
 };
 
-constexpr int kQueues = 8;
+constexpr int kQueues = 10;  // 0 reset, 1 ingest tiles, 2 march, 3 project, 4-7 gathers, 8 binning
+constexpr int kIngestTileW = 64;  // ingest tile width (storage cells)
 constexpr int kGatherItem = 4096;  // visible pairs per gather work item
 
 struct BatchLaunch {        // tuning of one step
@@ -199,7 +208,9 @@ void launch_batch_step(hipStream_t s, const BatchDev& d, const BatchLaunch& bl, 
                        float c0, float c1, float mr2, float margin, int clear_min,
                        const LayerDev* L, int nL, const void* images, int img_dtype, int cam_c,
                        int cam_w, const mem_binding* ib, int n_ib);
-size_t batch_ingest_lds_bytes(int chunk);
+// LDS of the tile-owned ingest for tiles of kIngestTileW x tile_h cells.
+size_t batch_tile_ingest_lds_bytes(int tile_h);
+constexpr int kBinTiles = 4096;  // ingest tiles a binning pass histograms at once
 
 void launch_reset_rect(hipStream_t s, const Grid& g, int x0, int x1, int y0, int y1, float* h,
                        float* v, int* cnt, int* clr, const LayerDev* L, int nL);
