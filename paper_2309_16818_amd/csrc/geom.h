@@ -267,35 +267,36 @@ __device__ __forceinline__ int walk_range_skip(const Grid& g, const Ray& r, cons
                 continue;
             }
         }
-        // up to U cells: positions and ray heights first, loads only if the
-        // run may matter
+        // up to U cells: positions only (a few integer operations per cell);
+        // ray heights, storage indices and loads only if the run may matter
         const int n = min(U, end - i);
+        int px[U], py[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            if (u < n) L.step();
+            px[u] = L.x;
+            py[u] = L.y;
+        }
+        i += n;
+        {
+            LineWalk A = L, B = L;  // first and last cell of the run
+            A.x = px[0];
+            A.y = py[0];
+            if (skip(box_max(g, tm.t8, tm.tw8, 3, px[0], py[0], L.x, L.y), walk_height(g, r, A),
+                     walk_height(g, r, B)))
+                continue;
+        }
         int st[U];
-        float zr[U];
-        int x0 = 0, y0 = 0, x1 = 0, y1 = 0;
-        float z0 = 0.0f, z1 = 0.0f;
+        float zr[U], hk[U];
 #pragma unroll
         for (int u = 0; u < U; u++) {
             st[u] = -1;
             zr[u] = 0.0f;
-            if (u < n) {
-                L.step();
-                zr[u] = walk_height(g, r, L);
-                if (u == 0) {
-                    x0 = L.x;
-                    y0 = L.y;
-                    z0 = zr[u];
-                }
-                x1 = L.x;
-                y1 = L.y;
-                z1 = zr[u];
-                const bool in = r.all_inside || (L.x >= 0 && L.x < g.W && L.y >= 0 && L.y < g.H);
-                if (in) st[u] = storage_index(g, L.x, L.y);
+            if (u < n && (r.all_inside || (px[u] >= 0 && px[u] < g.W && py[u] >= 0 && py[u] < g.H))) {
+                st[u] = storage_index(g, px[u], py[u]);
+                zr[u] = ray_height(r.o_major + (L.xmajor ? px[u] : py[u]), g.res, r.s_major, r.inv_d, r.s_z, r.dz);
             }
         }
-        i += n;
-        if (skip(box_max(g, tm.t8, tm.tw8, 3, x0, y0, x1, y1), z0, z1)) continue;
-        float hk[U];
 #pragma unroll
         for (int u = 0; u < U; u++) hk[u] = st[u] >= 0 ? h[st[u]] : __builtin_nanf("");
         bool stop = false;
