@@ -19,7 +19,15 @@ __device__ __forceinline__ int storage_index(const Grid& g, int ix, int iy)
     sx -= (sx >= g.W) ? g.W : 0;
     int sy = iy + g.ry;
     sy -= (sy >= g.H) ? g.H : 0;
-    return sy * g.W + sx;
+    return (int)__umul24((unsigned)sy, (unsigned)g.W) + sx;  // sides <= 16384 < 2^24
+}
+
+// h[st] for a storage index st >= 0 of a grid under 2^30 cells, addressed
+// with a 32-bit byte offset from the base (one address operation instead of
+// a 64-bit pointer sum per load).
+__device__ __forceinline__ float load_cell(const float* __restrict__ h, int st)
+{
+    return *(const float*)((const char*)h + (uint32_t)st * 4u);
 }
 
 // Logical cell of a storage index.
@@ -103,12 +111,18 @@ struct LineWalk {
     // step() produce.
     __device__ __forceinline__ void jump_from_start(int i)
     {
-        const int64_t dmaj = dmaj2 >> 1, dmin = dmin2 >> 1;
+        const int dmaj = dmaj2 >> 1, dmin = dmin2 >> 1;
         if (i <= 0 || dmaj == 0) return;
-        const int64_t m = (2 * (int64_t)i * dmin + dmaj - 1) / (2 * dmaj);
-        D = (int)(2 * dmin * ((int64_t)i + 1) - dmaj - 2 * dmaj * m);
-        x += mx * i + nx * (int)m;
-        y += my * i + ny * (int)m;
+        int m;
+        if (dmaj < 32768) {
+            // 2 i dmin + dmaj - 1 < 2^31 since i, dmin <= dmaj: 32-bit division
+            m = (int)((2u * (unsigned)i * (unsigned)dmin + (unsigned)dmaj - 1u) / (2u * (unsigned)dmaj));
+        } else {
+            m = (int)((2 * (int64_t)i * dmin + dmaj - 1) / (2 * (int64_t)dmaj));
+        }
+        D = (int)(2 * (int64_t)dmin * ((int64_t)i + 1) - dmaj - 2 * (int64_t)dmaj * m);
+        x += mx * i + nx * m;
+        y += my * i + ny * m;
     }
     __device__ __forceinline__ void step()
     {
@@ -157,45 +171,56 @@ struct Ray {
 // time: the U cells' heights are loaded together before any of them is
 // tested, so a lane keeps U loads in flight.  visit(st, h, z_ray) returns
 // true to stop the walk.  Cells outside the grid are skipped.  Returns the
-// number of in-grid cells loaded.
-template <int U, class Visit>
-__device__ __forceinline__ int walk_cells(const Grid& g, Ray& r, const float* __restrict__ h,
-                                          Visit&& visit)
+// number of in-grid cells loaded.  The batch of U is computed without
+// branches: past the last cell the walk keeps stepping and loads cell 0
+// (always in bounds) in place of the cells it does not visit, and a walk
+// that starts inside the grid (so every cell up to the target is inside)
+// needs no bounds test at all.  Cells not visited reach `visit` with a NaN
+// height, which every visit must ignore (NaN is also an empty cell's
+// height).  The walker's position after the call is unspecified.
+template <int U, bool Inside, class Visit>
+__device__ __forceinline__ int walk_cells_impl(const Grid& g, Ray& r, const float* __restrict__ h,
+                                               Visit& visit)
 {
     int rem = r.L.steps - 1;
     int loaded = 0;
     while (rem > 0) {
         int st[U];
         float zr[U];
+        bool ok[U];
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            st[u] = -1;
-            zr[u] = 0.0f;
-            if (u < rem) {
-                r.L.step();
-                const bool in = r.all_inside ||
-                                (r.L.x >= 0 && r.L.x < g.W && r.L.y >= 0 && r.L.y < g.H);
-                if (in) {
-                    st[u] = storage_index(g, r.L.x, r.L.y);
-                    zr[u] = ray_height(r.o_major + r.L.major(), g.res, r.s_major, r.inv_d, r.s_z, r.dz);
-                }
-            }
+            r.L.step();
+            ok[u] = u < rem;
+            if (!Inside) ok[u] = ok[u] && r.L.x >= 0 && r.L.x < g.W && r.L.y >= 0 && r.L.y < g.H;
+            const int si = storage_index(g, r.L.x, r.L.y);  // computed always: a select, not a branch
+            st[u] = ok[u] ? si : 0;
+            zr[u] = ray_height(r.o_major + r.L.major(), g.res, r.s_major, r.inv_d, r.s_z, r.dz);
         }
         float hk[U];
 #pragma unroll
-        for (int u = 0; u < U; u++) hk[u] = st[u] >= 0 ? h[st[u]] : __builtin_nanf("");
+        for (int u = 0; u < U; u++) {
+            const float x = load_cell(h, st[u]);
+            hk[u] = ok[u] ? x : __builtin_nanf("");
+        }
         bool stop = false;
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            if (st[u] >= 0) {
-                loaded++;
-                if (!stop && visit(st[u], hk[u], zr[u])) stop = true;
-            }
+            loaded += ok[u] ? 1 : 0;
+            if (!stop && visit(st[u], hk[u], zr[u])) stop = true;
         }
         if (stop) break;
         rem -= U;
     }
     return loaded;
+}
+
+template <int U, class Visit>
+__device__ __forceinline__ int walk_cells(const Grid& g, Ray& r, const float* __restrict__ h,
+                                          Visit&& visit)
+{
+    if (r.all_inside) return walk_cells_impl<U, true>(g, r, h, visit);
+    return walk_cells_impl<U, false>(g, r, h, visit);
 }
 
 // Visits `count` cells of the ray starting with intermediate cell `first`

@@ -8,7 +8,12 @@
 //                  (cell, field) it saw.
 //   k_clear_march  the ray cast of Table I's "height update & ray cast":
 //                  one ray per accepted point along Bresenham's line, voting
-//                  to clear cells whose height lies above the ray.
+//                  to clear cells whose height lies above the ray.  Rays of
+//                  up to kShortMax intermediate cells are walked one per
+//                  lane; longer ones are listed for
+//   k_clear_long   which walks each listed ray in segments of kSeg cells,
+//                  one segment per lane, so that no lane walks a whole long
+//                  ray while the rest of the chip idles.
 //   k_finalize     per-cell information-form Gaussian height fusion, clear
 //                  application, and fusion of bound point channels with the
 //                  layer's rule (Sec. III-C, Eq. (1), (2), (6)-(7), (12)).
@@ -27,12 +32,19 @@ constexpr size_t kStaticLds = sizeof(int) * 2 * kSlots + sizeof(float) * 2 * kSl
 
 static_assert(kSlots >= 2 * kChunk, "hash table must never fill");
 
+constexpr int kShortMax = 64;   // longest ray (intermediate cells) walked by one lane
+constexpr int kSeg = 32;        // cells per lane segment of a long ray
+constexpr int kLongRays = 64;   // long rays per k_clear_long workgroup
+constexpr int kLongGrid = 2048; // k_clear_long workgroups at most
+
 __global__ __launch_bounds__(256) void k_zero_accum(int HW, int* __restrict__ n,
                                                     float* __restrict__ wsum,
                                                     float* __restrict__ ssum,
                                                     int* __restrict__ clr,
-                                                    float* __restrict__ chsum, int Cb)
+                                                    float* __restrict__ chsum, int Cb,
+                                                    int* __restrict__ zero1)
 {
+    if (zero1 && blockIdx.x == 0 && threadIdx.x == 0) *zero1 = 0;
     int stride = gridDim.x * blockDim.x;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < HW; i += stride) {
         n[i] = 0;
@@ -66,17 +78,36 @@ __global__ __launch_bounds__(kWG) void k_ingest(Grid g, const float* __restrict_
     block_stats(stats, ids, vals);
 }
 
+// Clearing vote of one cell: the ray passes below the cell's height by more
+// than the margin.  NaN (no height) never votes.
+struct ClearVote {
+    int* clr;
+    float margin;
+    __device__ __forceinline__ bool operator()(int st, float hk, float zr) const
+    {
+        const float thr = zr + margin;
+        if (hk > thr) atomicAdd(&clr[st], 1);
+        return false;
+    }
+};
+
 // One ray per lane.  Scan order puts rays of very different lengths side by
 // side (the beams of one LiDAR firing), and a wave runs as long as its
 // longest ray, so the workgroup first sorts its 256 rays by length (bitonic
 // sort in LDS) and each wave walks 64 rays of similar length; neighbouring
-// points stay in one workgroup, so the walks still share cache lines.
+// points stay in one workgroup, so the walks still share cache lines.  Rays
+// longer than kShortMax cells are appended to `longs` (indices into this
+// launch's points) instead: workgroups whose points lie far away would
+// otherwise hold their CU long after the rest of the grid has finished.
 __global__ __launch_bounds__(256) void k_clear_march(Grid g, const float* __restrict__ xyz,
                                                      int64_t n, Pose T, float mr2, float margin,
                                                      const float* __restrict__ h,
                                                      int* __restrict__ clr,
+                                                     int* __restrict__ longs,
+                                                     int* __restrict__ n_long,
                                                      unsigned long long* __restrict__ stats)
 {
+    __shared__ int s_long_base;
     __shared__ uint32_t s_key[256];  // (intermediate cells << 8) | thread
     __shared__ float4 s_pt[256];
     __shared__ int2 s_cell[256];
@@ -108,19 +139,84 @@ __global__ __launch_bounds__(256) void k_clear_march(Grid g, const float* __rest
     }
     const int src = (int)(s_key[t] & 255u);
     const int my_steps = (int)(s_key[t] >> 8);
+    // sorted ascending, so the long rays are the workgroup's last lanes
+    const int n_mine = __syncthreads_count(my_steps > kShortMax);
+    if (t == 0 && n_mine > 0) s_long_base = atomicAdd(n_long, n_mine);
+    __syncthreads();
     int visited = 0;
-    if (my_steps > 0) {
+    if (my_steps > kShortMax) {
+        longs[s_long_base + t - (256 - n_mine)] = (int)((int64_t)blockIdx.x * 256 + src);
+    } else if (my_steps > 0) {
         const float4 p = s_pt[src];
         const int2 c = s_cell[src];
         Ray ray(g, ax, ay, c.x, c.y, sx, sy, sz, p.x, p.y, p.z);
-        visited = walk_cells<8>(g, ray, h, [&](int st, float hk, float zr) {
-            float thr = zr + margin;
-            if (hk > thr) atomicAdd(&clr[st], 1);  // NaN (no height) never votes
-            return false;
-        });
+        visited = walk_cells<8>(g, ray, h, ClearVote{clr, margin});
     }
     const int ids[2] = {ST_RAY_CELLS, ST_RAY_STEPS};
     int vals[2] = {visited, steps};
+    block_stats(stats, ids, vals);
+}
+
+// The listed long rays, kLongRays per workgroup: each ray is cut into
+// segments of kSeg cells (the last one shorter) and the workgroup's lanes
+// take the segments in turn, entering a ray mid-way with the closed-form
+// Bresenham jump; the votes are those of walking every ray whole.
+__global__ __launch_bounds__(256) void k_clear_long(Grid g, const float* __restrict__ xyz, Pose T,
+                                                    float mr2, float margin,
+                                                    const float* __restrict__ h,
+                                                    int* __restrict__ clr,
+                                                    const int* __restrict__ longs,
+                                                    const int* __restrict__ n_long,
+                                                    unsigned long long* __restrict__ stats)
+{
+    __shared__ float4 s_pt[kLongRays];
+    __shared__ int2 s_cell[kLongRays];
+    __shared__ int s_pre[kLongRays + 1];  // exclusive prefix of the segment counts, then the total
+    const int t = threadIdx.x;
+    const int count = *n_long;
+    const float sx = T.m[3], sy = T.m[7], sz = T.m[11];
+    int ax, ay;
+    lattice_cell(g, sx, sy, ax, ay);
+    int visited = 0;
+    for (int base = blockIdx.x * kLongRays; base < count; base += gridDim.x * kLongRays) {
+        if (t < kLongRays) {  // wave 0 loads the rays and scans their segment counts
+            int nseg = 0;
+            float px = 0.f, py = 0.f, pz = 0.f, r2;
+            int ix = 0, iy = 0;
+            if (base + t < count) {
+                const int64_t i = longs[base + t];
+                if (point_cell(g, T, mr2, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], px, py, pz, r2, ix, iy) == 0)
+                    nseg = (max(abs(ix - ax), abs(iy - ay)) - 1 + kSeg - 1) / kSeg;
+            }
+            s_pt[t] = make_float4(px, py, pz, 0.f);
+            s_cell[t] = make_int2(ix, iy);
+            int incl = nseg;
+#pragma unroll
+            for (int o = 1; o < kLongRays; o <<= 1) {
+                const int u = __shfl_up(incl, o);
+                if (t >= o) incl += u;
+            }
+            s_pre[t + 1] = incl;
+            if (t == 0) s_pre[0] = 0;
+        }
+        __syncthreads();
+        const int total = s_pre[kLongRays];
+        for (int q = t; q < total; q += 256) {
+            int r = 0;  // the last ray whose first segment is at or before q
+#pragma unroll
+            for (int bit = kLongRays / 2; bit > 0; bit >>= 1)
+                if (s_pre[r + bit] <= q) r += bit;
+            const float4 p = s_pt[r];
+            const int2 c = s_cell[r];
+            Ray ray(g, ax, ay, c.x, c.y, sx, sy, sz, p.x, p.y, p.z);
+            const int first = 1 + (q - s_pre[r]) * kSeg;
+            const int cnt = min(kSeg, ray.L.steps - first);
+            visited += walk_range<8>(g, ray, h, first, cnt, ClearVote{clr, margin});
+        }
+        __syncthreads();  // the next batch overwrites the LDS tables
+    }
+    const int ids[1] = {ST_RAY_CELLS};
+    int vals[1] = {visited};
     block_stats(stats, ids, vals);
 }
 
@@ -193,12 +289,13 @@ size_t ingest_lds_bytes(int Cb)
 }
 
 void launch_zero_accum(hipStream_t s, const Grid& g, int* n, float* wsum, float* ssum, int* clr,
-                       float* chsum, int Cb)
+                       float* chsum, int Cb, int* zero1)
 {
     int HW = g.W * g.H;
     unsigned b = blocks_for(HW, 256);
     if (b > 4096) b = 4096;
-    hipLaunchKernelGGL(k_zero_accum, dim3(b), dim3(256), 0, s, HW, n, wsum, ssum, clr, chsum, Cb);
+    if (b < 1) b = 1;
+    hipLaunchKernelGGL(k_zero_accum, dim3(b), dim3(256), 0, s, HW, n, wsum, ssum, clr, chsum, Cb, zero1);
 }
 
 void launch_ingest(hipStream_t s, const Grid& g, const float* xyz, int64_t n, const float* ch,
@@ -214,11 +311,22 @@ void launch_ingest(hipStream_t s, const Grid& g, const float* xyz, int64_t n, co
 }
 
 void launch_clear_march(hipStream_t s, const Grid& g, const float* xyz, int64_t n, const Pose& T,
-                        float mr2, float margin, const float* h, int* clr, unsigned long long* stats)
+                        float mr2, float margin, const float* h, int* clr, int* longs, int* n_long,
+                        unsigned long long* stats)
 {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_clear_march, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, xyz, n, T, mr2, margin, h,
-                       clr, stats);
+    // The long-ray list holds kMarchPass entries: clouds beyond that are
+    // marched in passes, each pass clearing the list's counter first (the
+    // first pass's counter was cleared with the accumulators).
+    for (int64_t b = 0; b < n; b += kMarchPass) {
+        const int64_t m = n - b < kMarchPass ? n - b : kMarchPass;
+        if (b > 0) launch_zero_int(s, n_long, 1);
+        hipLaunchKernelGGL(k_clear_march, dim3(blocks_for(m, 256)), dim3(256), 0, s, g, xyz + 3 * b, m, T, mr2,
+                           margin, h, clr, longs, n_long, stats);
+        unsigned gl = blocks_for(m, kLongRays);
+        if (gl > kLongGrid) gl = kLongGrid;
+        hipLaunchKernelGGL(k_clear_long, dim3(gl), dim3(256), 0, s, g, xyz + 3 * b, T, mr2, margin, h, clr,
+                           longs, n_long, stats);
+    }
 }
 
 TileMax tile_max_dims(const Grid& g, const float* t8, const float* t64)

@@ -96,6 +96,8 @@ struct mem_map {
     float* ssum = nullptr;
     float2* stash = nullptr;
     int* vcount = nullptr;      // cells listed in vlist
+    int* longs = nullptr;       // long rays of the clearing march (kMarchPass entries)
+    int* n_long = nullptr;      // their count
     int4* vlist = nullptr;      // cells inside a camera's view
     float* tmax = nullptr;      // block maxima of h: side 8, then side 64
     int* vcode = nullptr;       // their pixel per image
@@ -229,6 +231,8 @@ void free_map(mem_map* m)
     (void)hipFree(m->ssum);
     (void)hipFree(m->stash);
     (void)hipFree(m->vcount);
+    (void)hipFree(m->longs);
+    (void)hipFree(m->n_long);
     (void)hipFree(m->vlist);
     (void)hipFree(m->vcode);
     (void)hipFree(m->tmax);
@@ -322,6 +326,7 @@ mem_status mem_create(const mem_params* p, void* stream, mem_map** out)
         (st = dev_alloc(m, &m->stash, HW)) ||
         (st = dev_alloc(m, &m->vlist, HW)) || (st = dev_alloc(m, &m->vcode, HW * kMaxImages)) ||
         (st = dev_alloc(m, &m->vcount, 1)) || (st = dev_alloc(m, &m->tmax, m->tmax_size())) ||
+        (st = dev_alloc(m, &m->longs, kMarchPass)) || (st = dev_alloc(m, &m->n_long, 1)) ||
         (st = dev_alloc(m, &m->stats, kStats * kStatSlots))) {
         free_map(m);
         return st;
@@ -353,7 +358,7 @@ mem_status mem_create(const mem_params* p, void* stream, mem_map** out)
     Grid g = m->grid();
     auto devs = layer_devs(m);
     launch_reset_rect(s, g, 0, m->W, 0, m->H, m->h, m->v, m->cnt, m->clr, devs.data(), (int)devs.size());
-    launch_zero_accum(s, g, m->cnt, m->wsum, m->ssum, m->clr, nullptr, 0);
+    launch_zero_accum(s, g, m->cnt, m->wsum, m->ssum, m->clr, nullptr, 0, nullptr);
     launch_zero_int(s, (int*)m->stats, 2 * kStats * kStatSlots);
     launch_zero_int(s, m->vcount, 1);
     hipError_t e = hipGetLastError();
@@ -460,7 +465,7 @@ mem_status mem_input_pointcloud(mem_map* m, const float* xyz, int64_t n, const f
         m->chsum_planes = pb.Cb;
     }
     Grid g = m->grid();
-    timed(m, s, "zero_accum", [&] { launch_zero_accum(s, g, m->cnt, m->wsum, m->ssum, m->clr, m->chsum, pb.Cb); });
+    timed(m, s, "zero_accum", [&] { launch_zero_accum(s, g, m->cnt, m->wsum, m->ssum, m->clr, m->chsum, pb.Cb, m->n_long); });
     Pose T;
     memcpy(T.m, T_map_sensor, sizeof(T.m));
     timed(m, s, "ingest", [&] {
@@ -469,7 +474,8 @@ mem_status mem_input_pointcloud(mem_map* m, const float* xyz, int64_t n, const f
     });
     if (m->clear_min > 0 && n > 0)
         timed(m, s, "clear_march", [&] {
-            launch_clear_march(s, g, xyz, n, T, m->mr2, m->clear_margin, m->h, m->clr, m->stats);
+            launch_clear_march(s, g, xyz, n, T, m->mr2, m->clear_margin, m->h, m->clr, m->longs, m->n_long,
+                               m->stats);
         });
     timed(m, s, "finalize", [&] {
         launch_finalize(s, g, m->cnt, m->wsum, m->ssum, m->stash, m->clr, m->clear_min, m->h, m->v,

@@ -108,16 +108,22 @@ struct Camera {
 };
 
 // ---- launchers (implemented in the .hip files) ----
+// `zero1`, if not null, is one int cleared as well (the long-ray counter of
+// the clearing march).
 void launch_zero_accum(hipStream_t s, const Grid& g, int* n, float* wsum, float* ssum, int* clr,
-                       float* chsum, int Cb);
+                       float* chsum, int Cb, int* zero1);
 // LDS bytes of the ingest kernel for `Cb` channel planes reduced in LDS.
 size_t ingest_lds_bytes(int Cb);
 void launch_ingest(hipStream_t s, const Grid& g, const float* xyz, int64_t n, const float* ch,
                    const Pose& T, float c0, float c1, float mr2, const PointBinds& pb, int* cnt,
                    float* wsum, float* ssum, float2* stash, float* chsum,
                    unsigned long long* stats);
+// Points per clearing pass: the long-ray list `longs` holds this many
+// entries and `n_long` is its counter (cleared by launch_zero_accum).
+constexpr int64_t kMarchPass = 1 << 20;
 void launch_clear_march(hipStream_t s, const Grid& g, const float* xyz, int64_t n, const Pose& T,
-                        float mr2, float margin, const float* h, int* clr, unsigned long long* stats);
+                        float mr2, float margin, const float* h, int* clr, int* longs, int* n_long,
+                        unsigned long long* stats);
 void launch_finalize(hipStream_t s, const Grid& g, const int* cnt, const float* wsum,
                      const float* ssum, const float2* stash, const int* clr, int clear_min,
                      float* h, float* v, const float* chsum, const PointBinds& pb,

@@ -236,6 +236,43 @@ def test_single_point_sets_empty_cell_bit_exactly():
     assert h[6, 6] == np.float32(0.3)
 
 
+def test_cloud_larger_than_one_clearing_pass():
+    """More than 2^20 points in one call: the clearing march runs in passes
+    and walks long rays in segments; the votes, heights and every loaded
+    cell still match the oracle's walk of each whole ray."""
+    rng = np.random.default_rng(11)
+    g, o = make_pair(160, 160, 0.05, max_range=20.0, clear_margin=0.05, clear_min_count=2)
+    n0 = 200_000
+    xy = rng.uniform(-3.95, 3.95, (n0, 2))
+    z = 0.3 * np.sin(2 * xy[:, 0]) + 0.2 * np.cos(3 * xy[:, 1])
+    ground = np.concatenate([xy, z[:, None]], 1).astype(np.float32)
+    g.input_pointcloud(to_dev(ground), ID)
+    o.input_pointcloud(ground, ID)
+    compare(g, o, what="terrain")
+    sync_oracle(g, o)
+    before = g.stats()
+    # sensor 0.4 m up; targets at every range, many below the terrain so
+    # that rays cross raised cells and vote; in the half plane y > -0.2 no
+    # target is nearer than 2 m, so the cells there are crossed but receive
+    # no point and can be cleared
+    n1 = (1 << 20) + 123_457
+    r = np.concatenate([rng.uniform(0.05, 1.0, n1 // 2), rng.uniform(1.0, 3.9, n1 - n1 // 2)])
+    a = rng.uniform(0, 2 * np.pi, n1)
+    r = np.where(a < np.pi, np.maximum(r, 2.0 + (r % 0.1) * 19), r)
+    t = np.array([0.1, -0.2, 0.4], np.float32)
+    tgt = np.stack([r * np.cos(a) + 0.1, r * np.sin(a) - 0.2, rng.uniform(-0.6, 0.2, n1)], 1)
+    cloud = (tgt - t).astype(np.float32)
+    rng.shuffle(cloud)
+    g.input_pointcloud(to_dev(cloud), pose(tuple(t)))
+    o.input_pointcloud(cloud, pose(tuple(t)))
+    compare(g, o, what="cloud of more than one pass")
+    st = g.stats()
+    steps = st["ray_steps"] - before["ray_steps"]
+    assert steps > 20 * n1
+    assert st["ray_cells"] - before["ray_cells"] == steps  # every cell of every ray loaded once
+    assert st["cells_cleared"] > before["cells_cleared"]
+
+
 def test_empty_cloud_and_all_dropped_and_nothing_in_view():
     rng = np.random.default_rng(4)
     g, o = make_pair(30, 30, 0.1, layers=[(3, mem.MEM_LATEST, 0.0)], max_range=2.0)
