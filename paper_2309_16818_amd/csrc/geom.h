@@ -223,6 +223,72 @@ __device__ __forceinline__ int walk_cells(const Grid& g, Ray& r, const float* __
     return walk_cells_impl<U, false>(g, r, h, visit);
 }
 
+// walk_cells over a grid stored in logical order (`g` with rx = ry = 0, so
+// cell (x, y) is at y * W + x) for a ray that starts inside the grid, so
+// that every cell up to its target is inside: the linear index advances by
+// the major step plus, when Bresenham's error term says so, the minor
+// step, and the cell's major lattice coordinate is carried as a float
+// (k + 0.5 is exact below 2^22, so each ray height equals ray_height's).
+// Rays reaching beyond that range take walk_cells.
+template <int U, class Visit>
+__device__ __forceinline__ int walk_logical(const Grid& g, Ray& r, const float* __restrict__ h,
+                                            Visit&& visit)
+{
+    const LineWalk& L = r.L;
+    const int k0 = r.o_major + L.major();
+    const int sgn = L.xmajor ? L.mx : L.my;
+    const int k1 = k0 + sgn * L.steps;
+    if (!r.all_inside || max(abs(k0), abs(k1)) >= (1 << 22)) return walk_cells_impl<U, false>(g, r, h, visit);
+    const int inc_maj = L.mx + L.my * g.W, inc_min = L.nx + L.ny * g.W;
+    const int last = g.W * g.H - 1;
+    const float fs = (float)sgn;
+    float c = (float)k0 + 0.5f;
+    int lin = L.y * g.W + L.x;
+    int D = L.D;
+    int rem = L.steps - 1;
+    int loaded = 0;
+    while (rem > 0) {
+        int st[U];
+        float zr[U];
+        loaded += min(rem, U);
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const bool diag = D > 0;
+            lin += inc_maj + (diag ? inc_min : 0);
+            D += L.dmin2 - (diag ? L.dmaj2 : 0);
+            c += fs;
+            // past the target the walk may leave the grid: clamp, then ignore
+            st[u] = min((unsigned)lin, (unsigned)last);
+            float t = c * g.res;
+            t = (t - r.s_major) * r.inv_d;
+            zr[u] = r.s_z + r.dz * t;
+        }
+        float hk[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const float x = load_cell(h, st[u]);
+            hk[u] = u < rem ? x : __builtin_nanf("");
+        }
+        bool stop = false;
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            if (!stop && visit(st[u], hk[u], zr[u])) stop = true;
+        if (stop) break;
+        rem -= U;
+    }
+    return loaded;
+}
+
+// walk_logical over `count` cells from intermediate cell `first`.
+template <int U, class Visit>
+__device__ __forceinline__ int walk_range_logical(const Grid& g, Ray& r, const float* __restrict__ h,
+                                                  int first, int count, Visit&& visit)
+{
+    r.L.jump_from_start(first - 1);
+    r.L.steps = count + 1;
+    return walk_logical<U>(g, r, h, visit);
+}
+
 // Visits `count` cells of the ray starting with intermediate cell `first`
 // (1 = the cell after the start cell), U at a time, like walk_cells.
 template <int U, class Visit>

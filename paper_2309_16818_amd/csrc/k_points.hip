@@ -37,13 +37,18 @@ constexpr int kSeg = 32;        // cells per lane segment of a long ray
 constexpr int kLongRays = 64;   // long rays per k_clear_long workgroup
 constexpr int kLongGrid = 2048; // k_clear_long workgroups at most
 
-__global__ __launch_bounds__(256) void k_zero_accum(int HW, int* __restrict__ n,
+// Clears the accumulators (`clr` in any order) and, if `hl` is given,
+// copies the heights into logical order for the clearing march.
+__global__ __launch_bounds__(256) void k_zero_accum(Grid g, int* __restrict__ n,
                                                     float* __restrict__ wsum,
                                                     float* __restrict__ ssum,
                                                     int* __restrict__ clr,
                                                     float* __restrict__ chsum, int Cb,
-                                                    int* __restrict__ zero1)
+                                                    int* __restrict__ zero1,
+                                                    const float* __restrict__ h,
+                                                    float* __restrict__ hl)
 {
+    const int HW = g.W * g.H;
     if (zero1 && blockIdx.x == 0 && threadIdx.x == 0) *zero1 = 0;
     int stride = gridDim.x * blockDim.x;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < HW; i += stride) {
@@ -52,6 +57,11 @@ __global__ __launch_bounds__(256) void k_zero_accum(int HW, int* __restrict__ n,
         ssum[i] = 0.0f;
         clr[i] = 0;
         for (int q = 0; q < Cb; q++) chsum[(int64_t)q * HW + i] = 0.0f;
+        if (hl) {
+            int ix, iy;
+            logical_index(g, i, ix, iy);
+            hl[iy * g.W + ix] = h[i];
+        }
     }
 }
 
@@ -150,7 +160,7 @@ __global__ __launch_bounds__(256) void k_clear_march(Grid g, const float* __rest
         const float4 p = s_pt[src];
         const int2 c = s_cell[src];
         Ray ray(g, ax, ay, c.x, c.y, sx, sy, sz, p.x, p.y, p.z);
-        visited = walk_cells<8>(g, ray, h, ClearVote{clr, margin});
+        visited = walk_logical<8>(g, ray, h, ClearVote{clr, margin});
     }
     const int ids[2] = {ST_RAY_CELLS, ST_RAY_STEPS};
     int vals[2] = {visited, steps};
@@ -211,7 +221,7 @@ __global__ __launch_bounds__(256) void k_clear_long(Grid g, const float* __restr
             Ray ray(g, ax, ay, c.x, c.y, sx, sy, sz, p.x, p.y, p.z);
             const int first = 1 + (q - s_pre[r]) * kSeg;
             const int cnt = min(kSeg, ray.L.steps - first);
-            visited += walk_range<8>(g, ray, h, first, cnt, ClearVote{clr, margin});
+            visited += walk_range_logical<8>(g, ray, h, first, cnt, ClearVote{clr, margin});
         }
         __syncthreads();  // the next batch overwrites the LDS tables
     }
@@ -252,13 +262,23 @@ __global__ __launch_bounds__(256) void k_tile_max64(const float* __restrict__ t8
     if (lane == 0) t64[tile] = v;
 }
 
-__global__ __launch_bounds__(256) void k_finalize(Grid g, Accum acc, int clear_min,
-                                                  float* __restrict__ h, float* __restrict__ v,
-                                                  PointBinds pb,
+// The clearing votes arrive in logical order (`clr_l`); each cell's count
+// is stored into the storage-order layer acc.clr, which the clear-count
+// layer view reads.
+__global__ __launch_bounds__(256) void k_finalize(Grid g, Accum acc, const int* __restrict__ clr_l,
+                                                  int clear_min, float* __restrict__ h,
+                                                  float* __restrict__ v, PointBinds pb,
                                                   unsigned long long* __restrict__ stats)
 {
     const int st = blockIdx.x * blockDim.x + threadIdx.x;
-    const int r = (st < acc.HW) ? finalize_cell(st, acc, clear_min, h, v, pb) : 0;
+    int r = 0;
+    if (st < acc.HW) {
+        int ix, iy;
+        logical_index(g, st, ix, iy);
+        const int votes = clr_l[iy * g.W + ix];
+        acc.clr[st] = votes;
+        r = finalize_cell_v(st, acc, clear_min, h, v, pb, [&] { return votes; });
+    }
     const int ids[2] = {ST_TOUCHED, ST_CLEARED};
     int vals[2] = {r == 1 ? 1 : 0, r == 2 ? 1 : 0};
     block_stats(stats, ids, vals);
@@ -289,13 +309,13 @@ size_t ingest_lds_bytes(int Cb)
 }
 
 void launch_zero_accum(hipStream_t s, const Grid& g, int* n, float* wsum, float* ssum, int* clr,
-                       float* chsum, int Cb, int* zero1)
+                       float* chsum, int Cb, int* zero1, const float* h, float* hl)
 {
     int HW = g.W * g.H;
     unsigned b = blocks_for(HW, 256);
     if (b > 4096) b = 4096;
     if (b < 1) b = 1;
-    hipLaunchKernelGGL(k_zero_accum, dim3(b), dim3(256), 0, s, HW, n, wsum, ssum, clr, chsum, Cb, zero1);
+    hipLaunchKernelGGL(k_zero_accum, dim3(b), dim3(256), 0, s, g, n, wsum, ssum, clr, chsum, Cb, zero1, h, hl);
 }
 
 void launch_ingest(hipStream_t s, const Grid& g, const float* xyz, int64_t n, const float* ch,
@@ -310,10 +330,16 @@ void launch_ingest(hipStream_t s, const Grid& g, const float* xyz, int64_t n, co
                        c0, c1, mr2, pb, acc, stats);
 }
 
-void launch_clear_march(hipStream_t s, const Grid& g, const float* xyz, int64_t n, const Pose& T,
-                        float mr2, float margin, const float* h, int* clr, int* longs, int* n_long,
+void launch_clear_march(hipStream_t s, const Grid& g_storage, const float* xyz, int64_t n, const Pose& T,
+                        float mr2, float margin, const float* hl, int* clr_l, int* longs, int* n_long,
                         unsigned long long* stats)
 {
+    // heights and votes in logical order: the grid without its ring offsets
+    Grid g = g_storage;
+    g.rx = 0;
+    g.ry = 0;
+    const float* h = hl;
+    int* clr = clr_l;
     // The long-ray list holds kMarchPass entries: clouds beyond that are
     // marched in passes, each pass clearing the list's counter first (the
     // first pass's counter was cleared with the accumulators).
@@ -351,14 +377,14 @@ void launch_tile_max(hipStream_t s, const Grid& g, const float* h, float* t8, fl
 }
 
 void launch_finalize(hipStream_t s, const Grid& g, const int* cnt, const float* wsum,
-                     const float* ssum, const float2* stash, const int* clr, int clear_min,
+                     const float* ssum, const float2* stash, const int* clr_l, int* clr, int clear_min,
                      float* h, float* v, const float* chsum, const PointBinds& pb,
                      unsigned long long* stats)
 {
     const int HW = g.W * g.H;
     const Accum acc{const_cast<int*>(cnt), const_cast<float*>(wsum), const_cast<float*>(ssum),
-                    const_cast<float2*>(stash), const_cast<int*>(clr), const_cast<float*>(chsum), HW};
-    hipLaunchKernelGGL(k_finalize, dim3(blocks_for(HW, 256)), dim3(256), 0, s, g, acc, clear_min, h,
+                    const_cast<float2*>(stash), clr, const_cast<float*>(chsum), HW};
+    hipLaunchKernelGGL(k_finalize, dim3(blocks_for(HW, 256)), dim3(256), 0, s, g, acc, clr_l, clear_min, h,
                        v, pb, stats);
 }
 

@@ -97,6 +97,8 @@ struct mem_map {
     float2* stash = nullptr;
     int* vcount = nullptr;      // cells listed in vlist
     int* longs = nullptr;       // long rays of the clearing march (kMarchPass entries)
+    float* hl = nullptr;        // heights in logical order, for the clearing march
+    int* clr_l = nullptr;       // the march's votes in logical order
     int* n_long = nullptr;      // their count
     int4* vlist = nullptr;      // cells inside a camera's view
     float* tmax = nullptr;      // block maxima of h: side 8, then side 64
@@ -232,6 +234,8 @@ void free_map(mem_map* m)
     (void)hipFree(m->stash);
     (void)hipFree(m->vcount);
     (void)hipFree(m->longs);
+    (void)hipFree(m->hl);
+    (void)hipFree(m->clr_l);
     (void)hipFree(m->n_long);
     (void)hipFree(m->vlist);
     (void)hipFree(m->vcode);
@@ -327,6 +331,7 @@ mem_status mem_create(const mem_params* p, void* stream, mem_map** out)
         (st = dev_alloc(m, &m->vlist, HW)) || (st = dev_alloc(m, &m->vcode, HW * kMaxImages)) ||
         (st = dev_alloc(m, &m->vcount, 1)) || (st = dev_alloc(m, &m->tmax, m->tmax_size())) ||
         (st = dev_alloc(m, &m->longs, kMarchPass)) || (st = dev_alloc(m, &m->n_long, 1)) ||
+        (st = dev_alloc(m, &m->hl, HW)) || (st = dev_alloc(m, &m->clr_l, HW)) ||
         (st = dev_alloc(m, &m->stats, kStats * kStatSlots))) {
         free_map(m);
         return st;
@@ -358,7 +363,7 @@ mem_status mem_create(const mem_params* p, void* stream, mem_map** out)
     Grid g = m->grid();
     auto devs = layer_devs(m);
     launch_reset_rect(s, g, 0, m->W, 0, m->H, m->h, m->v, m->cnt, m->clr, devs.data(), (int)devs.size());
-    launch_zero_accum(s, g, m->cnt, m->wsum, m->ssum, m->clr, nullptr, 0, nullptr);
+    launch_zero_accum(s, g, m->cnt, m->wsum, m->ssum, m->clr, nullptr, 0, nullptr, nullptr, nullptr);
     launch_zero_int(s, (int*)m->stats, 2 * kStats * kStatSlots);
     launch_zero_int(s, m->vcount, 1);
     hipError_t e = hipGetLastError();
@@ -465,20 +470,24 @@ mem_status mem_input_pointcloud(mem_map* m, const float* xyz, int64_t n, const f
         m->chsum_planes = pb.Cb;
     }
     Grid g = m->grid();
-    timed(m, s, "zero_accum", [&] { launch_zero_accum(s, g, m->cnt, m->wsum, m->ssum, m->clr, m->chsum, pb.Cb, m->n_long); });
+    const bool march = m->clear_min > 0 && n > 0;
+    timed(m, s, "zero_accum", [&] {
+        launch_zero_accum(s, g, m->cnt, m->wsum, m->ssum, m->clr_l, m->chsum, pb.Cb, m->n_long, m->h,
+                          march ? m->hl : nullptr);
+    });
     Pose T;
     memcpy(T.m, T_map_sensor, sizeof(T.m));
     timed(m, s, "ingest", [&] {
         launch_ingest(s, g, xyz, n, ch, T, m->c0, m->c1, m->mr2, pb, m->cnt, m->wsum, m->ssum, m->stash,
                       m->chsum, m->stats);
     });
-    if (m->clear_min > 0 && n > 0)
+    if (march)
         timed(m, s, "clear_march", [&] {
-            launch_clear_march(s, g, xyz, n, T, m->mr2, m->clear_margin, m->h, m->clr, m->longs, m->n_long,
+            launch_clear_march(s, g, xyz, n, T, m->mr2, m->clear_margin, m->hl, m->clr_l, m->longs, m->n_long,
                                m->stats);
         });
     timed(m, s, "finalize", [&] {
-        launch_finalize(s, g, m->cnt, m->wsum, m->ssum, m->stash, m->clr, m->clear_min, m->h, m->v,
+        launch_finalize(s, g, m->cnt, m->wsum, m->ssum, m->stash, m->clr_l, m->clr, m->clear_min, m->h, m->v,
                         m->chsum, pb, m->stats);
     });
     return check_launch(m, "mem_input_pointcloud");

@@ -110,8 +110,10 @@ struct Camera {
 // ---- launchers (implemented in the .hip files) ----
 // `zero1`, if not null, is one int cleared as well (the long-ray counter of
 // the clearing march).
+// `hl`, if not null, receives a copy of the heights `h` in logical order
+// (index y * W + x).
 void launch_zero_accum(hipStream_t s, const Grid& g, int* n, float* wsum, float* ssum, int* clr,
-                       float* chsum, int Cb, int* zero1);
+                       float* chsum, int Cb, int* zero1, const float* h, float* hl);
 // LDS bytes of the ingest kernel for `Cb` channel planes reduced in LDS.
 size_t ingest_lds_bytes(int Cb);
 void launch_ingest(hipStream_t s, const Grid& g, const float* xyz, int64_t n, const float* ch,
@@ -121,11 +123,14 @@ void launch_ingest(hipStream_t s, const Grid& g, const float* xyz, int64_t n, co
 // Points per clearing pass: the long-ray list `longs` holds this many
 // entries and `n_long` is its counter (cleared by launch_zero_accum).
 constexpr int64_t kMarchPass = 1 << 20;
+// The march reads the heights `hl` and counts votes into `clr_l`, both in
+// logical order; finalize stores each cell's count into the storage-order
+// layer `clr`.
 void launch_clear_march(hipStream_t s, const Grid& g, const float* xyz, int64_t n, const Pose& T,
-                        float mr2, float margin, const float* h, int* clr, int* longs, int* n_long,
+                        float mr2, float margin, const float* hl, int* clr_l, int* longs, int* n_long,
                         unsigned long long* stats);
 void launch_finalize(hipStream_t s, const Grid& g, const int* cnt, const float* wsum,
-                     const float* ssum, const float2* stash, const int* clr, int clear_min,
+                     const float* ssum, const float2* stash, const int* clr_l, int* clr, int clear_min,
                      float* h, float* v, const float* chsum, const PointBinds& pb,
                      unsigned long long* stats);
 void launch_point_cells(hipStream_t s, const Grid& g, const float* xyz, int64_t n, const Pose& T,

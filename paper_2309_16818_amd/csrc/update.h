@@ -146,15 +146,18 @@ __device__ __forceinline__ int march_point(const Grid& g, const float* __restric
     });
 }
 
-// Height fusion, clearing and bound point channels of storage cell st.
-// Returns 1 if the cell received points, 2 if it was cleared, else 0.
-__device__ __forceinline__ int finalize_cell(int st, const Accum& acc, int clear_min,
-                                             float* __restrict__ h, float* __restrict__ v,
-                                             const PointBinds& pb)
+// Height fusion, clearing and bound point channels of storage cell st;
+// votes() gives the cell's clearing votes (read only for a cell without
+// points).  Returns 1 if the cell received points, 2 if it was cleared,
+// else 0.
+template <class Votes>
+__device__ __forceinline__ int finalize_cell_v(int st, const Accum& acc, int clear_min,
+                                               float* __restrict__ h, float* __restrict__ v,
+                                               const PointBinds& pb, Votes&& votes)
 {
     const int N = acc.cnt[st];
     if (N == 0) {
-        if (clear_min > 0 && acc.clr[st] >= clear_min && !isnan(h[st])) {
+        if (clear_min > 0 && votes() >= clear_min && !isnan(h[st])) {
             h[st] = __uint_as_float(0x7fc00000u);
             return 2;
         }
@@ -191,6 +194,14 @@ __device__ __forceinline__ int finalize_cell(int st, const Accum& acc, int clear
         if (L.rule == MEM_GAUSS) L.var[st] = gc.var;
     }
     return 1;
+}
+
+// finalize_cell_v with the votes in acc.clr at the same storage index.
+__device__ __forceinline__ int finalize_cell(int st, const Accum& acc, int clear_min,
+                                             float* __restrict__ h, float* __restrict__ v,
+                                             const PointBinds& pb)
+{
+    return finalize_cell_v(st, acc, clear_min, h, v, pb, [&] { return acc.clr[st]; });
 }
 
 // Association of logical cell (ix, iy) with every image of one camera pose
