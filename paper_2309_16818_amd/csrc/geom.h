@@ -246,11 +246,15 @@ __device__ __forceinline__ int walk_logical(const Grid& g, Ray& r, const float* 
     int lin = L.y * g.W + L.x;
     int D = L.D;
     int rem = L.steps - 1;
-    int loaded = 0;
-    while (rem > 0) {
-        int st[U];
-        float zr[U];
-        loaded += min(rem, U);
+    if (rem <= 0) return 0;
+    // Software pipelined: the next batch's loads are issued before the
+    // current batch is tested, so 2U loads are in flight.  The loop body
+    // always fetches (its batch is full) and the last batch is tested after
+    // the loop, so every path into a test has the same loads outstanding and
+    // each wait is for exactly the value it needs.
+    int st[U];
+    float zr[U], hk[U];
+    auto fetch = [&](int (&s_)[U], float (&z_)[U], float (&h_)[U]) {
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const bool diag = D > 0;
@@ -258,22 +262,44 @@ __device__ __forceinline__ int walk_logical(const Grid& g, Ray& r, const float* 
             D += L.dmin2 - (diag ? L.dmaj2 : 0);
             c += fs;
             // past the target the walk may leave the grid: clamp, then ignore
-            st[u] = min((unsigned)lin, (unsigned)last);
+            s_[u] = min((unsigned)lin, (unsigned)last);
             float t = c * g.res;
             t = (t - r.s_major) * r.inv_d;
-            zr[u] = r.s_z + r.dz * t;
+            z_[u] = r.s_z + r.dz * t;
         }
-        float hk[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) h_[u] = load_cell(h, s_[u]);
+    };
+    // Two batches alternate between the buffers (no copies, so no register
+    // of a load in flight is reused before its value is tested).
+    int st2[U];
+    float zr2[U], hk2[U];
+    int loaded = 0;
+    auto test = [&](const int (&s_)[U], const float (&z_)[U], const float (&h_)[U], int n) {
+        bool stop = false;
+        loaded += min(n, U);
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            const float x = load_cell(h, st[u]);
-            hk[u] = u < rem ? x : __builtin_nanf("");
+            const float hu = u < n ? h_[u] : __builtin_nanf("");
+            if (!stop && visit(s_[u], hu, z_[u])) stop = true;
         }
-        bool stop = false;
-#pragma unroll
-        for (int u = 0; u < U; u++)
-            if (!stop && visit(st[u], hk[u], zr[u])) stop = true;
-        if (stop) break;
+        return stop;
+    };
+    fetch(st, zr, hk);
+    while (true) {
+        if (rem <= U) {
+            test(st, zr, hk, rem);
+            break;
+        }
+        fetch(st2, zr2, hk2);
+        if (test(st, zr, hk, U)) break;
+        rem -= U;
+        if (rem <= U) {
+            test(st2, zr2, hk2, rem);
+            break;
+        }
+        fetch(st, zr, hk);
+        if (test(st2, zr2, hk2, U)) break;
         rem -= U;
     }
     return loaded;

@@ -36,6 +36,7 @@ constexpr int kShortMax = 64;   // longest ray (intermediate cells) walked by on
 constexpr int kSeg = 32;        // cells per lane segment of a long ray
 constexpr int kLongRays = 64;   // long rays per k_clear_long workgroup
 constexpr int kLongGrid = 2048; // k_clear_long workgroups at most
+constexpr int kSegTable = 1024; // segments of a k_clear_long batch found by table, not search
 
 // Clears the accumulators (`clr` in any order) and, if `hl` is given,
 // copies the heights into logical order for the clearing march.
@@ -103,12 +104,13 @@ struct ClearVote {
 
 // One ray per lane.  Scan order puts rays of very different lengths side by
 // side (the beams of one LiDAR firing), and a wave runs as long as its
-// longest ray, so the workgroup first sorts its 256 rays by length (bitonic
-// sort in LDS) and each wave walks 64 rays of similar length; neighbouring
-// points stay in one workgroup, so the walks still share cache lines.  Rays
-// longer than kShortMax cells are appended to `longs` (indices into this
-// launch's points) instead: workgroups whose points lie far away would
-// otherwise hold their CU long after the rest of the grid has finished.
+// longest ray, so the workgroup first orders its 256 rays by length bucket
+// (8 cells per bucket; a counting sort in LDS) and each wave walks 64 rays
+// of similar length; neighbouring points stay in one workgroup, so the
+// walks still share cache lines.  Rays longer than kShortMax cells (the
+// last bucket) are appended to `longs` (indices into this launch's points)
+// instead: workgroups whose points lie far away would otherwise hold their
+// CU long after the rest of the grid has finished.
 __global__ __launch_bounds__(256) void k_clear_march(Grid g, const float* __restrict__ xyz,
                                                      int64_t n, Pose T, float mr2, float margin,
                                                      const float* __restrict__ h,
@@ -117,8 +119,12 @@ __global__ __launch_bounds__(256) void k_clear_march(Grid g, const float* __rest
                                                      int* __restrict__ n_long,
                                                      unsigned long long* __restrict__ stats)
 {
+    constexpr int kBuckets = kShortMax / 8 + 2;  // none, 1-8, ..., 57-64, long
+    static_assert(kShortMax % 8 == 0, "length buckets of 8 cells");
     __shared__ int s_long_base;
-    __shared__ uint32_t s_key[256];  // (intermediate cells << 8) | thread
+    __shared__ int s_off[kBuckets];
+    __shared__ int s_order[256];
+    __shared__ int s_steps[256];
     __shared__ float4 s_pt[256];
     __shared__ int2 s_cell[256];
     const int t = threadIdx.x;
@@ -128,34 +134,35 @@ __global__ __launch_bounds__(256) void k_clear_march(Grid g, const float* __rest
     const float sx = T.m[3], sy = T.m[7], sz = T.m[11];
     int ax, ay;
     lattice_cell(g, sx, sy, ax, ay);
+    if (t < kBuckets) s_off[t] = 0;
     if (i < n && point_cell(g, T, mr2, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], px, py, pz, r2, ix, iy) == 0)
         steps = max(max(abs(ix - ax), abs(iy - ay)) - 1, 0);
-    s_key[t] = ((uint32_t)min(steps, 0xffffff) << 8) | (uint32_t)t;
+    s_steps[t] = steps;
     s_pt[t] = make_float4(px, py, pz, 0.f);
     s_cell[t] = make_int2(ix, iy);
+    const int bucket = min((steps + 7) >> 3, kBuckets - 1);
     __syncthreads();
-    for (int k = 2; k <= 256; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            const int o = t ^ j;
-            if (o > t) {
-                const uint32_t a = s_key[t], b = s_key[o];
-                if ((a > b) == ((t & k) == 0)) {
-                    s_key[t] = b;
-                    s_key[o] = a;
-                }
-            }
-            __syncthreads();
+    const int pos = atomicAdd(&s_off[bucket], 1);  // rank within the bucket
+    __syncthreads();
+    if (t == 0) {
+        int acc = 0;
+        for (int q = 0; q < kBuckets; q++) {
+            const int c = s_off[q];
+            s_off[q] = acc;
+            acc += c;
         }
+        const int nl = 256 - s_off[kBuckets - 1];
+        s_long_base = nl > 0 ? atomicAdd(n_long, nl) : 0;
     }
-    const int src = (int)(s_key[t] & 255u);
-    const int my_steps = (int)(s_key[t] >> 8);
-    // sorted ascending, so the long rays are the workgroup's last lanes
-    const int n_mine = __syncthreads_count(my_steps > kShortMax);
-    if (t == 0 && n_mine > 0) s_long_base = atomicAdd(n_long, n_mine);
     __syncthreads();
+    s_order[s_off[bucket] + pos] = t;
+    __syncthreads();
+    const int src = s_order[t];
+    const int my_steps = s_steps[src];
+    const int first_long = s_off[kBuckets - 1];  // the long rays are the last lanes
     int visited = 0;
-    if (my_steps > kShortMax) {
-        longs[s_long_base + t - (256 - n_mine)] = (int)((int64_t)blockIdx.x * 256 + src);
+    if (t >= first_long) {
+        longs[s_long_base + t - first_long] = (int)((int64_t)blockIdx.x * 256 + src);
     } else if (my_steps > 0) {
         const float4 p = s_pt[src];
         const int2 c = s_cell[src];
@@ -182,6 +189,8 @@ __global__ __launch_bounds__(256) void k_clear_long(Grid g, const float* __restr
     __shared__ float4 s_pt[kLongRays];
     __shared__ int2 s_cell[kLongRays];
     __shared__ int s_pre[kLongRays + 1];  // exclusive prefix of the segment counts, then the total
+    __shared__ uint16_t s_seg[kSegTable];  // segment q: its ray | (its index within the ray << 6)
+    static_assert(kLongRays <= 64 && kSegTable <= 65536, "segment table entries are 16 bits");
     const int t = threadIdx.x;
     const int count = *n_long;
     const float sx = T.m[3], sy = T.m[7], sz = T.m[11];
@@ -208,18 +217,28 @@ __global__ __launch_bounds__(256) void k_clear_long(Grid g, const float* __restr
             }
             s_pre[t + 1] = incl;
             if (t == 0) s_pre[0] = 0;
+            const int pre = incl - nseg;
+            for (int k = 0; k < nseg && pre + k < kSegTable; k++) s_seg[pre + k] = (uint16_t)(t | (k << 6));
         }
         __syncthreads();
         const int total = s_pre[kLongRays];
         for (int q = t; q < total; q += 256) {
-            int r = 0;  // the last ray whose first segment is at or before q
+            int r, k;
+            if (q < kSegTable) {
+                const int e = s_seg[q];
+                r = e & 63;
+                k = e >> 6;
+            } else {
+                r = 0;  // the last ray whose first segment is at or before q
 #pragma unroll
-            for (int bit = kLongRays / 2; bit > 0; bit >>= 1)
-                if (s_pre[r + bit] <= q) r += bit;
+                for (int bit = kLongRays / 2; bit > 0; bit >>= 1)
+                    if (s_pre[r + bit] <= q) r += bit;
+                k = q - s_pre[r];
+            }
             const float4 p = s_pt[r];
             const int2 c = s_cell[r];
             Ray ray(g, ax, ay, c.x, c.y, sx, sy, sz, p.x, p.y, p.z);
-            const int first = 1 + (q - s_pre[r]) * kSeg;
+            const int first = 1 + k * kSeg;
             const int cnt = min(kSeg, ray.L.steps - first);
             visited += walk_range_logical<8>(g, ray, h, first, cnt, ClearVote{clr, margin});
         }
