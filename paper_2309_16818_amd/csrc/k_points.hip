@@ -31,9 +31,10 @@ constexpr int kMaxLdsCh = 16;            // bound channels reduced in LDS at mos
 constexpr size_t kStaticLds = sizeof(int) * 2 * kSlots + sizeof(float) * 2 * kSlots + sizeof(float2) * kSlots;
 
 static_assert(kSlots >= 2 * kChunk, "hash table must never fill");
+static_assert(kChunk % kWG == 0, "whole points per ingest thread");
 
 constexpr int kShortMax = 64;   // longest ray (intermediate cells) walked by one lane
-constexpr int kSeg = 32;        // cells per lane segment of a long ray
+constexpr int kSeg = 64;        // cells per lane segment of a long ray
 constexpr int kLongRays = 64;   // long rays per k_clear_long workgroup
 constexpr int kLongGrid = 2048; // k_clear_long workgroups at most
 constexpr int kSegTable = 1024; // segments of a k_clear_long batch found by table, not search
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(kWG) void k_ingest(Grid g, const float* __restrict_
     const int64_t begin = (int64_t)blockIdx.x * kChunk;
     const int64_t end = begin + kChunk < n ? begin + kChunk : n;
     PointCounts pc;
-    ingest_range(g, xyz, begin, end, ch, T, c0, c1, mr2, pb, acc, lds, pc);
+    ingest_range<kChunk / kWG>(g, xyz, begin, end, ch, T, c0, c1, mr2, pb, acc, lds, pc);
     const int ids[5] = {ST_ACCEPTED, ST_NONFINITE, ST_RANGE, ST_OUTSIDE, ST_POINTS_IN};
     int vals[5] = {pc.acc, pc.nonfinite, pc.range, pc.outside,
                    pc.acc + pc.nonfinite + pc.range + pc.outside};

@@ -40,9 +40,11 @@ struct PointCounts {
 };
 
 // Aggregates points [begin, end) of a cloud (at most 2^slots_log2 / 2
-// points) into the LDS table, then flushes one global atomic per (cell,
-// field).  Every thread of the workgroup must call it; it starts and ends
-// with a workgroup barrier.
+// points, and at most P per thread) into the LDS table, then flushes one
+// global atomic per (cell, field).  A thread loads all its points before
+// hashing any, so their loads overlap.  Every thread of the workgroup must
+// call it; it starts and ends with a workgroup barrier.
+template <int P>
 __device__ __forceinline__ void ingest_range(const Grid& g, const float* __restrict__ xyz,
                                              int64_t begin, int64_t end,
                                              const float* __restrict__ ch, const Pose& T, float c0,
@@ -64,10 +66,23 @@ __device__ __forceinline__ void ingest_range(const Grid& g, const float* __restr
         for (int i = threadIdx.x; i < slots * pb.Cb; i += nthr) lds.ch[i] = 0.0f;
     __syncthreads();
 
-    for (int64_t i = begin + threadIdx.x; i < end; i += nthr) {
+    float in[P][3];
+#pragma unroll
+    for (int k = 0; k < P; k++) {
+        const int64_t i = begin + threadIdx.x + (int64_t)k * nthr;
+        if (i < end) {
+            in[k][0] = xyz[3 * i];
+            in[k][1] = xyz[3 * i + 1];
+            in[k][2] = xyz[3 * i + 2];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < P; k++) {
+        const int64_t i = begin + threadIdx.x + (int64_t)k * nthr;
+        if (i >= end) break;
         float px, py, pz, r2;
         int ix, iy;
-        int r = point_cell(g, T, mr2, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], px, py, pz, r2, ix, iy);
+        int r = point_cell(g, T, mr2, in[k][0], in[k][1], in[k][2], px, py, pz, r2, ix, iy);
         if (r != 0) {
             pc.nonfinite += (r == -1);
             pc.range += (r == -2);
