@@ -28,9 +28,12 @@ constexpr int kTile = 16;
 // vcode[k * cap + position].
 __global__ __launch_bounds__(256) void k_view(Grid g, Camera cam, const float* __restrict__ h,
                                               int4* __restrict__ vlist, int* __restrict__ vcode, int cap,
-                                              int* __restrict__ vcount, int32_t* __restrict__ dbg,
+                                              int* __restrict__ vcount, int* __restrict__ vcount_next,
+                                              int32_t* __restrict__ dbg,
                                               unsigned long long* __restrict__ stats)
 {
+    // the next projection's counter (this one's was cleared by the last)
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && threadIdx.y == 0) *vcount_next = 0;
     const int ix = blockIdx.x * kTile + threadIdx.x;
     const int iy = blockIdx.y * kTile + threadIdx.y;
     int code[kMaxImages];
@@ -183,11 +186,12 @@ void launch_zero_int(hipStream_t s, int* p, int n)
 }
 
 void launch_project(hipStream_t s, const Grid& g, const Camera& cam, const float* h, const TileMax& tm, int cap,
-                    int* vcount, int4* vlist, int* vcode, int32_t* dbg, unsigned long long* stats)
+                    int* vcount, int* vcount_next, int4* vlist, int* vcode, int32_t* dbg,
+                    unsigned long long* stats)
 {
     dim3 grid((g.W + kTile - 1) / kTile, (g.H + kTile - 1) / kTile);
-    hipLaunchKernelGGL(k_view, grid, dim3(kTile, kTile), 0, s, g, cam, h, vlist, vcode, cap, vcount, dbg,
-                       stats);
+    hipLaunchKernelGGL(k_view, grid, dim3(kTile, kTile), 0, s, g, cam, h, vlist, vcode, cap, vcount, vcount_next,
+                       dbg, stats);
     int64_t blocks = ((int64_t)cap * kOccLanes + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;

@@ -95,7 +95,9 @@ struct mem_map {
     float* wsum = nullptr;
     float* ssum = nullptr;
     float2* stash = nullptr;
-    int* vcount = nullptr;      // cells listed in vlist
+    int* vcount = nullptr;      // cells listed in vlist: two counters used by turns (vpar)
+    int vpar = 0;               // the counter the next projection uses; its k_view clears the other
+    bool tmax_stale = true;     // the heights changed since the block maxima were built
     int* longs = nullptr;       // long rays of the clearing march (kMarchPass entries)
     float* hl = nullptr;        // heights in logical order, for the clearing march
     int* clr_l = nullptr;       // the march's votes in logical order
@@ -116,12 +118,26 @@ struct mem_map {
         const int64_t n8 = (int64_t)((W + 7) / 8) * ((H + 7) / 8);
         return n8 + (int64_t)((W + 63) / 64) * ((H + 63) / 64);
     }
-    TileMax tiles(hipStream_t s) const
+    // Block maxima of the current heights, rebuilt only when a call changed
+    // the heights (or the ring offsets) since they were last built.
+    TileMax tiles(hipStream_t s)
     {
         const Grid g = grid();
         const int64_t n8 = (int64_t)((W + 7) / 8) * ((H + 7) / 8);
-        launch_tile_max(s, g, h, tmax, tmax + n8);
+        if (tmax_stale) {
+            launch_tile_max(s, g, h, tmax, tmax + n8);
+            tmax_stale = false;
+        }
         return tile_max_dims(g, tmax, tmax + n8);
+    }
+
+    // The projection counter for this call; the call's k_view clears the
+    // other one for the next call (calls on a map are stream ordered).
+    int* take_vcount()
+    {
+        int* c = vcount + vpar;
+        vpar ^= 1;
+        return c;
     }
 
     Grid grid() const
@@ -329,7 +345,7 @@ mem_status mem_create(const mem_params* p, void* stream, mem_map** out)
         (st = dev_alloc(m, &m->wsum, HW)) || (st = dev_alloc(m, &m->ssum, HW)) ||
         (st = dev_alloc(m, &m->stash, HW)) ||
         (st = dev_alloc(m, &m->vlist, HW)) || (st = dev_alloc(m, &m->vcode, HW * kMaxImages)) ||
-        (st = dev_alloc(m, &m->vcount, 1)) || (st = dev_alloc(m, &m->tmax, m->tmax_size())) ||
+        (st = dev_alloc(m, &m->vcount, 2)) || (st = dev_alloc(m, &m->tmax, m->tmax_size())) ||
         (st = dev_alloc(m, &m->longs, kMarchPass)) || (st = dev_alloc(m, &m->n_long, 1)) ||
         (st = dev_alloc(m, &m->hl, HW)) || (st = dev_alloc(m, &m->clr_l, HW)) ||
         (st = dev_alloc(m, &m->stats, kStats * kStatSlots))) {
@@ -365,7 +381,7 @@ mem_status mem_create(const mem_params* p, void* stream, mem_map** out)
     launch_reset_rect(s, g, 0, m->W, 0, m->H, m->h, m->v, m->cnt, m->clr, devs.data(), (int)devs.size());
     launch_zero_accum(s, g, m->cnt, m->wsum, m->ssum, m->clr, nullptr, 0, nullptr, nullptr, nullptr);
     launch_zero_int(s, (int*)m->stats, 2 * kStats * kStatSlots);
-    launch_zero_int(s, m->vcount, 1);
+    launch_zero_int(s, m->vcount, 2);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
@@ -405,6 +421,7 @@ mem_status mem_move(mem_map* m, float x, float y, void* stream)
     int ncx = (int)gx, ncy = (int)gy;
     int sx = ncx - m->cx, sy = ncy - m->cy;
     if (sx == 0 && sy == 0) return MEM_OK;
+    m->tmax_stale = true;
     m->cx = ncx;
     m->cy = ncy;
     auto devs = layer_devs(m);
@@ -486,6 +503,7 @@ mem_status mem_input_pointcloud(mem_map* m, const float* xyz, int64_t n, const f
             launch_clear_march(s, g, xyz, n, T, m->mr2, m->clear_margin, m->hl, m->clr_l, m->longs, m->n_long,
                                m->stats);
         });
+    m->tmax_stale = true;
     timed(m, s, "finalize", [&] {
         launch_finalize(s, g, m->cnt, m->wsum, m->ssum, m->stash, m->clr_l, m->clr, m->clear_min, m->h, m->v,
                         m->chsum, pb, m->stats);
@@ -546,11 +564,12 @@ mem_status mem_input_images(mem_map* m, const mem_image* images, int32_t n_image
     hipStream_t s = (hipStream_t)stream;
     Grid g = m->grid();
     const int cap = (int)m->cells();
-    timed(m, s, "zero_count", [&] { launch_zero_int(s, m->vcount, 1); });
     TileMax tm;
     timed(m, s, "tile_max", [&] { tm = m->tiles(s); });
+    int* vc = m->take_vcount();
+    int* vc_next = m->vcount + m->vpar;
     timed(m, s, "project", [&] {
-        launch_project(s, g, cam, m->h, tm, cap, m->vcount, m->vlist, m->vcode, nullptr, m->stats);
+        launch_project(s, g, cam, m->h, tm, cap, vc, vc_next, m->vlist, m->vcode, nullptr, m->stats);
     });
     for (int k = 0; k < n_images; k++) {
         const mem_image& im = images[k];
@@ -559,7 +578,7 @@ mem_status mem_input_images(mem_map* m, const mem_image* images, int32_t n_image
             resolve_layer(m, im.bind[b].layer, &L);
             LayerDev d = L->dev();
             timed(m, s, "gather_fuse", [&] {
-                launch_gather_fuse(s, m->vlist, m->vcode + (int64_t)k * cap, m->vcount, cap, im.data,
+                launch_gather_fuse(s, m->vlist, m->vcode + (int64_t)k * cap, vc, cap, im.data,
                                    im.dtype, im.strides[0], im.strides[1], im.strides[2], im.w,
                                    im.bind[b].ch_first, d);
             });
@@ -628,6 +647,7 @@ mem_status mem_set_layer(mem_map* m, int32_t layer, int32_t view, const float* i
         d = L->dev();
     }
     hipStream_t s = (hipStream_t)stream;
+    if (layer == MEM_LAYER_ELEVATION) m->tmax_stale = true;
     timed(m, s, "setlayer", [&] {
         launch_setlayer(s, m->grid(), layer, view, m->h, m->v, layer >= MEM_LAYER_USER0 ? &d : nullptr, in);
     });
@@ -660,9 +680,10 @@ mem_status mem_debug_cell_pixels(const mem_map* mc, int32_t h, int32_t w, const 
     cam.n = 1;
     cam.min_depth = m->min_depth;
     hipStream_t s = (hipStream_t)stream;
-    launch_zero_int(s, m->vcount, 1);
     const TileMax tm = m->tiles(s);
-    launch_project(s, m->grid(), cam, m->h, tm, (int)m->cells(), m->vcount, m->vlist, m->vcode, out, m->stats);
+    int* vc = m->take_vcount();
+    launch_project(s, m->grid(), cam, m->h, tm, (int)m->cells(), vc, m->vcount + m->vpar, m->vlist, m->vcode, out,
+                   m->stats);
     return check_launch(m, "mem_debug_cell_pixels");
 }
 

@@ -145,9 +145,11 @@ void launch_tile_max(hipStream_t s, const Grid& g, const float* h, float* t8, fl
 // (st, ix, iy, intermediate cells of the occlusion line; *vcount entries, at
 // most cap) with their pixel codes in vcode[k * cap + position] (-1 outside
 // image k), k_occlude overwrites the codes of occluded cells with -1.
-// *vcount must be zero on entry.
+// *vcount must be zero on entry; k_view clears *vcount_next (a different
+// counter, the next projection's) so that no separate clear is launched.
 void launch_project(hipStream_t s, const Grid& g, const Camera& cam, const float* h, const TileMax& tm, int cap,
-                    int* vcount, int4* vlist, int* vcode, int32_t* dbg, unsigned long long* stats);
+                    int* vcount, int* vcount_next, int4* vlist, int* vcode, int32_t* dbg,
+                    unsigned long long* stats);
 // Fuses image channels into layer L for the listed cells whose code (image's
 // row of vcode) is >= 0.
 void launch_gather_fuse(hipStream_t s, const int4* vlist, const int* vcode, const int* count, int max_pairs,
