@@ -34,18 +34,20 @@ HBM_PEAK_GBS = 8000.0
 # SIMDs x 16 lanes per clock x 2.4 GHz (the FP32 peak of 157.3 TFLOP/s counts
 # an FMA as two flops on 128 lanes).
 VALU_LANE_OPS = 256 * 64 * 2.4e9
-# VALU instructions a lane executes per cell of a Bresenham walk (step,
-# ray height, storage index, test), counted in the gfx950 ISA of the walk
-# loop of this build.
-WALK_VALU_PER_CELL = 40
+# VALU instructions a lane executes per cell of a Bresenham walk, counted in
+# the gfx950 ISA of this build: the clearing march's logical walk issues 294
+# per 16 cells in its main loop (step, linear index, ray height, test); the
+# occlusion walk with block-max skipping about 57 per cell it loads.
+WALK_VALU_PER_CELL = {"clear_march": 18, "project": 57}
 
 # HBM traffic of kernels from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled
 # by the same counters for a plain 256 MiB copy (profiles/), valid while the
 # kernel's sources hash to `sha`.
 TRAFFIC = {
-    # k_clear_march, full-rate workload: FETCH_SIZE 2146.9 KiB x 1.99985 (a
-    # 256 MiB copy reads FETCH_SIZE 131083.5 KiB) + WRITE_SIZE 461.1 KiB x 1.0
-    "clear_march": {"bytes_per_launch": 4868743, "sha": "6e58dfff130780b9"},
+    # k_clear_march + k_clear_long per cloud, full-rate workload: FETCH_SIZE
+    # (1476.0 + 1823.8) KiB x 1.99985 (a 256 MiB copy reads FETCH_SIZE
+    # 131083.5 KiB) + WRITE_SIZE (314.5 + 423.5) KiB x 1.0
+    "clear_march": {"bytes_per_launch": 7513196, "sha": "723591d4ac5991c6"},
 }
 
 
@@ -611,9 +613,9 @@ def main():
             roof = dict(kernel=dom, bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                         frac=round(ach / HBM_PEAK_GBS, 4), traffic=None)
         else:  # ray walks: VALU bound; achieved in ray cells per second
-            cells = st["ray_steps"] if dom == "clear_march" else st["occl_steps"]
+            cells = st["ray_steps"] if dom == "clear_march" else st["occl_cells"]
             rate = cells / (kd["total_ms"] * 1e-3) / 1e9
-            peak = VALU_LANE_OPS / WALK_VALU_PER_CELL / 1e9
+            peak = VALU_LANE_OPS / WALK_VALU_PER_CELL[dom] / 1e9
             roof = dict(kernel=dom, bound="alu", achieved=round(rate, 2), unit="Gcell/s", peak=round(peak, 1),
                         frac=round(rate / peak, 4), traffic=traffic_bytes(dom),
                         cells_per_launch=round(cells / kd["launches"]), avg_us=kd["avg_us"])
@@ -623,7 +625,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "full-rate single robot: 500x500 grid at 0.04 m; per frame 1 LiDAR 128x2048 "
-                               "+ 4 depth cameras 640x480 (~1.4M points), 4 RGB cameras x (RGB 640x480 u8, "
+                               "+ 4 depth cameras 640x480 (1.25M returns), 4 RGB cameras x (RGB 640x480 u8, "
                                "features 160x120x64 f32 Gaussian, classes 640x480x20 f32 Dirichlet)",
                    "frames": n_frames, "points_per_frame": round(st["points_in"] / args.steps)},
         "latency_ms": {"mean": round(float(lat.mean()), 4), "std": round(float(lat.std()), 4),
