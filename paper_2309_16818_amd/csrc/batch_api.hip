@@ -79,7 +79,7 @@ struct mem_batch {
 
     char* arena = nullptr;
     size_t arena_bytes = 0;
-    float *h = nullptr, *v = nullptr, *wsum = nullptr, *ssum = nullptr;
+    float *h = nullptr, *v = nullptr, *wsum = nullptr, *ssum = nullptr, *hl = nullptr;
     int *cnt = nullptr, *clr = nullptr;
     float2* stash = nullptr;
 
@@ -244,6 +244,7 @@ BatchDev device_view(const mem_batch* b)
 {
     BatchDev d;
     d.h = b->h;
+    d.hl = b->hl;
     d.v = b->v;
     d.cnt = b->cnt;
     d.clr = b->clr;
@@ -508,7 +509,7 @@ mem_status mem_batch_create(const mem_batch_params* p, void* stream, mem_batch**
     size_t a = 0;
     auto take = [&](size_t bytes) { size_t o = a; a = align256(a + bytes); return o; };
     const size_t o_h = take(4 * total), o_v = take(4 * total), o_cnt = take(4 * total), o_clr = take(4 * total),
-                 o_w = take(4 * total), o_s = take(4 * total), o_st = take(8 * total);
+                 o_w = take(4 * total), o_s = take(4 * total), o_st = take(8 * total), o_hl = take(4 * total);
     std::vector<size_t> o_val, o_var;
     for (int l = 0; l < p->n_layers; l++) {
         const mem_layer_desc& d = p->layers[l];
@@ -530,6 +531,7 @@ mem_status mem_batch_create(const mem_batch_params* p, void* stream, mem_batch**
     b->wsum = (float*)(b->arena + o_w);
     b->ssum = (float*)(b->arena + o_s);
     b->stash = (float2*)(b->arena + o_st);
+    b->hl = (float*)(b->arena + o_hl);
     for (int l = 0; l < p->n_layers; l++) {
         const mem_layer_desc& d = p->layers[l];
         BLayer L;

@@ -315,20 +315,6 @@ __device__ __forceinline__ int walk_range_logical(const Grid& g, Ray& r, const f
     return walk_logical<U>(g, r, h, visit);
 }
 
-// Visits `count` cells of the ray starting with intermediate cell `first`
-// (1 = the cell after the start cell), U at a time, like walk_cells.
-template <int U, class Visit>
-__device__ __forceinline__ int walk_range(const Grid& g, Ray& r, const float* __restrict__ h,
-                                          int first, int count, Visit&& visit)
-{
-    r.L.jump_from_start(first - 1);
-    const int steps = r.L.steps;
-    r.L.steps = count + 1;  // walk_cells visits steps - 1 cells
-    const int n = walk_cells<U>(g, r, h, visit);
-    r.L.steps = steps;
-    return n;
-}
-
 // Largest entry of a block-max table (blocks of side 1 << shift) over the
 // blocks that the logical cells between (x0, y0) and (x1, y1) (inclusive,
 // either order, clamped to the grid) fall in; -inf if none is inside.

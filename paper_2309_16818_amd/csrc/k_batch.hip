@@ -251,20 +251,88 @@ __global__ __launch_bounds__(kBatchWG) void k_b_tile_ingest(BatchDev d)
     }
 }
 
+// Every map's heights copied into logical order (index y * W + x within the
+// map) for the clearing walks: dense over the arena, each workgroup taking
+// ranges of kLogicalRange cells, finding the map of a range's first cell by
+// bisection over the maps' first cells and stepping to the next map where a
+// thread's cell lies past a boundary.
+constexpr int kLogicalRange = 4096;
+__global__ __launch_bounds__(256) void k_b_logical(BatchDev d)
+{
+    __shared__ int s_map;
+    for (int64_t c0 = (int64_t)blockIdx.x * kLogicalRange; c0 < d.total_cells;
+         c0 += (int64_t)gridDim.x * kLogicalRange) {
+        if (threadIdx.x == 0) {
+            int lo = 0, hi = d.n_maps;  // maps[lo].cell_off <= c0 < maps[hi].cell_off
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (d.maps[mid].cell_off <= c0) lo = mid;
+                else hi = mid;
+            }
+            s_map = lo;
+        }
+        __syncthreads();
+        int lo = s_map;
+        for (int k = 0; k < kLogicalRange; k += 256) {
+            const int64_t i = c0 + k + threadIdx.x;
+            if (i >= d.total_cells) break;
+            while (lo + 1 < d.n_maps && d.maps[lo + 1].cell_off <= i) lo++;
+            const BatchMap& m = d.maps[lo];
+            int ix, iy;
+            logical_index(m.g, (int)(i - m.cell_off), ix, iy);
+            d.hl[m.cell_off + (int64_t)iy * m.g.W + ix] = d.h[i];
+        }
+        __syncthreads();  // s_map is rewritten for the next range
+    }
+}
+
 __global__ __launch_bounds__(kBatchWG) void k_b_march(BatchDev d, const float* __restrict__ xyz,
                                                       float mr2, float margin)
 {
+    static_assert(kBatchWG == 256, "one ray per thread of a 256-thread group");
+    constexpr int kNB = 10;  // length buckets: none, 1-8, ..., 57-64, longer
     __shared__ int s_item;
-    int visited = 0;
+    __shared__ int s_off[kNB];
+    __shared__ int s_order[256];
+    __shared__ int s_steps[256];
+    __shared__ float4 s_pt[256];
+    __shared__ int2 s_cell[256];
+    const int t = threadIdx.x;
+    int visited = 0, all_steps = 0;
     const int n = d.n_items[1];
     for (int it = next_item(d.qctr, 2, n, &s_item); it >= 0; it = next_item(d.qctr, 2, n, &s_item)) {
         int64_t b0, b1;
         const BatchMap& m = d.maps[chunk_item(d, it, b0, b1)];
-        for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x)
-            visited += march_point(m.g, xyz, i, m.T, mr2, margin, d.h + m.cell_off, d.clr + m.cell_off);
+        Grid gl = m.g;  // the walks read the logical-order height copy
+        gl.rx = 0;
+        gl.ry = 0;
+        const float sx = m.T.m[3], sy = m.T.m[7], sz = m.T.m[11];
+        int ax, ay;
+        lattice_cell(m.g, sx, sy, ax, ay);
+        for (int64_t base = b0; base < b1; base += 256) {
+            const int64_t i = base + t;
+            float px = 0.f, py = 0.f, pz = 0.f, r2;
+            int ix = 0, iy = 0, steps = 0;
+            if (i < b1 &&
+                point_cell(m.g, m.T, mr2, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], px, py, pz, r2, ix, iy) == 0)
+                steps = max(max(abs(ix - ax), abs(iy - ay)) - 1, 0);
+            all_steps += steps;
+            s_steps[t] = steps;
+            s_pt[t] = make_float4(px, py, pz, 0.f);
+            s_cell[t] = make_int2(ix, iy);
+            const int src = order_by_length<kNB>(steps, s_off, s_order);
+            if (s_steps[src] > 0) {
+                const float4 p = s_pt[src];
+                const int2 c = s_cell[src];
+                Ray ray(gl, ax, ay, c.x, c.y, sx, sy, sz, p.x, p.y, p.z);
+                visited += walk_logical<8>(gl, ray, d.hl + m.cell_off,
+                                           ClearVoteLogical{d.clr + m.cell_off, m.g, margin});
+            }
+            __syncthreads();  // the next group overwrites the LDS tables
+        }
     }
-    const int ids[2] = {ST_RAY_CELLS, ST_RAY_STEPS};  // every cell of a ray is loaded here
-    int vals[2] = {visited, visited};
+    const int ids[2] = {ST_RAY_CELLS, ST_RAY_STEPS};
+    int vals[2] = {visited, all_steps};
     block_stats(d.stats, ids, vals);
 }
 
@@ -377,8 +445,12 @@ void launch_batch_step(hipStream_t s, const BatchDev& d, const BatchLaunch& bl, 
     hipLaunchKernelGGL(k_b_bin, dim3(bl.grid), dim3(kBatchWG), 0, s, d, xyz, c0, c1, mr2);
     hipLaunchKernelGGL(k_b_tile_ingest, dim3(bl.grid), dim3(kBatchWG), batch_tile_ingest_lds_bytes(d.itile_h), s,
                        d);
-    if (clear_min > 0)
+    if (clear_min > 0) {
+        int64_t lb = (d.total_cells + kLogicalRange - 1) / kLogicalRange;
+        if (lb > 4096) lb = 4096;
+        hipLaunchKernelGGL(k_b_logical, dim3((unsigned)lb), dim3(256), 0, s, d);
         hipLaunchKernelGGL(k_b_march, dim3(bl.grid), dim3(kBatchWG), 0, s, d, xyz, mr2, margin);
+    }
     hipLaunchKernelGGL(k_b_finalize, dim3((unsigned)zb), dim3(256), 0, s, d, clear_min);
     if (!images) return;
     hipLaunchKernelGGL(k_b_project, dim3(bl.grid), dim3(kBatchWG), 0, s, d, bl.tile);

@@ -90,19 +90,6 @@ __global__ __launch_bounds__(kWG) void k_ingest(Grid g, const float* __restrict_
     block_stats(stats, ids, vals);
 }
 
-// Clearing vote of one cell: the ray passes below the cell's height by more
-// than the margin.  NaN (no height) never votes.
-struct ClearVote {
-    int* clr;
-    float margin;
-    __device__ __forceinline__ bool operator()(int st, float hk, float zr) const
-    {
-        const float thr = zr + margin;
-        if (hk > thr) atomicAdd(&clr[st], 1);
-        return false;
-    }
-};
-
 // One ray per lane.  Scan order puts rays of very different lengths side by
 // side (the beams of one LiDAR firing), and a wave runs as long as its
 // longest ray, so the workgroup first orders its 256 rays by length bucket
@@ -112,10 +99,9 @@ struct ClearVote {
 // last bucket) are appended to `longs` (indices into this launch's points)
 // instead: workgroups whose points lie far away would otherwise hold their
 // CU long after the rest of the grid has finished.
-__global__ __launch_bounds__(256) void k_clear_march(Grid g, const float* __restrict__ xyz,
-                                                     int64_t n, Pose T, float mr2, float margin,
-                                                     const float* __restrict__ h,
-                                                     int* __restrict__ clr,
+__global__ __launch_bounds__(256) void k_clear_march(Grid g, Grid gl, const float* __restrict__ hl,
+                                                     const float* __restrict__ xyz, int64_t n, Pose T,
+                                                     float mr2, float margin, int* __restrict__ clr,
                                                      int* __restrict__ longs,
                                                      int* __restrict__ n_long,
                                                      unsigned long long* __restrict__ stats)
@@ -135,40 +121,27 @@ __global__ __launch_bounds__(256) void k_clear_march(Grid g, const float* __rest
     const float sx = T.m[3], sy = T.m[7], sz = T.m[11];
     int ax, ay;
     lattice_cell(g, sx, sy, ax, ay);
-    if (t < kBuckets) s_off[t] = 0;
     if (i < n && point_cell(g, T, mr2, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], px, py, pz, r2, ix, iy) == 0)
         steps = max(max(abs(ix - ax), abs(iy - ay)) - 1, 0);
     s_steps[t] = steps;
     s_pt[t] = make_float4(px, py, pz, 0.f);
     s_cell[t] = make_int2(ix, iy);
-    const int bucket = min((steps + 7) >> 3, kBuckets - 1);
-    __syncthreads();
-    const int pos = atomicAdd(&s_off[bucket], 1);  // rank within the bucket
-    __syncthreads();
+    const int src = order_by_length<kBuckets>(steps, s_off, s_order);
+    const int first_long = s_off[kBuckets - 1];  // the long rays are the last lanes
     if (t == 0) {
-        int acc = 0;
-        for (int q = 0; q < kBuckets; q++) {
-            const int c = s_off[q];
-            s_off[q] = acc;
-            acc += c;
-        }
-        const int nl = 256 - s_off[kBuckets - 1];
+        const int nl = 256 - first_long;
         s_long_base = nl > 0 ? atomicAdd(n_long, nl) : 0;
     }
     __syncthreads();
-    s_order[s_off[bucket] + pos] = t;
-    __syncthreads();
-    const int src = s_order[t];
     const int my_steps = s_steps[src];
-    const int first_long = s_off[kBuckets - 1];  // the long rays are the last lanes
     int visited = 0;
     if (t >= first_long) {
         longs[s_long_base + t - first_long] = (int)((int64_t)blockIdx.x * 256 + src);
     } else if (my_steps > 0) {
         const float4 p = s_pt[src];
         const int2 c = s_cell[src];
-        Ray ray(g, ax, ay, c.x, c.y, sx, sy, sz, p.x, p.y, p.z);
-        visited = walk_logical<8>(g, ray, h, ClearVote{clr, margin});
+        Ray ray(gl, ax, ay, c.x, c.y, sx, sy, sz, p.x, p.y, p.z);
+        visited = walk_logical<8>(gl, ray, hl, ClearVoteLogical{clr, g, margin});
     }
     const int ids[2] = {ST_RAY_CELLS, ST_RAY_STEPS};
     int vals[2] = {visited, steps};
@@ -179,9 +152,9 @@ __global__ __launch_bounds__(256) void k_clear_march(Grid g, const float* __rest
 // segments of kSeg cells (the last one shorter) and the workgroup's lanes
 // take the segments in turn, entering a ray mid-way with the closed-form
 // Bresenham jump; the votes are those of walking every ray whole.
-__global__ __launch_bounds__(256) void k_clear_long(Grid g, const float* __restrict__ xyz, Pose T,
+__global__ __launch_bounds__(256) void k_clear_long(Grid g, Grid gl, const float* __restrict__ hl,
+                                                    const float* __restrict__ xyz, Pose T,
                                                     float mr2, float margin,
-                                                    const float* __restrict__ h,
                                                     int* __restrict__ clr,
                                                     const int* __restrict__ longs,
                                                     const int* __restrict__ n_long,
@@ -238,10 +211,10 @@ __global__ __launch_bounds__(256) void k_clear_long(Grid g, const float* __restr
             }
             const float4 p = s_pt[r];
             const int2 c = s_cell[r];
-            Ray ray(g, ax, ay, c.x, c.y, sx, sy, sz, p.x, p.y, p.z);
+            Ray ray(gl, ax, ay, c.x, c.y, sx, sy, sz, p.x, p.y, p.z);
             const int first = 1 + k * kSeg;
             const int cnt = min(kSeg, ray.L.steps - first);
-            visited += walk_range_logical<8>(g, ray, h, first, cnt, ClearVote{clr, margin});
+            visited += walk_range_logical<8>(gl, ray, hl, first, cnt, ClearVoteLogical{clr, g, margin});
         }
         __syncthreads();  // the next batch overwrites the LDS tables
     }
@@ -282,23 +255,13 @@ __global__ __launch_bounds__(256) void k_tile_max64(const float* __restrict__ t8
     if (lane == 0) t64[tile] = v;
 }
 
-// The clearing votes arrive in logical order (`clr_l`); each cell's count
-// is stored into the storage-order layer acc.clr, which the clear-count
-// layer view reads.
-__global__ __launch_bounds__(256) void k_finalize(Grid g, Accum acc, const int* __restrict__ clr_l,
-                                                  int clear_min, float* __restrict__ h,
-                                                  float* __restrict__ v, PointBinds pb,
+__global__ __launch_bounds__(256) void k_finalize(Grid g, Accum acc, int clear_min,
+                                                  float* __restrict__ h, float* __restrict__ v,
+                                                  PointBinds pb,
                                                   unsigned long long* __restrict__ stats)
 {
     const int st = blockIdx.x * blockDim.x + threadIdx.x;
-    int r = 0;
-    if (st < acc.HW) {
-        int ix, iy;
-        logical_index(g, st, ix, iy);
-        const int votes = clr_l[iy * g.W + ix];
-        acc.clr[st] = votes;
-        r = finalize_cell_v(st, acc, clear_min, h, v, pb, [&] { return votes; });
-    }
+    const int r = (st < acc.HW) ? finalize_cell(st, acc, clear_min, h, v, pb) : 0;
     const int ids[2] = {ST_TOUCHED, ST_CLEARED};
     int vals[2] = {r == 1 ? 1 : 0, r == 2 ? 1 : 0};
     block_stats(stats, ids, vals);
@@ -351,27 +314,26 @@ void launch_ingest(hipStream_t s, const Grid& g, const float* xyz, int64_t n, co
 }
 
 void launch_clear_march(hipStream_t s, const Grid& g_storage, const float* xyz, int64_t n, const Pose& T,
-                        float mr2, float margin, const float* hl, int* clr_l, int* longs, int* n_long,
+                        float mr2, float margin, const float* hl, int* clr, int* longs, int* n_long,
                         unsigned long long* stats)
 {
-    // heights and votes in logical order: the grid without its ring offsets
-    Grid g = g_storage;
-    g.rx = 0;
-    g.ry = 0;
-    const float* h = hl;
-    int* clr = clr_l;
+    // the walks read heights in logical order: the grid without its ring offsets
+    const Grid& g = g_storage;
+    Grid gl = g_storage;
+    gl.rx = 0;
+    gl.ry = 0;
     // The long-ray list holds kMarchPass entries: clouds beyond that are
     // marched in passes, each pass clearing the list's counter first (the
     // first pass's counter was cleared with the accumulators).
     for (int64_t b = 0; b < n; b += kMarchPass) {
         const int64_t m = n - b < kMarchPass ? n - b : kMarchPass;
         if (b > 0) launch_zero_int(s, n_long, 1);
-        hipLaunchKernelGGL(k_clear_march, dim3(blocks_for(m, 256)), dim3(256), 0, s, g, xyz + 3 * b, m, T, mr2,
-                           margin, h, clr, longs, n_long, stats);
-        unsigned gl = blocks_for(m, kLongRays);
-        if (gl > kLongGrid) gl = kLongGrid;
-        hipLaunchKernelGGL(k_clear_long, dim3(gl), dim3(256), 0, s, g, xyz + 3 * b, T, mr2, margin, h, clr,
-                           longs, n_long, stats);
+        hipLaunchKernelGGL(k_clear_march, dim3(blocks_for(m, 256)), dim3(256), 0, s, g, gl, hl, xyz + 3 * b, m, T,
+                           mr2, margin, clr, longs, n_long, stats);
+        unsigned grid_long = blocks_for(m, kLongRays);
+        if (grid_long > kLongGrid) grid_long = kLongGrid;
+        hipLaunchKernelGGL(k_clear_long, dim3(grid_long), dim3(256), 0, s, g, gl, hl, xyz + 3 * b, T, mr2, margin,
+                           clr, longs, n_long, stats);
     }
 }
 
@@ -397,14 +359,14 @@ void launch_tile_max(hipStream_t s, const Grid& g, const float* h, float* t8, fl
 }
 
 void launch_finalize(hipStream_t s, const Grid& g, const int* cnt, const float* wsum,
-                     const float* ssum, const float2* stash, const int* clr_l, int* clr, int clear_min,
+                     const float* ssum, const float2* stash, const int* clr, int clear_min,
                      float* h, float* v, const float* chsum, const PointBinds& pb,
                      unsigned long long* stats)
 {
     const int HW = g.W * g.H;
     const Accum acc{const_cast<int*>(cnt), const_cast<float*>(wsum), const_cast<float*>(ssum),
-                    const_cast<float2*>(stash), clr, const_cast<float*>(chsum), HW};
-    hipLaunchKernelGGL(k_finalize, dim3(blocks_for(HW, 256)), dim3(256), 0, s, g, acc, clr_l, clear_min, h,
+                    const_cast<float2*>(stash), const_cast<int*>(clr), const_cast<float*>(chsum), HW};
+    hipLaunchKernelGGL(k_finalize, dim3(blocks_for(HW, 256)), dim3(256), 0, s, g, acc, clear_min, h,
                        v, pb, stats);
 }
 

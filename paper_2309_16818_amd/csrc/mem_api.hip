@@ -100,7 +100,6 @@ struct mem_map {
     bool tmax_stale = true;     // the heights changed since the block maxima were built
     int* longs = nullptr;       // long rays of the clearing march (kMarchPass entries)
     float* hl = nullptr;        // heights in logical order, for the clearing march
-    int* clr_l = nullptr;       // the march's votes in logical order
     int* n_long = nullptr;      // their count
     int4* vlist = nullptr;      // cells inside a camera's view
     float* tmax = nullptr;      // block maxima of h: side 8, then side 64
@@ -251,7 +250,6 @@ void free_map(mem_map* m)
     (void)hipFree(m->vcount);
     (void)hipFree(m->longs);
     (void)hipFree(m->hl);
-    (void)hipFree(m->clr_l);
     (void)hipFree(m->n_long);
     (void)hipFree(m->vlist);
     (void)hipFree(m->vcode);
@@ -347,7 +345,7 @@ mem_status mem_create(const mem_params* p, void* stream, mem_map** out)
         (st = dev_alloc(m, &m->vlist, HW)) || (st = dev_alloc(m, &m->vcode, HW * kMaxImages)) ||
         (st = dev_alloc(m, &m->vcount, 2)) || (st = dev_alloc(m, &m->tmax, m->tmax_size())) ||
         (st = dev_alloc(m, &m->longs, kMarchPass)) || (st = dev_alloc(m, &m->n_long, 1)) ||
-        (st = dev_alloc(m, &m->hl, HW)) || (st = dev_alloc(m, &m->clr_l, HW)) ||
+        (st = dev_alloc(m, &m->hl, HW)) ||
         (st = dev_alloc(m, &m->stats, kStats * kStatSlots))) {
         free_map(m);
         return st;
@@ -489,7 +487,7 @@ mem_status mem_input_pointcloud(mem_map* m, const float* xyz, int64_t n, const f
     Grid g = m->grid();
     const bool march = m->clear_min > 0 && n > 0;
     timed(m, s, "zero_accum", [&] {
-        launch_zero_accum(s, g, m->cnt, m->wsum, m->ssum, m->clr_l, m->chsum, pb.Cb, m->n_long, m->h,
+        launch_zero_accum(s, g, m->cnt, m->wsum, m->ssum, m->clr, m->chsum, pb.Cb, m->n_long, m->h,
                           march ? m->hl : nullptr);
     });
     Pose T;
@@ -500,12 +498,12 @@ mem_status mem_input_pointcloud(mem_map* m, const float* xyz, int64_t n, const f
     });
     if (march)
         timed(m, s, "clear_march", [&] {
-            launch_clear_march(s, g, xyz, n, T, m->mr2, m->clear_margin, m->hl, m->clr_l, m->longs, m->n_long,
+            launch_clear_march(s, g, xyz, n, T, m->mr2, m->clear_margin, m->hl, m->clr, m->longs, m->n_long,
                                m->stats);
         });
     m->tmax_stale = true;
     timed(m, s, "finalize", [&] {
-        launch_finalize(s, g, m->cnt, m->wsum, m->ssum, m->stash, m->clr_l, m->clr, m->clear_min, m->h, m->v,
+        launch_finalize(s, g, m->cnt, m->wsum, m->ssum, m->stash, m->clr, m->clear_min, m->h, m->v,
                         m->chsum, pb, m->stats);
     });
     return check_launch(m, "mem_input_pointcloud");

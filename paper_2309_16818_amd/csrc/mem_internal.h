@@ -123,14 +123,13 @@ void launch_ingest(hipStream_t s, const Grid& g, const float* xyz, int64_t n, co
 // Points per clearing pass: the long-ray list `longs` holds this many
 // entries and `n_long` is its counter (cleared by launch_zero_accum).
 constexpr int64_t kMarchPass = 1 << 20;
-// The march reads the heights `hl` and counts votes into `clr_l`, both in
-// logical order; finalize stores each cell's count into the storage-order
-// layer `clr`.
+// The march reads the heights in logical order (`hl`, written by
+// launch_zero_accum) and counts votes into the storage-order layer `clr`.
 void launch_clear_march(hipStream_t s, const Grid& g, const float* xyz, int64_t n, const Pose& T,
-                        float mr2, float margin, const float* hl, int* clr_l, int* longs, int* n_long,
+                        float mr2, float margin, const float* hl, int* clr, int* longs, int* n_long,
                         unsigned long long* stats);
 void launch_finalize(hipStream_t s, const Grid& g, const int* cnt, const float* wsum,
-                     const float* ssum, const float2* stash, const int* clr_l, int* clr, int clear_min,
+                     const float* ssum, const float2* stash, const int* clr, int clear_min,
                      float* h, float* v, const float* chsum, const PointBinds& pb,
                      unsigned long long* stats);
 void launch_point_cells(hipStream_t s, const Grid& g, const float* xyz, int64_t n, const Pose& T,
@@ -182,6 +181,7 @@ struct BatchItem {          // a work item: map plus two item-specific fields
 // Device pointers of a batch (concatenated over maps).
 struct BatchDev {
     float* h;
+    float* hl;              // this step's heights in logical order, for the clearing walks
     float* v;
     int* cnt;
     int* clr;

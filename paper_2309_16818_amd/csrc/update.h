@@ -138,27 +138,52 @@ __device__ __forceinline__ void ingest_range(const Grid& g, const float* __restr
     __syncthreads();
 }
 
-// Clearing walk of point i of a cloud (Table I's ray cast).  Returns the
-// number of in-grid cells it loaded.
-__device__ __forceinline__ int march_point(const Grid& g, const float* __restrict__ xyz, int64_t i,
-                                           const Pose& T, float mr2, float margin,
-                                           const float* __restrict__ h, int* __restrict__ clr,
-                                           int* steps = nullptr)
-{
-    float px, py, pz, r2;
-    int ix, iy;
-    int r = point_cell(g, T, mr2, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], px, py, pz, r2, ix, iy);
-    if (r != 0) return 0;
-    const float sx = T.m[3], sy = T.m[7], sz = T.m[11];
-    int ax, ay;
-    lattice_cell(g, sx, sy, ax, ay);
-    Ray ray(g, ax, ay, ix, iy, sx, sy, sz, px, py, pz);
-    if (steps) *steps = max(ray.L.steps - 1, 0);
-    return walk_cells<8>(g, ray, h, [&](int st, float hk, float zr) {
-        float thr = zr + margin;
-        if (hk > thr) atomicAdd(&clr[st], 1);  // NaN (no height) never votes
+// Clearing vote of a cell reached by a walk over logical-order heights: the
+// ray passes below the cell's height by more than the margin (NaN, no
+// height, never votes).  The vote is counted in the storage-order layer, so
+// the logical index is converted only for the rare cells that vote.
+struct ClearVoteLogical {
+    int* clr;  // storage order
+    Grid g;    // the map's grid with its ring offsets
+    float margin;
+    __device__ __forceinline__ bool operator()(int lin, float hk, float zr) const
+    {
+        const float thr = zr + margin;
+        if (hk > thr) {
+            const int y = lin / g.W, x = lin - y * g.W;
+            atomicAdd(&clr[storage_index(g, x, y)], 1);
+        }
         return false;
-    });
+    }
+};
+
+// Orders a workgroup's 256 rays by length bucket of 8 cells (bucket 0: no
+// cell; the last bucket takes every ray longer than 8 (NB - 2) cells) with
+// a counting sort in LDS, so that each wave walks rays of similar length.
+// Returns the thread whose ray this thread walks; s_off[b] is left holding
+// the first position of bucket b.  Every thread of the workgroup must call
+// it; it ends with a barrier.
+template <int NB>
+__device__ __forceinline__ int order_by_length(int steps, int* s_off, int* s_order)
+{
+    const int t = threadIdx.x;
+    if (t < NB) s_off[t] = 0;
+    __syncthreads();
+    const int bucket = min((steps + 7) >> 3, NB - 1);
+    const int pos = atomicAdd(&s_off[bucket], 1);  // rank within the bucket
+    __syncthreads();
+    if (t == 0) {
+        int acc = 0;
+        for (int q = 0; q < NB; q++) {
+            const int c = s_off[q];
+            s_off[q] = acc;
+            acc += c;
+        }
+    }
+    __syncthreads();
+    s_order[s_off[bucket] + pos] = t;
+    __syncthreads();
+    return s_order[t];
 }
 
 // Height fusion, clearing and bound point channels of storage cell st;
