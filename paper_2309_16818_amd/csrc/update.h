@@ -186,16 +186,18 @@ __device__ __forceinline__ int order_by_length(int steps, int* s_off, int* s_ord
     return s_order[t];
 }
 
-// Height fusion, clearing and bound point channels of storage cell st;
-// votes() gives the cell's clearing votes (read only for a cell without
-// points).  Returns 1 if the cell received points, 2 if it was cleared,
-// else 0.
-template <class Votes>
-__device__ __forceinline__ int finalize_cell_v(int st, const Accum& acc, int clear_min,
-                                               float* __restrict__ h, float* __restrict__ v,
-                                               const PointBinds& pb, Votes&& votes)
+// Height fusion, clearing and bound point channels of storage cell st from
+// the cloud's sums for the cell, read through S: S.n() points, S.w() = sum
+// of 1/v, S.s() = sum of z/v, S.first() = (z, v) of its only point when
+// n = 1, S.ch(plane) = a bound channel's sum (the sums are read only for a
+// cell with points).  votes() gives the cell's clearing votes (read only
+// for a cell without points).  Returns 1 if the cell received points, 2 if
+// it was cleared, else 0.
+template <class Sums, class Votes>
+__device__ __forceinline__ int fuse_cell(int st, const Sums& S, int clear_min, float* __restrict__ h,
+                                         float* __restrict__ v, const PointBinds& pb, Votes&& votes)
 {
-    const int N = acc.cnt[st];
+    const int N = S.n();
     if (N == 0) {
         if (clear_min > 0 && votes() >= clear_min && !isnan(h[st])) {
             h[st] = __uint_as_float(0x7fc00000u);
@@ -207,15 +209,15 @@ __device__ __forceinline__ int finalize_cell_v(int st, const Accum& acc, int cle
     float hn, vn;
     if (!isnan(hv)) {  // prior plus the cloud, information form
         const float vv = v[st];
-        vn = 1.0f / (1.0f / vv + acc.wsum[st]);
-        hn = vn * (hv / vv + acc.ssum[st]);
+        vn = 1.0f / (1.0f / vv + S.w());
+        hn = vn * (hv / vv + S.s());
     } else if (N == 1) {  // a single point sets an empty cell exactly
-        const float2 zv = acc.stash[st];
+        const float2 zv = S.first();
         hn = zv.x;
         vn = zv.y;
     } else {
-        vn = 1.0f / acc.wsum[st];
-        hn = acc.ssum[st] * vn;
+        vn = 1.0f / S.w();
+        hn = S.s() * vn;
     }
     h[st] = hn;
     v[st] = vn;
@@ -225,7 +227,7 @@ __device__ __forceinline__ int finalize_cell_v(int st, const Accum& acc, int cle
         GaussCoef gc{0.0f, 1.0f, 0.0f, true};
         if (L.rule == MEM_GAUSS) gc = gauss_coef(L.param, L.var[st], N);
         for (int q = 0; q < C; q++) {
-            const float sum = acc.chsum[(int64_t)(off + q) * acc.HW + st];
+            const float sum = S.ch(off + q);
             const float a = sum / (float)N;
             const int64_t idx = (int64_t)st * C + q;
             const float old = layer_load(L.val, L.storage, L.scale, idx, q);
@@ -234,6 +236,26 @@ __device__ __forceinline__ int finalize_cell_v(int st, const Accum& acc, int cle
         if (L.rule == MEM_GAUSS) L.var[st] = gc.var;
     }
     return 1;
+}
+
+// The sums of storage cell st in the per-cloud accumulator arrays.
+struct AccumSums {
+    const Accum& acc;
+    int st;
+    __device__ __forceinline__ int n() const { return acc.cnt[st]; }
+    __device__ __forceinline__ float w() const { return acc.wsum[st]; }
+    __device__ __forceinline__ float s() const { return acc.ssum[st]; }
+    __device__ __forceinline__ float2 first() const { return acc.stash[st]; }
+    __device__ __forceinline__ float ch(int plane) const { return acc.chsum[(int64_t)plane * acc.HW + st]; }
+};
+
+// fuse_cell from the accumulator arrays.
+template <class Votes>
+__device__ __forceinline__ int finalize_cell_v(int st, const Accum& acc, int clear_min,
+                                               float* __restrict__ h, float* __restrict__ v,
+                                               const PointBinds& pb, Votes&& votes)
+{
+    return fuse_cell(st, AccumSums{acc, st}, clear_min, h, v, pb, votes);
 }
 
 // finalize_cell_v with the votes in acc.clr at the same storage index.
