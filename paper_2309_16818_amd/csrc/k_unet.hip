@@ -186,6 +186,18 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A,
 // Pixels advance in slices of 32 through two LDS stages holding the slices
 // transposed ([column][pixel]), the next slice's loads in flight during the
 // MFMAs.
+// LDS slot of element (row, k) of a k_gemm_tn operand tile ([row][k], k =
+// pixel): the four 8-pixel groups of a row are permuted by bits 3-4 of the
+// row.  The pixel-major tiles are transposed into LDS with 2-byte stores in
+// which the lanes of one store write rows 8 apart, and rows 8 apart share a
+// bank; the permutation spreads them over four banks, and the MFMA operand
+// reads (a whole group of one row) follow the same map.
+static_assert(BK == 32, "tn_slot permutes the four 8-pixel groups of a row");
+__device__ __forceinline__ int tn_slot(int row, int k)
+{
+    return row * LDSK + ((((k >> 3) ^ (row >> 3)) & 3) << 3) + (k & 7);
+}
+
 template <bool CONV, int WM>
 __global__ __launch_bounds__(256) void k_gemm_tn(const uint16_t* __restrict__ A, int64_t lda,
                                                  const uint16_t* __restrict__ B, int64_t ldb, ConvSrc cs, int P,
@@ -261,7 +273,7 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const uint16_t* __restrict__ A,
             const int lp = ch / APR, lc = (ch % APR) * 8;
             const uint16_t* t = (const uint16_t*)&va[u];
 #pragma unroll
-            for (int j = 0; j < 8; j++) sA[st][(lc + j) * LDSK + lp] = t[j];
+            for (int j = 0; j < 8; j++) sA[st][tn_slot(lc + j, lp)] = t[j];
         }
 #pragma unroll
         for (int u = 0; u < CB; u++) {
@@ -270,7 +282,7 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const uint16_t* __restrict__ A,
             const int lp = ch / BPR, lc = (ch % BPR) * 8;
             const uint16_t* t = (const uint16_t*)&vb[u];
 #pragma unroll
-            for (int j = 0; j < 8; j++) sB[st][(lc + j) * LDSK + lp] = t[j];
+            for (int j = 0; j < 8; j++) sB[st][tn_slot(lc + j, lp)] = t[j];
         }
     };
     if (p_begin < p_end) {
@@ -285,10 +297,10 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const uint16_t* __restrict__ A,
         if (more) load(p0 + BK);
 #pragma unroll
         for (int i = 0; i < 2; i++) {
-            const bf16x8 a = as_bf16x8(*(const uint4*)&sA[cur][(wm + 16 * i + fr) * LDSK + fk]);
+            const bf16x8 a = as_bf16x8(*(const uint4*)&sA[cur][tn_slot(wm + 16 * i + fr, fk)]);
 #pragma unroll
             for (int j = 0; j < 2; j++) {
-                const bf16x8 b = as_bf16x8(*(const uint4*)&sB[cur][(wn + 16 * j + fr) * LDSK + fk]);
+                const bf16x8 b = as_bf16x8(*(const uint4*)&sB[cur][tn_slot(wn + 16 * j + fr, fk)]);
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
             }
         }
