@@ -446,6 +446,37 @@ __global__ __launch_bounds__(256) void k_colsum(const uint16_t* __restrict__ g, 
     }
 }
 
+// k_colsum for rows of 8-channel chunks (c % 8 == 0, 256 divisible by c / 8,
+// 16-byte aligned rows): each thread reads one 16-byte chunk of a row per
+// step and keeps 8 partial sums; the workgroup then adds the partial sums
+// of each channel in LDS, one atomic per channel and workgroup.
+__global__ __launch_bounds__(256) void k_colsum8(const uint16_t* __restrict__ g, int gs, int64_t rows, int c,
+                                                 float* __restrict__ db)
+{
+    __shared__ float red[256][9];  // padded against bank conflicts in the column sums
+    const int t = threadIdx.x, cpr = c >> 3, q = t % cpr, rr = t / cpr, rstep = 256 / cpr;
+    const int64_t per = (rows + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(rows, r0 + per);
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int64_t p = r0 + rr; p < r1; p += rstep) {
+        const uint4 v = *(const uint4*)(g + p * gs + q * 8);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            acc[2 * j] += __uint_as_float(w[j] << 16);
+            acc[2 * j + 1] += __uint_as_float(w[j] & 0xffff0000u);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; j++) red[t][j] = acc[j];
+    __syncthreads();
+    if (t < c) {  // channel t = chunk t / 8, element t % 8
+        float sum = 0.f;
+        for (int k = 0; k < rstep; k++) sum += red[k * cpr + (t >> 3)][t & 7];
+        if (sum != 0.f) unsafeAtomicAdd(&db[t], sum);
+    }
+}
+
 // Head (1x1 convolution, 2 outputs, FP32 weights) and the Gaussian NLL over
 // mask > 0: writes out (optional); with a target, the per-pixel output
 // gradient gout[p] = (dL/dm, dL/ds), the bias gradient and the loss
@@ -766,7 +797,11 @@ void unet_colsum(hipStream_t s, const uint16_t* g, int gs, int64_t rows, int c, 
     int64_t blocks = (rows + 255) / 256;
     if (blocks > 1024) blocks = 1024;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_colsum, dim3((unsigned)blocks), dim3(256), 0, s, g, gs, rows, c, db);
+    const int cpr = c / 8;
+    if (c % 8 == 0 && gs % 8 == 0 && cpr <= 256 && 256 % cpr == 0 && ((uintptr_t)g & 15) == 0)
+        hipLaunchKernelGGL(k_colsum8, dim3((unsigned)blocks), dim3(256), 0, s, g, gs, rows, c, db);
+    else
+        hipLaunchKernelGGL(k_colsum, dim3((unsigned)blocks), dim3(256), 0, s, g, gs, rows, c, db);
 }
 
 void unet_head_loss(hipStream_t s, const uint16_t* d0, int c, int64_t P, const float* w, const float* b,
