@@ -10,6 +10,7 @@
 //            weight gradients, split over pixel ranges with FP32 atomics.
 // Activations are NHWC BF16; a convolution's input is unfolded (im2col)
 // into a K-padded BF16 matrix first.
+#include <initializer_list>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -572,6 +573,65 @@ __global__ __launch_bounds__(256) void k_head_wgrad(const uint16_t* __restrict__
 }
 
 // dst[p][o] += src[p][o] (FP32, strides ds / ss).
+// 8-channel forms of k_relu_mask_add and k_add_f32 for rows of 8-channel
+// chunks (c / 8 a power of two, 2^sh; every stride a multiple of 8 and the
+// rows 16-byte aligned): one thread per chunk, vector loads and stores.
+__global__ void k_relu_mask_add8(const float* __restrict__ acc, int as, const float* __restrict__ add, int ads,
+                                 const uint16_t* __restrict__ y, int ysd, int64_t rows, int sh,
+                                 uint16_t* __restrict__ g, int gs)
+{
+    const int64_t total = rows << sh;
+    const int qm = (1 << sh) - 1;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = e >> sh;
+        const int o = (int)(e & qm) * 8;
+        const float4 a0 = *(const float4*)(acc + p * as + o), a1 = *(const float4*)(acc + p * as + o + 4);
+        float v[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+        if (add) {
+            const float4 d0 = *(const float4*)(add + p * ads + o), d1 = *(const float4*)(add + p * ads + o + 4);
+            const float dv[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
+#pragma unroll
+            for (int j = 0; j < 8; j++) v[j] += dv[j];
+        }
+        if (y) {  // no y: no ReLU mask
+            const uint4 yv = *(const uint4*)(y + p * ysd + o);
+            const uint32_t yw[4] = {yv.x, yv.y, yv.z, yv.w};
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                if (!(__uint_as_float(yw[j] << 16) > 0.f)) v[2 * j] = 0.f;
+                if (!(__uint_as_float(yw[j] & 0xffff0000u) > 0.f)) v[2 * j + 1] = 0.f;
+            }
+        }
+        uint4 out;
+        out.x = (uint32_t)bf(v[0]) | ((uint32_t)bf(v[1]) << 16);
+        out.y = (uint32_t)bf(v[2]) | ((uint32_t)bf(v[3]) << 16);
+        out.z = (uint32_t)bf(v[4]) | ((uint32_t)bf(v[5]) << 16);
+        out.w = (uint32_t)bf(v[6]) | ((uint32_t)bf(v[7]) << 16);
+        *(uint4*)(g + p * gs + o) = out;
+    }
+}
+
+__global__ void k_add_f32_8(float* __restrict__ dst, int ds, const float* __restrict__ src, int ss, int64_t rows,
+                            int sh)
+{
+    const int64_t total = rows << sh;
+    const int qm = (1 << sh) - 1;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = e >> sh;
+        const int o = (int)(e & qm) * 8;
+        float4* d = (float4*)(dst + p * ds + o);
+        const float4* r = (const float4*)(src + p * ss + o);
+        float4 x0 = d[0], x1 = d[1];
+        const float4 y0 = r[0], y1 = r[1];
+        x0.x += y0.x; x0.y += y0.y; x0.z += y0.z; x0.w += y0.w;
+        x1.x += y1.x; x1.y += y1.y; x1.z += y1.z; x1.w += y1.w;
+        d[0] = x0;
+        d[1] = x1;
+    }
+}
+
 __global__ void k_add_f32(float* __restrict__ dst, int ds, const float* __restrict__ src, int ss, int64_t rows, int c)
 {
     const int64_t total = rows * c;
@@ -785,9 +845,31 @@ void unet_maxpool_bwd(hipStream_t s, const float* dy, const uint8_t* arg, int B,
                        arg, B, S, c, dx, dxs);
 }
 
+// log2(c / 8) when rows of c channels can be processed in 8-channel chunks
+// with the given strides and base pointers, else -1.
+static int chunk_shift(int c, std::initializer_list<int> strides, std::initializer_list<const void*> ptrs)
+{
+    if (c % 8 != 0) return -1;
+    const int q = c / 8;
+    if (q & (q - 1)) return -1;
+    for (int st : strides)
+        if (st % 8 != 0) return -1;
+    for (const void* p : ptrs)
+        if (((uintptr_t)p & 15) != 0) return -1;
+    int sh = 0;
+    while ((1 << sh) < q) sh++;
+    return sh;
+}
+
 void unet_relu_mask_add(hipStream_t s, const float* acc, int as, const float* add, int ads, const uint16_t* y,
                         int ys, int64_t rows, int c, uint16_t* g, int gs)
 {
+    const int sh = chunk_shift(c, {as, add ? ads : 8, y ? ys : 8, gs}, {acc, add, y, g});
+    if (sh >= 0) {
+        hipLaunchKernelGGL(k_relu_mask_add8, dim3(grid_for(rows << sh)), dim3(256), 0, s, acc, as, add, ads, y, ys,
+                           rows, sh, g, gs);
+        return;
+    }
     hipLaunchKernelGGL(k_relu_mask_add, dim3(grid_for(rows * c)), dim3(256), 0, s, acc, as, add, ads, y, ys, rows,
                        c, g, gs);
 }
@@ -820,6 +902,11 @@ void unet_head_loss(hipStream_t s, const uint16_t* d0, int c, int64_t P, const f
 
 void unet_add_f32(hipStream_t s, float* dst, int ds, const float* src, int ss, int64_t rows, int c)
 {
+    const int sh = chunk_shift(c, {ds, ss}, {dst, src});
+    if (sh >= 0) {
+        hipLaunchKernelGGL(k_add_f32_8, dim3(grid_for(rows << sh)), dim3(256), 0, s, dst, ds, src, ss, rows, sh);
+        return;
+    }
     hipLaunchKernelGGL(k_add_f32, dim3(grid_for(rows * c)), dim3(256), 0, s, dst, ds, src, ss, rows, c);
 }
 
