@@ -483,6 +483,7 @@ __global__ __launch_bounds__(256) void k_colsum8(const uint16_t* __restrict__ g,
 // gradient gout[p] = (dL/dm, dL/ds), the bias gradient and the loss
 // (reduced per workgroup, one atomic each), and the gradient with respect to
 // d0's pre-activation (BF16, ReLU-masked by d0).
+template <bool V8>
 __global__ __launch_bounds__(256) void k_head(const uint16_t* __restrict__ d0, int c, int64_t P,
                                               const float* __restrict__ w, const float* __restrict__ b,
                                               const float* __restrict__ target, const float* __restrict__ mask,
@@ -493,10 +494,23 @@ __global__ __launch_bounds__(256) void k_head(const uint16_t* __restrict__ d0, i
     float l_acc = 0.f, g0_acc = 0.f, g1_acc = 0.f;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
         float o0 = b[0], o1 = b[1];
-        for (int i = 0; i < c; i++) {
-            const float a = fb(d0[p * c + i]);
-            o0 += a * w[2 * i];
-            o1 += a * w[2 * i + 1];
+        if (V8) {  // the row in 16-byte chunks, summed in the same channel order
+            for (int i0 = 0; i0 < c; i0 += 8) {
+                const uint4 v = *(const uint4*)(d0 + p * c + i0);
+                const uint32_t vw[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int j = 0; j < 8; j++) {
+                    const float a = __uint_as_float((j & 1) ? (vw[j >> 1] & 0xffff0000u) : (vw[j >> 1] << 16));
+                    o0 += a * w[2 * (i0 + j)];
+                    o1 += a * w[2 * (i0 + j) + 1];
+                }
+            }
+        } else {
+            for (int i = 0; i < c; i++) {
+                const float a = fb(d0[p * c + i]);
+                o0 += a * w[2 * i];
+                o1 += a * w[2 * i + 1];
+            }
         }
         if (out) {
             out[2 * p] = o0;
@@ -513,9 +527,26 @@ __global__ __launch_bounds__(256) void k_head(const uint16_t* __restrict__ d0, i
         g0_acc += g0;
         g1_acc += g1;
         gout[p] = make_float2(g0, g1);
-        for (int i = 0; i < c; i++) {
-            const float a = fb(d0[p * c + i]);
-            gd0[p * c + i] = bf((a > 0.f) ? g0 * w[2 * i] + g1 * w[2 * i + 1] : 0.f);
+        if (V8) {
+            for (int i0 = 0; i0 < c; i0 += 8) {
+                const uint4 v = *(const uint4*)(d0 + p * c + i0);
+                const uint32_t vw[4] = {v.x, v.y, v.z, v.w};
+                uint32_t ow[4];
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const float a0 = __uint_as_float(vw[j] << 16), a1 = __uint_as_float(vw[j] & 0xffff0000u);
+                    const int i = i0 + 2 * j;
+                    const uint16_t r0 = bf((a0 > 0.f) ? g0 * w[2 * i] + g1 * w[2 * i + 1] : 0.f);
+                    const uint16_t r1 = bf((a1 > 0.f) ? g0 * w[2 * i + 2] + g1 * w[2 * i + 3] : 0.f);
+                    ow[j] = (uint32_t)r0 | ((uint32_t)r1 << 16);
+                }
+                *(uint4*)(gd0 + p * c + i0) = make_uint4(ow[0], ow[1], ow[2], ow[3]);
+            }
+        } else {
+            for (int i = 0; i < c; i++) {
+                const float a = fb(d0[p * c + i]);
+                gd0[p * c + i] = bf((a > 0.f) ? g0 * w[2 * i] + g1 * w[2 * i + 1] : 0.f);
+            }
         }
     }
     if (!target) return;
@@ -572,7 +603,6 @@ __global__ __launch_bounds__(256) void k_head_wgrad(const uint16_t* __restrict__
     }
 }
 
-// dst[p][o] += src[p][o] (FP32, strides ds / ss).
 // 8-channel forms of k_relu_mask_add and k_add_f32 for rows of 8-channel
 // chunks (c / 8 a power of two, 2^sh; every stride a multiple of 8 and the
 // rows 16-byte aligned): one thread per chunk, vector loads and stores.
@@ -632,6 +662,43 @@ __global__ void k_add_f32_8(float* __restrict__ dst, int ds, const float* __rest
     }
 }
 
+// k_head_wgrad for rows of 8-channel chunks (c % 8 == 0, 256 divisible by
+// c / 8, 16-byte aligned rows): a thread sums 8 channels' products for its
+// pixels, then the workgroup adds them per weight in LDS.
+__global__ __launch_bounds__(256) void k_head_wgrad8(const uint16_t* __restrict__ d0, int c, int64_t P,
+                                                     const float2* __restrict__ gout, float* __restrict__ gw)
+{
+    __shared__ float red[256][17];  // 8 channels x 2 outputs, padded
+    const int t = threadIdx.x, cpr = c >> 3, q = t % cpr, pl = t / cpr, pstep = 256 / cpr;
+    const int64_t per = (P + gridDim.x - 1) / gridDim.x;
+    const int64_t p0 = (int64_t)blockIdx.x * per, p1 = min(P, p0 + per);
+    float s0[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, s1[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int64_t p = p0 + pl; p < p1; p += pstep) {
+        const uint4 v = *(const uint4*)(d0 + p * c + q * 8);
+        const uint32_t vw[4] = {v.x, v.y, v.z, v.w};
+        const float2 g = gout[p];
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            const float a = __uint_as_float((j & 1) ? (vw[j >> 1] & 0xffff0000u) : (vw[j >> 1] << 16));
+            s0[j] += a * g.x;
+            s1[j] += a * g.y;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+        red[t][2 * j] = s0[j];
+        red[t][2 * j + 1] = s1[j];
+    }
+    __syncthreads();
+    if (t < 2 * c) {  // weight t: channel t / 2, output t % 2
+        const int i = t >> 1, o = t & 1;
+        float sum = 0.f;
+        for (int k = 0; k < pstep; k++) sum += red[k * cpr + (i >> 3)][2 * (i & 7) + o];
+        if (sum != 0.f) unsafeAtomicAdd(&gw[t], sum);
+    }
+}
+
+// dst[p][o] += src[p][o] (FP32, strides ds / ss).
 __global__ void k_add_f32(float* __restrict__ dst, int ds, const float* __restrict__ src, int ss, int64_t rows, int c)
 {
     const int64_t total = rows * c;
@@ -892,12 +959,21 @@ void unet_head_loss(hipStream_t s, const uint16_t* d0, int c, int64_t P, const f
 {
     int64_t blocks = (P + 255) / 256;
     if (blocks > 2048) blocks = 2048;
-    hipLaunchKernelGGL(k_head, dim3((unsigned)(blocks < 1 ? 1 : blocks)), dim3(256), 0, s, d0, c, P, w, b, target,
-                       mask, inv_count, out, loss, gout, gb, gd0);
+    const int cpr = c / 8;
+    const bool v8 = c % 8 == 0 && ((uintptr_t)d0 & 15) == 0 && (!gd0 || ((uintptr_t)gd0 & 15) == 0);
+    if (v8)
+        hipLaunchKernelGGL(k_head<true>, dim3((unsigned)(blocks < 1 ? 1 : blocks)), dim3(256), 0, s, d0, c, P, w, b,
+                           target, mask, inv_count, out, loss, gout, gb, gd0);
+    else
+        hipLaunchKernelGGL(k_head<false>, dim3((unsigned)(blocks < 1 ? 1 : blocks)), dim3(256), 0, s, d0, c, P, w,
+                           b, target, mask, inv_count, out, loss, gout, gb, gd0);
     if (!target) return;
     int64_t wb = (P + 1023) / 1024;
     if (wb > 512) wb = 512;
-    hipLaunchKernelGGL(k_head_wgrad, dim3((unsigned)(wb < 1 ? 1 : wb)), dim3(256), 0, s, d0, c, P, gout, gw);
+    if (v8 && 2 * c <= 256 && 256 % cpr == 0)
+        hipLaunchKernelGGL(k_head_wgrad8, dim3((unsigned)(wb < 1 ? 1 : wb)), dim3(256), 0, s, d0, c, P, gout, gw);
+    else
+        hipLaunchKernelGGL(k_head_wgrad, dim3((unsigned)(wb < 1 ? 1 : wb)), dim3(256), 0, s, d0, c, P, gout, gw);
 }
 
 void unet_add_f32(hipStream_t s, float* dst, int ds, const float* src, int ss, int64_t rows, int c)
