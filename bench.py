@@ -45,9 +45,9 @@ WALK_VALU_PER_CELL = {"clear_march": 18, "project": 57}
 # kernel's sources hash to `sha`.
 TRAFFIC = {
     # k_clear_march + k_clear_long per cloud, full-rate workload: FETCH_SIZE
-    # (1476.0 + 1823.8) KiB x 1.99985 (a 256 MiB copy reads FETCH_SIZE
-    # 131083.5 KiB) + WRITE_SIZE (314.5 + 423.5) KiB x 1.0
-    "clear_march": {"bytes_per_launch": 7513196, "sha": "723591d4ac5991c6"},
+    # (1519.6 + 1871.0) KiB x 1.99985 (a 256 MiB copy reads FETCH_SIZE
+    # 131083.5 KiB) + WRITE_SIZE (314.8 + 423.4) KiB x 1.0
+    "clear_march": {"bytes_per_launch": 7699345, "sha": "43d99782ae345e74"},
 }
 
 
