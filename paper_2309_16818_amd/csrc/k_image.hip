@@ -79,9 +79,10 @@ __global__ __launch_bounds__(256) void k_view(Grid g, Camera cam, const float* _
 
 // Pass 2: kOccLanes lanes per in-view cell split its occlusion line into
 // equal runs of cells; the cell is visible iff no lane finds an occluder.
-// The first lane of the group appends the cell's pixel to every image's
-// pair list in which it lies inside the view.
-constexpr int kOccLanes = 8;
+// The first lane of the group overwrites the cell's pixel codes with -1
+// when one does (16 lanes: a sweep of 4-64 was fastest there).
+constexpr int kOccLanes = 16;
+static_assert(kOccLanes < 64 && 64 % kOccLanes == 0, "groups of lanes within one wave (mask of kOccLanes bits)");
 
 __global__ __launch_bounds__(256) void k_occlude(Grid g, Camera cam, const float* __restrict__ h, TileMax tm,
                                                  const int4* __restrict__ vlist,
