@@ -13,16 +13,38 @@ struct LayerSet {
     int n;
 };
 
-// Resets the logical rectangle [x0, x1) x [y0, y1): one thread per cell,
-// rows along blockIdx.y.
+constexpr int kResetCells = 32;  // cells of one row per k_reset_rect workgroup
+
+// Resets the logical rectangle [x0, x1) x [y0, y1): a workgroup per run of
+// up to kResetCells cells of one row, its threads over the run's (cell,
+// channel) elements of each layer, so that a cell's channel row is written
+// by consecutive lanes (the strips a move resets are often 1-3 cells wide).
 __global__ __launch_bounds__(256) void k_reset_rect(Grid g, int x0, int x1, int y0, int y1,
                                                     float* __restrict__ h, float* __restrict__ v,
                                                     int* __restrict__ cnt, int* __restrict__ clr,
                                                     LayerSet ls)
 {
-    const int ix = x0 + blockIdx.x * blockDim.x + threadIdx.x;
-    for (int iy = y0 + blockIdx.y; iy < y1; iy += gridDim.y)
-        if (ix < x1) reset_cell(storage_index(g, ix, iy), h, v, cnt, clr, ls.L, ls.n);
+    const int xa = x0 + blockIdx.x * kResetCells;
+    const int n = min(kResetCells, x1 - xa);
+    for (int iy = y0 + blockIdx.y; iy < y1; iy += gridDim.y) {
+        if ((int)threadIdx.x < n) {
+            const int st = storage_index(g, xa + threadIdx.x, iy);
+            h[st] = kNaN;
+            v[st] = __builtin_inff();
+            cnt[st] = 0;
+            clr[st] = 0;
+        }
+        for (int l = 0; l < ls.n; l++) {
+            const LayerDev& L = ls.L[l];
+            const float init = (L.rule == MEM_DIRICHLET) ? L.param : kNaN;
+            for (int e = threadIdx.x; e < n * L.C; e += blockDim.x) {
+                const int j = e / L.C, q = e - j * L.C;
+                const int st = storage_index(g, xa + j, iy);
+                layer_store(L.val, L.storage, L.scale, (int64_t)st * L.C + q, q, init);
+            }
+            if (L.rule == MEM_GAUSS && (int)threadIdx.x < n) L.var[storage_index(g, xa + threadIdx.x, iy)] = __builtin_inff();
+        }
+    }
 }
 
 // out[(iy*W + ix)*C + q], logical order.  layer < 8: built-in layers.
@@ -114,9 +136,8 @@ void launch_reset_rect(hipStream_t s, const Grid& g, int x0, int x1, int y0, int
     LayerSet ls;
     ls.n = nL;
     for (int l = 0; l < nL; l++) ls.L[l] = L[l];
-    const int bx = 64;
-    dim3 grid((unsigned)((x1 - x0 + bx - 1) / bx), (unsigned)(y1 - y0 < 2048 ? y1 - y0 : 2048));
-    hipLaunchKernelGGL(k_reset_rect, grid, dim3(bx), 0, s, g, x0, x1, y0, y1, h, v, cnt, clr, ls);
+    dim3 grid((unsigned)((x1 - x0 + kResetCells - 1) / kResetCells), (unsigned)(y1 - y0 < 2048 ? y1 - y0 : 2048));
+    hipLaunchKernelGGL(k_reset_rect, grid, dim3(256), 0, s, g, x0, x1, y0, y1, h, v, cnt, clr, ls);
 }
 
 void launch_readout(hipStream_t s, const Grid& g, int layer, int view, const float* h,
