@@ -716,6 +716,17 @@ __global__ void k_cast_bf16(const float* __restrict__ x, int64_t n, uint16_t* __
         y[i] = bf(x[i]);
 }
 
+// Zeroes every segment of `fl` in one launch: blockIdx.y picks the segment.
+__global__ void k_zero_many(FillList fl)
+{
+    const int sgm = blockIdx.y;
+    if (sgm >= fl.n) return;
+    float* x = fl.p[sgm];
+    const int64_t n = fl.len[sgm];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = 0.0f;
+}
+
 __global__ void k_fill(float* __restrict__ x, int64_t n, float v)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -994,6 +1005,16 @@ void unet_cast_bf16(hipStream_t s, const float* x, int64_t n, uint16_t* y)
 void unet_fill(hipStream_t s, float* x, int64_t n, float v)
 {
     hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(256), 0, s, x, n, v);
+}
+
+void unet_zero_many(hipStream_t s, const FillList& fl)
+{
+    if (fl.n <= 0) return;
+    int64_t big = 1;
+    for (int i = 0; i < fl.n; i++) big = fl.len[i] > big ? fl.len[i] : big;
+    int64_t bx = (big + 255) / 256;
+    if (bx > 1024) bx = 1024;
+    hipLaunchKernelGGL(k_zero_many, dim3((unsigned)bx, (unsigned)fl.n), dim3(256), 0, s, fl);
 }
 
 void unet_relayout(hipStream_t s, const float* w, int taps, int ci, int co, int kind, int kpad, uint16_t* dst)

@@ -29,6 +29,7 @@ mem_status api_fail(mem_status code, const char* fmt, ...);
 namespace {
 
 constexpr int NLAY = 18;
+static_assert(NLAY + 6 <= kFillMax, "the gradient clear takes every layer buffer, g, de[0..3] and the loss");
 
 struct ULayer {
     int taps, ci, co;
@@ -262,15 +263,16 @@ void conv_bwd(mem_unet* u, hipStream_t s, int i, const uint16_t* x, int xs, int 
 void backward(mem_unet* u, hipStream_t s, int B, const float* target, const float* mask, float inv_count)
 {
     const int b = u->base;
+    FillList fl;  // every accumulated gradient starts at zero: one launch
     for (int i = 0; i < NLAY; i++) {
         const ULayer& Y = u->L[i];
-        if (Y.kind == 0) u->prof.timed(s, "fill", [&] { unet_fill(s, Y.gbuf, (int64_t)Y.co * Y.kf, 0.f); });
-        if (Y.kind == 2) u->prof.timed(s, "fill", [&] { unet_fill(s, Y.gbuf, (int64_t)4 * Y.co * Y.ci, 0.f); });
+        if (Y.kind == 0) fl.add(Y.gbuf, (int64_t)Y.co * Y.kf);
+        if (Y.kind == 2) fl.add(Y.gbuf, (int64_t)4 * Y.co * Y.ci);
     }
-    u->prof.timed(s, "fill", [&] { unet_fill(s, u->g, u->n_params, 0.f); });
-    for (int l = 0; l < 4; l++)
-        u->prof.timed(s, "fill", [&] { unet_fill(s, u->de[l], P_at(u, B, l) * (b << l), 0.f); });
-    u->prof.timed(s, "fill", [&] { unet_fill(s, u->loss, 1, 0.f); });
+    fl.add(u->g, u->n_params);
+    for (int l = 0; l < 4; l++) fl.add(u->de[l], P_at(u, B, l) * (b << l));
+    fl.add(u->loss, 1);
+    u->prof.timed(s, "fill", [&] { unet_zero_many(s, fl); });
     const int H = NLAY - 1;
     const int64_t P0 = P_at(u, B, 0);
     u->prof.timed(s, "head", [&] {

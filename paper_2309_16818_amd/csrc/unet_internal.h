@@ -64,6 +64,20 @@ void unet_gemm_nt(hipStream_t s, int epi, const uint16_t* A, int64_t lda, const 
 // B (P x N, row stride ldb) is dense, or the unfolded input `conv` (N = 9 ci).
 void unet_gemm_tn(hipStream_t s, const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, const ConvSrc* conv,
                   int P, int M, int N, float* C, int64_t ldc, int n_cu);
+// Up to kFillMax float buffers cleared by one launch.
+constexpr int kFillMax = 32;
+struct FillList {
+    float* p[kFillMax];
+    int64_t len[kFillMax];
+    int n = 0;
+    void add(float* q, int64_t l)
+    {
+        p[n] = q;
+        len[n] = l;
+        n++;
+    }
+};
+void unet_zero_many(hipStream_t s, const FillList& fl);
 void unet_im2col3(hipStream_t s, const uint16_t* x, int xs, int xo, int B, int S, int ci, uint16_t* col,
                   int kpad);
 void unet_gather_children(hipStream_t s, const uint16_t* dy, int ys, int yo, int B, int S, int c, uint16_t* g);
