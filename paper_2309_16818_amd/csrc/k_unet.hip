@@ -739,12 +739,11 @@ __global__ void k_fill(float* __restrict__ x, int64_t n, float v)
 // wd[c][t' co + o] = W[8 - t'][c][o]; transposed conv forward operand
 // wu[t co + o][c] = U[t][c][o]; its input-gradient operand
 // wub[c][t co + o] = U[t][c][o].
-__global__ void k_relayout(const float* __restrict__ w, int taps, int ci, int co, int kind, int kpad,
-                           uint16_t* __restrict__ dst)
+__device__ __forceinline__ void relayout_job(const float* __restrict__ w, int taps, int ci, int co, int kind, int kpad,
+                                             uint16_t* __restrict__ dst, int64_t e0, int64_t stride)
 {
     const int64_t total = (int64_t)taps * ci * co;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t e = e0; e < total; e += stride) {
         const int o = (int)(e % co);
         const int c = (int)((e / co) % ci);
         const int t = (int)(e / ((int64_t)co * ci));
@@ -758,18 +757,29 @@ __global__ void k_relayout(const float* __restrict__ w, int taps, int ci, int co
     }
 }
 
-// Back to the flat layout: conv gradient g[co][t ci + c] (ld kpad) or convT
-// gradient g[t co + o][c] -> flat[t][c][o] (added).
-__global__ void k_grad_to_flat(const float* __restrict__ g, int taps, int ci, int co, int kind, int kpad,
-                               float* __restrict__ flat)
+__global__ void k_relayout_many(WJobs js)
 {
-    const int64_t total = (int64_t)taps * ci * co;
+    if ((int)blockIdx.y >= js.n) return;
+    const WJob& J = js.j[blockIdx.y];
+    relayout_job((const float*)J.src, J.taps, J.ci, J.co, J.kind, J.kpad, (uint16_t*)J.dst,
+                 (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
+}
+
+// Back to the flat layout: conv gradient g[co][t ci + c] (ld kpad) or convT
+// gradient g[t co + o][c] -> flat[t][c][o].
+__global__ void k_grad_to_flat_many(WJobs js)
+{
+    if ((int)blockIdx.y >= js.n) return;
+    const WJob& J = js.j[blockIdx.y];
+    const float* g = (const float*)J.src;
+    float* flat = (float*)J.dst;
+    const int64_t total = (int64_t)J.taps * J.ci * J.co;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
-        const int o = (int)(e % co);
-        const int c = (int)((e / co) % ci);
-        const int t = (int)(e / ((int64_t)co * ci));
-        flat[e] = (kind == 0) ? g[(int64_t)o * kpad + t * ci + c] : g[((int64_t)t * co + o) * ci + c];
+        const int o = (int)(e % J.co);
+        const int c = (int)((e / J.co) % J.ci);
+        const int t = (int)(e / ((int64_t)J.co * J.ci));
+        flat[e] = (J.kind == 0) ? g[(int64_t)o * J.kpad + t * J.ci + c] : g[((int64_t)t * J.co + o) * J.ci + c];
     }
 }
 
@@ -1017,16 +1027,23 @@ void unet_zero_many(hipStream_t s, const FillList& fl)
     hipLaunchKernelGGL(k_zero_many, dim3((unsigned)bx, (unsigned)fl.n), dim3(256), 0, s, fl);
 }
 
-void unet_relayout(hipStream_t s, const float* w, int taps, int ci, int co, int kind, int kpad, uint16_t* dst)
+static unsigned jobs_grid_x(const WJobs& js)
 {
-    hipLaunchKernelGGL(k_relayout, dim3(grid_for((int64_t)taps * ci * co)), dim3(256), 0, s, w, taps, ci, co, kind,
-                       kpad, dst);
+    int64_t big = 1;
+    for (int i = 0; i < js.n; i++) big = std::max(big, (int64_t)js.j[i].taps * js.j[i].ci * js.j[i].co);
+    return grid_for(big);
 }
 
-void unet_grad_to_flat(hipStream_t s, const float* g, int taps, int ci, int co, int kind, int kpad, float* flat)
+void unet_relayout_many(hipStream_t s, const WJobs& js)
 {
-    hipLaunchKernelGGL(k_grad_to_flat, dim3(grid_for((int64_t)taps * ci * co)), dim3(256), 0, s, g, taps, ci, co,
-                       kind, kpad, flat);
+    if (js.n > 0)
+        hipLaunchKernelGGL(k_relayout_many, dim3(jobs_grid_x(js), (unsigned)js.n), dim3(256), 0, s, js);
+}
+
+void unet_grad_to_flat_many(hipStream_t s, const WJobs& js)
+{
+    if (js.n > 0)
+        hipLaunchKernelGGL(k_grad_to_flat_many, dim3(jobs_grid_x(js), (unsigned)js.n), dim3(256), 0, s, js);
 }
 
 void unet_adam(hipStream_t s, float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,

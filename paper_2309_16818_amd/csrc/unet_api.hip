@@ -30,6 +30,7 @@ namespace {
 
 constexpr int NLAY = 18;
 static_assert(NLAY + 6 <= kFillMax, "the gradient clear takes every layer buffer, g, de[0..3] and the loss");
+static_assert(2 * NLAY <= kWJobsMax, "two relayout jobs per layer");
 
 struct ULayer {
     int taps, ci, co;
@@ -146,23 +147,25 @@ void free_unet(mem_unet* u)
     delete u;
 }
 
-// BF16 operands from the FP32 master weights.
+// BF16 operands from the FP32 master weights, every layer in one launch.
+// The K padding of the convolution operands is never written here: it was
+// zeroed once when the network was created.
 void relayout_all(mem_unet* u, hipStream_t s)
 {
+    WJobs js;
     for (int i = 0; i < NLAY; i++) {
         ULayer& Y = u->L[i];
         if (Y.kind == 4) continue;
         const float* W = u->w + Y.off;
         if (Y.kind == 0) {
-            (void)hipMemsetAsync(Y.wf, 0, sizeof(uint16_t) * (size_t)Y.co * Y.kf, s);
-            (void)hipMemsetAsync(Y.wd, 0, sizeof(uint16_t) * (size_t)Y.ci * Y.kd, s);
-            u->prof.timed(s, "relayout", [&] { unet_relayout(s, W, Y.taps, Y.ci, Y.co, 0, Y.kf, Y.wf); });
-            u->prof.timed(s, "relayout", [&] { unet_relayout(s, W, Y.taps, Y.ci, Y.co, 1, Y.kd, Y.wd); });
+            js.add(W, Y.wf, Y.taps, Y.ci, Y.co, 0, Y.kf);
+            js.add(W, Y.wd, Y.taps, Y.ci, Y.co, 1, Y.kd);
         } else {
-            u->prof.timed(s, "relayout", [&] { unet_relayout(s, W, Y.taps, Y.ci, Y.co, 2, 0, Y.wf); });
-            u->prof.timed(s, "relayout", [&] { unet_relayout(s, W, Y.taps, Y.ci, Y.co, 3, 0, Y.wd); });
+            js.add(W, Y.wf, Y.taps, Y.ci, Y.co, 2, 0);
+            js.add(W, Y.wd, Y.taps, Y.ci, Y.co, 3, 0);
         }
     }
+    u->prof.timed(s, "relayout", [&] { unet_relayout_many(s, js); });
 }
 
 // A convolution input whose channels and stride are multiples of 8 is read
@@ -330,13 +333,13 @@ void backward(mem_unet* u, hipStream_t s, int B, const float* target, const floa
             unet_maxpool_bwd(s, u->tmpf, u->arg[l - 1], B, u->S >> (l - 1), ci, u->de[l - 1], ci);
         });
     }
+    WJobs js;
     for (int i = 0; i < NLAY; i++) {
         const ULayer& Y = u->L[i];
         if (Y.kind == 4) continue;
-        u->prof.timed(s, "eltwise", [&] {
-            unet_grad_to_flat(s, Y.gbuf, Y.taps, Y.ci, Y.co, Y.kind, Y.kf, u->g + Y.off);
-        });
+        js.add(Y.gbuf, u->g + Y.off, Y.taps, Y.ci, Y.co, Y.kind, Y.kf);
     }
+    u->prof.timed(s, "eltwise", [&] { unet_grad_to_flat_many(s, js); });
 }
 
 mem_status check_batch(const mem_unet* u, int B)
@@ -453,6 +456,12 @@ mem_status mem_unet_create(int32_t base, int32_t max_batch, int32_t size, uint64
     if (e == hipSuccess) {
         u->prof.timed(s, "fill", [&] { unet_fill(s, u->am, u->n_params, 0.f); });
         u->prof.timed(s, "fill", [&] { unet_fill(s, u->av, u->n_params, 0.f); });
+        for (int i = 0; i < NLAY; i++) {  // the operands' K padding stays zero from here on
+            const ULayer& Y = u->L[i];
+            if (Y.kind != 0) continue;
+            (void)hipMemsetAsync(Y.wf, 0, sizeof(uint16_t) * (size_t)Y.co * Y.kf, s);
+            (void)hipMemsetAsync(Y.wd, 0, sizeof(uint16_t) * (size_t)Y.ci * Y.kd, s);
+        }
         relayout_all(u, s);
         e = hipGetLastError();
     }

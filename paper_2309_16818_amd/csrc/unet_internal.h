@@ -78,6 +78,31 @@ struct FillList {
     }
 };
 void unet_zero_many(hipStream_t s, const FillList& fl);
+
+// Per-layer weight layout conversions run as one launch (blockIdx.y = job):
+// relayout jobs read a layer's FP32 master weights `src` (flat [taps][ci][co])
+// and write a BF16 operand `dst`: kind 0 conv forward [co][t ci + c], kind 1
+// conv input gradient [c][(taps - 1 - t) co + o] (both rows padded to kpad),
+// kind 2 transposed-conv forward [t co + o][c], kind 3 its input gradient
+// [c][t co + o]; gradient jobs read a layer's FP32 weight gradient (kind 0:
+// [co][t ci + c], row kpad; kind 2: [t co + o][c]) and write it flat.
+constexpr int kWJobsMax = 40;
+struct WJob {
+    const void* src;
+    void* dst;
+    int taps, ci, co, kind, kpad;
+};
+struct WJobs {
+    WJob j[kWJobsMax];
+    int n = 0;
+    void add(const void* src, void* dst, int taps, int ci, int co, int kind, int kpad)
+    {
+        j[n] = WJob{src, dst, taps, ci, co, kind, kpad};
+        n++;
+    }
+};
+void unet_relayout_many(hipStream_t s, const WJobs& js);
+void unet_grad_to_flat_many(hipStream_t s, const WJobs& js);
 void unet_im2col3(hipStream_t s, const uint16_t* x, int xs, int xo, int B, int S, int ci, uint16_t* col,
                   int kpad);
 void unet_gather_children(hipStream_t s, const uint16_t* dy, int ys, int yo, int B, int S, int c, uint16_t* g);
@@ -95,8 +120,6 @@ void unet_head_loss(hipStream_t s, const uint16_t* d0, int c, int64_t P, const f
                     float* gb, uint16_t* gd0, float2* gout);
 void unet_cast_bf16(hipStream_t s, const float* x, int64_t n, uint16_t* y);
 void unet_fill(hipStream_t s, float* x, int64_t n, float v);
-void unet_relayout(hipStream_t s, const float* w, int taps, int ci, int co, int kind, int kpad, uint16_t* dst);
-void unet_grad_to_flat(hipStream_t s, const float* g, int taps, int ci, int co, int kind, int kpad, float* flat);
 void unet_adam(hipStream_t s, float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                float eps, float c1, float c2);
 void unet_map_input(hipStream_t s, const float* h, const float* v, const Grid& g, float z_ref, float* x);
