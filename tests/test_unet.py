@@ -120,10 +120,19 @@ def test_loss_and_gradient_match_oracle(base, B, S):
     per = [relerr(g[offs[i]:offs[i + 1]], rg[offs[i]:offs[i + 1]]) for i in range(18)]
     print(f"base {base} B {B} S {S}: loss {loss:.6f} vs {rl:.6f}, grad cos {cos:.7f} rel {e:.2e}, "
           f"worst layer {int(np.argmax(per))} {max(per):.2e}")
+    # each layer's bias gradient alone (sums over pixels, a small part of a
+    # layer's parameters): output widths of the 18 layers, encoder, decoder
+    # (up, conv, conv per level) and head
+    b = base
+    couts = [b, b, 2 * b, 2 * b, 4 * b, 4 * b, 8 * b, 8 * b, 4 * b, 4 * b, 4 * b, 2 * b, 2 * b, 2 * b, b, b, b, 2]
+    assert offs[18] - offs[17] == b * 2 + 2  # the head: 1x1, base -> 2, plus its bias
+    bias = [relerr(g[offs[i + 1] - couts[i]:offs[i + 1]], rg[offs[i + 1] - couts[i]:offs[i + 1]]) for i in range(18)]
+    print(f"   worst bias {int(np.argmax(bias))} {max(bias):.2e}")
     _, bg, bl = _bars(base)
     assert abs(loss - rl) <= (1e-5 if base <= 6 else 1e-3) * max(abs(rl), 1e-3)
     assert cos >= 0.999 and e <= bg
     assert max(per) <= bl
+    assert max(bias) <= bl
     if base == 32:
         _, g64 = O.unet_loss_grad(p, x, t, m, base)
         cos64 = float(g @ g64 / (np.linalg.norm(g) * np.linalg.norm(g64)))
