@@ -46,6 +46,7 @@ def lib() -> C.CDLL:
         L.orc_set_layer.restype = I
         L.orc_layer_channels.argtypes = [P, I]
         L.orc_layer_channels.restype = I
+        L.orc_normals.argtypes = [P, P]
         L.orc_bresenham.argtypes = [I, I, I, I, P, P, I]
         L.orc_bresenham.restype = I
         _lib = L
@@ -174,6 +175,13 @@ class OracleMap:
         if r != 0:
             raise ValueError(f"oracle: no view {view} of layer {layer}")
         return out.reshape(self.H, self.W, C_) if C_ > 1 or layer >= LAYER_USER0 else out.reshape(self.H, self.W)
+
+    def normals(self):
+        """[H, W, 3] unit surface normals from the heights: central
+        differences over the 4-neighbourhood (see orc_normals)."""
+        out = np.zeros(self.H * self.W * 3, np.float64)
+        lib().orc_normals(self._m, _ptr(out))
+        return out.reshape(self.H, self.W, 3)
 
     def set_layer(self, layer, view, values):
         v = np.ascontiguousarray(np.asarray(values, np.float64).reshape(-1))

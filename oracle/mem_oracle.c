@@ -721,3 +721,34 @@ int orc_set_layer(orc_map* m, int layer, int view, const double* in)
     }
     return -1;
 }
+
+/* ------------------------------------------------------------------ */
+/* Surface normals (Table I "normal calculation"; reading R21)          */
+/* ------------------------------------------------------------------ */
+
+/* Unit normal of every cell from the height layer: with the four
+ * edge-adjacent neighbours all holding a height, the slopes are central
+ * differences g_x = (h(x+1, y) - h(x-1, y)) / (2 res), likewise g_y, and the
+ * normal is (-g_x, -g_y, 1) / sqrt(g_x^2 + g_y^2 + 1); a cell without a
+ * height, on the grid's border, or with a neighbour without one gets NaN.
+ * out: [H][W][3], logical cell order. */
+void orc_normals(const orc_map* m, double* out)
+{
+    const int W = m->W, H = m->H;
+    const double res = (double)m->res;
+    for (int iy = 0; iy < H; iy++)
+        for (int ix = 0; ix < W; ix++) {
+            double* o = out + 3 * ((long)iy * W + ix);
+            o[0] = o[1] = o[2] = NAN;
+            if (ix < 1 || ix > W - 2 || iy < 1 || iy > H - 2) continue;
+            const long j = (long)iy * W + ix;
+            if (!m->valid[j] || !m->valid[j - 1] || !m->valid[j + 1] || !m->valid[j - W] || !m->valid[j + W])
+                continue;
+            const double gx = (m->h[j + 1] - m->h[j - 1]) / (2.0 * res);
+            const double gy = (m->h[j + W] - m->h[j - W]) / (2.0 * res);
+            const double n = sqrt(gx * gx + gy * gy + 1.0);
+            o[0] = -gx / n;
+            o[1] = -gy / n;
+            o[2] = 1.0 / n;
+        }
+}

@@ -81,6 +81,9 @@ void orc_point_cells(const orc_map* m, const float* xyz, int64_t n,
 
 /* Layer views, row-major [H][W][C] binary64. */
 int orc_get_layer(const orc_map* m, int layer, int view, double* out);
+/* Unit surface normals from the heights, [H][W][3]; NaN where a height of
+ * the cell's 4-neighbourhood is missing or the cell is on the border. */
+void orc_normals(const orc_map* m, double* out);
 int orc_set_layer(orc_map* m, int layer, int view, const double* in);
 int orc_layer_channels(const orc_map* m, int layer);
 

@@ -600,3 +600,61 @@ def test_move_there_and_back_restores_the_overlap_and_far_move_resets():
     m.move(100.0, 0.0)
     assert np.isnan(m.get_layer(0, 0)).all()
     assert (m.get_layer(O.LAYER_USER0 + 1, O.VIEW_AUX) == 1.0).all()
+
+
+# ---------------------------------------------------------------------------
+# Surface normals (Table I "normal calculation"): central differences of the
+# heights over the 4-neighbourhood, NaN without a full neighbourhood.
+# ---------------------------------------------------------------------------
+
+def _oracle_with_heights(h, res):
+    H, W = h.shape
+    o = O.OracleMap(W, H, res)
+    o.set_layer(O.LAYER_ELEVATION, 0, h)
+    return o
+
+
+def test_normals_of_a_plane_are_its_normal_and_border_is_nan():
+    """Central differences are exact on a plane: every interior normal is
+    (-a, -b, 1) / sqrt(a^2 + b^2 + 1) for h = a x + b y + c."""
+    H, W, res, a, b = 9, 12, 0.05, 0.3, -0.7
+    r32 = float(np.float32(res))  # the map's cell spacing is the binary32 resolution
+    iy, ix = np.mgrid[0:H, 0:W]
+    h = a * ix * r32 + b * iy * r32 + 0.25
+    n = _oracle_with_heights(h, res).normals()
+    want = np.array([-a, -b, 1.0]) / math.sqrt(a * a + b * b + 1.0)
+    inner = n[1:-1, 1:-1]
+    assert np.allclose(inner, want, rtol=0, atol=1e-12)
+    assert np.isnan(n[0]).all() and np.isnan(n[-1]).all() and np.isnan(n[:, 0]).all() and np.isnan(n[:, -1]).all()
+    assert np.allclose(np.linalg.norm(inner, axis=-1), 1.0, atol=1e-12)
+
+
+def test_normals_of_a_parabola_follow_its_exact_slope():
+    """For h = x^2 the central difference (x+r)^2 - (x-r)^2 over 2r is 2x
+    exactly, so n = (-2x, 0, 1) / sqrt(4x^2 + 1); the y slope is zero."""
+    H, W, res = 5, 11, 0.1
+    iy, ix = np.mgrid[0:H, 0:W]
+    x = (ix - 5) * float(np.float32(res))  # binary32 cell spacing
+    n = _oracle_with_heights(x ** 2, res).normals()
+    xs = x[1:-1, 1:-1]
+    want = np.stack([-2 * xs, np.zeros_like(xs), np.ones_like(xs)], -1) / np.sqrt(4 * xs ** 2 + 1)[..., None]
+    assert np.allclose(n[1:-1, 1:-1], want, rtol=0, atol=1e-12)
+
+
+def test_normals_axes_and_missing_heights():
+    """A slope along y only tilts the normal in y (a swapped axis fails), and
+    a missing height removes the normals of the cell and its 4 neighbours."""
+    H, W, res = 7, 8, 0.04
+    iy, ix = np.mgrid[0:H, 0:W]
+    h = 0.5 * iy * float(np.float32(res))
+    h[3, 4] = np.nan
+    n = _oracle_with_heights(h, res).normals()
+    nan = np.isnan(n[..., 0])
+    expect_nan = np.zeros((H, W), bool)
+    expect_nan[0, :] = expect_nan[-1, :] = expect_nan[:, 0] = expect_nan[:, -1] = True
+    for dy, dx in ((0, 0), (1, 0), (-1, 0), (0, 1), (0, -1)):
+        expect_nan[3 + dy, 4 + dx] = True
+    assert np.array_equal(nan, expect_nan)
+    ok = ~nan
+    assert np.allclose(n[ok][:, 0], 0.0, atol=1e-12)
+    assert np.allclose(n[ok][:, 1], -0.5 / math.sqrt(1.25), atol=1e-12)
