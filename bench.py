@@ -537,6 +537,42 @@ def kernel_bytes(name, st, launches):
     return 0
 
 
+def time_normals(m, torch, reps=50):
+    """Surface normals of the final map, outside the timed frames: average
+    launch time over `reps` launches bracketed by events on the stream they
+    run on; algorithmic bytes 16 per cell (height read once, 3 floats
+    written)."""
+    out = torch.empty((m.H, m.W, 3), dtype=torch.float32, device="cuda")
+    s = torch.cuda.current_stream()
+    m.normals(out, stream=s)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    for _ in range(reps):
+        m.normals(out, stream=s)
+    b.record(s)
+    b.synchronize()
+    us = a.elapsed_time(b) * 1e3 / reps
+    gbs = 16 * m.H * m.W / (us * 1e-6) / 1e9
+    return dict(avg_us=round(us, 3), alg_bytes=16 * m.H * m.W, alg_gbs=round(gbs, 1),
+                frac=round(gbs / HBM_PEAK_GBS, 4),
+                defined=int(torch.isfinite(out[..., 2]).sum().item()))
+
+
+def time_normals_large(torch, side=4096):
+    """Surface normals of a side x side map of seeded random heights (5%
+    holes), where the launch streams 16 B per cell rather than waiting on
+    launch latency as the 500 x 500 grid does."""
+    from paper_2309_16818_amd import mem
+    m = mem.Map(mem.MapParams(side, side, 0.04))
+    g = torch.Generator(device="cuda").manual_seed(5)
+    h = torch.randn((side, side), device="cuda", generator=g) * 0.2
+    h[torch.rand((side, side), device="cuda", generator=g) < 0.05] = float("nan")
+    m.set_layer(mem.MEM_LAYER_ELEVATION, 0, h)
+    r = time_normals(m, torch, reps=20)
+    m.close()
+    return r
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -579,6 +615,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st = m.stats()
+    post = {"normals": time_normals(m, torch), "normals_4096": time_normals_large(torch)}
     m.close()
     lat = np.array([a.elapsed_time(b) for a, b in ev])
     wall_ms = (t1 - t0) * 1e3 / args.steps
@@ -630,7 +667,7 @@ def main():
                    "frames": n_frames, "points_per_frame": round(st["points_in"] / args.steps)},
         "latency_ms": {"mean": round(float(lat.mean()), 4), "std": round(float(lat.std()), 4),
                        "median": round(float(np.median(lat)), 4), "p90": round(float(np.percentile(lat, 90)), 4)},
-        "stats": st, "kernels": kernels, "roofline": roof,
+        "stats": st, "kernels": kernels, "roofline": roof, "post": post,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(frames[:args.cpu_frames])

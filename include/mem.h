@@ -259,6 +259,21 @@ mem_status mem_get_layer(const mem_map* map, int32_t layer, int32_t view,
 mem_status mem_set_layer(mem_map* map, int32_t layer, int32_t view,
                          const float* in, void* stream);
 
+/* Surface normal of every cell (Table I, "normal calculation"; the paper
+ * lists the operation without a formula).  The normal of the height field
+ * z = h(x, y) at a cell is (-gx, -gy, 1) / sqrt(gx^2 + gy^2 + 1), with the
+ * gradient from central differences of the 4-neighbours' heights:
+ *   gx = (h(ix+1, iy) - h(ix-1, iy)) / (2 r),
+ *   gy = (h(ix, iy+1) - h(ix, iy-1)) / (2 r),
+ * r the map resolution, x along ix and y along iy in the map frame.
+ * out: device, H x W x 3 float (nx, ny, nz), logical row-major cell order as
+ * mem_get_layer returns it; caller-owned, fully overwritten.  All three
+ * components are NaN on the grid's border cells and where the cell or one of
+ * its 4-neighbours holds no height.  Computed in binary32.
+ * Errors: MEM_E_ARG if out is NULL; MEM_E_STATE / MEM_E_HIP as for every
+ * call. */
+mem_status mem_normals(const mem_map* map, float* out, void* stream);
+
 /* Current centre cell of the grid (host values; no device work). */
 mem_status mem_get_center(const mem_map* map, int32_t* cx, int32_t* cy);
 

@@ -1,5 +1,5 @@
 // k_map.hip - grid maintenance: resetting cells that enter the moving grid,
-// and the layer read-out / write-in views.
+// the layer read-out / write-in views, and the per-cell surface normals.
 #include "update.h"
 
 namespace memk {
@@ -127,6 +127,41 @@ __global__ __launch_bounds__(256) void k_setlayer(Grid g, int layer, int view,
         layer_store(L.val, L.storage, L.scale, (int64_t)st * L.C + q, q, in[(int64_t)j * L.C + q]);
 }
 
+
+// Surface normal of every logical cell (Table I, normal calculation): the
+// height gradient from central differences of the four 4-neighbours, the
+// normal (-gx, -gy, 1) / |(-gx, -gy, 1)|.  NaN where the cell lies on the
+// border or it or a 4-neighbour holds no height.  Tiles of 64 x 4 cells: a
+// wave reads one row run of heights and its two neighbour rows, and writes
+// 64 x 3 consecutive floats.
+__global__ __launch_bounds__(256) void k_normals(Grid g, const float* __restrict__ h, float* __restrict__ out)
+{
+    const int ix = blockIdx.x * 64 + threadIdx.x;
+    const int iy = blockIdx.y * 4 + threadIdx.y;
+    if (ix >= g.W || iy >= g.H) return;
+    float nx = kNaN, ny = kNaN, nz = kNaN;
+    if (ix >= 1 && ix <= g.W - 2 && iy >= 1 && iy <= g.H - 2) {
+        const float hc = h[storage_index(g, ix, iy)];
+        const float hw = h[storage_index(g, ix - 1, iy)];
+        const float he = h[storage_index(g, ix + 1, iy)];
+        const float hs = h[storage_index(g, ix, iy - 1)];
+        const float hn = h[storage_index(g, ix, iy + 1)];
+        if (!isnan(hc) && !isnan(hw) && !isnan(he) && !isnan(hs) && !isnan(hn)) {
+            const float d = 2.0f * g.res;
+            const float gx = (he - hw) / d;
+            const float gy = (hn - hs) / d;
+            const float r = 1.0f / sqrtf(gx * gx + gy * gy + 1.0f);
+            nx = -gx * r;
+            ny = -gy * r;
+            nz = r;
+        }
+    }
+    float* o = out + 3 * (int64_t)(iy * g.W + ix);
+    o[0] = nx;
+    o[1] = ny;
+    o[2] = nz;
+}
+
 }  // namespace
 
 void launch_reset_rect(hipStream_t s, const Grid& g, int x0, int x1, int y0, int y1, float* h,
@@ -157,6 +192,12 @@ void launch_setlayer(hipStream_t s, const Grid& g, int layer, int view, float* h
     LayerDev l{};
     if (L) l = *L;
     hipLaunchKernelGGL(k_setlayer, dim3((HW + 255) / 256), dim3(256), 0, s, g, layer, view, h, v, l, in);
+}
+
+void launch_normals(hipStream_t s, const Grid& g, const float* h, float* out)
+{
+    dim3 grid((unsigned)((g.W + 63) / 64), (unsigned)((g.H + 3) / 4));
+    hipLaunchKernelGGL(k_normals, grid, dim3(64, 4), 0, s, g, h, out);
 }
 
 }  // namespace memk

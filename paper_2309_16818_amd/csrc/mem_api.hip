@@ -627,6 +627,16 @@ mem_status mem_get_layer(const mem_map* mc, int32_t layer, int32_t view, float* 
     return check_launch(m, "mem_get_layer");
 }
 
+mem_status mem_normals(const mem_map* mc, float* out, void* stream)
+{
+    mem_map* m = const_cast<mem_map*>(mc);
+    if (mem_status st = usable(m)) return st;
+    if (!out) return fail(MEM_E_ARG, "out is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    timed(m, s, "normals", [&] { launch_normals(s, m->grid(), m->h, out); });
+    return check_launch(m, "mem_normals");
+}
+
 mem_status mem_set_layer(mem_map* m, int32_t layer, int32_t view, const float* in, void* stream)
 {
     if (mem_status st = usable(m)) return st;

@@ -231,5 +231,7 @@ void launch_readout(hipStream_t s, const Grid& g, int layer, int view, const flo
                     const float* v, const int* cnt, const int* clr, const LayerDev* L, float* out);
 void launch_setlayer(hipStream_t s, const Grid& g, int layer, int view, float* h, float* v,
                      const LayerDev* L, const float* in);
+// Surface normals of the heights h (storage order) into out ([H][W][3], logical order).
+void launch_normals(hipStream_t s, const Grid& g, const float* h, float* out);
 
 }  // namespace memk

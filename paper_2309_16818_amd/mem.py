@@ -29,7 +29,7 @@ STAT_FIELDS = ("points_in", "points_accepted", "dropped_nonfinite", "dropped_ran
 
 # Exported symbols of include/mem.h.
 SYMBOLS = ("mem_create", "mem_destroy", "mem_move", "mem_input_pointcloud", "mem_input_image",
-           "mem_input_images", "mem_get_layer", "mem_set_layer", "mem_get_center", "mem_debug_point_cells",
+           "mem_input_images", "mem_get_layer", "mem_set_layer", "mem_normals", "mem_get_center", "mem_debug_point_cells",
            "mem_debug_cell_pixels", "mem_get_stats", "mem_reset_stats", "mem_profile_enable",
            "mem_profile_read", "mem_last_error")
 
@@ -92,6 +92,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "mem_input_images": [P, C.POINTER(mem_image), I32, P, P],
         "mem_get_layer": [P, I32, I32, P, P],
         "mem_set_layer": [P, I32, I32, P, P],
+        "mem_normals": [P, P, P],
         "mem_get_center": [P, C.POINTER(I32), C.POINTER(I32)],
         "mem_debug_point_cells": [P, P, I64, P, P, P],
         "mem_debug_cell_pixels": [P, I32, I32, P, P, P, P],
@@ -276,6 +277,16 @@ class Map:
         _check(load().mem_set_layer(self._h, layer, view, _dev_ptr(v, "values"), _stream(stream)))
         # `v` may be a temporary copy: keep it alive until the kernel has read it
         (stream or torch.cuda.current_stream()).synchronize()
+
+    def normals(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """[H, W, 3] surface normals of the heights (NaN on the border and
+        next to cells without a height)."""
+        if out is None:
+            out = torch.empty((self.H, self.W, 3), dtype=torch.float32, device="cuda")
+        if out.dtype != torch.float32 or not out.is_contiguous() or out.numel() != self.H * self.W * 3:
+            raise ValueError("out must be a contiguous float32 tensor of H x W x 3 elements")
+        _check(load().mem_normals(self._h, _dev_ptr(out, "out"), _stream(stream)))
+        return out
 
     def center(self):
         cx, cy = C.c_int32(), C.c_int32()

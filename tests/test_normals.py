@@ -1,0 +1,100 @@
+"""Surface normals of the map (Table I, "normal calculation"): the GPU
+kernel against the oracle on the same seeded heights, written into both maps
+as binary32 values.
+
+Tolerance: |dn| <= 1e-5 per component.  The normal is a unit vector; the
+GPU computes the central-difference gradient, the norm and the quotients in
+binary32 (one rounding per operation, about 8 roundings on the longest
+chain, i.e. below 1e-6), the oracle in binary64 from the same binary32
+heights.  Validity (NaN) must agree exactly.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2309_16818_amd import mem, synth
+
+N_TOL = 1e-5
+
+pytestmark = pytest.mark.gpu
+
+
+def terrain_heights(rng, W, H, res, ox, oy, hole_frac=0.05):
+    """Binary32 heights of a seeded terrain at the cell centres of the grid
+    whose logical cell (0, 0) is lattice cell (ox, oy), with holes."""
+    # boxes are placed away from the origin: give small grids a terrain of
+    # a few metres all the same
+    ter = synth.make_terrain(rng, extent=max(max(W, H) * res, 8.0))
+    xs = (ox + np.arange(W) + 0.5) * res
+    ys = (oy + np.arange(H) + 0.5) * res
+    X, Y = np.meshgrid(xs, ys)
+    h = ter.height(X, Y)
+    h[rng.uniform(size=h.shape) < hole_frac] = np.nan
+    return h.astype(np.float32)
+
+
+def pair_with_heights(W, H, res, moves, rng, hole_frac=0.05):
+    g = mem.Map(mem.MapParams(W, H, res))
+    o = O.OracleMap(W, H, res)
+    for mx, my in moves:
+        g.move(mx, my)
+        o.move(mx, my)
+    cx, cy = g.center()
+    assert (cx, cy) == o.center()
+    h = terrain_heights(rng, W, H, float(np.float32(res)), cx - W // 2, cy - H // 2, hole_frac)
+    g.set_layer(mem.MEM_LAYER_ELEVATION, 0, torch.from_numpy(h))
+    o.set_layer(O.LAYER_ELEVATION, 0, h.astype(np.float64))
+    return g, o
+
+
+def check_normals(g, o):
+    a = g.normals()
+    torch.cuda.synchronize()
+    a = a.double().cpu().numpy()
+    b = o.normals()
+    assert a.shape == b.shape == (g.H, g.W, 3)
+    assert np.array_equal(np.isnan(a), np.isnan(b)), np.argwhere(np.isnan(a) != np.isnan(b))[:5]
+    ok = ~np.isnan(b)
+    err = np.abs(a[ok] - b[ok]).max(initial=0.0)
+    assert err <= N_TOL, err
+    return int(ok.all(axis=2).sum())
+
+
+@pytest.mark.parametrize("W,H,res,moves", [
+    (61, 47, 0.05, [(0.4, -0.3)]),                       # ragged in both tile directions
+    (130, 9, 0.04, [(1.0, 0.2), (-0.37, 0.11)]),         # three tile columns, ring offsets
+    (200, 200, 0.04, [(3.1, -2.7)]),                     # small workload's grid
+    (500, 500, 0.04, [(7.3, 5.9), (-0.2, 0.4)]),         # full workload's grid
+])
+def test_normals_match_oracle(W, H, res, moves):
+    rng = np.random.default_rng(W * 1000 + H)
+    g, o = pair_with_heights(W, H, res, moves, rng)
+    n_ok = check_normals(g, o)
+    # holes of 5% leave most interior normals defined
+    assert n_ok > 0.5 * (W - 2) * (H - 2)
+
+
+@pytest.mark.parametrize("W,H", [(1, 1), (2, 2), (1, 7), (7, 1), (3, 3), (2, 64), (65, 3)])
+def test_normals_on_degenerate_grids(W, H):
+    """Grids without interior cells give only NaN; a 3 x k grid has one
+    interior row."""
+    rng = np.random.default_rng(W + 31 * H)
+    g, o = pair_with_heights(W, H, 0.1, [(0.25, -0.35)], rng, hole_frac=0.0)
+    n_ok = check_normals(g, o)
+    assert n_ok == max(W - 2, 0) * max(H - 2, 0)
+
+
+def test_normals_of_an_empty_map_are_nan():
+    g = mem.Map(mem.MapParams(37, 29, 0.05))
+    n = g.normals()
+    torch.cuda.synchronize()
+    assert torch.isnan(n).all()
+
+
+def test_normals_reject_a_wrong_output():
+    g = mem.Map(mem.MapParams(8, 8, 0.05))
+    with pytest.raises(ValueError):
+        g.normals(out=torch.empty((8, 8, 2), dtype=torch.float32, device="cuda"))
