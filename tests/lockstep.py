@@ -1,8 +1,11 @@
 """Lockstep parity harness: GPU map (libmem.so) against the CPU oracle.
 
-Before each call the GPU state is copied into the oracle (binary32 ->
-binary64 is exact), both sides run the same call on the same inputs, and
-the results are compared:
+Both maps run every call on the same inputs.  Before a call the oracle's
+own state, rounded to each GPU layer's storage type (binary32, or BF16 /
+FP8 E4M3 for reduced-precision layers, rounded on the host with torch's CPU
+conversions), is written into both maps, so that the call starts from one
+state on both sides and no oracle input ever comes from the GPU.  The
+results are then compared:
 
   * integer results bit-exact: cell of each point, hit and clearing counts,
     validity, pixel of each cell, argmax class (outside near-ties);
@@ -40,22 +43,47 @@ def gpu_layer(g: mem.Map, layer, view=0) -> np.ndarray:
     return t.double().cpu().numpy()
 
 
-def sync_oracle(g: mem.Map, o: O.OracleMap):
-    """Copies the GPU map state into the oracle."""
-    cx, cy = g.center()
-    o.set_center(cx, cy)
-    o.set_layer(O.LAYER_ELEVATION, 0, gpu_layer(g, mem.MEM_LAYER_ELEVATION))
-    o.set_layer(O.LAYER_VARIANCE, 0, gpu_layer(g, mem.MEM_LAYER_VARIANCE))
-    o.set_layer(O.LAYER_HITS, 0, gpu_layer(g, mem.MEM_LAYER_HITS))
-    o.set_layer(O.LAYER_CLEAR, 0, gpu_layer(g, mem.MEM_LAYER_CLEAR))
+def to_storage(x, storage=mem.MEM_F32, ch_scale=None) -> np.ndarray:
+    """Host rounding of binary64 values to a layer's storage type, returned
+    as binary32: round to nearest even for BF16; for FP8 E4M3 the value is
+    divided by the channel's scale amax / 448, saturated at +-448, rounded
+    to E4M3 and multiplied back (the codec the storage tests pin)."""
+    x32 = np.asarray(x, np.float64).astype(np.float32)
+    if storage == mem.MEM_F32:
+        return x32
+    if storage == mem.MEM_BF16:
+        return torch.from_numpy(x32).to(torch.bfloat16).float().numpy()
+    C = x32.shape[-1]
+    amax = np.asarray(ch_scale if ch_scale is not None else [1.0] * C, np.float32)
+    s = (amax / np.float32(448.0)).astype(np.float32)
+    q = np.clip(x32 / s, -448, 448).astype(np.float32)
+    return (torch.from_numpy(q).to(torch.float8_e4m3fn).float().numpy() * s).astype(np.float32)
+
+
+def sync_from_oracle(g, o: O.OracleMap):
+    """Writes the oracle's state, rounded to the GPU layers' storage, into
+    both maps (the per-cloud hit and clearing counts are outputs of each
+    cloud, not state, and are left as both sides computed them)."""
+    assert g.center() == o.center(), "the maps must have taken the same moves"
+    H, W = g.H, g.W
+
+    def put(lid, view, storage=mem.MEM_F32, ch_scale=None):
+        x = o.get_layer(lid, view)
+        C = x.size // (H * W)
+        x = to_storage(x.reshape(H, W, C), storage, ch_scale)
+        o.set_layer(lid, view, x.astype(np.float64))
+        g.set_layer(lid, view, torch.from_numpy(x if lid >= mem.MEM_LAYER_USER0 else x.reshape(H, W)))
+
+    put(O.LAYER_ELEVATION, 0)
+    put(O.LAYER_VARIANCE, 0)
     for k, l in enumerate(g.layers):
         lid = mem.MEM_LAYER_USER0 + k
         if l.rule == mem.MEM_DIRICHLET:
-            o.set_layer(lid, 1, gpu_layer(g, lid, 1))
+            put(lid, 1)
         else:
-            o.set_layer(lid, 0, gpu_layer(g, lid, 0))
+            put(lid, 0, l.storage, l.ch_scale)
             if l.rule == mem.MEM_GAUSS:
-                o.set_layer(lid, 1, gpu_layer(g, lid, 1))
+                put(lid, 1)
 
 
 def compare(g: mem.Map, o: O.OracleMap, counts: bool = True, what: str = "",

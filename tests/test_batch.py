@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import oracle as O
-from lockstep import compare, gpu_layer, sync_oracle, to_dev
+from lockstep import compare, gpu_layer, sync_from_oracle, to_dev
 from paper_2309_16818_amd import mem, synth
 
 pytestmark = pytest.mark.gpu
@@ -95,7 +95,7 @@ def test_every_map_of_a_batch_matches_the_oracle_in_lockstep():
         counts[1] = 0 if it == 1 else counts[1]  # a map without points this step
         xyz, offs, Ts, Tc, Ks, imgs = step_inputs(rng, SIZES, poses, counts)
         for v, o in zip(views, orcs):
-            sync_oracle(v, o)
+            sync_from_oracle(v, o)
         run_batch_step(B, poses, xyz, offs, Ts, imgs, Ks, Tc)
         for m, (v, o) in enumerate(zip(views, orcs)):
             o.move(*poses[m][:2])

@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import oracle as O
-from lockstep import compare, gpu_layer, make_pair, sync_oracle, to_dev
+from lockstep import compare, gpu_layer, make_pair, sync_from_oracle, to_dev
 from paper_2309_16818_amd import mem, synth
 
 pytestmark = pytest.mark.gpu
@@ -28,19 +28,19 @@ def pose(t=(0.0, 0.0, 0.0), R=None):
 def run_frame(g, o, frame, check=True):
     """move -> cloud -> RGB image -> class image, each call in lockstep."""
     x, y, _ = frame["pose"]
-    sync_oracle(g, o)
+    sync_from_oracle(g, o)
     g.move(x, y)
     o.move(x, y)
     if check:
         compare(g, o, what="move")
     cl = frame["cloud"]
-    sync_oracle(g, o)
+    sync_from_oracle(g, o)
     g.input_pointcloud(to_dev(cl["xyz"]), cl["T"], ch=to_dev(cl["ch"]), bind=[(8, 0, 4)])
     o.input_pointcloud(cl["xyz"], cl["T"], ch=cl["ch"], bind=[(8, 0, 4)])
     rep = compare(g, o, what="cloud") if check else {}
     cam = frame["camera"]
     for img, b in ((cam["rgb"], [(9, 0, 3)]), (cam["classes"], [(10, 0, 8)])):
-        sync_oracle(g, o)
+        sync_from_oracle(g, o)
         dimg = to_dev(img)
         pg = g.debug_cell_pixels(img.shape[0], img.shape[1], cam["K"], cam["T"])
         g.input_image(dimg, cam["K"], cam["T"], bind=b)
@@ -60,7 +60,7 @@ def test_small_workload_lockstep(small_workload):
         cl = f["cloud"]
         # bit-exact association before the call
         cg = g.debug_point_cells(to_dev(cl["xyz"]), cl["T"]).cpu().numpy()
-        sync_oracle(g, o)
+        sync_from_oracle(g, o)
         assert np.array_equal(cg, o.point_cells(cl["xyz"], cl["T"]))
         run_frame(g, o, f)
     st = g.stats()
@@ -84,7 +84,7 @@ def test_point_cells_bit_exact_with_ragged_sizes(n):
     a = g.debug_point_cells(to_dev(xyz.reshape(-1, 3)), T).cpu().numpy()
     b = o.point_cells(xyz, T)
     assert np.array_equal(a, b)
-    sync_oracle(g, o)
+    sync_from_oracle(g, o)
     g.input_pointcloud(to_dev(xyz.reshape(-1, 3)), T)
     o.input_pointcloud(xyz, T)
     compare(g, o, what=f"n={n}")
@@ -103,11 +103,13 @@ def test_points_on_cell_edges_decide_like_the_oracle():
 
 
 def rand_map_state(g, o, rng, valid_frac=0.8, hscale=0.3):
+    """Seeded heights (with holes) and variances, given to the oracle and
+    then written from it into the GPU map."""
     H, W = g.H, g.W
     h = np.where(rng.uniform(size=(H, W)) < valid_frac, rng.normal(0, hscale, (H, W)), np.nan)
-    g.set_layer(mem.MEM_LAYER_ELEVATION, 0, torch.tensor(h, dtype=torch.float32))
-    g.set_layer(mem.MEM_LAYER_VARIANCE, 0, torch.tensor(rng.uniform(1e-4, 1e-2, (H, W)), dtype=torch.float32))
-    sync_oracle(g, o)
+    o.set_layer(O.LAYER_ELEVATION, 0, h)
+    o.set_layer(O.LAYER_VARIANCE, 0, rng.uniform(1e-4, 1e-2, (H, W)))
+    sync_from_oracle(g, o)
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
@@ -142,7 +144,7 @@ def test_point_channel_rules(C):
         ch = rng.uniform(0, 1, (n, 4 * C + 2)).astype(np.float32)
         bind = [(8 + k, 2 + k * C, C) for k in range(4)]
         T = pose((0.05, -0.02, 0.4))
-        sync_oracle(g, o)
+        sync_from_oracle(g, o)
         g.input_pointcloud(to_dev(xyz), T, ch=to_dev(ch), bind=bind)
         o.input_pointcloud(xyz, T, ch=ch, bind=bind)
         compare(g, o, what=f"points C={C} it={it}")
@@ -164,7 +166,7 @@ def test_image_channel_rules(dtype, layout):
         R = synth.camera_rotation(rng.uniform(0, 2 * np.pi), math.radians(40)).astype(np.float32)
         T = pose((rng.uniform(-0.2, 0.2), rng.uniform(-0.2, 0.2), 0.8), R)
         bind = [(8 + k, k * C, C) for k in range(4)]
-        sync_oracle(g, o)
+        sync_from_oracle(g, o)
         if layout == "hwc":
             dimg = to_dev(img)
             o.input_image(img, K, T, bind=bind)
@@ -194,7 +196,7 @@ def test_images_of_one_pose_equal_sequential_single_images():
         feat = synth.feature_image(rng, 24, 32, 8)
         cls = synth.class_image(rng, 96, 128, 5)
         ims = [(rgb, K, [(8, 0, 3)]), (feat, Kq, [(9, 0, 8)]), (cls, K, [(10, 0, 5)]), (rgb2, K, [(8, 0, 3)])]
-        sync_oracle(g, o)
+        sync_from_oracle(g, o)
         g.input_images([(to_dev(a), k, b) for a, k, b in ims], T)
         for a, k, b in ims:
             o.input_image(a, k, T, bind=b)
@@ -212,8 +214,9 @@ def test_move_matches_oracle_bitwise(moves):
     bind = [(8, 0, 3), (9, 3, 2), (10, 5, 4)]
     T = pose((0.0, 0.0, 0.5))
     g.input_pointcloud(to_dev(xyz), T, ch=to_dev(ch), bind=bind)
+    o.input_pointcloud(xyz, T, ch=ch, bind=bind)
     for (x, y) in moves:
-        sync_oracle(g, o)
+        sync_from_oracle(g, o)
         g.move(x, y)
         o.move(x, y)
         assert g.center() == o.center()
@@ -249,7 +252,7 @@ def test_cloud_larger_than_one_clearing_pass():
     g.input_pointcloud(to_dev(ground), ID)
     o.input_pointcloud(ground, ID)
     compare(g, o, what="terrain")
-    sync_oracle(g, o)
+    sync_from_oracle(g, o)
     before = g.stats()
     # sensor 0.4 m up; targets at every range, many below the terrain so
     # that rays cross raised cells and vote; in the half plane y > -0.2 no
@@ -278,7 +281,8 @@ def test_empty_cloud_and_all_dropped_and_nothing_in_view():
     g, o = make_pair(30, 30, 0.1, layers=[(3, mem.MEM_LATEST, 0.0)], max_range=2.0)
     xyz = np.stack([rng.uniform(-1, 1, 500), rng.uniform(-1, 1, 500), np.zeros(500)], 1).astype(np.float32)
     g.input_pointcloud(to_dev(xyz), pose((0, 0, 1.0)))
-    sync_oracle(g, o)
+    o.input_pointcloud(xyz, pose((0, 0, 1.0)))
+    sync_from_oracle(g, o)
     # n = 0: only clears the per-cloud layers
     g.input_pointcloud(torch.empty((0, 3), dtype=torch.float32, device="cuda"), ID)
     o.input_pointcloud(np.zeros((0, 3), np.float32), ID)
@@ -286,7 +290,7 @@ def test_empty_cloud_and_all_dropped_and_nothing_in_view():
     assert gpu_layer(g, 3).sum() == 0
     # every point beyond max_range
     far = np.full((100, 3), 5.0, np.float32)
-    sync_oracle(g, o)
+    sync_from_oracle(g, o)
     g.input_pointcloud(to_dev(far), ID)
     o.input_pointcloud(far, ID)
     compare(g, o, what="all dropped")

@@ -7,7 +7,8 @@ import numpy as np
 import pytest
 import torch
 
-from lockstep import gpu_layer, make_pair, sync_oracle, to_dev
+import oracle as O
+from lockstep import gpu_layer, make_pair, sync_from_oracle, to_dev
 from paper_2309_16818_amd import mem, synth
 
 pytestmark = pytest.mark.gpu
@@ -64,8 +65,8 @@ def test_feature_fusion_within_one_storage_rounding(storage, rel):
     layers = [(C, mem.MEM_GAUSS, 1.0, storage), (C, mem.MEM_EXPAVG, 0.5, storage)]
     g, o = make_pair(48, 48, 0.05, layers=layers)
     h = np.where(rng.uniform(size=(48, 48)) < 0.9, rng.normal(0, 0.05, (48, 48)), np.nan)
-    g.set_layer(0, 0, torch.tensor(h, dtype=torch.float32))
-    g.set_layer(1, 0, torch.full((48, 48), 1e-3))
+    o.set_layer(O.LAYER_ELEVATION, 0, h)
+    o.set_layer(O.LAYER_VARIANCE, 0, np.full((48, 48), 1e-3))
     K = (60.0, 60.0, 47.5, 35.5)
     for it in range(4):
         img = synth.feature_image(rng, 72, 96, 2 * C)
@@ -73,7 +74,7 @@ def test_feature_fusion_within_one_storage_rounding(storage, rel):
         T = np.zeros((3, 4), np.float32)
         T[:, :3] = R
         T[:, 3] = (rng.uniform(-0.2, 0.2), rng.uniform(-0.2, 0.2), 0.8)
-        sync_oracle(g, o)
+        sync_from_oracle(g, o)
         g.input_image(to_dev(img), K, T, bind=[(8, 0, C), (9, C, C)])
         o.input_image(img, K, T, bind=[(8, 0, C), (9, C, C)])
         for lid in (8, 9):
