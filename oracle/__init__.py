@@ -63,7 +63,9 @@ def _pose(T) -> np.ndarray:
 
 
 def _bind(bind) -> tuple[np.ndarray, int]:
-    b = np.ascontiguousarray(np.asarray(bind if bind else [(0, 0, 0)], dtype=np.int32).reshape(-1, 3))
+    """Bindings (layer, ch_first, ch_count[, topk]) as int32 quadruples."""
+    rows = [tuple(x) + (0,) * (4 - len(x)) for x in bind] if bind else [(0, 0, 0, 0)]
+    b = np.ascontiguousarray(np.asarray(rows, dtype=np.int32).reshape(-1, 4))
     return b, (len(bind) if bind else 0)
 
 

@@ -434,6 +434,26 @@ static void fuse_cell(orc_layer* L, long j, int N, const double* mean, const dou
     }
 }
 
+/* A class measurement given as its top k classes (Sec. III-C, the top-k
+ * class input): values v[0..k) are class indices and v[k..2k) their
+ * probabilities; the measurement is the K-vector that holds each listed
+ * probability at its class and zero elsewhere (a repeated class adds).  A
+ * listed index that is not an integer in [0, K) contributes nothing. */
+static int class_index(double v, int K)
+{
+    if (!(v >= 0.0) || v >= (double)K || v != floor(v)) return -1; /* NaN fails the first test */
+    return (int)v;
+}
+
+static void expand_topk(const double* v, int k, int K, double* m)
+{
+    for (int q = 0; q < K; q++) m[q] = 0.0;
+    for (int q = 0; q < k; q++) {
+        int c = class_index(v[q], K);
+        if (c >= 0) m[c] += v[k + q];
+    }
+}
+
 /* ------------------------------------------------------------------ */
 /* Point clouds                                                         */
 /* ------------------------------------------------------------------ */
@@ -465,7 +485,14 @@ void orc_input_pointcloud(orc_map* m, const float* xyz, int64_t n, const float* 
     int32_t* cell = (int32_t*)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
     float* pm = (float*)malloc(sizeof(float) * 3 * (n > 0 ? n : 1));
     double** chs = (double**)calloc(n_bind > 0 ? n_bind : 1, sizeof(double*));
-    for (int b = 0; b < n_bind; b++) chs[b] = (double*)calloc(HW * bind[3 * b + 2], sizeof(double));
+    int maxc = 1; /* widest binding: its inputs and its layer's channels */
+    for (int b = 0; b < n_bind; b++) {
+        chs[b] = (double*)calloc(HW * m->L[bind[4 * b] - ORC_LAYER_USER0].C, sizeof(double));
+        if (bind[4 * b + 2] > maxc) maxc = bind[4 * b + 2];
+        if (m->L[bind[4 * b] - ORC_LAYER_USER0].C > maxc) maxc = m->L[bind[4 * b] - ORC_LAYER_USER0].C;
+    }
+    double* vin = (double*)malloc(sizeof(double) * maxc); /* one point's bound inputs */
+    double* mi = (double*)malloc(sizeof(double) * maxc);  /* its measurement m_i */
 
     /* Association and per-cell sums. */
     for (int64_t i = 0; i < n; i++) {
@@ -489,8 +516,14 @@ void orc_input_pointcloud(orc_map* m, const float* xyz, int64_t n, const float* 
         z1[j] = zm;
         v1[j] = var;
         for (int b = 0; b < n_bind; b++) {
-            int f = bind[3 * b + 1], cnt = bind[3 * b + 2];
-            for (int q = 0; q < cnt; q++) chs[b][j * cnt + q] += (double)ch[i * c + f + q];
+            int f = bind[4 * b + 1], cnt = bind[4 * b + 2], k = bind[4 * b + 3];
+            int K = m->L[bind[4 * b] - ORC_LAYER_USER0].C;
+            for (int q = 0; q < cnt; q++) vin[q] = (double)ch[i * c + f + q];
+            if (k > 0) /* the K-vector of a top-k measurement */
+                expand_topk(vin, k, K, mi);
+            else
+                for (int q = 0; q < K; q++) mi[q] = vin[q];
+            for (int q = 0; q < K; q++) chs[b][j * K + q] += mi[q];
         }
     }
 
@@ -544,8 +577,8 @@ void orc_input_pointcloud(orc_map* m, const float* xyz, int64_t n, const float* 
 
     /* Extra point fields into their layers (Sec. III-C). */
     for (int b = 0; b < n_bind; b++) {
-        orc_layer* L = &m->L[bind[3 * b] - ORC_LAYER_USER0];
-        int cnt = bind[3 * b + 2];
+        orc_layer* L = &m->L[bind[4 * b] - ORC_LAYER_USER0];
+        int cnt = L->C;
         double* mean = (double*)malloc(sizeof(double) * cnt);
         for (long j = 0; j < HW; j++) {
             int N = m->hits[j];
@@ -561,6 +594,8 @@ void orc_input_pointcloud(orc_map* m, const float* xyz, int64_t n, const float* 
 
     for (int b = 0; b < n_bind; b++) free(chs[b]);
     free(chs);
+    free(vin);
+    free(mi);
     free(Wsum);
     free(Ssum);
     free(z1);
@@ -587,6 +622,13 @@ static double pixel_value(const void* img, int dtype, int64_t off)
     return (double)((const float*)img)[off];
 }
 
+/* A class index read from an image: u8 images carry it as the byte itself. */
+static double pixel_index(const void* img, int dtype, int64_t off)
+{
+    if (dtype == ORC_IMG_U8) return (double)((const unsigned char*)img)[off];
+    return (double)((const float*)img)[off];
+}
+
 void orc_input_image(orc_map* m, const void* img, int dtype, int h, int w, int c,
                      const int64_t strides[3], const float K[4], const float T[12],
                      const int* bind, int n_bind, int32_t* out_pix)
@@ -598,18 +640,25 @@ void orc_input_image(orc_map* m, const void* img, int dtype, int h, int w, int c
      * height, Sec. III-B), then fusion of every visible cell with N_j = 1. */
     orc_cell_pixels(m, h, w, K, T, pix);
     for (int b = 0; b < n_bind; b++) {
-        orc_layer* L = &m->L[bind[3 * b] - ORC_LAYER_USER0];
-        int f = bind[3 * b + 1], cnt = bind[3 * b + 2];
-        double* a = (double*)malloc(sizeof(double) * cnt);
+        orc_layer* L = &m->L[bind[4 * b] - ORC_LAYER_USER0];
+        int f = bind[4 * b + 1], cnt = bind[4 * b + 2], k = bind[4 * b + 3];
+        double* a = (double*)malloc(sizeof(double) * (cnt > L->C ? cnt : L->C));
+        double* v = (double*)malloc(sizeof(double) * (cnt > 0 ? cnt : 1));
         for (long j = 0; j < HW; j++) {
             if (pix[j] < 0) continue;
             int row = pix[j] / w, col = pix[j] % w;
-            for (int q = 0; q < cnt; q++)
-                a[q] = pixel_value(img, dtype,
-                                   row * strides[0] + col * strides[1] + (int64_t)(f + q) * strides[2]);
+            int64_t base = row * strides[0] + col * strides[1];
+            if (k > 0) { /* k indices, then k probabilities */
+                for (int q = 0; q < cnt; q++)
+                    v[q] = (q < k ? pixel_index : pixel_value)(img, dtype, base + (int64_t)(f + q) * strides[2]);
+                expand_topk(v, k, L->C, a);
+            } else {
+                for (int q = 0; q < cnt; q++) a[q] = pixel_value(img, dtype, base + (int64_t)(f + q) * strides[2]);
+            }
             fuse_cell(L, j, 1, a, a);
         }
         free(a);
+        free(v);
     }
     if (out_pix) memcpy(out_pix, pix, sizeof(int32_t) * HW);
     free(pix);

@@ -57,7 +57,11 @@ void orc_get_center(const orc_map* m, int* cx, int* cy);
 /* Relabels the grid without moving content (used to load a saved state). */
 void orc_set_center(orc_map* m, int cx, int cy);
 
-/* bind: n_bind triples (layer, ch_first, ch_count).  out_cells (n int32 or
+/* bind: n_bind quadruples (layer, ch_first, ch_count, topk).  topk = 0: the
+ * ch_count inputs are the layer's channels.  topk = k > 0 (DIRICHLET layers):
+ * the ch_count = 2k inputs are k class indices then their probabilities,
+ * fused as the K-vector with each probability at its class (a class that is
+ * not an integer in [0, K) is ignored; u8 images carry indices as bytes).  out_cells (n int32 or
  * NULL): logical cell iy*W+ix of each point, or -1/-2/-3 (non-finite, out
  * of range, outside the grid). */
 void orc_input_pointcloud(orc_map* m, const float* xyz, int64_t n,

@@ -658,3 +658,115 @@ def test_normals_axes_and_missing_heights():
     ok = ~nan
     assert np.allclose(n[ok][:, 0], 0.0, atol=1e-12)
     assert np.allclose(n[ok][:, 1], -0.5 / math.sqrt(1.25), atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Top-k class input (Sec. III-C): k (class, probability) pairs per point or
+# pixel instead of the K probabilities, fused by the Dirichlet rule as the
+# K-vector with each listed probability at its class.
+# ---------------------------------------------------------------------------
+
+def topk_inputs(rng, n, K, k, invalid=True):
+    """n measurements of k distinct classes with probabilities; some listed
+    indices invalid (negative, >= K, fractional, NaN) when asked."""
+    idx = np.stack([rng.permutation(K)[:k] for _ in range(n)]).astype(np.float32)
+    p = rng.dirichlet(np.ones(K), n)[:, :k].astype(np.float32)
+    if invalid:
+        bad = rng.uniform(size=idx.shape) < 0.1
+        idx[bad] = rng.choice(np.array([-1.0, K, K + 3, 2.5, np.nan], np.float32), bad.sum())
+    return idx, p
+
+
+def brute_alpha(alpha0, cells, idx, p, K):
+    """alpha0 plus, per measurement with a cell >= 0, each probability at its
+    listed class if that class is an integer in [0, K)."""
+    a = alpha0.copy()
+    for j, ids, ps in zip(cells, idx, p):
+        if j < 0:
+            continue
+        for c, q in zip(ids, ps):
+            if np.isfinite(c) and c == int(c) and 0 <= c < K:
+                a[j, int(c)] += float(q)
+    return a
+
+
+def test_topk_points_add_each_listed_probability_to_its_class():
+    rng = np.random.default_rng(40)
+    K, k, W = 7, 3, 6
+    m = O.OracleMap(W, W, 0.5, clear_min_count=0, layers=[(K, O.DIRICHLET, 1.0)])
+    alpha = np.ones((W * W, K))
+    for _ in range(4):
+        n = 400
+        xyz = np.stack([rng.uniform(-1.6, 1.6, n), rng.uniform(-1.6, 1.6, n), np.zeros(n)], 1).astype(np.float32)
+        idx, p = topk_inputs(rng, n, K, k)
+        extra = rng.uniform(size=(n, 2)).astype(np.float32)  # unbound channels around the binding
+        ch = np.concatenate([extra[:, :1], idx, p, extra[:, 1:]], 1)
+        cells = m.point_cells(xyz, ID)
+        alpha = brute_alpha(alpha, cells, idx, p, K)
+        m.input_pointcloud(xyz, ID, ch=ch, bind=[(O.LAYER_USER0, 1, 2 * k, k)])
+    got = m.get_layer(O.LAYER_USER0, O.VIEW_AUX).reshape(-1, K)
+    assert np.allclose(got, alpha, rtol=1e-12, atol=1e-12)
+    assert (got > 1.0).any()
+
+
+def test_topk_listing_every_class_equals_the_dense_input():
+    rng = np.random.default_rng(41)
+    K, W, n = 5, 6, 500
+    dense = O.OracleMap(W, W, 0.5, clear_min_count=0, layers=[(K, O.DIRICHLET, 1.0)])
+    sparse = O.OracleMap(W, W, 0.5, clear_min_count=0, layers=[(K, O.DIRICHLET, 1.0)])
+    xyz = np.stack([rng.uniform(-1.6, 1.6, n), rng.uniform(-1.6, 1.6, n), np.zeros(n)], 1).astype(np.float32)
+    p = rng.dirichlet(np.ones(K), n).astype(np.float32)
+    perm = np.stack([rng.permutation(K) for _ in range(n)])
+    ch = np.concatenate([perm.astype(np.float32), np.take_along_axis(p, perm, 1)], 1)
+    dense.input_pointcloud(xyz, ID, ch=p, bind=[(O.LAYER_USER0, 0, K)])
+    sparse.input_pointcloud(xyz, ID, ch=ch, bind=[(O.LAYER_USER0, 0, 2 * K, K)])
+    a, b = dense.get_layer(O.LAYER_USER0, O.VIEW_AUX), sparse.get_layer(O.LAYER_USER0, O.VIEW_AUX)
+    assert np.allclose(a, b, rtol=1e-12, atol=1e-12)
+
+
+def test_topk_one_hot_counts_observations_per_class():
+    """Top-1 with probability 1: alpha - alpha0 counts each class's points
+    per cell exactly (integers)."""
+    rng = np.random.default_rng(42)
+    K, W, n = 4, 6, 600
+    m = O.OracleMap(W, W, 0.5, clear_min_count=0, layers=[(K, O.DIRICHLET, 0.5)])
+    xyz = np.stack([rng.uniform(-1.6, 1.6, n), rng.uniform(-1.6, 1.6, n), np.zeros(n)], 1).astype(np.float32)
+    cls = rng.integers(0, K, n)
+    m.input_pointcloud(xyz, ID, ch=np.stack([cls, np.ones(n)], 1).astype(np.float32), bind=[(O.LAYER_USER0, 0, 2, 1)])
+    cells = m.point_cells(xyz, ID)
+    want = np.full((W * W, K), 0.5)
+    np.add.at(want, (cells[cells >= 0], cls[cells >= 0]), 1.0)
+    assert np.array_equal(m.get_layer(O.LAYER_USER0, O.VIEW_AUX).reshape(-1, K), want)
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_topk_image_pixels_fuse_their_listed_classes(dtype):
+    """A top-2 class image seen from above: every visible cell adds its
+    pixel's probabilities at its pixel's classes; u8 images carry the class
+    as the byte and the probability as byte / 255."""
+    W = H = 16
+    K, k = 6, 2
+    m = O.OracleMap(W, H, 0.25, layers=[(K, O.DIRICHLET, 1.0)])
+    m.set_layer(O.LAYER_ELEVATION, O.VIEW_VALUE, np.zeros((H, W)))
+    m.set_layer(O.LAYER_VARIANCE, O.VIEW_VALUE, np.ones((H, W)))
+    rng = np.random.default_rng(43)
+    idx = rng.integers(0, K + 2, (64, 64, k))  # classes K, K+1 are invalid
+    if dtype == "u8":
+        img = np.concatenate([idx, rng.integers(0, 256, (64, 64, k))], -1).astype(np.uint8)
+        probs = img[..., k:] / 255.0
+    else:
+        img = np.concatenate([idx, rng.uniform(0, 0.5, (64, 64, k))], -1).astype(np.float32)
+        img[5, 7, 0] = 1.5  # fractional class: ignored
+        probs = img[..., k:].astype(np.float64)
+    T = down_camera((0.0, 0.0, 4.0))
+    pix = m.input_image(img, (64.0, 64.0, 31.5, 31.5), T, bind=[(O.LAYER_USER0, 0, 2 * k, k)])
+    got = m.get_layer(O.LAYER_USER0, O.VIEW_AUX)
+    for iy in range(H):
+        for ix in range(W):
+            r, c = divmod(int(pix[iy, ix]), 64)
+            want = np.ones(K)
+            for q in range(k):
+                v = float(img[r, c, q])
+                if v == int(v) and 0 <= v < K:
+                    want[int(v)] += probs[r, c, q]
+            assert np.allclose(got[iy, ix], want, rtol=0, atol=1e-15), (ix, iy)
