@@ -424,9 +424,23 @@ __global__ __launch_bounds__(kBatchWG) void k_b_gather(BatchDev d, int queue,
 
 }  // namespace
 
-size_t batch_tile_ingest_lds_bytes(int tile_h)
+// Dynamic LDS of k_b_tile_ingest: per-cell sums of a kIngestTileW x tile_h tile.
+static size_t tile_ingest_dyn_lds(int tile_h)
 {
     return (size_t)kIngestTileW * tile_h * (sizeof(int) + 2 * sizeof(float) + sizeof(float2));
+}
+
+// All LDS of a k_b_tile_ingest workgroup: the kernel's static variables as
+// the compiler laid them out plus the dynamic per-cell sums.
+size_t batch_tile_ingest_lds_bytes(int tile_h)
+{
+    static const size_t fixed = [] {
+        hipFuncAttributes a{};
+        const bool ok = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_b_tile_ingest)) == hipSuccess;
+        (void)hipGetLastError();
+        return ok ? (size_t)a.sharedSizeBytes : (size_t)1024;
+    }();
+    return fixed + tile_ingest_dyn_lds(tile_h);
 }
 
 void launch_batch_step(hipStream_t s, const BatchDev& d, const BatchLaunch& bl, const float* xyz,
@@ -443,7 +457,7 @@ void launch_batch_step(hipStream_t s, const BatchDev& d, const BatchLaunch& bl, 
     int64_t zb = (d.total_cells + 255) / 256;
     if (zb > 8192) zb = 8192;
     hipLaunchKernelGGL(k_b_bin, dim3(bl.grid), dim3(kBatchWG), 0, s, d, xyz, c0, c1, mr2);
-    hipLaunchKernelGGL(k_b_tile_ingest, dim3(bl.grid), dim3(kBatchWG), batch_tile_ingest_lds_bytes(d.itile_h), s,
+    hipLaunchKernelGGL(k_b_tile_ingest, dim3(bl.grid), dim3(kBatchWG), tile_ingest_dyn_lds(d.itile_h), s,
                        d);
     if (clear_min > 0) {
         int64_t lb = (d.total_cells + kLogicalRange - 1) / kLogicalRange;

@@ -286,9 +286,19 @@ inline unsigned blocks_for(int64_t n, int per)
 
 }  // namespace
 
+// LDS of a k_ingest workgroup that reduces Cb channel planes in LDS: the
+// kernel's static arrays as the compiler laid them out (the hash table and
+// the per-block statistics) plus the dynamic channel sums; more than any
+// device offers when Cb exceeds kMaxLdsCh.
 size_t ingest_lds_bytes(int Cb)
 {
-    return kStaticLds + (Cb > kMaxLdsCh ? (size_t)1 << 30 : sizeof(float) * kSlots * Cb);
+    static const size_t fixed = [] {
+        hipFuncAttributes a{};
+        const bool ok = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_ingest)) == hipSuccess;
+        (void)hipGetLastError();
+        return ok && a.sharedSizeBytes >= kStaticLds ? (size_t)a.sharedSizeBytes : kStaticLds + 1024;
+    }();
+    return fixed + (Cb > kMaxLdsCh ? (size_t)1 << 30 : sizeof(float) * kSlots * Cb);
 }
 
 void launch_zero_accum(hipStream_t s, const Grid& g, int* n, float* wsum, float* ssum, int* clr,

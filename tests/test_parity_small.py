@@ -317,3 +317,21 @@ def test_invalid_arguments_leave_the_map_untouched():
     assert np.isnan(gpu_layer(g, 0)).all()
     g.input_pointcloud(xyz, ID)  # the map still works
     assert gpu_layer(g, 3)[5, 5] == 10
+
+
+@pytest.mark.parametrize("planes", [13, 14, 16, 17])
+def test_point_channels_around_the_lds_limit(planes):
+    """Bound channel planes around the most the ingest reduces in LDS (the
+    hash table, the block statistics and planes x 2048 sums must fit one
+    workgroup's LDS; beyond that the sums go to global atomics)."""
+    rng = np.random.default_rng(planes)
+    layers = [(planes - 4, mem.MEM_LATEST, 0.0), (4, mem.MEM_DIRICHLET, 1.0)]
+    g, o = make_pair(30, 30, 0.05, layers=layers, clear_min_count=0)
+    n = 5000
+    xyz = np.stack([rng.uniform(-0.8, 0.8, n), rng.uniform(-0.8, 0.8, n), rng.normal(0, 0.05, n)], 1).astype(np.float32)
+    ch = rng.uniform(0, 1, (n, planes)).astype(np.float32)
+    bind = [(8, 0, planes - 4), (9, planes - 4, 4)]
+    sync_from_oracle(g, o)
+    g.input_pointcloud(to_dev(xyz), ID, ch=to_dev(ch), bind=bind)
+    o.input_pointcloud(xyz, ID, ch=ch, bind=bind)
+    compare(g, o, what=f"{planes} planes")
