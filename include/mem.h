@@ -124,12 +124,22 @@ typedef struct mem_params {
 } mem_params;
 
 /* Binds input channels [ch_first, ch_first + ch_count) of a point cloud or an
- * image to a user layer with exactly ch_count channels (Sec. III-C: the user
- * chooses the target layer of every input source). */
+ * image to a user layer (Sec. III-C: the user chooses the target layer of
+ * every input source).
+ *   topk = 0: the ch_count inputs are the layer's channels (ch_count = C).
+ *   topk = k in 1..min(K, 64), DIRICHLET layers of K classes only (the top-k
+ *     class input of Sec. III-C): the ch_count = 2k inputs are k class
+ *     indices followed by their k probabilities.  The measurement fused by
+ *     Eq. (12) is the K-vector holding each listed probability at its class
+ *     and zero elsewhere (a class listed twice adds both).  A listed index
+ *     that is not an integer in [0, K) (or is NaN) contributes nothing.
+ *     u8 images carry the index as the byte itself, the probability as
+ *     byte / 255.  Batches (mem_batch_create) accept only topk = 0. */
 typedef struct mem_binding {
     int32_t layer;    /* MEM_LAYER_USER0 + k */
     int32_t ch_first;
     int32_t ch_count;
+    int32_t topk;     /* 0: dense channels; k > 0: top-k class pairs */
 } mem_binding;
 
 /* Counters accumulated by the device since the last mem_reset_stats. */

@@ -462,6 +462,7 @@ mem_status mem_batch_create(const mem_batch_params* p, void* stream, mem_batch**
             return api_fail(MEM_E_ARG, "n_img_bind must be 0..4 with a binding array");
         for (int k = 0; k < p->n_img_bind; k++) {
             const mem_binding& bd = p->img_bind[k];
+            if (bd.topk != 0) return api_fail(MEM_E_UNSUPPORTED, "image binding %d: batches take dense class inputs only", k);
             const int l = bd.layer - MEM_LAYER_USER0;
             if (l < 0 || l >= p->n_layers || bd.ch_first < 0 || bd.ch_count != p->layers[l].channels ||
                 bd.ch_first + bd.ch_count > p->cam_c)

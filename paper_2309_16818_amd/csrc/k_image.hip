@@ -13,7 +13,8 @@
 //                  the image a group of lanes (a power of two >= the layer's
 //                  channels, at most 64) reads the pixel's channels and
 //                  read-modify-writes the cell's channel-contiguous layer row
-//                  with the layer's rule.
+//                  with the layer's rule; a top-k class input takes one lane
+//                  per cell, which adds each listed probability to its class.
 #include "update.h"
 
 namespace memk {
@@ -156,7 +157,7 @@ __global__ __launch_bounds__(256) void k_gather_fuse(const int4* __restrict__ vl
                                                      const int* __restrict__ count,
                                                      const void* __restrict__ img, int64_t s0,
                                                      int64_t s1, int64_t s2, int w, int ch_first,
-                                                     LayerDev L, int lpp_log2)
+                                                     LayerDev L, int lpp_log2, int topk)
 {
     const int N = *count;
     const int lane = threadIdx.x & 63;
@@ -169,7 +170,11 @@ __global__ __launch_bounds__(256) void k_gather_fuse(const int4* __restrict__ vl
     for (int64_t pbase = wave * ppw; pbase < N; pbase += nwaves * ppw) {
         const int64_t p = pbase + sub;
         const int code = p < N ? vcode[p] : -1;
-        if (code >= 0) gather_pair<IMG, S>(make_int2(vlist[p].x, code), img, s0, s1, s2, w, ch_first, L, q0, LPP);
+        if (code < 0) continue;
+        if (topk > 0)  // one lane per pair (lpp_log2 = 0)
+            gather_topk<IMG>(make_int2(vlist[p].x, code), img, s0, s1, s2, w, ch_first, L, topk);
+        else
+            gather_pair<IMG, S>(make_int2(vlist[p].x, code), img, s0, s1, s2, w, ch_first, L, q0, LPP);
     }
 }
 
@@ -202,10 +207,10 @@ void launch_project(hipStream_t s, const Grid& g, const Camera& cam, const float
 
 void launch_gather_fuse(hipStream_t s, const int4* vlist, const int* vcode, const int* count, int max_pairs,
                         const void* img, int img_dtype, int64_t s0, int64_t s1, int64_t s2, int w,
-                        int ch_first, const LayerDev& L)
+                        int ch_first, const LayerDev& L, int topk)
 {
     int lpp_log2 = 0;
-    while ((1 << lpp_log2) < L.C && lpp_log2 < 6) lpp_log2++;
+    while (topk == 0 && (1 << lpp_log2) < L.C && lpp_log2 < 6) lpp_log2++;
     int ppw = 64 >> lpp_log2;
     int64_t waves = ((int64_t)max_pairs + ppw - 1) / ppw;
     int64_t blocks = (waves + 3) / 4;
@@ -214,7 +219,7 @@ void launch_gather_fuse(hipStream_t s, const int4* vlist, const int* vcode, cons
     dim3 gr((unsigned)blocks), bl(256);
 #define MEM_GF(IMG, S) \
     hipLaunchKernelGGL((k_gather_fuse<IMG, S>), gr, bl, 0, s, vlist, vcode, count, img, s0, s1, s2, w, ch_first, \
-                       L, lpp_log2)
+                       L, lpp_log2, topk)
     if (img_dtype == MEM_U8) {
         if (L.storage == MEM_BF16) MEM_GF(MEM_U8, MEM_BF16);
         else if (L.storage == MEM_FP8_E4M3) MEM_GF(MEM_U8, MEM_FP8_E4M3);

@@ -446,6 +446,27 @@ mem_status mem_move(mem_map* m, float x, float y, void* stream)
     return check_launch(m, "mem_move");
 }
 
+// A binding's inputs fit `c` channels and match its layer: C dense channels,
+// or 2k inputs (k class indices, then their probabilities) for a top-k class
+// input into a Dirichlet layer of K >= k classes.
+static mem_status check_binding(const mem_binding& bd, const Layer* L, int c, const char* what)
+{
+    if (bd.topk < 0 || bd.topk > kMaxTopk) return fail(MEM_E_ARG, "%s: topk must be 0..%d", what, kMaxTopk);
+    if (bd.topk > 0) {
+        if (L->rule != MEM_DIRICHLET) return fail(MEM_E_ARG, "%s: a top-k class input needs a Dirichlet layer", what);
+        if (bd.topk > L->C) return fail(MEM_E_ARG, "%s: topk %d exceeds the layer's %d classes", what, bd.topk, L->C);
+        if (bd.ch_count != 2 * bd.topk)
+            return fail(MEM_E_ARG, "%s: a top-%d class input reads %d channels, not %d", what, bd.topk, 2 * bd.topk,
+                        bd.ch_count);
+    } else if (bd.ch_count != L->C) {
+        return fail(MEM_E_ARG, "%s: %d channels for a layer of %d", what, bd.ch_count, L->C);
+    }
+    if (bd.ch_first < 0 || (int64_t)bd.ch_first + bd.ch_count > c)
+        return fail(MEM_E_ARG, "%s: channels [%d, %lld) do not fit %d inputs", what, bd.ch_first,
+                    (long long)bd.ch_first + bd.ch_count, c);
+    return MEM_OK;
+}
+
 mem_status mem_input_pointcloud(mem_map* m, const float* xyz, int64_t n, const float* ch, int32_t c,
                                 const mem_binding* bind, int32_t n_bind, const float T_map_sensor[12],
                                 void* stream)
@@ -463,11 +484,12 @@ mem_status mem_input_pointcloud(mem_map* m, const float* xyz, int64_t n, const f
     for (int b = 0; b < n_bind; b++) {
         const Layer* L = nullptr;
         if (mem_status st = resolve_layer(m, bind[b].layer, &L)) return st;
-        if (bind[b].ch_first < 0 || bind[b].ch_count != L->C || bind[b].ch_first + bind[b].ch_count > c)
-            return fail(MEM_E_ARG, "binding %d: channels [%d, %d) do not fit %d inputs / layer of %d",
-                        b, bind[b].ch_first, bind[b].ch_first + bind[b].ch_count, c, L->C);
+        char what[32];
+        snprintf(what, sizeof what, "binding %d", b);
+        if (mem_status st = check_binding(bind[b], L, c, what)) return st;
         pb.b[b].layer = bind[b].layer - MEM_LAYER_USER0;
         pb.b[b].ch_first = bind[b].ch_first;
+        pb.b[b].topk = bind[b].topk;
         pb.b[b].C = L->C;
         pb.b[b].sum_off = pb.Cb;
         pb.L[b] = L->dev();
@@ -540,8 +562,9 @@ static mem_status check_image(const mem_map* m, const mem_image& im, int k, Came
     for (int b = 0; b < im.n_bind; b++) {
         const Layer* L = nullptr;
         if (mem_status st = resolve_layer(m, im.bind[b].layer, &L)) return st;
-        if (im.bind[b].ch_first < 0 || im.bind[b].ch_count != L->C || im.bind[b].ch_first + im.bind[b].ch_count > im.c)
-            return fail(MEM_E_ARG, "image %d binding %d does not fit the image / layer", k, b);
+        char what[48];
+        snprintf(what, sizeof what, "image %d binding %d", k, b);
+        if (mem_status st = check_binding(im.bind[b], L, im.c, what)) return st;
     }
     return MEM_OK;
 }
@@ -578,7 +601,7 @@ mem_status mem_input_images(mem_map* m, const mem_image* images, int32_t n_image
             timed(m, s, "gather_fuse", [&] {
                 launch_gather_fuse(s, m->vlist, m->vcode + (int64_t)k * cap, vc, cap, im.data,
                                    im.dtype, im.strides[0], im.strides[1], im.strides[2], im.w,
-                                   im.bind[b].ch_first, d);
+                                   im.bind[b].ch_first, d, im.bind[b].topk);
             });
         }
     }

@@ -28,6 +28,7 @@
 namespace memk {
 
 constexpr int kMaxBind = 8;
+constexpr int kMaxTopk = 64;  // classes listed per top-k class input
 constexpr int kStats = 13;  // device counters, order of mem_stats
 // Device counters are [kStats][kStatSlots]: a workgroup adds into slot
 // (block id mod kStatSlots), so no single address sees more than
@@ -83,8 +84,9 @@ struct LayerDev {
 struct PointBind {
     int layer;     // index into layers
     int ch_first;  // input channel
-    int C;
+    int C;         // the layer's channels (planes of chsum)
     int sum_off;   // first plane of this binding in chsum
+    int topk;      // 0: C dense inputs; k > 0: k class indices, then k probabilities
 };
 
 struct PointBinds {
@@ -151,9 +153,11 @@ void launch_project(hipStream_t s, const Grid& g, const Camera& cam, const float
                     unsigned long long* stats);
 // Fuses image channels into layer L for the listed cells whose code (image's
 // row of vcode) is >= 0.
+// topk > 0: the binding's inputs are topk class indices then their
+// probabilities (Dirichlet layers), fused by one lane per visible pair.
 void launch_gather_fuse(hipStream_t s, const int4* vlist, const int* vcode, const int* count, int max_pairs,
                         const void* img, int img_dtype, int64_t s0, int64_t s1, int64_t s2, int w,
-                        int ch_first, const LayerDev& L);
+                        int ch_first, const LayerDev& L, int topk = 0);
 
 // ---- batches of maps ----
 
@@ -221,7 +225,8 @@ void launch_batch_step(hipStream_t s, const BatchDev& d, const BatchLaunch& bl, 
                        float c0, float c1, float mr2, float margin, int clear_min,
                        const LayerDev* L, int nL, const void* images, int img_dtype, int cam_c,
                        int cam_w, const mem_binding* ib, int n_ib);
-// LDS of the tile-owned ingest for tiles of kIngestTileW x tile_h cells.
+// All LDS (static and dynamic) a tile-owned ingest workgroup needs for tiles
+// of kIngestTileW x tile_h cells.
 size_t batch_tile_ingest_lds_bytes(int tile_h);
 constexpr int kBinTiles = 4096;  // ingest tiles a binning pass histograms at once
 

@@ -44,6 +44,13 @@ struct PointCounts {
 // global atomic per (cell, field).  A thread loads all its points before
 // hashing any, so their loads overlap.  Every thread of the workgroup must
 // call it; it starts and ends with a workgroup barrier.
+// Class of a listed top-k index v among K classes, or -1 when v is not an
+// integer in [0, K) (NaN included).
+__device__ __forceinline__ int class_index(float v, int K)
+{
+    return (v >= 0.0f && v < (float)K && v == floorf(v)) ? (int)v : -1;
+}
+
 template <int P>
 __device__ __forceinline__ void ingest_range(const Grid& g, const float* __restrict__ xyz,
                                              int64_t begin, int64_t end,
@@ -109,12 +116,18 @@ __device__ __forceinline__ void ingest_range(const Grid& g, const float* __restr
         atomicAdd(&lds.s[slot], pz * w);
         for (int b = 0; b < pb.n; b++) {
             const float* src = ch + i * pb.c_in + pb.b[b].ch_first;
-            for (int q = 0; q < pb.b[b].C; q++) {
-                const int plane = pb.b[b].sum_off + q;
+            const int k = pb.b[b].topk;
+            // dense: channel q into plane q; top-k: the q-th listed
+            // probability into its class's plane
+            for (int q = 0; q < (k > 0 ? k : pb.b[b].C); q++) {
+                const int c = k > 0 ? class_index(src[q], pb.b[b].C) : q;
+                if (c < 0) continue;
+                const float val = src[k > 0 ? k + q : q];
+                const int plane = pb.b[b].sum_off + c;
                 if (lds_ch)
-                    atomicAdd(&lds.ch[plane * slots + slot], src[q]);
+                    atomicAdd(&lds.ch[plane * slots + slot], val);
                 else
-                    unsafeAtomicAdd(&acc.chsum[(int64_t)plane * acc.HW + st], src[q]);
+                    unsafeAtomicAdd(&acc.chsum[(int64_t)plane * acc.HW + st], val);
             }
         }
     }
@@ -401,6 +414,32 @@ __device__ __forceinline__ float pixel_value(const void* img, int64_t off)
 {
     if (IMG == MEM_U8) return (float)((const uint8_t*)img)[off] / 255.0f;
     return ((const float*)img)[off];
+}
+
+// A class index as an input carries it: u8 images the byte itself.
+template <int IMG>
+__device__ __forceinline__ float pixel_index(const void* img, int64_t off)
+{
+    if (IMG == MEM_U8) return (float)((const uint8_t*)img)[off];
+    return ((const float*)img)[off];
+}
+
+// Top-k class input of one visible pair (Eq. (12) with the K-vector that
+// holds each listed probability at its class): one lane adds the k
+// probabilities to the cell's concentrations in list order, so a class
+// listed twice adds twice.  Dirichlet layers are binary32.
+template <int IMG>
+__device__ __forceinline__ void gather_topk(int2 pr, const void* __restrict__ img, int64_t s0, int64_t s1,
+                                            int64_t s2, int w, int ch_first, const LayerDev& L, int k)
+{
+    const int st = pr.x;
+    const int row = pr.y / w, col = pr.y - (pr.y / w) * w;
+    const int64_t pix = (int64_t)row * s0 + (int64_t)col * s1 + (int64_t)ch_first * s2;
+    float* alpha = (float*)L.val + (int64_t)st * L.C;
+    for (int q = 0; q < k; q++) {
+        const int c = class_index(pixel_index<IMG>(img, pix + (int64_t)q * s2), L.C);
+        if (c >= 0) alpha[c] += pixel_value<IMG>(img, pix + (int64_t)(k + q) * s2);
+    }
 }
 
 // Fuses channels q0, q0 + LPP, ... of one visible pair's pixel into layer L

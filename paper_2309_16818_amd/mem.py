@@ -48,7 +48,7 @@ class mem_params(C.Structure):
 
 
 class mem_binding(C.Structure):
-    _fields_ = [("layer", C.c_int32), ("ch_first", C.c_int32), ("ch_count", C.c_int32)]
+    _fields_ = [("layer", C.c_int32), ("ch_first", C.c_int32), ("ch_count", C.c_int32), ("topk", C.c_int32)]
 
 
 class mem_image(C.Structure):
@@ -134,10 +134,12 @@ def _pose(T):
 
 
 def _bindings(bind):
+    """Bindings (layer, ch_first, ch_count[, topk]) as a mem_binding array."""
     bind = list(bind or [])
     arr = (mem_binding * max(1, len(bind)))()
-    for i, (layer, f, cnt) in enumerate(bind):
-        arr[i] = mem_binding(int(layer), int(f), int(cnt))
+    for i, b in enumerate(bind):
+        layer, f, cnt = b[:3]
+        arr[i] = mem_binding(int(layer), int(f), int(cnt), int(b[3]) if len(b) > 3 else 0)
     return arr, len(bind)
 
 

@@ -36,7 +36,7 @@ def test_struct_layouts_match_the_header():
     assert mem.mem_layer_desc.ch_scale.offset == 16
     assert C.sizeof(mem.mem_params) == 48
     assert mem.mem_params.layers.offset == 40
-    assert C.sizeof(mem.mem_binding) == 12
+    assert C.sizeof(mem.mem_binding) == 16 and mem.mem_binding.topk.offset == 12
     assert C.sizeof(mem.mem_stats) == 8 * len(mem.STAT_FIELDS)
     assert C.sizeof(mem.mem_kernel_time) == 48
     assert C.sizeof(mem.mem_image) == 80
