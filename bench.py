@@ -83,10 +83,11 @@ def parse():
     ap.add_argument("--frames-cache", default=None,
                     help="full: .npz of generated frames to load (written first if missing)")
     ap.add_argument("--precision-frames", type=int, default=8,
-                    help="precision: frames run by every storage type and by the binary64 oracle")
-    ap.add_argument("--workload", choices=["full", "batch", "learned", "copy", "precision"], default="full",
+                    help="precision, layers: frames run by every configuration (precision: also by the binary64 oracle)")
+    ap.add_argument("--workload", choices=["full", "batch", "learned", "copy", "precision", "layers"], default="full",
                     help="full: one robot at full rate; batch: 1024 uneven maps per step; "
-                         "learned: the completion network's training and inference at 256x256")
+                         "learned: the completion network's training and inference at 256x256; "
+                         "precision: reduced-precision feature storage; layers: 1-20 multi-modal layers")
     ap.add_argument("--pairs", type=int, default=288, help="learned: generated (input, target) windows")
     ap.add_argument("--train-steps", type=int, default=1500,
                     help="learned: total training steps before the quality evaluation")
@@ -432,6 +433,80 @@ def run_precision(args):
     print(json.dumps(out), flush=True)
 
 
+def run_layers(args):
+    """Scalability in the number of multi-modal layers (the layer sweep of
+    the paper's time-performance figure): the full-rate frames with L
+    three-channel layers, each fed every camera's RGB image, under
+    exponential averaging and under Gaussian (Bayesian) fusion.  Reports the
+    frame time and the image fusion's gather time per frame for every L and
+    a least-squares line through them."""
+    import torch
+    from paper_2309_16818_amd import mem, synth
+    torch.cuda.set_device(0)
+    n = args.precision_frames
+    t0 = time.time()
+    frames = [f for _, f in synth.iter_full_frames(seed=args.seed, n_frames=n, device="cuda")]
+    print(f"# generated {n} frames in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    dframes = upload(frames)
+    p = dict(synth.FULL_MAP)
+    W, H, res = p.pop("width"), p.pop("height"), p.pop("resolution")
+    counts = (1, 2, 4, 8, 12, 16, 20)
+
+    def frame(m, f, L):
+        x, y, _ = f["pose"]
+        m.move(x, y)
+        for c in f["clouds"]:
+            m.input_pointcloud(c["xyz"], c["T"])
+        binds = [(8 + l, 0, 3) for l in range(L)]
+        for c in f["cameras"]:  # up to 8 bindings per image entry, one pose
+            m.input_images([(c["rgb"], c["K"], binds[i:i + 8]) for i in range(0, L, 8)], c["T"])
+
+    def run(rule, param, L):
+        make = lambda: mem.Map(mem.MapParams(W, H, res, layers=[mem.Layer(3, rule, param)] * L, **p))
+        mp = make()  # per-launch events on a twin map, outside the timed frames
+        mp.profile_enable(True)
+        mp.profile_read()
+        for f in dframes:
+            frame(mp, f, L)
+        kern = mp.profile_read()
+        mp.close()
+        m = make()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+        for k, f in enumerate(dframes):
+            ev[k][0].record()
+            frame(m, f, L)
+            ev[k][1].record()
+        torch.cuda.synchronize()
+        m.close()
+        lat = np.array([a.elapsed_time(b) for a, b in ev])[1:]  # first frame: empty map
+        return round(float(lat.mean()), 4), round(kern.get("gather_fuse", (0, 0.0))[1] / n, 4)
+
+    sweep = {}
+    for name, rule, param in (("expavg", mem.MEM_EXPAVG, 0.5), ("gauss", mem.MEM_GAUSS, 1.0)):
+        rows = {L: run(rule, param, L) for L in counts}
+        x = np.array(counts, np.float64)
+        fit = {}
+        for q, key in ((0, "frame"), (1, "fusion")):
+            y = np.array([rows[L][q] for L in counts])
+            slope, icpt = np.polyfit(x, y, 1)
+            r2 = 1 - ((y - (slope * x + icpt)) ** 2).sum() / max(((y - y.mean()) ** 2).sum(), 1e-30)
+            fit[key] = dict(ms_per_layer=round(float(slope), 5), ms_at_zero=round(float(icpt), 4), r2=round(float(r2), 4))
+        sweep[name] = dict(ms_per_frame={L: rows[L][0] for L in counts},
+                           fusion_ms_per_frame={L: rows[L][1] for L in counts}, fit=fit)
+        print(f"# {name}: {sweep[name]}", file=sys.stderr, flush=True)
+    ms20 = sweep["expavg"]["ms_per_frame"][20]
+    out = {
+        "metric": "frame time with 20 multi-modal layers", "value": ms20, "unit": "ms", "n_gpus": 1,
+        "steps": n - 1, "warmup": 1, "ms_per_step": ms20, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "layer sweep: full-rate single robot (500x500 at 0.04 m, 5 clouds and 4 cameras "
+                               "per frame) with L = 1-20 three-channel layers each fed every RGB image, "
+                               "exponential averaging and Gaussian fusion", "frames": n},
+        "sweep": sweep,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_copy(args):
     """A plain device copy of 256 MiB (torch's copy kernel): the reference
     for scaling rocprof's FETCH_SIZE / WRITE_SIZE counters to bytes."""
@@ -558,6 +633,38 @@ def time_normals(m, torch, reps=50):
                 defined=int(torch.isfinite(out[..., 2]).sum().item()))
 
 
+def time_topk(m, frame, torch, k=3, reps=20):
+    """Class-image fusion of the last frame's first camera into the final
+    map, the dense 640x480x20 probabilities against their top-k reduction
+    (k indices, then k probabilities): average k_gather_fuse launch from
+    per-launch HIP events and its algorithmic GB/s (dense: 20 probabilities
+    read and 20 concentrations read and written per visible pair; top-k: 2k
+    values read and k concentrations read and written; both 8 B of list)."""
+    c = frame["cameras"][0]
+    probs = c["classes"]
+    K = probs.shape[-1]
+    p, idx = torch.topk(probs, k, dim=-1)
+    top = torch.cat([idx.float(), p], -1).contiguous()
+    out = {}
+    for name, img, bind, per_pair in (("dense", probs, [(10, 0, K)], 4 * K + 8 * K + 8),
+                                      (f"top{k}", top, [(10, 0, 2 * k, k)], 8 * k + 8 * k + 8)):
+        m.input_images([(img, c["K"], bind)], c["T"])
+        torch.cuda.synchronize()
+        m.reset_stats()
+        m.profile_enable(True)
+        m.profile_read()
+        for _ in range(reps):
+            m.input_images([(img, c["K"], bind)], c["T"])
+        kern = m.profile_read()
+        m.profile_enable(False)
+        pairs = m.stats()["pairs_visible"] / reps
+        launches, ms = kern["gather_fuse"]
+        us = 1e3 * ms / launches
+        out[name] = dict(gather_us=round(us, 3), pairs=int(pairs), input_bytes_per_pixel=4 * img.shape[-1],
+                         alg_gbs=round(per_pair * pairs / (us * 1e-6) / 1e9, 1))
+    return out
+
+
 def time_normals_large(torch, side=4096):
     """Surface normals of a side x side map of seeded random heights (5%
     holes), where the launch streams 16 B per cell rather than waiting on
@@ -587,6 +694,8 @@ def main():
         return run_copy(args)
     if args.workload == "precision":
         return run_precision(args)
+    if args.workload == "layers":
+        return run_layers(args)
     import torch
     from paper_2309_16818_amd import mem
 
@@ -615,7 +724,8 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st = m.stats()
-    post = {"normals": time_normals(m, torch), "normals_4096": time_normals_large(torch)}
+    post = {"normals": time_normals(m, torch), "normals_4096": time_normals_large(torch),
+            "class_image": time_topk(m, dframes[-1], torch)}
     m.close()
     lat = np.array([a.elapsed_time(b) for a, b in ev])
     wall_ms = (t1 - t0) * 1e3 / args.steps
