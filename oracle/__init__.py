@@ -47,6 +47,8 @@ def lib() -> C.CDLL:
         L.orc_layer_channels.argtypes = [P, I]
         L.orc_layer_channels.restype = I
         L.orc_normals.argtypes = [P, P]
+        L.orc_set_drift.argtypes = [P, I, C.c_float, I]
+        L.orc_drift_last.argtypes = [P, C.POINTER(C.c_double), C.POINTER(I)]
         L.orc_bresenham.argtypes = [I, I, I, I, P, P, I]
         L.orc_bresenham.restype = I
         _lib = L
@@ -177,6 +179,16 @@ class OracleMap:
         if r != 0:
             raise ValueError(f"oracle: no view {view} of layer {layer}")
         return out.reshape(self.H, self.W, C_) if C_ > 1 or layer >= LAYER_USER0 else out.reshape(self.H, self.W)
+
+    def set_drift(self, on=True, kappa=3.0, min_points=100):
+        """Drift compensation of later point clouds (see orc_set_drift)."""
+        lib().orc_set_drift(self._m, 1 if on else 0, float(kappa), int(min_points))
+
+    def drift_last(self):
+        """(offset applied by the last cloud, its consistent points)."""
+        d, n = C.c_double(), C.c_int()
+        lib().orc_drift_last(self._m, C.byref(d), C.byref(n))
+        return d.value, n.value
 
     def normals(self):
         """[H, W, 3] unit surface normals from the heights: central

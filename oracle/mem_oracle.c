@@ -50,6 +50,12 @@ struct orc_map {
     int32_t* clear;
     int nL;
     orc_layer* L;
+    /* drift compensation (off unless set): consistency bound kappa, the
+     * consistent points it needs, and what the last cloud found */
+    int drift_on, drift_min_points;
+    float drift_kappa;
+    double drift_offset;
+    int drift_count;
 };
 
 /* ------------------------------------------------------------------ */
@@ -527,7 +533,48 @@ void orc_input_pointcloud(orc_map* m, const float* xyz, int64_t n, const float* 
         }
     }
 
-    /* Ray cast against the heights held before this call. */
+    /* z-error count and drift compensation (Table I, rows 1-2; the paper
+     * defers their definition).  A point whose cell holds a height is
+     * consistent with the map when its height error e = z - h satisfies
+     * e^2 <= kappa^2 (v + v_i), both variances those of Eq. (6)-(7)'s
+     * Gaussian model, decided in binary32 like every association.  The
+     * common offset of the consistent errors, their precision-weighted
+     * mean (the maximum-likelihood offset of Gaussian errors), summed in
+     * binary64 and rounded to binary32, shifts every held height before the
+     * height update and the ray cast when at least drift_min_points points
+     * are consistent; the shifted heights are binary32 sums. */
+    m->drift_offset = 0.0;
+    m->drift_count = 0;
+    if (m->drift_on) {
+        const float kappa2 = m->drift_kappa * m->drift_kappa;
+        double sw = 0.0, swe = 0.0;
+        int cnt = 0;
+        for (int64_t i = 0; i < n; i++) {
+            if (cell[i] < 0 || !m->valid[cell[i]]) continue;
+            const long j = cell[i];
+            float x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
+            float r2 = x * x + y * y; /* the binary32 range of point_cell */
+            r2 = r2 + z * z;
+            const float sig = (float)m->c0 + (float)m->c1 * r2;
+            const float vi = sig * sig;
+            const float e = pm[3 * i + 2] - (float)m->h[j];
+            const float tot = (float)m->v[j] + vi;
+            if (!(e * e <= kappa2 * tot)) continue;
+            sw += 1.0 / (double)tot;
+            swe += (double)e / (double)tot;
+            cnt++;
+        }
+        m->drift_count = cnt;
+        if (cnt >= m->drift_min_points && cnt > 0) {
+            const float d = (float)(swe / sw);
+            m->drift_offset = d;
+            for (long j = 0; j < HW; j++)
+                if (m->valid[j]) m->h[j] = (double)((float)m->h[j] + d);
+        }
+    }
+
+    /* Ray cast against the heights held before this call (after the drift
+     * shift when one applies). */
     if (m->clear_min_count > 0) {
         int ax, ay;
         lattice_cell(m, T[3], T[7], &ax, &ay);
@@ -800,4 +847,17 @@ void orc_normals(const orc_map* m, double* out)
             o[1] = -gy / n;
             o[2] = 1.0 / n;
         }
+}
+
+void orc_set_drift(orc_map* m, int on, float kappa, int min_points)
+{
+    m->drift_on = on;
+    m->drift_kappa = kappa;
+    m->drift_min_points = min_points;
+}
+
+void orc_drift_last(const orc_map* m, double* offset, int* count)
+{
+    *offset = m->drift_offset;
+    *count = m->drift_count;
 }

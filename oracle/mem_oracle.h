@@ -68,6 +68,15 @@ void orc_input_pointcloud(orc_map* m, const float* xyz, int64_t n,
                           const float* ch, int c, const int* bind, int n_bind,
                           const float T[12], int32_t* out_cells);
 
+/* Drift compensation of point clouds (off by default): a point whose cell
+ * holds a height is consistent when (z - h)^2 <= kappa^2 (v + v_i) in
+ * binary32; with at least min_points consistent points every held height
+ * is shifted by their precision-weighted mean error before the height
+ * update and the ray cast.  orc_drift_last: the last cloud's offset (0 when
+ * none applied) and its number of consistent points. */
+void orc_set_drift(orc_map* m, int on, float kappa, int min_points);
+void orc_drift_last(const orc_map* m, double* offset, int* count);
+
 /* out_pix (H*W int32 or NULL): pixel row*w+col of each logical cell, or
  * -1 no height, -2 outside the view, -3 occluded. */
 void orc_input_image(orc_map* m, const void* img, int dtype, int h, int w,

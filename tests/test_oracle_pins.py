@@ -770,3 +770,98 @@ def test_topk_image_pixels_fuse_their_listed_classes(dtype):
                 if v == int(v) and 0 <= v < K:
                     want[int(v)] += probs[r, c, q]
             assert np.allclose(got[iy, ix], want, rtol=0, atol=1e-15), (ix, iy)
+
+
+# ---------------------------------------------------------------------------
+# z-error count and drift compensation (Table I rows 1-2, reading R23)
+# ---------------------------------------------------------------------------
+
+def flat_map(W, res, h0=0.0, v0=1e-4, **kw):
+    m = O.OracleMap(W, W, res, clear_min_count=0, **kw)
+    m.set_layer(O.LAYER_ELEVATION, O.VIEW_VALUE, np.full((W, W), h0))
+    m.set_layer(O.LAYER_VARIANCE, O.VIEW_VALUE, np.full((W, W), v0))
+    return m
+
+
+def centres(W, res, z):
+    g = (np.arange(W) - W // 2 + 0.5) * res
+    X, Y = np.meshgrid(g, g)
+    return np.stack([X.ravel(), Y.ravel(), np.full(X.size, z)], 1).astype(np.float32)
+
+
+def test_drift_of_a_uniformly_raised_cloud_is_its_offset():
+    """Every point 2^-5 m above a flat map: the weighted mean of equal errors
+    is that error exactly, every held height moves by it, and the fused
+    heights stay there."""
+    W, res, d = 8, 0.5, 2.0 ** -5
+    m = flat_map(W, res)
+    m.set_drift(True, kappa=3.0, min_points=10)
+    xyz = centres(W, res, d)
+    m.input_pointcloud(xyz, ID)
+    off, n = m.drift_last()
+    assert off == d and n == W * W
+    assert np.allclose(m.get_layer(O.LAYER_ELEVATION), d, rtol=0, atol=1e-15)
+
+
+def test_drift_needs_its_minimum_of_consistent_points():
+    W, res, d = 8, 0.5, 2.0 ** -5
+    m = flat_map(W, res)
+    m.set_drift(True, kappa=3.0, min_points=W * W + 1)
+    m.input_pointcloud(centres(W, res, d)[: W * W // 2], ID)  # half the cells observed
+    off, n = m.drift_last()
+    assert off == 0.0 and n == W * W // 2
+    h = m.get_layer(O.LAYER_ELEVATION).ravel()
+    assert (h == 0.0).sum() == W * W // 2  # unobserved cells keep their height
+
+
+def test_drift_matches_a_brute_force_of_its_definition():
+    """Random terrain with random variances, a cloud raised by 3 cm with
+    noise and 10 % outliers: the consistent set (binary32 test), the
+    binary64 weighted mean rounded to binary32, and the shifted heights of
+    cells without points, recomputed point by point."""
+    rng = np.random.default_rng(50)
+    W, res = 12, 0.25
+    m = O.OracleMap(W, W, res, clear_min_count=0)
+    h = rng.normal(0, 0.2, (W, W))
+    h[rng.uniform(size=(W, W)) < 0.15] = np.nan
+    v = rng.uniform(1e-4, 4e-3, (W, W))
+    m.set_layer(O.LAYER_ELEVATION, O.VIEW_VALUE, h.astype(np.float32))
+    m.set_layer(O.LAYER_VARIANCE, O.VIEW_VALUE, v.astype(np.float32))
+    kappa = np.float32(2.5)
+    m.set_drift(True, kappa=float(kappa), min_points=5)
+    n = 300
+    xy = rng.uniform(-W * res / 2, W * res / 2, (n, 2))
+    xyz = np.concatenate([xy, np.zeros((n, 1))], 1).astype(np.float32)
+    cells = m.point_cells(xyz, ID)
+    hh = np.nan_to_num(h.ravel()[np.maximum(cells, 0)])
+    z = hh + 0.03 + rng.normal(0, 0.01, n)
+    out = rng.uniform(size=n) < 0.1  # outliers a metre off
+    z[out] += rng.choice([-1.0, 1.0], int(out.sum()))
+    xyz[:, 2] = z.astype(np.float32)
+    f32 = np.float32
+    c0, c1 = f32(0.01), f32(0.001)
+    sw = swe = 0.0
+    cnt = 0
+    for (x, y, zz), j in zip(xyz, cells):
+        if j < 0 or np.isnan(h.ravel()[j]):
+            continue
+        r2 = f32(f32(f32(x * x) + f32(y * y)) + f32(zz * zz))
+        sig = f32(c0 + f32(c1 * r2))
+        vi = f32(sig * sig)
+        e = f32(zz - f32(h.ravel()[j]))
+        tot = f32(f32(v.ravel()[j]) + vi)
+        if not f32(e * e) <= f32(f32(kappa * kappa) * tot):
+            continue
+        sw += 1.0 / float(tot)
+        swe += float(e) / float(tot)
+        cnt += 1
+    want = float(f32(swe / sw))
+    m.input_pointcloud(xyz, ID)
+    off, got_n = m.drift_last()
+    assert got_n == cnt and 0.5 * n < cnt < n
+    assert off == want and abs(off - 0.03) < 0.005
+    after = m.get_layer(O.LAYER_ELEVATION).ravel()
+    hit = np.zeros(W * W, bool)
+    hit[cells[cells >= 0]] = True
+    keep = ~hit & ~np.isnan(h.ravel())
+    assert np.array_equal(after[keep], (h.ravel()[keep].astype(f32) + f32(want)).astype(np.float64))
