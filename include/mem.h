@@ -284,6 +284,28 @@ mem_status mem_set_layer(mem_map* map, int32_t layer, int32_t view,
  * call. */
 mem_status mem_normals(const mem_map* map, float* out, void* stream);
 
+/* z-error count and drift compensation of later point clouds (Table I,
+ * "point trsf. & z err. cnt" and "drift compensation"; the paper gives no
+ * formula).  When enabled, mem_input_pointcloud first tests every accepted
+ * point whose cell holds a height h with variance v: its height error
+ * e = z - h (z the point's map-frame height) is consistent with the map iff
+ *   e * e <= (kappa * kappa) * (v + v_i)   in binary32,
+ * v_i = (c0 + c1 r^2)^2 the point's variance.  With at least min_points
+ * consistent points, every held height is shifted by
+ *   d = binary32( sum e_i / (v + v_i)  /  sum 1 / (v + v_i) )   (sums in binary64),
+ * h <- h + d in binary32 (variances unchanged), before the cloud's height
+ * update and clearing rays.  Host state only; takes effect from the next
+ * call.  Errors: MEM_E_ARG if enabled with kappa not positive and finite or
+ * min_points < 1. */
+mem_status mem_set_drift_compensation(mem_map* map, int32_t enable, float kappa,
+                                      int32_t min_points);
+
+/* The last point cloud's applied offset d (0 when none was applied, or the
+ * feature is off) and its number of consistent points (0 when off).
+ * Host pointers; waits for `stream`. */
+mem_status mem_get_drift(const mem_map* map, float* offset, int32_t* consistent,
+                         void* stream);
+
 /* Current centre cell of the grid (host values; no device work). */
 mem_status mem_get_center(const mem_map* map, int32_t* cx, int32_t* cy);
 

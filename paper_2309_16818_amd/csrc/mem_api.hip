@@ -101,6 +101,10 @@ struct mem_map {
     int* longs = nullptr;       // long rays of the clearing march (kMarchPass entries)
     float* hl = nullptr;        // heights in logical order, for the clearing march
     int* n_long = nullptr;      // their count
+    DriftDev* drift = nullptr;  // the last cloud's drift compensation
+    bool drift_on = false;
+    float drift_kappa2 = 0.0f;  // binary32 kappa * kappa
+    int drift_min = 0;
     int4* vlist = nullptr;      // cells inside a camera's view
     float* tmax = nullptr;      // block maxima of h: side 8, then side 64
     int* vcode = nullptr;       // their pixel per image
@@ -251,6 +255,7 @@ void free_map(mem_map* m)
     (void)hipFree(m->longs);
     (void)hipFree(m->hl);
     (void)hipFree(m->n_long);
+    (void)hipFree(m->drift);
     (void)hipFree(m->vlist);
     (void)hipFree(m->vcode);
     (void)hipFree(m->tmax);
@@ -344,7 +349,7 @@ mem_status mem_create(const mem_params* p, void* stream, mem_map** out)
         (st = dev_alloc(m, &m->stash, HW)) ||
         (st = dev_alloc(m, &m->vlist, HW)) || (st = dev_alloc(m, &m->vcode, HW * kMaxImages)) ||
         (st = dev_alloc(m, &m->vcount, 2)) || (st = dev_alloc(m, &m->tmax, m->tmax_size())) ||
-        (st = dev_alloc(m, &m->longs, kMarchPass)) || (st = dev_alloc(m, &m->n_long, 1)) ||
+        (st = dev_alloc(m, &m->longs, kMarchPass)) || (st = dev_alloc(m, &m->n_long, 1)) || (st = dev_alloc(m, &m->drift, 1)) ||
         (st = dev_alloc(m, &m->hl, HW)) ||
         (st = dev_alloc(m, &m->stats, kStats * kStatSlots))) {
         free_map(m);
@@ -377,7 +382,7 @@ mem_status mem_create(const mem_params* p, void* stream, mem_map** out)
     Grid g = m->grid();
     auto devs = layer_devs(m);
     launch_reset_rect(s, g, 0, m->W, 0, m->H, m->h, m->v, m->cnt, m->clr, devs.data(), (int)devs.size());
-    launch_zero_accum(s, g, m->cnt, m->wsum, m->ssum, m->clr, nullptr, 0, nullptr, nullptr, nullptr);
+    launch_zero_accum(s, g, m->cnt, m->wsum, m->ssum, m->clr, nullptr, 0, nullptr, nullptr, nullptr, m->drift);
     launch_zero_int(s, (int*)m->stats, 2 * kStats * kStatSlots);
     launch_zero_int(s, m->vcount, 2);
     hipError_t e = hipGetLastError();
@@ -510,7 +515,7 @@ mem_status mem_input_pointcloud(mem_map* m, const float* xyz, int64_t n, const f
     const bool march = m->clear_min > 0 && n > 0;
     timed(m, s, "zero_accum", [&] {
         launch_zero_accum(s, g, m->cnt, m->wsum, m->ssum, m->clr, m->chsum, pb.Cb, m->n_long, m->h,
-                          march ? m->hl : nullptr);
+                          march ? m->hl : nullptr, m->drift);
     });
     Pose T;
     memcpy(T.m, T_map_sensor, sizeof(T.m));
@@ -518,6 +523,11 @@ mem_status mem_input_pointcloud(mem_map* m, const float* xyz, int64_t n, const f
         launch_ingest(s, g, xyz, n, ch, T, m->c0, m->c1, m->mr2, pb, m->cnt, m->wsum, m->ssum, m->stash,
                       m->chsum, m->stats);
     });
+    if (m->drift_on && n > 0)
+        timed(m, s, "drift", [&] {
+            launch_drift(s, g, xyz, n, T, m->c0, m->c1, m->mr2, m->h, m->v, m->drift_kappa2, m->drift_min,
+                         m->drift, march ? m->hl : nullptr);
+        });
     if (march)
         timed(m, s, "clear_march", [&] {
             launch_clear_march(s, g, xyz, n, T, m->mr2, m->clear_margin, m->hl, m->clr, m->longs, m->n_long,
@@ -529,6 +539,33 @@ mem_status mem_input_pointcloud(mem_map* m, const float* xyz, int64_t n, const f
                         m->chsum, pb, m->stats);
     });
     return check_launch(m, "mem_input_pointcloud");
+}
+
+mem_status mem_set_drift_compensation(mem_map* m, int32_t enable, float kappa, int32_t min_points)
+{
+    if (mem_status st = usable(m)) return st;
+    if (enable) {
+        if (!(kappa > 0.0f) || !std::isfinite(kappa)) return fail(MEM_E_ARG, "kappa must be positive and finite");
+        if (min_points < 1) return fail(MEM_E_ARG, "min_points must be >= 1");
+    }
+    m->drift_on = enable != 0;
+    m->drift_kappa2 = kappa * kappa;
+    m->drift_min = min_points;
+    return MEM_OK;
+}
+
+mem_status mem_get_drift(const mem_map* mc, float* offset, int32_t* consistent, void* stream)
+{
+    mem_map* m = const_cast<mem_map*>(mc);
+    if (mem_status st = usable(m)) return st;
+    if (!offset || !consistent) return fail(MEM_E_ARG, "NULL argument");
+    DriftDev dd{};
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(m, hipMemcpyAsync(&dd, m->drift, sizeof dd, hipMemcpyDeviceToHost, s));
+    HIP_TRY(m, hipStreamSynchronize(s));
+    *offset = dd.d;
+    *consistent = dd.n;
+    return MEM_OK;
 }
 
 // Adds image k's intrinsics and size to `cam`.

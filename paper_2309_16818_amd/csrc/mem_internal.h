@@ -98,6 +98,15 @@ struct PointBinds {
     LayerDev L[kMaxBind];
 };
 
+// Drift compensation of one point cloud: the consistent points' binary64
+// sums, their count, and the binary32 offset that was applied (0 if none).
+struct DriftDev {
+    double sw;   // sum of 1 / (v + v_i)
+    double swe;  // sum of e_i / (v + v_i)
+    int n;       // consistent points
+    float d;     // offset applied to the held heights
+};
+
 constexpr int kMaxImages = 4;  // images sharing one camera pose per call
 
 // One camera pose and the intrinsics / sizes of the images taken from it.
@@ -115,7 +124,7 @@ struct Camera {
 // `hl`, if not null, receives a copy of the heights `h` in logical order
 // (index y * W + x).
 void launch_zero_accum(hipStream_t s, const Grid& g, int* n, float* wsum, float* ssum, int* clr,
-                       float* chsum, int Cb, int* zero1, const float* h, float* hl);
+                       float* chsum, int Cb, int* zero1, const float* h, float* hl, DriftDev* drift);
 // LDS bytes of the ingest kernel for `Cb` channel planes reduced in LDS.
 size_t ingest_lds_bytes(int Cb);
 void launch_ingest(hipStream_t s, const Grid& g, const float* xyz, int64_t n, const float* ch,
@@ -130,6 +139,13 @@ constexpr int64_t kMarchPass = 1 << 20;
 void launch_clear_march(hipStream_t s, const Grid& g, const float* xyz, int64_t n, const Pose& T,
                         float mr2, float margin, const float* hl, int* clr, int* longs, int* n_long,
                         unsigned long long* stats);
+// z-error count and drift compensation of one cloud: the consistent points'
+// sums into `drift`, then, with at least min_points of them, the shift of
+// every held height h (and its logical-order copy hl, if given) by their
+// precision-weighted mean error.  Reads h and v before the height update.
+void launch_drift(hipStream_t s, const Grid& g, const float* xyz, int64_t n, const Pose& T, float c0,
+                  float c1, float mr2, float* h, const float* v, float kappa2, int min_points,
+                  DriftDev* drift, float* hl);
 void launch_finalize(hipStream_t s, const Grid& g, const int* cnt, const float* wsum,
                      const float* ssum, const float2* stash, const int* clr, int clear_min,
                      float* h, float* v, const float* chsum, const PointBinds& pb,

@@ -29,7 +29,8 @@ STAT_FIELDS = ("points_in", "points_accepted", "dropped_nonfinite", "dropped_ran
 
 # Exported symbols of include/mem.h.
 SYMBOLS = ("mem_create", "mem_destroy", "mem_move", "mem_input_pointcloud", "mem_input_image",
-           "mem_input_images", "mem_get_layer", "mem_set_layer", "mem_normals", "mem_get_center", "mem_debug_point_cells",
+           "mem_input_images", "mem_get_layer", "mem_set_layer", "mem_normals", "mem_set_drift_compensation", "mem_get_drift",
+           "mem_get_center", "mem_debug_point_cells",
            "mem_debug_cell_pixels", "mem_get_stats", "mem_reset_stats", "mem_profile_enable",
            "mem_profile_read", "mem_last_error")
 
@@ -93,6 +94,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "mem_get_layer": [P, I32, I32, P, P],
         "mem_set_layer": [P, I32, I32, P, P],
         "mem_normals": [P, P, P],
+        "mem_set_drift_compensation": [P, I32, F, I32],
+        "mem_get_drift": [P, C.POINTER(F), C.POINTER(I32), P],
         "mem_get_center": [P, C.POINTER(I32), C.POINTER(I32)],
         "mem_debug_point_cells": [P, P, I64, P, P, P],
         "mem_debug_cell_pixels": [P, I32, I32, P, P, P, P],
@@ -279,6 +282,15 @@ class Map:
         _check(load().mem_set_layer(self._h, layer, view, _dev_ptr(v, "values"), _stream(stream)))
         # `v` may be a temporary copy: keep it alive until the kernel has read it
         (stream or torch.cuda.current_stream()).synchronize()
+
+    def set_drift_compensation(self, enable: bool = True, kappa: float = 3.0, min_points: int = 100):
+        _check(load().mem_set_drift_compensation(self._h, 1 if enable else 0, float(kappa), int(min_points)))
+
+    def drift(self, stream=None):
+        """(offset applied by the last point cloud, its consistent points)."""
+        d, n = C.c_float(), C.c_int32()
+        _check(load().mem_get_drift(self._h, C.byref(d), C.byref(n), _stream(stream)))
+        return d.value, n.value
 
     def normals(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         """[H, W, 3] surface normals of the heights (NaN on the border and

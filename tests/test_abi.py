@@ -91,6 +91,8 @@ def test_null_handles_are_rejected():
     assert lib.mem_input_pointcloud(None, None, 0, None, 0, None, 0, T, None) == mem.MEM_E_ARG
     assert lib.mem_get_layer(None, 0, 0, None, None) == mem.MEM_E_ARG
     assert lib.mem_normals(None, None, None) == mem.MEM_E_ARG
+    assert lib.mem_set_drift_compensation(None, 1, 3.0, 10) == mem.MEM_E_ARG
+    assert lib.mem_get_drift(None, None, None, None) == mem.MEM_E_ARG
     assert lib.mem_destroy(None, None) == mem.MEM_OK
 
 
