@@ -45,9 +45,9 @@ WALK_VALU_PER_CELL = {"clear_march": 18, "project": 57}
 # kernel's sources hash to `sha`.
 TRAFFIC = {
     # k_clear_march + k_clear_long per cloud, full-rate workload: FETCH_SIZE
-    # (1519.6 + 1871.0) KiB x 1.99985 (a 256 MiB copy reads FETCH_SIZE
-    # 131083.5 KiB) + WRITE_SIZE (314.8 + 423.4) KiB x 1.0
-    "clear_march": {"bytes_per_launch": 7699345, "sha": "43d99782ae345e74"},
+    # (882.6 + 1871.2) KiB x 1.99985 (a 256 MiB copy reads FETCH_SIZE
+    # 131083.5 KiB) + WRITE_SIZE (314.7 + 423.4) KiB x 1.0
+    "clear_march": {"bytes_per_launch": 6394997, "sha": "c5c383cfffb8c395"},
 }
 
 
@@ -665,6 +665,46 @@ def time_topk(m, frame, torch, k=3, reps=20):
     return out
 
 
+def time_drift(dframes, warmup, torch, kappa=3.0, min_points=100):
+    """The timed frames again with drift compensation on (kappa 3, at least
+    100 consistent points): frame time from frame-level events, and the
+    drift step's own time (z-error count over the cloud plus the shift of
+    the held heights) from per-launch events on a twin map.  Algorithmic
+    bytes of the step: 12 B per input point, 8 B (h, v) per accepted point,
+    12 B per cell (h read and written, its logical copy written)."""
+    def run(profile):
+        m = make_map()
+        m.set_drift_compensation(True, kappa, min_points)
+        for f in dframes[:warmup]:
+            run_frame(m, f)
+        torch.cuda.synchronize()
+        m.reset_stats()
+        if profile:
+            m.profile_enable(True)
+            m.profile_read()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in dframes[warmup:]]
+        offsets = []
+        for k, f in enumerate(dframes[warmup:]):
+            ev[k][0].record()
+            run_frame(m, f)
+            ev[k][1].record()
+            if profile:
+                offsets.append(m.drift())
+        torch.cuda.synchronize()
+        out = (np.array([a.elapsed_time(b) for a, b in ev]), m.stats(), m.profile_read() if profile else None, offsets)
+        m.close()
+        return out
+    lat, _, _, _ = run(False)
+    _, st, kern, offsets = run(True)
+    launches, ms = kern["drift"]
+    nf = len(dframes) - warmup
+    cells = 500 * 500
+    b = 12 * st["points_in"] + 8 * st["points_accepted"] + 12 * cells * launches
+    return dict(ms_per_frame=round(float(lat.mean()), 4), drift_us_per_cloud=round(1e3 * ms / launches, 3),
+                drift_ms_per_frame=round(ms / nf, 4), alg_gbs=round(b / (ms * 1e-3) / 1e9, 1),
+                last_offset_m=offsets[-1][0], last_consistent=offsets[-1][1])
+
+
 def time_normals_large(torch, side=4096):
     """Surface normals of a side x side map of seeded random heights (5%
     holes), where the launch streams 16 B per cell rather than waiting on
@@ -727,6 +767,7 @@ def main():
     post = {"normals": time_normals(m, torch), "normals_4096": time_normals_large(torch),
             "class_image": time_topk(m, dframes[-1], torch)}
     m.close()
+    post["drift"] = time_drift(dframes, args.warmup, torch)
     lat = np.array([a.elapsed_time(b) for a, b in ev])
     wall_ms = (t1 - t0) * 1e3 / args.steps
     pts_s = st["points_accepted"] / ((t1 - t0))

@@ -286,90 +286,6 @@ inline unsigned blocks_for(int64_t n, int per)
     return (unsigned)((n + per - 1) / per);
 }
 
-// z-error count (Table I): a grid-stride pass over the cloud that finds each
-// accepted point's cell again and, where the cell holds a height, tests the
-// height error against the combined variance in binary32; consistent points
-// add 1 / (v + v_i) and e / (v + v_i) to binary64 sums, reduced over the
-// workgroup before one global atomic per sum.
-__global__ __launch_bounds__(256) void k_drift_count(Grid g, const float* __restrict__ xyz, int64_t n, Pose T,
-                                                     float c0, float c1, float mr2,
-                                                     const float* __restrict__ h,
-                                                     const float* __restrict__ v, float kappa2,
-                                                     DriftDev* __restrict__ drift)
-{
-    double sw = 0.0, swe = 0.0;
-    int cnt = 0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        float px, py, pz, r2;
-        int ix, iy;
-        if (point_cell(g, T, mr2, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], px, py, pz, r2, ix, iy) != 0)
-            continue;
-        const int st = storage_index(g, ix, iy);
-        const float hj = h[st];
-        if (isnan(hj)) continue;
-        const float sig = c0 + c1 * r2;
-        const float vi = sig * sig;
-        const float e = pz - hj;
-        const float tot = v[st] + vi;
-        if (!(e * e <= kappa2 * tot)) continue;
-        sw += 1.0 / (double)tot;
-        swe += (double)e / (double)tot;
-        cnt++;
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        sw += __shfl_down(sw, off);
-        swe += __shfl_down(swe, off);
-        cnt += __shfl_down(cnt, off);
-    }
-    __shared__ double s_sw[4], s_swe[4];
-    __shared__ int s_n[4];
-    const int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        s_sw[wave] = sw;
-        s_swe[wave] = swe;
-        s_n[wave] = cnt;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < (int)(blockDim.x >> 6); w++) {
-            sw += s_sw[w];
-            swe += s_swe[w];
-            cnt += s_n[w];
-        }
-        if (cnt > 0) {
-            atomicAdd(&drift->sw, sw);
-            atomicAdd(&drift->swe, swe);
-            atomicAdd(&drift->n, cnt);
-        }
-    }
-}
-
-// Drift compensation (Table I): with at least min_points consistent points,
-// every held height moves by d = binary32(swe / sw); the logical-order copy
-// the clearing march reads moves with it.
-__global__ __launch_bounds__(256) void k_drift_apply(Grid g, DriftDev* __restrict__ drift, int min_points,
-                                                     float* __restrict__ h, float* __restrict__ hl)
-{
-    const DriftDev dd = *drift;
-    if (dd.n < min_points || dd.n == 0) return;
-    const float d = (float)(dd.swe / dd.sw);
-    if (blockIdx.x == 0 && threadIdx.x == 0) drift->d = d;
-    const int HW = g.W * g.H;
-    const int stride = gridDim.x * blockDim.x;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < HW; i += stride) {
-        const float x = h[i];
-        if (isnan(x)) continue;
-        const float y = x + d;
-        h[i] = y;
-        if (hl) {
-            int ix, iy;
-            logical_index(g, i, ix, iy);
-            hl[iy * g.W + ix] = y;
-        }
-    }
-}
-
 }  // namespace
 
 // LDS of a k_ingest workgroup that reduces Cb channel planes in LDS: the
@@ -473,21 +389,6 @@ void launch_point_cells(hipStream_t s, const Grid& g, const float* xyz, int64_t 
     if (n <= 0) return;
     hipLaunchKernelGGL(k_point_cells, dim3(blocks_for(n, 256)), dim3(256), 0, s, g, xyz, n, T, mr2,
                        out);
-}
-
-void launch_drift(hipStream_t s, const Grid& g, const float* xyz, int64_t n, const Pose& T, float c0,
-                  float c1, float mr2, float* h, const float* v, float kappa2, int min_points,
-                  DriftDev* drift, float* hl)
-{
-    if (n <= 0) return;
-    int64_t bc = (n + 255) / 256;
-    if (bc > 2048) bc = 2048;
-    hipLaunchKernelGGL(k_drift_count, dim3((unsigned)bc), dim3(256), 0, s, g, xyz, n, T, c0, c1, mr2, h, v, kappa2,
-                       drift);
-    unsigned ba = blocks_for((int64_t)g.W * g.H, 256);
-    if (ba > 2048) ba = 2048;
-    if (ba < 1) ba = 1;
-    hipLaunchKernelGGL(k_drift_apply, dim3(ba), dim3(256), 0, s, g, drift, min_points, h, hl);
 }
 
 }  // namespace memk

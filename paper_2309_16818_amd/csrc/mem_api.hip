@@ -102,6 +102,7 @@ struct mem_map {
     float* hl = nullptr;        // heights in logical order, for the clearing march
     int* n_long = nullptr;      // their count
     DriftDev* drift = nullptr;  // the last cloud's drift compensation
+    char* drift_part = nullptr; // its per-workgroup partial sums
     bool drift_on = false;
     float drift_kappa2 = 0.0f;  // binary32 kappa * kappa
     int drift_min = 0;
@@ -256,6 +257,7 @@ void free_map(mem_map* m)
     (void)hipFree(m->hl);
     (void)hipFree(m->n_long);
     (void)hipFree(m->drift);
+    (void)hipFree(m->drift_part);
     (void)hipFree(m->vlist);
     (void)hipFree(m->vcode);
     (void)hipFree(m->tmax);
@@ -349,7 +351,7 @@ mem_status mem_create(const mem_params* p, void* stream, mem_map** out)
         (st = dev_alloc(m, &m->stash, HW)) ||
         (st = dev_alloc(m, &m->vlist, HW)) || (st = dev_alloc(m, &m->vcode, HW * kMaxImages)) ||
         (st = dev_alloc(m, &m->vcount, 2)) || (st = dev_alloc(m, &m->tmax, m->tmax_size())) ||
-        (st = dev_alloc(m, &m->longs, kMarchPass)) || (st = dev_alloc(m, &m->n_long, 1)) || (st = dev_alloc(m, &m->drift, 1)) ||
+        (st = dev_alloc(m, &m->longs, kMarchPass)) || (st = dev_alloc(m, &m->n_long, 1)) || (st = dev_alloc(m, &m->drift, 1)) || (st = dev_alloc(m, &m->drift_part, drift_part_bytes())) ||
         (st = dev_alloc(m, &m->hl, HW)) ||
         (st = dev_alloc(m, &m->stats, kStats * kStatSlots))) {
         free_map(m);
@@ -526,7 +528,7 @@ mem_status mem_input_pointcloud(mem_map* m, const float* xyz, int64_t n, const f
     if (m->drift_on && n > 0)
         timed(m, s, "drift", [&] {
             launch_drift(s, g, xyz, n, T, m->c0, m->c1, m->mr2, m->h, m->v, m->drift_kappa2, m->drift_min,
-                         m->drift, march ? m->hl : nullptr);
+                         m->drift, m->drift_part, march ? m->hl : nullptr);
         });
     if (march)
         timed(m, s, "clear_march", [&] {

@@ -143,9 +143,11 @@ void launch_clear_march(hipStream_t s, const Grid& g, const float* xyz, int64_t 
 // sums into `drift`, then, with at least min_points of them, the shift of
 // every held height h (and its logical-order copy hl, if given) by their
 // precision-weighted mean error.  Reads h and v before the height update.
+// `part` holds drift_part_bytes() of per-workgroup partial sums.
 void launch_drift(hipStream_t s, const Grid& g, const float* xyz, int64_t n, const Pose& T, float c0,
                   float c1, float mr2, float* h, const float* v, float kappa2, int min_points,
-                  DriftDev* drift, float* hl);
+                  DriftDev* drift, void* part, float* hl);
+size_t drift_part_bytes();
 void launch_finalize(hipStream_t s, const Grid& g, const int* cnt, const float* wsum,
                      const float* ssum, const float2* stash, const int* clr, int clear_min,
                      float* h, float* v, const float* chsum, const PointBinds& pb,
