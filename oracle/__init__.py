@@ -48,6 +48,7 @@ def lib() -> C.CDLL:
         L.orc_layer_channels.restype = I
         L.orc_normals.argtypes = [P, P]
         L.orc_set_drift.argtypes = [P, I, C.c_float, I]
+        L.orc_set_overlap.argtypes = [P, I, C.c_float, C.c_float]
         L.orc_drift_last.argtypes = [P, C.POINTER(C.c_double), C.POINTER(I)]
         L.orc_bresenham.argtypes = [I, I, I, I, P, P, I]
         L.orc_bresenham.restype = I
@@ -183,6 +184,10 @@ class OracleMap:
     def set_drift(self, on=True, kappa=3.0, min_points=100):
         """Drift compensation of later point clouds (see orc_set_drift)."""
         lib().orc_set_drift(self._m, 1 if on else 0, float(kappa), int(min_points))
+
+    def set_overlap(self, on=True, range_xy=4.0, range_z=2.0):
+        """Overlap clearance after later point clouds (see orc_set_overlap)."""
+        lib().orc_set_overlap(self._m, 1 if on else 0, float(range_xy), float(range_z))
 
     def drift_last(self):
         """(offset applied by the last cloud, its consistent points)."""

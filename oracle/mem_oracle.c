@@ -56,6 +56,9 @@ struct orc_map {
     float drift_kappa;
     double drift_offset;
     int drift_count;
+    /* overlap clearance (off unless set): horizontal and vertical ranges */
+    int overlap_on;
+    float overlap_xy, overlap_z;
 };
 
 /* ------------------------------------------------------------------ */
@@ -636,6 +639,29 @@ void orc_input_pointcloud(orc_map* m, const float* xyz, int64_t n, const float* 
         free(mean);
     }
 
+    /* Overlap clearance (Table I, after the height update and the
+     * multi-modal update; the paper gives no definition).  A held height
+     * within the horizontal range overlap_xy of the sensor that lies more
+     * than overlap_z above or below the
+     * sensor's height belongs to another level overlapping the robot's
+     * surroundings (a floor above, an overhang) and is removed.  Decisions
+     * in binary32: the cell centre as in the camera association, squared
+     * horizontal distance against overlap_xy^2, |h - z_sensor| against
+     * overlap_z. */
+    if (m->overlap_on) {
+        const float r2max = m->overlap_xy * m->overlap_xy;
+        for (int iy = 0; iy < H; iy++)
+            for (int ix = 0; ix < W; ix++) {
+                const long j = (long)iy * W + ix;
+                if (!m->valid[j]) continue;
+                const float dx = ((float)(origin_x(m) + ix) + 0.5f) * m->res - T[3];
+                const float dy = ((float)(origin_y(m) + iy) + 0.5f) * m->res - T[7];
+                const float d2 = dx * dx + dy * dy;
+                if (!(d2 <= r2max)) continue;
+                if (fabsf((float)m->h[j] - T[11]) > m->overlap_z) m->valid[j] = 0;
+            }
+    }
+
     if (out_cells)
         for (int64_t i = 0; i < n; i++) out_cells[i] = cell[i];
 
@@ -860,4 +886,11 @@ void orc_drift_last(const orc_map* m, double* offset, int* count)
 {
     *offset = m->drift_offset;
     *count = m->drift_count;
+}
+
+void orc_set_overlap(orc_map* m, int on, float range_xy, float range_z)
+{
+    m->overlap_on = on;
+    m->overlap_xy = range_xy;
+    m->overlap_z = range_z;
 }

@@ -77,6 +77,11 @@ void orc_input_pointcloud(orc_map* m, const float* xyz, int64_t n,
 void orc_set_drift(orc_map* m, int on, float kappa, int min_points);
 void orc_drift_last(const orc_map* m, double* offset, int* count);
 
+/* Overlap clearance after each point cloud's height update (off by
+ * default): held heights within range_xy of the sensor horizontally and
+ * more than range_z above or below it are removed (binary32 decisions). */
+void orc_set_overlap(orc_map* m, int on, float range_xy, float range_z);
+
 /* out_pix (H*W int32 or NULL): pixel row*w+col of each logical cell, or
  * -1 no height, -2 outside the view, -3 occluded. */
 void orc_input_image(orc_map* m, const void* img, int dtype, int h, int w,

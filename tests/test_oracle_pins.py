@@ -865,3 +865,54 @@ def test_drift_matches_a_brute_force_of_its_definition():
     hit[cells[cells >= 0]] = True
     keep = ~hit & ~np.isnan(h.ravel())
     assert np.array_equal(after[keep], (h.ravel()[keep].astype(f32) + f32(want)).astype(np.float64))
+
+
+# ---------------------------------------------------------------------------
+# Overlap clearance (Table I, reading R24)
+# ---------------------------------------------------------------------------
+
+def test_overlap_clearance_removes_other_levels_near_the_sensor():
+    """A floor at 0 with a slab at 2.5 m over part of it (a level above) and
+    a pit at -1.5 m: with ranges 1.2 m horizontally and 1 m vertically, only
+    the slab and pit cells within 1.2 m of the sensor lose their heights,
+    decided by brute force in binary32; an empty cloud still clears."""
+    W, res = 24, 0.25
+    m = O.OracleMap(W, W, res, clear_min_count=0)
+    h = np.zeros((W, W))
+    h[:, 14:] = 2.5
+    h[2:6, 2:6] = -1.5
+    h[10, 10] = np.nan
+    m.set_layer(O.LAYER_ELEVATION, O.VIEW_VALUE, h)
+    m.set_layer(O.LAYER_VARIANCE, O.VIEW_VALUE, np.full((W, W), 1e-3))
+    m.set_overlap(True, range_xy=1.2, range_z=1.0)
+    s = np.array([0.3, -0.1, 0.6], np.float32)
+    m.input_pointcloud(np.zeros((0, 3), np.float32), pose(tuple(s)))
+    f32 = np.float32
+    want = ~np.isnan(h)
+    for iy in range(W):
+        for ix in range(W):
+            if not want[iy, ix]:
+                continue
+            dx = f32(f32(f32(ix - W // 2) + f32(0.5)) * f32(res)) - s[0]
+            dy = f32(f32(f32(iy - W // 2) + f32(0.5)) * f32(res)) - s[1]
+            if f32(f32(dx * dx) + f32(dy * dy)) <= f32(f32(1.2) * f32(1.2)) and abs(f32(f32(h[iy, ix]) - s[2])) > f32(1.0):
+                want[iy, ix] = False
+    got = ~np.isnan(m.get_layer(O.LAYER_ELEVATION))
+    assert np.array_equal(got, want)
+    removed = ~np.isnan(h) & ~want
+    assert removed.sum() > 10 and (h[removed] != 0).all()  # only slab and pit cells
+
+
+def test_overlap_clearance_is_off_by_default_and_keeps_its_own_level():
+    W, res = 16, 0.25
+    m = O.OracleMap(W, W, res, clear_min_count=0)
+    m.set_layer(O.LAYER_ELEVATION, O.VIEW_VALUE, np.full((W, W), 3.0))
+    m.set_layer(O.LAYER_VARIANCE, O.VIEW_VALUE, np.full((W, W), 1e-3))
+    m.input_pointcloud(np.zeros((0, 3), np.float32), pose((0.0, 0.0, 0.5)))
+    assert not np.isnan(m.get_layer(O.LAYER_ELEVATION)).any()
+    m.set_overlap(True, range_xy=10.0, range_z=3.0)  # 2.5 m away: within range_z
+    m.input_pointcloud(np.zeros((0, 3), np.float32), pose((0.0, 0.0, 0.5)))
+    assert not np.isnan(m.get_layer(O.LAYER_ELEVATION)).any()
+    m.set_overlap(True, range_xy=10.0, range_z=2.0)
+    m.input_pointcloud(np.zeros((0, 3), np.float32), pose((0.0, 0.0, 0.5)))
+    assert np.isnan(m.get_layer(O.LAYER_ELEVATION)).all()
