@@ -275,3 +275,41 @@ def round_bf16(v):
     _unet_sigs(L)
     f = np.vectorize(L.orc_round_bf16, otypes=[np.float64])
     return f(np.asarray(v, np.float64))
+
+
+# ---------------------------------------------------------------------------
+# PCA layer of a feature layer (the post-processing plugin of the paper's
+# post-processing figure; reading R25)
+# ---------------------------------------------------------------------------
+
+def pca_layer(values: np.ndarray, k: int = 3):
+    """[H, W, C] feature values -> ([H, W, k] projections, [k] eigenvalues,
+    [k, C] components).  Over the cells whose C values are all finite: the
+    mean m and the population covariance S = (1/N) sum (f - m)(f - m)^T;
+    the components are S's eigenvectors of the k largest eigenvalues in
+    descending order, each signed so that its largest-magnitude entry (the
+    first of equal ones) is positive; a cell's projection is
+    ((f - m) . e_1, ..., (f - m) . e_k), NaN for the other cells.  Fewer
+    than k channels leave the missing components and projections 0."""
+    H, W, C = values.shape
+    f = values.reshape(-1, C).astype(np.float64)
+    ok = np.isfinite(f).all(1)
+    out = np.full((H * W, k), np.nan)
+    lam = np.zeros(k)
+    comp = np.zeros((k, C))
+    n = int(ok.sum())
+    if n == 0:
+        return out.reshape(H, W, k), lam, comp
+    x = f[ok]
+    m = x.sum(0) / n
+    d = x - m
+    S = (d.T @ d) / n
+    w, V = np.linalg.eigh(S)          # ascending
+    order = np.argsort(-w, kind="stable")[: min(k, C)]
+    for r, i in enumerate(order):
+        e = V[:, i]
+        j = int(np.argmax(np.abs(e)))  # first of the largest magnitudes
+        comp[r] = e if e[j] > 0 else -e
+        lam[r] = w[i]
+    out[ok] = d @ comp.T
+    return out.reshape(H, W, k), lam, comp

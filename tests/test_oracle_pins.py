@@ -916,3 +916,59 @@ def test_overlap_clearance_is_off_by_default_and_keeps_its_own_level():
     m.set_overlap(True, range_xy=10.0, range_z=2.0)
     m.input_pointcloud(np.zeros((0, 3), np.float32), pose((0.0, 0.0, 0.5)))
     assert np.isnan(m.get_layer(O.LAYER_ELEVATION)).all()
+
+
+# ---------------------------------------------------------------------------
+# PCA layer of a feature layer (post-processing plugin, reading R25)
+# ---------------------------------------------------------------------------
+
+def test_pca_recovers_known_axes_of_a_symmetric_cloud():
+    """Pairs m +- a_i q_i along an orthonormal basis Q: the mean is m
+    exactly, the covariance (1/d) sum a_i^2 q_i q_i^T, so the components
+    are q_1..q_3 (signed), the eigenvalues a_i^2 / d, and the projection of
+    m + a_1 q_1 is (a_1, 0, 0) up to the component's sign."""
+    rng = np.random.default_rng(80)
+    d = 8
+    Q, _ = np.linalg.qr(rng.normal(size=(d, d)))
+    a = np.array([5.0, 3.0, 2.0, 1.0, 0.5, 0.4, 0.3, 0.2])
+    m = rng.normal(size=d)
+    pts = np.concatenate([m + a[:, None] * Q.T, m - a[:, None] * Q.T])  # 2d points
+    vals = np.full((4, 5, d), np.nan)
+    vals.reshape(-1, d)[: 2 * d] = pts
+    out, lam, comp = O.pca_layer(vals)
+    assert np.allclose(lam, a[:3] ** 2 / d, rtol=1e-12)
+    for r in range(3):
+        assert abs(abs(comp[r] @ Q[:, r]) - 1.0) < 1e-12
+        j = np.argmax(np.abs(comp[r]))
+        assert comp[r][j] > 0
+    flat = out.reshape(-1, 3)
+    assert np.allclose(np.abs(flat[0]), [a[0], 0, 0], atol=1e-12)
+    assert np.isnan(flat[2 * d:]).all()
+
+
+def test_pca_projections_are_centred_and_decorrelated():
+    """Invariants at any size: the projections have zero mean and their
+    covariance is diag(lambda); a channel permutation permutes the
+    components and leaves the projections."""
+    rng = np.random.default_rng(81)
+    H, W, C = 20, 30, 12
+    base = rng.normal(size=(H * W, 4)) @ rng.normal(size=(4, C)) * np.array([3, 2, 1, 0.5, *[0.2] * (C - 4)])
+    vals = (base + 0.01 * rng.normal(size=base.shape)).reshape(H, W, C)
+    vals[rng.uniform(size=(H, W)) < 0.2] = np.nan
+    out, lam, comp = O.pca_layer(vals)
+    p = out.reshape(-1, 3)
+    p = p[np.isfinite(p).all(1)]
+    assert np.allclose(p.mean(0), 0, atol=1e-10)
+    assert np.allclose(p.T @ p / len(p), np.diag(lam), atol=1e-9 * lam[0])
+    perm = rng.permutation(C)
+    out2, lam2, comp2 = O.pca_layer(vals[..., perm])
+    assert np.allclose(lam2, lam, rtol=1e-10)
+    assert np.allclose(out2, out, atol=1e-9, equal_nan=True)
+
+
+def test_pca_with_fewer_channels_than_components():
+    vals = np.stack([np.arange(6.0), 2 * np.arange(6.0)], 1).reshape(2, 3, 2)
+    out, lam, comp = O.pca_layer(vals)
+    assert np.allclose(comp[0], [1, 2] / np.sqrt(5)) and (comp[2] == 0).all()
+    assert np.allclose(lam[0], np.var(np.arange(6.0)) * 5)
+    assert (out[..., 2] == 0).all()
