@@ -705,6 +705,59 @@ def time_drift(dframes, warmup, torch, kappa=3.0, min_points=100):
                 last_offset_m=offsets[-1][0], last_consistent=offsets[-1][1])
 
 
+def time_overlap(dframes, warmup, torch, range_xy=4.0, range_z=2.0):
+    """The timed frames again with overlap clearance on (4 m around the
+    sensor, 2 m above and below it): frame time, and the clearance step's
+    own time from per-launch events on a twin map.  Its unit is a cell of
+    the disc's bounding box (4 B read; writes only where a height goes)."""
+    def run(profile):
+        m = make_map()
+        m.set_overlap_clearance(True, range_xy, range_z)
+        for f in dframes[:warmup]:
+            run_frame(m, f)
+        torch.cuda.synchronize()
+        if profile:
+            m.profile_enable(True)
+            m.profile_read()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in dframes[warmup:]]
+        for k, f in enumerate(dframes[warmup:]):
+            ev[k][0].record()
+            run_frame(m, f)
+            ev[k][1].record()
+        torch.cuda.synchronize()
+        out = (np.array([a.elapsed_time(b) for a, b in ev]), m.profile_read() if profile else None)
+        m.close()
+        return out
+    lat, _ = run(False)
+    _, kern = run(True)
+    launches, ms = kern["overlap_clear"]
+    return dict(ms_per_frame=round(float(lat.mean()), 4), overlap_us_per_cloud=round(1e3 * ms / launches, 3))
+
+
+def time_pca(m, torch, layer=9, reps=10):
+    """PCA layer of the final map's 64-channel feature layer: average time
+    of the whole call (sums, covariance, eigensolver, projection) from
+    events on its stream.  Algorithmic work: the layer read three times
+    (4 B per channel per cell) and 12 B written per cell; 2 C^2 binary64
+    flops per cell for the covariance."""
+    C = 64
+    s = torch.cuda.current_stream()
+    out = torch.empty((m.H, m.W, 3), dtype=torch.float32, device="cuda")
+    _, lam = m.pca(layer, out, stream=s)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    for _ in range(reps):
+        m.pca(layer, out, stream=s)
+    b.record(s)
+    b.synchronize()
+    us = a.elapsed_time(b) * 1e3 / reps
+    cells = m.H * m.W
+    byts = 3 * 4 * C * cells + 12 * cells
+    return dict(avg_us=round(us, 3), alg_gbs=round(byts / (us * 1e-6) / 1e9, 1),
+                fp64_tflops=round(2 * C * C * cells / (us * 1e-6) / 1e12, 2),
+                observed_cells=int(torch.isfinite(out[..., 0]).sum().item()), eigenvalues=[round(x, 6) for x in lam])
+
+
 def time_normals_large(torch, side=4096):
     """Surface normals of a side x side map of seeded random heights (5%
     holes), where the launch streams 16 B per cell rather than waiting on
@@ -765,9 +818,10 @@ def main():
     t1 = time.perf_counter()
     st = m.stats()
     post = {"normals": time_normals(m, torch), "normals_4096": time_normals_large(torch),
-            "class_image": time_topk(m, dframes[-1], torch)}
+            "pca": time_pca(m, torch), "class_image": time_topk(m, dframes[-1], torch)}
     m.close()
     post["drift"] = time_drift(dframes, args.warmup, torch)
+    post["overlap_clearance"] = time_overlap(dframes, args.warmup, torch)
     lat = np.array([a.elapsed_time(b) for a, b in ev])
     wall_ms = (t1 - t0) * 1e3 / args.steps
     pts_s = st["points_accepted"] / ((t1 - t0))

@@ -300,6 +300,39 @@ mem_status mem_normals(const mem_map* map, float* out, void* stream);
 mem_status mem_set_drift_compensation(mem_map* map, int32_t enable, float kappa,
                                       int32_t min_points);
 
+/* PCA layer of a feature layer (the post-processing plugin that turns
+ * feature layers into a PCA layer; the paper gives no formula).  Over the
+ * cells whose C channels are all observed (finite): the mean m and the
+ * population covariance S = (1/N) sum (f - m)(f - m)^T, both accumulated in
+ * binary64; e_1..e_3 the eigenvectors of S's three largest eigenvalues in
+ * descending order (Jacobi rotations in binary64), each signed so that its
+ * largest-magnitude entry (the first of equal ones) is positive.
+ * out: device, H x W x 3 float, logical row-major order as mem_get_layer:
+ * ((f - m).e_1, (f - m).e_2, (f - m).e_3) per cell, NaN where a channel is
+ * unobserved; caller-owned, fully overwritten.  eigenvalues: host, 3 floats
+ * or NULL (then the call does not wait for the stream); 0 for components
+ * beyond C or when no cell is observed.  Eigenvectors are defined only up
+ * to the span of equal eigenvalues.  The first call allocates about 17 MB
+ * of scratch for the map.  layer: a LATEST, EXPAVG or GAUSS user layer.
+ * Errors: MEM_E_ARG (NULL out, no such layer, a DIRICHLET layer),
+ * MEM_E_UNSUPPORTED (more than 64 channels), MEM_E_NOMEM. */
+mem_status mem_pca(const mem_map* map, int32_t layer, float* out, float eigenvalues[3],
+                   void* stream);
+
+/* Overlap clearance after every later point cloud (Table I, "overlap
+ * clearance", after the multi-modal update; the paper defines it nowhere).
+ * When enabled, mem_input_pointcloud ends by removing every held height
+ * whose cell centre c (binary32, ((o + i) + 0.5) * res per axis) lies within
+ * range_xy of the sensor horizontally and whose height lies more than
+ * range_z above or below the sensor:
+ *   (c.x - t.x)^2 + (c.y - t.y)^2 <= range_xy^2  and  |h - t.z| > range_z
+ * in binary32, t the sensor position of T_map_sensor (an empty cloud
+ * included).  Variances and layers are kept, as for the clearing rays.
+ * Host state only.  Errors: MEM_E_ARG if enabled with a range that is not
+ * finite and >= 0. */
+mem_status mem_set_overlap_clearance(mem_map* map, int32_t enable, float range_xy,
+                                     float range_z);
+
 /* The last point cloud's applied offset d (0 when none was applied, or the
  * feature is off) and its number of consistent points (0 when off).
  * Host pointers; waits for `stream`. */

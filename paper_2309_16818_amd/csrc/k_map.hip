@@ -1,5 +1,7 @@
 // k_map.hip - grid maintenance: resetting cells that enter the moving grid,
 // the layer read-out / write-in views, and the per-cell surface normals.
+#include <cmath>
+
 #include "update.h"
 
 namespace memk {
@@ -162,6 +164,29 @@ __global__ __launch_bounds__(256) void k_normals(Grid g, const float* __restrict
     o[2] = nz;
 }
 
+// Overlap clearance (Table I, after the multi-modal update): logical cells
+// [x0, x1) x [y0, y1), a box that holds every cell whose centre can lie
+// within the horizontal range; a held height there more than rz above or
+// below the sensor is removed.  Binary32 decisions with the cell centre of
+// the camera association.
+__global__ __launch_bounds__(256) void k_overlap_clear(Grid g, int x0, int x1, int y0, int y1, float sx, float sy,
+                                                       float sz, float r2max, float rz, float* __restrict__ h)
+{
+    const int bw = x1 - x0;
+    const int64_t nb = (int64_t)bw * (y1 - y0);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nb; k += stride) {
+        const int ix = x0 + (int)(k % bw), iy = y0 + (int)(k / bw);
+        const int st = storage_index(g, ix, iy);
+        const float hj = h[st];
+        if (isnan(hj)) continue;
+        const float dx = ((float)(g.ox + ix) + 0.5f) * g.res - sx;
+        const float dy = ((float)(g.oy + iy) + 0.5f) * g.res - sy;
+        const float d2 = dx * dx + dy * dy;
+        if (d2 <= r2max && fabsf(hj - sz) > rz) h[st] = kNaN;
+    }
+}
+
 }  // namespace
 
 void launch_reset_rect(hipStream_t s, const Grid& g, int x0, int x1, int y0, int y1, float* h,
@@ -198,6 +223,25 @@ void launch_normals(hipStream_t s, const Grid& g, const float* h, float* out)
 {
     dim3 grid((unsigned)((g.W + 63) / 64), (unsigned)((g.H + 3) / 4));
     hipLaunchKernelGGL(k_normals, grid, dim3(64, 4), 0, s, g, h, out);
+}
+
+void launch_overlap_clear(hipStream_t s, const Grid& g, float sx, float sy, float sz, float rxy, float rz, float* h)
+{
+    // a box one cell wider than the disc on every side: binary32 rounding
+    // of the centres cannot reach a cell outside it
+    const double r = (double)rxy;
+    // clamped in double before the conversion (the range may be huge)
+    auto cell = [&](double pos, int origin, int add, int n) {
+        const double c = std::floor(pos / g.res) - origin + add;
+        return (int)(c < 0.0 ? 0.0 : c > n ? (double)n : c);
+    };
+    const int x0 = cell((double)sx - r, g.ox, -1, g.W), x1 = cell((double)sx + r, g.ox, 2, g.W);
+    const int y0 = cell((double)sy - r, g.oy, -1, g.H), y1 = cell((double)sy + r, g.oy, 2, g.H);
+    if (x1 <= x0 || y1 <= y0) return;
+    int64_t blocks = ((int64_t)(x1 - x0) * (y1 - y0) + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(k_overlap_clear, dim3((unsigned)blocks), dim3(256), 0, s, g, x0, x1, y0, y1, sx, sy, sz,
+                       rxy * rxy, rz, h);
 }
 
 }  // namespace memk

@@ -1,0 +1,283 @@
+// k_pca.hip - PCA layer of a feature layer (the post-processing plugin that
+// turns feature layers into a three-channel layer).
+//
+//   k_pca_sum      one wave per cell, one lane per channel: a ballot keeps
+//                  the cells whose channels are all observed; binary64 sums
+//                  per channel, one partial row per workgroup.
+//   k_pca_cov      every workgroup reduces the sums to the mean in one fixed
+//                  order, then accumulates the centred outer products: lane
+//                  c holds row c of the workgroup's covariance (the cell's
+//                  centred vector is broadcast from LDS); the four waves
+//                  are summed in LDS into one partial matrix.
+//   k_pca_reduce   fixed-order sum of the partial matrices, divided by N.
+//   k_pca_eig      one workgroup: parallel cyclic Jacobi rotations (disjoint
+//                  index pairs of a round-robin schedule) on the matrix and
+//                  its eigenvector matrix in LDS, then the three largest
+//                  eigenpairs with the sign convention.
+//   k_pca_project  one lane per logical cell: the centred vector's three
+//                  projections, NaN for cells with an unobserved channel.
+#include "update.h"
+
+namespace memk {
+
+namespace {
+
+constexpr int kPcaBlocks = 512;  // workgroups of the two passes over the cells
+constexpr int kPcaSweeps = 40;   // Jacobi sweeps at most
+
+struct PcaParts {
+    double sum[kPcaBlocks][kPcaMaxC + 1];            // channel sums, then the count
+    double cov[kPcaBlocks][kPcaMaxC * kPcaMaxC];     // partial centred outer products
+    double S[kPcaMaxC * kPcaMaxC];                   // the covariance
+};
+
+__device__ __forceinline__ float feature(const LayerDev& L, int64_t st, int lane)
+{
+    return lane < L.C ? layer_load(L.val, L.storage, L.scale, st * L.C + lane, lane) : 0.0f;
+}
+
+__global__ __launch_bounds__(256) void k_pca_sum(LayerDev L, int HW, PcaParts* __restrict__ P)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double s = 0.0;
+    int n = 0;
+    for (int64_t st = (int64_t)blockIdx.x * 4 + w; st < HW; st += (int64_t)gridDim.x * 4) {
+        const float v = feature(L, st, lane);
+        if (__ballot(!isfinite(v))) continue;  // wave-uniform: the cell has an unobserved channel
+        s += (double)v;
+        n++;
+    }
+    __shared__ double sh[4][64];
+    __shared__ int shn[4];
+    sh[w][lane] = s;
+    if (lane == 0) shn[w] = n;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        P->sum[blockIdx.x][lane] = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
+        if (lane == 0) P->sum[blockIdx.x][kPcaMaxC] = (double)(((shn[0] + shn[1]) + shn[2]) + shn[3]);
+    }
+}
+
+// Mean of channel `lane` and the count, from the sum partials in one order.
+__device__ __forceinline__ double pca_mean(const PcaParts* __restrict__ P, int nblk, int lane, double& N)
+{
+    double s = 0.0, n = 0.0;
+    for (int b = 0; b < nblk; b++) {
+        s += P->sum[b][lane];
+        n += P->sum[b][kPcaMaxC];
+    }
+    N = n;
+    return n > 0.0 ? s / n : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_pca_cov(LayerDev L, int HW, PcaParts* __restrict__ P, int nblk)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double N;
+    const double mean = pca_mean(P, nblk, lane, N);
+    __shared__ double sd[4][64];
+    double acc[kPcaMaxC];
+#pragma unroll
+    for (int k = 0; k < kPcaMaxC; k++) acc[k] = 0.0;
+    for (int64_t st = (int64_t)blockIdx.x * 4 + w; st < HW; st += (int64_t)gridDim.x * 4) {
+        const float v = feature(L, st, lane);
+        if (__ballot(!isfinite(v))) continue;
+        const double d = lane < L.C ? (double)v - mean : 0.0;
+        sd[w][lane] = d;
+        __builtin_amdgcn_wave_barrier();  // the wave's row is written before any lane reads it
+#pragma unroll
+        for (int k = 0; k < kPcaMaxC; k++) acc[k] += d * sd[w][k];
+        __builtin_amdgcn_wave_barrier();  // ... and read before the next cell overwrites it
+    }
+    // the four waves' rows summed in LDS, in wave order
+    __shared__ double tile[kPcaMaxC][kPcaMaxC + 1];
+    for (int ww = 0; ww < 4; ww++) {
+        if (w == ww)
+#pragma unroll
+            for (int k = 0; k < kPcaMaxC; k++) tile[lane][k] = ww == 0 ? acc[k] : tile[lane][k] + acc[k];
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < kPcaMaxC * kPcaMaxC; e += 256)
+        P->cov[blockIdx.x][e] = tile[e / kPcaMaxC][e % kPcaMaxC];
+}
+
+__global__ __launch_bounds__(256) void k_pca_reduce(PcaParts* __restrict__ P, int nblk)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= kPcaMaxC * kPcaMaxC) return;
+    double N = 0.0, s = 0.0;
+    for (int b = 0; b < nblk; b++) {
+        s += P->cov[b][e];
+        N += P->sum[b][kPcaMaxC];
+    }
+    P->S[e] = N > 0.0 ? s / N : 0.0;
+}
+
+// Jacobi eigensolver of the C x C covariance, one workgroup.  The index set
+// is padded to an even n with a zero row and column; each round rotates n/2
+// disjoint pairs (a round-robin tournament over n - 1 rounds per sweep), so
+// their Givens rotations commute and are applied together: rows, then
+// columns of S, then columns of V.
+__global__ __launch_bounds__(256) void k_pca_eig(const PcaParts* __restrict__ P, int C, PcaOut* __restrict__ out,
+                                                 int nblk)
+{
+    __shared__ double S[kPcaMaxC][kPcaMaxC + 1];
+    __shared__ double V[kPcaMaxC][kPcaMaxC + 1];
+    __shared__ double cs[kPcaMaxC / 2], sn[kPcaMaxC / 2];
+    __shared__ int pa[kPcaMaxC / 2], pb[kPcaMaxC / 2];
+    __shared__ double red[256];
+    __shared__ int done;
+    const int t = threadIdx.x;
+    const int n = C + (C & 1);
+    for (int e = t; e < n * n; e += 256) {
+        const int r = e / n, c = e % n;
+        S[r][c] = (r < C && c < C) ? P->S[r * kPcaMaxC + c] : 0.0;
+        V[r][c] = r == c ? 1.0 : 0.0;
+    }
+    if (t < kPcaMaxC) {
+        double N;
+        out->mean[t] = t < C ? pca_mean(P, nblk, t, N) : 0.0;
+        if (t == 0) out->n = N;
+    }
+    if (t == 0) done = 0;
+    __syncthreads();
+    // scale for the stopping test: the squared Frobenius norm
+    double fro = 0.0;
+    for (int e = t; e < n * n; e += 256) fro += S[e / n][e % n] * S[e / n][e % n];
+    red[t] = fro;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off) red[t] += red[t + off];
+        __syncthreads();
+    }
+    const double fro2 = red[0];
+    __syncthreads();
+    const int half = n / 2;
+    for (int sweep = 0; sweep < kPcaSweeps && n > 1; sweep++) {
+        for (int r = 0; r < n - 1; r++) {
+            if (t < half) {
+                // player 0 stays, the others rotate by one each round
+                auto player = [&](int i) { return i == 0 ? 0 : (i - 1 + r) % (n - 1) + 1; };
+                const int a = player(t), b = player(n - 1 - t);
+                const double apq = S[a][b];
+                double c = 1.0, s = 0.0;
+                if (apq != 0.0) {
+                    const double tau = (S[b][b] - S[a][a]) / (2.0 * apq);
+                    const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    c = 1.0 / sqrt(1.0 + tt * tt);
+                    s = tt * c;
+                }
+                cs[t] = c;
+                sn[t] = s;
+                pa[t] = a;
+                pb[t] = b;
+            }
+            __syncthreads();
+            for (int e = t; e < half * n; e += 256) {  // rows: S <- G^T S
+                const int p = e / n, k = e % n;
+                const double c = cs[p], s = sn[p];
+                const double x = S[pa[p]][k], y = S[pb[p]][k];
+                S[pa[p]][k] = c * x - s * y;
+                S[pb[p]][k] = s * x + c * y;
+            }
+            __syncthreads();
+            for (int e = t; e < half * n; e += 256) {  // columns: S <- S G, V <- V G
+                const int p = e / n, k = e % n;
+                const double c = cs[p], s = sn[p];
+                const double x = S[k][pa[p]], y = S[k][pb[p]];
+                S[k][pa[p]] = c * x - s * y;
+                S[k][pb[p]] = s * x + c * y;
+                const double u = V[k][pa[p]], z = V[k][pb[p]];
+                V[k][pa[p]] = c * u - s * z;
+                V[k][pb[p]] = s * u + c * z;
+            }
+            __syncthreads();
+        }
+        double off = 0.0;
+        for (int e = t; e < n * n; e += 256)
+            if (e / n != e % n) off += S[e / n][e % n] * S[e / n][e % n];
+        red[t] = off;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (t < o) red[t] += red[t + o];
+            __syncthreads();
+        }
+        if (t == 0) done = red[0] <= 1e-30 * fro2;
+        __syncthreads();
+        if (done) break;
+    }
+    if (t == 0) {
+        // the three largest eigenvalues, descending (the lower index first
+        // among equal ones), each vector signed by its largest entry
+        int taken[kPcaK] = {-1, -1, -1};
+        for (int k = 0; k < kPcaK; k++) {
+            int best = -1;
+            for (int i = 0; i < C; i++) {
+                bool used = false;
+                for (int q = 0; q < k; q++) used = used || taken[q] == i;
+                if (!used && (best < 0 || S[i][i] > S[best][best])) best = i;
+            }
+            taken[k] = best;
+            if (best < 0) {
+                out->lam[k] = 0.0;
+                for (int i = 0; i < kPcaMaxC; i++) out->comp[k][i] = 0.0;
+                continue;
+            }
+            int j = 0;
+            for (int i = 1; i < C; i++)
+                if (fabs(V[i][best]) > fabs(V[j][best])) j = i;
+            const double sg = V[j][best] > 0.0 ? 1.0 : -1.0;
+            out->lam[k] = S[best][best];
+            for (int i = 0; i < kPcaMaxC; i++) out->comp[k][i] = i < C ? sg * V[i][best] : 0.0;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_pca_project(Grid g, LayerDev L, const PcaOut* __restrict__ pc,
+                                                     float* __restrict__ out)
+{
+    __shared__ double s_m[kPcaMaxC], s_e[kPcaK][kPcaMaxC];
+    for (int i = threadIdx.x; i < kPcaMaxC; i += blockDim.x) {
+        s_m[i] = pc->mean[i];
+        for (int k = 0; k < kPcaK; k++) s_e[k][i] = pc->comp[k][i];
+    }
+    __syncthreads();
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= g.W * g.H) return;
+    const int ix = j % g.W, iy = j / g.W;
+    const int64_t st = storage_index(g, ix, iy);
+    double p[kPcaK] = {0.0, 0.0, 0.0};
+    bool ok = true;
+    for (int c = 0; c < L.C; c++) {
+        const float v = layer_load(L.val, L.storage, L.scale, st * L.C + c, c);
+        ok = ok && isfinite(v);
+        const double d = (double)v - s_m[c];
+#pragma unroll
+        for (int k = 0; k < kPcaK; k++) p[k] += d * s_e[k][c];
+    }
+#pragma unroll
+    for (int k = 0; k < kPcaK; k++) out[(int64_t)j * kPcaK + k] = ok ? (float)p[k] : __builtin_nanf("");
+}
+
+}  // namespace
+
+size_t pca_scratch_bytes()
+{
+    return sizeof(PcaParts);
+}
+
+void launch_pca(hipStream_t s, const Grid& g, const LayerDev& L, void* scratch, PcaOut* res, float* out)
+{
+    PcaParts* P = static_cast<PcaParts*>(scratch);
+    const int HW = g.W * g.H;
+    int nblk = (HW + 3) / 4;
+    if (nblk > kPcaBlocks) nblk = kPcaBlocks;
+    if (nblk < 1) nblk = 1;
+    hipLaunchKernelGGL(k_pca_sum, dim3(nblk), dim3(256), 0, s, L, HW, P);
+    hipLaunchKernelGGL(k_pca_cov, dim3(nblk), dim3(256), 0, s, L, HW, P, nblk);
+    hipLaunchKernelGGL(k_pca_reduce, dim3((kPcaMaxC * kPcaMaxC + 255) / 256), dim3(256), 0, s, P, nblk);
+    hipLaunchKernelGGL(k_pca_eig, dim3(1), dim3(256), 0, s, P, L.C, res, nblk);
+    hipLaunchKernelGGL(k_pca_project, dim3((HW + 255) / 256), dim3(256), 0, s, g, L, res, out);
+}
+
+}  // namespace memk

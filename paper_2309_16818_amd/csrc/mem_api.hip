@@ -106,6 +106,10 @@ struct mem_map {
     bool drift_on = false;
     float drift_kappa2 = 0.0f;  // binary32 kappa * kappa
     int drift_min = 0;
+    void* pca_scratch = nullptr; // partial sums of the PCA layer (allocated on first use)
+    PcaOut* pca_out = nullptr;
+    bool overlap_on = false;    // overlap clearance after each point cloud
+    float overlap_xy = 0.0f, overlap_z = 0.0f;
     int4* vlist = nullptr;      // cells inside a camera's view
     float* tmax = nullptr;      // block maxima of h: side 8, then side 64
     int* vcode = nullptr;       // their pixel per image
@@ -258,6 +262,8 @@ void free_map(mem_map* m)
     (void)hipFree(m->n_long);
     (void)hipFree(m->drift);
     (void)hipFree(m->drift_part);
+    (void)hipFree(m->pca_scratch);
+    (void)hipFree(m->pca_out);
     (void)hipFree(m->vlist);
     (void)hipFree(m->vcode);
     (void)hipFree(m->tmax);
@@ -540,6 +546,10 @@ mem_status mem_input_pointcloud(mem_map* m, const float* xyz, int64_t n, const f
         launch_finalize(s, g, m->cnt, m->wsum, m->ssum, m->stash, m->clr, m->clear_min, m->h, m->v,
                         m->chsum, pb, m->stats);
     });
+    if (m->overlap_on)
+        timed(m, s, "overlap_clear", [&] {
+            launch_overlap_clear(s, g, T.m[3], T.m[7], T.m[11], m->overlap_xy, m->overlap_z, m->h);
+        });
     return check_launch(m, "mem_input_pointcloud");
 }
 
@@ -553,6 +563,44 @@ mem_status mem_set_drift_compensation(mem_map* m, int32_t enable, float kappa, i
     m->drift_on = enable != 0;
     m->drift_kappa2 = kappa * kappa;
     m->drift_min = min_points;
+    return MEM_OK;
+}
+
+mem_status mem_pca(const mem_map* mc, int32_t layer, float* out, float eigenvalues[3], void* stream)
+{
+    mem_map* m = const_cast<mem_map*>(mc);
+    if (mem_status st = usable(m)) return st;
+    if (!out) return fail(MEM_E_ARG, "out is NULL");
+    const Layer* L = nullptr;
+    if (mem_status st = resolve_layer(m, layer, &L)) return st;
+    if (L->rule == MEM_DIRICHLET) return fail(MEM_E_ARG, "layer %d is a class layer, not a feature layer", layer);
+    if (L->C > kPcaMaxC) return fail(MEM_E_UNSUPPORTED, "PCA of %d channels (at most %d)", L->C, kPcaMaxC);
+    if (!m->pca_scratch) {
+        char* p = nullptr;
+        if (mem_status st = dev_alloc(m, &p, pca_scratch_bytes())) return st;
+        m->pca_scratch = p;
+        if (mem_status st = dev_alloc(m, &m->pca_out, 1)) return st;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    timed(m, s, "pca", [&] { launch_pca(s, m->grid(), L->dev(), m->pca_scratch, m->pca_out, out); });
+    if (mem_status st = check_launch(m, "mem_pca")) return st;
+    if (eigenvalues) {
+        double lam[kPcaK];
+        HIP_TRY(m, hipMemcpyAsync(lam, m->pca_out->lam, sizeof lam, hipMemcpyDeviceToHost, s));
+        HIP_TRY(m, hipStreamSynchronize(s));
+        for (int k = 0; k < kPcaK; k++) eigenvalues[k] = (float)lam[k];
+    }
+    return MEM_OK;
+}
+
+mem_status mem_set_overlap_clearance(mem_map* m, int32_t enable, float range_xy, float range_z)
+{
+    if (mem_status st = usable(m)) return st;
+    if (enable && (!(range_xy >= 0.0f) || !std::isfinite(range_xy) || !(range_z >= 0.0f) || !std::isfinite(range_z)))
+        return fail(MEM_E_ARG, "ranges must be finite and >= 0");
+    m->overlap_on = enable != 0;
+    m->overlap_xy = range_xy;
+    m->overlap_z = range_z;
     return MEM_OK;
 }
 

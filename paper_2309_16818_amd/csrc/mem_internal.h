@@ -254,6 +254,23 @@ void launch_readout(hipStream_t s, const Grid& g, int layer, int view, const flo
                     const float* v, const int* cnt, const int* clr, const LayerDev* L, float* out);
 void launch_setlayer(hipStream_t s, const Grid& g, int layer, int view, float* h, float* v,
                      const LayerDev* L, const float* in);
+// Overlap clearance: held heights within rxy of (sx, sy) horizontally and more
+// than rz from sz vertically are removed.
+void launch_overlap_clear(hipStream_t s, const Grid& g, float sx, float sy, float sz, float rxy, float rz, float* h);
+// PCA layer of a feature layer of at most kPcaMaxC channels: the mean, the
+// three leading components and eigenvalues into `res` (device), the
+// projections into out ([H][W][3], logical order).  `scratch` holds
+// pca_scratch_bytes().
+constexpr int kPcaMaxC = 64;
+constexpr int kPcaK = 3;
+struct PcaOut {
+    double mean[kPcaMaxC];
+    double comp[kPcaK][kPcaMaxC];
+    double lam[kPcaK];
+    double n;  // cells with every channel observed
+};
+size_t pca_scratch_bytes();
+void launch_pca(hipStream_t s, const Grid& g, const LayerDev& L, void* scratch, PcaOut* res, float* out);
 // Surface normals of the heights h (storage order) into out ([H][W][3], logical order).
 void launch_normals(hipStream_t s, const Grid& g, const float* h, float* out);
 

@@ -30,6 +30,7 @@ STAT_FIELDS = ("points_in", "points_accepted", "dropped_nonfinite", "dropped_ran
 # Exported symbols of include/mem.h.
 SYMBOLS = ("mem_create", "mem_destroy", "mem_move", "mem_input_pointcloud", "mem_input_image",
            "mem_input_images", "mem_get_layer", "mem_set_layer", "mem_normals", "mem_set_drift_compensation", "mem_get_drift",
+           "mem_set_overlap_clearance", "mem_pca",
            "mem_get_center", "mem_debug_point_cells",
            "mem_debug_cell_pixels", "mem_get_stats", "mem_reset_stats", "mem_profile_enable",
            "mem_profile_read", "mem_last_error")
@@ -96,6 +97,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "mem_normals": [P, P, P],
         "mem_set_drift_compensation": [P, I32, F, I32],
         "mem_get_drift": [P, C.POINTER(F), C.POINTER(I32), P],
+        "mem_set_overlap_clearance": [P, I32, F, F],
+        "mem_pca": [P, I32, P, C.POINTER(F), P],
         "mem_get_center": [P, C.POINTER(I32), C.POINTER(I32)],
         "mem_debug_point_cells": [P, P, I64, P, P, P],
         "mem_debug_cell_pixels": [P, I32, I32, P, P, P, P],
@@ -285,6 +288,20 @@ class Map:
 
     def set_drift_compensation(self, enable: bool = True, kappa: float = 3.0, min_points: int = 100):
         _check(load().mem_set_drift_compensation(self._h, 1 if enable else 0, float(kappa), int(min_points)))
+
+    def set_overlap_clearance(self, enable: bool = True, range_xy: float = 4.0, range_z: float = 2.0):
+        _check(load().mem_set_overlap_clearance(self._h, 1 if enable else 0, float(range_xy), float(range_z)))
+
+    def pca(self, layer: int, out: torch.Tensor | None = None, stream=None):
+        """([H, W, 3] projections on the layer's three leading principal
+        components, [3] eigenvalues)."""
+        if out is None:
+            out = torch.empty((self.H, self.W, 3), dtype=torch.float32, device="cuda")
+        if out.dtype != torch.float32 or not out.is_contiguous() or out.numel() != self.H * self.W * 3:
+            raise ValueError("out must be a contiguous float32 tensor of H x W x 3 elements")
+        lam = (C.c_float * 3)()
+        _check(load().mem_pca(self._h, layer, _dev_ptr(out, "out"), lam, _stream(stream)))
+        return out, list(lam)
 
     def drift(self, stream=None):
         """(offset applied by the last point cloud, its consistent points)."""

@@ -1,0 +1,95 @@
+"""Overlap clearance (Table I, after the multi-modal update): the GPU map
+against the oracle in lockstep with the feature on.  Which heights are
+removed is a binary32 decision on both sides, so validity must agree
+exactly; heights, variances and votes follow the lockstep bars.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from lockstep import compare, gpu_layer, make_pair, sync_from_oracle, to_dev
+from paper_2309_16818_amd import mem
+
+pytestmark = pytest.mark.gpu
+
+
+def pose(t):
+    T = np.zeros((3, 4), np.float32)
+    T[:, :3] = np.eye(3)
+    T[:, 3] = t
+    return T
+
+
+def levels_pair(rng, W, res, moves=(), **kw):
+    """A floor near 0 with a slab 2.5 m above over part of it and a pit
+    1.5 m below, with holes."""
+    g, o = make_pair(W, W, res, **kw)
+    for mx, my in moves:
+        g.move(mx, my)
+        o.move(mx, my)
+    h = rng.normal(0, 0.05, (W, W))
+    h[:, int(0.6 * W):] += 2.5
+    h[W // 8:W // 4, W // 8:W // 4] -= 1.5
+    h[rng.uniform(size=h.shape) < 0.05] = np.nan
+    o.set_layer(O.LAYER_ELEVATION, 0, h)
+    o.set_layer(O.LAYER_VARIANCE, 0, rng.uniform(1e-4, 1e-3, (W, W)))
+    sync_from_oracle(g, o)
+    return g, o
+
+
+@pytest.mark.parametrize("clear_min", [0, 2])
+def test_overlap_lockstep_with_clouds(clear_min):
+    rng = np.random.default_rng(70 + clear_min)
+    W, res = 80, 0.05
+    g, o = levels_pair(rng, W, res, moves=[(0.37, -0.21)], clear_min_count=clear_min, max_range=10.0)
+    g.set_overlap_clearance(True, 1.3, 1.0)
+    o.set_overlap(True, 1.3, 1.0)
+    removed = 0
+    for it in range(3):
+        s = (0.37 + rng.uniform(-0.4, 0.4), -0.21 + rng.uniform(-0.4, 0.4), 0.6)
+        n = 8000
+        xy = rng.uniform(-1.6, 1.6, (n, 2)) + np.array(s[:2])
+        z = np.where(xy[:, 0] > 0.37 + 0.1 * W * res, 2.5, 0.0) + rng.normal(0, 0.02, n)
+        cl = (np.concatenate([xy, z[:, None]], 1) - np.array(s)).astype(np.float32)
+        sync_from_oracle(g, o)
+        before = ~np.isnan(o.get_layer(O.LAYER_ELEVATION))
+        g.input_pointcloud(to_dev(cl), pose(s))
+        o.input_pointcloud(cl, pose(s))
+        compare(g, o, what=f"overlap cloud {it}")
+        after = ~np.isnan(o.get_layer(O.LAYER_ELEVATION))
+        removed += int((before & ~after).sum())
+    assert removed > 100
+
+
+@pytest.mark.parametrize("rxy,rz,sensor", [
+    (0.0, 1.0, (0.0, 0.0, 0.5)),          # a disc of one point
+    (1e30, 1.0, (0.0, 0.0, 0.5)),         # every cell in range
+    (0.8, 0.0, (1.9, 1.9, 0.0)),          # sensor at the grid's corner
+    (2.0, 1.0, (9.0, -9.0, 0.0)),         # disc outside the grid
+])
+def test_overlap_edges_with_empty_clouds(rxy, rz, sensor):
+    rng = np.random.default_rng(71)
+    g, o = levels_pair(rng, 80, 0.05, moves=[(-0.63, 0.44)], clear_min_count=0)
+    g.set_overlap_clearance(True, rxy, rz)
+    o.set_overlap(True, rxy, rz)
+    empty = np.zeros((0, 3), np.float32)
+    g.input_pointcloud(to_dev(empty), pose(sensor))
+    o.input_pointcloud(empty, pose(sensor))
+    compare(g, o, what=f"overlap {rxy} {rz} {sensor}")
+
+
+def test_overlap_arguments_are_checked_and_off_by_default():
+    rng = np.random.default_rng(72)
+    g, o = levels_pair(rng, 32, 0.1, clear_min_count=0)
+    before = gpu_layer(g, 0)
+    g.input_pointcloud(to_dev(np.zeros((0, 3), np.float32)), pose((0, 0, 0)))
+    assert np.array_equal(gpu_layer(g, 0), before, equal_nan=True)
+    for rxy, rz in ((-1.0, 1.0), (1.0, -0.5), (float("inf"), 1.0), (1.0, float("nan"))):
+        with pytest.raises(mem.MemError) as e:
+            g.set_overlap_clearance(True, rxy, rz)
+        assert e.value.code == mem.MEM_E_ARG
+    g.set_overlap_clearance(False, -1.0, -1.0)  # disabling takes no ranges
+    torch.cuda.synchronize()
