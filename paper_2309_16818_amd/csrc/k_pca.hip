@@ -10,7 +10,7 @@
 //                  centred vector is broadcast from LDS); the four waves
 //                  are summed in LDS into one partial matrix.
 //   k_pca_reduce   fixed-order sum of the partial matrices, divided by N.
-//   k_pca_eig      one workgroup: parallel cyclic Jacobi rotations (disjoint
+//   k_pca_eig      one workgroup of 1024 lanes: parallel cyclic Jacobi rotations (disjoint
 //                  index pairs of a round-robin schedule) on the matrix and
 //                  its eigenvector matrix in LDS, then the three largest
 //                  eigenpairs with the sign convention.
@@ -113,24 +113,27 @@ __global__ __launch_bounds__(256) void k_pca_reduce(PcaParts* __restrict__ P, in
     P->S[e] = N > 0.0 ? s / N : 0.0;
 }
 
-// Jacobi eigensolver of the C x C covariance, one workgroup.  The index set
-// is padded to an even n with a zero row and column; each round rotates n/2
-// disjoint pairs (a round-robin tournament over n - 1 rounds per sweep), so
-// their Givens rotations commute and are applied together: rows, then
-// columns of S, then columns of V.
-__global__ __launch_bounds__(256) void k_pca_eig(const PcaParts* __restrict__ P, int C, PcaOut* __restrict__ out,
-                                                 int nblk)
+// Jacobi eigensolver of the C x C covariance, one workgroup of 1024 lanes.
+// The matrix is held as kPcaMaxC x kPcaMaxC with zero rows and columns past
+// C (their rotations are identities), so a sweep is always kPcaMaxC - 1
+// rounds of kPcaMaxC / 2 disjoint pairs (a round-robin tournament); the
+// pairs' Givens rotations commute and are applied together: rows, then
+// columns of S and of V, two elements per lane and phase.
+constexpr int kEigLanes = 1024;
+static_assert(kPcaMaxC == 64 && (kPcaMaxC / 2) * kPcaMaxC == 2 * kEigLanes, "two (pair, column) elements per lane");
+
+__global__ __launch_bounds__(kEigLanes) void k_pca_eig(const PcaParts* __restrict__ P, int C,
+                                                       PcaOut* __restrict__ out, int nblk)
 {
-    __shared__ double S[kPcaMaxC][kPcaMaxC + 1];
-    __shared__ double V[kPcaMaxC][kPcaMaxC + 1];
-    __shared__ double cs[kPcaMaxC / 2], sn[kPcaMaxC / 2];
-    __shared__ int pa[kPcaMaxC / 2], pb[kPcaMaxC / 2];
-    __shared__ double red[256];
-    __shared__ int done;
+    constexpr int n = kPcaMaxC, half = kPcaMaxC / 2;
+    __shared__ double S[n][n + 1];
+    __shared__ double V[n][n + 1];
+    __shared__ double cs[half], sn[half];
+    __shared__ int pa[half], pb[half];
+    __shared__ double red[kEigLanes];
     const int t = threadIdx.x;
-    const int n = C + (C & 1);
-    for (int e = t; e < n * n; e += 256) {
-        const int r = e / n, c = e % n;
+    for (int e = t; e < n * n; e += kEigLanes) {
+        const int r = e >> 6, c = e & 63;
         S[r][c] = (r < C && c < C) ? P->S[r * kPcaMaxC + c] : 0.0;
         V[r][c] = r == c ? 1.0 : 0.0;
     }
@@ -139,24 +142,27 @@ __global__ __launch_bounds__(256) void k_pca_eig(const PcaParts* __restrict__ P,
         out->mean[t] = t < C ? pca_mean(P, nblk, t, N) : 0.0;
         if (t == 0) out->n = N;
     }
-    if (t == 0) done = 0;
     __syncthreads();
-    // scale for the stopping test: the squared Frobenius norm
-    double fro = 0.0;
-    for (int e = t; e < n * n; e += 256) fro += S[e / n][e % n] * S[e / n][e % n];
-    red[t] = fro;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (t < off) red[t] += red[t + off];
+    // squared Frobenius norm (scale of the stopping test) and, per sweep,
+    // the squared off-diagonal norm, reduced over the workgroup
+    auto block_sum = [&](double x) {
+        red[t] = x;
         __syncthreads();
-    }
-    const double fro2 = red[0];
-    __syncthreads();
-    const int half = n / 2;
-    for (int sweep = 0; sweep < kPcaSweeps && n > 1; sweep++) {
+        for (int o = kEigLanes / 2; o > 0; o >>= 1) {
+            if (t < o) red[t] += red[t + o];
+            __syncthreads();
+        }
+        const double r = red[0];
+        __syncthreads();
+        return r;
+    };
+    double f = 0.0;
+    for (int e = t; e < n * n; e += kEigLanes) f += S[e >> 6][e & 63] * S[e >> 6][e & 63];
+    const double fro2 = block_sum(f);
+    for (int sweep = 0; sweep < kPcaSweeps && C > 1; sweep++) {
         for (int r = 0; r < n - 1; r++) {
             if (t < half) {
-                // player 0 stays, the others rotate by one each round
+                // player 0 stays, the others move one seat each round
                 auto player = [&](int i) { return i == 0 ? 0 : (i - 1 + r) % (n - 1) + 1; };
                 const int a = player(t), b = player(n - 1 - t);
                 const double apq = S[a][b];
@@ -173,40 +179,34 @@ __global__ __launch_bounds__(256) void k_pca_eig(const PcaParts* __restrict__ P,
                 pb[t] = b;
             }
             __syncthreads();
-            for (int e = t; e < half * n; e += 256) {  // rows: S <- G^T S
-                const int p = e / n, k = e % n;
+#pragma unroll
+            for (int u = 0; u < 2; u++) {  // rows: S <- G^T S
+                const int e = t + u * kEigLanes, p = e >> 6, k = e & 63;
                 const double c = cs[p], s = sn[p];
                 const double x = S[pa[p]][k], y = S[pb[p]][k];
                 S[pa[p]][k] = c * x - s * y;
                 S[pb[p]][k] = s * x + c * y;
             }
             __syncthreads();
-            for (int e = t; e < half * n; e += 256) {  // columns: S <- S G, V <- V G
-                const int p = e / n, k = e % n;
+#pragma unroll
+            for (int u = 0; u < 2; u++) {  // columns: S <- S G, V <- V G
+                const int e = t + u * kEigLanes, p = e >> 6, k = e & 63;
                 const double c = cs[p], s = sn[p];
                 const double x = S[k][pa[p]], y = S[k][pb[p]];
                 S[k][pa[p]] = c * x - s * y;
                 S[k][pb[p]] = s * x + c * y;
-                const double u = V[k][pa[p]], z = V[k][pb[p]];
-                V[k][pa[p]] = c * u - s * z;
-                V[k][pb[p]] = s * u + c * z;
+                const double v = V[k][pa[p]], z = V[k][pb[p]];
+                V[k][pa[p]] = c * v - s * z;
+                V[k][pb[p]] = s * v + c * z;
             }
             __syncthreads();
         }
         double off = 0.0;
-        for (int e = t; e < n * n; e += 256)
-            if (e / n != e % n) off += S[e / n][e % n] * S[e / n][e % n];
-        red[t] = off;
-        __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if (t < o) red[t] += red[t + o];
-            __syncthreads();
-        }
+        for (int e = t; e < n * n; e += kEigLanes)
+            if ((e >> 6) != (e & 63)) off += S[e >> 6][e & 63] * S[e >> 6][e & 63];
         // off-diagonal norm at 1e-12 of the matrix's: rounding keeps it near
         // n eps, so a tighter bound would never be met
-        if (t == 0) done = red[0] <= 1e-24 * fro2;
-        __syncthreads();
-        if (done) break;
+        if (block_sum(off) <= 1e-24 * fro2) break;
     }
     if (t == 0) {
         // the three largest eigenvalues, descending (the lower index first
@@ -278,7 +278,7 @@ void launch_pca(hipStream_t s, const Grid& g, const LayerDev& L, void* scratch, 
     hipLaunchKernelGGL(k_pca_sum, dim3(nblk), dim3(256), 0, s, L, HW, P);
     hipLaunchKernelGGL(k_pca_cov, dim3(nblk), dim3(256), 0, s, L, HW, P, nblk);
     hipLaunchKernelGGL(k_pca_reduce, dim3((kPcaMaxC * kPcaMaxC + 255) / 256), dim3(256), 0, s, P, nblk);
-    hipLaunchKernelGGL(k_pca_eig, dim3(1), dim3(256), 0, s, P, L.C, res, nblk);
+    hipLaunchKernelGGL(k_pca_eig, dim3(1), dim3(kEigLanes), 0, s, P, L.C, res, nblk);
     hipLaunchKernelGGL(k_pca_project, dim3((HW + 255) / 256), dim3(256), 0, s, g, L, res, out);
 }
 
