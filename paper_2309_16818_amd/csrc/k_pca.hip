@@ -4,12 +4,13 @@
 //   k_pca_sum      one wave per cell, one lane per channel: a ballot keeps
 //                  the cells whose channels are all observed; binary64 sums
 //                  per channel, one partial row per workgroup.
-//   k_pca_cov      every workgroup reduces the sums to the mean in one fixed
-//                  order, then accumulates the centred outer products: lane
+//   k_pca_total    the partial sums' totals, in one fixed order.
+//   k_pca_cov      from the totals' mean, the centred outer products: lane
 //                  c holds row c of the workgroup's covariance (the cell's
 //                  centred vector is broadcast from LDS); the four waves
 //                  are summed in LDS into one partial matrix.
-//   k_pca_reduce   fixed-order sum of the partial matrices, divided by N.
+//   k_pca_reduce   fixed-order sum of the partial matrices (16 lanes per
+//                  entry, combined in lane order), divided by N.
 //   k_pca_eig      one workgroup of 1024 lanes: parallel cyclic Jacobi rotations (disjoint
 //                  index pairs of a round-robin schedule) on the matrix and
 //                  its eigenvector matrix in LDS, then the three largest
@@ -29,6 +30,7 @@ struct PcaParts {
     double sum[kPcaBlocks][kPcaMaxC + 1];            // channel sums, then the count
     double cov[kPcaBlocks][kPcaMaxC * kPcaMaxC];     // partial centred outer products
     double S[kPcaMaxC * kPcaMaxC];                   // the covariance
+    double tot[kPcaMaxC + 1];                        // channel sums, then the count
 };
 
 __device__ __forceinline__ float feature(const LayerDev& L, int64_t st, int lane)
@@ -58,23 +60,38 @@ __global__ __launch_bounds__(256) void k_pca_sum(LayerDev L, int HW, PcaParts* _
     }
 }
 
-// Mean of channel `lane` and the count, from the sum partials in one order.
-__device__ __forceinline__ double pca_mean(const PcaParts* __restrict__ P, int nblk, int lane, double& N)
+// Totals of the sum partials: 16 entries (channel sums, then the count) per
+// workgroup, each summed by 16 lanes over every 16th partial and the 16
+// sums added in lane order.
+__global__ __launch_bounds__(256) void k_pca_total(PcaParts* __restrict__ P, int nblk)
 {
-    double s = 0.0, n = 0.0;
-    for (int b = 0; b < nblk; b++) {
-        s += P->sum[b][lane];
-        n += P->sum[b][kPcaMaxC];
+    const int q = threadIdx.x & 15, part = threadIdx.x >> 4;
+    const int e = blockIdx.x * 16 + q;
+    double s = 0.0;
+    if (e <= kPcaMaxC)
+        for (int b = part; b < nblk; b += 16) s += P->sum[b][e];
+    __shared__ double red[16][17];
+    red[part][q] = s;
+    __syncthreads();
+    if (threadIdx.x < 16 && e <= kPcaMaxC) {
+        double t = 0.0;
+        for (int k = 0; k < 16; k++) t += red[k][q];
+        P->tot[e] = t;
     }
-    N = n;
-    return n > 0.0 ? s / n : 0.0;
 }
 
-__global__ __launch_bounds__(256) void k_pca_cov(LayerDev L, int HW, PcaParts* __restrict__ P, int nblk)
+// Mean of channel `lane` and the count of cells with every channel observed.
+__device__ __forceinline__ double pca_mean(const PcaParts* __restrict__ P, int lane, double& N)
+{
+    N = P->tot[kPcaMaxC];
+    return N > 0.0 ? P->tot[lane] / N : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_pca_cov(LayerDev L, int HW, PcaParts* __restrict__ P)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double N;
-    const double mean = pca_mean(P, nblk, lane, N);
+    const double mean = pca_mean(P, lane, N);
     __shared__ double sd[4][64];
     double acc[kPcaMaxC];
 #pragma unroll
@@ -101,16 +118,23 @@ __global__ __launch_bounds__(256) void k_pca_cov(LayerDev L, int HW, PcaParts* _
         P->cov[blockIdx.x][e] = tile[e / kPcaMaxC][e % kPcaMaxC];
 }
 
+// 16 entries per workgroup, each summed by 16 lanes over every 16th partial
+// and the 16 sums added in lane order: a fixed order at any launch.
 __global__ __launch_bounds__(256) void k_pca_reduce(PcaParts* __restrict__ P, int nblk)
 {
-    const int e = blockIdx.x * 256 + threadIdx.x;
-    if (e >= kPcaMaxC * kPcaMaxC) return;
-    double N = 0.0, s = 0.0;
-    for (int b = 0; b < nblk; b++) {
-        s += P->cov[b][e];
-        N += P->sum[b][kPcaMaxC];
+    const int q = threadIdx.x & 15, part = threadIdx.x >> 4;
+    const int e = blockIdx.x * 16 + q;
+    double s = 0.0;
+    for (int b = part; b < nblk; b += 16) s += P->cov[b][e];
+    __shared__ double red[16][17];
+    red[part][q] = s;
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        double t = 0.0;
+        for (int k = 0; k < 16; k++) t += red[k][q];
+        const double N = P->tot[kPcaMaxC];
+        P->S[e] = N > 0.0 ? t / N : 0.0;
     }
-    P->S[e] = N > 0.0 ? s / N : 0.0;
 }
 
 // Jacobi eigensolver of the C x C covariance, one workgroup of 1024 lanes.
@@ -123,7 +147,7 @@ constexpr int kEigLanes = 1024;
 static_assert(kPcaMaxC == 64 && (kPcaMaxC / 2) * kPcaMaxC == 2 * kEigLanes, "two (pair, column) elements per lane");
 
 __global__ __launch_bounds__(kEigLanes) void k_pca_eig(const PcaParts* __restrict__ P, int C,
-                                                       PcaOut* __restrict__ out, int nblk)
+                                                       PcaOut* __restrict__ out)
 {
     constexpr int n = kPcaMaxC, half = kPcaMaxC / 2;
     __shared__ double S[n][n + 1];
@@ -139,7 +163,7 @@ __global__ __launch_bounds__(kEigLanes) void k_pca_eig(const PcaParts* __restric
     }
     if (t < kPcaMaxC) {
         double N;
-        out->mean[t] = t < C ? pca_mean(P, nblk, t, N) : 0.0;
+        out->mean[t] = t < C ? pca_mean(P, t, N) : 0.0;
         if (t == 0) out->n = N;
     }
     __syncthreads();
@@ -276,9 +300,10 @@ void launch_pca(hipStream_t s, const Grid& g, const LayerDev& L, void* scratch, 
     if (nblk > kPcaBlocks) nblk = kPcaBlocks;
     if (nblk < 1) nblk = 1;
     hipLaunchKernelGGL(k_pca_sum, dim3(nblk), dim3(256), 0, s, L, HW, P);
-    hipLaunchKernelGGL(k_pca_cov, dim3(nblk), dim3(256), 0, s, L, HW, P, nblk);
-    hipLaunchKernelGGL(k_pca_reduce, dim3((kPcaMaxC * kPcaMaxC + 255) / 256), dim3(256), 0, s, P, nblk);
-    hipLaunchKernelGGL(k_pca_eig, dim3(1), dim3(kEigLanes), 0, s, P, L.C, res, nblk);
+    hipLaunchKernelGGL(k_pca_total, dim3((kPcaMaxC + 1 + 15) / 16), dim3(256), 0, s, P, nblk);
+    hipLaunchKernelGGL(k_pca_cov, dim3(nblk), dim3(256), 0, s, L, HW, P);
+    hipLaunchKernelGGL(k_pca_reduce, dim3(kPcaMaxC * kPcaMaxC / 16), dim3(256), 0, s, P, nblk);
+    hipLaunchKernelGGL(k_pca_eig, dim3(1), dim3(kEigLanes), 0, s, P, L.C, res);
     hipLaunchKernelGGL(k_pca_project, dim3((HW + 255) / 256), dim3(256), 0, s, g, L, res, out);
 }
 

@@ -575,11 +575,18 @@ mem_status mem_pca(const mem_map* mc, int32_t layer, float* out, float eigenvalu
     if (mem_status st = resolve_layer(m, layer, &L)) return st;
     if (L->rule == MEM_DIRICHLET) return fail(MEM_E_ARG, "layer %d is a class layer, not a feature layer", layer);
     if (L->C > kPcaMaxC) return fail(MEM_E_UNSUPPORTED, "PCA of %d channels (at most %d)", L->C, kPcaMaxC);
-    if (!m->pca_scratch) {
+    if (!m->pca_scratch || !m->pca_out) {  // both or neither: a failed call leaves neither
         char* p = nullptr;
+        PcaOut* o = nullptr;
         if (mem_status st = dev_alloc(m, &p, pca_scratch_bytes())) return st;
+        if (mem_status st = dev_alloc(m, &o, 1)) {
+            (void)hipFree(p);
+            return st;
+        }
+        (void)hipFree(m->pca_scratch);
+        (void)hipFree(m->pca_out);
         m->pca_scratch = p;
-        if (mem_status st = dev_alloc(m, &m->pca_out, 1)) return st;
+        m->pca_out = o;
     }
     hipStream_t s = (hipStream_t)stream;
     timed(m, s, "pca", [&] { launch_pca(s, m->grid(), L->dev(), m->pca_scratch, m->pca_out, out); });
