@@ -594,7 +594,8 @@ def make_map():
 
 def kernel_bytes(name, st, launches):
     """Algorithmic HBM bytes of a kernel over the timed region, from the
-    per-call counters (units and per-unit bytes as documented in the design doc)."""
+    per-call counters: for each kernel its unit (input point, cell, visible
+    pair) times the algorithmic bytes of one unit."""
     cells = 500 * 500
     if name == "ingest":       # 12 B per input point; 12 B of sums per touched cell
         return 12 * st["points_in"] + 12 * st["cells_touched"]
