@@ -98,3 +98,16 @@ def test_normals_reject_a_wrong_output():
     g = mem.Map(mem.MapParams(8, 8, 0.05))
     with pytest.raises(ValueError):
         g.normals(out=torch.empty((8, 8, 2), dtype=torch.float32, device="cuda"))
+
+
+def test_normals_into_an_unaligned_output():
+    """An output that starts 4 bytes into an allocation gives the same
+    normals as an aligned one."""
+    rng = np.random.default_rng(7)
+    g, o = pair_with_heights(128, 36, 0.05, [(0.3, 0.2)], rng)
+    a = g.normals()
+    buf = torch.empty(128 * 36 * 3 + 1, dtype=torch.float32, device="cuda")
+    b = g.normals(out=buf[1:].view(36, 128, 3))
+    torch.cuda.synchronize()
+    assert torch.equal(torch.nan_to_num(a, nan=7.0), torch.nan_to_num(b, nan=7.0))
+    check_normals(g, o)
