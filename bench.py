@@ -580,9 +580,10 @@ def run_frame(m, f):
     m.move(x, y)
     for c in f["clouds"]:
         m.input_pointcloud(c["xyz"], c["T"])
-    for c in f["cameras"]:  # RGB, features and classes share the camera pose
-        m.input_images([(c["rgb"], c["K"], [(8, 0, 3)]), (c["features"], c["K_feat"], [(9, 0, 64)]),
-                        (c["classes"], c["K"], [(10, 0, 20)])], c["T"])
+    # the four camera poses of a frame in one call (RGB, features and classes
+    # share each pose)
+    m.input_image_poses([([(c["rgb"], c["K"], [(8, 0, 3)]), (c["features"], c["K_feat"], [(9, 0, 64)]),
+                           (c["classes"], c["K"], [(10, 0, 20)])], c["T"]) for c in f["cameras"]])
 
 
 def make_map():
@@ -606,8 +607,8 @@ def kernel_bytes(name, st, launches):
     if name == "gather_fuse":  # pixel + state RMW per visible pair, per layer
         per_pair = (3 + 2 * 3 * 4) + (64 * 4 + 2 * 64 * 4 + 8) + (20 * 4 + 2 * 20 * 4)
         return per_pair * st["pairs_visible"] // 3 + 8 * st["pairs_visible"]
-    if name == "project":      # h per cell
-        return 4 * cells * launches
+    if name == "project":      # h per cell and camera pose (four poses per launch)
+        return 4 * cells * 4 * launches
     if name == "clear_march":  # xyz re-read
         return 12 * st["points_in"]
     return 0

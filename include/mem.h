@@ -257,6 +257,18 @@ typedef struct mem_image {
 mem_status mem_input_images(mem_map* map, const mem_image* images, int32_t n_images,
                             const float T_map_cam[12], void* stream);
 
+/* Images of up to 4 camera poses (e.g. the cameras around a robot taken at
+ * one instant): n_images[p] images of pose p (1..4), consecutive in
+ * `images`, and T_map_cam the n_poses x 12 host array of their poses.  The
+ * result equals calling mem_input_images for each pose in order: fusing
+ * images does not change heights, so every pose's frustum test, pixel and
+ * occlusion walk are evaluated together, and the channels are then fused
+ * pose by pose, image by image.  The first call with more than one pose
+ * allocates the lists of 4 poses (about 32 bytes per cell and image slot).
+ * Errors as mem_input_images, checked for every pose before any work. */
+mem_status mem_input_image_poses(mem_map* map, const mem_image* images, const int32_t* n_images,
+                                 int32_t n_poses, const float* T_map_cam, void* stream);
+
 /* Writes a layer view to `out` (device, H x W x C float, C = 1 for the
  * built-in layers and for MEM_VIEW_ARGMAX).  See the view enum. */
 mem_status mem_get_layer(const mem_map* map, int32_t layer, int32_t view,

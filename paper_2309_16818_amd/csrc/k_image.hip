@@ -27,14 +27,21 @@ constexpr int kTile = 16;
 // per cell; cells inside at least one view are appended to vlist
 // (st, ix, iy, intermediate cells of the occlusion line) and their codes to
 // vcode[k * cap + position].
-__global__ __launch_bounds__(256) void k_view(Grid g, Camera cam, const float* __restrict__ h,
+__global__ __launch_bounds__(256) void k_view(Grid g, CameraSet cs, const float* __restrict__ h,
                                               int4* __restrict__ vlist, int* __restrict__ vcode, int cap,
                                               int* __restrict__ vcount, int* __restrict__ vcount_next,
                                               int32_t* __restrict__ dbg,
                                               unsigned long long* __restrict__ stats)
 {
+    // one pose per grid layer z: its list, codes and counter
+    const int pose = blockIdx.z;
+    const Camera& cam = cs.c[pose];
+    vlist += (int64_t)pose * cap;
+    vcode += (int64_t)pose * kMaxImages * cap;
+    vcount += pose;
     // the next projection's counter (this one's was cleared by the last)
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && threadIdx.y == 0) *vcount_next = 0;
+    if (vcount_next && blockIdx.x == 0 && blockIdx.y == 0 && pose == 0 && threadIdx.x == 0 && threadIdx.y == 0)
+        *vcount_next = 0;
     const int ix = blockIdx.x * kTile + threadIdx.x;
     const int iy = blockIdx.y * kTile + threadIdx.y;
     int code[kMaxImages];
@@ -85,14 +92,19 @@ __global__ __launch_bounds__(256) void k_view(Grid g, Camera cam, const float* _
 constexpr int kOccLanes = 16;
 static_assert(kOccLanes < 64 && 64 % kOccLanes == 0, "groups of lanes within one wave (mask of kOccLanes bits)");
 
-__global__ __launch_bounds__(256) void k_occlude(Grid g, Camera cam, const float* __restrict__ h, TileMax tm,
+__global__ __launch_bounds__(256) void k_occlude(Grid g, CameraSet cs, const float* __restrict__ h, TileMax tm,
                                                  const int4* __restrict__ vlist,
                                                  int* __restrict__ vcode, int cap,
                                                  const int* __restrict__ vcount,
                                                  int32_t* __restrict__ dbg,
                                                  unsigned long long* __restrict__ stats)
 {
-    const int N = *vcount;
+    // one pose per grid row y
+    const int pose = blockIdx.y;
+    const Camera& cam = cs.c[pose];
+    vlist += (int64_t)pose * cap;
+    vcode += (int64_t)pose * kMaxImages * cap;
+    const int N = vcount[pose];
     const int lane = __lane_id();
     const int sub = lane % kOccLanes;        // lane within the cell's group
     const int grp = lane / kOccLanes;        // group within the wave
@@ -191,18 +203,19 @@ void launch_zero_int(hipStream_t s, int* p, int n)
     hipLaunchKernelGGL(k_zero_int, dim3((n + 63) / 64), dim3(64), 0, s, p, n);
 }
 
-void launch_project(hipStream_t s, const Grid& g, const Camera& cam, const float* h, const TileMax& tm, int cap,
+void launch_project(hipStream_t s, const Grid& g, const CameraSet& cs, const float* h, const TileMax& tm, int cap,
                     int* vcount, int* vcount_next, int4* vlist, int* vcode, int32_t* dbg,
                     unsigned long long* stats)
 {
-    dim3 grid((g.W + kTile - 1) / kTile, (g.H + kTile - 1) / kTile);
-    hipLaunchKernelGGL(k_view, grid, dim3(kTile, kTile), 0, s, g, cam, h, vlist, vcode, cap, vcount, vcount_next,
-                       dbg, stats);
+    dim3 grid((g.W + kTile - 1) / kTile, (g.H + kTile - 1) / kTile, (unsigned)cs.n);
+    int32_t* d = cs.n == 1 ? dbg : nullptr;
+    hipLaunchKernelGGL(k_view, grid, dim3(kTile, kTile), 0, s, g, cs, h, vlist, vcode, cap, vcount, vcount_next,
+                       d, stats);
     int64_t blocks = ((int64_t)cap * kOccLanes + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_occlude, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, h, tm, vlist, vcode, cap,
-                       vcount, dbg, stats);
+    hipLaunchKernelGGL(k_occlude, dim3((unsigned)blocks, (unsigned)cs.n), dim3(256), 0, s, g, cs, h, tm, vlist, vcode,
+                       cap, vcount, d, stats);
 }
 
 void launch_gather_fuse(hipStream_t s, const int4* vlist, const int* vcode, const int* count, int max_pairs,

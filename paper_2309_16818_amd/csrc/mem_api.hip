@@ -95,6 +95,9 @@ struct mem_map {
     float* wsum = nullptr;
     float* ssum = nullptr;
     float2* stash = nullptr;
+    int4* vlist_poses = nullptr; // lists, codes and counters of several poses (first use)
+    int* vcode_poses = nullptr;
+    int* vcount_poses = nullptr;
     int* vcount = nullptr;      // cells listed in vlist: two counters used by turns (vpar)
     int vpar = 0;               // the counter the next projection uses; its k_view clears the other
     bool tmax_stale = true;     // the heights changed since the block maxima were built
@@ -262,6 +265,9 @@ void free_map(mem_map* m)
     (void)hipFree(m->n_long);
     (void)hipFree(m->drift);
     (void)hipFree(m->drift_part);
+    (void)hipFree(m->vlist_poses);
+    (void)hipFree(m->vcode_poses);
+    (void)hipFree(m->vcount_poses);
     (void)hipFree(m->pca_scratch);
     (void)hipFree(m->pca_out);
     (void)hipFree(m->vlist);
@@ -663,43 +669,102 @@ static mem_status check_image(const mem_map* m, const mem_image& im, int k, Came
     return MEM_OK;
 }
 
-mem_status mem_input_images(mem_map* m, const mem_image* images, int32_t n_images,
-                            const float T_map_cam[12], void* stream)
+// Images of n_poses camera poses (counts[p] images of pose p, consecutive
+// in `images`).  The poses' projections are independent of each other (no
+// image changes a height), so they run as one view launch and one
+// occlusion launch; the gathers then follow in call order.
+static mem_status input_poses(mem_map* m, const mem_image* images, const int32_t* counts, int n_poses,
+                              const float* T_map_cam, void* stream)
 {
     if (mem_status st = usable(m)) return st;
-    if (n_images < 1 || n_images > kMaxImages || !images)
-        return fail(MEM_E_ARG, "n_images must be 1..%d with an image array", kMaxImages);
-    Camera cam{};
-    if (mem_status st = check_pose(m, T_map_cam, "T_map_cam")) return st;
-    memcpy(cam.T.m, T_map_cam, sizeof(cam.T.m));
-    cam.n = n_images;
-    cam.min_depth = m->min_depth;
-    for (int k = 0; k < n_images; k++)
-        if (mem_status st = check_image(m, images[k], k, &cam)) return st;
+    if (n_poses < 1 || n_poses > kMaxPoses || !counts || !T_map_cam)
+        return fail(MEM_E_ARG, "n_poses must be 1..%d with counts and poses", kMaxPoses);
+    if (!images) return fail(MEM_E_ARG, "images is NULL");
+    CameraSet cs{};
+    cs.n = n_poses;
+    int first = 0;
+    for (int p = 0; p < n_poses; p++) {
+        if (counts[p] < 1 || counts[p] > kMaxImages)
+            return fail(MEM_E_ARG, "pose %d: n_images must be 1..%d", p, kMaxImages);
+        Camera& cam = cs.c[p];
+        if (mem_status st = check_pose(m, T_map_cam + 12 * p, "T_map_cam")) return st;
+        memcpy(cam.T.m, T_map_cam + 12 * p, sizeof(cam.T.m));
+        cam.n = counts[p];
+        cam.min_depth = m->min_depth;
+        for (int k = 0; k < counts[p]; k++)
+            if (mem_status st = check_image(m, images[first + k], k, &cam)) return st;
+        first += counts[p];
+    }
     hipStream_t s = (hipStream_t)stream;
     Grid g = m->grid();
     const int cap = (int)m->cells();
+    int4* vlist = m->vlist;
+    int* vcode = m->vcode;
+    int* vc = nullptr;
+    int* vc_next = nullptr;
+    if (n_poses == 1) {
+        vc = m->take_vcount();
+        vc_next = m->vcount + m->vpar;
+    } else {
+        if (!m->vlist_poses) {  // lists of kMaxPoses poses, allocated on first use
+            int4* l = nullptr;
+            int* c = nullptr;
+            int* n = nullptr;
+            if (mem_status st = dev_alloc(m, &l, (size_t)kMaxPoses * cap)) return st;
+            if (mem_status st = dev_alloc(m, &c, (size_t)kMaxPoses * kMaxImages * cap)) {
+                (void)hipFree(l);
+                return st;
+            }
+            if (mem_status st = dev_alloc(m, &n, kMaxPoses)) {
+                (void)hipFree(l);
+                (void)hipFree(c);
+                return st;
+            }
+            m->vlist_poses = l;
+            m->vcode_poses = c;
+            m->vcount_poses = n;
+        }
+        vlist = m->vlist_poses;
+        vcode = m->vcode_poses;
+        vc = m->vcount_poses;
+        launch_zero_int(s, vc, n_poses);
+    }
     TileMax tm;
     timed(m, s, "tile_max", [&] { tm = m->tiles(s); });
-    int* vc = m->take_vcount();
-    int* vc_next = m->vcount + m->vpar;
-    timed(m, s, "project", [&] {
-        launch_project(s, g, cam, m->h, tm, cap, vc, vc_next, m->vlist, m->vcode, nullptr, m->stats);
-    });
-    for (int k = 0; k < n_images; k++) {
-        const mem_image& im = images[k];
-        for (int b = 0; b < im.n_bind; b++) {
-            const Layer* L = nullptr;
-            resolve_layer(m, im.bind[b].layer, &L);
-            LayerDev d = L->dev();
-            timed(m, s, "gather_fuse", [&] {
-                launch_gather_fuse(s, m->vlist, m->vcode + (int64_t)k * cap, vc, cap, im.data,
-                                   im.dtype, im.strides[0], im.strides[1], im.strides[2], im.w,
-                                   im.bind[b].ch_first, d, im.bind[b].topk);
-            });
+    timed(m, s, "project", [&] { launch_project(s, g, cs, m->h, tm, cap, vc, vc_next, vlist, vcode, nullptr, m->stats); });
+    first = 0;
+    for (int p = 0; p < n_poses; p++) {
+        for (int k = 0; k < counts[p]; k++) {
+            const mem_image& im = images[first + k];
+            for (int b = 0; b < im.n_bind; b++) {
+                const Layer* L = nullptr;
+                resolve_layer(m, im.bind[b].layer, &L);
+                LayerDev d = L->dev();
+                timed(m, s, "gather_fuse", [&] {
+                    launch_gather_fuse(s, vlist + (int64_t)p * cap,
+                                       vcode + ((int64_t)p * kMaxImages + k) * cap, vc + p, cap, im.data,
+                                       im.dtype, im.strides[0], im.strides[1], im.strides[2], im.w,
+                                       im.bind[b].ch_first, d, im.bind[b].topk);
+                });
+            }
         }
+        first += counts[p];
     }
     return check_launch(m, "mem_input_images");
+}
+
+mem_status mem_input_images(mem_map* m, const mem_image* images, int32_t n_images,
+                            const float T_map_cam[12], void* stream)
+{
+    if (!images || n_images < 1 || n_images > kMaxImages)
+        return fail(MEM_E_ARG, "n_images must be 1..%d with an image array", kMaxImages);
+    return input_poses(m, images, &n_images, 1, T_map_cam, stream);
+}
+
+mem_status mem_input_image_poses(mem_map* m, const mem_image* images, const int32_t* n_images,
+                                 int32_t n_poses, const float* T_map_cam, void* stream)
+{
+    return input_poses(m, images, n_images, n_poses, T_map_cam, stream);
 }
 
 mem_status mem_input_image(mem_map* m, const void* img, int32_t dtype, int32_t h, int32_t w, int32_t c,
@@ -804,10 +869,13 @@ mem_status mem_debug_cell_pixels(const mem_map* mc, int32_t h, int32_t w, const 
     memcpy(cam.T.m, T, sizeof(cam.T.m));
     cam.n = 1;
     cam.min_depth = m->min_depth;
+    CameraSet cs{};
+    cs.c[0] = cam;
+    cs.n = 1;
     hipStream_t s = (hipStream_t)stream;
     const TileMax tm = m->tiles(s);
     int* vc = m->take_vcount();
-    launch_project(s, m->grid(), cam, m->h, tm, (int)m->cells(), vc, m->vcount + m->vpar, m->vlist, m->vcode, out,
+    launch_project(s, m->grid(), cs, m->h, tm, (int)m->cells(), vc, m->vcount + m->vpar, m->vlist, m->vcode, out,
                    m->stats);
     return check_launch(m, "mem_debug_cell_pixels");
 }

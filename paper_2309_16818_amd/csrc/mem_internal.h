@@ -118,6 +118,14 @@ struct Camera {
     float min_depth;
 };
 
+// Camera poses projected by one launch: their lists, pixel codes and
+// counters lie at pose * cap, pose * kMaxImages * cap and pose.
+constexpr int kMaxPoses = 4;
+struct CameraSet {
+    Camera c[kMaxPoses];
+    int n;
+};
+
 // ---- launchers (implemented in the .hip files) ----
 // `zero1`, if not null, is one int cleared as well (the long-ray counter of
 // the clearing march).
@@ -164,9 +172,10 @@ void launch_tile_max(hipStream_t s, const Grid& g, const float* h, float* t8, fl
 // (st, ix, iy, intermediate cells of the occlusion line; *vcount entries, at
 // most cap) with their pixel codes in vcode[k * cap + position] (-1 outside
 // image k), k_occlude overwrites the codes of occluded cells with -1.
-// *vcount must be zero on entry; k_view clears *vcount_next (a different
-// counter, the next projection's) so that no separate clear is launched.
-void launch_project(hipStream_t s, const Grid& g, const Camera& cam, const float* h, const TileMax& tm, int cap,
+// Every pose's counter must be zero on entry; k_view clears *vcount_next (a
+// different counter, the next projection's; may be null) so that no
+// separate clear is launched.  dbg is written for a single pose only.
+void launch_project(hipStream_t s, const Grid& g, const CameraSet& cs, const float* h, const TileMax& tm, int cap,
                     int* vcount, int* vcount_next, int4* vlist, int* vcode, int32_t* dbg,
                     unsigned long long* stats);
 // Fuses image channels into layer L for the listed cells whose code (image's

@@ -30,7 +30,7 @@ STAT_FIELDS = ("points_in", "points_accepted", "dropped_nonfinite", "dropped_ran
 # Exported symbols of include/mem.h.
 SYMBOLS = ("mem_create", "mem_destroy", "mem_move", "mem_input_pointcloud", "mem_input_image",
            "mem_input_images", "mem_get_layer", "mem_set_layer", "mem_normals", "mem_set_drift_compensation", "mem_get_drift",
-           "mem_set_overlap_clearance", "mem_pca",
+           "mem_set_overlap_clearance", "mem_pca", "mem_input_image_poses",
            "mem_get_center", "mem_debug_point_cells",
            "mem_debug_cell_pixels", "mem_get_stats", "mem_reset_stats", "mem_profile_enable",
            "mem_profile_read", "mem_last_error")
@@ -92,6 +92,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "mem_input_pointcloud": [P, P, I64, P, I32, C.POINTER(mem_binding), I32, P, P],
         "mem_input_image": [P, P, I32, I32, I32, I32, P, P, P, C.POINTER(mem_binding), I32, P],
         "mem_input_images": [P, C.POINTER(mem_image), I32, P, P],
+        "mem_input_image_poses": [P, C.POINTER(mem_image), C.POINTER(I32), I32, P, P],
         "mem_get_layer": [P, I32, I32, P, P],
         "mem_set_layer": [P, I32, I32, P, P],
         "mem_normals": [P, P, P],
@@ -260,6 +261,27 @@ class Map:
             arr[k] = mem_image(_dev_ptr(img, "img"), MEM_U8 if img.dtype == torch.uint8 else MEM_F32,
                                h, w, c, (C.c_int64 * 3)(*img.stride()), _floats(K, 4), b, nb)
         _check(load().mem_input_images(self._h, arr, len(images), _pose(T), _stream(stream)))
+
+    def input_image_poses(self, poses, stream=None):
+        """poses: sequence of (images, T), images as for input_images; equals
+        input_images for each pose in order."""
+        flat = [im for images, _ in poses for im in images]
+        arr = (mem_image * max(1, len(flat)))()
+        keep = []
+        for k, (img, K, bind) in enumerate(flat):
+            if img.dim() != 3 or img.dtype not in (torch.uint8, torch.float32):
+                raise ValueError("images must be uint8 or float32 [h, w, c] tensors")
+            b, nb = _bindings(bind)
+            keep.append(b)
+            h, w, c = img.shape
+            arr[k] = mem_image(_dev_ptr(img, "img"), MEM_U8 if img.dtype == torch.uint8 else MEM_F32,
+                               h, w, c, (C.c_int64 * 3)(*img.stride()), _floats(K, 4), b, nb)
+        counts = (C.c_int32 * max(1, len(poses)))(*[len(images) for images, _ in poses])
+        Ts = (C.c_float * (12 * max(1, len(poses))))()
+        for p, (_, T) in enumerate(poses):
+            for q, v in enumerate(_pose(T)):
+                Ts[12 * p + q] = v
+        _check(load().mem_input_image_poses(self._h, arr, counts, len(poses), Ts, _stream(stream)))
 
     # -- read-out -------------------------------------------------------------
     def channels(self, layer: int, view: int = MEM_VIEW_VALUE) -> int:
