@@ -881,30 +881,34 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(frames):
+def cpu_baseline(frames, min_seconds=10.0, max_passes=4):
     """The oracle (plain C, one thread) on the first frames of the same
-    workload, from an empty map."""
+    workload, from an empty map, passed over again (the map keeps its
+    state, as a robot driving the loop twice would) until at least
+    `min_seconds` of CPU work are timed or `max_passes` passes are done."""
     import oracle as O
     from paper_2309_16818_amd import synth
     p = dict(synth.FULL_MAP)
     o = O.OracleMap(p.pop("width"), p.pop("height"), p.pop("resolution"), layers=synth.FULL_LAYERS, **p)
     acc = 0
+    passes = 0
     t0 = time.perf_counter()
-    for f in frames:
-        x, y, _ = f["pose"]
-        o.move(x, y)
-        for c in f["clouds"]:
-            cells = o.input_pointcloud(c["xyz"], c["T"])
-            acc += int((cells >= 0).sum())
-        for c in f["cameras"]:
-            o.input_image(c["rgb"], c["K"], c["T"], bind=[(8, 0, 3)])
-            o.input_image(c["features"], c["K_feat"], c["T"], bind=[(9, 0, 64)])
-            o.input_image(c["classes"], c["K"], c["T"], bind=[(10, 0, 20)])
+    while passes < max_passes and (passes == 0 or time.perf_counter() - t0 < min_seconds):
+        for f in frames:
+            x, y, _ = f["pose"]
+            o.move(x, y)
+            for c in f["clouds"]:
+                cells = o.input_pointcloud(c["xyz"], c["T"])
+                acc += int((cells >= 0).sum())
+            for c in f["cameras"]:
+                o.input_image(c["rgb"], c["K"], c["T"], bind=[(8, 0, 3)])
+                o.input_image(c["features"], c["K_feat"], c["T"], bind=[(9, 0, 64)])
+                o.input_image(c["classes"], c["K"], c["T"], bind=[(10, 0, 20)])
+        passes += 1
     dt = time.perf_counter() - t0
     return {"value": round(acc / dt, 1), "unit": "points/s", "cores": 1, "kind": "oracle",
-            "sample": f"{len(frames)} frame(s) of the same workload from an empty map "
+            "sample": f"{passes} pass(es) over {len(frames)} frame(s) of the same workload from an empty map "
                       f"({acc} accepted points, {dt:.1f} s)"}
-
 
 if __name__ == "__main__":
     main()
