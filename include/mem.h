@@ -134,7 +134,7 @@ typedef struct mem_params {
  *     and zero elsewhere (a class listed twice adds both).  A listed index
  *     that is not an integer in [0, K) (or is NaN) contributes nothing.
  *     u8 images carry the index as the byte itself, the probability as
- *     byte / 255.  Batches (mem_batch_create) accept only topk = 0. */
+ *     byte / 255.  Batches take top-k image bindings the same way. */
 typedef struct mem_binding {
     int32_t layer;    /* MEM_LAYER_USER0 + k */
     int32_t ch_first;

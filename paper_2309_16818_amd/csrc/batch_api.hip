@@ -462,10 +462,15 @@ mem_status mem_batch_create(const mem_batch_params* p, void* stream, mem_batch**
             return api_fail(MEM_E_ARG, "n_img_bind must be 0..4 with a binding array");
         for (int k = 0; k < p->n_img_bind; k++) {
             const mem_binding& bd = p->img_bind[k];
-            if (bd.topk != 0) return api_fail(MEM_E_UNSUPPORTED, "image binding %d: batches take dense class inputs only", k);
             const int l = bd.layer - MEM_LAYER_USER0;
-            if (l < 0 || l >= p->n_layers || bd.ch_first < 0 || bd.ch_count != p->layers[l].channels ||
-                bd.ch_first + bd.ch_count > p->cam_c)
+            if (l < 0 || l >= p->n_layers || bd.ch_first < 0 || bd.topk < 0 || bd.topk > kMaxTopk)
+                return api_fail(MEM_E_ARG, "image binding %d does not fit", k);
+            // dense: the layer's C channels; top-k: 2k inputs into a
+            // Dirichlet layer of at least k classes
+            const int want = bd.topk > 0 ? 2 * bd.topk : p->layers[l].channels;
+            if (bd.topk > 0 && (p->layers[l].rule != MEM_DIRICHLET || bd.topk > p->layers[l].channels))
+                return api_fail(MEM_E_ARG, "image binding %d: top-k needs a Dirichlet layer of >= k classes", k);
+            if (bd.ch_count != want || (int64_t)bd.ch_first + bd.ch_count > p->cam_c)
                 return api_fail(MEM_E_ARG, "image binding %d does not fit", k);
         }
     }

@@ -397,7 +397,7 @@ template <int IMG, int S>
 __global__ __launch_bounds__(kBatchWG) void k_b_gather(BatchDev d, int queue,
                                                        const void* __restrict__ images, int cam_c,
                                                        int cam_w, int ch_first, LayerDev L,
-                                                       int lpp_log2)
+                                                       int lpp_log2, int topk)
 {
     __shared__ int s_item;
     const int lane = threadIdx.x & 63;
@@ -416,9 +416,13 @@ __global__ __launch_bounds__(kBatchWG) void k_b_gather(BatchDev d, int queue,
         const int end = I.a + kGatherItem < N ? I.a + kGatherItem : N;
         const char* img = (const char*)images + m.img_off * esz;
         const int2* pairs = d.pairs + m.cell_off;
-        for (int p = I.a + wave * ppw + sub; p < end; p += nw * ppw)
-            gather_pair<IMG, S>(pairs[p], img, (int64_t)cam_w * cam_c, cam_c, 1, cam_w, ch_first, L,
-                                q0, LPP);
+        for (int p = I.a + wave * ppw + sub; p < end; p += nw * ppw) {
+            if (topk > 0)  // top-k class input: one lane per pair (lpp_log2 = 0)
+                gather_topk<IMG>(pairs[p], img, (int64_t)cam_w * cam_c, cam_c, 1, cam_w, ch_first, L, topk);
+            else
+                gather_pair<IMG, S>(pairs[p], img, (int64_t)cam_w * cam_c, cam_c, 1, cam_w, ch_first, L,
+                                    q0, LPP);
+        }
     }
 }
 
@@ -471,11 +475,11 @@ void launch_batch_step(hipStream_t s, const BatchDev& d, const BatchLaunch& bl, 
     for (int b = 0; b < n_ib; b++) {
         const LayerDev& Lb = L[ib[b].layer - MEM_LAYER_USER0];
         int lpp_log2 = 0;
-        while ((1 << lpp_log2) < Lb.C && lpp_log2 < 6) lpp_log2++;
+        while (ib[b].topk == 0 && (1 << lpp_log2) < Lb.C && lpp_log2 < 6) lpp_log2++;
         // one gather pass per binding, each with its own queue (4 + b)
 #define MEM_BG(IMG, S)                                                                            \
     hipLaunchKernelGGL((k_b_gather<IMG, S>), dim3(bl.grid), dim3(kBatchWG), 0, s, d, 4 + b, images, \
-                       cam_c, cam_w, ib[b].ch_first, Lb, lpp_log2)
+                       cam_c, cam_w, ib[b].ch_first, Lb, lpp_log2, ib[b].topk)
         if (img_dtype == MEM_U8) {
             if (Lb.storage == MEM_BF16) MEM_BG(MEM_U8, MEM_BF16);
             else if (Lb.storage == MEM_FP8_E4M3) MEM_BG(MEM_U8, MEM_FP8_E4M3);

@@ -171,7 +171,44 @@ def test_topk_bindings_are_checked():
     img = torch.zeros((8, 8, 6), device="cuda")
     with pytest.raises(mem.MemError):
         g.input_image(img, (8.0, 8.0, 3.5, 3.5), ID, bind=[(9, 0, 6, 3)])
-    with pytest.raises(mem.MemError) as e:
+    with pytest.raises(mem.MemError) as e:  # a batch checks its bindings the same way
         mem.Batch([16], [16], 0.1, layers=[mem.Layer(5, mem.MEM_DIRICHLET, 1.0)], max_points=16,
-                  cam=(8, 8, 6, mem.MEM_F32), img_bind=[(8, 0, 6, 3)])
-    assert e.value.code == mem.MEM_E_UNSUPPORTED
+                  cam=(8, 8, 6, mem.MEM_F32), img_bind=[(8, 0, 6, 2)])
+    assert e.value.code == mem.MEM_E_ARG
+
+
+def test_topk_in_a_batch_matches_the_oracle():
+    """A batch of maps of different sizes whose camera image carries top-3
+    class pairs beside three dense feature channels: every map in lockstep
+    with its oracle over moves, clouds and images."""
+    from test_batch import MapView, step_inputs, walk
+    rng = np.random.default_rng(140)
+    sizes = [(24, 24), (40, 33), (17, 50), (64, 64)]
+    K, k, res = 12, 3, 0.05
+    H, W = 48, 64
+    layers = [(K, mem.MEM_DIRICHLET, 1.0), (3, mem.MEM_EXPAVG, 0.5)]
+    bind = [(8, 0, 2 * k, k), (9, 2 * k, 3)]
+    B = mem.Batch([w for w, _ in sizes], [h for _, h in sizes], res, layers=layers, max_points=100000,
+                  cam=(H, W, 2 * k + 3, mem.MEM_F32), img_bind=bind)
+    orcs = [O.OracleMap(w, h, res, max_range=100.0, layers=[l[:3] for l in layers]) for w, h in sizes]
+    views = [MapView(B, m) for m in range(len(sizes))]
+    poses = [(rng.uniform(-1, 1), rng.uniform(-1, 1), rng.uniform(0, 6)) for _ in sizes]
+    for it in range(3):
+        poses = walk(rng, poses)
+        counts = [int(c) for c in rng.integers(500, 3000, len(sizes))]
+        xyz, offs, Ts, Tc, Ks, _ = step_inputs(rng, sizes, poses, counts)
+        imgs = []
+        for _ in sizes:
+            idx, p = topk_of(synth.class_image(rng, H, W, K), k)
+            imgs.append(np.concatenate([spoil(rng, idx, K), p, rng.uniform(0, 1, (H, W, 3)).astype(np.float32)], -1))
+        imgs = np.stack(imgs).astype(np.float32)
+        for v, o in zip(views, orcs):
+            sync_from_oracle(v, o)
+        B.step(np.array([q[:2] for q in poses], np.float32), to_dev(xyz.reshape(-1, 3)), offs, Ts,
+               images=to_dev(imgs), K=Ks, T_cam=Tc)
+        for m, (v, o) in enumerate(zip(views, orcs)):
+            o.move(*poses[m][:2])
+            o.input_pointcloud(xyz[offs[m]:offs[m + 1]], Ts[m])
+            o.input_image(imgs[m], Ks[m], Tc[m], bind=bind)
+            compare(v, o, counts=True, what=f"batch top-k step {it} map {m}")
+    assert B.stats()["pairs_visible"] > 0
