@@ -111,3 +111,37 @@ def test_normals_into_an_unaligned_output():
     torch.cuda.synchronize()
     assert torch.equal(torch.nan_to_num(a, nan=7.0), torch.nan_to_num(b, nan=7.0))
     check_normals(g, o)
+
+
+def test_normals_on_a_large_grid_at_sampled_windows():
+    """An 8192 x 8192 map (67M cells, moved so that its storage wraps):
+    normals depend only on a cell's 4-neighbours, so the oracle run on a
+    window of the heights with a one-cell margin gives the exact expected
+    normals of the window's interior; eight windows, two on the border."""
+    S, res = 8192, 0.04
+    rng = np.random.default_rng(8192)
+    g = mem.Map(mem.MapParams(S, S, res, clear_min_count=0))
+    g.move(37.3, -21.9)
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    h = torch.randn((S, S), device="cuda", generator=gen) * 0.2
+    h[torch.rand((S, S), device="cuda", generator=gen) < 0.03] = float("nan")
+    g.set_layer(mem.MEM_LAYER_ELEVATION, 0, h)
+    n = g.normals()
+    torch.cuda.synchronize()
+    wins = [(0, 0), (S - 64, S - 64)] + [tuple(rng.integers(1, S - 65, 2)) for _ in range(6)]
+    for y0, x0 in wins:
+        # window [y0 - 1, y0 + 65) x [x0 - 1, x0 + 65), clipped to the grid
+        ya, yb, xa, xb = max(y0 - 1, 0), min(y0 + 65, S), max(x0 - 1, 0), min(x0 + 65, S)
+        hw = h[ya:yb, xa:xb].double().cpu().numpy()
+        o = O.OracleMap(xb - xa, yb - ya, res)
+        o.set_layer(O.LAYER_ELEVATION, 0, hw)
+        want = o.normals()
+        got = n[ya:yb, xa:xb].double().cpu().numpy()
+        # interior of the window: cells whose 4-neighbours lie in the window,
+        # and grid border cells where the window reaches the border
+        iy = slice(1 if ya > 0 or y0 > 0 else 0, (yb - ya) - (1 if yb < S else 0))
+        ix = slice(1 if xa > 0 or x0 > 0 else 0, (xb - xa) - (1 if xb < S else 0))
+        a, b = got[iy, ix], want[iy, ix]
+        assert np.array_equal(np.isnan(a), np.isnan(b)), (y0, x0)
+        ok = ~np.isnan(b)
+        assert np.abs(a[ok] - b[ok]).max(initial=0.0) <= N_TOL, (y0, x0)
