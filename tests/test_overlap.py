@@ -93,3 +93,34 @@ def test_overlap_arguments_are_checked_and_off_by_default():
         assert e.value.code == mem.MEM_E_ARG
     g.set_overlap_clearance(False, -1.0, -1.0)  # disabling takes no ranges
     torch.cuda.synchronize()
+
+
+def test_overlap_on_the_full_grid():
+    """The full workload's grid (500 x 500 at 0.04 m) with the ranges the
+    bench uses (4 m around the sensor, 2 m above and below): a level 3 m up
+    over the half of the grid right of the sensor, a cloud on the floor of
+    the left half."""
+    rng = np.random.default_rng(73)
+    W, res = 500, 0.04
+    g, o = make_pair(W, W, res, clear_min_count=2, max_range=20.0)
+    g.move(1.3, -0.7)
+    o.move(1.3, -0.7)
+    h = rng.normal(0, 0.05, (W, W))
+    h[:, W // 2:] += 3.0  # x >= 1.3 m: the sensor's column onwards
+    h[rng.uniform(size=h.shape) < 0.05] = np.nan
+    o.set_layer(O.LAYER_ELEVATION, 0, h)
+    o.set_layer(O.LAYER_VARIANCE, 0, rng.uniform(1e-4, 1e-3, (W, W)))
+    sync_from_oracle(g, o)
+    g.set_overlap_clearance(True, 4.0, 2.0)
+    o.set_overlap(True, 4.0, 2.0)
+    s = (1.3, -0.7, 0.6)
+    n = 200000
+    xy = np.stack([rng.uniform(-4.5, -0.1, n), rng.uniform(-4.5, 4.5, n)], 1) + np.array(s[:2])
+    z = rng.normal(0, 0.03, n)
+    cl = (np.concatenate([xy, z[:, None]], 1) - np.array(s)).astype(np.float32)
+    before = ~np.isnan(o.get_layer(O.LAYER_ELEVATION))
+    g.input_pointcloud(to_dev(cl), pose(s))
+    o.input_pointcloud(cl, pose(s))
+    compare(g, o, what="overlap on the full grid")
+    after = ~np.isnan(o.get_layer(O.LAYER_ELEVATION))
+    assert (before & ~after).sum() > 1000
