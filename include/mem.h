@@ -264,7 +264,8 @@ mem_status mem_input_images(mem_map* map, const mem_image* images, int32_t n_ima
  * images does not change heights, so every pose's frustum test, pixel and
  * occlusion walk are evaluated together, and the channels are then fused
  * pose by pose, image by image.  The first call with more than one pose
- * allocates the lists of 4 poses (about 32 bytes per cell and image slot).
+ * allocates the lists of 4 poses: 128 bytes per cell (an in-view entry of
+ * 16 bytes and 4 pixel codes of 4 bytes per pose), kept until destroy.
  * Errors as mem_input_images, checked for every pose before any work. */
 mem_status mem_input_image_poses(mem_map* map, const mem_image* images, const int32_t* n_images,
                                  int32_t n_poses, const float* T_map_cam, void* stream);
