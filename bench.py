@@ -347,9 +347,8 @@ def run_precision(args):
         m.move(x, y)
         for c in f["clouds"]:
             m.input_pointcloud(c["xyz"], c["T"])
-        for c, ft in zip(f["cameras"], feat):
-            m.input_images([(c["rgb"], c["K"], [(8, 0, 3)]), (ft, c["K_feat"], [(9, 0, ft.shape[-1])]),
-                            (c["classes"], c["K"], [(10, 0, 20)])], c["T"])
+        m.input_image_poses([([(c["rgb"], c["K"], [(8, 0, 3)]), (ft, c["K_feat"], [(9, 0, ft.shape[-1])]),
+                               (c["classes"], c["K"], [(10, 0, 20)])], c["T"]) for c, ft in zip(f["cameras"], feat)])
 
     def timed_run(storage, C, keep=False):
         feat = [[c["features"][..., :C].contiguous() for c in f["cameras"]] for f in dframes]
@@ -457,9 +456,9 @@ def run_layers(args):
         m.move(x, y)
         for c in f["clouds"]:
             m.input_pointcloud(c["xyz"], c["T"])
-        binds = [(8 + l, 0, 3) for l in range(L)]
-        for c in f["cameras"]:  # up to 8 bindings per image entry, one pose
-            m.input_images([(c["rgb"], c["K"], binds[i:i + 8]) for i in range(0, L, 8)], c["T"])
+        binds = [(8 + l, 0, 3) for l in range(L)]  # up to 8 bindings per image entry
+        m.input_image_poses([([(c["rgb"], c["K"], binds[i:i + 8]) for i in range(0, L, 8)], c["T"])
+                             for c in f["cameras"]])
 
     def run(rule, param, L):
         make = lambda: mem.Map(mem.MapParams(W, H, res, layers=[mem.Layer(3, rule, param)] * L, **p))
