@@ -228,9 +228,10 @@ __global__ __launch_bounds__(kEigLanes) void k_pca_eig(const PcaParts* __restric
         double off = 0.0;
         for (int e = t; e < n * n; e += kEigLanes)
             if ((e >> 6) != (e & 63)) off += S[e >> 6][e & 63] * S[e >> 6][e & 63];
-        // off-diagonal norm at 1e-12 of the matrix's: rounding keeps it near
-        // n eps, so a tighter bound would never be met
-        if (block_sum(off) <= 1e-24 * fro2) break;
+        // off-diagonal norm at 1e-10 of the matrix's (eigenvector error about
+        // that over the relative eigenvalue gap; rounding keeps the norm near
+        // n eps, so a bound much tighter would never be met)
+        if (block_sum(off) <= 1e-20 * fro2) break;
     }
     if (t == 0) {
         // the three largest eigenvalues, descending (the lower index first
