@@ -484,9 +484,11 @@ mem_status mem_batch_reset_stats(mem_batch* batch, void* stream);
  * BF16 operands (activations and a BF16 copy of the weights) with FP32
  * accumulation; the master weights and Adam moments are FP32.
  *
- * Training loss over cells with mask > 0, for out = (m, s):
- *   L = inv_count * sum 0.5 (s + (t - m)^2 exp(-s))
- * the Gaussian negative log-likelihood of the target height t. */
+ * Training loss over the N cells with mask > 0, for out = (m, s):
+ *   L = (1 / N) sum 0.5 (s + (t - m)^2 exp(-s))
+ * the Gaussian negative log-likelihood of the target height t averaged over
+ * the cells the target observed (N is counted on the device, 1 / N rounded
+ * once from binary64; N = 0 gives L = 0 and a zero gradient). */
 typedef struct mem_unet mem_unet;
 
 /* Number of parameters for a base width (1 .. 256), or -1. */
@@ -528,16 +530,15 @@ mem_status mem_unet_forward(mem_unet* net, const float* x, int32_t batch, float*
 
 /* Loss and its gradient with respect to every parameter (flat layout) for
  * targets t and masks (device, batch x size x size each); grad and loss are
- * device pointers and may be NULL.  inv_count > 0, normally 1 / (number of
- * cells with mask > 0). */
+ * device pointers and may be NULL.  Nothing is read back to the host. */
 mem_status mem_unet_loss_grad(mem_unet* net, const float* x, const float* target, const float* mask,
-                              int32_t batch, float inv_count, float* grad, float* loss, void* stream);
+                              int32_t batch, float* grad, float* loss, void* stream);
 
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the
  * gradient of mem_unet_loss_grad at learning rate lr; loss (device) may be
  * NULL. */
 mem_status mem_unet_train_step(mem_unet* net, const float* x, const float* target, const float* mask,
-                               int32_t batch, float inv_count, float lr, float* loss, void* stream);
+                               int32_t batch, float lr, float* loss, void* stream);
 
 /* The network input x (device, height x width x 3, NHWC) of one window
  * from its height and variance layers h, v (device, height x width, logical

@@ -478,8 +478,28 @@ __global__ __launch_bounds__(256) void k_colsum8(const uint16_t* __restrict__ g,
     }
 }
 
+// Cells of the target that count in the loss (mask > 0) into *count, which
+// must hold 0: a wave sum per wave, one integer atomic per workgroup (exact,
+// so the total does not depend on the order).
+__global__ __launch_bounds__(256) void k_mask_count(const float* __restrict__ mask, int64_t P, int* __restrict__ count)
+{
+    int n = 0;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x)
+        n += mask[p] > 0.f;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o);
+    __shared__ int red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = n;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int tot = red[0] + red[1] + red[2] + red[3];
+        if (tot) atomicAdd(count, tot);
+    }
+}
+
 // Head (1x1 convolution, 2 outputs, FP32 weights) and the Gaussian NLL over
-// mask > 0: writes out (optional); with a target, the per-pixel output
+// mask > 0, averaged over the *count such cells (the loss's normaliser):
+// writes out (optional); with a target, the per-pixel output
 // gradient gout[p] = (dL/dm, dL/ds), the bias gradient and the loss
 // (reduced per workgroup, one atomic each), and the gradient with respect to
 // d0's pre-activation (BF16, ReLU-masked by d0).
@@ -487,11 +507,15 @@ template <bool V8>
 __global__ __launch_bounds__(256) void k_head(const uint16_t* __restrict__ d0, int c, int64_t P,
                                               const float* __restrict__ w, const float* __restrict__ b,
                                               const float* __restrict__ target, const float* __restrict__ mask,
-                                              float inv_count, float* __restrict__ out, float* __restrict__ loss,
+                                              const int* __restrict__ count, float* __restrict__ out,
+                                              float* __restrict__ loss,
                                               float2* __restrict__ gout, float* __restrict__ gb,
                                               uint16_t* __restrict__ gd0)
 {
     float l_acc = 0.f, g0_acc = 0.f, g1_acc = 0.f;
+    // 1 / (cells in the loss), rounded once from binary64 (an empty mask
+    // counts as one cell: the loss and its gradient are then zero)
+    const float inv_count = target ? (float)(1.0 / (double)max(*count, 1)) : 0.f;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
         float o0 = b[0], o1 = b[1];
         if (V8) {  // the row in 16-byte chunks, summed in the same channel order
@@ -975,7 +999,7 @@ void unet_colsum(hipStream_t s, const uint16_t* g, int gs, int64_t rows, int c, 
 }
 
 void unet_head_loss(hipStream_t s, const uint16_t* d0, int c, int64_t P, const float* w, const float* b,
-                    const float* target, const float* mask, float inv_count, float* out, float* loss, float* gw,
+                    const float* target, const float* mask, const int* count, float* out, float* loss, float* gw,
                     float* gb, uint16_t* gd0, float2* gout)
 {
     int64_t blocks = (P + 255) / 256;
@@ -984,10 +1008,10 @@ void unet_head_loss(hipStream_t s, const uint16_t* d0, int c, int64_t P, const f
     const bool v8 = c % 8 == 0 && ((uintptr_t)d0 & 15) == 0 && (!gd0 || ((uintptr_t)gd0 & 15) == 0);
     if (v8)
         hipLaunchKernelGGL(k_head<true>, dim3((unsigned)(blocks < 1 ? 1 : blocks)), dim3(256), 0, s, d0, c, P, w, b,
-                           target, mask, inv_count, out, loss, gout, gb, gd0);
+                           target, mask, count, out, loss, gout, gb, gd0);
     else
         hipLaunchKernelGGL(k_head<false>, dim3((unsigned)(blocks < 1 ? 1 : blocks)), dim3(256), 0, s, d0, c, P, w,
-                           b, target, mask, inv_count, out, loss, gout, gb, gd0);
+                           b, target, mask, count, out, loss, gout, gb, gd0);
     if (!target) return;
     int64_t wb = (P + 1023) / 1024;
     if (wb > 512) wb = 512;
@@ -1010,6 +1034,13 @@ void unet_add_f32(hipStream_t s, float* dst, int ds, const float* src, int ss, i
 void unet_cast_bf16(hipStream_t s, const float* x, int64_t n, uint16_t* y)
 {
     hipLaunchKernelGGL(k_cast_bf16, dim3(grid_for(n)), dim3(256), 0, s, x, n, y);
+}
+
+void unet_mask_count(hipStream_t s, const float* mask, int64_t P, int* count)
+{
+    int64_t blocks = (P + 1023) / 1024;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_mask_count, dim3((unsigned)(blocks < 1 ? 1 : blocks)), dim3(256), 0, s, mask, P, count);
 }
 
 void unet_fill(hipStream_t s, float* x, int64_t n, float v)

@@ -263,7 +263,7 @@ void conv_bwd(mem_unet* u, hipStream_t s, int i, const uint16_t* x, int xs, int 
 }
 
 // Loss gradient of every parameter into u->g (flat), loss into u->loss.
-void backward(mem_unet* u, hipStream_t s, int B, const float* target, const float* mask, float inv_count)
+void backward(mem_unet* u, hipStream_t s, int B, const float* target, const float* mask)
 {
     const int b = u->base;
     FillList fl;  // every accumulated gradient starts at zero: one launch
@@ -274,12 +274,14 @@ void backward(mem_unet* u, hipStream_t s, int B, const float* target, const floa
     }
     fl.add(u->g, u->n_params);
     for (int l = 0; l < 4; l++) fl.add(u->de[l], P_at(u, B, l) * (b << l));
-    fl.add(u->loss, 1);
+    fl.add(u->loss, 2);  // the loss and the count of masked cells (int 0)
     u->prof.timed(s, "fill", [&] { unet_zero_many(s, fl); });
     const int H = NLAY - 1;
     const int64_t P0 = P_at(u, B, 0);
+    int* count = (int*)(u->loss + 1);
     u->prof.timed(s, "head", [&] {
-        unet_head_loss(s, u->d[0], b, P0, u->w + u->L[H].off, bias(u, u->w, H), target, mask, inv_count, u->out,
+        unet_mask_count(s, mask, P0, count);
+        unet_head_loss(s, u->d[0], b, P0, u->w + u->L[H].off, bias(u, u->w, H), target, mask, count, u->out,
                        u->loss, u->g + u->L[H].off, bias(u, u->g, H), u->g1, (float2*)u->tmpf);
     });
     uint16_t* gd = u->g1;  // gradient of d_l's pre-activation
@@ -401,7 +403,7 @@ mem_status mem_unet_create(int32_t base, int32_t max_batch, int32_t size, uint64
     (void)hipGetLastError();
     const int B = max_batch;
     bool ok = ualloc(&u->w, u->n_params) && ualloc(&u->g, u->n_params) && ualloc(&u->am, u->n_params) &&
-              ualloc(&u->av, u->n_params) && ualloc(&u->loss, 1);
+              ualloc(&u->av, u->n_params) && ualloc(&u->loss, 2);
     size_t col = 0;
     for (int i = 0; i < NLAY && ok; i++) {
         ULayer& Y = u->L[i];
@@ -517,32 +519,31 @@ mem_status mem_unet_forward(mem_unet* u, const float* x, int32_t batch, float* o
     // the head alone (no loss)
     const int H = NLAY - 1;
     u->prof.timed(s, "head", [&] {
-        unet_head_loss(s, u->d[0], u->base, P0, u->w + u->L[H].off, bias(u, u->w, H), nullptr, nullptr, 0.f, out,
+        unet_head_loss(s, u->d[0], u->base, P0, u->w + u->L[H].off, bias(u, u->w, H), nullptr, nullptr, nullptr, out,
                        nullptr, nullptr, nullptr, nullptr, nullptr);
     });
     return finish(u, "mem_unet_forward");
 }
 
 mem_status mem_unet_loss_grad(mem_unet* u, const float* x, const float* target, const float* mask, int32_t batch,
-                              float inv_count, float* grad, float* loss, void* stream)
+                              float* grad, float* loss, void* stream)
 {
     if (mem_status st = check_batch(u, batch)) return st;
     if (!x || !target || !mask) return api_fail(MEM_E_ARG, "x, target and mask must not be NULL");
-    if (!(inv_count > 0.f)) return api_fail(MEM_E_ARG, "inv_count must be positive (1 / masked cells)");
     hipStream_t s = (hipStream_t)stream;
     u->prof.timed(s, "eltwise", [&] { unet_cast_bf16(s, x, P_at(u, batch, 0) * 3, u->x); });
     forward(u, s, batch);
-    backward(u, s, batch, target, mask, inv_count);
+    backward(u, s, batch, target, mask);
     if (grad) (void)hipMemcpyAsync(grad, u->g, sizeof(float) * u->n_params, hipMemcpyDeviceToDevice, s);
     if (loss) (void)hipMemcpyAsync(loss, u->loss, sizeof(float), hipMemcpyDeviceToDevice, s);
     return finish(u, "mem_unet_loss_grad");
 }
 
 mem_status mem_unet_train_step(mem_unet* u, const float* x, const float* target, const float* mask,
-                               int32_t batch, float inv_count, float lr, float* loss, void* stream)
+                               int32_t batch, float lr, float* loss, void* stream)
 {
     if (!(lr > 0.f) || !std::isfinite(lr)) return api_fail(MEM_E_ARG, "lr must be positive");
-    if (mem_status st = mem_unet_loss_grad(u, x, target, mask, batch, inv_count, nullptr, loss, stream)) return st;
+    if (mem_status st = mem_unet_loss_grad(u, x, target, mask, batch, nullptr, loss, stream)) return st;
     hipStream_t s = (hipStream_t)stream;
     u->step++;
     const float b1 = 0.9f, b2 = 0.999f;

@@ -113,10 +113,13 @@ void unet_add_f32(hipStream_t s, float* dst, int ds, const float* src, int ss, i
 void unet_relu_mask_add(hipStream_t s, const float* acc, int as, const float* add, int ads, const uint16_t* y,
                         int ys, int64_t rows, int c, uint16_t* g, int gs);
 void unet_colsum(hipStream_t s, const uint16_t* g, int gs, int64_t rows, int c, float* db);
+// Adds the number of mask entries > 0 among P to *count (device int).
+void unet_mask_count(hipStream_t s, const float* mask, int64_t P, int* count);
 // Head output (out may be NULL) and, with a target, loss and head / d0
-// gradients; gout (P float2) is scratch.
+// gradients, the loss averaged over the *count masked cells (device int);
+// gout (P float2) is scratch.
 void unet_head_loss(hipStream_t s, const uint16_t* d0, int c, int64_t P, const float* w, const float* b,
-                    const float* target, const float* mask, float inv_count, float* out, float* loss, float* gw,
+                    const float* target, const float* mask, const int* count, float* out, float* loss, float* gw,
                     float* gb, uint16_t* gd0, float2* gout);
 void unet_cast_bf16(hipStream_t s, const float* x, int64_t n, uint16_t* y);
 void unet_fill(hipStream_t s, float* x, int64_t n, float v);

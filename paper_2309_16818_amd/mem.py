@@ -572,8 +572,8 @@ def _load_unet():
         "mem_unet_save": [P, C.c_char_p, P],
         "mem_unet_load": [P, C.c_char_p, P],
         "mem_unet_forward": [P, P, I32, P, P],
-        "mem_unet_loss_grad": [P, P, P, P, I32, F, P, P, P],
-        "mem_unet_train_step": [P, P, P, P, I32, F, F, P, P],
+        "mem_unet_loss_grad": [P, P, P, P, I32, P, P, P],
+        "mem_unet_train_step": [P, P, P, P, I32, F, P, P],
         "mem_unet_input": [P, P, I32, I32, F, P, P],
         "mem_unet_complete": [P, P, I32, F, F, P, P, P],
         "mem_complete": [P, P, F, F, P, P, P],
@@ -663,16 +663,12 @@ class UNet:
                                              _stream(stream)))
         return out
 
-    @staticmethod
-    def _inv_count(mask):
-        return 1.0 / max(int((mask > 0).sum().item()), 1)
-
     def loss_grad(self, x, target, mask, stream=None):
         B = x.shape[0]
         grad = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
         loss = torch.empty(1, dtype=torch.float32, device="cuda")
         _check(_load_unet().mem_unet_loss_grad(self._u, self._x(x, 3, "x"), self._tm(target, B, "target"),
-                                               self._tm(mask, B, "mask"), B, self._inv_count(mask),
+                                               self._tm(mask, B, "mask"), B,
                                                _dev_ptr(grad, "grad"), _dev_ptr(loss, "loss"), _stream(stream)))
         return loss, grad
 
@@ -680,7 +676,7 @@ class UNet:
         B = x.shape[0]
         lp = _dev_ptr(loss_out, "loss") if loss_out is not None else None
         _check(_load_unet().mem_unet_train_step(self._u, self._x(x, 3, "x"), self._tm(target, B, "target"),
-                                                self._tm(mask, B, "mask"), B, self._inv_count(mask), float(lr),
+                                                self._tm(mask, B, "mask"), B, float(lr),
                                                 lp, _stream(stream)))
 
     def complete_windows(self, x, z_ref, sigma_max, stream=None):

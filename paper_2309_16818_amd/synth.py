@@ -172,19 +172,39 @@ def raycast(ter: Terrain, o, d, tmax: float, step: float = 0.04, tmin: float = 0
         lo = torch.full(O.shape[:1], tmin, device=device, dtype=dt)
         hit = torch.full_like(lo, float("nan"))
         hi_t = torch.full_like(lo, float("nan"))
+        # the sample positions t -> t2 of the march, in the order taken
+        steps = []
         t = tmin
-        prev_above = f(lo) > 0
         while t < tmax:
             t2 = min(t + step, tmax)
-            val = f(torch.full_like(lo, t2))
-            cross = prev_above & (val <= 0) & torch.isnan(hi_t)
-            lo = torch.where(cross, torch.full_like(lo, t), lo)
-            hi_t = torch.where(cross, torch.full_like(lo, t2), hi_t)
-            escaped = (D[:, 2] >= 0) & (O[:, 2] + t2 * D[:, 2] > zmax)
-            prev_above = prev_above & ~cross & ~escaped
-            if not bool(prev_above.any()):
-                break
+            steps.append((t, t2))
             t = t2
+        prev_above = f(lo) > 0
+        # blocks of `chunk` samples per launch: a ray stops at its first
+        # sample below the terrain (a crossing in [t, t2]) or where it has
+        # left the height field's bounding slab upwards
+        chunk = 32
+        for b0 in range(0, len(steps), chunk):
+            blk = steps[b0:b0 + chunk]
+            T0 = torch.tensor([a for a, _ in blk], device=device, dtype=dt)
+            T2 = torch.tensor([b for _, b in blk], device=device, dtype=dt)
+            idx = torch.nonzero(prev_above).squeeze(1)
+            if idx.numel() == 0:
+                break
+            Oi, Di = O[idx], D[idx]
+            x = Oi[:, 0:1] + T2[None, :] * Di[:, 0:1]
+            y = Oi[:, 1:2] + T2[None, :] * Di[:, 1:2]
+            val = Oi[:, 2:3] + T2[None, :] * Di[:, 2:3] - ter.height_t(x, y)
+            cross = val <= 0
+            escaped = (Di[:, 2:3] >= 0) & (Oi[:, 2:3] + T2[None, :] * Di[:, 2:3] > zmax)
+            stop = cross | escaped
+            any_stop = stop.any(1)
+            first = torch.argmax(stop.to(torch.int8), 1)
+            crossed = any_stop & cross.gather(1, first[:, None]).squeeze(1)
+            ci = idx[crossed]
+            lo[ci] = T0[first[crossed]]
+            hi_t[ci] = T2[first[crossed]]
+            prev_above[idx[any_stop]] = False
         m = ~torch.isnan(hi_t)
         a, b = lo[m], hi_t[m]
         Om, Dm = O[m], D[m]

@@ -114,7 +114,8 @@ def test_unet_host_checks():
         assert lib.mem_unet_create(*args[:3], 0, args[3], None, C.byref(h)) == mem.MEM_E_ARG, args
         assert not h.value
     assert lib.mem_unet_forward(None, None, 1, None, None) == mem.MEM_E_ARG
-    assert lib.mem_unet_train_step(None, None, None, None, 1, 1.0, 1e-3, None, None) == mem.MEM_E_ARG
+    assert lib.mem_unet_train_step(None, None, None, None, 1, 1e-3, None, None) == mem.MEM_E_ARG
+    assert lib.mem_unet_loss_grad(None, None, None, None, 1, None, None, None) == mem.MEM_E_ARG
     assert lib.mem_complete(None, None, 0.0, 0.05, None, None, None) == mem.MEM_E_ARG
     assert lib.mem_unet_destroy(None, None) == mem.MEM_OK
 

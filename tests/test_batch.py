@@ -192,3 +192,40 @@ def test_batch_rejects_bad_inputs_without_touching_maps():
         assert torch.isnan(B.get_layer(m, 0)).all() and B.center(m) == (0, 0)
     B.step(np.zeros((len(SIZES), 2), np.float32), to_dev(xyz), offs, Ts)
     assert sum(int(B.get_layer(m, 3).sum()) for m in range(len(SIZES))) == 10 * len(SIZES)
+
+
+# Maps of the batched workload's sizes (sides 64-256 cells): several 64x64
+# ingest tiles per map, sides that are not multiples of 64, non-square maps,
+# clouds of 10k-60k points and rays of up to ~128 cells.
+LARGE = [(256, 256), (200, 131), (65, 250), (129, 97), (256, 70), (100, 100), (190, 190)]
+
+
+def test_large_uneven_maps_match_the_oracle_in_lockstep():
+    rng = np.random.default_rng(5)
+    counts_max = 60000
+    B = make_batch(LARGE, max_points=len(LARGE) * counts_max)
+    orcs = make_oracles(LARGE)
+    views = [MapView(B, m) for m in range(len(LARGE))]
+    poses = [(rng.uniform(-1, 1), rng.uniform(-1, 1), rng.uniform(0, 6)) for _ in LARGE]
+    long_rays = 0
+    for it in range(4):
+        poses = walk(rng, poses, jump=1 if it == 2 else None)
+        counts = [int(c) for c in rng.integers(10000, counts_max + 1, len(LARGE))]
+        xyz, offs, Ts, Tc, Ks, imgs = step_inputs(rng, LARGE, poses, counts)
+        for v, o in zip(views, orcs):
+            sync_from_oracle(v, o)
+        run_batch_step(B, poses, xyz, offs, Ts, imgs, Ks, Tc)
+        for m, (v, o) in enumerate(zip(views, orcs)):
+            o.move(*poses[m][:2])
+            cells = o.input_pointcloud(xyz[offs[m]:offs[m + 1]], Ts[m])
+            # rays longer than 64 cells (the march's segmented path)
+            ok = cells >= 0
+            cx, cy = cells[ok] % LARGE[m][0], cells[ok] // LARGE[m][0]
+            sx, sy = LARGE[m][0] // 2, LARGE[m][1] // 2
+            long_rays += int((np.maximum(np.abs(cx - sx), np.abs(cy - sy)) > 66).sum())
+            o.input_image(imgs[m], Ks[m], Tc[m], bind=IMG_BIND)
+            compare(v, o, counts=True, what=f"step {it} map {m} ({LARGE[m][0]}x{LARGE[m][1]})")
+        print(f"step {it}: {sum(counts)} points", flush=True)
+    assert long_rays > 10000
+    st = B.stats()
+    assert st["points_accepted"] > 0 and st["pairs_visible"] > 0

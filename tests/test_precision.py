@@ -55,13 +55,16 @@ def test_fp8_storage_matches_torch_e4m3_with_saturation_and_scales():
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("C", [48, 200, 384])
 @pytest.mark.parametrize("storage,rel", [(mem.MEM_F32, 1e-4), (mem.MEM_BF16, 2.0 ** -8), (mem.MEM_FP8_E4M3, 2.0 ** -3)])
-def test_feature_fusion_within_one_storage_rounding(storage, rel):
+def test_feature_fusion_within_one_storage_rounding(storage, rel, C):
     """One image update from the same state on both sides: the GPU result
     differs from the binary64 oracle by at most the storage rounding (plus
-    binary32 arithmetic), per channel, relative to the layer's scale."""
-    rng = np.random.default_rng(2)
-    C = 48
+    binary32 arithmetic), per channel, relative to the layer's scale.  The
+    widths span one pass of a pair's lanes over the channels (48), a ragged
+    last pass (200) and the 384-channel feature layer of the precision
+    workload (six passes of 64 lanes)."""
+    rng = np.random.default_rng(2 + C)
     layers = [(C, mem.MEM_GAUSS, 1.0, storage), (C, mem.MEM_EXPAVG, 0.5, storage)]
     g, o = make_pair(48, 48, 0.05, layers=layers)
     h = np.where(rng.uniform(size=(48, 48)) < 0.9, rng.normal(0, 0.05, (48, 48)), np.nan)

@@ -20,7 +20,15 @@ rounding boundary.
   the binary64 one by the same amount (torch's own FP32 convolutions in the
   same format differ by 4e-3 forward).  Bars against both oracles, the
   format's own error budget: forward 1e-2, gradient cosine >= 0.999 and
-  norm-wise 2e-2, every layer 0.15, loss 1e-3."""
+  norm-wise 2e-2, loss 1e-3, and every layer LAYER_BAR_WIDE.
+
+LAYER_BAR_WIDE is measured, not chosen: torch's FP32 convolutions with the
+format's rounding points (an implementation independent of this library),
+run in eight summation orders (input channels in 1, 2, 3 or 5 chunks, with
+and without its oneDNN path) on the two base-32 cases below, differ from the
+BF16-format oracle by at most 0.073 in one layer's gradient (0.040-0.054 at
+64x64; 0.003 or 0.073 at 32x32, where one flipped rounding decides); the bar
+is 1.5 times that.  tests/test_unet_oracle.py re-measures it on the CPU."""
 import os
 
 import numpy as np
@@ -85,11 +93,16 @@ def make(base, B, S, p):
 # (base 2 and 6 give K and N that are not multiples of the tile), and the
 # full width at a reduced window.
 CASES = [(2, 2, 16), (4, 2, 32), (6, 1, 24), (32, 1, 32), (32, 2, 64)]
+assert all(c in CASES for c in [(32, 1, 32), (32, 2, 64)])
+
+
+LAYER_BAR_WIDE = 0.11
+WIDE_CASES = [(32, 1, 32), (32, 2, 64)]
 
 
 def _bars(base):
     """(forward, gradient, per-layer) norm-wise bars against the bf16 oracle."""
-    return (1e-4, 1e-4, 1e-3) if base <= 6 else (1e-2, 2e-2, 0.15)
+    return (1e-4, 1e-4, 1e-3) if base <= 6 else (1e-2, 2e-2, LAYER_BAR_WIDE)
 
 
 @pytest.mark.parametrize("base,B,S", CASES)

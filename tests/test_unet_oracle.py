@@ -151,47 +151,57 @@ def test_bf16_rounding_matches_torch():
     assert np.signbit(O.round_bf16(-0.0))
 
 
-class _Rf(torch.autograd.Function):  # forward-only BF16 rounding
-    @staticmethod
-    def forward(ctx, x):
-        return x.float().to(torch.bfloat16).double()
-
-    @staticmethod
-    def backward(ctx, g):
-        return g
-
-
-class _Rb(torch.autograd.Function):  # gradient-only BF16 rounding
-    @staticmethod
-    def forward(ctx, x):
-        return x.clone()
-
-    @staticmethod
-    def backward(ctx, g):
-        return g.float().to(torch.bfloat16).double()
-
-
-def torch_unet_bf16(p, x, base):
+def torch_unet_bf16(p, x, base, dtype=torch.float64, chunks=1):
     """torch_unet with the BF16 storage format: BF16 input and convolution
     weights, binary32 biases and head; every convolution / transposed
     convolution output stored in BF16, and the gradient with respect to it
-    (after the ReLU mask) rounded to BF16."""
+    (after the ReLU mask) rounded to BF16.  Arithmetic in `dtype`; with
+    chunks > 1 every 3x3 convolution sums its input channels in that many
+    groups (another summation order of the same products)."""
     L = spec(base)
     offs = O.unet_layer_offsets(base)
-    rf, rb = _Rf.apply, _Rb.apply
+
+    class Rf(torch.autograd.Function):  # forward-only BF16 rounding
+        @staticmethod
+        def forward(ctx, a):
+            return a.float().to(torch.bfloat16).to(dtype)
+
+        @staticmethod
+        def backward(ctx, g):
+            return g
+
+    class Rb(torch.autograd.Function):  # gradient-only BF16 rounding
+        @staticmethod
+        def forward(ctx, a):
+            return a.clone()
+
+        @staticmethod
+        def backward(ctx, g):
+            return g.float().to(torch.bfloat16).to(dtype)
+
+    rf, rb = Rf.apply, Rb.apply
 
     def wb(i):
         taps, ci, co = L[i]
         o = int(offs[i])
         w = p[o:o + taps * ci * co].view(taps, ci, co)
         b = p[o + taps * ci * co:o + taps * ci * co + co]
-        w = w.float().double() if i == 17 else rf(w)
-        return w, b.float().double()
+        w = w.float().to(dtype) if i == 17 else rf(w)
+        return w, b.float().to(dtype)
 
     def conv3(i, a):
         w, b = wb(i)
         ci, co = w.shape[1], w.shape[2]
-        return F.conv2d(a, w.view(3, 3, ci, co).permute(3, 2, 0, 1), b, padding=1)
+        w4 = w.view(3, 3, ci, co).permute(3, 2, 0, 1)
+        k = min(chunks, ci)
+        if k == 1:
+            return F.conv2d(a, w4, b, padding=1)
+        cut = [ci * j // k for j in range(k + 1)]
+        parts = [F.conv2d(a[:, cut[j]:cut[j + 1]], w4[:, cut[j]:cut[j + 1]], None, padding=1) for j in range(k)]
+        y = parts[-1]
+        for q in parts[-2::-1]:
+            y = y + q
+        return y + b[None, :, None, None]
 
     def up(i, a):
         w, b = wb(i)
@@ -232,3 +242,28 @@ def test_bf16_format_matches_torch_autograd_with_the_same_roundings(base, B, S):
     assert np.linalg.norm(g - gt) <= 1e-7 * np.linalg.norm(gt)
     # and the format really differs from binary64
     assert not np.allclose(out, O.unet_forward(p, x, base), rtol=1e-6, atol=0)
+
+
+def test_fp32_format_error_budget_at_full_width():
+    """The per-layer gradient bar of the GPU's base-32 cases
+    (tests/test_unet.py, LAYER_BAR_WIDE) is 1.5 times the largest per-layer
+    error of torch's FP32 convolutions in the same format against the
+    BF16-format oracle, over eight summation orders; re-measured here."""
+    import test_unet as TU
+    worst = 0.0
+    for base, B, S in TU.WIDE_CASES:
+        p, x, t, m = TU.sample(base, B, S, 13 * base + S)  # the GPU test's inputs
+        _, rg = O.unet_loss_grad(p, x, t, m, base, bf16=True)
+        offs = list(O.unet_layer_offsets(base)) + [len(p)]
+        for chunks in (1, 2, 3, 5):
+            for onednn in (True, False):
+                with torch.backends.mkldnn.flags(enabled=onednn):
+                    pt = torch.tensor(p, dtype=torch.float32, requires_grad=True)
+                    ot = torch_unet_bf16(pt, torch.tensor(x, dtype=torch.float32), base, torch.float32, chunks)
+                    nll(ot, torch.tensor(t, dtype=torch.float32), torch.tensor(m, dtype=torch.float32)).backward()
+                g = pt.grad.double().numpy()
+                per = [np.linalg.norm(g[offs[i]:offs[i + 1]] - rg[offs[i]:offs[i + 1]])
+                       / np.linalg.norm(rg[offs[i]:offs[i + 1]]) for i in range(18)]
+                worst = max(worst, max(per))
+    print(f"largest per-layer gradient error of FP32 in the BF16 format: {worst:.4f}")
+    assert 0.02 < worst <= TU.LAYER_BAR_WIDE / 1.5
