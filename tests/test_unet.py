@@ -165,7 +165,7 @@ def test_empty_mask_gives_zero_loss_and_gradient():
     import ctypes as C
     z = dev(np.zeros((B, S, S)))
     mem._check(lib.mem_unet_loss_grad(net._u, C.c_void_p(dev(x).data_ptr()), C.c_void_p(dev(t).data_ptr()),
-                                      C.c_void_p(z.data_ptr()), B, 1.0, C.c_void_p(grad.data_ptr()),
+                                      C.c_void_p(z.data_ptr()), B, C.c_void_p(grad.data_ptr()),
                                       C.c_void_p(loss.data_ptr()), mem._stream()))
     torch.cuda.synchronize()
     assert loss.item() == 0.0 and not grad.any()
