@@ -11,8 +11,18 @@ synthetic, generated before timing and resident in HBM.
 
 Prints one JSON line: fused points/s over the whole update (value), the
 per-frame latency, per-kernel times from HIP events recorded on the
-library's stream during the timed region, the roofline of the dominant
-kernel, and the oracle's throughput on the host CPU for a bounded sample.
+library's stream (a second pass over the same frames), the roofline of the
+dominant kernel and of the ingest, finalize and gather kernels (HBM bytes
+against 8 TB/s and against the copy rate measured by the library's
+calibration kernel; the ingest's global atomics against the measured atomic
+rate), the post-processing steps, a batched leg (256 uneven maps per graph
+step against the same maps updated one by one) and a learned leg (the
+completion network's training step and its inference on one map), and the
+oracle's throughput on the host's cores for a bounded sample.
+
+Other workloads (--workload): batch (1024 maps), learned (training to
+quality), precision (384-channel BF16 / FP8 storage), layers (1-20
+multi-modal layers), copy (a plain 256 MiB copy for counter scaling).
 """
 from __future__ import annotations
 
@@ -95,56 +105,119 @@ def parse():
     ap.add_argument("--maps", type=int, default=1024)
     ap.add_argument("--plain-steps", type=int, default=2,
                     help="batch workload: steps of the per-map call sequence timed beside it")
+    ap.add_argument("--legs", type=int, default=1,
+                    help="full: also time a batched leg (--leg-maps maps) and the learned completion's "
+                         "training and inference on the same GPU")
+    ap.add_argument("--leg-maps", type=int, default=256)
     return ap.parse_args()
 
 
-def run_batch(args):
-    """1024 independent maps (sides 64-256 cells at 0.05 m, 4k-60k points and
-    one 128x96x16 feature camera each) per step: the batched graph step
-    against the same step as per-map call sequences on one stream."""
+def batch_kernel_bytes(name, st, cells, launches, C=16):
+    """Algorithmic HBM bytes of a batch stage over `launches` steps, from
+    the step counters: binning reads every point's xyz (12 B) and writes a
+    16 B record per accepted point; the block-owned ingest reads the
+    records and writes four 4 B sums per cell (count, weights, weighted
+    heights, zero votes); the logical copy reads and writes 4 B per cell;
+    finalize reads count and votes (8 B) per cell and h, v, W, S with h, v
+    written (24 B) per touched cell; projection reads h (4 B) per cell and
+    writes an 8 B pair per visible pair; the gather reads the pixel's C
+    floats, reads and writes the C-float mean and the 4 B variance and
+    reads the pair (4 C + 8 C + 8 + 8 B per visible pair)."""
+    if name == "b_bin":
+        return 12 * st["points_in"] + 16 * st["points_accepted"]
+    if name == "b_tile_ingest":
+        return 16 * st["points_accepted"] + 16 * cells * launches
+    if name == "b_logical":
+        return 8 * cells * launches
+    if name == "b_finalize":
+        return 8 * cells * launches + 24 * st["cells_touched"]
+    if name == "b_project":
+        return 4 * cells * launches + 8 * st["pairs_visible"]
+    if name == "b_gather":
+        return (12 * C + 16) * st["pairs_visible"]
+    return 0
+
+
+def batch_leg(n_maps, steps, warmup, plain_steps, seed=3):
+    """n_maps independent maps (sides 64-256 cells at 0.05 m, 4k-60k points
+    and one 128x96x16 feature camera each) per step: the batched graph step
+    (timed, HIP events around each step on the current stream) against the
+    same steps as per-map call sequences on one stream, then the same steps
+    again with events around every stage (direct launches) for the per-stage
+    table and the roofline of the stages."""
     import torch
     from paper_2309_16818_amd import mem, synth
     t0 = time.time()
-    world = synth.BatchWorld(n=args.maps, seed=3, device="cuda")
-    steps = [world.step(k) for k in range(args.warmup + args.steps)]
+    world = synth.BatchWorld(n=n_maps, seed=seed, device="cuda")
+    all_steps = [world.step(k) for k in range(warmup + steps)]
     imgs = [world.images(11), world.images(12)]
     torch.cuda.synchronize()
-    print(f"# generated {len(steps)} batch steps in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    print(f"# generated {len(all_steps)} batch steps of {n_maps} maps in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
     side = [int(s) for s in world.side]
+    cells = int(sum(s_ * s_ for s_ in side))
     cam = synth.BATCH_CAM
     layers = [mem.Layer(cam["c"], mem.MEM_GAUSS, 1.0)]
-    max_pts = max(int(s["offsets"][-1]) for s in steps)
-    B = mem.Batch(side, side, synth.BATCH_RES, layers=layers, max_points=max_pts,
-                  cam=(cam["h"], cam["w"], cam["c"], mem.MEM_F32), img_bind=[(8, 0, cam["c"])],
-                  max_range=100.0)
+    max_pts = max(int(s["offsets"][-1]) for s in all_steps)
 
-    def bstep(k):
-        s = steps[k]
+    def make():
+        return mem.Batch(side, side, synth.BATCH_RES, layers=layers, max_points=max_pts,
+                         cam=(cam["h"], cam["w"], cam["c"], mem.MEM_F32), img_bind=[(8, 0, cam["c"])],
+                         max_range=100.0)
+
+    def bstep(B, k):
+        s = all_steps[k]
         B.step(s["robot_xy"], s["xyz"], s["offsets"], s["T"], images=imgs[k % 2], K=s["K"], T_cam=s["T_cam"])
 
-    s0 = steps[0]
+    B = make()
+    s0 = all_steps[0]
     tuning = B.tune(s0["robot_xy"], s0["xyz"], s0["offsets"], s0["T"], images=imgs[0], K=s0["K"], T_cam=s0["T_cam"])
     print(f"# tuned: {tuning}", file=sys.stderr, flush=True)
-    for k in range(args.warmup):
-        bstep(k)
+    for k in range(warmup):
+        bstep(B, k)
     torch.cuda.synchronize()
     B.reset_stats()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     t1 = time.perf_counter()
-    for j in range(args.steps):
+    for j in range(steps):
         ev[j][0].record()
-        bstep(args.warmup + j)
+        bstep(B, warmup + j)
         ev[j][1].record()
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     st = B.stats()
     lat = np.array([a.elapsed_time(b) for a, b in ev])
     batched_pts = st["points_accepted"] / (t2 - t1)
+    B.close()
+
+    # per-stage events on a twin batch over the same steps (direct launches)
+    P = make()
+    P.set_tuning(tuning["chunk"], tuning["wg_per_cu"], tuning["tile"], graph=0)
+    for k in range(warmup):
+        bstep(P, k)
+    torch.cuda.synchronize()
+    P.profile_enable(True)
+    P.profile_read()
+    for j in range(steps):
+        bstep(P, warmup + j)
+    kern = P.profile_read()
+    P.profile_enable(False)
+    P.close()
+    stages = {}
+    for name, (launches, ms) in kern.items():
+        b = batch_kernel_bytes(name, st, cells, launches, cam["c"])
+        stages[name] = dict(launches=launches, ms_per_step=round(ms / steps, 4),
+                            alg_gbs=round(b / (ms * 1e-3) / 1e9, 1) if b and ms > 0 else None)
+    hbm = {k: v for k, v in stages.items() if v["alg_gbs"] is not None}
+    dom = max(hbm, key=lambda k: stages[k]["ms_per_step"])
+    ach = stages[dom]["alg_gbs"]
+    step_bytes = sum(batch_kernel_bytes(k, st, cells, kern[k][0], cam["c"]) for k in kern) / steps
 
     # the same steps as per-map call sequences (mem_move, mem_input_pointcloud, mem_input_image)
     plain = [mem.Map(mem.MapParams(s_, s_, synth.BATCH_RES, max_range=100.0, layers=layers)) for s_ in side]
+
     def pstep(k):
-        s = steps[k]
+        s = all_steps[k]
         o = s["offsets"]
         for m, mp in enumerate(plain):
             mp.move(*s["robot_xy"][m])
@@ -155,28 +228,50 @@ def run_batch(args):
     for mp in plain:
         mp.reset_stats()
     t3 = time.perf_counter()
-    for j in range(args.plain_steps):
+    for j in range(plain_steps):
         pstep(1 + j)
     torch.cuda.synchronize()
     t4 = time.perf_counter()
     p_acc = sum(mp.stats()["points_accepted"] for mp in plain)
+    for mp in plain:
+        mp.close()
     plain_pts = p_acc / (t4 - t3)
-    out = {
-        "metric": METRIC, "value": round(batched_pts, 1), "unit": "points/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round((t2 - t1) * 1e3 / args.steps, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"batched: {args.maps} maps, sides 64-256 cells at 0.05 m, 4k-60k points and "
-                               f"one 128x96x16 feature camera per map per step, one graph launch per step",
-                   "cells": int(sum(s_ * s_ for s_ in side)),
-                   "points_per_step": round(st["points_in"] / args.steps)},
+    step_ms = (t2 - t1) * 1e3 / steps
+    return {
+        "value": round(batched_pts, 1), "unit": "points/s", "steps": steps, "warmup": warmup,
+        "ms_per_step": round(step_ms, 4),
+        "workload": f"batched: {n_maps} maps, sides 64-256 cells at 0.05 m, 4k-60k points and one 128x96x16 "
+                    f"feature camera per map per step, one graph launch per step",
+        "cells": cells, "points_per_step": round(st["points_in"] / steps),
         "latency_ms": {"mean": round(float(lat.mean()), 4), "std": round(float(lat.std()), 4),
                        "median": round(float(np.median(lat)), 4), "p90": round(float(np.percentile(lat, 90)), 4)},
         "tuning": tuning,
         "plain": {"value": round(plain_pts, 1), "unit": "points/s",
-                  "ms_per_step": round((t4 - t3) * 1e3 / args.plain_steps, 3), "steps": args.plain_steps},
+                  "ms_per_step": round((t4 - t3) * 1e3 / plain_steps, 3), "steps": plain_steps,
+                  "what": "the same steps as per-map mem_move / mem_input_pointcloud / mem_input_image calls"},
         "batched_over_plain": round(batched_pts / plain_pts, 2),
+        "stages": stages,
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None},
+        "step_alg_bytes": round(step_bytes), "step_alg_gbs": round(step_bytes / (step_ms * 1e-3) / 1e9, 1),
         "stats": st,
     }
+
+
+def run_batch(args):
+    """1024 independent maps per step: the batched graph step against the
+    same step as per-map call sequences on one stream."""
+    import torch
+    torch.cuda.set_device(0)
+    leg = batch_leg(args.maps, args.steps, args.warmup, args.plain_steps)
+    out = {
+        "metric": METRIC, "value": leg.pop("value"), "unit": leg.pop("unit"), "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": leg.pop("ms_per_step"),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": leg.pop("workload"), "cells": leg.pop("cells"),
+                   "points_per_step": leg.pop("points_per_step")},
+    }
+    out.update(leg)
     print(json.dumps(out), flush=True)
 
 
@@ -210,6 +305,97 @@ def unet_gemm_flops(base, size, batch):
     return f
 
 
+def learned_timing(net, train, steps, warmup, bs, base, S):
+    """Training-step time of the completion network on batches of `bs`
+    windows (forward, backward and Adam; wall clock over `steps` steps
+    after `warmup`), then the same steps with events around every launch:
+    per-kernel times, TFLOP/s of each kind of matrix product and the MFMA
+    roofline of the dominant one."""
+    import torch
+    from paper_2309_16818_amd import completion
+    completion.train(net, train, steps=warmup, batch=bs, lr=1e-3, seed=0, lr_final=1e-3)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    completion.train(net, train, steps=steps, batch=bs, lr=1e-3, seed=1, lr_final=1e-3)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    net.profile_enable(True)
+    net.profile_read()
+    completion.train(net, train, steps=steps, batch=bs, lr=1e-3, seed=1, lr_final=1e-3)
+    kern = net.profile_read()
+    net.profile_enable(False)
+    step_ms = (t2 - t1) * 1e3 / steps
+    flops = unet_gemm_flops(base, S, bs)
+    kernels = {}
+    for name, (launches, ms) in kern.items():
+        per_step = launches / steps
+        k = dict(launches=launches, total_ms=round(ms, 4), avg_us=round(1e3 * ms / max(launches, 1), 3),
+                 ms_per_step=round(ms / steps, 4))
+        if name in flops:
+            k["tflops"] = round(flops[name] * steps / (ms * 1e-3) / 1e12, 2)
+            k["gflop_per_launch"] = round(flops[name] / per_step / 1e9, 3)
+        kernels[name] = k
+    gemm = [k for k in kernels if k in flops]
+    dom = max(gemm, key=lambda k: kernels[k]["total_ms"])
+    ach = kernels[dom]["tflops"]
+    all_gemm = sum(flops.values()) * steps / (sum(kernels[k]["total_ms"] for k in gemm) * 1e-3) / 1e12
+    roof = {"kernel": dom, "bound": "mfma", "achieved": ach, "peak": MFMA_BF16_PEAK_TFS, "unit": "TFLOP/s",
+            "frac": round(ach / MFMA_BF16_PEAK_TFS, 4), "traffic": None,
+            "gflop_per_launch": kernels[dom]["gflop_per_launch"], "avg_us": kernels[dom]["avg_us"]}
+    train_info = {"samples_per_s": round(bs / (step_ms * 1e-3), 1), "ms_per_step": round(step_ms, 3),
+                  "gemm_tflops_all": round(all_gemm, 2)}
+    return step_ms, train_info, kernels, roof
+
+
+def complete_latency(net, S, res, seed, torch, reps=20):
+    """mem_complete on one map holding a sparse fusion: HIP events around
+    each call on the current stream."""
+    from paper_2309_16818_amd import mem, synth
+    w = synth.CompletionWorld(1, size=S, res=res, seed=seed + 99)
+    st = w.sparse_step()
+    m = mem.Map(mem.MapParams(S, S, res, max_range=20.0))
+    m.input_pointcloud(st["xyz"], st["T"][0])
+    z = float(w.ground[0])
+    for _ in range(3):
+        net.complete(m, z, 0.05)
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        net.complete(m, z, 0.05)
+        b.record()
+        torch.cuda.synchronize()
+        lat.append(a.elapsed_time(b))
+    m.close()
+    lat = np.array(lat)
+    return {"what": f"mem_complete on one {S}x{S} map", "mean": round(float(lat.mean()), 4),
+            "std": round(float(lat.std()), 4), "median": round(float(np.median(lat)), 4),
+            "p90": round(float(np.percentile(lat, 90)), 4)}
+
+
+def learned_leg(n_pairs=16, steps=10, warmup=3, bs=8, seed=1):
+    """The completion network at its full size (base 32, 256x256 windows of a
+    0.04 m map) on a few generated pairs: training-step time with the
+    per-kernel MFMA roofline, and the latency of mem_complete on one map
+    (the classical update's output completed and gated)."""
+    import torch
+    from paper_2309_16818_amd import completion, mem
+    S, res, base = 256, 0.04, 32
+    t0 = time.time()
+    pairs = completion.make_pairs(n_pairs, size=S, res=res, seed=seed)
+    print(f"# generated {n_pairs} completion pairs in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    net = mem.UNet(base=base, max_batch=bs, size=S, seed=0)
+    step_ms, train, kernels, roof = learned_timing(net, pairs, steps, warmup, bs, base, S)
+    lat = complete_latency(net, S, res, seed, torch)
+    n_params = net.n_params
+    net.close()
+    return {"workload": f"learned completion: 4-level U-Net, base {base} ({n_params} parameters), {S}x{S} "
+                        f"windows at {res} m, batch {bs}, BF16 MFMA forward and backward, Adam",
+            "steps": steps, "warmup": warmup, "train": train, "complete_latency_ms": lat, "roofline": roof,
+            "kernels": {k: v for k, v in kernels.items() if k in ("gemm_fwd", "gemm_up", "gemm_dgrad", "gemm_wgrad")}}
+
+
 def run_learned(args):
     """The completion network at its full size (base 32, 256x256 windows of a
     0.04 m map): pairs from the batched map update, timed training steps
@@ -217,7 +403,7 @@ def run_learned(args):
     mem_complete on one map, and the completion's quality on held-out pairs
     after training."""
     import torch
-    from paper_2309_16818_amd import completion, mem, synth
+    from paper_2309_16818_amd import completion, mem
     torch.cuda.set_device(0)
     S, res, base, bs = 256, 0.04, 32, args.train_batch
     t0 = time.time()
@@ -227,33 +413,7 @@ def run_learned(args):
     held = pairs.subset(range(args.pairs - n_hold, args.pairs))
     print(f"# generated {args.pairs} pairs in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     net = mem.UNet(base=base, max_batch=bs, size=S, seed=0)
-    completion.train(net, train, steps=args.warmup, batch=bs, lr=1e-3, seed=0, lr_final=1e-3)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    completion.train(net, train, steps=args.steps, batch=bs, lr=1e-3, seed=1, lr_final=1e-3)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    # the same number of steps again with HIP events around every launch
-    net.profile_enable(True)
-    net.profile_read()
-    completion.train(net, train, steps=args.steps, batch=bs, lr=1e-3, seed=1, lr_final=1e-3)
-    kern = net.profile_read()
-    net.profile_enable(False)
-    step_ms = (t2 - t1) * 1e3 / args.steps
-    flops = unet_gemm_flops(base, S, bs)
-    kernels = {}
-    for name, (launches, ms) in kern.items():
-        per_step = launches / args.steps
-        k = dict(launches=launches, total_ms=round(ms, 4), avg_us=round(1e3 * ms / max(launches, 1), 3),
-                 ms_per_step=round(ms / args.steps, 4))
-        if name in flops:
-            k["tflops"] = round(flops[name] * args.steps / (ms * 1e-3) / 1e12, 2)
-            k["gflop_per_launch"] = round(flops[name] / per_step / 1e9, 3)
-        kernels[name] = k
-    gemm = [k for k in kernels if k in flops]
-    dom = max(gemm, key=lambda k: kernels[k]["total_ms"])
-    ach = kernels[dom]["tflops"]
-    all_gemm = sum(flops.values()) * args.steps / (sum(kernels[k]["total_ms"] for k in gemm) * 1e-3) / 1e12
+    step_ms, train_info, kernels, roof = learned_timing(net, train, args.steps, args.warmup, bs, base, S)
     # the rest of the training, then quality on held-out windows
     rest = max(0, args.train_steps - args.warmup - 2 * args.steps)
     t3 = time.time()
@@ -261,24 +421,7 @@ def run_learned(args):
     torch.cuda.synchronize()
     print(f"# trained {rest} more steps in {time.time() - t3:.1f}s", file=sys.stderr, flush=True)
     q = completion.evaluate(net, held, 0.05)
-    # inference: mem_complete on one map holding a sparse fusion
-    w = synth.CompletionWorld(1, size=S, res=res, seed=args.seed + 99)
-    st = w.sparse_step()
-    m = mem.Map(mem.MapParams(S, S, res, max_range=20.0))
-    m.input_pointcloud(st["xyz"], st["T"][0])
-    z = float(w.ground[0])
-    for _ in range(3):
-        net.complete(m, z, 0.05)
-    torch.cuda.synchronize()
-    lat = []
-    for _ in range(20):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        net.complete(m, z, 0.05)
-        b.record()
-        torch.cuda.synchronize()
-        lat.append(a.elapsed_time(b))
-    lat = np.array(lat)
+    lat = complete_latency(net, S, res, args.seed, torch)
     # batched inference throughput (windows of the held-out set)
     xb = held.x[:bs].contiguous()
     net.complete_windows(xb, 0.0, 0.05)
@@ -298,15 +441,11 @@ def run_learned(args):
                                f"(dense 360-degree sweeps vs one forward sensor with occluders), batch {bs}",
                    "pairs": args.pairs, "train_steps": args.train_steps},
         "value_is": "completion inference: gated cells per second on batches of windows",
-        "train": {"samples_per_s": round(bs / (step_ms * 1e-3), 1), "ms_per_step": round(step_ms, 3),
-                  "gemm_tflops_all": round(all_gemm, 2)},
-        "latency_ms": {"what": "mem_complete on one 256x256 map", "mean": round(float(lat.mean()), 4),
-                       "std": round(float(lat.std()), 4), "median": round(float(np.median(lat)), 4),
-                       "p90": round(float(np.percentile(lat, 90)), 4)},
+        "train": train_info,
+        "latency_ms": lat,
         "quality": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in q.items()},
         "kernels": kernels,
-        "roofline": {"kernel": dom, "bound": "mfma", "achieved": ach, "peak": MFMA_BF16_PEAK_TFS,
-                     "unit": "TFLOP/s", "frac": round(ach / MFMA_BF16_PEAK_TFS, 4), "traffic": None},
+        "roofline": roof,
     }
     print(json.dumps(out), flush=True)
 
@@ -774,6 +913,78 @@ def time_normals_large(torch, side=4096):
     return r
 
 
+def calibration(torch, copy_bytes=1 << 30, atomic_words=1 << 24):
+    """Peaks measured on this GPU with the library's calibration kernels
+    (include/mem_calib.h), HIP events on the stream they run on:
+    copy     1 GiB read and 1 GiB written per launch (16-byte non-temporal
+             loads and stores), GB/s counted as bytes read + written;
+    atomics  G adds per second of 2^24 relaxed device-scope adds, binary32
+             and int32, on unique consecutive words (a wave's 64 lanes on
+             256 contiguous bytes), on a bijection of 2^24 words that puts
+             neighbouring lanes far apart (the point ingest's flush of
+             scattered cells) and on 64 shared words (contention)."""
+    from paper_2309_16818_amd import mem
+    s = torch.cuda.current_stream()
+
+    def timeit(fn, reps):
+        fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        for _ in range(reps):
+            fn()
+        b.record(s)
+        b.synchronize()
+        return a.elapsed_time(b) / reps
+
+    src = torch.ones(copy_bytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    ms = timeit(lambda: mem.calib_copy(src, dst, stream=s), 20)
+    ok = bool(torch.equal(src[-4096:], dst[-4096:]))
+    del src, dst
+    out = {"copy": {"gbs": round(2 * copy_bytes / (ms * 1e-3) / 1e9, 1), "bytes_per_launch": 2 * copy_bytes,
+                    "avg_us": round(ms * 1e3, 2), "frac_of_8tbs": round(2 * copy_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "checked": ok}}
+    atom = {}
+    for dname, dt in (("f32", torch.float32), ("i32", torch.int32)):
+        buf = torch.zeros(atomic_words, dtype=dt, device="cuda")
+        for pname, pat, n_addr in (("unique", mem.MEM_CALIB_UNIQUE, atomic_words),
+                                   ("scatter", mem.MEM_CALIB_SCATTER, atomic_words),
+                                   ("shared64", mem.MEM_CALIB_SHARED, 64)):
+            ms = timeit(lambda: mem.calib_atomic(buf, pat, atomic_words, n_addr, stream=s), 10)
+            atom[f"{dname}_{pname}"] = round(atomic_words / (ms * 1e-3) / 1e9, 2)
+        del buf
+    out["atomics_gops"] = atom
+    return out
+
+
+def kernel_rooflines(kernels, st, cal):
+    """HBM roofline of the point ingest, the finalize pass and the pixel
+    gather over the timed frames (algorithmic bytes of kernel_bytes per
+    average launch time, against the 8 TB/s peak and the measured copy
+    rate), and the ingest's global atomics (3 per flushed cell sum: count,
+    weight sum, weighted-height sum) per second of ingest time against the
+    measured rate of scattered binary32 adds."""
+    out = {}
+    copy = cal["copy"]["gbs"]
+    for name in ("ingest", "finalize", "gather_fuse"):
+        k = kernels.get(name)
+        if not k or not k["alg_gbs"]:
+            continue
+        out[name] = {"bound": "hbm", "achieved": k["alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(k["alg_gbs"] / HBM_PEAK_GBS, 4), "frac_of_copy": round(k["alg_gbs"] / copy, 4),
+                     "bytes_per_launch": round(kernel_bytes(name, st, k["launches"]) / k["launches"]),
+                     "avg_us": k["avg_us"], "traffic": traffic_bytes(name)}
+    k = kernels.get("ingest")
+    if k and st.get("cell_flushes"):
+        ops = 3 * st["cell_flushes"]
+        rate = ops / (k["total_ms"] * 1e-3) / 1e9
+        peak = cal["atomics_gops"]["f32_scatter"]
+        out["ingest"]["atomics"] = {"ops_per_launch": round(ops / k["launches"]), "achieved_gops": round(rate, 2),
+                                    "peak_gops": peak, "frac": round(rate / peak, 4),
+                                    "peak_is": "measured scattered binary32 atomic adds"}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -875,39 +1086,80 @@ def main():
                        "median": round(float(np.median(lat)), 4), "p90": round(float(np.percentile(lat, 90)), 4)},
         "stats": st, "kernels": kernels, "roofline": roof, "post": post,
     }
+    cal = calibration(torch)
+    out["calibration"] = cal
+    out["rooflines"] = kernel_rooflines(kernels, st, cal)
+    if args.legs:
+        out["batched"] = batch_leg(args.leg_maps, 10, 2, 1)
+        print(f"# batched leg: {out['batched']['value']:.4g} points/s", file=sys.stderr, flush=True)
+        out["learned"] = learned_leg()
+        print(f"# learned leg: {out['learned']['train']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(frames[:args.cpu_frames])
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(frames, min_seconds=10.0, max_passes=4):
-    """The oracle (plain C, one thread) on the first frames of the same
-    workload, from an empty map, passed over again (the map keeps its
-    state, as a robot driving the loop twice would) until at least
-    `min_seconds` of CPU work are timed or `max_passes` passes are done."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def oracle_pass(frames, counter=None):
+    """One oracle map (plain C, one thread) over `frames` from an empty map;
+    returns the accepted points."""
     import oracle as O
     from paper_2309_16818_amd import synth
     p = dict(synth.FULL_MAP)
     o = O.OracleMap(p.pop("width"), p.pop("height"), p.pop("resolution"), layers=synth.FULL_LAYERS, **p)
     acc = 0
-    passes = 0
+    for f in frames:
+        x, y, _ = f["pose"]
+        o.move(x, y)
+        for c in f["clouds"]:
+            cells = o.input_pointcloud(c["xyz"], c["T"])
+            acc += int((cells >= 0).sum())
+        for c in f["cameras"]:
+            o.input_image(c["rgb"], c["K"], c["T"], bind=[(8, 0, 3)])
+            o.input_image(c["features"], c["K_feat"], c["T"], bind=[(9, 0, 64)])
+            o.input_image(c["classes"], c["K"], c["T"], bind=[(10, 0, 20)])
+    o.close()
+    return acc
+
+
+def cpu_baseline(frames, target_cpu_s=20.0, max_threads=16):
+    """The oracle as it stands on the host's cores, for a bounded sample of
+    the same workload.  One thread first runs one map over the first frames
+    from an empty map (the single-core rate); then one independent oracle
+    map per core (threads; the oracle's calls release the interpreter lock)
+    each runs over the first k frames, k chosen so that the cores together
+    do about `target_cpu_s` seconds of work: the all-core rate is the
+    accepted points of every map over the wall time.  Cores: the threads
+    used, at most the CPUs this process may run on and at most 16."""
+    import concurrent.futures as cf
+    n1 = min(len(frames), 3)
     t0 = time.perf_counter()
-    while passes < max_passes and (passes == 0 or time.perf_counter() - t0 < min_seconds):
-        for f in frames:
-            x, y, _ = f["pose"]
-            o.move(x, y)
-            for c in f["clouds"]:
-                cells = o.input_pointcloud(c["xyz"], c["T"])
-                acc += int((cells >= 0).sum())
-            for c in f["cameras"]:
-                o.input_image(c["rgb"], c["K"], c["T"], bind=[(8, 0, 3)])
-                o.input_image(c["features"], c["K_feat"], c["T"], bind=[(9, 0, 64)])
-                o.input_image(c["classes"], c["K"], c["T"], bind=[(10, 0, 20)])
-        passes += 1
-    dt = time.perf_counter() - t0
-    return {"value": round(acc / dt, 1), "unit": "points/s", "cores": 1, "kind": "oracle",
-            "sample": f"{passes} pass(es) over {len(frames)} frame(s) of the same workload from an empty map "
-                      f"({acc} accepted points, {dt:.1f} s)"}
+    acc1 = oracle_pass(frames[:n1])
+    dt1 = time.perf_counter() - t0
+    per_frame = dt1 / n1
+    threads = max(1, min(max_threads, len(os.sched_getaffinity(0))))
+    k = max(1, min(len(frames), int(round(target_cpu_s / (threads * per_frame)))))
+    t1 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        accs = list(ex.map(lambda _: oracle_pass(frames[:k]), range(threads)))
+    dtn = time.perf_counter() - t1
+    return {"value": round(sum(accs) / dtn, 1), "unit": "points/s", "cores": threads, "kind": "oracle",
+            "sample": f"{threads} independent oracle maps, one per thread, each over the first {k} frame(s) of "
+                      f"the same workload from an empty map ({sum(accs)} accepted points in {dtn:.1f} s wall)",
+            "single_core": {"value": round(acc1 / dt1, 1), "unit": "points/s", "cores": 1,
+                            "sample": f"one map over the first {n1} frame(s) ({acc1} accepted points, {dt1:.1f} s)"},
+            "cpu_model": cpu_model(), "cpus_available": len(os.sched_getaffinity(0))}
+
 
 if __name__ == "__main__":
     main()

@@ -159,6 +159,13 @@ typedef struct mem_stats {
                                    (ray_cells is smaller where runs of cells are
                                    ruled out by their block maxima)              */
     int64_t occl_steps;         /* likewise for the occlusion rays               */
+    int64_t cell_flushes;       /* (cell, workgroup) sums the point ingest added
+                                   into a cloud's per-cell accumulators with
+                                   global atomics: 3 each (count, sum of
+                                   weights, weighted heights) plus one per
+                                   bound channel plane held in LDS; 0 for
+                                   batches, whose ingest writes its sums with
+                                   plain stores                                 */
 } mem_stats;
 
 /* Creates a map centred on cell (0, 0) with every cell empty: no height,
@@ -458,6 +465,16 @@ mem_status mem_batch_set_layer(mem_batch* batch, int32_t map, int32_t layer, int
 mem_status mem_batch_get_center(const mem_batch* batch, int32_t map, int32_t* cx, int32_t* cy);
 mem_status mem_batch_get_stats(mem_batch* batch, mem_stats* out, void* stream);
 mem_status mem_batch_reset_stats(mem_batch* batch, void* stream);
+
+/* Per-stage event timing of a batch's steps, as mem_profile_enable /
+ * mem_profile_read for a map.  While enabled, mem_batch_step launches its
+ * stages directly on `stream` (not as the captured graph) with two events
+ * around each; names: b_prep, b_reset, b_bin, b_tile_ingest, b_logical,
+ * b_march, b_finalize, b_project, b_gather.  mem_batch_profile_read waits
+ * for the recorded events, returns per name the launches and summed
+ * milliseconds, and clears the totals. */
+mem_status mem_batch_profile_enable(mem_batch* batch, int32_t on);
+mem_status mem_batch_profile_read(mem_batch* batch, mem_kernel_time* out, int32_t max, int32_t* count);
 
 /* ---------------------------------------------------------------------- */
 /* Learned completion of the height layers                                 */

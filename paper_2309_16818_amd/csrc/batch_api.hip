@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "mem_internal.h"
+#include "prof.h"
 
 using namespace memk;
 
@@ -107,6 +108,7 @@ struct mem_batch {
     BatchLaunch bl{1024, 1024, 16};
     bool use_graph = true;
     double tuned_ms = 0.0;
+    Profiler prof;  // while on, steps launch directly with events around every stage
 };
 
 namespace {
@@ -134,6 +136,7 @@ mem_status busable(const mem_batch* b)
 
 void free_batch(mem_batch* b)
 {
+    b->prof.release();
     for (auto& s : b->stg) {
         if (s.exec) (void)hipGraphExecDestroy(s.exec);
         if (s.graph) (void)hipGraphDestroy(s.graph);
@@ -367,14 +370,14 @@ mem_status prepare(mem_batch* b, const mem_batch_input* in, Staging& s, size_t* 
     return MEM_OK;
 }
 
-void enqueue_step(mem_batch* b, hipStream_t s, Staging& st, size_t bytes, const mem_batch_input* in)
+void enqueue_step(mem_batch* b, hipStream_t s, Staging& st, size_t bytes, const mem_batch_input* in, Profiler* prof)
 {
     (void)hipMemcpyAsync(b->tables, st.host, bytes, hipMemcpyHostToDevice, s);
     std::vector<LayerDev> L;
     for (auto& l : b->layers) L.push_back(l.dev());
     launch_batch_step(s, device_view(b), b->bl, in->xyz, b->c0, b->c1, b->mr2, b->margin, b->clear_min,
                       L.data(), (int)L.size(), in->images, b->cam_dtype, b->cam_c, b->cam_w,
-                      b->img_bind.data(), (int)b->img_bind.size());
+                      b->img_bind.data(), (int)b->img_bind.size(), prof);
 }
 
 mem_status run_step(mem_batch* b, const mem_batch_input* in, hipStream_t s)
@@ -387,7 +390,7 @@ mem_status run_step(mem_batch* b, const mem_batch_input* in, hipStream_t s)
         b->grid = saved;
         return r;
     }
-    if (b->use_graph) {
+    if (b->use_graph && !b->prof.on) {
         // The graph copies the whole table region, so its node is independent
         // of this step's item count.
         const size_t full = b->tables_bytes;
@@ -400,7 +403,7 @@ mem_status run_step(mem_batch* b, const mem_batch_input* in, hipStream_t s)
             st.exec = nullptr;
             st.graph = nullptr;
             BTRY(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-            enqueue_step(b, b->cap_stream, st, full, in);
+            enqueue_step(b, b->cap_stream, st, full, in, nullptr);
             BTRY(b, hipStreamEndCapture(b->cap_stream, &st.graph));
             BTRY(b, hipGraphInstantiate(&st.exec, st.graph, nullptr, nullptr, 0));
             st.key_xyz = in->xyz;
@@ -409,7 +412,7 @@ mem_status run_step(mem_batch* b, const mem_batch_input* in, hipStream_t s)
         }
         BTRY(b, hipGraphLaunch(st.exec, s));
     } else {
-        enqueue_step(b, s, st, bytes, in);
+        enqueue_step(b, s, st, bytes, in, b->prof.on ? &b->prof : nullptr);
         BTRY(b, hipGetLastError());
     }
     BTRY(b, hipEventRecord(st.done, s));
@@ -791,6 +794,21 @@ mem_status mem_batch_reset_stats(mem_batch* b, void* stream)
     launch_zero_int((hipStream_t)stream, (int*)b->stats, 2 * kStats * kStatSlots);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return bfail(b, e, "mem_batch_reset_stats");
+    return MEM_OK;
+}
+
+mem_status mem_batch_profile_enable(mem_batch* b, int32_t on)
+{
+    if (mem_status st = busable(b)) return st;
+    b->prof.enable(on != 0);
+    return MEM_OK;
+}
+
+mem_status mem_batch_profile_read(mem_batch* b, mem_kernel_time* out, int32_t max, int32_t* count)
+{
+    if (mem_status st = busable(b)) return st;
+    if (!count || (max > 0 && !out)) return api_fail(MEM_E_ARG, "NULL output");
+    *count = b->prof.read(out, max);
     return MEM_OK;
 }
 

@@ -17,6 +17,7 @@
 //   k_b_finalize  every cell (dense): height fusion and clearing
 //   k_b_project   (map, tile) items: frustum, pixel, occlusion, pair lists
 //   k_b_gather    (map, pair chunk) items: pixel gather and fusion
+#include "prof.h"
 #include "update.h"
 
 namespace memk {
@@ -450,28 +451,40 @@ size_t batch_tile_ingest_lds_bytes(int tile_h)
 void launch_batch_step(hipStream_t s, const BatchDev& d, const BatchLaunch& bl, const float* xyz,
                        float c0, float c1, float mr2, float margin, int clear_min,
                        const LayerDev* L, int nL, const void* images, int img_dtype, int cam_c,
-                       int cam_w, const mem_binding* ib, int n_ib)
+                       int cam_w, const mem_binding* ib, int n_ib, Profiler* prof)
 {
+    // every stage bracketed by events while a profiler is given
+    auto stage = [&](const char* name, auto&& f) {
+        if (prof)
+            prof->timed(s, name, f);
+        else
+            f();
+    };
     const int pre = (d.n_maps > kQueues ? d.n_maps : kQueues);
-    hipLaunchKernelGGL(k_b_prep, dim3((pre + 255) / 256), dim3(256), 0, s, d);
+    stage("b_prep", [&] { hipLaunchKernelGGL(k_b_prep, dim3((pre + 255) / 256), dim3(256), 0, s, d); });
     BatchLayers ls;
     ls.n = nL;
     for (int l = 0; l < nL; l++) ls.L[l] = L[l];
-    hipLaunchKernelGGL(k_b_reset, dim3(bl.grid), dim3(kBatchWG), 0, s, d, ls);
+    stage("b_reset", [&] { hipLaunchKernelGGL(k_b_reset, dim3(bl.grid), dim3(kBatchWG), 0, s, d, ls); });
     int64_t zb = (d.total_cells + 255) / 256;
     if (zb > 8192) zb = 8192;
-    hipLaunchKernelGGL(k_b_bin, dim3(bl.grid), dim3(kBatchWG), 0, s, d, xyz, c0, c1, mr2);
-    hipLaunchKernelGGL(k_b_tile_ingest, dim3(bl.grid), dim3(kBatchWG), tile_ingest_dyn_lds(d.itile_h), s,
-                       d);
+    stage("b_bin", [&] { hipLaunchKernelGGL(k_b_bin, dim3(bl.grid), dim3(kBatchWG), 0, s, d, xyz, c0, c1, mr2); });
+    stage("b_tile_ingest", [&] {
+        hipLaunchKernelGGL(k_b_tile_ingest, dim3(bl.grid), dim3(kBatchWG), tile_ingest_dyn_lds(d.itile_h), s, d);
+    });
     if (clear_min > 0) {
         int64_t lb = (d.total_cells + kLogicalRange - 1) / kLogicalRange;
         if (lb > 4096) lb = 4096;
-        hipLaunchKernelGGL(k_b_logical, dim3((unsigned)lb), dim3(256), 0, s, d);
-        hipLaunchKernelGGL(k_b_march, dim3(bl.grid), dim3(kBatchWG), 0, s, d, xyz, mr2, margin);
+        stage("b_logical", [&] { hipLaunchKernelGGL(k_b_logical, dim3((unsigned)lb), dim3(256), 0, s, d); });
+        stage("b_march", [&] {
+            hipLaunchKernelGGL(k_b_march, dim3(bl.grid), dim3(kBatchWG), 0, s, d, xyz, mr2, margin);
+        });
     }
-    hipLaunchKernelGGL(k_b_finalize, dim3((unsigned)zb), dim3(256), 0, s, d, clear_min);
+    stage("b_finalize", [&] {
+        hipLaunchKernelGGL(k_b_finalize, dim3((unsigned)zb), dim3(256), 0, s, d, clear_min);
+    });
     if (!images) return;
-    hipLaunchKernelGGL(k_b_project, dim3(bl.grid), dim3(kBatchWG), 0, s, d, bl.tile);
+    stage("b_project", [&] { hipLaunchKernelGGL(k_b_project, dim3(bl.grid), dim3(kBatchWG), 0, s, d, bl.tile); });
     for (int b = 0; b < n_ib; b++) {
         const LayerDev& Lb = L[ib[b].layer - MEM_LAYER_USER0];
         int lpp_log2 = 0;
@@ -480,15 +493,17 @@ void launch_batch_step(hipStream_t s, const BatchDev& d, const BatchLaunch& bl, 
 #define MEM_BG(IMG, S)                                                                            \
     hipLaunchKernelGGL((k_b_gather<IMG, S>), dim3(bl.grid), dim3(kBatchWG), 0, s, d, 4 + b, images, \
                        cam_c, cam_w, ib[b].ch_first, Lb, lpp_log2, ib[b].topk)
-        if (img_dtype == MEM_U8) {
-            if (Lb.storage == MEM_BF16) MEM_BG(MEM_U8, MEM_BF16);
-            else if (Lb.storage == MEM_FP8_E4M3) MEM_BG(MEM_U8, MEM_FP8_E4M3);
-            else MEM_BG(MEM_U8, MEM_F32);
-        } else {
-            if (Lb.storage == MEM_BF16) MEM_BG(MEM_F32, MEM_BF16);
-            else if (Lb.storage == MEM_FP8_E4M3) MEM_BG(MEM_F32, MEM_FP8_E4M3);
-            else MEM_BG(MEM_F32, MEM_F32);
-        }
+        stage("b_gather", [&] {
+            if (img_dtype == MEM_U8) {
+                if (Lb.storage == MEM_BF16) MEM_BG(MEM_U8, MEM_BF16);
+                else if (Lb.storage == MEM_FP8_E4M3) MEM_BG(MEM_U8, MEM_FP8_E4M3);
+                else MEM_BG(MEM_U8, MEM_F32);
+            } else {
+                if (Lb.storage == MEM_BF16) MEM_BG(MEM_F32, MEM_BF16);
+                else if (Lb.storage == MEM_FP8_E4M3) MEM_BG(MEM_F32, MEM_FP8_E4M3);
+                else MEM_BG(MEM_F32, MEM_F32);
+            }
+        });
 #undef MEM_BG
     }
 }

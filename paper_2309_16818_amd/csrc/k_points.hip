@@ -86,9 +86,9 @@ __global__ __launch_bounds__(kWG) void k_ingest(Grid g, const float* __restrict_
     const int64_t end = begin + kChunk < n ? begin + kChunk : n;
     PointCounts pc;
     ingest_range<kChunk / kWG>(g, xyz, begin, end, ch, T, c0, c1, mr2, pb, acc, lds, pc);
-    const int ids[5] = {ST_ACCEPTED, ST_NONFINITE, ST_RANGE, ST_OUTSIDE, ST_POINTS_IN};
-    int vals[5] = {pc.acc, pc.nonfinite, pc.range, pc.outside,
-                   pc.acc + pc.nonfinite + pc.range + pc.outside};
+    const int ids[6] = {ST_ACCEPTED, ST_NONFINITE, ST_RANGE, ST_OUTSIDE, ST_POINTS_IN, ST_FLUSHES};
+    int vals[6] = {pc.acc, pc.nonfinite, pc.range, pc.outside,
+                   pc.acc + pc.nonfinite + pc.range + pc.outside, pc.flushed};
     block_stats(stats, ids, vals);
 }
 

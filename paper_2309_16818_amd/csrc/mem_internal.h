@@ -29,7 +29,7 @@ namespace memk {
 
 constexpr int kMaxBind = 8;
 constexpr int kMaxTopk = 64;  // classes listed per top-k class input
-constexpr int kStats = 13;  // device counters, order of mem_stats
+constexpr int kStats = 14;  // device counters, order of mem_stats
 // Device counters are [kStats][kStatSlots]: a workgroup adds into slot
 // (block id mod kStatSlots), so no single address sees more than
 // 1/kStatSlots of the atomics.
@@ -48,7 +48,8 @@ enum Stat {
     ST_VISIBLE,
     ST_OCCL_CELLS,
     ST_RAY_STEPS,
-    ST_OCCL_STEPS
+    ST_OCCL_STEPS,
+    ST_FLUSHES
 };
 
 // Grid geometry handed to every kernel.
@@ -248,10 +249,12 @@ struct BatchLaunch {        // tuning of one step
     int tile;               // projection tile side (8 or 16)
 };
 
+struct Profiler;
+// prof: every stage's launch bracketed by events (NULL: none).
 void launch_batch_step(hipStream_t s, const BatchDev& d, const BatchLaunch& bl, const float* xyz,
                        float c0, float c1, float mr2, float margin, int clear_min,
                        const LayerDev* L, int nL, const void* images, int img_dtype, int cam_c,
-                       int cam_w, const mem_binding* ib, int n_ib);
+                       int cam_w, const mem_binding* ib, int n_ib, Profiler* prof);
 // All LDS (static and dynamic) a tile-owned ingest workgroup needs for tiles
 // of kIngestTileW x tile_h cells.
 size_t batch_tile_ingest_lds_bytes(int tile_h);

@@ -37,6 +37,7 @@ struct IngestLds {
 
 struct PointCounts {
     int acc = 0, nonfinite = 0, range = 0, outside = 0;
+    int flushed = 0;  // cells whose sums this thread flushed with global atomics
 };
 
 // Aggregates points [begin, end) of a cloud (at most 2^slots_log2 / 2
@@ -137,6 +138,7 @@ __device__ __forceinline__ void ingest_range(const Grid& g, const float* __restr
     for (int slot = threadIdx.x; slot < slots; slot += nthr) {
         const int st = lds.key[slot];
         if (st < 0) continue;
+        pc.flushed++;
         const int c = lds.cnt[slot];
         atomicAdd(&acc.cnt[st], c);
         unsafeAtomicAdd(&acc.wsum[st], lds.w[slot]);

@@ -25,7 +25,7 @@ MEM_VIEW_VALUE, MEM_VIEW_AUX, MEM_VIEW_ARGMAX = 0, 1, 2
 
 STAT_FIELDS = ("points_in", "points_accepted", "dropped_nonfinite", "dropped_range", "dropped_outside",
                "cells_touched", "cells_cleared", "ray_cells", "cells_in_view", "pairs_visible",
-               "occl_cells", "ray_steps", "occl_steps")
+               "occl_cells", "ray_steps", "occl_steps", "cell_flushes")
 
 # Exported symbols of include/mem.h.
 SYMBOLS = ("mem_create", "mem_destroy", "mem_move", "mem_input_pointcloud", "mem_input_image",
@@ -114,8 +114,39 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         fn.restype = C.c_int32
     L.mem_last_error.restype = C.c_char_p
     L.mem_last_error.argtypes = []
+    L.mem_calib_copy.argtypes = [P, P, I64, P]
+    L.mem_calib_copy.restype = C.c_int
+    L.mem_calib_atomic.argtypes = [P, I32, I32, I64, I64, P]
+    L.mem_calib_atomic.restype = C.c_int
+    L.mem_calib_last_error.argtypes = []
+    L.mem_calib_last_error.restype = C.c_char_p
     _lib = L
     return L
+
+
+# Calibration kernels of include/mem_calib.h (the measured peaks).
+CALIB_SYMBOLS = ("mem_calib_copy", "mem_calib_atomic", "mem_calib_last_error")
+MEM_CALIB_I32, MEM_CALIB_F32 = 0, 1
+MEM_CALIB_UNIQUE, MEM_CALIB_SCATTER, MEM_CALIB_SHARED = 0, 1, 2
+
+
+def calib_copy(src: torch.Tensor, dst: torch.Tensor, stream=None):
+    """mem_calib_copy of src's bytes into dst (device tensors, same size)."""
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nb or not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("dst must be contiguous and hold src's bytes")
+    if load().mem_calib_copy(_dev_ptr(src, "src"), _dev_ptr(dst, "dst"), nb, _stream(stream)) != 0:
+        raise MemError(MEM_E_ARG, load().mem_calib_last_error().decode())
+
+
+def calib_atomic(buf: torch.Tensor, pattern: int, n_ops: int, n_addr: int | None = None, stream=None):
+    """mem_calib_atomic: n_ops atomic adds of 1 into buf (int32 or float32)."""
+    dt = {torch.int32: MEM_CALIB_I32, torch.float32: MEM_CALIB_F32}[buf.dtype]
+    n_addr = buf.numel() if n_addr is None else n_addr
+    if n_addr > buf.numel():
+        raise ValueError("n_addr exceeds the buffer")
+    if load().mem_calib_atomic(_dev_ptr(buf, "buf"), dt, pattern, n_ops, n_addr, _stream(stream)) != 0:
+        raise MemError(MEM_E_ARG, load().mem_calib_last_error().decode())
 
 
 def _check(code: int):
@@ -403,7 +434,7 @@ class mem_batch_tuning(C.Structure):
 BATCH_SYMBOLS = ("mem_batch_create", "mem_batch_destroy", "mem_batch_step", "mem_batch_tune",
                  "mem_batch_set_tuning", "mem_batch_get_tuning", "mem_batch_get_layer",
                  "mem_batch_set_layer", "mem_batch_get_center", "mem_batch_get_stats",
-                 "mem_batch_reset_stats")
+                 "mem_batch_reset_stats", "mem_batch_profile_enable", "mem_batch_profile_read")
 
 
 def _load_batch():
@@ -423,6 +454,8 @@ def _load_batch():
         "mem_batch_get_center": [P, I32, C.POINTER(I32), C.POINTER(I32)],
         "mem_batch_get_stats": [P, C.POINTER(mem_stats), P],
         "mem_batch_reset_stats": [P, P],
+        "mem_batch_profile_enable": [P, I32],
+        "mem_batch_profile_read": [P, C.POINTER(mem_kernel_time), I32, C.POINTER(I32)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -551,6 +584,17 @@ class Batch:
 
     def reset_stats(self, stream=None):
         _check(_load_batch().mem_batch_reset_stats(self._b, _stream(stream)))
+
+    def profile_enable(self, on: bool = True):
+        """While on, steps launch their stages directly with events around each."""
+        _check(_load_batch().mem_batch_profile_enable(self._b, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        """{stage: (launches, total_ms)} since the last read."""
+        arr = (mem_kernel_time * 64)()
+        n = C.c_int32()
+        _check(_load_batch().mem_batch_profile_read(self._b, arr, 64, C.byref(n)))
+        return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(min(n.value, 64))}
 
 
 UNET_SYMBOLS = ("mem_unet_num_params", "mem_unet_create", "mem_unet_destroy", "mem_unet_set_params",

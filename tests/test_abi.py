@@ -10,9 +10,11 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_symbols():
-    text = open(os.path.join(ROOT, "include", "mem.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:mem_status|const char\*|int64_t)\s+(mem_\w+)\s*\(", text, re.M)))
+def declared_symbols(header=None):
+    inc = os.path.join(ROOT, "include")
+    names = [header] if header else sorted(f for f in os.listdir(inc) if f.endswith(".h"))
+    text = "".join(open(os.path.join(inc, f)).read() for f in names)
+    return sorted(set(re.findall(r"^\s*(?:mem_status|const char\*|int64_t|int)\s+(mem_\w+)\s*\(", text, re.M)))
 
 
 def test_header_declares_the_boundary():
@@ -27,7 +29,22 @@ def test_library_exports_every_declared_symbol():
     lib = mem.load()
     for s in declared_symbols():
         assert hasattr(lib, s), s
-    assert sorted(mem.SYMBOLS + mem.BATCH_SYMBOLS + mem.UNET_SYMBOLS) == declared_symbols()
+    assert sorted(mem.SYMBOLS + mem.BATCH_SYMBOLS + mem.UNET_SYMBOLS + mem.CALIB_SYMBOLS) == declared_symbols()
+    assert sorted(mem.CALIB_SYMBOLS) == declared_symbols("mem_calib.h")
+
+
+def test_calibration_kernels_reject_bad_arguments():
+    from paper_2309_16818_amd import mem
+    lib = mem.load()
+    assert lib.mem_calib_copy(None, None, 16, None) == -1
+    assert lib.mem_calib_copy(C.c_void_p(16), C.c_void_p(32), 15, None) == -1
+    assert lib.mem_calib_copy(C.c_void_p(8), C.c_void_p(32), 16, None) == -1
+    assert lib.mem_calib_atomic(C.c_void_p(64), mem.MEM_CALIB_F32, mem.MEM_CALIB_SCATTER, 10, 12, None) == -1
+    assert lib.mem_calib_atomic(C.c_void_p(64), mem.MEM_CALIB_F32, mem.MEM_CALIB_SCATTER, 20, 16, None) == -1
+    assert lib.mem_calib_atomic(C.c_void_p(64), mem.MEM_CALIB_I32, mem.MEM_CALIB_UNIQUE, 20, 16, None) == -1
+    assert lib.mem_calib_atomic(C.c_void_p(64), 7, mem.MEM_CALIB_UNIQUE, 1, 1, None) == -1
+    assert lib.mem_calib_atomic(C.c_void_p(64), mem.MEM_CALIB_I32, 9, 1, 1, None) == -1
+    assert b"pattern" in lib.mem_calib_last_error()
 
 
 def test_struct_layouts_match_the_header():

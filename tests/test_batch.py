@@ -136,6 +136,38 @@ def test_batch_equals_independent_single_maps_and_graph_equals_direct():
                 assert torch.allclose(a[ok], b[ok], rtol=1e-5, atol=1e-6), (m, L, v)
 
 
+def test_profiled_steps_equal_graph_steps_and_time_every_stage():
+    """With per-stage events on, a step launches its stages directly; the
+    maps end equal to the same steps replayed as the captured graph."""
+    rng = np.random.default_rng(11)
+    A, P = make_batch(), make_batch()
+    P.profile_enable(True)
+    poses = [(rng.uniform(-1, 1), rng.uniform(-1, 1), rng.uniform(0, 6)) for _ in SIZES]
+    for it in range(2):
+        poses = walk(rng, poses)
+        counts = [int(c) for c in rng.integers(100, 4000, len(SIZES))]
+        xyz, offs, Ts, Tc, Ks, imgs = step_inputs(rng, SIZES, poses, counts)
+        run_batch_step(A, poses, xyz, offs, Ts, imgs, Ks, Tc)
+        run_batch_step(P, poses, xyz, offs, Ts, imgs, Ks, Tc)
+    kern = P.profile_read()
+    for stage in ("b_prep", "b_reset", "b_bin", "b_tile_ingest", "b_logical", "b_march", "b_finalize",
+                  "b_project", "b_gather"):
+        # two steps; the gather runs once per image binding (two)
+        assert kern[stage][0] == (2 * len(IMG_BIND) if stage == "b_gather" else 2), (stage, kern.get(stage))
+        assert kern[stage][1] > 0.0
+    P.profile_enable(False)
+    # integers exact; floats to the batch's own run-to-run bar (its per-cell
+    # sums are LDS atomics, so their order differs between runs)
+    for m in range(len(SIZES)):
+        for L in (2, 3, 4):
+            assert torch.equal(A.get_layer(m, L), P.get_layer(m, L)), (m, L)
+        for L, v in ((0, 0), (1, 0), (8, 0), (8, 1), (9, 0)):
+            a, b = A.get_layer(m, L, v), P.get_layer(m, L, v)
+            assert torch.equal(torch.isnan(a), torch.isnan(b))
+            ok = ~torch.isnan(b) & ~torch.isinf(b)
+            assert torch.allclose(a[ok], b[ok], rtol=1e-5, atol=1e-6), (m, L, v)
+
+
 def test_maps_are_isolated():
     rng = np.random.default_rng(2)
     A, Bb = make_batch(), make_batch()
