@@ -339,6 +339,24 @@ mem_status mem_set_drift_compensation(mem_map* map, int32_t enable, float kappa,
 mem_status mem_pca(const mem_map* map, int32_t layer, float* out, float eigenvalues[3],
                    void* stream);
 
+/* mem_pca for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same result bit for bit, with the partial sums in a
+ * static device array of the library (about 17 MB, held by every GPU the
+ * library runs on until the process ends) instead of the map's scratch.
+ * Calls no hipMalloc, hipFree or allocating library routine and never waits
+ * for the stream.  out: as mem_pca.  eigenvalues: device, 3 floats, written
+ * on the stream, or NULL.  Every call on one GPU shares that array: calls
+ * that overlap on one GPU (different streams, or different host threads)
+ * race and must be serialised by the caller; nothing in the array needs to
+ * start cleared (every partial is written before it is read).  The first
+ * call on a device looks up the array's address there.  Limit: at most 64
+ * channels.  Errors: MEM_E_ARG (NULL out, no such layer, a DIRICHLET
+ * layer), MEM_E_UNSUPPORTED (more than 64 channels), MEM_E_HIP (the array's
+ * address could not be found, or a launch failed). */
+mem_status mem_pca_noalloc(const mem_map* map, int32_t layer, float* out, float* eigenvalues,
+                           void* stream);
+
 /* Overlap clearance after every later point cloud (Table I, "overlap
  * clearance", after the multi-modal update; the paper defines it nowhere).
  * When enabled, mem_input_pointcloud ends by removing every held height

@@ -17,6 +17,8 @@
 //                  eigenpairs with the sign convention.
 //   k_pca_project  one lane per logical cell: the centred vector's three
 //                  projections, NaN for cells with an unobserved channel.
+#include <mutex>
+
 #include "update.h"
 
 namespace memk {
@@ -147,7 +149,7 @@ constexpr int kEigLanes = 1024;
 static_assert(kPcaMaxC == 64 && (kPcaMaxC / 2) * kPcaMaxC == 2 * kEigLanes, "two (pair, column) elements per lane");
 
 __global__ __launch_bounds__(kEigLanes) void k_pca_eig(const PcaParts* __restrict__ P, int C,
-                                                       PcaOut* __restrict__ out)
+                                                       PcaOut* __restrict__ out, float* __restrict__ lam_out)
 {
     constexpr int n = kPcaMaxC, half = kPcaMaxC / 2;
     __shared__ double S[n][n + 1];
@@ -257,6 +259,8 @@ __global__ __launch_bounds__(kEigLanes) void k_pca_eig(const PcaParts* __restric
             out->lam[k] = S[best][best];
             for (int i = 0; i < kPcaMaxC; i++) out->comp[k][i] = i < C ? sg * V[i][best] : 0.0;
         }
+        if (lam_out)
+            for (int k = 0; k < kPcaK; k++) lam_out[k] = (float)out->lam[k];
     }
 }
 
@@ -293,7 +297,46 @@ size_t pca_scratch_bytes()
     return sizeof(PcaParts);
 }
 
-void launch_pca(hipStream_t s, const Grid& g, const LayerDev& L, void* scratch, PcaOut* res, float* out)
+// The scratch of mem_pca_noalloc: the partial sums, then the result, of one
+// PCA in a device array that every GPU the library runs on holds until the
+// process ends (about 17 MB), so that the call allocates nothing.  Its
+// address on a device comes from hipGetSymbolAddress, looked up once per
+// device with that device current; host code never uses the array's name.
+constexpr size_t kPcaPartsBytes = (sizeof(PcaParts) + 255) & ~(size_t)255;
+constexpr size_t kPcaStaticBytes = kPcaPartsBytes + sizeof(PcaOut);
+static __device__ __align__(256) char scratch[kPcaStaticBytes];
+
+size_t pca_static_scratch_bytes()
+{
+    return kPcaStaticBytes;
+}
+
+hipError_t pca_static_scratch(int device, void** parts, PcaOut** res)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static char* addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[device] = static_cast<char*>(p);
+    }
+    *parts = addr[device];
+    *res = reinterpret_cast<PcaOut*>(addr[device] + kPcaPartsBytes);
+    return hipSuccess;
+}
+
+void launch_pca(hipStream_t s, const Grid& g, const LayerDev& L, void* scratch, PcaOut* res, float* out,
+                float* lam_out)
 {
     PcaParts* P = static_cast<PcaParts*>(scratch);
     const int HW = g.W * g.H;
@@ -304,7 +347,7 @@ void launch_pca(hipStream_t s, const Grid& g, const LayerDev& L, void* scratch, 
     hipLaunchKernelGGL(k_pca_total, dim3((kPcaMaxC + 1 + 15) / 16), dim3(256), 0, s, P, nblk);
     hipLaunchKernelGGL(k_pca_cov, dim3(nblk), dim3(256), 0, s, L, HW, P);
     hipLaunchKernelGGL(k_pca_reduce, dim3(kPcaMaxC * kPcaMaxC / 16), dim3(256), 0, s, P, nblk);
-    hipLaunchKernelGGL(k_pca_eig, dim3(1), dim3(kEigLanes), 0, s, P, L.C, res);
+    hipLaunchKernelGGL(k_pca_eig, dim3(1), dim3(kEigLanes), 0, s, P, L.C, res, lam_out);
     hipLaunchKernelGGL(k_pca_project, dim3((HW + 255) / 256), dim3(256), 0, s, g, L, res, out);
 }
 

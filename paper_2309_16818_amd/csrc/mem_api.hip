@@ -595,7 +595,7 @@ mem_status mem_pca(const mem_map* mc, int32_t layer, float* out, float eigenvalu
         m->pca_out = o;
     }
     hipStream_t s = (hipStream_t)stream;
-    timed(m, s, "pca", [&] { launch_pca(s, m->grid(), L->dev(), m->pca_scratch, m->pca_out, out); });
+    timed(m, s, "pca", [&] { launch_pca(s, m->grid(), L->dev(), m->pca_scratch, m->pca_out, out, nullptr); });
     if (mem_status st = check_launch(m, "mem_pca")) return st;
     if (eigenvalues) {
         double lam[kPcaK];
@@ -604,6 +604,26 @@ mem_status mem_pca(const mem_map* mc, int32_t layer, float* out, float eigenvalu
         for (int k = 0; k < kPcaK; k++) eigenvalues[k] = (float)lam[k];
     }
     return MEM_OK;
+}
+
+mem_status mem_pca_noalloc(const mem_map* mc, int32_t layer, float* out, float* eigenvalues, void* stream)
+{
+    mem_map* m = const_cast<mem_map*>(mc);
+    if (mem_status st = usable(m)) return st;
+    if (!out) return fail(MEM_E_ARG, "out is NULL");
+    const Layer* L = nullptr;
+    if (mem_status st = resolve_layer(m, layer, &L)) return st;
+    if (L->rule == MEM_DIRICHLET) return fail(MEM_E_ARG, "layer %d is a class layer, not a feature layer", layer);
+    if (L->C > kPcaMaxC)
+        return fail(MEM_E_UNSUPPORTED, "PCA of %d channels: the static scratch holds at most %d", L->C, kPcaMaxC);
+    void* parts = nullptr;
+    PcaOut* res = nullptr;
+    const hipError_t e = pca_static_scratch(m->device, &parts, &res);
+    if (e != hipSuccess)
+        return fail(MEM_E_HIP, "address of the PCA's static scratch on device %d: %s", m->device, hipGetErrorString(e));
+    hipStream_t s = (hipStream_t)stream;
+    launch_pca(s, m->grid(), L->dev(), parts, res, out, eigenvalues);
+    return check_launch(m, "mem_pca_noalloc");
 }
 
 mem_status mem_set_overlap_clearance(mem_map* m, int32_t enable, float range_xy, float range_z)

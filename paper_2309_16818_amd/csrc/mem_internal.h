@@ -282,7 +282,13 @@ struct PcaOut {
     double n;  // cells with every channel observed
 };
 size_t pca_scratch_bytes();
-void launch_pca(hipStream_t s, const Grid& g, const LayerDev& L, void* scratch, PcaOut* res, float* out);
+// lam_out: device, kPcaK floats (the eigenvalues), or NULL.
+void launch_pca(hipStream_t s, const Grid& g, const LayerDev& L, void* scratch, PcaOut* res, float* out,
+                float* lam_out);
+// The PCA's partial sums and result in the library's static device array on
+// `device` (looked up on the first call for that device).
+size_t pca_static_scratch_bytes();
+hipError_t pca_static_scratch(int device, void** parts, PcaOut** res);
 // Surface normals of the heights h (storage order) into out ([H][W][3], logical order).
 void launch_normals(hipStream_t s, const Grid& g, const float* h, float* out);
 

@@ -30,7 +30,7 @@ STAT_FIELDS = ("points_in", "points_accepted", "dropped_nonfinite", "dropped_ran
 # Exported symbols of include/mem.h.
 SYMBOLS = ("mem_create", "mem_destroy", "mem_move", "mem_input_pointcloud", "mem_input_image",
            "mem_input_images", "mem_get_layer", "mem_set_layer", "mem_normals", "mem_set_drift_compensation", "mem_get_drift",
-           "mem_set_overlap_clearance", "mem_pca", "mem_input_image_poses",
+           "mem_set_overlap_clearance", "mem_pca", "mem_pca_noalloc", "mem_input_image_poses",
            "mem_get_center", "mem_debug_point_cells",
            "mem_debug_cell_pixels", "mem_get_stats", "mem_reset_stats", "mem_profile_enable",
            "mem_profile_read", "mem_last_error")
@@ -100,6 +100,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "mem_get_drift": [P, C.POINTER(F), C.POINTER(I32), P],
         "mem_set_overlap_clearance": [P, I32, F, F],
         "mem_pca": [P, I32, P, C.POINTER(F), P],
+        "mem_pca_noalloc": [P, I32, P, P, P],
         "mem_get_center": [P, C.POINTER(I32), C.POINTER(I32)],
         "mem_debug_point_cells": [P, P, I64, P, P, P],
         "mem_debug_cell_pixels": [P, I32, I32, P, P, P, P],
@@ -355,6 +356,17 @@ class Map:
         lam = (C.c_float * 3)()
         _check(load().mem_pca(self._h, layer, _dev_ptr(out, "out"), lam, _stream(stream)))
         return out, list(lam)
+
+    def pca_noalloc(self, layer: int, out: torch.Tensor, eigenvalues: torch.Tensor | None = None, stream=None):
+        """mem_pca_noalloc into caller-allocated device tensors: out [H, W, 3]
+        float32, eigenvalues [3] float32 or None; nothing waits for the stream."""
+        if out.dtype != torch.float32 or not out.is_contiguous() or out.numel() != self.H * self.W * 3:
+            raise ValueError("out must be a contiguous float32 tensor of H x W x 3 elements")
+        if eigenvalues is not None and (eigenvalues.dtype != torch.float32 or eigenvalues.numel() != 3
+                                        or not eigenvalues.is_contiguous()):
+            raise ValueError("eigenvalues must be a contiguous float32 tensor of 3 elements")
+        lp = _dev_ptr(eigenvalues, "eigenvalues") if eigenvalues is not None else None
+        _check(load().mem_pca_noalloc(self._h, layer, _dev_ptr(out, "out"), lp, _stream(stream)))
 
     def drift(self, stream=None):
         """(offset applied by the last point cloud, its consistent points)."""

@@ -112,6 +112,7 @@ def test_null_handles_are_rejected():
     assert lib.mem_get_drift(None, None, None, None) == mem.MEM_E_ARG
     assert lib.mem_set_overlap_clearance(None, 1, 4.0, 2.0) == mem.MEM_E_ARG
     assert lib.mem_pca(None, 8, None, None, None) == mem.MEM_E_ARG
+    assert lib.mem_pca_noalloc(None, 8, None, None, None) == mem.MEM_E_ARG
     assert lib.mem_input_image_poses(None, None, None, 2, None, None) == mem.MEM_E_ARG
     assert lib.mem_destroy(None, None) == mem.MEM_OK
 
