@@ -165,6 +165,19 @@ struct Ray {
         dz = pz - sz;
         all_inside = ax >= 0 && ax < g.W && ay >= 0 && ay < g.H;
     }
+    // The same ray from its reciprocal major extent and height difference
+    // as the constructor above computes them.
+    __device__ __forceinline__ Ray(const Grid& g, int ax, int ay, int bx, int by, float sx, float sy, float sz,
+                                   float inv_d_, float dz_, int /*tag*/)
+        : L(ax, ay, bx, by)
+    {
+        o_major = L.xmajor ? g.ox : g.oy;
+        s_major = L.xmajor ? sx : sy;
+        inv_d = inv_d_;
+        s_z = sz;
+        dz = dz_;
+        all_inside = ax >= 0 && ax < g.W && ay >= 0 && ay < g.H;
+    }
 };
 
 // Visits the cells strictly between the ray's end cells, in order, U at a

@@ -6,24 +6,26 @@
 //                  points into an LDS table keyed by cell, reduces equal cells
 //                  with LDS atomics, then issues one global atomic per
 //                  (cell, field) it saw.
-//   k_clear_march  the ray cast of Table I's "height update & ray cast":
+//   k_ray_prep     the ray cast of Table I's "height update & ray cast":
 //                  one ray per accepted point along Bresenham's line, voting
-//                  to clear cells whose height lies above the ray.  Rays of
-//                  up to kShortMax intermediate cells are walked one per
-//                  lane; longer ones are listed for
-//   k_clear_long   which walks each listed ray in segments of kSeg cells,
-//                  one segment per lane, so that no lane walks a whole long
-//                  ray while the rest of the chip idles.
+//                  to clear cells whose height lies above the ray.  Lists
+//                  every ray's segments of kSegLen cells, full ones apart
+//                  from each ray's shorter last one, for
+//   k_ray_walk     which walks one segment per lane, full segments first,
+//                  so that the waves walk segments of equal length.
 //   k_finalize     per-cell information-form Gaussian height fusion, clear
 //                  application, and fusion of bound point channels with the
 //                  layer's rule (Sec. III-C, Eq. (1), (2), (6)-(7), (12)).
+#include <algorithm>
+#include <cmath>
+
 #include "update.h"
 
 namespace memk {
 
 namespace {
 
-constexpr int kWG = 256;
+constexpr int kWG = 1024;             // threads per ingest workgroup (one point each)
 constexpr int kChunk = 1024;             // points per ingest workgroup
 constexpr int kSlotsLog2 = 11;
 constexpr int kSlots = 1 << kSlotsLog2;  // LDS hash slots (2 x points)
@@ -33,11 +35,7 @@ constexpr size_t kStaticLds = sizeof(int) * 2 * kSlots + sizeof(float) * 2 * kSl
 static_assert(kSlots >= 2 * kChunk, "hash table must never fill");
 static_assert(kChunk % kWG == 0, "whole points per ingest thread");
 
-constexpr int kShortMax = 64;   // longest ray (intermediate cells) walked by one lane
-constexpr int kSeg = 64;        // cells per lane segment of a long ray
-constexpr int kLongRays = 64;   // long rays per k_clear_long workgroup
-constexpr int kLongGrid = 2048; // k_clear_long workgroups at most
-constexpr int kSegTable = 1024; // segments of a k_clear_long batch found by table, not search
+constexpr int kWalkGrid = 1280;  // k_ray_walk workgroups: about five per CU
 
 // Clears the accumulators (`clr` in any order) and, if `hl` is given,
 // copies the heights into logical order for the clearing march.
@@ -46,13 +44,14 @@ __global__ __launch_bounds__(256) void k_zero_accum(Grid g, int* __restrict__ n,
                                                     float* __restrict__ ssum,
                                                     int* __restrict__ clr,
                                                     float* __restrict__ chsum, int Cb,
-                                                    int* __restrict__ zero1,
+                                                    int* __restrict__ march_counts,
                                                     const float* __restrict__ h,
                                                     float* __restrict__ hl,
                                                     DriftDev* __restrict__ drift)
 {
     const int HW = g.W * g.H;
-    if (zero1 && blockIdx.x == 0 && threadIdx.x == 0) *zero1 = 0;
+    if (march_counts && blockIdx.x == 0)
+        for (int k = threadIdx.x; k < kSegLists * kSegSubs; k += blockDim.x) march_counts[k] = 0;
     if (drift && blockIdx.x == 0 && threadIdx.x == 0) *drift = DriftDev{0.0, 0.0, 0, 0.0f};
     int stride = gridDim.x * blockDim.x;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < HW; i += stride) {
@@ -72,8 +71,9 @@ __global__ __launch_bounds__(256) void k_zero_accum(Grid g, int* __restrict__ n,
 __global__ __launch_bounds__(kWG) void k_ingest(Grid g, const float* __restrict__ xyz, int64_t n,
                                                 const float* __restrict__ ch, Pose T, float c0,
                                                 float c1, float mr2, PointBinds pb, Accum acc,
-                                                unsigned long long* __restrict__ stats)
+                                                MarchBufs mb, int march, unsigned long long* __restrict__ stats)
 {
+    __shared__ int s_march[kMarchLds];
     __shared__ int s_key[kSlots];
     __shared__ int s_cnt[kSlots];
     __shared__ float s_w[kSlots];
@@ -85,140 +85,125 @@ __global__ __launch_bounds__(kWG) void k_ingest(Grid g, const float* __restrict_
     const int64_t begin = (int64_t)blockIdx.x * kChunk;
     const int64_t end = begin + kChunk < n ? begin + kChunk : n;
     PointCounts pc;
-    ingest_range<kChunk / kWG>(g, xyz, begin, end, ch, T, c0, c1, mr2, pb, acc, lds, pc);
-    const int ids[6] = {ST_ACCEPTED, ST_NONFINITE, ST_RANGE, ST_OUTSIDE, ST_POINTS_IN, ST_FLUSHES};
-    int vals[6] = {pc.acc, pc.nonfinite, pc.range, pc.outside,
-                   pc.acc + pc.nonfinite + pc.range + pc.outside, pc.flushed};
+    ingest_range<kChunk / kWG>(g, xyz, begin, end, ch, T, c0, c1, mr2, pb, acc, lds, pc, march != 0, mb, s_march);
+    const int ids[7] = {ST_ACCEPTED, ST_NONFINITE, ST_RANGE, ST_OUTSIDE, ST_POINTS_IN, ST_FLUSHES, ST_RAY_STEPS};
+    int vals[7] = {pc.acc, pc.nonfinite, pc.range, pc.outside,
+                   pc.acc + pc.nonfinite + pc.range + pc.outside, pc.flushed, pc.ray_steps};
     block_stats(stats, ids, vals);
 }
 
-// One ray per lane.  Scan order puts rays of very different lengths side by
-// side (the beams of one LiDAR firing), and a wave runs as long as its
-// longest ray, so the workgroup first orders its 256 rays by length bucket
-// (8 cells per bucket; a counting sort in LDS) and each wave walks 64 rays
-// of similar length; neighbouring points stay in one workgroup, so the
-// walks still share cache lines.  Rays longer than kShortMax cells (the
-// last bucket) are appended to `longs` (indices into this launch's points)
-// instead: workgroups whose points lie far away would otherwise hold their
-// CU long after the rest of the grid has finished.
-__global__ __launch_bounds__(256) void k_clear_march(Grid g, Grid gl, const float* __restrict__ hl,
-                                                     const float* __restrict__ xyz, int64_t n, Pose T,
-                                                     float mr2, float margin, int* __restrict__ clr,
-                                                     int* __restrict__ longs,
-                                                     int* __restrict__ n_long,
-                                                     unsigned long long* __restrict__ stats)
+// The clearing march in two kernels.  k_ray_prep (one lane per point)
+// transforms the point, stores the ray's record (its cell, the reciprocal
+// of its major extent and its height difference)
+// and lists the ray's segments of kSegLen cells: every full segment in the
+// full list and the last, shorter segment (if any) in one of four lists by
+// its length (for 64-cell segments: 48-63, 32-47, 16-31, 1-15 cells).  Each list is split into
+// kSegSubs sub-lists with their own counters (workgroup b appends to
+// sub-list b mod kSegSubs, reserving its room with one atomic per list), so
+// no counter sees more than 1 / kSegSubs of the workgroups: atomics on one
+// address serialise.  k_ray_walk then hands each lane one segment in the
+// order full list, then the partial lists from the longest, so the lanes of
+// a wave walk segments of nearly equal length, every wave of the grid is
+// full, and no wave walks a whole long ray while others idle.  Each lane
+// enters its ray mid-way with the closed-form Bresenham jump; the votes are
+// those of walking every ray whole (integer atomics, any order).
+__global__ __launch_bounds__(256) void k_ray_prep(Grid g, const float* __restrict__ xyz, int64_t n, Pose T,
+                                                  float mr2, MarchBufs mb, unsigned long long* __restrict__ stats)
 {
-    constexpr int kBuckets = kShortMax / 8 + 2;  // none, 1-8, ..., 57-64, long
-    static_assert(kShortMax % 8 == 0, "length buckets of 8 cells");
-    __shared__ int s_long_base;
-    __shared__ int s_off[kBuckets];
-    __shared__ int s_order[256];
-    __shared__ int s_steps[256];
-    __shared__ float4 s_pt[256];
-    __shared__ int2 s_cell[256];
-    const int t = threadIdx.x;
-    const int64_t i = (int64_t)blockIdx.x * 256 + t;
+    __shared__ int s_march[kMarchLds];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     float px = 0.f, py = 0.f, pz = 0.f, r2;
-    int ix = 0, iy = 0, steps = 0;
-    const float sx = T.m[3], sy = T.m[7], sz = T.m[11];
+    int ix = 0, iy = 0;
     int ax, ay;
-    lattice_cell(g, sx, sy, ax, ay);
+    lattice_cell(g, T.m[3], T.m[7], ax, ay);
+    int steps[1] = {0};
+    const int ri[1] = {(int)i};  // a pass holds at most kMarchPass points
     if (i < n && point_cell(g, T, mr2, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], px, py, pz, r2, ix, iy) == 0)
-        steps = max(max(abs(ix - ax), abs(iy - ay)) - 1, 0);
-    s_steps[t] = steps;
-    s_pt[t] = make_float4(px, py, pz, 0.f);
-    s_cell[t] = make_int2(ix, iy);
-    const int src = order_by_length<kBuckets>(steps, s_off, s_order);
-    const int first_long = s_off[kBuckets - 1];  // the long rays are the last lanes
-    if (t == 0) {
-        const int nl = 256 - first_long;
-        s_long_base = nl > 0 ? atomicAdd(n_long, nl) : 0;
+        steps[0] = max(max(abs(ix - ax), abs(iy - ay)) - 1, 0);
+    if (steps[0] > 0) {
+        // the walks need the ray's reciprocal major extent and height
+        // difference, computed once here
+        const Ray ray(g, ax, ay, ix, iy, T.m[3], T.m[7], T.m[11], px, py, pz);
+        mb.rec[i] = make_float4(ray.inv_d, ray.dz, __int_as_float(ix | (iy << 16)), 0.0f);
     }
-    __syncthreads();
-    const int my_steps = s_steps[src];
-    int visited = 0;
-    if (t >= first_long) {
-        longs[s_long_base + t - first_long] = (int)((int64_t)blockIdx.x * 256 + src);
-    } else if (my_steps > 0) {
-        const float4 p = s_pt[src];
-        const int2 c = s_cell[src];
-        Ray ray(gl, ax, ay, c.x, c.y, sx, sy, sz, p.x, p.y, p.z);
-        visited = walk_logical<8>(gl, ray, hl, ClearVoteLogical{clr, g, margin});
-    }
-    const int ids[2] = {ST_RAY_CELLS, ST_RAY_STEPS};
-    int vals[2] = {visited, steps};
+    march_lists<1>(mb, ri, steps, s_march, s_march + kSegLists, s_march + 2 * kSegLists);
+    const int ids[1] = {ST_RAY_STEPS};
+    int vals[1] = {steps[0]};
     block_stats(stats, ids, vals);
 }
 
-// The listed long rays, kLongRays per workgroup: each ray is cut into
-// segments of kSeg cells (the last one shorter) and the workgroup's lanes
-// take the segments in turn, entering a ray mid-way with the closed-form
-// Bresenham jump; the votes are those of walking every ray whole.
-__global__ __launch_bounds__(256) void k_clear_long(Grid g, Grid gl, const float* __restrict__ hl,
-                                                    const float* __restrict__ xyz, Pose T,
-                                                    float mr2, float margin,
-                                                    int* __restrict__ clr,
-                                                    const int* __restrict__ longs,
-                                                    const int* __restrict__ n_long,
-                                                    unsigned long long* __restrict__ stats)
+__global__ __launch_bounds__(256) void k_ray_walk(Grid g, Grid gl, const float* __restrict__ hl, Pose T,
+                                                  float margin, int* __restrict__ clr, MarchBufs mb,
+                                                  unsigned long long* __restrict__ stats)
 {
-    __shared__ float4 s_pt[kLongRays];
-    __shared__ int2 s_cell[kLongRays];
-    __shared__ int s_pre[kLongRays + 1];  // exclusive prefix of the segment counts, then the total
-    __shared__ uint16_t s_seg[kSegTable];  // segment q: its ray | (its index within the ray << 6)
-    static_assert(kLongRays <= 64 && kSegTable <= 65536, "segment table entries are 16 bits");
-    const int t = threadIdx.x;
-    const int count = *n_long;
+    constexpr int NS = kSegLists * kSegSubs;
+    // exclusive prefix of the sub-lists' counts in walk order (list-major)
+    __shared__ int s_pre[NS + 1];
+    __shared__ int s_wave[4];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    {
+        static_assert(NS <= 2 * 256, "two sub-lists per thread");
+        // entries t and t + 256 of the list-major order: a workgroup scan of
+        // the first 256, then of the rest on top of their total
+        // counts clamped to the capacities (which bound them by construction)
+        auto count = [&](int e) {
+            const int64_t cap = e < kSegSubs ? mb.full_sub : mb.part_sub;
+            return e < NS ? (int)min((int64_t)mb.counts[e], cap) : 0;
+        };
+        const int a = count(t);
+        const int b = count(t + 256);
+        int incl = a;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_up(incl, o);
+            if (lane >= o) incl += u;
+        }
+        if (lane == 63) s_wave[w] = incl;
+        __syncthreads();
+        int base = 0;
+        for (int k = 0; k < w; k++) base += s_wave[k];
+        const int tot_a = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+        if (t < NS) s_pre[t] = base + incl - a;
+        __syncthreads();
+        int incl_b = b;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_up(incl_b, o);
+            if (lane >= o) incl_b += u;
+        }
+        if (lane == 63) s_wave[w] = incl_b;
+        __syncthreads();
+        int base_b = tot_a;
+        for (int k = 0; k < w; k++) base_b += s_wave[k];
+        if (t + 256 < NS) s_pre[t + 256] = base_b + incl_b - b;
+        if (t == 255) s_pre[NS] = base_b + incl_b;
+        __syncthreads();
+    }
+    const int total = s_pre[NS];
     const float sx = T.m[3], sy = T.m[7], sz = T.m[11];
     int ax, ay;
     lattice_cell(g, sx, sy, ax, ay);
+    const int wave = blockIdx.x * 4 + w, nwaves = gridDim.x * 4;
     int visited = 0;
-    for (int base = blockIdx.x * kLongRays; base < count; base += gridDim.x * kLongRays) {
-        if (t < kLongRays) {  // wave 0 loads the rays and scans their segment counts
-            int nseg = 0;
-            float px = 0.f, py = 0.f, pz = 0.f, r2;
-            int ix = 0, iy = 0;
-            if (base + t < count) {
-                const int64_t i = longs[base + t];
-                if (point_cell(g, T, mr2, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], px, py, pz, r2, ix, iy) == 0)
-                    nseg = (max(abs(ix - ax), abs(iy - ay)) - 1 + kSeg - 1) / kSeg;
-            }
-            s_pt[t] = make_float4(px, py, pz, 0.f);
-            s_cell[t] = make_int2(ix, iy);
-            int incl = nseg;
-#pragma unroll
-            for (int o = 1; o < kLongRays; o <<= 1) {
-                const int u = __shfl_up(incl, o);
-                if (t >= o) incl += u;
-            }
-            s_pre[t + 1] = incl;
-            if (t == 0) s_pre[0] = 0;
-            const int pre = incl - nseg;
-            for (int k = 0; k < nseg && pre + k < kSegTable; k++) s_seg[pre + k] = (uint16_t)(t | (k << 6));
+    // wave-sized chunks of the concatenated sub-lists, dealt to the waves in turn
+    for (int q0 = wave * 64; q0 < total; q0 += nwaves * 64) {
+        const int q = q0 + lane;
+        if (q >= total) continue;
+        int lo = 0, hi = NS;  // s_pre[lo] <= q < s_pre[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (s_pre[mid] <= q) lo = mid;
+            else hi = mid;
         }
-        __syncthreads();
-        const int total = s_pre[kLongRays];
-        for (int q = t; q < total; q += 256) {
-            int r, k;
-            if (q < kSegTable) {
-                const int e = s_seg[q];
-                r = e & 63;
-                k = e >> 6;
-            } else {
-                r = 0;  // the last ray whose first segment is at or before q
-#pragma unroll
-                for (int bit = kLongRays / 2; bit > 0; bit >>= 1)
-                    if (s_pre[r + bit] <= q) r += bit;
-                k = q - s_pre[r];
-            }
-            const float4 p = s_pt[r];
-            const int2 c = s_cell[r];
-            Ray ray(gl, ax, ay, c.x, c.y, sx, sy, sz, p.x, p.y, p.z);
-            const int first = 1 + k * kSeg;
-            const int cnt = min(kSeg, ray.L.steps - first);
-            visited += walk_range_logical<8>(gl, ray, hl, first, cnt, ClearVoteLogical{clr, g, margin});
-        }
-        __syncthreads();  // the next batch overwrites the LDS tables
+        const int local = q - s_pre[lo];
+        const int2 e = lo < kSegSubs ? mb.full[(int64_t)lo * mb.full_sub + local]
+                                     : mb.part[(int64_t)(lo - kSegSubs) * mb.part_sub + local];
+        const float4 p = mb.rec[e.x];
+        const int cell = __float_as_int(p.z);
+        Ray ray(gl, ax, ay, cell & 0xffff, cell >> 16, sx, sy, sz, p.x, p.y, 0);
+        const int first = 1 + e.y * kSegLen;
+        const int cnt = min(kSegLen, ray.L.steps - first);
+        visited += walk_range_logical<8>(gl, ray, hl, first, cnt, ClearVoteLogical{clr, g, margin});
     }
     const int ids[1] = {ST_RAY_CELLS};
     int vals[1] = {visited};
@@ -304,49 +289,75 @@ size_t ingest_lds_bytes(int Cb)
 }
 
 void launch_zero_accum(hipStream_t s, const Grid& g, int* n, float* wsum, float* ssum, int* clr,
-                       float* chsum, int Cb, int* zero1, const float* h, float* hl, DriftDev* drift)
+                       float* chsum, int Cb, int* march_counts, const float* h, float* hl, DriftDev* drift)
 {
     int HW = g.W * g.H;
     unsigned b = blocks_for(HW, 256);
     if (b > 4096) b = 4096;
     if (b < 1) b = 1;
-    hipLaunchKernelGGL(k_zero_accum, dim3(b), dim3(256), 0, s, g, n, wsum, ssum, clr, chsum, Cb, zero1, h, hl,
+    hipLaunchKernelGGL(k_zero_accum, dim3(b), dim3(256), 0, s, g, n, wsum, ssum, clr, chsum, Cb, march_counts, h, hl,
                        drift);
 }
 
 void launch_ingest(hipStream_t s, const Grid& g, const float* xyz, int64_t n, const float* ch,
                    const Pose& T, float c0, float c1, float mr2, const PointBinds& pb, int* cnt,
-                   float* wsum, float* ssum, float2* stash, float* chsum,
+                   float* wsum, float* ssum, float2* stash, float* chsum, const MarchBufs* march,
                    unsigned long long* stats)
 {
     if (n <= 0) return;
     const Accum acc{cnt, wsum, ssum, stash, nullptr, chsum, g.W * g.H};
     const size_t lds = pb.lds_ch ? sizeof(float) * kSlots * pb.Cb : 0;
     hipLaunchKernelGGL(k_ingest, dim3(blocks_for(n, kChunk)), dim3(kWG), lds, s, g, xyz, n, ch, T,
-                       c0, c1, mr2, pb, acc, stats);
+                       c0, c1, mr2, pb, acc, march ? *march : MarchBufs{}, march ? 1 : 0, stats);
+}
+
+void march_pass(float mr2, float res, int64_t n, int64_t* pts, int64_t* full_per_ray)
+{
+    // a ray's steps lie below range / res + 2 cells (a margin of 0.1 % for
+    // the pose's rotation, orthonormal to 1e-4)
+    const double lmax = std::ceil(1.001 * std::sqrt((double)mr2) / (double)res) + 2.0;
+    const int64_t fpr = (int64_t)std::min(lmax / kSegLen, 1e15);
+    int64_t p = fpr > 0 ? kMarchFullCap / fpr : kMarchPass;
+    p = std::max<int64_t>(1, std::min<int64_t>(p, kMarchPass));
+    *pts = std::min<int64_t>(n, p);
+    *full_per_ray = fpr;
+}
+
+MarchSizes march_sizes(int64_t pts, int64_t full_per_ray)
+{
+    // Sub-list s takes the workgroups b = s mod kSegSubs of a pass, which
+    // list 256 points each (k_ray_prep) or kChunk (k_ingest): rays per
+    // sub-list at most, for either.
+    auto rays = [&](int64_t per_wg) {
+        const int64_t wgs = (pts + per_wg - 1) / per_wg;
+        return (wgs + kSegSubs - 1) / kSegSubs * per_wg;
+    };
+    const int64_t per_sub = std::max(rays(256), rays(kChunk));
+    MarchSizes z;
+    z.part_sub = per_sub;
+    z.full_sub = per_sub * std::max<int64_t>(full_per_ray, 1);
+    return z;
 }
 
 void launch_clear_march(hipStream_t s, const Grid& g_storage, const float* xyz, int64_t n, const Pose& T,
-                        float mr2, float margin, const float* hl, int* clr, int* longs, int* n_long,
-                        unsigned long long* stats)
+                        float mr2, float margin, const float* hl, int* clr, const MarchBufs& mb,
+                        bool prepared, unsigned long long* stats)
 {
     // the walks read heights in logical order: the grid without its ring offsets
     const Grid& g = g_storage;
     Grid gl = g_storage;
     gl.rx = 0;
     gl.ry = 0;
-    // The long-ray list holds kMarchPass entries: clouds beyond that are
-    // marched in passes, each pass clearing the list's counter first (the
-    // first pass's counter was cleared with the accumulators).
-    for (int64_t b = 0; b < n; b += kMarchPass) {
-        const int64_t m = n - b < kMarchPass ? n - b : kMarchPass;
-        if (b > 0) launch_zero_int(s, n_long, 1);
-        hipLaunchKernelGGL(k_clear_march, dim3(blocks_for(m, 256)), dim3(256), 0, s, g, gl, hl, xyz + 3 * b, m, T,
-                           mr2, margin, clr, longs, n_long, stats);
-        unsigned grid_long = blocks_for(m, kLongRays);
-        if (grid_long > kLongGrid) grid_long = kLongGrid;
-        hipLaunchKernelGGL(k_clear_long, dim3(grid_long), dim3(256), 0, s, g, gl, hl, xyz + 3 * b, T, mr2, margin,
-                           clr, longs, n_long, stats);
+    // Clouds beyond the buffers' capacity are marched in passes, each pass
+    // clearing the lists' counts first (the first pass's counts were cleared
+    // with the accumulators).
+    for (int64_t b = 0; b < n; b += mb.cap_pts) {
+        const int64_t m = n - b < mb.cap_pts ? n - b : mb.cap_pts;
+        if (b > 0) launch_zero_int(s, mb.counts, kSegLists * kSegSubs);
+        if (!(prepared && b == 0))
+            hipLaunchKernelGGL(k_ray_prep, dim3(blocks_for(m, 256)), dim3(256), 0, s, g, xyz + 3 * b, m, T, mr2,
+                               mb, stats);
+        hipLaunchKernelGGL(k_ray_walk, dim3(kWalkGrid), dim3(256), 0, s, g, gl, hl, T, margin, clr, mb, stats);
     }
 }
 

@@ -101,9 +101,8 @@ struct mem_map {
     int* vcount = nullptr;      // cells listed in vlist: two counters used by turns (vpar)
     int vpar = 0;               // the counter the next projection uses; its k_view clears the other
     bool tmax_stale = true;     // the heights changed since the block maxima were built
-    int* longs = nullptr;       // long rays of the clearing march (kMarchPass entries)
+    MarchBufs march;            // clearing march: rays and segment lists (grown on first use)
     float* hl = nullptr;        // heights in logical order, for the clearing march
-    int* n_long = nullptr;      // their count
     DriftDev* drift = nullptr;  // the last cloud's drift compensation
     char* drift_part = nullptr; // its per-workgroup partial sums
     bool drift_on = false;
@@ -260,9 +259,11 @@ void free_map(mem_map* m)
     (void)hipFree(m->ssum);
     (void)hipFree(m->stash);
     (void)hipFree(m->vcount);
-    (void)hipFree(m->longs);
+    (void)hipFree(m->march.rec);
+    (void)hipFree(m->march.full);
+    (void)hipFree(m->march.part);
+    (void)hipFree(m->march.counts);
     (void)hipFree(m->hl);
-    (void)hipFree(m->n_long);
     (void)hipFree(m->drift);
     (void)hipFree(m->drift_part);
     (void)hipFree(m->vlist_poses);
@@ -363,7 +364,7 @@ mem_status mem_create(const mem_params* p, void* stream, mem_map** out)
         (st = dev_alloc(m, &m->stash, HW)) ||
         (st = dev_alloc(m, &m->vlist, HW)) || (st = dev_alloc(m, &m->vcode, HW * kMaxImages)) ||
         (st = dev_alloc(m, &m->vcount, 2)) || (st = dev_alloc(m, &m->tmax, m->tmax_size())) ||
-        (st = dev_alloc(m, &m->longs, kMarchPass)) || (st = dev_alloc(m, &m->n_long, 1)) || (st = dev_alloc(m, &m->drift, 1)) || (st = dev_alloc(m, &m->drift_part, drift_part_bytes())) ||
+        (st = dev_alloc(m, &m->march.counts, kSegLists * kSegSubs)) || (st = dev_alloc(m, &m->drift, 1)) || (st = dev_alloc(m, &m->drift_part, drift_part_bytes())) ||
         (st = dev_alloc(m, &m->hl, HW)) ||
         (st = dev_alloc(m, &m->stats, kStats * kStatSlots))) {
         free_map(m);
@@ -527,15 +528,39 @@ mem_status mem_input_pointcloud(mem_map* m, const float* xyz, int64_t n, const f
     }
     Grid g = m->grid();
     const bool march = m->clear_min > 0 && n > 0;
+    if (march) {
+        int64_t pts = 0, fpr = 0;
+        march_pass(m->mr2, m->res, n, &pts, &fpr);
+        if (pts > m->march.cap_pts) {
+            // Stream-ordered growth: wait for earlier users of the old buffers.
+            HIP_TRY(m, hipStreamSynchronize(s));
+            (void)hipFree(m->march.rec);
+            (void)hipFree(m->march.full);
+            (void)hipFree(m->march.part);
+            m->march.rec = nullptr;
+            m->march.full = nullptr;
+            m->march.part = nullptr;
+            m->march.cap_pts = 0;
+            const MarchSizes z = march_sizes(pts, fpr);
+            if (mem_status st = dev_alloc(m, &m->march.rec, pts)) return st;
+            if (mem_status st = dev_alloc(m, &m->march.full, kSegSubs * z.full_sub)) return st;
+            if (mem_status st = dev_alloc(m, &m->march.part, 4 * kSegSubs * z.part_sub)) return st;
+            m->march.cap_pts = pts;
+            m->march.full_sub = z.full_sub;
+            m->march.part_sub = z.part_sub;
+        }
+    }
     timed(m, s, "zero_accum", [&] {
-        launch_zero_accum(s, g, m->cnt, m->wsum, m->ssum, m->clr, m->chsum, pb.Cb, m->n_long, m->h,
+        launch_zero_accum(s, g, m->cnt, m->wsum, m->ssum, m->clr, m->chsum, pb.Cb, m->march.counts, m->h,
                           march ? m->hl : nullptr, m->drift);
     });
     Pose T;
     memcpy(T.m, T_map_sensor, sizeof(T.m));
+    // a cloud that fits one march pass has its rays listed by the ingest
+    const bool fused = march && n <= m->march.cap_pts;
     timed(m, s, "ingest", [&] {
         launch_ingest(s, g, xyz, n, ch, T, m->c0, m->c1, m->mr2, pb, m->cnt, m->wsum, m->ssum, m->stash,
-                      m->chsum, m->stats);
+                      m->chsum, fused ? &m->march : nullptr, m->stats);
     });
     if (m->drift_on && n > 0)
         timed(m, s, "drift", [&] {
@@ -544,7 +569,7 @@ mem_status mem_input_pointcloud(mem_map* m, const float* xyz, int64_t n, const f
         });
     if (march)
         timed(m, s, "clear_march", [&] {
-            launch_clear_march(s, g, xyz, n, T, m->mr2, m->clear_margin, m->hl, m->clr, m->longs, m->n_long,
+            launch_clear_march(s, g, xyz, n, T, m->mr2, m->clear_margin, m->hl, m->clr, m->march, fused,
                                m->stats);
         });
     m->tmax_stale = true;

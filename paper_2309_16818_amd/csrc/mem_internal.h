@@ -128,26 +128,55 @@ struct CameraSet {
 };
 
 // ---- launchers (implemented in the .hip files) ----
-// `zero1`, if not null, is one int cleared as well (the long-ray counter of
-// the clearing march).
+// `march_counts`, if not null, are the clearing march's kSegLists list
+// counts, cleared as well.
 // `hl`, if not null, receives a copy of the heights `h` in logical order
 // (index y * W + x).
 void launch_zero_accum(hipStream_t s, const Grid& g, int* n, float* wsum, float* ssum, int* clr,
-                       float* chsum, int Cb, int* zero1, const float* h, float* hl, DriftDev* drift);
+                       float* chsum, int Cb, int* march_counts, const float* h, float* hl, DriftDev* drift);
 // LDS bytes of the ingest kernel for `Cb` channel planes reduced in LDS.
 size_t ingest_lds_bytes(int Cb);
+struct MarchBufs;
+// `march`, if not null: also lists the clearing march's segments of this
+// cloud's rays (a single pass: n <= march->cap_pts).
 void launch_ingest(hipStream_t s, const Grid& g, const float* xyz, int64_t n, const float* ch,
                    const Pose& T, float c0, float c1, float mr2, const PointBinds& pb, int* cnt,
-                   float* wsum, float* ssum, float2* stash, float* chsum,
+                   float* wsum, float* ssum, float2* stash, float* chsum, const MarchBufs* march,
                    unsigned long long* stats);
-// Points per clearing pass: the long-ray list `longs` holds this many
-// entries and `n_long` is its counter (cleared by launch_zero_accum).
-constexpr int64_t kMarchPass = 1 << 20;
+// The clearing march's buffers: a pass's rays (1 / major extent, height
+// difference, cell), the
+// kSegSubs sub-lists of their full segments of kSegLen cells (full_sub
+// entries each), the 4 x kSegSubs sub-lists of their last, shorter segments
+// by length class (part_sub entries each) and the kSegLists x kSegSubs
+// counts (cleared by launch_zero_accum).
+constexpr int kSegLen = 64;
+constexpr int kSegLists = 5;
+constexpr int kSegSubs = 64;
+constexpr int64_t kMarchPass = 1 << 20;        // points per pass at most
+constexpr int64_t kMarchFullCap = 1 << 24;     // full segments per pass at most
+struct MarchSizes {
+    int64_t full_sub = 0, part_sub = 0;
+};
+struct MarchBufs {
+    float4* rec = nullptr;  // cap_pts: (inv_d, dz, ix | iy << 16, 0) of rays with cells to walk
+    int2* full = nullptr;   // kSegSubs * full_sub: (ray, segment)
+    int2* part = nullptr;   // 4 * kSegSubs * part_sub
+    int* counts = nullptr;  // kSegLists * kSegSubs, list-major
+    int64_t cap_pts = 0, full_sub = 0, part_sub = 0;
+};
+// Points per pass for a cloud of n points (at most kMarchPass, and few
+// enough that the full list holds every segment) and the full segments a
+// ray within the map's range can have.
+void march_pass(float mr2, float res, int64_t n, int64_t* pts, int64_t* full_per_ray);
+// Sub-list capacities for passes of `pts` points.
+MarchSizes march_sizes(int64_t pts, int64_t full_per_ray);
 // The march reads the heights in logical order (`hl`, written by
 // launch_zero_accum) and counts votes into the storage-order layer `clr`.
+// `prepared`: the point ingest already listed the first pass's segments
+// (launch_ingest with `march`, for a cloud of at most cap_pts points).
 void launch_clear_march(hipStream_t s, const Grid& g, const float* xyz, int64_t n, const Pose& T,
-                        float mr2, float margin, const float* hl, int* clr, int* longs, int* n_long,
-                        unsigned long long* stats);
+                        float mr2, float margin, const float* hl, int* clr, const MarchBufs& mb,
+                        bool prepared, unsigned long long* stats);
 // z-error count and drift compensation of one cloud: the consistent points'
 // sums into `drift`, then, with at least min_points of them, the shift of
 // every held height h (and its logical-order copy hl, if given) by their

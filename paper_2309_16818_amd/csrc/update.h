@@ -38,6 +38,7 @@ struct IngestLds {
 struct PointCounts {
     int acc = 0, nonfinite = 0, range = 0, outside = 0;
     int flushed = 0;  // cells whose sums this thread flushed with global atomics
+    int ray_steps = 0;  // cells the clearing rays of this thread's points walk (when listed)
 };
 
 // Aggregates points [begin, end) of a cloud (at most 2^slots_log2 / 2
@@ -52,13 +53,70 @@ __device__ __forceinline__ int class_index(float v, int K)
     return (v >= 0.0f && v < (float)K && v == floorf(v)) ? (int)v : -1;
 }
 
+// The clearing march's segment lists (see k_points.hip): the ray of point
+// i (index within the pass) with `steps` cells to walk gets its record and
+// its segments of kSegLen cells.  Every thread of the workgroup calls it
+// with its P points (steps 0 for none); the workgroup scans its full
+// segments, counts its partial ones per length class in LDS, reserves room
+// in sub-list (block id mod kSegSubs) of every list with one atomic each and
+// writes the entries.  s_cnt, s_base: kSegLists ints of LDS; s_wave: one
+// int per wave (at most 16).  Starts and ends with a barrier.
+constexpr int kMarchLds = 2 * kSegLists + 16;  // ints of LDS march_lists takes
+template <int P>
+__device__ __forceinline__ void march_lists(const MarchBufs& mb, const int (&ri)[P], const int (&steps)[P],
+                                            int* s_cnt, int* s_base, int* s_wave)
+{
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = (blockDim.x + 63) >> 6;
+    const int sub = blockIdx.x % kSegSubs;
+    __syncthreads();
+    if (t < kSegLists) s_cnt[t] = 0;
+    int nfull = 0;
+#pragma unroll
+    for (int k = 0; k < P; k++) nfull += steps[k] / kSegLen;
+    int incl = nfull;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(incl, o);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) s_wave[w] = incl;
+    __syncthreads();
+    int fpos = incl - nfull;
+    for (int k = 0; k < w; k++) fpos += s_wave[k];
+    int ppos[P], list[P];
+#pragma unroll
+    for (int k = 0; k < P; k++) {
+        const int rem = steps[k] % kSegLen;
+        list[k] = 1 + (kSegLen - 1 - rem) * 4 / kSegLen;  // for rem > 0: 1 (longest quarter) .. 4
+        ppos[k] = rem > 0 ? atomicAdd(&s_cnt[list[k]], 1) : 0;
+    }
+    if (t == (int)blockDim.x - 1) s_cnt[0] = fpos + nfull;
+    __syncthreads();
+    if (t < kSegLists) s_base[t] = s_cnt[t] > 0 ? atomicAdd(&mb.counts[t * kSegSubs + sub], s_cnt[t]) : 0;
+    __syncthreads();
+    // (the capacities bound every sub-list; the tests only guard them)
+    int2* fl = mb.full + (int64_t)sub * mb.full_sub;
+    int f = s_base[0] + fpos;
+#pragma unroll
+    for (int k = 0; k < P; k++) {
+        const int nf = steps[k] / kSegLen, rem = steps[k] - nf * kSegLen;
+        for (int j = 0; j < nf; j++, f++)
+            if (f < mb.full_sub) fl[f] = make_int2(ri[k], j);
+        if (rem > 0 && (int64_t)s_base[list[k]] + ppos[k] < mb.part_sub)
+            mb.part[((int64_t)(list[k] - 1) * kSegSubs + sub) * mb.part_sub + s_base[list[k]] + ppos[k]] =
+                make_int2(ri[k], nf);
+    }
+    __syncthreads();
+}
+
 template <int P>
 __device__ __forceinline__ void ingest_range(const Grid& g, const float* __restrict__ xyz,
                                              int64_t begin, int64_t end,
                                              const float* __restrict__ ch, const Pose& T, float c0,
                                              float c1, float mr2, const PointBinds& pb,
                                              const Accum& acc, const IngestLds& lds,
-                                             PointCounts& pc)
+                                             PointCounts& pc, bool march = false,
+                                             const MarchBufs& mb = MarchBufs{}, int* s_march = nullptr)
 {
     const int slots = 1 << lds.slots_log2;
     const int nthr = blockDim.x;
@@ -75,14 +133,37 @@ __device__ __forceinline__ void ingest_range(const Grid& g, const float* __restr
     __syncthreads();
 
     float in[P][3];
+    int msteps[P], mri[P];
 #pragma unroll
     for (int k = 0; k < P; k++) {
         const int64_t i = begin + threadIdx.x + (int64_t)k * nthr;
+        msteps[k] = 0;
+        mri[k] = (int)i;
         if (i < end) {
             in[k][0] = xyz[3 * i];
             in[k][1] = xyz[3 * i + 1];
             in[k][2] = xyz[3 * i + 2];
         }
+    }
+    if (march) {
+        // the clearing rays of the accepted points (cell decisions as below)
+        int ax, ay;
+        lattice_cell(g, T.m[3], T.m[7], ax, ay);
+#pragma unroll
+        for (int k = 0; k < P; k++) {
+            const int64_t i = begin + threadIdx.x + (int64_t)k * nthr;
+            float px, py, pz, r2;
+            int ix, iy;
+            if (i < end && point_cell(g, T, mr2, in[k][0], in[k][1], in[k][2], px, py, pz, r2, ix, iy) == 0) {
+                msteps[k] = max(max(abs(ix - ax), abs(iy - ay)) - 1, 0);
+                pc.ray_steps += msteps[k];
+                if (msteps[k] > 0) {
+                    const Ray ray(g, ax, ay, ix, iy, T.m[3], T.m[7], T.m[11], px, py, pz);
+                    mb.rec[i] = make_float4(ray.inv_d, ray.dz, __int_as_float(ix | (iy << 16)), 0.0f);
+                }
+            }
+        }
+        march_lists<P>(mb, mri, msteps, s_march, s_march + kSegLists, s_march + 2 * kSegLists);
     }
 #pragma unroll
     for (int k = 0; k < P; k++) {
