@@ -126,7 +126,7 @@ __global__ __launch_bounds__(256) void k_ray_prep(Grid g, const float* __restric
         const Ray ray(g, ax, ay, ix, iy, T.m[3], T.m[7], T.m[11], px, py, pz);
         mb.rec[i] = make_float4(ray.inv_d, ray.dz, __int_as_float(ix | (iy << 16)), 0.0f);
     }
-    march_lists<1>(mb, ri, steps, s_march, s_march + kSegLists, s_march + 2 * kSegLists);
+    march_lists<1>(mb, ri, steps, s_march);
     const int ids[1] = {ST_RAY_STEPS};
     int vals[1] = {steps[0]};
     block_stats(stats, ids, vals);

@@ -54,20 +54,33 @@ __device__ __forceinline__ int class_index(float v, int K)
 }
 
 // The clearing march's segment lists (see k_points.hip): the ray of point
-// i (index within the pass) with `steps` cells to walk gets its record and
-// its segments of kSegLen cells.  Every thread of the workgroup calls it
-// with its P points (steps 0 for none); the workgroup scans its full
-// segments, counts its partial ones per length class in LDS, reserves room
-// in sub-list (block id mod kSegSubs) of every list with one atomic each and
-// writes the entries.  s_cnt, s_base: kSegLists ints of LDS; s_wave: one
-// int per wave (at most 16).  Starts and ends with a barrier.
-constexpr int kMarchLds = 2 * kSegLists + 16;  // ints of LDS march_lists takes
+// i (index within the pass) with `steps` cells to walk gets its segments of
+// kSegLen cells.  In two steps, so that the reservation's atomics are in
+// flight while the caller does other work: march_reserve (every thread of
+// the workgroup, with its P points, steps 0 for none) scans the workgroup's
+// full segments, counts its partial ones per length class in LDS and lets
+// threads 0..kSegLists-1 reserve room in sub-list (block id mod kSegSubs)
+// of every list with one atomic each; march_write (every thread) writes
+// the entries.  s_march: kMarchLds ints of LDS (s_cnt, s_base, one int per
+// wave, at most 16 waves).  march_reserve starts with a barrier,
+// march_write ends with one.
+constexpr int kMarchLds = 2 * kSegLists + 16;  // ints of LDS the listing takes
 template <int P>
-__device__ __forceinline__ void march_lists(const MarchBufs& mb, const int (&ri)[P], const int (&steps)[P],
-                                            int* s_cnt, int* s_base, int* s_wave)
+struct MarchSlots {
+    int fpos;     // first entry of this thread's full segments within the workgroup's
+    int ppos[P];  // rank of each partial segment within its list
+    int list[P];  // its list (1..4)
+    int base;     // threads < kSegLists: the reservation in their list
+};
+
+template <int P>
+__device__ __forceinline__ MarchSlots<P> march_reserve(const MarchBufs& mb, const int (&steps)[P], int* s_march)
 {
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = (blockDim.x + 63) >> 6;
+    int* s_cnt = s_march;
+    int* s_wave = s_march + 2 * kSegLists;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int sub = blockIdx.x % kSegSubs;
+    MarchSlots<P> r;
     __syncthreads();
     if (t < kSegLists) s_cnt[t] = 0;
     int nfull = 0;
@@ -81,32 +94,52 @@ __device__ __forceinline__ void march_lists(const MarchBufs& mb, const int (&ri)
     }
     if (lane == 63) s_wave[w] = incl;
     __syncthreads();
-    int fpos = incl - nfull;
-    for (int k = 0; k < w; k++) fpos += s_wave[k];
-    int ppos[P], list[P];
+    r.fpos = incl - nfull;
+    for (int k = 0; k < w; k++) r.fpos += s_wave[k];
 #pragma unroll
     for (int k = 0; k < P; k++) {
         const int rem = steps[k] % kSegLen;
-        list[k] = 1 + (kSegLen - 1 - rem) * 4 / kSegLen;  // for rem > 0: 1 (longest quarter) .. 4
-        ppos[k] = rem > 0 ? atomicAdd(&s_cnt[list[k]], 1) : 0;
+        r.list[k] = 1 + (kSegLen - 1 - rem) * 4 / kSegLen;  // for rem > 0: 1 (longest quarter) .. 4
+        r.ppos[k] = rem > 0 ? atomicAdd(&s_cnt[r.list[k]], 1) : 0;
     }
-    if (t == (int)blockDim.x - 1) s_cnt[0] = fpos + nfull;
+    if (t == (int)blockDim.x - 1) s_cnt[0] = r.fpos + nfull;
     __syncthreads();
-    if (t < kSegLists) s_base[t] = s_cnt[t] > 0 ? atomicAdd(&mb.counts[t * kSegSubs + sub], s_cnt[t]) : 0;
+    r.base = 0;
+    if (t < kSegLists && s_cnt[t] > 0) r.base = atomicAdd(&mb.counts[t * kSegSubs + sub], s_cnt[t]);
+    return r;
+}
+
+template <int P>
+__device__ __forceinline__ void march_write(const MarchBufs& mb, const int (&ri)[P], const int (&steps)[P],
+                                            const MarchSlots<P>& r, int* s_march)
+{
+    int* s_base = s_march + kSegLists;
+    const int t = threadIdx.x;
+    const int sub = blockIdx.x % kSegSubs;
+    if (t < kSegLists) s_base[t] = r.base;
     __syncthreads();
     // (the capacities bound every sub-list; the tests only guard them)
     int2* fl = mb.full + (int64_t)sub * mb.full_sub;
-    int f = s_base[0] + fpos;
+    int f = s_base[0] + r.fpos;
 #pragma unroll
     for (int k = 0; k < P; k++) {
         const int nf = steps[k] / kSegLen, rem = steps[k] - nf * kSegLen;
         for (int j = 0; j < nf; j++, f++)
             if (f < mb.full_sub) fl[f] = make_int2(ri[k], j);
-        if (rem > 0 && (int64_t)s_base[list[k]] + ppos[k] < mb.part_sub)
-            mb.part[((int64_t)(list[k] - 1) * kSegSubs + sub) * mb.part_sub + s_base[list[k]] + ppos[k]] =
-                make_int2(ri[k], nf);
+        const int l = r.list[k];
+        if (rem > 0 && (int64_t)s_base[l] + r.ppos[k] < mb.part_sub)
+            mb.part[((int64_t)(l - 1) * kSegSubs + sub) * mb.part_sub + s_base[l] + r.ppos[k]] = make_int2(ri[k], nf);
     }
     __syncthreads();
+}
+
+// Both steps at once.
+template <int P>
+__device__ __forceinline__ void march_lists(const MarchBufs& mb, const int (&ri)[P], const int (&steps)[P],
+                                            int* s_march)
+{
+    const MarchSlots<P> r = march_reserve<P>(mb, steps, s_march);
+    march_write<P>(mb, ri, steps, r, s_march);
 }
 
 template <int P>
@@ -163,8 +196,10 @@ __device__ __forceinline__ void ingest_range(const Grid& g, const float* __restr
                 }
             }
         }
-        march_lists<P>(mb, mri, msteps, s_march, s_march + kSegLists, s_march + 2 * kSegLists);
     }
+    // the reservation's atomics stay in flight during the hashing below
+    MarchSlots<P> mslots;
+    if (march) mslots = march_reserve<P>(mb, msteps, s_march);
 #pragma unroll
     for (int k = 0; k < P; k++) {
         const int64_t i = begin + threadIdx.x + (int64_t)k * nthr;
@@ -183,7 +218,15 @@ __device__ __forceinline__ void ingest_range(const Grid& g, const float* __restr
         const float sig = c0 + c1 * r2;
         const float var = sig * sig;
         const float w = 1.0f / var;
-        int slot = (int)(((unsigned)st * 2654435761u) >> (32 - lds.slots_log2));
+        // Slot: the cell's index within its aligned block of `slots` cells,
+        // xored with a hash of the block in multiples of 16.  Cells that are
+        // neighbours in memory stay neighbours in the table (each aligned
+        // group of 16 cells in one aligned group of 16 slots), so the lanes
+        // of the flush below, which take consecutive slots, add into
+        // consecutive cells and the memory side merges their atomics per
+        // cache line; distinct blocks spread over the table.
+        const unsigned blk = (unsigned)st >> lds.slots_log2;
+        int slot = (int)(((unsigned)st ^ ((blk * 2654435761u) << 4)) & (unsigned)(slots - 1));
         for (;;) {
             int old = atomicCAS(&lds.key[slot], -1, st);
             if (old == -1) {
@@ -213,6 +256,7 @@ __device__ __forceinline__ void ingest_range(const Grid& g, const float* __restr
             }
         }
     }
+    if (march) march_write<P>(mb, mri, msteps, mslots, s_march);
     __syncthreads();
 
     // Flush: one global atomic per (cell, field) seen by this workgroup.
