@@ -114,8 +114,9 @@ def parse():
 
 def batch_kernel_bytes(name, st, cells, launches, C=16):
     """Algorithmic HBM bytes of a batch stage over `launches` steps, from
-    the step counters: binning reads every point's xyz (12 B) and writes a
-    16 B record per accepted point; the block-owned ingest reads the
+    the step counters: binning reads every point's xyz (12 B) to count them
+    per tile and again to write a 16 B record per accepted point; the
+    block-owned ingest reads the
     records and writes four 4 B sums per cell (count, weights, weighted
     heights, zero votes); the logical copy reads and writes 4 B per cell;
     finalize reads count and votes (8 B) per cell and h, v, W, S with h, v
@@ -124,6 +125,8 @@ def batch_kernel_bytes(name, st, cells, launches, C=16):
     floats, reads and writes the C-float mean and the 4 B variance and
     reads the pair (4 C + 8 C + 8 + 8 B per visible pair)."""
     if name == "b_bin":
+        return 12 * st["points_in"]
+    if name == "b_bin_scatter":
         return 12 * st["points_in"] + 16 * st["points_accepted"]
     if name == "b_tile_ingest":
         return 16 * st["points_accepted"] + 16 * cells * launches

@@ -101,6 +101,7 @@ struct mem_batch {
     float4* rec = nullptr;                  // binned points, max_points records
     int* tile_start = nullptr;
     int* tile_cnt = nullptr;
+    int* tile_cur = nullptr;
 
     Staging stg[2];
     int next_stg = 0;
@@ -156,6 +157,7 @@ void free_batch(mem_batch* b)
     (void)hipFree(b->rec);
     (void)hipFree(b->tile_start);
     (void)hipFree(b->tile_cnt);
+    (void)hipFree(b->tile_cur);
     for (auto& L : b->layers) (void)hipFree(L.scale);
     delete b;
 }
@@ -229,6 +231,7 @@ mem_status build_itiles(mem_batch* b)
     b->n_itiles = (int)t.size();
     BTRY(b, hipMalloc((void**)&b->tile_start, sizeof(int) * t.size()));
     BTRY(b, hipMalloc((void**)&b->tile_cnt, sizeof(int) * t.size()));
+    BTRY(b, hipMalloc((void**)&b->tile_cur, sizeof(int) * t.size()));
     BTRY(b, hipMalloc((void**)&b->rec, sizeof(float4) * (size_t)std::max<int64_t>(b->max_points, 1)));
     return MEM_OK;
 }
@@ -270,6 +273,7 @@ BatchDev device_view(const mem_batch* b)
     d.rec = b->rec;
     d.tile_start = b->tile_start;
     d.tile_cnt = b->tile_cnt;
+    d.tile_cur = b->tile_cur;
     d.n_tiles = b->n_tiles;
     d.n_gitems = b->n_gitems;
     d.n_maps = b->n;

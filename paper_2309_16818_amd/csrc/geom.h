@@ -243,9 +243,13 @@ __device__ __forceinline__ int walk_cells(const Grid& g, Ray& r, const float* __
 // step, and the cell's major lattice coordinate is carried as a float
 // (k + 0.5 is exact below 2^22, so each ray height equals ray_height's).
 // Rays reaching beyond that range take walk_cells.
-template <int U, class Visit>
-__device__ __forceinline__ int walk_logical(const Grid& g, Ray& r, const float* __restrict__ h,
-                                            Visit&& visit)
+// The pipelined walk itself: batch(st, z, h, n) tests a batch of U cells
+// (storage indices, ray heights, heights; the first n are cells of the ray,
+// the rest past its end) and returns true to stop the walk; `visit` serves
+// the rays that take walk_cells instead.
+template <int U, class Visit, class Batch>
+__device__ __forceinline__ int walk_logical_batches(const Grid& g, Ray& r, const float* __restrict__ h,
+                                                    Visit& visit, Batch&& batch)
 {
     const LineWalk& L = r.L;
     const int k0 = r.o_major + L.major();
@@ -289,14 +293,8 @@ __device__ __forceinline__ int walk_logical(const Grid& g, Ray& r, const float* 
     float zr2[U], hk2[U];
     int loaded = 0;
     auto test = [&](const int (&s_)[U], const float (&z_)[U], const float (&h_)[U], int n) {
-        bool stop = false;
         loaded += min(n, U);
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-            const float hu = u < n ? h_[u] : __builtin_nanf("");
-            if (!stop && visit(s_[u], hu, z_[u])) stop = true;
-        }
-        return stop;
+        return batch(s_, z_, h_, n);
     };
     fetch(st, zr, hk);
     while (true) {
@@ -316,6 +314,22 @@ __device__ __forceinline__ int walk_logical(const Grid& g, Ray& r, const float* 
         rem -= U;
     }
     return loaded;
+}
+
+template <int U, class Visit>
+__device__ __forceinline__ int walk_logical(const Grid& g, Ray& r, const float* __restrict__ h,
+                                            Visit&& visit)
+{
+    return walk_logical_batches<U>(g, r, h, visit,
+                                   [&](const int (&s_)[U], const float (&z_)[U], const float (&h_)[U], int n) {
+                                       bool stop = false;
+#pragma unroll
+                                       for (int u = 0; u < U; u++) {
+                                           const float hu = u < n ? h_[u] : __builtin_nanf("");
+                                           if (!stop && visit(s_[u], hu, z_[u])) stop = true;
+                                       }
+                                       return stop;
+                                   });
 }
 
 // walk_logical over `count` cells from intermediate cell `first`.

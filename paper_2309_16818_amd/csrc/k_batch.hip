@@ -26,6 +26,21 @@ namespace {
 
 constexpr int kBatchWG = 256;
 
+// Items of a stage with uniform work, dealt to the workgroups in turn:
+// workgroup b takes items b, b + grid, ...  (no shared counter: atomics on
+// one address serialise).  Every thread of the workgroup calls both;
+// next_static starts with a barrier, as next_item does.
+__device__ __forceinline__ int first_static(int n)
+{
+    return (int)blockIdx.x < n ? (int)blockIdx.x : -1;
+}
+__device__ __forceinline__ int next_static(int it, int n)
+{
+    __syncthreads();
+    const int r = it + (int)gridDim.x;
+    return r < n ? r : -1;
+}
+
 // Pulls the next item of queue q for the whole workgroup (-1: none left).
 __device__ __forceinline__ int next_item(int* qctr, int q, int n, int* s_item)
 {
@@ -54,12 +69,6 @@ __device__ __forceinline__ int chunk_item(const BatchDev& d, int it, int64_t& be
     return lo;
 }
 
-__device__ __forceinline__ Accum map_accum(const BatchDev& d, const BatchMap& m)
-{
-    const int64_t o = m.cell_off;
-    return Accum{d.cnt + o, d.wsum + o, d.ssum + o, d.stash + o, d.clr + o, nullptr, m.g.W * m.g.H};
-}
-
 struct BatchLayers {
     LayerDev L[32];
     int n;
@@ -70,13 +79,13 @@ __global__ void k_b_prep(BatchDev d)
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < kQueues) d.qctr[i] = 0;
     if (i < d.n_maps) d.pair_count[i] = 0;
+    for (int k = i; k < d.n_itiles; k += gridDim.x * blockDim.x) d.tile_cnt[k] = 0;
 }
 
 __global__ __launch_bounds__(kBatchWG) void k_b_reset(BatchDev d, BatchLayers ls)
 {
-    __shared__ int s_item;
     const int n = d.n_items[0];
-    for (int r = next_item(d.qctr, 0, n, &s_item); r >= 0; r = next_item(d.qctr, 0, n, &s_item)) {
+    for (int r = first_static(n); r >= 0; r = next_static(r, n)) {
         const BatchRect R = d.rects[r];
         const BatchMap& m = d.maps[R.map];
         const int w = R.x1 - R.x0;
@@ -89,115 +98,159 @@ __global__ __launch_bounds__(kBatchWG) void k_b_reset(BatchDev d, BatchLayers ls
     }
 }
 
-// Map items: bins the map's accepted points by ingest tile (a counting
-// sort in LDS: histogram, scan, scatter), one point transform per point and
-// pass, so each tile's workgroup later reads only its own points.  Records
-// of map m fill [pt_begin, pt_begin + accepted) in tile order.  Counts the
-// map's points and drops.
-__global__ __launch_bounds__(kBatchWG) void k_b_bin(BatchDev d, const float* __restrict__ xyz, float c0, float c1,
-                                                    float mr2)
+// Binning of the accepted points by ingest tile (a counting sort over the
+// whole batch), in three stages so that every stage runs on uniform items:
+//   k_b_bin        (map, chunk) items: each chunk's accepted points counted
+//                  per tile in LDS and added to the tile's count with one
+//                  atomic per tile the chunk reaches; the points and drops;
+//   k_b_bin_scan   map items: the map's tiles' first records (exclusive
+//                  prefix of the counts from the map's first point), which
+//                  also start the tiles' scatter cursors;
+//   k_b_bin_scatter (map, chunk) items: each chunk reserves its points' room
+//                  in every tile it reaches with one atomic on the tile's
+//                  cursor and writes a 16-byte record per accepted point
+//                  (storage cell, z, variance).
+// Records of map m fill [pt_begin, pt_begin + accepted) in tile order (the
+// order within a tile is the order of the reservations).  A map with more
+// tiles than kBinTiles counts and reserves with one global atomic per point.
+__device__ __forceinline__ int bin_tile(const BatchMap& m, int itile_h, int ix, int iy)
+{
+    const int sh = itile_h == 64 ? 6 : 5;
+    int sx = ix + m.g.rx;
+    sx -= (sx >= m.g.W) ? m.g.W : 0;
+    int sy = iy + m.g.ry;
+    sy -= (sy >= m.g.H) ? m.g.H : 0;
+    return (sy >> sh) * m.itiles_x + (sx >> 6);
+}
+
+__device__ __forceinline__ int bin_ntiles(const BatchMap& m, int itile_h)
+{
+    return m.itiles_x * ((m.g.H + itile_h - 1) / itile_h);
+}
+
+__global__ __launch_bounds__(kBatchWG) void k_b_bin(BatchDev d, const float* __restrict__ xyz, float mr2)
 {
     __shared__ int s_hist[kBinTiles];
-    __shared__ int s_part[kBatchWG];
-    __shared__ int s_item;
     PointCounts pc;
     int points_in = 0;
-    const int sh = d.itile_h == 64 ? 6 : 5;
-    for (int it = next_item(d.qctr, 8, d.n_maps, &s_item); it >= 0; it = next_item(d.qctr, 8, d.n_maps, &s_item)) {
-        const BatchMap& m = d.maps[it];
-        const int W = m.g.W, H = m.g.H;
-        const int ntiles = m.itiles_x * ((H + d.itile_h - 1) >> sh);
-        int64_t base = m.pt_begin;
-        for (int r0 = 0; r0 < ntiles; r0 += kBinTiles) {
-            const int nr = min(kBinTiles, ntiles - r0);
-            for (int k = threadIdx.x; k < kBinTiles; k += blockDim.x) s_hist[k] = 0;
-            __syncthreads();
-            // pass 1 counts, pass 2 scatters; both transform every point
-            for (int pass = 0; pass < 2; pass++) {
-                constexpr int U = 8;
-                for (int64_t i0 = m.pt_begin + threadIdx.x; i0 < m.pt_end; i0 += (int64_t)U * blockDim.x) {
-                    float p3[U][3];
-#pragma unroll
-                    for (int u = 0; u < U; u++) {
-                        const int64_t i = i0 + (int64_t)u * blockDim.x;
-                        const bool in = i < m.pt_end;
-                        p3[u][0] = in ? xyz[3 * i] : 0.0f;
-                        p3[u][1] = in ? xyz[3 * i + 1] : 0.0f;
-                        p3[u][2] = in ? xyz[3 * i + 2] : 0.0f;
-                    }
-#pragma unroll
-                    for (int u = 0; u < U; u++) {
-                        const bool in = i0 + (int64_t)u * blockDim.x < m.pt_end;
-                        float px, py, pz, r2;
-                        int ix, iy;
-                        const int r = in ? point_cell(m.g, m.T, mr2, p3[u][0], p3[u][1], p3[u][2], px, py, pz, r2,
-                                                      ix, iy)
-                                         : 1;  // 1: no point
-                        if (pass == 0 && r0 == 0 && in) {
-                            points_in++;
-                            pc.acc += (r == 0);
-                            pc.nonfinite += (r == -1);
-                            pc.range += (r == -2);
-                            pc.outside += (r == -3);
-                        }
-                        int t = -1, sx = 0, sy = 0;
-                        if (r == 0) {
-                            sx = ix + m.g.rx;
-                            sx -= (sx >= W) ? W : 0;
-                            sy = iy + m.g.ry;
-                            sy -= (sy >= H) ? H : 0;
-                            t = (sy >> sh) * m.itiles_x + (sx >> 6) - r0;
-                            if (t >= nr) t = -1;
-                        }
-                        if (t < 0) continue;
-                        const int pos = atomicAdd(&s_hist[t], 1);
-                        if (pass == 1) {
-                            const float sig = c0 + c1 * r2;
-                            d.rec[base + pos] = make_float4(__int_as_float(sx | (sy << 16)), pz, sig * sig, 0.0f);
-                        }
-                    }
-                }
-                __syncthreads();
-                if (pass == 0) {
-                    // exclusive scan of the counts: 16 per thread, then across threads
-                    constexpr int PER = kBinTiles / kBatchWG;
-                    int run = 0;
-                    for (int q = 0; q < PER; q++) run += s_hist[threadIdx.x * PER + q];
-                    s_part[threadIdx.x] = run;
-                    __syncthreads();
-                    if (threadIdx.x == 0) {
-                        int acc = 0;
-                        for (int q = 0; q < kBatchWG; q++) {
-                            const int v = s_part[q];
-                            s_part[q] = acc;
-                            acc += v;
-                        }
-                    }
-                    __syncthreads();
-                    int off = s_part[threadIdx.x];
-                    for (int q = 0; q < PER; q++) {
-                        const int k = threadIdx.x * PER + q;
-                        const int c = s_hist[k];
-                        if (k < nr) {
-                            d.tile_start[m.itile_base + r0 + k] = (int)(base + off);
-                            d.tile_cnt[m.itile_base + r0 + k] = c;
-                        }
-                        s_hist[k] = off;  // becomes the scatter cursor
-                        off += c;
-                    }
-                    __syncthreads();
-                }
-            }
-            // the next range's records follow this range's
-            if (threadIdx.x == 0) s_part[0] = s_hist[kBinTiles - 1];
-            __syncthreads();
-            base += s_part[0];
-            __syncthreads();
+    const int n = d.n_items[1];
+    for (int it = first_static(n); it >= 0; it = next_static(it, n)) {
+        int64_t b0, b1;
+        const BatchMap& m = d.maps[chunk_item(d, it, b0, b1)];
+        const int ntiles = bin_ntiles(m, d.itile_h);
+        const bool lds = ntiles <= kBinTiles;
+        if (lds)
+            for (int k = threadIdx.x; k < ntiles; k += blockDim.x) s_hist[k] = 0;
+        __syncthreads();
+        for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
+            float px, py, pz, r2;
+            int ix, iy;
+            const int r = point_cell(m.g, m.T, mr2, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], px, py, pz, r2, ix, iy);
+            points_in++;
+            pc.acc += (r == 0);
+            pc.nonfinite += (r == -1);
+            pc.range += (r == -2);
+            pc.outside += (r == -3);
+            if (r != 0) continue;
+            const int t = bin_tile(m, d.itile_h, ix, iy);
+            if (lds)
+                atomicAdd(&s_hist[t], 1);
+            else
+                atomicAdd(&d.tile_cnt[m.itile_base + t], 1);
         }
+        __syncthreads();
+        if (lds)
+            for (int k = threadIdx.x; k < ntiles; k += blockDim.x)
+                if (s_hist[k] > 0) atomicAdd(&d.tile_cnt[m.itile_base + k], s_hist[k]);
     }
     const int ids[5] = {ST_ACCEPTED, ST_NONFINITE, ST_RANGE, ST_OUTSIDE, ST_POINTS_IN};
     int vals[5] = {pc.acc, pc.nonfinite, pc.range, pc.outside, points_in};
     block_stats(d.stats, ids, vals);
+}
+
+__global__ __launch_bounds__(kBatchWG) void k_b_bin_scan(BatchDev d)
+{
+    __shared__ int s_wave[kBatchWG / 64];
+    __shared__ int s_run;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    for (int it = first_static(d.n_maps); it >= 0; it = next_static(it, d.n_maps)) {
+        const BatchMap& m = d.maps[it];
+        const int ntiles = bin_ntiles(m, d.itile_h);
+        if (t == 0) s_run = 0;
+        __syncthreads();
+        for (int k0 = 0; k0 < ntiles; k0 += kBatchWG) {
+            const int k = k0 + t;
+            const int c = k < ntiles ? d.tile_cnt[m.itile_base + k] : 0;
+            int incl = c;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int u = __shfl_up(incl, o);
+                if (lane >= o) incl += u;
+            }
+            if (lane == 63) s_wave[w] = incl;
+            __syncthreads();
+            int pre = s_run + incl - c;
+            for (int q = 0; q < w; q++) pre += s_wave[q];
+            if (k < ntiles) {
+                d.tile_start[m.itile_base + k] = (int)(m.pt_begin + pre);
+                d.tile_cur[m.itile_base + k] = (int)(m.pt_begin + pre);
+            }
+            __syncthreads();
+            if (t == kBatchWG - 1) s_run = pre + c;
+            __syncthreads();
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBatchWG) void k_b_bin_scatter(BatchDev d, const float* __restrict__ xyz, float c0,
+                                                            float c1, float mr2)
+{
+    __shared__ int s_hist[kBinTiles];
+    const int n = d.n_items[1];
+    for (int it = first_static(n); it >= 0; it = next_static(it, n)) {
+        int64_t b0, b1;
+        const BatchMap& m = d.maps[chunk_item(d, it, b0, b1)];
+        const int ntiles = bin_ntiles(m, d.itile_h);
+        const bool lds = ntiles <= kBinTiles;
+        if (lds)
+            for (int k = threadIdx.x; k < ntiles; k += blockDim.x) s_hist[k] = 0;
+        __syncthreads();
+        // pass 1: each point's rank among the chunk's points in its tile
+        constexpr int U = 8;  // points per thread: chunks of at most 2048 points (the tuning's largest)
+        static_assert(U * kBatchWG >= 2048, "a chunk's points fit the workgroup's registers");
+        int tile[U], rank[U];
+        float4 recu[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            tile[u] = -1;
+            const int64_t i = b0 + threadIdx.x + (int64_t)u * blockDim.x;
+            if (i >= b1) continue;
+            float px, py, pz, r2;
+            int ix, iy;
+            if (point_cell(m.g, m.T, mr2, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], px, py, pz, r2, ix, iy) != 0)
+                continue;
+            tile[u] = bin_tile(m, d.itile_h, ix, iy);
+            int sx = ix + m.g.rx;
+            sx -= (sx >= m.g.W) ? m.g.W : 0;
+            int sy = iy + m.g.ry;
+            sy -= (sy >= m.g.H) ? m.g.H : 0;
+            const float sig = c0 + c1 * r2;
+            recu[u] = make_float4(__int_as_float(sx | (sy << 16)), pz, sig * sig, 0.0f);
+            rank[u] = lds ? atomicAdd(&s_hist[tile[u]], 1) : 0;
+        }
+        __syncthreads();
+        // the chunk's room in each tile it reaches: one atomic per tile
+        if (lds)
+            for (int k = threadIdx.x; k < ntiles; k += blockDim.x)
+                if (s_hist[k] > 0) s_hist[k] = atomicAdd(&d.tile_cur[m.itile_base + k], s_hist[k]);
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            if (tile[u] < 0) continue;
+            const int pos = lds ? s_hist[tile[u]] + rank[u] : atomicAdd(&d.tile_cur[m.itile_base + tile[u]], 1);
+            d.rec[pos] = recu[u];
+        }
+    }
 }
 
 // (map, tile) items: the workgroup owns a kIngestTileW x itile_h block of
@@ -215,8 +268,7 @@ __global__ __launch_bounds__(kBatchWG) void k_b_tile_ingest(BatchDev d)
     float* s_w = (float*)(s_cnt + NC);
     float* s_s = s_w + NC;
     float2* s_first = (float2*)(s_s + NC);
-    __shared__ int s_item;
-    for (int it = next_item(d.qctr, 1, d.n_itiles, &s_item); it >= 0; it = next_item(d.qctr, 1, d.n_itiles, &s_item)) {
+    for (int it = first_static(d.n_itiles); it >= 0; it = next_static(it, d.n_itiles)) {
         const BatchItem I = d.itiles[it];
         const BatchMap& m = d.maps[I.map];
         const int W = m.g.W, x0 = I.a, y0 = I.b;
@@ -326,8 +378,8 @@ __global__ __launch_bounds__(kBatchWG) void k_b_march(BatchDev d, const float* _
                 const float4 p = s_pt[src];
                 const int2 c = s_cell[src];
                 Ray ray(gl, ax, ay, c.x, c.y, sx, sy, sz, p.x, p.y, p.z);
-                visited += walk_logical<8>(gl, ray, d.hl + m.cell_off,
-                                           ClearVoteLogical{d.clr + m.cell_off, m.g, margin});
+                visited += walk_votes<8>(gl, ray, d.hl + m.cell_off, 1, ray.L.steps - 1,
+                                         ClearVoteLogical{d.clr + m.cell_off, m.g, margin});
             }
             __syncthreads();  // the next group overwrites the LDS tables
         }
@@ -357,15 +409,13 @@ __global__ __launch_bounds__(256) void k_b_finalize(BatchDev d, int clear_min)
 // tile side T: the workgroup covers (256 / T^2) tiles per item step.
 __global__ __launch_bounds__(kBatchWG) void k_b_project(BatchDev d, int tile)
 {
-    __shared__ int s_item;
     int visited = 0, in_view_all = 0, vis_all = 0;
     const int per = tile * tile;
     const int sub = threadIdx.x / per;          // tile within the item group
     const int tx = (threadIdx.x % per) % tile, ty = (threadIdx.x % per) / tile;
     const int group = kBatchWG / per;           // tiles per queue pull
     const int n_groups = (d.n_tiles + group - 1) / group;
-    for (int it = next_item(d.qctr, 3, n_groups, &s_item); it >= 0;
-         it = next_item(d.qctr, 3, n_groups, &s_item)) {
+    for (int it = first_static(n_groups); it >= 0; it = next_static(it, n_groups)) {
         const int t = it * group + sub;
         int code[kMaxImages];
 #pragma unroll
@@ -400,7 +450,6 @@ __global__ __launch_bounds__(kBatchWG) void k_b_gather(BatchDev d, int queue,
                                                        int cam_w, int ch_first, LayerDev L,
                                                        int lpp_log2, int topk)
 {
-    __shared__ int s_item;
     const int lane = threadIdx.x & 63;
     const int LPP = 1 << lpp_log2;
     const int sub = lane >> lpp_log2;
@@ -409,8 +458,7 @@ __global__ __launch_bounds__(kBatchWG) void k_b_gather(BatchDev d, int queue,
     const int wave = threadIdx.x >> 6;
     const int nw = blockDim.x >> 6;
     const int esz = IMG == MEM_U8 ? 1 : 4;
-    for (int it = next_item(d.qctr, queue, d.n_gitems, &s_item); it >= 0;
-         it = next_item(d.qctr, queue, d.n_gitems, &s_item)) {
+    for (int it = first_static(d.n_gitems); it >= 0; it = next_static(it, d.n_gitems)) {
         const BatchItem I = d.gitems[it];
         const BatchMap& m = d.maps[I.map];
         const int N = d.pair_count[I.map];
@@ -468,7 +516,11 @@ void launch_batch_step(hipStream_t s, const BatchDev& d, const BatchLaunch& bl, 
     stage("b_reset", [&] { hipLaunchKernelGGL(k_b_reset, dim3(bl.grid), dim3(kBatchWG), 0, s, d, ls); });
     int64_t zb = (d.total_cells + 255) / 256;
     if (zb > 8192) zb = 8192;
-    stage("b_bin", [&] { hipLaunchKernelGGL(k_b_bin, dim3(bl.grid), dim3(kBatchWG), 0, s, d, xyz, c0, c1, mr2); });
+    stage("b_bin", [&] { hipLaunchKernelGGL(k_b_bin, dim3(bl.grid), dim3(kBatchWG), 0, s, d, xyz, mr2); });
+    stage("b_bin_scan", [&] { hipLaunchKernelGGL(k_b_bin_scan, dim3(bl.grid), dim3(kBatchWG), 0, s, d); });
+    stage("b_bin_scatter", [&] {
+        hipLaunchKernelGGL(k_b_bin_scatter, dim3(bl.grid), dim3(kBatchWG), 0, s, d, xyz, c0, c1, mr2);
+    });
     stage("b_tile_ingest", [&] {
         hipLaunchKernelGGL(k_b_tile_ingest, dim3(bl.grid), dim3(kBatchWG), tile_ingest_dyn_lds(d.itile_h), s, d);
     });

@@ -203,7 +203,7 @@ __global__ __launch_bounds__(256) void k_ray_walk(Grid g, Grid gl, const float* 
         Ray ray(gl, ax, ay, cell & 0xffff, cell >> 16, sx, sy, sz, p.x, p.y, 0);
         const int first = 1 + e.y * kSegLen;
         const int cnt = min(kSegLen, ray.L.steps - first);
-        visited += walk_range_logical<8>(gl, ray, hl, first, cnt, ClearVoteLogical{clr, g, margin});
+        visited += walk_votes<8>(gl, ray, hl, first, cnt, ClearVoteLogical{clr, g, margin});
     }
     const int ids[1] = {ST_RAY_CELLS};
     int vals[1] = {visited};

@@ -262,6 +262,7 @@ struct BatchDev {
     float4* rec;             // accepted points binned by ingest tile: (sx | sy << 16, z, v, -)
     int* tile_start;         // [n_itiles] first record of each ingest tile
     int* tile_cnt;           // [n_itiles] its records
+    int* tile_cur;           // [n_itiles] the binning's scatter cursors
     int n_tiles, n_gitems, n_maps, chunk;
     int n_itiles, itile_h;   // ingest tiles are kIngestTileW x itile_h cells
     int64_t total_cells;

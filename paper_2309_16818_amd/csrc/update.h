@@ -286,16 +286,43 @@ struct ClearVoteLogical {
     int* clr;  // storage order
     Grid g;    // the map's grid with its ring offsets
     float margin;
+    __device__ __forceinline__ bool votes(float hk, float zr) const { return hk > zr + margin; }
+    __device__ __forceinline__ void add(int lin) const
+    {
+        const int y = lin / g.W, x = lin - y * g.W;
+        atomicAdd(&clr[storage_index(g, x, y)], 1);
+    }
     __device__ __forceinline__ bool operator()(int lin, float hk, float zr) const
     {
-        const float thr = zr + margin;
-        if (hk > thr) {
-            const int y = lin / g.W, x = lin - y * g.W;
-            atomicAdd(&clr[storage_index(g, x, y)], 1);
-        }
+        if (votes(hk, zr)) add(lin);
         return false;
     }
 };
+
+// walk_range_logical for the clearing votes: each batch's U comparisons are
+// taken without a branch and the rare votes added afterwards, one atomic per
+// voting cell (the same votes as visiting the cells one by one).
+template <int U>
+__device__ __forceinline__ int walk_votes(const Grid& g, Ray& r, const float* __restrict__ h, int first,
+                                          int count, const ClearVoteLogical& vote)
+{
+    r.L.jump_from_start(first - 1);
+    r.L.steps = count + 1;
+    ClearVoteLogical v = vote;
+    return walk_logical_batches<U>(g, r, h, v,
+                                   [&](const int (&s_)[U], const float (&z_)[U], const float (&h_)[U], int n) {
+                                       unsigned m = 0;
+#pragma unroll
+                                       for (int u = 0; u < U; u++)
+                                           m |= (unsigned)(u < n && vote.votes(h_[u], z_[u])) << u;
+                                       if (m) {
+#pragma unroll
+                                           for (int u = 0; u < U; u++)
+                                               if ((m >> u) & 1u) vote.add(s_[u]);
+                                       }
+                                       return false;
+                                   });
+}
 
 // Orders a workgroup's 256 rays by length bucket of 8 cells (bucket 0: no
 // cell; the last bucket takes every ray longer than 8 (NB - 2) cells) with
