@@ -45,19 +45,22 @@ HBM_PEAK_GBS = 8000.0
 # an FMA as two flops on 128 lanes).
 VALU_LANE_OPS = 256 * 64 * 2.4e9
 # VALU instructions a lane executes per cell of a Bresenham walk, counted in
-# the gfx950 ISA of this build: the clearing march's logical walk issues 294
-# per 16 cells in its main loop (step, linear index, ray height, test); the
-# occlusion walk with block-max skipping about 57 per cell it loads.
-WALK_VALU_PER_CELL = {"clear_march": 18, "project": 57}
+# the gfx950 ISA of this build: the clearing walk's main loop issues 208 per
+# 16 cells on its path without votes (step, linear index, ray height,
+# comparison); the occlusion walk with block-max skipping about 57 per cell
+# it loads.
+WALK_VALU_PER_CELL = {"clear_march": 13, "project": 57}
 
-# HBM traffic of kernels from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled
-# by the same counters for a plain 256 MiB copy (profiles/), valid while the
-# kernel's sources hash to `sha`.
+# HBM traffic of kernels from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of the
+# full-rate workload, scaled by the same counters for the calibration copy
+# (a 1 GiB copy reads FETCH_SIZE 524303 KiB: factor 1.99994; writes
+# WRITE_SIZE 1048676 KiB: factor 0.99991; profiles/point_path_traffic.md),
+# bytes per launch, valid while the kernel's sources hash to `sha`.
 TRAFFIC = {
-    # k_clear_march + k_clear_long per cloud, full-rate workload: FETCH_SIZE
-    # (882.6 + 1871.2) KiB x 1.99985 (a 256 MiB copy reads FETCH_SIZE
-    # 131083.5 KiB) + WRITE_SIZE (314.7 + 423.4) KiB x 1.0
-    "clear_march": {"bytes_per_launch": 6394997, "sha": "c5c383cfffb8c395"},
+    "clear_march": {"bytes_per_launch": 4468941, "sha": "c0f96fb031f88851"},  # k_ray_walk
+    "ingest": {"bytes_per_launch": 5627057, "sha": "c0f96fb031f88851"},
+    "finalize": {"bytes_per_launch": 1300155, "sha": "c0f96fb031f88851"},
+    "gather_fuse": {"bytes_per_launch": 2383839, "sha": "a151bc3e23968eab"},  # mean over the frame's images
 }
 
 
@@ -69,8 +72,10 @@ def source_sha(files):
     return h.hexdigest()[:16]
 
 
-KERNEL_SOURCES = {"clear_march": ("k_points.hip", "update.h", "geom.h", "codec.h"),
-                  "project": ("k_image.hip", "update.h", "geom.h", "codec.h")}
+_POINT_SOURCES = ("k_points.hip", "update.h", "geom.h", "codec.h", "mem_internal.h")
+_IMAGE_SOURCES = ("k_image.hip", "update.h", "geom.h", "codec.h", "mem_internal.h")
+KERNEL_SOURCES = {"clear_march": _POINT_SOURCES, "ingest": _POINT_SOURCES, "finalize": _POINT_SOURCES,
+                  "gather_fuse": _IMAGE_SOURCES, "project": _IMAGE_SOURCES}
 
 
 def traffic_bytes(kernel):
@@ -739,8 +744,11 @@ def kernel_bytes(name, st, launches):
     per-call counters: for each kernel its unit (input point, cell, visible
     pair) times the algorithmic bytes of one unit."""
     cells = 500 * 500
-    if name == "ingest":       # 12 B per input point; 12 B of sums per touched cell
-        return 12 * st["points_in"] + 12 * st["cells_touched"]
+    if name == "ingest":       # 12 B per input point; 12 B of sums per touched cell;
+        # the clearing march's lists: a 16 B record per accepted point and an
+        # 8 B entry per ray segment
+        return (12 * st["points_in"] + 12 * st["cells_touched"] + 16 * st["points_accepted"]
+                + 8 * st["ray_segments"])
     if name == "finalize":     # dense n + clr reads; touched: W,S,h,v read, h,v write
         return 8 * cells * launches + 24 * st["cells_touched"]
     if name == "zero_accum":   # n, W, S, clr cleared
@@ -750,8 +758,8 @@ def kernel_bytes(name, st, launches):
         return per_pair * st["pairs_visible"] // 3 + 8 * st["pairs_visible"]
     if name == "project":      # h per cell and camera pose (four poses per launch)
         return 4 * cells * 4 * launches
-    if name == "clear_march":  # xyz re-read
-        return 12 * st["points_in"]
+    if name == "clear_march":  # per segment an 8 B list entry and its ray's 16 B record
+        return 24 * st["ray_segments"]
     return 0
 
 

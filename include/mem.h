@@ -166,6 +166,9 @@ typedef struct mem_stats {
                                    bound channel plane held in LDS; 0 for
                                    batches, whose ingest writes its sums with
                                    plain stores                                 */
+    int64_t ray_segments;       /* pieces of at most 64 cells the clearing rays
+                                   are cut into, one per lane of the walk (0 for
+                                   batches)                                     */
 } mem_stats;
 
 /* Creates a map centred on cell (0, 0) with every cell empty: no height,

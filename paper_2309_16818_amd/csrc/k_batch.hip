@@ -142,10 +142,24 @@ __global__ __launch_bounds__(kBatchWG) void k_b_bin(BatchDev d, const float* __r
         if (lds)
             for (int k = threadIdx.x; k < ntiles; k += blockDim.x) s_hist[k] = 0;
         __syncthreads();
-        for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
+        // every point of the chunk (at most 2048) loaded before any is binned
+        constexpr int U = 8;
+        static_assert(U * kBatchWG >= 2048, "a chunk's points fit the workgroup's registers");
+        float p3[U][3];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t i = b0 + threadIdx.x + (int64_t)u * blockDim.x;
+            const bool in = i < b1;
+            p3[u][0] = in ? xyz[3 * i] : 0.0f;
+            p3[u][1] = in ? xyz[3 * i + 1] : 0.0f;
+            p3[u][2] = in ? xyz[3 * i + 2] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            if (b0 + threadIdx.x + (int64_t)u * blockDim.x >= b1) continue;
             float px, py, pz, r2;
             int ix, iy;
-            const int r = point_cell(m.g, m.T, mr2, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], px, py, pz, r2, ix, iy);
+            const int r = point_cell(m.g, m.T, mr2, p3[u][0], p3[u][1], p3[u][2], px, py, pz, r2, ix, iy);
             points_in++;
             pc.acc += (r == 0);
             pc.nonfinite += (r == -1);
@@ -220,6 +234,15 @@ __global__ __launch_bounds__(kBatchWG) void k_b_bin_scatter(BatchDev d, const fl
         static_assert(U * kBatchWG >= 2048, "a chunk's points fit the workgroup's registers");
         int tile[U], rank[U];
         float4 recu[U];
+        float p3[U][3];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t i = b0 + threadIdx.x + (int64_t)u * blockDim.x;
+            const bool in = i < b1;
+            p3[u][0] = in ? xyz[3 * i] : 0.0f;
+            p3[u][1] = in ? xyz[3 * i + 1] : 0.0f;
+            p3[u][2] = in ? xyz[3 * i + 2] : 0.0f;
+        }
 #pragma unroll
         for (int u = 0; u < U; u++) {
             tile[u] = -1;
@@ -227,7 +250,7 @@ __global__ __launch_bounds__(kBatchWG) void k_b_bin_scatter(BatchDev d, const fl
             if (i >= b1) continue;
             float px, py, pz, r2;
             int ix, iy;
-            if (point_cell(m.g, m.T, mr2, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], px, py, pz, r2, ix, iy) != 0)
+            if (point_cell(m.g, m.T, mr2, p3[u][0], p3[u][1], p3[u][2], px, py, pz, r2, ix, iy) != 0)
                 continue;
             tile[u] = bin_tile(m, d.itile_h, ix, iy);
             int sx = ix + m.g.rx;

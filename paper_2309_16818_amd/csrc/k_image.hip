@@ -205,22 +205,22 @@ void launch_zero_int(hipStream_t s, int* p, int n)
 
 void launch_project(hipStream_t s, const Grid& g, const CameraSet& cs, const float* h, const TileMax& tm, int cap,
                     int* vcount, int* vcount_next, int4* vlist, int* vcode, int32_t* dbg,
-                    unsigned long long* stats)
+                    unsigned long long* stats, LaunchEv ev)
 {
     dim3 grid((g.W + kTile - 1) / kTile, (g.H + kTile - 1) / kTile, (unsigned)cs.n);
     int32_t* d = cs.n == 1 ? dbg : nullptr;
-    hipLaunchKernelGGL(k_view, grid, dim3(kTile, kTile), 0, s, g, cs, h, vlist, vcode, cap, vcount, vcount_next,
-                       d, stats);
+    hipExtLaunchKernelGGL(k_view, grid, dim3(kTile, kTile), 0, s, ev.start, nullptr, 0, g, cs, h, vlist, vcode, cap,
+                          vcount, vcount_next, d, stats);
     int64_t blocks = ((int64_t)cap * kOccLanes + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_occlude, dim3((unsigned)blocks, (unsigned)cs.n), dim3(256), 0, s, g, cs, h, tm, vlist, vcode,
-                       cap, vcount, d, stats);
+    hipExtLaunchKernelGGL(k_occlude, dim3((unsigned)blocks, (unsigned)cs.n), dim3(256), 0, s, nullptr, ev.stop, 0, g,
+                          cs, h, tm, vlist, vcode, cap, vcount, d, stats);
 }
 
 void launch_gather_fuse(hipStream_t s, const int4* vlist, const int* vcode, const int* count, int max_pairs,
                         const void* img, int img_dtype, int64_t s0, int64_t s1, int64_t s2, int w,
-                        int ch_first, const LayerDev& L, int topk)
+                        int ch_first, const LayerDev& L, int topk, LaunchEv ev)
 {
     int lpp_log2 = 0;
     while (topk == 0 && (1 << lpp_log2) < L.C && lpp_log2 < 6) lpp_log2++;
@@ -231,8 +231,8 @@ void launch_gather_fuse(hipStream_t s, const int4* vlist, const int* vcode, cons
     if (blocks < 1) blocks = 1;
     dim3 gr((unsigned)blocks), bl(256);
 #define MEM_GF(IMG, S) \
-    hipLaunchKernelGGL((k_gather_fuse<IMG, S>), gr, bl, 0, s, vlist, vcode, count, img, s0, s1, s2, w, ch_first, \
-                       L, lpp_log2, topk)
+    hipExtLaunchKernelGGL((k_gather_fuse<IMG, S>), gr, bl, 0, s, ev.start, ev.stop, 0, vlist, vcode, count, img, s0, \
+                          s1, s2, w, ch_first, L, lpp_log2, topk)
     if (img_dtype == MEM_U8) {
         if (L.storage == MEM_BF16) MEM_GF(MEM_U8, MEM_BF16);
         else if (L.storage == MEM_FP8_E4M3) MEM_GF(MEM_U8, MEM_FP8_E4M3);

@@ -86,9 +86,10 @@ __global__ __launch_bounds__(kWG) void k_ingest(Grid g, const float* __restrict_
     const int64_t end = begin + kChunk < n ? begin + kChunk : n;
     PointCounts pc;
     ingest_range<kChunk / kWG>(g, xyz, begin, end, ch, T, c0, c1, mr2, pb, acc, lds, pc, march != 0, mb, s_march);
-    const int ids[7] = {ST_ACCEPTED, ST_NONFINITE, ST_RANGE, ST_OUTSIDE, ST_POINTS_IN, ST_FLUSHES, ST_RAY_STEPS};
-    int vals[7] = {pc.acc, pc.nonfinite, pc.range, pc.outside,
-                   pc.acc + pc.nonfinite + pc.range + pc.outside, pc.flushed, pc.ray_steps};
+    const int ids[8] = {ST_ACCEPTED,  ST_NONFINITE, ST_RANGE,     ST_OUTSIDE,
+                        ST_POINTS_IN, ST_FLUSHES,   ST_RAY_STEPS, ST_SEGMENTS};
+    int vals[8] = {pc.acc,     pc.nonfinite, pc.range,     pc.outside, pc.acc + pc.nonfinite + pc.range + pc.outside,
+                   pc.flushed, pc.ray_steps, pc.ray_segs};
     block_stats(stats, ids, vals);
 }
 
@@ -127,8 +128,8 @@ __global__ __launch_bounds__(256) void k_ray_prep(Grid g, const float* __restric
         mb.rec[i] = make_float4(ray.inv_d, ray.dz, __int_as_float(ix | (iy << 16)), 0.0f);
     }
     march_lists<1>(mb, ri, steps, s_march);
-    const int ids[1] = {ST_RAY_STEPS};
-    int vals[1] = {steps[0]};
+    const int ids[2] = {ST_RAY_STEPS, ST_SEGMENTS};
+    int vals[2] = {steps[0], (steps[0] + kSegLen - 1) / kSegLen};
     block_stats(stats, ids, vals);
 }
 
@@ -289,26 +290,27 @@ size_t ingest_lds_bytes(int Cb)
 }
 
 void launch_zero_accum(hipStream_t s, const Grid& g, int* n, float* wsum, float* ssum, int* clr,
-                       float* chsum, int Cb, int* march_counts, const float* h, float* hl, DriftDev* drift)
+                       float* chsum, int Cb, int* march_counts, const float* h, float* hl, DriftDev* drift,
+                       LaunchEv ev)
 {
     int HW = g.W * g.H;
     unsigned b = blocks_for(HW, 256);
     if (b > 4096) b = 4096;
     if (b < 1) b = 1;
-    hipLaunchKernelGGL(k_zero_accum, dim3(b), dim3(256), 0, s, g, n, wsum, ssum, clr, chsum, Cb, march_counts, h, hl,
-                       drift);
+    hipExtLaunchKernelGGL(k_zero_accum, dim3(b), dim3(256), 0, s, ev.start, ev.stop, 0, g, n, wsum, ssum, clr, chsum,
+                          Cb, march_counts, h, hl, drift);
 }
 
 void launch_ingest(hipStream_t s, const Grid& g, const float* xyz, int64_t n, const float* ch,
                    const Pose& T, float c0, float c1, float mr2, const PointBinds& pb, int* cnt,
                    float* wsum, float* ssum, float2* stash, float* chsum, const MarchBufs* march,
-                   unsigned long long* stats)
+                   unsigned long long* stats, LaunchEv ev)
 {
     if (n <= 0) return;
     const Accum acc{cnt, wsum, ssum, stash, nullptr, chsum, g.W * g.H};
     const size_t lds = pb.lds_ch ? sizeof(float) * kSlots * pb.Cb : 0;
-    hipLaunchKernelGGL(k_ingest, dim3(blocks_for(n, kChunk)), dim3(kWG), lds, s, g, xyz, n, ch, T,
-                       c0, c1, mr2, pb, acc, march ? *march : MarchBufs{}, march ? 1 : 0, stats);
+    hipExtLaunchKernelGGL(k_ingest, dim3(blocks_for(n, kChunk)), dim3(kWG), (uint32_t)lds, s, ev.start, ev.stop, 0, g,
+                          xyz, n, ch, T, c0, c1, mr2, pb, acc, march ? *march : MarchBufs{}, march ? 1 : 0, stats);
 }
 
 void march_pass(float mr2, float res, int64_t n, int64_t* pts, int64_t* full_per_ray)
@@ -341,7 +343,7 @@ MarchSizes march_sizes(int64_t pts, int64_t full_per_ray)
 
 void launch_clear_march(hipStream_t s, const Grid& g_storage, const float* xyz, int64_t n, const Pose& T,
                         float mr2, float margin, const float* hl, int* clr, const MarchBufs& mb,
-                        bool prepared, unsigned long long* stats)
+                        bool prepared, unsigned long long* stats, LaunchEv ev)
 {
     // the walks read heights in logical order: the grid without its ring offsets
     const Grid& g = g_storage;
@@ -354,10 +356,15 @@ void launch_clear_march(hipStream_t s, const Grid& g_storage, const float* xyz, 
     for (int64_t b = 0; b < n; b += mb.cap_pts) {
         const int64_t m = n - b < mb.cap_pts ? n - b : mb.cap_pts;
         if (b > 0) launch_zero_int(s, mb.counts, kSegLists * kSegSubs);
-        if (!(prepared && b == 0))
-            hipLaunchKernelGGL(k_ray_prep, dim3(blocks_for(m, 256)), dim3(256), 0, s, g, xyz + 3 * b, m, T, mr2,
-                               mb, stats);
-        hipLaunchKernelGGL(k_ray_walk, dim3(kWalkGrid), dim3(256), 0, s, g, gl, hl, T, margin, clr, mb, stats);
+        // the events: start on the pass's first kernel, stop on the last pass's walk
+        hipEvent_t e0 = b == 0 ? ev.start : nullptr, e1 = b + m >= n ? ev.stop : nullptr;
+        if (!(prepared && b == 0)) {
+            hipExtLaunchKernelGGL(k_ray_prep, dim3(blocks_for(m, 256)), dim3(256), 0, s, e0, nullptr, 0, g, xyz + 3 * b,
+                                  m, T, mr2, mb, stats);
+            e0 = nullptr;
+        }
+        hipExtLaunchKernelGGL(k_ray_walk, dim3(kWalkGrid), dim3(256), 0, s, e0, e1, 0, g, gl, hl, T, margin, clr, mb,
+                              stats);
     }
 }
 
@@ -385,13 +392,13 @@ void launch_tile_max(hipStream_t s, const Grid& g, const float* h, float* t8, fl
 void launch_finalize(hipStream_t s, const Grid& g, const int* cnt, const float* wsum,
                      const float* ssum, const float2* stash, const int* clr, int clear_min,
                      float* h, float* v, const float* chsum, const PointBinds& pb,
-                     unsigned long long* stats)
+                     unsigned long long* stats, LaunchEv ev)
 {
     const int HW = g.W * g.H;
     const Accum acc{const_cast<int*>(cnt), const_cast<float*>(wsum), const_cast<float*>(ssum),
                     const_cast<float2*>(stash), const_cast<int*>(clr), const_cast<float*>(chsum), HW};
-    hipLaunchKernelGGL(k_finalize, dim3(blocks_for(HW, 256)), dim3(256), 0, s, g, acc, clear_min, h,
-                       v, pb, stats);
+    hipExtLaunchKernelGGL(k_finalize, dim3(blocks_for(HW, 256)), dim3(256), 0, s, ev.start, ev.stop, 0, g, acc,
+                          clear_min, h, v, pb, stats);
 }
 
 void launch_point_cells(hipStream_t s, const Grid& g, const float* xyz, int64_t n, const Pose& T,

@@ -194,6 +194,14 @@ void timed(mem_map* m, hipStream_t s, const char* name, F&& f)
     m->prof.timed(s, name, f);
 }
 
+// Runs a launcher that takes LaunchEv (events recorded by its kernels' own
+// dispatch) while profiling is on.
+template <class F>
+void timed_ext(mem_map* m, hipStream_t s, const char* name, F&& f)
+{
+    m->prof.timed_ext(s, name, f);
+}
+
 mem_status usable(const mem_map* m)
 {
     if (!m) return fail(MEM_E_ARG, "map is NULL");
@@ -550,32 +558,33 @@ mem_status mem_input_pointcloud(mem_map* m, const float* xyz, int64_t n, const f
             m->march.part_sub = z.part_sub;
         }
     }
-    timed(m, s, "zero_accum", [&] {
+    timed_ext(m, s, "zero_accum", [&](LaunchEv ev) {
         launch_zero_accum(s, g, m->cnt, m->wsum, m->ssum, m->clr, m->chsum, pb.Cb, m->march.counts, m->h,
-                          march ? m->hl : nullptr, m->drift);
+                          march ? m->hl : nullptr, m->drift, ev);
     });
     Pose T;
     memcpy(T.m, T_map_sensor, sizeof(T.m));
     // a cloud that fits one march pass has its rays listed by the ingest
     const bool fused = march && n <= m->march.cap_pts;
-    timed(m, s, "ingest", [&] {
-        launch_ingest(s, g, xyz, n, ch, T, m->c0, m->c1, m->mr2, pb, m->cnt, m->wsum, m->ssum, m->stash,
-                      m->chsum, fused ? &m->march : nullptr, m->stats);
-    });
+    if (n > 0)
+        timed_ext(m, s, "ingest", [&](LaunchEv ev) {
+            launch_ingest(s, g, xyz, n, ch, T, m->c0, m->c1, m->mr2, pb, m->cnt, m->wsum, m->ssum, m->stash,
+                          m->chsum, fused ? &m->march : nullptr, m->stats, ev);
+        });
     if (m->drift_on && n > 0)
         timed(m, s, "drift", [&] {
             launch_drift(s, g, xyz, n, T, m->c0, m->c1, m->mr2, m->h, m->v, m->drift_kappa2, m->drift_min,
                          m->drift, m->drift_part, march ? m->hl : nullptr);
         });
     if (march)
-        timed(m, s, "clear_march", [&] {
+        timed_ext(m, s, "clear_march", [&](LaunchEv ev) {
             launch_clear_march(s, g, xyz, n, T, m->mr2, m->clear_margin, m->hl, m->clr, m->march, fused,
-                               m->stats);
+                               m->stats, ev);
         });
     m->tmax_stale = true;
-    timed(m, s, "finalize", [&] {
+    timed_ext(m, s, "finalize", [&](LaunchEv ev) {
         launch_finalize(s, g, m->cnt, m->wsum, m->ssum, m->stash, m->clr, m->clear_min, m->h, m->v,
-                        m->chsum, pb, m->stats);
+                        m->chsum, pb, m->stats, ev);
     });
     if (m->overlap_on)
         timed(m, s, "overlap_clear", [&] {
@@ -776,7 +785,9 @@ static mem_status input_poses(mem_map* m, const mem_image* images, const int32_t
     }
     TileMax tm;
     timed(m, s, "tile_max", [&] { tm = m->tiles(s); });
-    timed(m, s, "project", [&] { launch_project(s, g, cs, m->h, tm, cap, vc, vc_next, vlist, vcode, nullptr, m->stats); });
+    timed_ext(m, s, "project", [&](LaunchEv ev) {
+        launch_project(s, g, cs, m->h, tm, cap, vc, vc_next, vlist, vcode, nullptr, m->stats, ev);
+    });
     first = 0;
     for (int p = 0; p < n_poses; p++) {
         for (int k = 0; k < counts[p]; k++) {
@@ -785,11 +796,11 @@ static mem_status input_poses(mem_map* m, const mem_image* images, const int32_t
                 const Layer* L = nullptr;
                 resolve_layer(m, im.bind[b].layer, &L);
                 LayerDev d = L->dev();
-                timed(m, s, "gather_fuse", [&] {
+                timed_ext(m, s, "gather_fuse", [&](LaunchEv ev) {
                     launch_gather_fuse(s, vlist + (int64_t)p * cap,
                                        vcode + ((int64_t)p * kMaxImages + k) * cap, vc + p, cap, im.data,
                                        im.dtype, im.strides[0], im.strides[1], im.strides[2], im.w,
-                                       im.bind[b].ch_first, d, im.bind[b].topk);
+                                       im.bind[b].ch_first, d, im.bind[b].topk, ev);
                 });
             }
         }

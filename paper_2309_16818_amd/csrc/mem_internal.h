@@ -23,13 +23,15 @@
 #include <string>
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "../../include/mem.h"
 
 namespace memk {
 
 constexpr int kMaxBind = 8;
 constexpr int kMaxTopk = 64;  // classes listed per top-k class input
-constexpr int kStats = 14;  // device counters, order of mem_stats
+constexpr int kStats = 15;  // device counters, order of mem_stats
 // Device counters are [kStats][kStatSlots]: a workgroup adds into slot
 // (block id mod kStatSlots), so no single address sees more than
 // 1/kStatSlots of the atomics.
@@ -49,7 +51,8 @@ enum Stat {
     ST_OCCL_CELLS,
     ST_RAY_STEPS,
     ST_OCCL_STEPS,
-    ST_FLUSHES
+    ST_FLUSHES,
+    ST_SEGMENTS
 };
 
 // Grid geometry handed to every kernel.
@@ -127,13 +130,22 @@ struct CameraSet {
     int n;
 };
 
+// Events a profiled launcher hands to hipExtLaunchKernel: `start` is
+// recorded when its first kernel starts executing and `stop` when its last
+// one ends, so their interval is the kernels' own time (no dispatch gap);
+// null when not profiling.
+struct LaunchEv {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
 // ---- launchers (implemented in the .hip files) ----
 // `march_counts`, if not null, are the clearing march's kSegLists list
 // counts, cleared as well.
 // `hl`, if not null, receives a copy of the heights `h` in logical order
 // (index y * W + x).
 void launch_zero_accum(hipStream_t s, const Grid& g, int* n, float* wsum, float* ssum, int* clr,
-                       float* chsum, int Cb, int* march_counts, const float* h, float* hl, DriftDev* drift);
+                       float* chsum, int Cb, int* march_counts, const float* h, float* hl, DriftDev* drift,
+                       LaunchEv ev = {});
 // LDS bytes of the ingest kernel for `Cb` channel planes reduced in LDS.
 size_t ingest_lds_bytes(int Cb);
 struct MarchBufs;
@@ -142,7 +154,7 @@ struct MarchBufs;
 void launch_ingest(hipStream_t s, const Grid& g, const float* xyz, int64_t n, const float* ch,
                    const Pose& T, float c0, float c1, float mr2, const PointBinds& pb, int* cnt,
                    float* wsum, float* ssum, float2* stash, float* chsum, const MarchBufs* march,
-                   unsigned long long* stats);
+                   unsigned long long* stats, LaunchEv ev = {});
 // The clearing march's buffers: a pass's rays (1 / major extent, height
 // difference, cell), the
 // kSegSubs sub-lists of their full segments of kSegLen cells (full_sub
@@ -176,7 +188,7 @@ MarchSizes march_sizes(int64_t pts, int64_t full_per_ray);
 // (launch_ingest with `march`, for a cloud of at most cap_pts points).
 void launch_clear_march(hipStream_t s, const Grid& g, const float* xyz, int64_t n, const Pose& T,
                         float mr2, float margin, const float* hl, int* clr, const MarchBufs& mb,
-                        bool prepared, unsigned long long* stats);
+                        bool prepared, unsigned long long* stats, LaunchEv ev = {});
 // z-error count and drift compensation of one cloud: the consistent points'
 // sums into `drift`, then, with at least min_points of them, the shift of
 // every held height h (and its logical-order copy hl, if given) by their
@@ -189,7 +201,7 @@ size_t drift_part_bytes();
 void launch_finalize(hipStream_t s, const Grid& g, const int* cnt, const float* wsum,
                      const float* ssum, const float2* stash, const int* clr, int clear_min,
                      float* h, float* v, const float* chsum, const PointBinds& pb,
-                     unsigned long long* stats);
+                     unsigned long long* stats, LaunchEv ev = {});
 void launch_point_cells(hipStream_t s, const Grid& g, const float* xyz, int64_t n, const Pose& T,
                         float mr2, int32_t* out);
 
@@ -207,14 +219,14 @@ void launch_tile_max(hipStream_t s, const Grid& g, const float* h, float* t8, fl
 // separate clear is launched.  dbg is written for a single pose only.
 void launch_project(hipStream_t s, const Grid& g, const CameraSet& cs, const float* h, const TileMax& tm, int cap,
                     int* vcount, int* vcount_next, int4* vlist, int* vcode, int32_t* dbg,
-                    unsigned long long* stats);
+                    unsigned long long* stats, LaunchEv ev = {});
 // Fuses image channels into layer L for the listed cells whose code (image's
 // row of vcode) is >= 0.
 // topk > 0: the binding's inputs are topk class indices then their
 // probabilities (Dirichlet layers), fused by one lane per visible pair.
 void launch_gather_fuse(hipStream_t s, const int4* vlist, const int* vcode, const int* count, int max_pairs,
                         const void* img, int img_dtype, int64_t s0, int64_t s1, int64_t s2, int w,
-                        int ch_first, const LayerDev& L, int topk = 0);
+                        int ch_first, const LayerDev& L, int topk = 0, LaunchEv ev = {});
 
 // ---- batches of maps ----
 

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "mem.h"
+#include "mem_internal.h"
 
 namespace memk {
 
@@ -65,6 +66,22 @@ struct Profiler {
         (void)hipEventRecord(a, s);
         f();
         (void)hipEventRecord(b, s);
+        pending.push_back({name, a, b});
+        if (pending.size() >= 8192) drain();
+    }
+
+    // As timed(), for launchers that take the events themselves (LaunchEv:
+    // recorded by the kernels' own dispatch, so without the dispatch gap).
+    template <class F>
+    void timed_ext(hipStream_t s, const char* name, F&& f)
+    {
+        (void)s;
+        if (!on) {
+            f(LaunchEv{});
+            return;
+        }
+        hipEvent_t a = get(), b = get();
+        f(LaunchEv{a, b});
         pending.push_back({name, a, b});
         if (pending.size() >= 8192) drain();
     }

@@ -39,6 +39,7 @@ struct PointCounts {
     int acc = 0, nonfinite = 0, range = 0, outside = 0;
     int flushed = 0;  // cells whose sums this thread flushed with global atomics
     int ray_steps = 0;  // cells the clearing rays of this thread's points walk (when listed)
+    int ray_segs = 0;   // the segments they are listed in
 };
 
 // Aggregates points [begin, end) of a cloud (at most 2^slots_log2 / 2
@@ -190,6 +191,7 @@ __device__ __forceinline__ void ingest_range(const Grid& g, const float* __restr
             if (i < end && point_cell(g, T, mr2, in[k][0], in[k][1], in[k][2], px, py, pz, r2, ix, iy) == 0) {
                 msteps[k] = max(max(abs(ix - ax), abs(iy - ay)) - 1, 0);
                 pc.ray_steps += msteps[k];
+                pc.ray_segs += (msteps[k] + kSegLen - 1) / kSegLen;
                 if (msteps[k] > 0) {
                     const Ray ray(g, ax, ay, ix, iy, T.m[3], T.m[7], T.m[11], px, py, pz);
                     mb.rec[i] = make_float4(ray.inv_d, ray.dz, __int_as_float(ix | (iy << 16)), 0.0f);

@@ -25,7 +25,7 @@ MEM_VIEW_VALUE, MEM_VIEW_AUX, MEM_VIEW_ARGMAX = 0, 1, 2
 
 STAT_FIELDS = ("points_in", "points_accepted", "dropped_nonfinite", "dropped_range", "dropped_outside",
                "cells_touched", "cells_cleared", "ray_cells", "cells_in_view", "pairs_visible",
-               "occl_cells", "ray_steps", "occl_steps", "cell_flushes")
+               "occl_cells", "ray_steps", "occl_steps", "cell_flushes", "ray_segments")
 
 # Exported symbols of include/mem.h.
 SYMBOLS = ("mem_create", "mem_destroy", "mem_move", "mem_input_pointcloud", "mem_input_image",
