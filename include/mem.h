@@ -554,6 +554,13 @@ mem_status mem_unet_get_params(const mem_unet* net, float* params, void* stream)
  * gemm_wgrad (weight gradients), im2col, head, pool, eltwise, colsum, fill,
  * relayout, adam. */
 mem_status mem_unet_profile_enable(mem_unet* net, int32_t on);
+/* Tests: every product C = A B^T of the network (forward convolutions,
+ * transposed convolutions, input gradients) takes workgroup tile `shape`:
+ * 0 = 64 x 64, 1 = 128 x 32, 2 = 256 x 32, 3 = 128 x 128 (rows x columns);
+ * -1 (the default) chooses by the product's shape.  Every shape sums each
+ * output over K in the same order, so the products are equal bit for bit.
+ * Errors: MEM_E_ARG. */
+mem_status mem_unet_debug_tiles(mem_unet* net, int32_t shape);
 mem_status mem_unet_profile_read(mem_unet* net, mem_kernel_time* out, int32_t max, int32_t* count);
 
 /* Writes / reads the parameters as a file: the 8 bytes "MEMUNET1", int32

@@ -89,29 +89,33 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v)
     return r;
 }
 
-// C = A B^T on a (32 WM) x (32 WN) tile, WM WN = 4: four waves, each a
-// 32x32 quadrant of 2x2 MFMA 16x16x32 blocks.  Lane l of an MFMA block
-// supplies A[l % 16][8 (l / 16) .. + 7] and B[l % 16][8 (l / 16) .. + 7] and
-// receives D[4 (l / 16) + j][l % 16].  K advances in slices of 32 through two
-// LDS stages: the next slice's global loads are in flight while the MFMAs
-// consume the current one, with one barrier per slice.
-template <int EPI, bool CONV, int WM>
+// C = A B^T on a (WTM WM) x (WTN WN) tile, WM WN = 4: four waves, each a
+// WTM x WTN block of (WTM / 16) x (WTN / 16) MFMA 16x16x32 blocks.  Lane l
+// of an MFMA block supplies A[l % 16][8 (l / 16) .. + 7] and
+// B[l % 16][8 (l / 16) .. + 7] and receives D[4 (l / 16) + j][l % 16].  A
+// wave reads its WTN / 16 B fragments of a K slice once and each A fragment
+// once, so every fragment read from LDS feeds WTN / 16 (or WTM / 16) MFMAs.
+// K advances in slices of 32 through two LDS stages: the next slice's
+// global loads are in flight while the MFMAs consume the current one, with
+// one barrier per slice.
+template <int EPI, bool CONV, int WM, int WTM, int WTN>
 __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A, int64_t lda, ConvSrc cs,
                                                  const uint16_t* __restrict__ B, int64_t ldb, int M,
                                                  int N, int K, Epilogue ep)
 {
-    constexpr int WN = 4 / WM, TM = 32 * WM, TN = 32 * WN;
+    constexpr int WN = 4 / WM, TM = WTM * WM, TN = WTN * WN, IM = WTM / 16, JN = WTN / 16;
+    static_assert(TM % 64 == 0 && WTM % 16 == 0 && WTN % 16 == 0, "tile shape");
     constexpr int CA = TM * 4 / 256, CB = (TN * 4 + 255) / 256;  // 8-wide chunks per thread
     __shared__ uint16_t sA[2][TM * LDSK];
     __shared__ uint16_t sB[2][TN * LDSK];
     const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave / WN) * 32, wn = (wave % WN) * 32;
-    f32x4 acc[2][2];
+    const int wm = (wave / WN) * WTM, wn = (wave % WN) * WTN;
+    f32x4 acc[IM][JN];
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < IM; i++)
 #pragma unroll
-        for (int j = 0; j < 2; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < JN; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int lk = (tid & 3) * 8;  // K offset of every chunk of this thread
     int64_t pn[CA];
     int pr[CA], pq[CA];
@@ -157,23 +161,23 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A,
     for (int k0 = 0; k0 < K; k0 += BK) {
         const bool more = k0 + BK < K;
         if (more) load(k0 + BK);
+        bf16x8 b[JN];
 #pragma unroll
-        for (int i = 0; i < 2; i++) {
+        for (int j = 0; j < JN; j++) b[j] = as_bf16x8(*(const uint4*)&sB[cur][(wn + 16 * j + fr) * LDSK + fk]);
+#pragma unroll
+        for (int i = 0; i < IM; i++) {
             const bf16x8 a = as_bf16x8(*(const uint4*)&sA[cur][(wm + 16 * i + fr) * LDSK + fk]);
 #pragma unroll
-            for (int j = 0; j < 2; j++) {
-                const bf16x8 b = as_bf16x8(*(const uint4*)&sB[cur][(wn + 16 * j + fr) * LDSK + fk]);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
-            }
+            for (int j = 0; j < JN; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[i][j], 0, 0, 0);
         }
         if (more) stash(cur ^ 1);
         __syncthreads();
         cur ^= 1;
     }
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < IM; i++)
 #pragma unroll
-        for (int j = 0; j < 2; j++)
+        for (int j = 0; j < JN; j++)
 #pragma unroll
             for (int r = 0; r < 4; r++) {
                 const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
@@ -880,29 +884,44 @@ inline unsigned grid_for(int64_t n)
 
 }  // namespace
 
-// Narrow outputs (32 columns or fewer) take 128x32 tiles so no MFMA block
-// works on padding.
+// Tile of a product: 128 x 32 for 32 or fewer output columns (no MFMA block
+// on padding), else 64 x 64; both with waves of 32 x 32.  Larger tiles
+// (256 x 32 and 128 x 128, waves of 64 x 32 and 64 x 64, so that each LDS
+// fragment feeds more MFMAs) measured slower on every layer of the network
+// (the products wait on their operand loads, not on LDS): they are kept for
+// force_shape >= 0 (0: 64 x 64, 1: 128 x 32, 2: 256 x 32, 3: 128 x 128),
+// which the tests use to check that every shape gives the same products.
 void unet_gemm_nt(hipStream_t s, int epi, const uint16_t* A, int64_t lda, const ConvSrc* conv, const uint16_t* B,
-                  int64_t ldb, int M, int N, int K, const Epilogue& ep)
+                  int64_t ldb, int M, int N, int K, const Epilogue& ep, int n_cu, int force_shape)
 {
+    (void)n_cu;
     const ConvSrc cs = conv ? *conv : ConvSrc{nullptr, 0, 1, 1};
-    const bool narrow = N <= 32;
-    const int TM = narrow ? 128 : 64, TN = narrow ? 32 : 64;
+    const int shape = force_shape >= 0 ? (force_shape & 3) : (N <= 32 ? 1 : 0);
+    const int TM = shape == 0 ? 64 : shape == 2 ? 256 : 128;
+    const int TN = shape == 0 ? 64 : shape == 3 ? 128 : 32;
     dim3 grid((M + TM - 1) / TM, (N + TN - 1) / TN);
-#define MEM_GNT(E, CV, W) \
-    hipLaunchKernelGGL((k_gemm_nt<E, CV, W>), grid, dim3(256), 0, s, A, lda, cs, B, ldb, M, N, K, ep)
-#define MEM_GNT_E(CV, W)                                   \
+#define MEM_GNT(E, CV, W, WTM, WTN) \
+    hipLaunchKernelGGL((k_gemm_nt<E, CV, W, WTM, WTN>), grid, dim3(256), 0, s, A, lda, cs, B, ldb, M, N, K, ep)
+#define MEM_GNT_S(E, CV)                                            \
+    switch (shape) {                                                \
+    case 1: MEM_GNT(E, CV, 4, 32, 32); break;                       \
+    case 2: MEM_GNT(E, CV, 4, 64, 32); break;                       \
+    case 3: MEM_GNT(E, CV, 2, 64, 64); break;                       \
+    default: MEM_GNT(E, CV, 2, 32, 32); break;                      \
+    }
+#define MEM_GNT_E(CV)                                      \
     switch (epi) {                                         \
-    case EPI_STORE: MEM_GNT(EPI_STORE, CV, W); break;      \
-    case EPI_CONVT: MEM_GNT(EPI_CONVT, CV, W); break;      \
-    default: MEM_GNT(EPI_F32, CV, W); break;               \
+    case EPI_STORE: MEM_GNT_S(EPI_STORE, CV) break;        \
+    case EPI_CONVT: MEM_GNT_S(EPI_CONVT, CV) break;        \
+    default: MEM_GNT_S(EPI_F32, CV) break;                 \
     }
     if (conv) {
-        if (narrow) { MEM_GNT_E(true, 4) } else { MEM_GNT_E(true, 2) }
+        MEM_GNT_E(true)
     } else {
-        if (narrow) { MEM_GNT_E(false, 4) } else { MEM_GNT_E(false, 2) }
+        MEM_GNT_E(false)
     }
 #undef MEM_GNT_E
+#undef MEM_GNT_S
 #undef MEM_GNT
 }
 

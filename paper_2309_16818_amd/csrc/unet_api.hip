@@ -48,6 +48,7 @@ int round32(int k) { return (k + 31) / 32 * 32; }
 
 struct mem_unet {
     int base = 0, S = 0, maxB = 0, n_cu = 256;
+    int gemm_shape = -1;  // forced tile shape of the nt products (-1: automatic)
     int64_t n_params = 0;
     bool broken = false;
     ULayer L[NLAY];
@@ -184,13 +185,13 @@ void conv_fwd(mem_unet* u, hipStream_t s, int i, const uint16_t* x, int xs, int 
     if (implicit(Y.ci, xs)) {  // the GEMM reads the unfolded input in place
         const ConvSrc cs{x, xs, Y.ci, S};
         u->prof.timed(s, "gemm_fwd", [&] {
-            unet_gemm_nt(s, EPI_STORE, nullptr, 0, &cs, Y.wf, Y.kf, P, Y.co, 9 * Y.ci, ep);
+            unet_gemm_nt(s, EPI_STORE, nullptr, 0, &cs, Y.wf, Y.kf, P, Y.co, 9 * Y.ci, ep, u->n_cu, u->gemm_shape);
         });
         return;
     }
     u->prof.timed(s, "im2col", [&] { unet_im2col3(s, x, xs, 0, B, S, Y.ci, u->col, Y.kf); });
     u->prof.timed(s, "gemm_fwd", [&] {
-        unet_gemm_nt(s, EPI_STORE, u->col, Y.kf, nullptr, Y.wf, Y.kf, P, Y.co, Y.kf, ep);
+        unet_gemm_nt(s, EPI_STORE, u->col, Y.kf, nullptr, Y.wf, Y.kf, P, Y.co, Y.kf, ep, u->n_cu, u->gemm_shape);
     });
 }
 
@@ -217,7 +218,7 @@ void forward(mem_unet* u, hipStream_t s, int B)
         const ULayer& U = u->L[k];
         Epilogue ep{bias(u, u->w, k), 0, u->cat[l], 2 * c, 0, nullptr, 0, u->S >> (l + 1), c};
         u->prof.timed(s, "gemm_up", [&] {
-            unet_gemm_nt(s, EPI_CONVT, below, U.ci, nullptr, U.wf, U.ci, (int)P_at(u, B, l + 1), 4 * c, U.ci, ep);
+            unet_gemm_nt(s, EPI_CONVT, below, U.ci, nullptr, U.wf, U.ci, (int)P_at(u, B, l + 1), 4 * c, U.ci, ep, u->n_cu, u->gemm_shape);
         });
         conv_fwd(u, s, k + 1, u->cat[l], 2 * c, B, l, u->m[l], c, 0);
         conv_fwd(u, s, k + 2, u->m[l], c, B, l, u->d[l], c, 0);
@@ -252,13 +253,13 @@ void conv_bwd(mem_unet* u, hipStream_t s, int i, const uint16_t* x, int xs, int 
     if (implicit(Y.co, Y.co)) {
         const ConvSrc cs{gy, Y.co, Y.co, S};
         u->prof.timed(s, "gemm_dgrad", [&] {
-            unet_gemm_nt(s, EPI_F32, nullptr, 0, &cs, Y.wd, Y.kd, P, Y.ci, 9 * Y.co, ep);
+            unet_gemm_nt(s, EPI_F32, nullptr, 0, &cs, Y.wd, Y.kd, P, Y.ci, 9 * Y.co, ep, u->n_cu, u->gemm_shape);
         });
         return;
     }
     u->prof.timed(s, "im2col", [&] { unet_im2col3(s, gy, Y.co, 0, B, S, Y.co, u->col, Y.kd); });
     u->prof.timed(s, "gemm_dgrad", [&] {
-        unet_gemm_nt(s, EPI_F32, u->col, Y.kd, nullptr, Y.wd, Y.kd, P, Y.ci, Y.kd, ep);
+        unet_gemm_nt(s, EPI_F32, u->col, Y.kd, nullptr, Y.wd, Y.kd, P, Y.ci, Y.kd, ep, u->n_cu, u->gemm_shape);
     });
 }
 
@@ -310,7 +311,7 @@ void backward(mem_unet* u, hipStream_t s, int B, const float* target, const floa
         u->prof.timed(s, "colsum", [&] { unet_colsum(s, gt, c, P, c, bias(u, u->g, k)); });
         Epilogue ep{nullptr, 0, nullptr, 0, 0, u->tmpf, U.ci, 0, 0};
         u->prof.timed(s, "gemm_dgrad", [&] {
-            unet_gemm_nt(s, EPI_F32, u->gch, 4 * c, nullptr, U.wd, 4 * c, (int)Pb, U.ci, 4 * c, ep);
+            unet_gemm_nt(s, EPI_F32, u->gch, 4 * c, nullptr, U.wd, 4 * c, (int)Pb, U.ci, 4 * c, ep, u->n_cu, u->gemm_shape);
         });
         if (l < 2) {
             u->prof.timed(s, "eltwise", [&] {
@@ -551,6 +552,14 @@ mem_status mem_unet_train_step(mem_unet* u, const float* x, const float* target,
     u->prof.timed(s, "adam", [&] { unet_adam(s, u->w, u->g, u->am, u->av, u->n_params, lr, b1, b2, 1e-8f, c1, c2); });
     relayout_all(u, s);
     return finish(u, "mem_unet_train_step");
+}
+
+mem_status mem_unet_debug_tiles(mem_unet* u, int32_t shape)
+{
+    if (!u) return api_fail(MEM_E_ARG, "network is NULL");
+    if (shape < -1 || shape > 3) return api_fail(MEM_E_ARG, "shape must be -1 (automatic) or 0..3");
+    u->gemm_shape = shape;
+    return MEM_OK;
 }
 
 mem_status mem_unet_profile_enable(mem_unet* u, int32_t on)

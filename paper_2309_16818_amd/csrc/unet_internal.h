@@ -60,7 +60,8 @@ struct ConvSrc {
 // A (M x K, row stride lda) is dense, or the unfolded input `conv` (then A
 // and lda are ignored and K = 9 ci).
 void unet_gemm_nt(hipStream_t s, int epi, const uint16_t* A, int64_t lda, const ConvSrc* conv, const uint16_t* B,
-                  int64_t ldb, int M, int N, int K, const Epilogue& ep);
+                  int64_t ldb, int M, int N, int K, const Epilogue& ep, int n_cu,
+                  int force_shape = -1);
 // B (P x N, row stride ldb) is dense, or the unfolded input `conv` (N = 9 ci).
 void unet_gemm_tn(hipStream_t s, const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, const ConvSrc* conv,
                   int P, int M, int N, float* C, int64_t ldc, int n_cu);

@@ -612,7 +612,7 @@ class Batch:
 UNET_SYMBOLS = ("mem_unet_num_params", "mem_unet_create", "mem_unet_destroy", "mem_unet_set_params",
                 "mem_unet_get_params", "mem_unet_save", "mem_unet_load", "mem_unet_forward",
                 "mem_unet_loss_grad", "mem_unet_train_step", "mem_unet_input", "mem_unet_complete",
-                "mem_unet_profile_enable", "mem_unet_profile_read", "mem_complete")
+                "mem_unet_profile_enable", "mem_unet_profile_read", "mem_complete", "mem_unet_debug_tiles")
 
 
 def _load_unet():
@@ -634,6 +634,7 @@ def _load_unet():
         "mem_unet_complete": [P, P, I32, F, F, P, P, P],
         "mem_complete": [P, P, F, F, P, P, P],
         "mem_unet_profile_enable": [P, I32],
+        "mem_unet_debug_tiles": [P, I32],
         "mem_unet_profile_read": [P, C.POINTER(mem_kernel_time), I32, C.POINTER(I32)],
     }
     for name, args in sig.items():
@@ -698,6 +699,10 @@ class UNet:
 
     def profile_enable(self, on=True):
         _check(_load_unet().mem_unet_profile_enable(self._u, 1 if on else 0))
+
+    def debug_tiles(self, shape: int):
+        """Force the tile shape of every nt product (0-3; -1 automatic)."""
+        _check(_load_unet().mem_unet_debug_tiles(self._u, int(shape)))
 
     def profile_read(self) -> dict:
         """{name: (launches, total_ms)} since the last read."""

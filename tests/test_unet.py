@@ -119,6 +119,32 @@ def test_forward_matches_oracle(base, B, S):
     net.close()
 
 
+@pytest.mark.parametrize("base,B,S", [(6, 2, 40), (32, 1, 32)])
+def test_every_tile_shape_gives_the_same_products(base, B, S):
+    """Every workgroup tile of the products C = A B^T (64x64, 128x32,
+    256x32, 128x128; forced here, chosen by size in use) sums each output
+    over K in the same order, so the forward outputs are equal bit for bit
+    and the gradients equal up to the order of the weight gradients' FP32
+    atomics; every shape also meets the oracle's narrow-width bars."""
+    p, x, t, m = sample(base, B, S, 7 * base + S)
+    net = make(base, B, S, p)
+    ref_out = None
+    for shape in (0, 1, 2, 3):
+        net.debug_tiles(shape)
+        out = net.forward(dev(x)).cpu().double().numpy()
+        _, g = net.loss_grad(dev(x), dev(t), dev(m))
+        g = g.cpu().double().numpy()
+        if ref_out is None:
+            ref_out, ref_g = out, g
+            if base <= 6:
+                assert relerr(out, O.unet_forward(p, x, base, bf16=True)) <= 1e-4
+                assert relerr(g, O.unet_loss_grad(p, x, t, m, base, bf16=True)[1]) <= 1e-4
+        assert np.array_equal(out, ref_out), shape
+        assert relerr(g, ref_g) <= 1e-6, (shape, relerr(g, ref_g))
+    net.debug_tiles(-1)
+    net.close()
+
+
 @pytest.mark.parametrize("base,B,S", CASES)
 def test_loss_and_gradient_match_oracle(base, B, S):
     p, x, t, m = sample(base, B, S, 13 * base + S)
