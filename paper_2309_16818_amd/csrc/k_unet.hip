@@ -13,6 +13,7 @@
 #include <initializer_list>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "codec.h"
@@ -206,7 +207,8 @@ __device__ __forceinline__ int tn_slot(int row, int k)
 template <bool CONV, int WM>
 __global__ __launch_bounds__(256) void k_gemm_tn(const uint16_t* __restrict__ A, int64_t lda,
                                                  const uint16_t* __restrict__ B, int64_t ldb, ConvSrc cs, int P,
-                                                 int M, int N, float* __restrict__ C, int64_t ldc)
+                                                 int M, int N, float* __restrict__ C, int64_t ldc,
+                                                 float* __restrict__ parts)
 {
     constexpr int WN = 4 / WM, TM = 32 * WM, TN = 32 * WN;
     constexpr int CA = (TM * 4 + 255) / 256, CB = (TN * 4 + 255) / 256;
@@ -321,8 +323,52 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const uint16_t* __restrict__ A,
             for (int r = 0; r < 4; r++) {
                 const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
                 const int n = n0 + wn + 16 * j + (lane & 15);
-                if (m < M && n < N) unsafeAtomicAdd(&C[(int64_t)m * ldc + n], acc[i][j][r]);
+                if (m >= M || n >= N) continue;
+                if (parts)  // this pixel slice's partial product, summed in a fixed order later
+                    parts[((int64_t)blockIdx.z * M + m) * N + n] = acc[i][j][r];
+                else
+                    unsafeAtomicAdd(&C[(int64_t)m * ldc + n], acc[i][j][r]);
             }
+}
+
+// dst[m][n] (row stride ldd) += sum over k = 0, 1, ... nparts - 1 of
+// parts[k pstride + e], e = m N + n < len: per-workgroup partial sums added
+// in one fixed order, so the result does not depend on the order in which
+// the workgroups ran.  One lane per element, the parts in sequence.
+__global__ void k_reduce_parts(const float* __restrict__ parts, int nparts, int64_t pstride, int64_t len, int N,
+                               float* __restrict__ dst, int64_t ldd)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (int64_t)gridDim.x * blockDim.x) {
+        float s = 0.f;
+        for (int k = 0; k < nparts; k++) s += parts[(int64_t)k * pstride + e];
+        const int64_t m = e / N, n = e - m * N;
+        dst[m * ldd + n] += s;
+    }
+}
+
+// The same sums for few elements and many parts: one workgroup per element,
+// lane t summing parts t, t + 256, ... in sequence, then a tree over the
+// lanes in a fixed pattern.
+__global__ __launch_bounds__(256) void k_reduce_parts_wide(const float* __restrict__ parts, int nparts,
+                                                           int64_t pstride, int64_t len, int N,
+                                                           float* __restrict__ dst, int64_t ldd)
+{
+    __shared__ float red[256];
+    for (int64_t e = blockIdx.x; e < len; e += gridDim.x) {
+        float s = 0.f;
+        for (int k = threadIdx.x; k < nparts; k += 256) s += parts[(int64_t)k * pstride + e];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const int64_t m = e / N, n = e - m * N;
+            dst[m * ldd + n] += red[0];
+        }
+        __syncthreads();
+    }
 }
 
 // Unfolds 3x3 neighbourhoods (zero padding): col[p][t * ci + c] =
@@ -430,7 +476,7 @@ __global__ void k_relu_mask_add(const float* __restrict__ acc, int as, const flo
 // sums a contiguous range of rows for 64 columns at a time (4 row lanes per
 // column, coalesced 128-byte rows), then one atomic per (workgroup, column).
 __global__ __launch_bounds__(256) void k_colsum(const uint16_t* __restrict__ g, int gs, int64_t rows, int c,
-                                                float* __restrict__ db)
+                                                float* __restrict__ db, float* __restrict__ parts)
 {
     const int oc = threadIdx.x & 63, rl = threadIdx.x >> 6;
     const int64_t per = (rows + gridDim.x - 1) / gridDim.x;
@@ -445,7 +491,10 @@ __global__ __launch_bounds__(256) void k_colsum(const uint16_t* __restrict__ g, 
         __syncthreads();
         if (rl == 0 && o < c) {
             const float t = red[0][oc] + red[1][oc] + red[2][oc] + red[3][oc];
-            if (t != 0.f) unsafeAtomicAdd(&db[o], t);
+            if (parts)
+                parts[(int64_t)blockIdx.x * c + o] = t;
+            else if (t != 0.f)
+                unsafeAtomicAdd(&db[o], t);
         }
         __syncthreads();
     }
@@ -456,7 +505,7 @@ __global__ __launch_bounds__(256) void k_colsum(const uint16_t* __restrict__ g, 
 // step and keeps 8 partial sums; the workgroup then adds the partial sums
 // of each channel in LDS, one atomic per channel and workgroup.
 __global__ __launch_bounds__(256) void k_colsum8(const uint16_t* __restrict__ g, int gs, int64_t rows, int c,
-                                                 float* __restrict__ db)
+                                                 float* __restrict__ db, float* __restrict__ parts)
 {
     __shared__ float red[256][9];  // padded against bank conflicts in the column sums
     const int t = threadIdx.x, cpr = c >> 3, q = t % cpr, rr = t / cpr, rstep = 256 / cpr;
@@ -478,7 +527,10 @@ __global__ __launch_bounds__(256) void k_colsum8(const uint16_t* __restrict__ g,
     if (t < c) {  // channel t = chunk t / 8, element t % 8
         float sum = 0.f;
         for (int k = 0; k < rstep; k++) sum += red[k * cpr + (t >> 3)][t & 7];
-        if (sum != 0.f) unsafeAtomicAdd(&db[t], sum);
+        if (parts)
+            parts[(int64_t)blockIdx.x * c + t] = sum;
+        else if (sum != 0.f)
+            unsafeAtomicAdd(&db[t], sum);
     }
 }
 
@@ -514,7 +566,7 @@ __global__ __launch_bounds__(256) void k_head(const uint16_t* __restrict__ d0, i
                                               const int* __restrict__ count, float* __restrict__ out,
                                               float* __restrict__ loss,
                                               float2* __restrict__ gout, float* __restrict__ gb,
-                                              uint16_t* __restrict__ gd0)
+                                              uint16_t* __restrict__ gd0, float* __restrict__ parts)
 {
     float l_acc = 0.f, g0_acc = 0.f, g1_acc = 0.f;
     // 1 / (cells in the loss), rounded once from binary64 (an empty mask
@@ -594,7 +646,10 @@ __global__ __launch_bounds__(256) void k_head(const uint16_t* __restrict__ d0, i
     __syncthreads();
     if (threadIdx.x < 3) {
         const float v = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
-        if (v != 0.f) unsafeAtomicAdd(threadIdx.x == 0 ? loss : &gb[threadIdx.x - 1], v);
+        if (parts)
+            parts[(int64_t)blockIdx.x * 3 + threadIdx.x] = v;
+        else if (v != 0.f)
+            unsafeAtomicAdd(threadIdx.x == 0 ? loss : &gb[threadIdx.x - 1], v);
     }
 }
 
@@ -602,7 +657,8 @@ __global__ __launch_bounds__(256) void k_head(const uint16_t* __restrict__ d0, i
 // sums a range of pixels for 64 channels (4 pixel lanes per channel), then
 // one atomic per (workgroup, weight).
 __global__ __launch_bounds__(256) void k_head_wgrad(const uint16_t* __restrict__ d0, int c, int64_t P,
-                                                    const float2* __restrict__ gout, float* __restrict__ gw)
+                                                    const float2* __restrict__ gout, float* __restrict__ gw,
+                                                    float* __restrict__ parts)
 {
     const int oc = threadIdx.x & 63, pl = threadIdx.x >> 6;
     const int64_t per = (P + gridDim.x - 1) / gridDim.x;
@@ -624,8 +680,13 @@ __global__ __launch_bounds__(256) void k_head_wgrad(const uint16_t* __restrict__
         if (pl == 0 && i < c) {
             const float t0 = red[0][oc][0] + red[1][oc][0] + red[2][oc][0] + red[3][oc][0];
             const float t1 = red[0][oc][1] + red[1][oc][1] + red[2][oc][1] + red[3][oc][1];
-            if (t0 != 0.f) unsafeAtomicAdd(&gw[2 * i], t0);
-            if (t1 != 0.f) unsafeAtomicAdd(&gw[2 * i + 1], t1);
+            if (parts) {
+                parts[(int64_t)blockIdx.x * 2 * c + 2 * i] = t0;
+                parts[(int64_t)blockIdx.x * 2 * c + 2 * i + 1] = t1;
+            } else {
+                if (t0 != 0.f) unsafeAtomicAdd(&gw[2 * i], t0);
+                if (t1 != 0.f) unsafeAtomicAdd(&gw[2 * i + 1], t1);
+            }
         }
         __syncthreads();
     }
@@ -694,7 +755,8 @@ __global__ void k_add_f32_8(float* __restrict__ dst, int ds, const float* __rest
 // c / 8, 16-byte aligned rows): a thread sums 8 channels' products for its
 // pixels, then the workgroup adds them per weight in LDS.
 __global__ __launch_bounds__(256) void k_head_wgrad8(const uint16_t* __restrict__ d0, int c, int64_t P,
-                                                     const float2* __restrict__ gout, float* __restrict__ gw)
+                                                     const float2* __restrict__ gout, float* __restrict__ gw,
+                                                     float* __restrict__ parts)
 {
     __shared__ float red[256][17];  // 8 channels x 2 outputs, padded
     const int t = threadIdx.x, cpr = c >> 3, q = t % cpr, pl = t / cpr, pstep = 256 / cpr;
@@ -722,7 +784,10 @@ __global__ __launch_bounds__(256) void k_head_wgrad8(const uint16_t* __restrict_
         const int i = t >> 1, o = t & 1;
         float sum = 0.f;
         for (int k = 0; k < pstep; k++) sum += red[k * cpr + (i >> 3)][2 * (i & 7) + o];
-        if (sum != 0.f) unsafeAtomicAdd(&gw[t], sum);
+        if (parts)
+            parts[(int64_t)blockIdx.x * 2 * c + t] = sum;
+        else if (sum != 0.f)
+            unsafeAtomicAdd(&gw[t], sum);
     }
 }
 
@@ -925,30 +990,61 @@ void unet_gemm_nt(hipStream_t s, int epi, const uint16_t* A, int64_t lda, const 
 #undef MEM_GNT
 }
 
-// Narrow outputs (32 rows or fewer) take 32x128 tiles.
-void unet_gemm_tn(hipStream_t s, const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, const ConvSrc* conv,
-                  int P, int M, int N, float* C, int64_t ldc, int n_cu)
+// Narrow outputs (32 rows or fewer) take 32x128 tiles; the pixels are split
+// over enough workgroups to give each CU four.
+static int tn_split(int P, int M, int N, int n_cu, int* TM, int* TN)
 {
     const bool narrow = M <= 32;
-    const int TM = narrow ? 32 : 64, TN = narrow ? 128 : 64;
-    const int tiles = ((M + TM - 1) / TM) * ((N + TN - 1) / TN);
+    *TM = narrow ? 32 : 64;
+    *TN = narrow ? 128 : 64;
+    const int tiles = ((M + *TM - 1) / *TM) * ((N + *TN - 1) / *TN);
     int split = (4 * n_cu + tiles - 1) / tiles;
     const int max_split = (P + 255) / 256;
     if (split > max_split) split = max_split;
     if (split < 1) split = 1;
+    return split;
+}
+
+size_t unet_tn_parts(int P, int M, int N, int n_cu)
+{
+    int TM, TN;
+    return (size_t)tn_split(P, M, N, n_cu, &TM, &TN) * M * N;
+}
+
+// dst (rows of N, stride ldd) += the fixed-order sum of nparts partial
+// arrays of len elements (the k-th at parts + k pstride).
+static void reduce_parts(hipStream_t s, const float* parts, int nparts, int64_t pstride, int64_t len, int N,
+                         float* dst, int64_t ldd)
+{
+    if (len <= 65536 && nparts > 64) {
+        const unsigned g = (unsigned)std::min<int64_t>(len, 4096);
+        hipLaunchKernelGGL(k_reduce_parts_wide, dim3(g), dim3(256), 0, s, parts, nparts, pstride, len, N, dst, ldd);
+    } else {
+        hipLaunchKernelGGL(k_reduce_parts, dim3(grid_for(len)), dim3(256), 0, s, parts, nparts, pstride, len, N, dst,
+                           ldd);
+    }
+}
+
+void unet_gemm_tn(hipStream_t s, const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, const ConvSrc* conv,
+                  int P, int M, int N, float* C, int64_t ldc, int n_cu, float* parts)
+{
+    int TM, TN;
+    const int split = tn_split(P, M, N, n_cu, &TM, &TN);
+    const bool narrow = M <= 32;
     dim3 grid((M + TM - 1) / TM, (N + TN - 1) / TN, split);
     const ConvSrc cs = conv ? *conv : ConvSrc{nullptr, 0, 1, 1};
     if (conv) {
         if (narrow)
-            hipLaunchKernelGGL((k_gemm_tn<true, 1>), grid, dim3(256), 0, s, A, lda, B, ldb, cs, P, M, N, C, ldc);
+            hipLaunchKernelGGL((k_gemm_tn<true, 1>), grid, dim3(256), 0, s, A, lda, B, ldb, cs, P, M, N, C, ldc, parts);
         else
-            hipLaunchKernelGGL((k_gemm_tn<true, 2>), grid, dim3(256), 0, s, A, lda, B, ldb, cs, P, M, N, C, ldc);
+            hipLaunchKernelGGL((k_gemm_tn<true, 2>), grid, dim3(256), 0, s, A, lda, B, ldb, cs, P, M, N, C, ldc, parts);
     } else {
         if (narrow)
-            hipLaunchKernelGGL((k_gemm_tn<false, 1>), grid, dim3(256), 0, s, A, lda, B, ldb, cs, P, M, N, C, ldc);
+            hipLaunchKernelGGL((k_gemm_tn<false, 1>), grid, dim3(256), 0, s, A, lda, B, ldb, cs, P, M, N, C, ldc, parts);
         else
-            hipLaunchKernelGGL((k_gemm_tn<false, 2>), grid, dim3(256), 0, s, A, lda, B, ldb, cs, P, M, N, C, ldc);
+            hipLaunchKernelGGL((k_gemm_tn<false, 2>), grid, dim3(256), 0, s, A, lda, B, ldb, cs, P, M, N, C, ldc, parts);
     }
+    if (parts) reduce_parts(s, parts, split, (int64_t)M * N, (int64_t)M * N, N, C, ldc);
 }
 
 void unet_im2col3(hipStream_t s, const uint16_t* x, int xs, int xo, int B, int S, int ci, uint16_t* col, int kpad)
@@ -1005,39 +1101,73 @@ void unet_relu_mask_add(hipStream_t s, const float* acc, int as, const float* ad
                        c, g, gs);
 }
 
-void unet_colsum(hipStream_t s, const uint16_t* g, int gs, int64_t rows, int c, float* db)
+static int64_t colsum_blocks(int64_t rows)
 {
     int64_t blocks = (rows + 255) / 256;
     if (blocks > 1024) blocks = 1024;
-    if (blocks < 1) blocks = 1;
+    return blocks < 1 ? 1 : blocks;
+}
+
+size_t unet_colsum_parts(int64_t rows, int c)
+{
+    return (size_t)colsum_blocks(rows) * c;
+}
+
+void unet_colsum(hipStream_t s, const uint16_t* g, int gs, int64_t rows, int c, float* db, float* parts)
+{
+    const int64_t blocks = colsum_blocks(rows);
     const int cpr = c / 8;
     if (c % 8 == 0 && gs % 8 == 0 && cpr <= 256 && 256 % cpr == 0 && ((uintptr_t)g & 15) == 0)
-        hipLaunchKernelGGL(k_colsum8, dim3((unsigned)blocks), dim3(256), 0, s, g, gs, rows, c, db);
+        hipLaunchKernelGGL(k_colsum8, dim3((unsigned)blocks), dim3(256), 0, s, g, gs, rows, c, db, parts);
     else
-        hipLaunchKernelGGL(k_colsum, dim3((unsigned)blocks), dim3(256), 0, s, g, gs, rows, c, db);
+        hipLaunchKernelGGL(k_colsum, dim3((unsigned)blocks), dim3(256), 0, s, g, gs, rows, c, db, parts);
+    if (parts) reduce_parts(s, parts, (int)blocks, c, c, c, db, c);
+}
+
+static int64_t head_blocks(int64_t P)
+{
+    int64_t blocks = (P + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    return blocks < 1 ? 1 : blocks;
+}
+
+static int64_t head_wgrad_blocks(int64_t P)
+{
+    int64_t wb = (P + 1023) / 1024;
+    if (wb > 512) wb = 512;
+    return wb < 1 ? 1 : wb;
+}
+
+size_t unet_head_parts(int64_t P, int c)
+{
+    return (size_t)std::max(head_blocks(P) * 3, head_wgrad_blocks(P) * 2 * c);
 }
 
 void unet_head_loss(hipStream_t s, const uint16_t* d0, int c, int64_t P, const float* w, const float* b,
                     const float* target, const float* mask, const int* count, float* out, float* loss, float* gw,
-                    float* gb, uint16_t* gd0, float2* gout)
+                    float* gb, uint16_t* gd0, float2* gout, float* parts)
 {
-    int64_t blocks = (P + 255) / 256;
-    if (blocks > 2048) blocks = 2048;
+    const int64_t blocks = head_blocks(P);
     const int cpr = c / 8;
     const bool v8 = c % 8 == 0 && ((uintptr_t)d0 & 15) == 0 && (!gd0 || ((uintptr_t)gd0 & 15) == 0);
+    float* hp = target ? parts : nullptr;
     if (v8)
-        hipLaunchKernelGGL(k_head<true>, dim3((unsigned)(blocks < 1 ? 1 : blocks)), dim3(256), 0, s, d0, c, P, w, b,
-                           target, mask, count, out, loss, gout, gb, gd0);
+        hipLaunchKernelGGL(k_head<true>, dim3((unsigned)blocks), dim3(256), 0, s, d0, c, P, w, b, target, mask, count,
+                           out, loss, gout, gb, gd0, hp);
     else
-        hipLaunchKernelGGL(k_head<false>, dim3((unsigned)(blocks < 1 ? 1 : blocks)), dim3(256), 0, s, d0, c, P, w,
-                           b, target, mask, count, out, loss, gout, gb, gd0);
+        hipLaunchKernelGGL(k_head<false>, dim3((unsigned)blocks), dim3(256), 0, s, d0, c, P, w, b, target, mask,
+                           count, out, loss, gout, gb, gd0, hp);
     if (!target) return;
-    int64_t wb = (P + 1023) / 1024;
-    if (wb > 512) wb = 512;
+    if (hp) {  // the loss, then the two bias gradients
+        reduce_parts(s, hp, (int)blocks, 3, 1, 1, loss, 1);
+        reduce_parts(s, hp + 1, (int)blocks, 3, 2, 2, gb, 2);
+    }
+    const int64_t wb = head_wgrad_blocks(P);
     if (v8 && 2 * c <= 256 && 256 % cpr == 0)
-        hipLaunchKernelGGL(k_head_wgrad8, dim3((unsigned)(wb < 1 ? 1 : wb)), dim3(256), 0, s, d0, c, P, gout, gw);
+        hipLaunchKernelGGL(k_head_wgrad8, dim3((unsigned)wb), dim3(256), 0, s, d0, c, P, gout, gw, parts);
     else
-        hipLaunchKernelGGL(k_head_wgrad, dim3((unsigned)(wb < 1 ? 1 : wb)), dim3(256), 0, s, d0, c, P, gout, gw);
+        hipLaunchKernelGGL(k_head_wgrad, dim3((unsigned)wb), dim3(256), 0, s, d0, c, P, gout, gw, parts);
+    if (parts) reduce_parts(s, parts, (int)wb, 2 * c, 2 * c, 2 * c, gw, 2 * c);
 }
 
 void unet_add_f32(hipStream_t s, float* dst, int ds, const float* src, int ss, int64_t rows, int c)

@@ -49,6 +49,7 @@ int round32(int k) { return (k + 31) / 32 * 32; }
 struct mem_unet {
     int base = 0, S = 0, maxB = 0, n_cu = 256;
     int gemm_shape = -1;  // forced tile shape of the nt products (-1: automatic)
+    float* parts = nullptr;  // per-workgroup partial sums of the gradient reductions
     int64_t n_params = 0;
     bool broken = false;
     ULayer L[NLAY];
@@ -132,7 +133,7 @@ void free_unet(mem_unet* u)
         (void)hipFree(Y.gbuf);
     }
     void* bufs[] = {u->w, u->g, u->am, u->av, u->x, u->e3, u->out, u->col, u->g1, u->g2, u->gch, u->tmpf,
-                    u->loss, u->xin};
+                    u->loss, u->xin, u->parts};
     for (void* b : bufs) (void)hipFree(b);
     for (int l = 0; l < 4; l++) {
         (void)hipFree(u->a[l]);
@@ -239,15 +240,15 @@ void conv_bwd(mem_unet* u, hipStream_t s, int i, const uint16_t* x, int xs, int 
     if (implicit(Y.ci, xs)) {
         const ConvSrc cs{x, xs, Y.ci, S};
         u->prof.timed(s, "gemm_wgrad", [&] {
-            unet_gemm_tn(s, gy, Y.co, nullptr, 0, &cs, P, Y.co, 9 * Y.ci, Y.gbuf, Y.kf, u->n_cu);
+            unet_gemm_tn(s, gy, Y.co, nullptr, 0, &cs, P, Y.co, 9 * Y.ci, Y.gbuf, Y.kf, u->n_cu, u->parts);
         });
     } else {
         u->prof.timed(s, "im2col", [&] { unet_im2col3(s, x, xs, 0, B, S, Y.ci, u->col, Y.kf); });
         u->prof.timed(s, "gemm_wgrad", [&] {
-            unet_gemm_tn(s, gy, Y.co, u->col, Y.kf, nullptr, P, Y.co, Y.kf, Y.gbuf, Y.kf, u->n_cu);
+            unet_gemm_tn(s, gy, Y.co, u->col, Y.kf, nullptr, P, Y.co, Y.kf, Y.gbuf, Y.kf, u->n_cu, u->parts);
         });
     }
-    u->prof.timed(s, "colsum", [&] { unet_colsum(s, gy, Y.co, P, Y.co, bias(u, u->g, i)); });
+    u->prof.timed(s, "colsum", [&] { unet_colsum(s, gy, Y.co, P, Y.co, bias(u, u->g, i), u->parts); });
     if (!dx) return;
     Epilogue ep{nullptr, 0, nullptr, 0, 0, dx, Y.ci, 0, 0};
     if (implicit(Y.co, Y.co)) {
@@ -283,7 +284,7 @@ void backward(mem_unet* u, hipStream_t s, int B, const float* target, const floa
     u->prof.timed(s, "head", [&] {
         unet_mask_count(s, mask, P0, count);
         unet_head_loss(s, u->d[0], b, P0, u->w + u->L[H].off, bias(u, u->w, H), target, mask, count, u->out,
-                       u->loss, u->g + u->L[H].off, bias(u, u->g, H), u->g1, (float2*)u->tmpf);
+                       u->loss, u->g + u->L[H].off, bias(u, u->g, H), u->g1, (float2*)u->tmpf, u->parts);
     });
     uint16_t* gd = u->g1;  // gradient of d_l's pre-activation
     uint16_t* gt = u->g2;
@@ -306,9 +307,9 @@ void backward(mem_unet* u, hipStream_t s, int B, const float* target, const floa
         u->prof.timed(s, "eltwise", [&] { unet_gather_children(s, gt, c, 0, B, u->S >> (l + 1), c, u->gch); });
         const uint16_t* below = (l == 2) ? u->e3 : u->d[l + 1];
         u->prof.timed(s, "gemm_wgrad", [&] {
-            unet_gemm_tn(s, u->gch, 4 * c, below, U.ci, nullptr, (int)Pb, 4 * c, U.ci, U.gbuf, U.ci, u->n_cu);
+            unet_gemm_tn(s, u->gch, 4 * c, below, U.ci, nullptr, (int)Pb, 4 * c, U.ci, U.gbuf, U.ci, u->n_cu, u->parts);
         });
-        u->prof.timed(s, "colsum", [&] { unet_colsum(s, gt, c, P, c, bias(u, u->g, k)); });
+        u->prof.timed(s, "colsum", [&] { unet_colsum(s, gt, c, P, c, bias(u, u->g, k), u->parts); });
         Epilogue ep{nullptr, 0, nullptr, 0, 0, u->tmpf, U.ci, 0, 0};
         u->prof.timed(s, "gemm_dgrad", [&] {
             unet_gemm_nt(s, EPI_F32, u->gch, 4 * c, nullptr, U.wd, 4 * c, (int)Pb, U.ci, 4 * c, ep, u->n_cu, u->gemm_shape);
@@ -425,6 +426,24 @@ mem_status mem_unet_create(int32_t base, int32_t max_batch, int32_t size, uint64
         col = std::max(col, (size_t)P_at(u, B, l) * std::max(kf, kd));
     }
     const int64_t P0 = P_at(u, B, 0);
+    // partial sums of the weight and bias gradients and the loss: the largest
+    // of any reduction of a batch of at most B windows (fewer windows split
+    // into fewer or equal parts)
+    size_t parts = unet_head_parts(P0, base);
+    for (int i = 0; i < NLAY; i++) {
+        const ULayer& Y = u->L[i];
+        if (Y.kind == 0) {
+            const int l = (i < 8) ? i / 2 : 2 - (i - 8) / 3;
+            const int P = (int)P_at(u, B, l);
+            parts = std::max({parts, unet_tn_parts(P, Y.co, 9 * Y.ci, u->n_cu), unet_tn_parts(P, Y.co, Y.kf, u->n_cu),
+                              unet_colsum_parts(P, Y.co)});
+        } else if (Y.kind == 2) {
+            const int l = 2 - (i - 8) / 3;  // output level of the transposed convolution
+            parts = std::max({parts, unet_tn_parts((int)P_at(u, B, l + 1), 4 * Y.co, Y.ci, u->n_cu),
+                              unet_colsum_parts(P_at(u, B, l), Y.co)});
+        }
+    }
+    ok = ok && ualloc(&u->parts, parts);
     ok = ok && ualloc(&u->x, P0 * 3) && ualloc(&u->out, P0 * 2) && ualloc(&u->col, col) &&
          ualloc(&u->g1, P0 * 2 * base) && ualloc(&u->g2, P0 * 2 * base) && ualloc(&u->gch, P0 * base) &&
          ualloc(&u->tmpf, P0 * 2 * base) && ualloc(&u->e3, P_at(u, B, 3) * 8 * base) && ualloc(&u->xin, P0 * 3);
@@ -521,7 +540,7 @@ mem_status mem_unet_forward(mem_unet* u, const float* x, int32_t batch, float* o
     const int H = NLAY - 1;
     u->prof.timed(s, "head", [&] {
         unet_head_loss(s, u->d[0], u->base, P0, u->w + u->L[H].off, bias(u, u->w, H), nullptr, nullptr, nullptr, out,
-                       nullptr, nullptr, nullptr, nullptr, nullptr);
+                       nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     });
     return finish(u, "mem_unet_forward");
 }

@@ -63,8 +63,12 @@ void unet_gemm_nt(hipStream_t s, int epi, const uint16_t* A, int64_t lda, const 
                   int64_t ldb, int M, int N, int K, const Epilogue& ep, int n_cu,
                   int force_shape = -1);
 // B (P x N, row stride ldb) is dense, or the unfolded input `conv` (N = 9 ci).
+// parts (device, unet_tn_parts floats, or NULL for FP32 atomics): each
+// pixel slice's partial product, summed into C in a fixed order afterwards,
+// so the gradient does not depend on the order in which workgroups ran.
 void unet_gemm_tn(hipStream_t s, const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, const ConvSrc* conv,
-                  int P, int M, int N, float* C, int64_t ldc, int n_cu);
+                  int P, int M, int N, float* C, int64_t ldc, int n_cu, float* parts);
+size_t unet_tn_parts(int P, int M, int N, int n_cu);
 // Up to kFillMax float buffers cleared by one launch.
 constexpr int kFillMax = 32;
 struct FillList {
@@ -113,7 +117,9 @@ void unet_maxpool_bwd(hipStream_t s, const float* dy, const uint8_t* arg, int B,
 void unet_add_f32(hipStream_t s, float* dst, int ds, const float* src, int ss, int64_t rows, int c);
 void unet_relu_mask_add(hipStream_t s, const float* acc, int as, const float* add, int ads, const uint16_t* y,
                         int ys, int64_t rows, int c, uint16_t* g, int gs);
-void unet_colsum(hipStream_t s, const uint16_t* g, int gs, int64_t rows, int c, float* db);
+// parts: as for unet_gemm_tn (unet_colsum_parts floats, or NULL).
+void unet_colsum(hipStream_t s, const uint16_t* g, int gs, int64_t rows, int c, float* db, float* parts);
+size_t unet_colsum_parts(int64_t rows, int c);
 // Adds the number of mask entries > 0 among P to *count (device int).
 void unet_mask_count(hipStream_t s, const float* mask, int64_t P, int* count);
 // Head output (out may be NULL) and, with a target, loss and head / d0
@@ -121,7 +127,8 @@ void unet_mask_count(hipStream_t s, const float* mask, int64_t P, int* count);
 // gout (P float2) is scratch.
 void unet_head_loss(hipStream_t s, const uint16_t* d0, int c, int64_t P, const float* w, const float* b,
                     const float* target, const float* mask, const int* count, float* out, float* loss, float* gw,
-                    float* gb, uint16_t* gd0, float2* gout);
+                    float* gb, uint16_t* gd0, float2* gout, float* parts);
+size_t unet_head_parts(int64_t P, int c);
 void unet_cast_bf16(hipStream_t s, const float* x, int64_t n, uint16_t* y);
 void unet_fill(hipStream_t s, float* x, int64_t n, float v);
 void unet_adam(hipStream_t s, float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
