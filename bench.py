@@ -489,23 +489,33 @@ def run_precision(args):
                   mem.Layer(20, mem.MEM_DIRICHLET, 1.0)]
         return mem.Map(mem.MapParams(W, H, res, layers=layers, **p))
 
-    def frame(m, f, feat):
+    def frame(m, f, feat, features_only=False):
         x, y, _ = f["pose"]
         m.move(x, y)
         for c in f["clouds"]:
             m.input_pointcloud(c["xyz"], c["T"])
+        if features_only:
+            m.input_image_poses([([(ft, c["K_feat"], [(9, 0, ft.shape[-1])])], c["T"])
+                                 for c, ft in zip(f["cameras"], feat)])
+            return
         m.input_image_poses([([(c["rgb"], c["K"], [(8, 0, 3)]), (ft, c["K_feat"], [(9, 0, ft.shape[-1])]),
                                (c["classes"], c["K"], [(10, 0, 20)])], c["T"]) for c, ft in zip(f["cameras"], feat)])
 
-    def timed_run(storage, C, keep=False):
-        feat = [[c["features"][..., :C].contiguous() for c in f["cameras"]] for f in dframes]
-        mp = make(storage, C)  # per-launch events on a twin map, outside the timed frames
+    def profiled(storage, C, feat, features_only):
+        """Per-launch event times on a twin map, outside the timed frames."""
+        mp = make(storage, C)
         mp.profile_enable(True)
         mp.profile_read()
         for k, f in enumerate(dframes):
-            frame(mp, f, feat[k])
+            frame(mp, f, feat[k], features_only)
         kern = mp.profile_read()
         mp.close()
+        return kern
+
+    def timed_run(storage, C, keep=False):
+        feat = [[c["features"][..., :C].contiguous() for c in f["cameras"]] for f in dframes]
+        kern = profiled(storage, C, feat, False)
+        kfeat = profiled(storage, C, feat, True)  # the feature images' gathers alone
         m = make(storage, C)
         m.reset_stats()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
@@ -518,6 +528,7 @@ def run_precision(args):
         st = m.stats()
         out = dict(ms_per_frame=round(float(lat.mean()), 4), points_per_s=round(st["points_accepted"] / (lat.sum() * 1e-3 * n / (n - 1)), 1),
                    gather_fuse_ms_per_frame=round(kern.get("gather_fuse", (0, 0.0))[1] / n, 4),
+                   feature_gather_ms_per_frame=round(kfeat.get("gather_fuse", (0, 0.0))[1] / n, 4),
                    state_mb=round(W * H * C * {mem.MEM_F32: 4, mem.MEM_BF16: 2, mem.MEM_FP8_E4M3: 1}[storage] / 2**20, 1))
         if keep:
             return out, m

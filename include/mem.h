@@ -395,6 +395,13 @@ mem_status mem_debug_point_cells(const mem_map* map, const float* xyz, int64_t n
 mem_status mem_debug_cell_pixels(const mem_map* map, int32_t h, int32_t w,
                                  const float K[4], const float T_map_cam[12],
                                  int32_t* out, void* stream);
+/* Tests: channels per lane of this map's image gathers.  1 forces one
+ * channel per lane; 0 (the default) lets each gather take 16 bytes of layer
+ * storage per lane (4 FP32, 8 BF16 or 16 FP8 E4M3 channels) where the
+ * layer's channels, the image's strides and the addresses allow it.  Every
+ * element goes through the same arithmetic either way, so both give the
+ * same layer bits.  Errors: MEM_E_ARG (other values). */
+mem_status mem_debug_gather_width(mem_map* map, int32_t width);
 
 /* Statistics (synchronises `stream`). */
 mem_status mem_get_stats(mem_map* map, mem_stats* out, void* stream);

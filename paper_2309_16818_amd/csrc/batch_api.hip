@@ -42,6 +42,7 @@ struct BLayer {
         d.val = (char*)val + off * C * esz;
         d.var = var ? var + off : nullptr;
         d.scale = scale;
+        d.rscale = scale_block_rd(scale, C);
         d.C = C;
         d.rule = rule;
         d.storage = storage;
@@ -587,8 +588,9 @@ mem_status mem_batch_create(const mem_batch_params* p, void* stream, mem_batch**
         std::vector<float> sc(d.channels, 1.0f / 448.0f);
         if (d.ch_scale)
             for (int q = 0; q < d.channels; q++) sc[q] = d.ch_scale[q] / 448.0f;
-        if (hipMalloc((void**)&b->layers[l].scale, sizeof(float) * d.channels) != hipSuccess ||
-            hipMemcpy(b->layers[l].scale, sc.data(), sizeof(float) * d.channels, hipMemcpyHostToDevice) != hipSuccess) {
+        const std::vector<float> blk = scale_block_host(sc);
+        if (hipMalloc((void**)&b->layers[l].scale, sizeof(float) * blk.size()) != hipSuccess ||
+            hipMemcpy(b->layers[l].scale, blk.data(), sizeof(float) * blk.size(), hipMemcpyHostToDevice) != hipSuccess) {
             free_batch(b);
             return api_fail(MEM_E_NOMEM, "layer scales");
         }

@@ -29,37 +29,64 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f)
     return (uint16_t)(u >> 16);
 }
 
+// E4M3 <-> binary32 with the GPU's conversion instructions, which use the
+// OCP E4M3 ("fn") format on gfx950.  Decoding is exact.  The encoder rounds
+// to nearest even; saturation comes from clamping to +-448 first (the
+// instruction itself would turn overflow into NaN), and since the clamp
+// turns a NaN into a number, NaN inputs are mapped to 0x7F separately.
+// Equal, for all 2^32 binary32 inputs, to the textbook steps (split off the
+// binade, scale the significand to [8, 16), round the integer, carry into
+// the exponent, saturate), and to them for all 256 codes when decoding.
 __device__ __forceinline__ float e4m3_to_f32(uint8_t c)
 {
-    uint32_t e = (c >> 3) & 0xfu, m = c & 7u;
-    if (e == 0xfu && m == 7u) return __uint_as_float(0x7fc00000u);
-    float v = (e == 0) ? (float)m * 0.001953125f  // m * 2^-9
-                       : ldexpf(1.0f + (float)m * 0.125f, (int)e - 7);
-    return (c & 0x80u) ? -v : v;
+    return __builtin_amdgcn_cvt_f32_fp8((int)c, 0);
 }
+
+// Byte k (0..3, a compile-time constant after unrolling) of a word of four
+// codes.
+__device__ __forceinline__ float e4m3_word_to_f32(uint32_t w, int k)
+{
+    switch (k) {
+    case 0: return __builtin_amdgcn_cvt_f32_fp8((int)w, 0);
+    case 1: return __builtin_amdgcn_cvt_f32_fp8((int)w, 1);
+    case 2: return __builtin_amdgcn_cvt_f32_fp8((int)w, 2);
+    default: return __builtin_amdgcn_cvt_f32_fp8((int)w, 3);
+    }
+}
+
+__device__ __forceinline__ float e4m3_clamp(float x) { return fminf(fmaxf(x, -448.0f), 448.0f); }
 
 __device__ __forceinline__ uint8_t f32_to_e4m3(float x)
 {
-    if (isnan(x)) return 0x7f;
-    uint8_t sign = signbit(x) ? 0x80 : 0x00;
-    float a = fabsf(x);
-    if (a >= 448.0f) return sign | 0x7e;
-    if (a < 0.015625f) {  // below 2^-6: quantum 2^-9; m == 8 is the smallest normal
-        int m = (int)rintf(a * 512.0f);
-        return sign | (uint8_t)m;
+    const float y = e4m3_clamp(x);
+    const uint32_t c = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(y, y, 0, false) & 0xffu;
+    return x != x ? (uint8_t)0x7f : (uint8_t)c;
+}
+
+// Four values into one word of codes (value k in byte k).
+__device__ __forceinline__ uint32_t f32x4_to_e4m3(float x0, float x1, float x2, float x3)
+{
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(e4m3_clamp(x0), e4m3_clamp(x1), 0, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(e4m3_clamp(x2), e4m3_clamp(x3), w, true);
+    uint32_t u = (uint32_t)w;
+    if ((x0 != x0) | (x1 != x1) | (x2 != x2) | (x3 != x3)) {
+        const float x[4] = {x0, x1, x2, x3};
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            if (x[k] != x[k]) u = (u & ~(0xffu << (8 * k))) | (0x7fu << (8 * k));
     }
-    int E;
-    frexpf(a, &E);     // a = f 2^E, f in [0.5, 1)
-    int e = E - 1;     // a in [2^e, 2^(e+1)), e in [-6, 8]
-    float q = ldexpf(a, 3 - e);  // a / 2^(e-3), in [8, 16)
-    int m = (int)rintf(q);
-    if (m == 16) {
-        m = 8;
-        e += 1;
-    }
-    int code = ((e + 7) << 3) | (m - 8);
-    if (code > 0x7e) code = 0x7e;
-    return sign | (uint8_t)code;
+    return u;
+}
+
+// v / s for a scale s given as rd = 1 / s rounded to binary64: the binary64
+// product is within 2^-52 (relative) of v / s, and v / s (both binary32)
+// lies more than 2^-49 from every binary32 rounding midpoint, so rounding
+// the product to binary32 gives the correctly rounded quotient (checked for
+// all 2^32 v on several scales); one multiply instead of a correctly
+// rounded divide.
+__device__ __forceinline__ float div_rd(float v, double rd)
+{
+    return (float)((double)v * rd);
 }
 
 // Element access by storage type.

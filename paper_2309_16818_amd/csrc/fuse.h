@@ -35,20 +35,31 @@ __device__ __forceinline__ GaussCoef gauss_coef(float sf2, float s0, int N)
     return g;
 }
 
-// New value of one channel.  a = mean of this update's observations
-// (Eq. (1)), sum = their sum, old = stored value.
+// New value of one channel under rule R (known at compile time).  a = mean
+// of this update's observations (Eq. (1)), sum = their sum, old = stored
+// value.
+template <int R>
+__device__ __forceinline__ float fuse_rule(float param, float old, float a, float sum, const GaussCoef& g)
+{
+    if constexpr (R == MEM_LATEST)
+        return a;
+    else if constexpr (R == MEM_EXPAVG)  // Eq. (2); the first observation sets the value
+        return isnan(old) ? a : param * a + (1.0f - param) * old;
+    else if constexpr (R == MEM_GAUSS)  // Eq. (6)
+        return g.first ? a : g.w0 * old + g.wa * a;
+    else  // MEM_DIRICHLET, Eq. (12)
+        return old + sum;
+}
+
+// The same with the rule chosen at run time.
 __device__ __forceinline__ float fuse_value(int rule, float param, float old, float a, float sum,
                                             const GaussCoef& g)
 {
     switch (rule) {
-    case MEM_LATEST:
-        return a;
-    case MEM_EXPAVG:  // Eq. (2); the first observation sets the value
-        return isnan(old) ? a : param * a + (1.0f - param) * old;
-    case MEM_GAUSS:  // Eq. (6)
-        return g.first ? a : g.w0 * old + g.wa * a;
-    default:  // MEM_DIRICHLET, Eq. (12)
-        return old + sum;
+    case MEM_LATEST: return fuse_rule<MEM_LATEST>(param, old, a, sum, g);
+    case MEM_EXPAVG: return fuse_rule<MEM_EXPAVG>(param, old, a, sum, g);
+    case MEM_GAUSS: return fuse_rule<MEM_GAUSS>(param, old, a, sum, g);
+    default: return fuse_rule<MEM_DIRICHLET>(param, old, a, sum, g);
     }
 }
 

@@ -467,7 +467,7 @@ __global__ __launch_bounds__(kBatchWG) void k_b_project(BatchDev d, int tile)
     block_stats(d.stats, ids, vals);
 }
 
-template <int IMG, int S>
+template <int IMG, int S, int V>
 __global__ __launch_bounds__(kBatchWG) void k_b_gather(BatchDev d, int queue,
                                                        const void* __restrict__ images, int cam_c,
                                                        int cam_w, int ch_first, LayerDev L,
@@ -491,6 +491,9 @@ __global__ __launch_bounds__(kBatchWG) void k_b_gather(BatchDev d, int queue,
         for (int p = I.a + wave * ppw + sub; p < end; p += nw * ppw) {
             if (topk > 0)  // top-k class input: one lane per pair (lpp_log2 = 0)
                 gather_topk<IMG>(pairs[p], img, (int64_t)cam_w * cam_c, cam_c, 1, cam_w, ch_first, L, topk);
+            else if constexpr (V > 1)
+                gather_pair_vec<IMG, S, V>(pairs[p], img, (int64_t)cam_w * cam_c, cam_c, cam_w, ch_first, L, q0,
+                                           LPP);
             else
                 gather_pair<IMG, S>(pairs[p], img, (int64_t)cam_w * cam_c, cam_c, 1, cam_w, ch_first, L,
                                     q0, LPP);
@@ -562,23 +565,36 @@ void launch_batch_step(hipStream_t s, const BatchDev& d, const BatchLaunch& bl, 
     stage("b_project", [&] { hipLaunchKernelGGL(k_b_project, dim3(bl.grid), dim3(kBatchWG), 0, s, d, bl.tile); });
     for (int b = 0; b < n_ib; b++) {
         const LayerDev& Lb = L[ib[b].layer - MEM_LAYER_USER0];
+        // every map's image starts at a multiple of cam_c channels, so the
+        // first map's alignment holds for all
+        const int V = ib[b].topk ? 1
+                                 : gather_vec_width(Lb.storage, Lb.C, img_dtype, images, (int64_t)cam_w * cam_c,
+                                                    cam_c, 1, ib[b].ch_first, Lb);
         int lpp_log2 = 0;
-        while (ib[b].topk == 0 && (1 << lpp_log2) < Lb.C && lpp_log2 < 6) lpp_log2++;
+        while (ib[b].topk == 0 && (1 << lpp_log2) * V < Lb.C && lpp_log2 < 6) lpp_log2++;
         // one gather pass per binding, each with its own queue (4 + b)
-#define MEM_BG(IMG, S)                                                                            \
-    hipLaunchKernelGGL((k_b_gather<IMG, S>), dim3(bl.grid), dim3(kBatchWG), 0, s, d, 4 + b, images, \
+#define MEM_BG(IMG, S, VV)                                                                            \
+    hipLaunchKernelGGL((k_b_gather<IMG, S, VV>), dim3(bl.grid), dim3(kBatchWG), 0, s, d, 4 + b, images, \
                        cam_c, cam_w, ib[b].ch_first, Lb, lpp_log2, ib[b].topk)
+#define MEM_BG2(IMG, S, VV) \
+    do {                    \
+        if (V > 1)          \
+            MEM_BG(IMG, S, VV); \
+        else                \
+            MEM_BG(IMG, S, 1);  \
+    } while (0)
         stage("b_gather", [&] {
             if (img_dtype == MEM_U8) {
-                if (Lb.storage == MEM_BF16) MEM_BG(MEM_U8, MEM_BF16);
-                else if (Lb.storage == MEM_FP8_E4M3) MEM_BG(MEM_U8, MEM_FP8_E4M3);
-                else MEM_BG(MEM_U8, MEM_F32);
+                if (Lb.storage == MEM_BF16) MEM_BG2(MEM_U8, MEM_BF16, 8);
+                else if (Lb.storage == MEM_FP8_E4M3) MEM_BG2(MEM_U8, MEM_FP8_E4M3, 8);
+                else MEM_BG2(MEM_U8, MEM_F32, 4);
             } else {
-                if (Lb.storage == MEM_BF16) MEM_BG(MEM_F32, MEM_BF16);
-                else if (Lb.storage == MEM_FP8_E4M3) MEM_BG(MEM_F32, MEM_FP8_E4M3);
-                else MEM_BG(MEM_F32, MEM_F32);
+                if (Lb.storage == MEM_BF16) MEM_BG2(MEM_F32, MEM_BF16, 8);
+                else if (Lb.storage == MEM_FP8_E4M3) MEM_BG2(MEM_F32, MEM_FP8_E4M3, 8);
+                else MEM_BG2(MEM_F32, MEM_F32, 4);
             }
         });
+#undef MEM_BG2
 #undef MEM_BG
     }
 }

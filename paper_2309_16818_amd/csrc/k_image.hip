@@ -11,10 +11,12 @@
 //                  codes are overwritten with -1 in place (no atomics).
 //   k_gather_fuse  grid-stride over the listed cells; for those visible in
 //                  the image a group of lanes (a power of two >= the layer's
-//                  channels, at most 64) reads the pixel's channels and
+//                  channels / V, at most 64) reads the pixel's channels and
 //                  read-modify-writes the cell's channel-contiguous layer row
-//                  with the layer's rule; a top-k class input takes one lane
-//                  per cell, which adds each listed probability to its class.
+//                  with the layer's rule, V channels per lane (4 FP32, 8 BF16
+//                  or FP8 where rows and pixels are aligned for it, else 1);
+//                  a top-k class input takes one lane per cell, which adds
+//                  each listed probability to its class.
 #include "update.h"
 
 namespace memk {
@@ -163,7 +165,7 @@ __global__ __launch_bounds__(256) void k_occlude(Grid g, CameraSet cs, const flo
     block_stats(stats, ids, vals);
 }
 
-template <int IMG, int S>
+template <int IMG, int S, int V>
 __global__ __launch_bounds__(256) void k_gather_fuse(const int4* __restrict__ vlist,
                                                      const int* __restrict__ vcode,
                                                      const int* __restrict__ count,
@@ -179,14 +181,19 @@ __global__ __launch_bounds__(256) void k_gather_fuse(const int4* __restrict__ vl
     const int ppw = 64 >> lpp_log2;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    // one entry per lane group at a time; its cell is read with its code
     for (int64_t pbase = wave * ppw; pbase < N; pbase += nwaves * ppw) {
         const int64_t p = pbase + sub;
-        const int code = p < N ? vcode[p] : -1;
+        const bool in = p < N;
+        const int code = in ? vcode[p] : -1;
+        const int st = in ? vlist[p].x : 0;
         if (code < 0) continue;
         if (topk > 0)  // one lane per pair (lpp_log2 = 0)
-            gather_topk<IMG>(make_int2(vlist[p].x, code), img, s0, s1, s2, w, ch_first, L, topk);
+            gather_topk<IMG>(make_int2(st, code), img, s0, s1, s2, w, ch_first, L, topk);
+        else if constexpr (V > 1)
+            gather_pair_vec<IMG, S, V>(make_int2(st, code), img, s0, s1, w, ch_first, L, q0, LPP);
         else
-            gather_pair<IMG, S>(make_int2(vlist[p].x, code), img, s0, s1, s2, w, ch_first, L, q0, LPP);
+            gather_pair<IMG, S>(make_int2(st, code), img, s0, s1, s2, w, ch_first, L, q0, LPP);
     }
 }
 
@@ -220,28 +227,37 @@ void launch_project(hipStream_t s, const Grid& g, const CameraSet& cs, const flo
 
 void launch_gather_fuse(hipStream_t s, const int4* vlist, const int* vcode, const int* count, int max_pairs,
                         const void* img, int img_dtype, int64_t s0, int64_t s1, int64_t s2, int w,
-                        int ch_first, const LayerDev& L, int topk, LaunchEv ev)
+                        int ch_first, const LayerDev& L, int topk, bool one_channel, LaunchEv ev)
 {
+    const int V = topk || one_channel ? 1 : gather_vec_width(L.storage, L.C, img_dtype, img, s0, s1, s2, ch_first, L);
     int lpp_log2 = 0;
-    while (topk == 0 && (1 << lpp_log2) < L.C && lpp_log2 < 6) lpp_log2++;
-    int ppw = 64 >> lpp_log2;
+    while (topk == 0 && (1 << lpp_log2) * V < L.C && lpp_log2 < 6) lpp_log2++;
+    const int ppw = 64 >> lpp_log2;
     int64_t waves = ((int64_t)max_pairs + ppw - 1) / ppw;
     int64_t blocks = (waves + 3) / 4;
     if (blocks > 2048) blocks = 2048;
     if (blocks < 1) blocks = 1;
     dim3 gr((unsigned)blocks), bl(256);
-#define MEM_GF(IMG, S) \
-    hipExtLaunchKernelGGL((k_gather_fuse<IMG, S>), gr, bl, 0, s, ev.start, ev.stop, 0, vlist, vcode, count, img, s0, \
-                          s1, s2, w, ch_first, L, lpp_log2, topk)
+#define MEM_GF(IMG, S, V) \
+    hipExtLaunchKernelGGL((k_gather_fuse<IMG, S, V>), gr, bl, 0, s, ev.start, ev.stop, 0, vlist, vcode, count, img, \
+                          s0, s1, s2, w, ch_first, L, lpp_log2, topk)
+#define MEM_GF2(IMG, S, VV) \
+    do {                    \
+        if (V > 1)          \
+            MEM_GF(IMG, S, VV); \
+        else                \
+            MEM_GF(IMG, S, 1);  \
+    } while (0)
     if (img_dtype == MEM_U8) {
-        if (L.storage == MEM_BF16) MEM_GF(MEM_U8, MEM_BF16);
-        else if (L.storage == MEM_FP8_E4M3) MEM_GF(MEM_U8, MEM_FP8_E4M3);
-        else MEM_GF(MEM_U8, MEM_F32);
+        if (L.storage == MEM_BF16) MEM_GF2(MEM_U8, MEM_BF16, 8);
+        else if (L.storage == MEM_FP8_E4M3) MEM_GF2(MEM_U8, MEM_FP8_E4M3, 8);
+        else MEM_GF2(MEM_U8, MEM_F32, 4);
     } else {
-        if (L.storage == MEM_BF16) MEM_GF(MEM_F32, MEM_BF16);
-        else if (L.storage == MEM_FP8_E4M3) MEM_GF(MEM_F32, MEM_FP8_E4M3);
-        else MEM_GF(MEM_F32, MEM_F32);
+        if (L.storage == MEM_BF16) MEM_GF2(MEM_F32, MEM_BF16, 8);
+        else if (L.storage == MEM_FP8_E4M3) MEM_GF2(MEM_F32, MEM_FP8_E4M3, 8);
+        else MEM_GF2(MEM_F32, MEM_F32, 4);
     }
+#undef MEM_GF2
 #undef MEM_GF
 }
 

@@ -62,6 +62,7 @@ struct Layer {
         d.val = val;
         d.var = var;
         d.scale = scale;
+        d.rscale = scale_block_rd(scale, C);
         d.C = C;
         d.rule = rule;
         d.storage = storage;
@@ -83,6 +84,7 @@ struct mem_map {
     float res = 0, inv_res = 0;
     float c0 = 0, c1 = 0, max_range = 0, mr2 = 0, clear_margin = 0, min_depth = 0;
     int clear_min = 0;
+    int gather_v1 = 0;  // image gathers forced to one channel per lane (tests)
     int cx = 0, cy = 0, rx = 0, ry = 0;
     int device = 0;
     int max_lds = 65536;  // LDS bytes a workgroup may use on this device
@@ -389,14 +391,15 @@ mem_status mem_create(const mem_params* p, void* stream, mem_map** out)
         Layer& M = m->layers.back();
         if ((st = dev_alloc(m, (uint8_t**)&M.val, HW * d.channels * elem_size(d.storage))) ||
             (d.rule == MEM_GAUSS && (st = dev_alloc(m, &M.var, HW))) ||
-            (st = dev_alloc(m, &M.scale, d.channels))) {
+            (st = dev_alloc(m, &M.scale, scale_block_floats(d.channels)))) {
             free_map(m);
             return st;
         }
         std::vector<float> sc(d.channels, 1.0f / 448.0f);
         if (d.ch_scale)
             for (int q = 0; q < d.channels; q++) sc[q] = d.ch_scale[q] / 448.0f;
-        hipError_t e = hipMemcpy(M.scale, sc.data(), sizeof(float) * d.channels, hipMemcpyHostToDevice);
+        const std::vector<float> blk = scale_block_host(sc);
+        hipError_t e = hipMemcpy(M.scale, blk.data(), sizeof(float) * blk.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             free_map(m);
             return fail(MEM_E_HIP, "hipMemcpy: %s", hipGetErrorString(e));
@@ -800,7 +803,7 @@ static mem_status input_poses(mem_map* m, const mem_image* images, const int32_t
                     launch_gather_fuse(s, vlist + (int64_t)p * cap,
                                        vcode + ((int64_t)p * kMaxImages + k) * cap, vc + p, cap, im.data,
                                        im.dtype, im.strides[0], im.strides[1], im.strides[2], im.w,
-                                       im.bind[b].ch_first, d, im.bind[b].topk, ev);
+                                       im.bind[b].ch_first, d, im.bind[b].topk, m->gather_v1 != 0, ev);
                 });
             }
         }
@@ -911,6 +914,14 @@ mem_status mem_debug_point_cells(const mem_map* mc, const float* xyz, int64_t n,
     memcpy(P.m, T, sizeof(P.m));
     launch_point_cells((hipStream_t)stream, m->grid(), xyz, n, P, m->mr2, out);
     return check_launch(m, "mem_debug_point_cells");
+}
+
+mem_status mem_debug_gather_width(mem_map* m, int32_t width)
+{
+    if (mem_status st = usable(m)) return st;
+    if (width != 0 && width != 1) return fail(MEM_E_ARG, "width must be 0 (automatic) or 1");
+    m->gather_v1 = width;
+    return MEM_OK;
 }
 
 mem_status mem_debug_cell_pixels(const mem_map* mc, int32_t h, int32_t w, const float K[4],

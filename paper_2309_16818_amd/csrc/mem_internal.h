@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -76,10 +77,27 @@ struct Pose {
 };
 
 // One user layer as the kernels see it.
+// A layer's FP8 scales in one device block: C binary32 scales, then, from
+// a 16-byte aligned offset, their reciprocals rounded to binary64.
+inline size_t scale_block_floats(int C) { return (size_t)((C + 3) & ~3) + 2 * (size_t)C; }
+inline double* scale_block_rd(float* scale, int C) { return scale ? (double*)(scale + ((C + 3) & ~3)) : nullptr; }
+inline std::vector<float> scale_block_host(const std::vector<float>& sc)
+{
+    const int C = (int)sc.size();
+    std::vector<float> blk(scale_block_floats(C), 0.0f);
+    for (int q = 0; q < C; q++) {
+        blk[q] = sc[q];
+        const double rd = 1.0 / (double)sc[q];
+        memcpy(&blk[((C + 3) & ~3) + 2 * q], &rd, sizeof rd);
+    }
+    return blk;
+}
+
 struct LayerDev {
     void* val;
     float* var;
-    float* scale;  // FP8: per-channel amax/448 (device)
+    float* scale;   // FP8: per-channel amax/448 (device)
+    double* rscale; // FP8: 1 / scale rounded to binary64 (device)
     int C, rule, storage;
     float param;
 };
@@ -226,7 +244,8 @@ void launch_project(hipStream_t s, const Grid& g, const CameraSet& cs, const flo
 // probabilities (Dirichlet layers), fused by one lane per visible pair.
 void launch_gather_fuse(hipStream_t s, const int4* vlist, const int* vcode, const int* count, int max_pairs,
                         const void* img, int img_dtype, int64_t s0, int64_t s1, int64_t s2, int w,
-                        int ch_first, const LayerDev& L, int topk = 0, LaunchEv ev = {});
+                        int ch_first, const LayerDev& L, int topk = 0, bool one_channel = false,
+                        LaunchEv ev = {});
 
 // ---- batches of maps ----
 

@@ -622,6 +622,174 @@ __device__ __forceinline__ void gather_pair(int2 pr, const void* __restrict__ im
     if (L.rule == MEM_GAUSS && q0 == 0) L.var[st] = gc.var;
 }
 
+// NW consecutive 32-bit words at p (aligned to min(4 NW, 16) bytes) in
+// loads / stores of up to 16 bytes.
+template <int NW>
+__device__ __forceinline__ void load_words(const void* __restrict__ p, uint32_t (&w)[NW])
+{
+    if constexpr (NW % 4 == 0) {
+#pragma unroll
+        for (int i = 0; i < NW / 4; i++) {
+            const uint4 v = ((const uint4*)p)[i];
+            w[4 * i] = v.x;
+            w[4 * i + 1] = v.y;
+            w[4 * i + 2] = v.z;
+            w[4 * i + 3] = v.w;
+        }
+    } else if constexpr (NW == 2) {
+        const uint2 v = *(const uint2*)p;
+        w[0] = v.x;
+        w[1] = v.y;
+    } else {
+        static_assert(NW == 1, "1, 2 or a multiple of 4 words");
+        w[0] = *(const uint32_t*)p;
+    }
+}
+
+template <int NW>
+__device__ __forceinline__ void store_words(void* __restrict__ p, const uint32_t (&w)[NW])
+{
+    if constexpr (NW % 4 == 0) {
+#pragma unroll
+        for (int i = 0; i < NW / 4; i++)
+            ((uint4*)p)[i] = make_uint4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]);
+    } else if constexpr (NW == 2) {
+        *(uint2*)p = make_uint2(w[0], w[1]);
+    } else {
+        static_assert(NW == 1, "1, 2 or a multiple of 4 words");
+        *(uint32_t*)p = w[0];
+    }
+}
+
+// Element k of a little-endian run of B-byte elements held in words.
+template <int B, int NW>
+__device__ __forceinline__ uint32_t word_elem(const uint32_t (&w)[NW], int k)
+{
+    if constexpr (B == 4) return w[k];
+    constexpr int per = 4 / B;
+    return (w[k / per] >> (8 * B * (k % per))) & ((1u << (8 * B)) - 1u);
+}
+
+// The FP8 scales of the V channels from q and their binary64 reciprocals;
+// 1 for other storage types.
+template <int S, int V>
+struct ChanScales {
+    float sc[V];
+    double rd[V];
+    __device__ __forceinline__ void load(const LayerDev& L, int q)
+    {
+#pragma unroll
+        for (int k = 0; k < V; k++) {
+            sc[k] = 1.0f;
+            rd[k] = 1.0;
+        }
+        if constexpr (S == MEM_FP8_E4M3) {
+            uint32_t ws[V], wd[2 * V];
+            load_words(L.scale + q, ws);
+            load_words(L.rscale + q, wd);
+#pragma unroll
+            for (int k = 0; k < V; k++) {
+                sc[k] = __uint_as_float(ws[k]);
+                rd[k] = __hiloint2double((int)wd[2 * k + 1], (int)wd[2 * k]);
+            }
+        }
+    }
+};
+
+// gather_pair with V consecutive channels per lane: one pass moves 4V image
+// bytes and V storage elements per lane in word loads and stores (16 bytes
+// of FP32 or BF16 storage, 8 of FP8), so a BF16 row takes half FP32's
+// memory instructions.  The per-element arithmetic is gather_pair's, so
+// both give the same bits.  Needs C % V == 0 and the pixel's channels
+// contiguous (s2 == 1) at an offset that is a multiple of V.
+template <int IMG, int S, int V, int R>
+__device__ __forceinline__ void gather_pair_vec_rule(int2 pr, const void* __restrict__ img, int64_t s0,
+                                                     int64_t s1, int w, int ch_first, const LayerDev& L,
+                                                     int q0, int LPP)
+{
+    constexpr int B = S == MEM_F32 ? 4 : S == MEM_BF16 ? 2 : 1;
+    constexpr int NW = V * B / 4;                  // storage words per lane and pass
+    constexpr int NI = IMG == MEM_U8 ? V / 4 : V;  // image words
+    static_assert(V * B % 4 == 0 && (IMG != MEM_U8 || V % 4 == 0), "whole words");
+    const int st = pr.x;
+    const int row = pr.y / w, col = pr.y - (pr.y / w) * w;
+    const int64_t pix = (int64_t)row * s0 + (int64_t)col * s1 + ch_first;
+    GaussCoef gc{0.0f, 1.0f, 0.0f, true};
+    if constexpr (R == MEM_GAUSS) gc = gauss_coef(L.param, L.var[st], 1);
+    const int C = L.C;
+    for (int q = q0 * V; q < C; q += LPP * V) {
+        ChanScales<S, V> cs;  // (keeping a lane's scales across passes measured no faster)
+        cs.load(L, q);
+        uint32_t wi[NI], wv[NW], out[NW];
+        static_assert(S != MEM_FP8_E4M3 || V % 4 == 0, "whole words of FP8 codes");
+        load_words(IMG == MEM_U8 ? (const void*)((const uint8_t*)img + pix + q)
+                                 : (const void*)((const float*)img + pix + q), wi);
+        uint8_t* row_p = (uint8_t*)L.val + ((int64_t)st * C + q) * B;
+        load_words(row_p, wv);
+        float nv[V];
+#pragma unroll
+        for (int k = 0; k < V; k++) {
+            const uint32_t pe = word_elem<IMG == MEM_U8 ? 1 : 4>(wi, k);
+            const float a = IMG == MEM_U8 ? (float)pe / 255.0f : __uint_as_float(pe);
+            float old;
+            if constexpr (S == MEM_F32) old = __uint_as_float(wv[k]);
+            else if constexpr (S == MEM_BF16) old = bf16_to_f32((uint16_t)word_elem<2>(wv, k));
+            else old = e4m3_word_to_f32(wv[k / 4], k % 4) * cs.sc[k];
+            nv[k] = fuse_rule<R>(L.param, old, a, a, gc);
+        }
+#pragma unroll
+        for (int i = 0; i < NW; i++) {
+            if constexpr (S == MEM_F32) out[i] = __float_as_uint(nv[i]);
+            else if constexpr (S == MEM_BF16)
+                out[i] = (uint32_t)f32_to_bf16(nv[2 * i]) | ((uint32_t)f32_to_bf16(nv[2 * i + 1]) << 16);
+            else  // v / sc[k] through the binary64 reciprocal: the correctly rounded quotient
+                out[i] = f32x4_to_e4m3(div_rd(nv[4 * i], cs.rd[4 * i]), div_rd(nv[4 * i + 1], cs.rd[4 * i + 1]),
+                                       div_rd(nv[4 * i + 2], cs.rd[4 * i + 2]),
+                                       div_rd(nv[4 * i + 3], cs.rd[4 * i + 3]));
+        }
+        store_words(row_p, out);
+    }
+    if (R == MEM_GAUSS && q0 == 0) L.var[st] = gc.var;
+}
+
+// The rule as a compile-time constant, so that no element pays for the choice.
+template <int IMG, int S, int V>
+__device__ __forceinline__ void gather_pair_vec(int2 pr, const void* __restrict__ img, int64_t s0,
+                                                int64_t s1, int w, int ch_first, const LayerDev& L,
+                                                int q0, int LPP)
+{
+    switch (L.rule) {
+    case MEM_LATEST:
+        gather_pair_vec_rule<IMG, S, V, MEM_LATEST>(pr, img, s0, s1, w, ch_first, L, q0, LPP);
+        break;
+    case MEM_EXPAVG:
+        gather_pair_vec_rule<IMG, S, V, MEM_EXPAVG>(pr, img, s0, s1, w, ch_first, L, q0, LPP);
+        break;
+    case MEM_GAUSS:
+        gather_pair_vec_rule<IMG, S, V, MEM_GAUSS>(pr, img, s0, s1, w, ch_first, L, q0, LPP);
+        break;
+    default:
+        gather_pair_vec_rule<IMG, S, V, MEM_DIRICHLET>(pr, img, s0, s1, w, ch_first, L, q0, LPP);
+        break;
+    }
+}
+
+// Channels per lane of the vector gather for a layer of storage S (4 FP32,
+// 8 BF16, 8 FP8: 16 bytes of storage, 8 for FP8, whose 8 scales and
+// reciprocals a lane keeps in registers) where the layer's rows, the
+// pixel's channels and every address allow it, else 1.
+inline int gather_vec_width(int storage, int C, int img_dtype, const void* img, int64_t s0, int64_t s1,
+                            int64_t s2, int ch_first, const LayerDev& L)
+{
+    const int V = storage == MEM_F32 ? 4 : 8;
+    const int ib = img_dtype == MEM_U8 ? 1 : 4;
+    const int64_t ia = V * ib < 16 ? V * ib : 16;  // alignment of the image loads
+    const bool ok = C % V == 0 && s2 == 1 && s0 % V == 0 && s1 % V == 0 && ch_first % V == 0 &&
+                    (uintptr_t)img % ia == 0 && (uintptr_t)L.val % 16 == 0 &&
+                    (storage != MEM_FP8_E4M3 || ((uintptr_t)L.scale % 16 == 0 && L.rscale));
+    return ok ? V : 1;
+}
+
 // An empty cell: no height, never observed layers, Dirichlet alpha_0.
 __device__ __forceinline__ void reset_cell(int st, float* __restrict__ h, float* __restrict__ v,
                                            int* __restrict__ cnt, int* __restrict__ clr,

@@ -31,7 +31,7 @@ STAT_FIELDS = ("points_in", "points_accepted", "dropped_nonfinite", "dropped_ran
 SYMBOLS = ("mem_create", "mem_destroy", "mem_move", "mem_input_pointcloud", "mem_input_image",
            "mem_input_images", "mem_get_layer", "mem_set_layer", "mem_normals", "mem_set_drift_compensation", "mem_get_drift",
            "mem_set_overlap_clearance", "mem_pca", "mem_pca_noalloc", "mem_input_image_poses",
-           "mem_get_center", "mem_debug_point_cells",
+           "mem_get_center", "mem_debug_point_cells", "mem_debug_gather_width",
            "mem_debug_cell_pixels", "mem_get_stats", "mem_reset_stats", "mem_profile_enable",
            "mem_profile_read", "mem_last_error")
 
@@ -104,6 +104,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "mem_get_center": [P, C.POINTER(I32), C.POINTER(I32)],
         "mem_debug_point_cells": [P, P, I64, P, P, P],
         "mem_debug_cell_pixels": [P, I32, I32, P, P, P, P],
+        "mem_debug_gather_width": [P, I32],
         "mem_get_stats": [P, C.POINTER(mem_stats), P],
         "mem_reset_stats": [P, P],
         "mem_profile_enable": [P, I32],
@@ -408,6 +409,11 @@ class Map:
 
     def reset_stats(self, stream=None):
         _check(load().mem_reset_stats(self._h, _stream(stream)))
+
+    def debug_gather_width(self, width: int):
+        """Tests: 1 forces one channel per lane in this map's image gathers,
+        0 restores the automatic width."""
+        _check(load().mem_debug_gather_width(self._h, width))
 
     def profile_enable(self, on: bool = True):
         _check(load().mem_profile_enable(self._h, 1 if on else 0))

@@ -55,6 +55,21 @@ def test_fp8_storage_matches_torch_e4m3_with_saturation_and_scales():
     assert np.array_equal(got, want)
 
 
+def test_fp8_encoder_on_a_sweep_of_all_binary32_patterns():
+    """Every 64th binary32 bit pattern (both signs, every binade, zeros,
+    subnormals, infinities, NaNs and the rounding ties of every binade),
+    stored with scale 1 (amax 448), reads back as torch's E4M3 conversion
+    after saturation at +-448."""
+    u = np.arange(0, 2 ** 32, 64, dtype=np.uint64).astype(np.uint32)
+    v = u.view(np.float32).reshape(8192, 8192, 1)
+    want = torch.from_numpy(np.clip(v, -448.0, 448.0)).to(torch.float8_e4m3fn).float().numpy()
+    g = mem.Map(mem.MapParams(8192, 8192, 0.1, layers=[mem.Layer(1, mem.MEM_LATEST, 0.0, mem.MEM_FP8_E4M3, [448.0])]))
+    g.set_layer(8, 0, torch.from_numpy(v))
+    got = g.get_layer(8).cpu().numpy().reshape(8192, 8192, 1)
+    g.close()
+    assert np.array_equal(got, want, equal_nan=True)
+
+
 @pytest.mark.parametrize("C", [48, 200, 384])
 @pytest.mark.parametrize("storage,rel", [(mem.MEM_F32, 1e-4), (mem.MEM_BF16, 2.0 ** -8), (mem.MEM_FP8_E4M3, 2.0 ** -3)])
 def test_feature_fusion_within_one_storage_rounding(storage, rel, C):
@@ -90,3 +105,45 @@ def test_feature_fusion_within_one_storage_rounding(storage, rel, C):
             err = np.abs(a[ok] - b[ok])
             bound = rel * np.abs(b[ok]) + (1e-6 if storage != mem.MEM_FP8_E4M3 else 2.0 ** -9 / 448 + 1e-6)
             assert (err <= bound).all(), (storage, lid, float((err - bound).max()))
+
+
+@pytest.mark.parametrize("C", [20, 64, 200, 384])
+@pytest.mark.parametrize("storage", [mem.MEM_F32, mem.MEM_BF16, mem.MEM_FP8_E4M3])
+def test_vector_gather_writes_the_one_channel_bits(storage, C):
+    """The image gather with 16 bytes of storage per lane (4 FP32, 8 BF16 or
+    16 FP8 channels) and the gather with one channel per lane put every
+    element through the same arithmetic, so two maps fed the same images,
+    one of them forced to one channel, hold the same layer bits: Gaussian and
+    averaging rules, float and u8 images, widths that take the vector path
+    (multiples of its channels per lane) and widths that fall back to one
+    channel (20 channels in BF16 / FP8, 200 in FP8)."""
+    rng = np.random.default_rng(40 + C + 7 * storage)
+    scales = list(rng.uniform(0.2, 3.0, C).astype(np.float32)) if storage == mem.MEM_FP8_E4M3 else None
+    maps = []
+    for width in (0, 1):
+        m = mem.Map(mem.MapParams(48, 48, 0.05, layers=[mem.Layer(C, mem.MEM_GAUSS, 1.0, storage, scales),
+                                                         mem.Layer(C, mem.MEM_EXPAVG, 0.5, storage, scales)]))
+        m.debug_gather_width(width)
+        maps.append(m)
+    h = np.where(rng.uniform(size=(48, 48)) < 0.9, rng.normal(0, 0.05, (48, 48)), np.nan).astype(np.float32)
+    for m in maps:
+        m.set_layer(mem.MEM_LAYER_ELEVATION, 0, torch.tensor(h))
+        m.set_layer(mem.MEM_LAYER_VARIANCE, 0, torch.full((48, 48), 1e-3))
+    K = (60.0, 60.0, 47.5, 35.5)
+    for it in range(4):
+        if it % 2:
+            img = torch.tensor(rng.integers(0, 256, (72, 96, 2 * C)), dtype=torch.uint8, device="cuda")
+        else:
+            img = to_dev(synth.feature_image(rng, 72, 96, 2 * C) * 3.0)
+        R = synth.camera_rotation(rng.uniform(0, 2 * np.pi), math.radians(40)).astype(np.float32)
+        T = np.zeros((3, 4), np.float32)
+        T[:, :3] = R
+        T[:, 3] = (rng.uniform(-0.2, 0.2), rng.uniform(-0.2, 0.2), 0.8)
+        for m in maps:
+            m.input_image(img, K, T, bind=[(8, 0, C), (9, C, C)])
+    for lid, view in ((8, 0), (8, 1), (9, 0)):
+        a, b = gpu_layer(maps[0], lid, view), gpu_layer(maps[1], lid, view)
+        assert np.isfinite(a).any()
+        assert np.array_equal(a, b, equal_nan=True), (lid, view)
+    for m in maps:
+        m.close()
