@@ -1084,11 +1084,11 @@ def main():
     if dom:
         kd = kernels[dom]
         b = kernel_bytes(dom, st, kd["launches"])
-        if b and dom not in ("clear_march", "project"):
+        if b and dom not in WALK_VALU_PER_CELL:
             ach = b / (kd["total_ms"] * 1e-3) / 1e9
             roof = dict(kernel=dom, bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                         frac=round(ach / HBM_PEAK_GBS, 4), traffic=None)
-        else:  # ray walks: VALU bound; achieved in ray cells per second
+        elif dom in WALK_VALU_PER_CELL:  # ray walks: VALU bound; achieved in ray cells per second
             cells = st["ray_steps"] if dom == "clear_march" else st["occl_cells"]
             rate = cells / (kd["total_ms"] * 1e-3) / 1e9
             peak = VALU_LANE_OPS / WALK_VALU_PER_CELL[dom] / 1e9

@@ -357,6 +357,21 @@ __device__ __forceinline__ float box_max(const Grid& g, const float* __restrict_
     return m;
 }
 
+// box_max for a box at most two blocks wide in each direction (a run of at
+// most 1 << shift cells of a line): its four corner blocks' maxima, loaded
+// together (the same block twice where the box is one block wide).
+__device__ __forceinline__ float box_max2(const Grid& g, const float* __restrict__ t, int tw, int shift, int x0,
+                                          int y0, int x1, int y1)
+{
+    const int xa = max(min(x0, x1), 0), xb = min(max(x0, x1), g.W - 1);
+    const int ya = max(min(y0, y1), 0), yb = min(max(y0, y1), g.H - 1);
+    if (xa > xb || ya > yb) return -__builtin_inff();
+    const int tx0 = xa >> shift, tx1 = xb >> shift, ty0 = ya >> shift, ty1 = yb >> shift;
+    const float a = t[ty0 * tw + tx0], b = t[ty0 * tw + tx1];
+    const float c = t[ty1 * tw + tx0], d = t[ty1 * tw + tx1];
+    return fmaxf(fmaxf(a, b), fmaxf(c, d));
+}
+
 // Ray height above the cell the walk stands on.
 __device__ __forceinline__ float walk_height(const Grid& g, const Ray& r, const LineWalk& L)
 {
@@ -371,7 +386,8 @@ __device__ __forceinline__ float walk_height(const Grid& g, const Ray& r, const 
 // loading a cell: skip(hmax, z_first, z_last) must return true only if no
 // cell with height <= hmax and ray height >= min(z_first, z_last) can make
 // visit act.  Runs are 64 cells (checked against blocks of 64) and then 8
-// cells (blocks of 8); the remaining cells are visited as walk_range does.
+// cells (blocks of 8; a run spans at most two blocks each way, whose maxima
+// are loaded together); the remaining cells are visited as walk_range does.
 // `r` must be at the start cell.  Returns the number of cells loaded.
 template <class Skip, class Visit>
 __device__ __forceinline__ int walk_range_skip(const Grid& g, const Ray& r, const float* __restrict__ h,
@@ -390,7 +406,7 @@ __device__ __forceinline__ int walk_range_skip(const Grid& g, const Ray& r, cons
             A.step();
             LineWalk E = r.L;
             E.jump_from_start(i + 63);
-            const float hm = box_max(g, tm.t64, tm.tw64, 6, A.x, A.y, E.x, E.y);
+            const float hm = box_max2(g, tm.t64, tm.tw64, 6, A.x, A.y, E.x, E.y);
             if (skip(hm, walk_height(g, r, A), walk_height(g, r, E))) {
                 L = E;
                 i += 64;
@@ -412,7 +428,7 @@ __device__ __forceinline__ int walk_range_skip(const Grid& g, const Ray& r, cons
             LineWalk A = L, B = L;  // first and last cell of the run
             A.x = px[0];
             A.y = py[0];
-            if (skip(box_max(g, tm.t8, tm.tw8, 3, px[0], py[0], L.x, L.y), walk_height(g, r, A),
+            if (skip(box_max2(g, tm.t8, tm.tw8, 3, px[0], py[0], L.x, L.y), walk_height(g, r, A),
                      walk_height(g, r, B)))
                 continue;
         }

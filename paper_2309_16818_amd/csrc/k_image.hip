@@ -27,7 +27,8 @@ constexpr int kTile = 16;
 
 // Pass 1 of the two-pass projection: frustum test and pixel of every image
 // per cell; cells inside at least one view are appended to vlist
-// (st, ix, iy, intermediate cells of the occlusion line) and their codes to
+// (st, ix | iy << 16, intermediate cells of the occlusion line, the cell's
+// height as bits; sides are at most 16384 cells) and their codes to
 // vcode[k * cap + position].
 __global__ __launch_bounds__(256) void k_view(Grid g, CameraSet cs, const float* __restrict__ h,
                                               int4* __restrict__ vlist, int* __restrict__ vcode, int cap,
@@ -76,7 +77,7 @@ __global__ __launch_bounds__(256) void k_view(Grid g, CameraSet cs, const float*
     __syncthreads();
     if (any) {
         const int pos = s_base + woff + __popcll(mask & ((1ull << lane) - 1ull));
-        vlist[pos] = make_int4(st, ix, iy, steps > 0 ? steps : 0);
+        vlist[pos] = make_int4(st, ix | (iy << 16), steps > 0 ? steps : 0, __float_as_int(h[st]));
 #pragma unroll
         for (int k = 0; k < kMaxImages; k++)
             if (k < cam.n) vcode[(int64_t)k * cap + pos] = code[k];
@@ -121,17 +122,18 @@ __global__ __launch_bounds__(256) void k_occlude(Grid g, CameraSet cs, const flo
         int4 e = make_int4(0, 0, 0, 0);
         if (pos < N) {
             e = vlist[pos];
-            const int total = e.w;  // intermediate cells of the line
+            const int total = e.z;  // intermediate cells of the line
             const int run = (total + kOccLanes - 1) / kOccLanes;
             const int first = 1 + sub * run;
             const int cnt = min(run, total - sub * run);
             if (cnt > 0) {
-                const float hj = h[e.x];
-                const float xc = ((float)(g.ox + e.y) + 0.5f) * g.res;
-                const float yc = ((float)(g.oy + e.z) + 0.5f) * g.res;
+                const int ix = e.y & 0xffff, iy = e.y >> 16;
+                const float hj = __int_as_float(e.w);
+                const float xc = ((float)(g.ox + ix) + 0.5f) * g.res;
+                const float yc = ((float)(g.oy + iy) + 0.5f) * g.res;
                 int ax, ay;
                 lattice_cell(g, T[3], T[7], ax, ay);
-                const Ray ray(g, ax, ay, e.y, e.z, T[3], T[7], T[11], xc, yc, hj);
+                const Ray ray(g, ax, ay, ix, iy, T[3], T[7], T[11], xc, yc, hj);
                 steps += cnt;
                 visited += walk_range_skip(
                     g, ray, h, tm, first, cnt, [&](float hm, float z0, float z1) { return hm < fminf(z0, z1); },
@@ -157,7 +159,7 @@ __global__ __launch_bounds__(256) void k_occlude(Grid g, CameraSet cs, const flo
                 else
                     n_vis++;
             }
-            if (dbg) dbg[e.z * g.W + e.y] = (c0 >= 0 && occluded) ? -3 : c0;
+            if (dbg) dbg[(e.y >> 16) * g.W + (e.y & 0xffff)] = (c0 >= 0 && occluded) ? -3 : c0;
         }
     }
     const int ids[3] = {ST_VISIBLE, ST_OCCL_CELLS, ST_OCCL_STEPS};
@@ -219,7 +221,7 @@ void launch_project(hipStream_t s, const Grid& g, const CameraSet& cs, const flo
     hipExtLaunchKernelGGL(k_view, grid, dim3(kTile, kTile), 0, s, ev.start, nullptr, 0, g, cs, h, vlist, vcode, cap,
                           vcount, vcount_next, d, stats);
     int64_t blocks = ((int64_t)cap * kOccLanes + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
+    if (blocks > 1024) blocks = 1024;  // per pose; 256..4096 measured, 1024 fastest
     if (blocks < 1) blocks = 1;
     hipExtLaunchKernelGGL(k_occlude, dim3((unsigned)blocks, (unsigned)cs.n), dim3(256), 0, s, nullptr, ev.stop, 0, g,
                           cs, h, tm, vlist, vcode, cap, vcount, d, stats);

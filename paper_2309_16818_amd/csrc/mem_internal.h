@@ -229,9 +229,10 @@ void launch_zero_int(hipStream_t s, int* p, int n);
 TileMax tile_max_dims(const Grid& g, const float* t8, const float* t64);
 void launch_tile_max(hipStream_t s, const Grid& g, const float* h, float* t8, float* t64);
 // Two passes: k_view lists the cells inside any image's view in vlist
-// (st, ix, iy, intermediate cells of the occlusion line; *vcount entries, at
-// most cap) with their pixel codes in vcode[k * cap + position] (-1 outside
-// image k), k_occlude overwrites the codes of occluded cells with -1.
+// (st, ix | iy << 16, intermediate cells of the occlusion line, height
+// bits; *vcount entries, at most cap) with their pixel codes in
+// vcode[k * cap + position] (-1 outside image k), k_occlude overwrites the
+// codes of occluded cells with -1.
 // Every pose's counter must be zero on entry; k_view clears *vcount_next (a
 // different counter, the next projection's; may be null) so that no
 // separate clear is launched.  dbg is written for a single pose only.

@@ -42,7 +42,7 @@ struct Profiler {
     void drain()
     {
         if (pending.empty()) return;
-        (void)hipEventSynchronize(pending.back().b);
+        for (auto& r : pending) (void)hipEventSynchronize(r.b);  // pairs may be on several streams
         for (auto& r : pending) {
             float ms = 0.0f;
             (void)hipEventElapsedTime(&ms, r.a, r.b);
