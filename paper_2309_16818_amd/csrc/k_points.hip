@@ -246,10 +246,35 @@ __global__ __launch_bounds__(256) void k_tile_max64(const float* __restrict__ t8
 __global__ __launch_bounds__(256) void k_finalize(Grid g, Accum acc, int clear_min,
                                                   float* __restrict__ h, float* __restrict__ v,
                                                   PointBinds pb,
-                                                  unsigned long long* __restrict__ stats)
+                                                  unsigned long long* __restrict__ stats, int clean,
+                                                  int* __restrict__ zero_cnt, int* __restrict__ zero_clr,
+                                                  float* __restrict__ hl, int* __restrict__ march_counts,
+                                                  DriftDev* __restrict__ drift)
 {
     const int st = blockIdx.x * blockDim.x + threadIdx.x;
-    const int r = (st < acc.HW) ? finalize_cell(st, acc, clear_min, h, v, pb) : 0;
+    int r = 0;
+    if (st < acc.HW) {
+        r = finalize_cell(st, acc, clear_min, h, v, pb);
+        if (clean) {
+            if (acc.cnt[st] != 0) {  // only cells with points hold nonzero sums
+                acc.wsum[st] = 0.0f;
+                acc.ssum[st] = 0.0f;
+                for (int q = 0; q < pb.Cb; q++) acc.chsum[(int64_t)q * acc.HW + st] = 0.0f;
+            }
+            if (zero_cnt[st] != 0) zero_cnt[st] = 0;
+            if (zero_clr[st] != 0) zero_clr[st] = 0;
+            if (hl && r != 0) {
+                int ix, iy;
+                logical_index(g, st, ix, iy);
+                hl[iy * g.W + ix] = h[st];
+            }
+        }
+    }
+    if (clean && blockIdx.x == 0) {
+        if (march_counts)
+            for (int k = threadIdx.x; k < kSegLists * kSegSubs; k += blockDim.x) march_counts[k] = 0;
+        if (drift && threadIdx.x == 0) *drift = DriftDev{0.0, 0.0, 0, 0.0f};
+    }
     const int ids[2] = {ST_TOUCHED, ST_CLEARED};
     int vals[2] = {r == 1 ? 1 : 0, r == 2 ? 1 : 0};
     block_stats(stats, ids, vals);
@@ -389,16 +414,15 @@ void launch_tile_max(hipStream_t s, const Grid& g, const float* h, float* t8, fl
                        tm.th64);
 }
 
-void launch_finalize(hipStream_t s, const Grid& g, const int* cnt, const float* wsum,
-                     const float* ssum, const float2* stash, const int* clr, int clear_min,
-                     float* h, float* v, const float* chsum, const PointBinds& pb,
-                     unsigned long long* stats, LaunchEv ev)
+void launch_finalize(hipStream_t s, const Grid& g, int* cnt, float* wsum, float* ssum, const float2* stash,
+                     int* clr, int clear_min, float* h, float* v, float* chsum, const PointBinds& pb,
+                     unsigned long long* stats, bool clean, int* zero_cnt, int* zero_clr, float* hl,
+                     int* march_counts, DriftDev* drift, LaunchEv ev)
 {
     const int HW = g.W * g.H;
-    const Accum acc{const_cast<int*>(cnt), const_cast<float*>(wsum), const_cast<float*>(ssum),
-                    const_cast<float2*>(stash), const_cast<int*>(clr), const_cast<float*>(chsum), HW};
+    const Accum acc{cnt, wsum, ssum, const_cast<float2*>(stash), clr, chsum, HW};
     hipExtLaunchKernelGGL(k_finalize, dim3(blocks_for(HW, 256)), dim3(256), 0, s, ev.start, ev.stop, 0, g, acc,
-                          clear_min, h, v, pb, stats);
+                          clear_min, h, v, pb, stats, clean ? 1 : 0, zero_cnt, zero_clr, hl, march_counts, drift);
 }
 
 void launch_point_cells(hipStream_t s, const Grid& g, const float* xyz, int64_t n, const Pose& T,

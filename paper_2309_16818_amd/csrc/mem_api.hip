@@ -92,8 +92,10 @@ struct mem_map {
 
     float* h = nullptr;
     float* v = nullptr;
-    int* cnt = nullptr;
-    int* clr = nullptr;
+    int* cnt = nullptr;         // per-cloud accumulators: points per cell,
+    int* clr = nullptr;         // clearing votes
+    int* cnt_last = nullptr;    // the last cloud's (read out as hits and clears; swapped with cnt, clr
+    int* clr_last = nullptr;    // at every cloud's end)
     float* wsum = nullptr;
     float* ssum = nullptr;
     float2* stash = nullptr;
@@ -103,6 +105,8 @@ struct mem_map {
     int* vcount = nullptr;      // cells listed in vlist: two counters used by turns (vpar)
     int vpar = 0;               // the counter the next projection uses; its k_view clears the other
     bool tmax_stale = true;     // the heights changed since the block maxima were built
+    bool acc_clean = false;     // accumulators and march counts are zero (the last cloud's finalize cleared them)
+    bool hl_fresh = false;      // hl holds the heights in logical order
     MarchBufs march;            // clearing march: rays and segment lists (grown on first use)
     float* hl = nullptr;        // heights in logical order, for the clearing march
     DriftDev* drift = nullptr;  // the last cloud's drift compensation
@@ -265,6 +269,8 @@ void free_map(mem_map* m)
     (void)hipFree(m->v);
     (void)hipFree(m->cnt);
     (void)hipFree(m->clr);
+    (void)hipFree(m->cnt_last);
+    (void)hipFree(m->clr_last);
     (void)hipFree(m->wsum);
     (void)hipFree(m->ssum);
     (void)hipFree(m->stash);
@@ -370,6 +376,7 @@ mem_status mem_create(const mem_params* p, void* stream, mem_map** out)
     mem_status st = MEM_OK;
     if ((st = dev_alloc(m, &m->h, HW)) || (st = dev_alloc(m, &m->v, HW)) ||
         (st = dev_alloc(m, &m->cnt, HW)) || (st = dev_alloc(m, &m->clr, HW)) ||
+        (st = dev_alloc(m, &m->cnt_last, HW)) || (st = dev_alloc(m, &m->clr_last, HW)) ||
         (st = dev_alloc(m, &m->wsum, HW)) || (st = dev_alloc(m, &m->ssum, HW)) ||
         (st = dev_alloc(m, &m->stash, HW)) ||
         (st = dev_alloc(m, &m->vlist, HW)) || (st = dev_alloc(m, &m->vcode, HW * kMaxImages)) ||
@@ -407,7 +414,8 @@ mem_status mem_create(const mem_params* p, void* stream, mem_map** out)
     }
     Grid g = m->grid();
     auto devs = layer_devs(m);
-    launch_reset_rect(s, g, 0, m->W, 0, m->H, m->h, m->v, m->cnt, m->clr, devs.data(), (int)devs.size());
+    launch_reset_rect(s, g, 0, m->W, 0, m->H, m->h, m->v, m->cnt_last, m->clr_last, devs.data(),
+                      (int)devs.size());
     launch_zero_accum(s, g, m->cnt, m->wsum, m->ssum, m->clr, nullptr, 0, nullptr, nullptr, nullptr, m->drift);
     launch_zero_int(s, (int*)m->stats, 2 * kStats * kStatSlots);
     launch_zero_int(s, m->vcount, 2);
@@ -451,6 +459,7 @@ mem_status mem_move(mem_map* m, float x, float y, void* stream)
     int sx = ncx - m->cx, sy = ncy - m->cy;
     if (sx == 0 && sy == 0) return MEM_OK;
     m->tmax_stale = true;
+    m->hl_fresh = false;
     m->cx = ncx;
     m->cy = ncy;
     auto devs = layer_devs(m);
@@ -458,7 +467,7 @@ mem_status mem_move(mem_map* m, float x, float y, void* stream)
         if (std::abs(sx) >= m->W || std::abs(sy) >= m->H) {
             m->rx = 0;
             m->ry = 0;
-            launch_reset_rect(s, m->grid(), 0, m->W, 0, m->H, m->h, m->v, m->cnt, m->clr, devs.data(),
+            launch_reset_rect(s, m->grid(), 0, m->W, 0, m->H, m->h, m->v, m->cnt_last, m->clr_last, devs.data(),
                               (int)devs.size());
             return;
         }
@@ -466,13 +475,17 @@ mem_status mem_move(mem_map* m, float x, float y, void* stream)
         m->ry = ((m->ry + sy) % m->H + m->H) % m->H;
         Grid g = m->grid();
         if (sx > 0)
-            launch_reset_rect(s, g, m->W - sx, m->W, 0, m->H, m->h, m->v, m->cnt, m->clr, devs.data(), (int)devs.size());
+            launch_reset_rect(s, g, m->W - sx, m->W, 0, m->H, m->h, m->v, m->cnt_last, m->clr_last, devs.data(),
+                              (int)devs.size());
         else if (sx < 0)
-            launch_reset_rect(s, g, 0, -sx, 0, m->H, m->h, m->v, m->cnt, m->clr, devs.data(), (int)devs.size());
+            launch_reset_rect(s, g, 0, -sx, 0, m->H, m->h, m->v, m->cnt_last, m->clr_last, devs.data(),
+                              (int)devs.size());
         if (sy > 0)
-            launch_reset_rect(s, g, 0, m->W, m->H - sy, m->H, m->h, m->v, m->cnt, m->clr, devs.data(), (int)devs.size());
+            launch_reset_rect(s, g, 0, m->W, m->H - sy, m->H, m->h, m->v, m->cnt_last, m->clr_last, devs.data(),
+                              (int)devs.size());
         else if (sy < 0)
-            launch_reset_rect(s, g, 0, m->W, 0, -sy, m->h, m->v, m->cnt, m->clr, devs.data(), (int)devs.size());
+            launch_reset_rect(s, g, 0, m->W, 0, -sy, m->h, m->v, m->cnt_last, m->clr_last, devs.data(),
+                              (int)devs.size());
     });
     return check_launch(m, "mem_move");
 }
@@ -534,6 +547,7 @@ mem_status mem_input_pointcloud(mem_map* m, const float* xyz, int64_t n, const f
         (void)hipFree(m->chsum);
         m->chsum = nullptr;
         m->chsum_planes = 0;
+        m->acc_clean = false;
         if (mem_status st = dev_alloc(m, &m->chsum, (size_t)pb.Cb * m->cells())) return st;
         m->chsum_planes = pb.Cb;
     }
@@ -561,10 +575,17 @@ mem_status mem_input_pointcloud(mem_map* m, const float* xyz, int64_t n, const f
             m->march.part_sub = z.part_sub;
         }
     }
-    timed_ext(m, s, "zero_accum", [&](LaunchEv ev) {
-        launch_zero_accum(s, g, m->cnt, m->wsum, m->ssum, m->clr, m->chsum, pb.Cb, m->march.counts, m->h,
-                          march ? m->hl : nullptr, m->drift, ev);
-    });
+    // The clearing pass runs only where the last cloud's finalize left work:
+    // dirty accumulators, or heights changed since hl was written.
+    if (!m->acc_clean || (march && !m->hl_fresh)) {
+        timed_ext(m, s, "zero_accum", [&](LaunchEv ev) {
+            launch_zero_accum(s, g, m->cnt, m->wsum, m->ssum, m->clr, m->chsum, pb.Cb, m->march.counts, m->h,
+                              march ? m->hl : nullptr, m->drift, ev);
+        });
+        if (march) m->hl_fresh = true;
+    }
+    m->acc_clean = false;
+    const bool drift_runs = m->drift_on && n > 0;
     Pose T;
     memcpy(T.m, T_map_sensor, sizeof(T.m));
     // a cloud that fits one march pass has its rays listed by the ingest
@@ -574,7 +595,7 @@ mem_status mem_input_pointcloud(mem_map* m, const float* xyz, int64_t n, const f
             launch_ingest(s, g, xyz, n, ch, T, m->c0, m->c1, m->mr2, pb, m->cnt, m->wsum, m->ssum, m->stash,
                           m->chsum, fused ? &m->march : nullptr, m->stats, ev);
         });
-    if (m->drift_on && n > 0)
+    if (drift_runs)
         timed(m, s, "drift", [&] {
             launch_drift(s, g, xyz, n, T, m->c0, m->c1, m->mr2, m->h, m->v, m->drift_kappa2, m->drift_min,
                          m->drift, m->drift_part, march ? m->hl : nullptr);
@@ -585,14 +606,24 @@ mem_status mem_input_pointcloud(mem_map* m, const float* xyz, int64_t n, const f
                                m->stats, ev);
         });
     m->tmax_stale = true;
+    // finalize leaves the accumulators and counts zero, keeps hl equal to
+    // the heights (when the march kept it so), and clears the drift record
+    // of a cloud without drift compensation
     timed_ext(m, s, "finalize", [&](LaunchEv ev) {
         launch_finalize(s, g, m->cnt, m->wsum, m->ssum, m->stash, m->clr, m->clear_min, m->h, m->v,
-                        m->chsum, pb, m->stats, ev);
+                        m->chsum, pb, m->stats, true, m->cnt_last, m->clr_last, march ? m->hl : nullptr,
+                        m->march.counts, drift_runs ? nullptr : m->drift, ev);
     });
-    if (m->overlap_on)
+    std::swap(m->cnt, m->cnt_last);
+    std::swap(m->clr, m->clr_last);
+    m->acc_clean = true;
+    if (!march && n > 0) m->hl_fresh = false;
+    if (m->overlap_on) {
         timed(m, s, "overlap_clear", [&] {
             launch_overlap_clear(s, g, T.m[3], T.m[7], T.m[11], m->overlap_xy, m->overlap_z, m->h);
         });
+        m->hl_fresh = false;
+    }
     return check_launch(m, "mem_input_pointcloud");
 }
 
@@ -863,7 +894,8 @@ mem_status mem_get_layer(const mem_map* mc, int32_t layer, int32_t view, float* 
     }
     hipStream_t s = (hipStream_t)stream;
     timed(m, s, "readout", [&] {
-        launch_readout(s, m->grid(), layer, view, m->h, m->v, m->cnt, m->clr, layer >= MEM_LAYER_USER0 ? &d : nullptr, out);
+        launch_readout(s, m->grid(), layer, view, m->h, m->v, m->cnt_last, m->clr_last,
+                       layer >= MEM_LAYER_USER0 ? &d : nullptr, out);
     });
     return check_launch(m, "mem_get_layer");
 }
@@ -896,7 +928,10 @@ mem_status mem_set_layer(mem_map* m, int32_t layer, int32_t view, const float* i
         d = L->dev();
     }
     hipStream_t s = (hipStream_t)stream;
-    if (layer == MEM_LAYER_ELEVATION) m->tmax_stale = true;
+    if (layer == MEM_LAYER_ELEVATION) {
+        m->tmax_stale = true;
+        m->hl_fresh = false;
+    }
     timed(m, s, "setlayer", [&] {
         launch_setlayer(s, m->grid(), layer, view, m->h, m->v, layer >= MEM_LAYER_USER0 ? &d : nullptr, in);
     });

@@ -216,10 +216,19 @@ void launch_drift(hipStream_t s, const Grid& g, const float* xyz, int64_t n, con
                   float c1, float mr2, float* h, const float* v, float kappa2, int min_points,
                   DriftDev* drift, void* part, float* hl);
 size_t drift_part_bytes();
-void launch_finalize(hipStream_t s, const Grid& g, const int* cnt, const float* wsum,
-                     const float* ssum, const float2* stash, const int* clr, int clear_min,
-                     float* h, float* v, const float* chsum, const PointBinds& pb,
-                     unsigned long long* stats, LaunchEv ev = {});
+// The cloud's end: fuses the accumulated sums into the heights and bound
+// layers.  With clean set it also prepares the next cloud, so that it needs
+// no separate clearing pass: the sums of every cell that received points
+// return to zero (cnt and clr stay: they become the last cloud's counts),
+// the count buffers of the cloud before (zero_cnt, zero_clr: the next
+// cloud's accumulators) are zeroed, march_counts too and, if given, the
+// drift record; if hl is given (hl equal to h in logical order before the
+// call), every changed height is written into it.
+void launch_finalize(hipStream_t s, const Grid& g, int* cnt, float* wsum, float* ssum, const float2* stash,
+                     int* clr, int clear_min, float* h, float* v, float* chsum, const PointBinds& pb,
+                     unsigned long long* stats, bool clean = false, int* zero_cnt = nullptr,
+                     int* zero_clr = nullptr, float* hl = nullptr, int* march_counts = nullptr,
+                     DriftDev* drift = nullptr, LaunchEv ev = {});
 void launch_point_cells(hipStream_t s, const Grid& g, const float* xyz, int64_t n, const Pose& T,
                         float mr2, int32_t* out);
 
