@@ -328,17 +328,24 @@ mem_status mem_set_drift_compensation(mem_map* map, int32_t enable, float kappa,
  * cells whose C channels are all observed (finite): the mean m and the
  * population covariance S = (1/N) sum (f - m)(f - m)^T, both accumulated in
  * binary64; e_1..e_3 the eigenvectors of S's three largest eigenvalues in
- * descending order (Jacobi rotations in binary64), each signed so that its
- * largest-magnitude entry (the first of equal ones) is positive.
+ * descending order, each signed so that its largest-magnitude entry (the
+ * first of equal ones) is positive.  Up to 64 channels the eigenpairs come
+ * from Jacobi rotations of the whole matrix in binary64; from 65 to 512
+ * channels from orthogonal iteration with Rayleigh-Ritz on a block of eight
+ * vectors (binary64), stopped when the three leading pairs' residuals fall
+ * below 1e-12 of the largest eigenvalue or after 300 steps: it converges at
+ * the rate of the ninth to the third eigenvalue, so nearly equal leading
+ * eigenvalues leave the components inexact (they are ill defined there).
  * out: device, H x W x 3 float, logical row-major order as mem_get_layer:
  * ((f - m).e_1, (f - m).e_2, (f - m).e_3) per cell, NaN where a channel is
  * unobserved; caller-owned, fully overwritten.  eigenvalues: host, 3 floats
  * or NULL (then the call does not wait for the stream); 0 for components
  * beyond C or when no cell is observed.  Eigenvectors are defined only up
- * to the span of equal eigenvalues.  The first call allocates about 17 MB
- * of scratch for the map.  layer: a LATEST, EXPAVG or GAUSS user layer.
+ * to the span of equal eigenvalues.  The first call allocates scratch for
+ * the map: about 17 MB, or 42 MB plus one byte per cell above 64 channels.
+ * layer: a LATEST, EXPAVG or GAUSS user layer.
  * Errors: MEM_E_ARG (NULL out, no such layer, a DIRICHLET layer),
- * MEM_E_UNSUPPORTED (more than 64 channels), MEM_E_NOMEM. */
+ * MEM_E_UNSUPPORTED (more than 512 channels), MEM_E_NOMEM. */
 mem_status mem_pca(const mem_map* map, int32_t layer, float* out, float eigenvalues[3],
                    void* stream);
 

@@ -116,6 +116,8 @@ struct mem_map {
     int drift_min = 0;
     void* pca_scratch = nullptr; // partial sums of the PCA layer (allocated on first use)
     PcaOut* pca_out = nullptr;
+    char* pcw_scratch = nullptr;   // the same for more than kPcaMaxC channels (first use)
+    PcaWideOut* pcw_out = nullptr;
     bool overlap_on = false;    // overlap clearance after each point cloud
     float overlap_xy = 0.0f, overlap_z = 0.0f;
     int4* vlist = nullptr;      // cells inside a camera's view
@@ -287,6 +289,8 @@ void free_map(mem_map* m)
     (void)hipFree(m->vcount_poses);
     (void)hipFree(m->pca_scratch);
     (void)hipFree(m->pca_out);
+    (void)hipFree(m->pcw_scratch);
+    (void)hipFree(m->pcw_out);
     (void)hipFree(m->vlist);
     (void)hipFree(m->vcode);
     (void)hipFree(m->tmax);
@@ -648,7 +652,32 @@ mem_status mem_pca(const mem_map* mc, int32_t layer, float* out, float eigenvalu
     const Layer* L = nullptr;
     if (mem_status st = resolve_layer(m, layer, &L)) return st;
     if (L->rule == MEM_DIRICHLET) return fail(MEM_E_ARG, "layer %d is a class layer, not a feature layer", layer);
-    if (L->C > kPcaMaxC) return fail(MEM_E_UNSUPPORTED, "PCA of %d channels (at most %d)", L->C, kPcaMaxC);
+    if (L->C > kPcaWideC) return fail(MEM_E_UNSUPPORTED, "PCA of %d channels (at most %d)", L->C, kPcaWideC);
+    hipStream_t s = (hipStream_t)stream;
+    if (L->C > kPcaMaxC) {
+        if (!m->pcw_scratch || !m->pcw_out) {  // both or neither
+            char* p = nullptr;
+            PcaWideOut* o = nullptr;
+            if (mem_status st = dev_alloc(m, &p, pca_wide_scratch_bytes(m->cells()))) return st;
+            if (mem_status st = dev_alloc(m, &o, 1)) {
+                (void)hipFree(p);
+                return st;
+            }
+            (void)hipFree(m->pcw_scratch);
+            (void)hipFree(m->pcw_out);
+            m->pcw_scratch = p;
+            m->pcw_out = o;
+        }
+        timed(m, s, "pca", [&] { launch_pca_wide(s, m->grid(), L->dev(), m->pcw_scratch, m->pcw_out, out, nullptr); });
+        if (mem_status st = check_launch(m, "mem_pca")) return st;
+        if (eigenvalues) {
+            double lam[kPcaK];
+            HIP_TRY(m, hipMemcpyAsync(lam, m->pcw_out->lam, sizeof lam, hipMemcpyDeviceToHost, s));
+            HIP_TRY(m, hipStreamSynchronize(s));
+            for (int k = 0; k < kPcaK; k++) eigenvalues[k] = (float)lam[k];
+        }
+        return MEM_OK;
+    }
     if (!m->pca_scratch || !m->pca_out) {  // both or neither: a failed call leaves neither
         char* p = nullptr;
         PcaOut* o = nullptr;
@@ -662,7 +691,6 @@ mem_status mem_pca(const mem_map* mc, int32_t layer, float* out, float eigenvalu
         m->pca_scratch = p;
         m->pca_out = o;
     }
-    hipStream_t s = (hipStream_t)stream;
     timed(m, s, "pca", [&] { launch_pca(s, m->grid(), L->dev(), m->pca_scratch, m->pca_out, out, nullptr); });
     if (mem_status st = check_launch(m, "mem_pca")) return st;
     if (eigenvalues) {

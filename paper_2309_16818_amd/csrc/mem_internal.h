@@ -353,6 +353,20 @@ struct PcaOut {
     double n;  // cells with every channel observed
 };
 size_t pca_scratch_bytes();
+// The same for kPcaMaxC + 1 .. kPcaWideC channels (k_pca_wide.hip): the
+// covariance in 64 x 64 tiles and the three leading eigenpairs by orthogonal
+// iteration with Rayleigh-Ritz.  `scratch` holds pca_wide_scratch_bytes(cells).
+constexpr int kPcaWideC = 512;
+struct PcaWideOut {
+    double mean[kPcaWideC];
+    double comp[kPcaK][kPcaWideC];
+    double lam[kPcaK];
+    double n;   // cells with every channel observed
+    int iters;  // iterations the eigensolver took
+};
+size_t pca_wide_scratch_bytes(int64_t cells);
+void launch_pca_wide(hipStream_t s, const Grid& g, const LayerDev& L, void* scratch, PcaWideOut* res, float* out,
+                     float* lam_out);
 // lam_out: device, kPcaK floats (the eigenvalues), or NULL.
 void launch_pca(hipStream_t s, const Grid& g, const LayerDev& L, void* scratch, PcaOut* res, float* out,
                 float* lam_out);

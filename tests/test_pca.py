@@ -66,6 +66,21 @@ def test_pca_matches_oracle(C, storage, moves, scale):
     assert n > 0.7 * 70 * 53 and lam[0] > lam[1] > lam[2] > 0
 
 
+@pytest.mark.parametrize("C,storage", [(65, mem.MEM_F32), (200, mem.MEM_BF16), (384, mem.MEM_F32)])
+def test_pca_of_wide_layers_matches_oracle(C, storage):
+    """More than 64 channels (the 384-channel feature layer of the precision
+    workload among them): covariance in 64 x 64 tiles, eigenpairs by
+    orthogonal iteration, the same bars."""
+    rng = np.random.default_rng(300 + C)
+    g, o = make_pair(70, 53, 0.05, layers=[(C, mem.MEM_GAUSS, 1.0, storage)])
+    g.move(0.4, -0.3)
+    o.move(0.4, -0.3)
+    o.set_layer(8, 0, features(rng, 53, 70, C))
+    sync_from_oracle(g, o)
+    n, lam = check(g, o, 8)
+    assert n > 0.7 * 70 * 53 and lam[0] > lam[1] > lam[2] > 0
+
+
 @pytest.mark.parametrize("C", [1, 2, 3])
 def test_pca_with_few_channels(C):
     rng = np.random.default_rng(95 + C)
@@ -93,7 +108,7 @@ def test_pca_on_the_full_grid():
 def test_pca_of_an_unobserved_layer_and_bad_layers():
     g = mem.Map(mem.MapParams(20, 20, 0.1, layers=[mem.Layer(5, mem.MEM_EXPAVG, 0.5),
                                                    mem.Layer(4, mem.MEM_DIRICHLET, 1.0),
-                                                   mem.Layer(65, mem.MEM_LATEST, 0.0)]))
+                                                   mem.Layer(513, mem.MEM_LATEST, 0.0)]))
     out, lam = g.pca(8)
     torch.cuda.synchronize()
     assert torch.isnan(out).all() and lam == [0.0, 0.0, 0.0]
