@@ -57,10 +57,10 @@ WALK_VALU_PER_CELL = {"clear_march": 13, "project": 57}
 # WRITE_SIZE 1048676 KiB: factor 0.99991; profiles/point_path_traffic.md),
 # bytes per launch, valid while the kernel's sources hash to `sha`.
 TRAFFIC = {
-    "clear_march": {"bytes_per_launch": 4468941, "sha": "c0f96fb031f88851"},  # k_ray_walk
-    "ingest": {"bytes_per_launch": 5627057, "sha": "c0f96fb031f88851"},
-    "finalize": {"bytes_per_launch": 1300155, "sha": "c0f96fb031f88851"},
-    "gather_fuse": {"bytes_per_launch": 2383839, "sha": "a151bc3e23968eab"},  # mean over the frame's images
+    "clear_march": {"bytes_per_launch": 4458056, "sha": "4764a1f55d856783"},  # k_ray_walk
+    "ingest": {"bytes_per_launch": 5627987, "sha": "4764a1f55d856783"},
+    "finalize": {"bytes_per_launch": 2214547, "sha": "4764a1f55d856783"},
+    "gather_fuse": {"bytes_per_launch": 2251170, "sha": "7b8ca984d9a524cc"},  # mean over the frame's images
 }
 
 
@@ -1100,7 +1100,7 @@ def main():
         if b and dom not in WALK_VALU_PER_CELL:
             ach = b / (kd["total_ms"] * 1e-3) / 1e9
             roof = dict(kernel=dom, bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=round(ach / HBM_PEAK_GBS, 4), traffic=None)
+                        frac=round(ach / HBM_PEAK_GBS, 4), traffic=traffic_bytes(dom))
         elif dom in WALK_VALU_PER_CELL:  # ray walks: VALU bound; achieved in ray cells per second
             cells = st["ray_steps"] if dom == "clear_march" else st["occl_cells"]
             rate = cells / (kd["total_ms"] * 1e-3) / 1e9

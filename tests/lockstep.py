@@ -21,6 +21,10 @@ import torch
 import oracle as O
 from paper_2309_16818_amd import mem
 
+# Heights: 1e-4 relative with a floor of 1 m, i.e. |dh| <= 1e-4 max(|h|, 1 m):
+# the information-form sums (Eq. (6)-(7)) carry an error relative to the
+# heights' magnitude in metres (terms z / v), not to the fused height, which
+# can cancel to near zero on terrain around z = 0.
 H_TOL = 1e-4
 V_TOL = 1e-4
 F_TOL = 1e-4
