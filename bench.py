@@ -492,8 +492,7 @@ def run_precision(args):
     def frame(m, f, feat, features_only=False):
         x, y, _ = f["pose"]
         m.move(x, y)
-        for c in f["clouds"]:
-            m.input_pointcloud(c["xyz"], c["T"])
+        m.input_pointclouds([(c["xyz"], c["T"]) for c in f["clouds"]])
         if features_only:
             m.input_image_poses([([(ft, c["K_feat"], [(9, 0, ft.shape[-1])])], c["T"])
                                  for c, ft in zip(f["cameras"], feat)])
@@ -625,8 +624,7 @@ def run_layers(args):
     def frame(m, f, L):
         x, y, _ = f["pose"]
         m.move(x, y)
-        for c in f["clouds"]:
-            m.input_pointcloud(c["xyz"], c["T"])
+        m.input_pointclouds([(c["xyz"], c["T"]) for c in f["clouds"]])
         binds = [(8 + l, 0, 3) for l in range(L)]  # up to 8 bindings per image entry
         m.input_image_poses([([(c["rgb"], c["K"], binds[i:i + 8]) for i in range(0, L, 8)], c["T"])
                              for c in f["cameras"]])
@@ -748,8 +746,9 @@ def upload(frames):
 def run_frame(m, f):
     x, y, _ = f["pose"]
     m.move(x, y)
-    for c in f["clouds"]:
-        m.input_pointcloud(c["xyz"], c["T"])
+    # the frame's five clouds in one call (binned by one launch; with drift
+    # compensation or overlap clearance on, one call each)
+    m.input_pointclouds([(c["xyz"], c["T"]) for c in f["clouds"]])
     # the four camera poses of a frame in one call (RGB, features and classes
     # share each pose)
     m.input_image_poses([([(c["rgb"], c["K"], [(8, 0, 3)]), (c["features"], c["K_feat"], [(9, 0, 64)]),

@@ -221,6 +221,37 @@ mem_status mem_input_pointcloud(mem_map* map, const float* xyz, int64_t n,
                                 const mem_binding* bind, int32_t n_bind,
                                 const float T_map_sensor[12], void* stream);
 
+/* One point cloud of a mem_input_pointclouds call (same meaning as the
+ * arguments of mem_input_pointcloud). */
+typedef struct mem_cloud {
+    const float* xyz;        /* device, n x 3 */
+    int64_t n;
+    const float* ch;         /* device, n x c, or NULL if c == 0 */
+    int32_t c;
+    const mem_binding* bind; /* host */
+    int32_t n_bind;
+    float T_map_sensor[12];
+} mem_cloud;
+
+/* Fuses up to 8 point clouds (e.g. the sensors of one robot at one instant,
+ * Sec. III-B) with the result of calling mem_input_pointcloud for each in
+ * order: every cloud's rays test the heights left by the clouds before it.
+ * The association and sums of a cloud do not depend on the heights, so
+ * where no cloud binds channels, every cloud's points fit one clearing pass
+ * (the clouds of a 100 m range hold up to 262144 points, more for shorter
+ * ranges) and neither drift compensation nor overlap clearance is on, the
+ * points of all clouds are binned in one launch into per-cloud sums and ray
+ * lists, and the clouds' clearing walks and height updates then follow in
+ * order; otherwise the clouds run one call each.  The first such call of k
+ * clouds allocates k - 1 further sets of sums and ray lists (32 bytes per
+ * cell and 24 bytes per point of capacity each), kept until destroy.
+ * Height updates add float sums in an order that is not fixed, so results
+ * equal the one-call-each results up to rounding (the decisions and counts
+ * exactly where no sum is at a threshold).  Every cloud is checked before
+ * any work: an invalid call leaves the map untouched. */
+mem_status mem_input_pointclouds(mem_map* map, const mem_cloud* clouds, int32_t n_clouds,
+                                 void* stream);
+
 /* Fuses one multi-modal image (Sec. III-B, second paragraph; Fig. 3).
  *   img      device, element (row, col, k) at img[row*strides[0] +
  *            col*strides[1] + k*strides[2]] (strides in elements, >= 0).

@@ -17,6 +17,12 @@
 //                  or FP8 where rows and pixels are aligned for it, else 1);
 //                  a top-k class input takes one lane per cell, which adds
 //                  each listed probability to its class.
+//   k_gather_multi k_gather_fuse of several images (of one or more poses)
+//                  into different layers in one launch, each image on its own
+//                  range of workgroups.
+#include <algorithm>
+#include <utility>
+
 #include "update.h"
 
 namespace memk {
@@ -91,8 +97,9 @@ __global__ __launch_bounds__(256) void k_view(Grid g, CameraSet cs, const float*
 // Pass 2: kOccLanes lanes per in-view cell split its occlusion line into
 // equal runs of cells; the cell is visible iff no lane finds an occluder.
 // The first lane of the group overwrites the cell's pixel codes with -1
-// when one does (16 lanes: a sweep of 4-64 was fastest there).
-constexpr int kOccLanes = 16;
+// when one does (8 lanes: of 4, 8, 16 and 32, 8 measured fastest with the
+// cell height carried in the list entry).
+constexpr int kOccLanes = 8;
 static_assert(kOccLanes < 64 && 64 % kOccLanes == 0, "groups of lanes within one wave (mask of kOccLanes bits)");
 
 __global__ __launch_bounds__(256) void k_occlude(Grid g, CameraSet cs, const float* __restrict__ h, TileMax tm,
@@ -167,13 +174,15 @@ __global__ __launch_bounds__(256) void k_occlude(Grid g, CameraSet cs, const flo
     block_stats(stats, ids, vals);
 }
 
+// The gather of one job on workgroups blk = 0 .. nblk - 1 (grid-stride over
+// the listed cells, one entry per lane group at a time; its cell is read
+// with its code).
 template <int IMG, int S, int V>
-__global__ __launch_bounds__(256) void k_gather_fuse(const int4* __restrict__ vlist,
-                                                     const int* __restrict__ vcode,
-                                                     const int* __restrict__ count,
-                                                     const void* __restrict__ img, int64_t s0,
-                                                     int64_t s1, int64_t s2, int w, int ch_first,
-                                                     LayerDev L, int lpp_log2, int topk)
+__device__ __forceinline__ void gather_blocks(const int4* __restrict__ vlist, const int* __restrict__ vcode,
+                                              const int* __restrict__ count, const void* __restrict__ img,
+                                              int64_t s0, int64_t s1, int64_t s2, int w, int ch_first,
+                                              const LayerDev& L, int lpp_log2, int topk, int64_t blk,
+                                              int64_t nblk)
 {
     const int N = *count;
     const int lane = threadIdx.x & 63;
@@ -181,9 +190,8 @@ __global__ __launch_bounds__(256) void k_gather_fuse(const int4* __restrict__ vl
     const int sub = lane >> lpp_log2;
     const int q0 = lane & (LPP - 1);
     const int ppw = 64 >> lpp_log2;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    // one entry per lane group at a time; its cell is read with its code
+    const int64_t wave = (blk * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = (nblk * blockDim.x) >> 6;
     for (int64_t pbase = wave * ppw; pbase < N; pbase += nwaves * ppw) {
         const int64_t p = pbase + sub;
         const bool in = p < N;
@@ -197,6 +205,75 @@ __global__ __launch_bounds__(256) void k_gather_fuse(const int4* __restrict__ vl
         else
             gather_pair<IMG, S>(make_int2(st, code), img, s0, s1, s2, w, ch_first, L, q0, LPP);
     }
+}
+
+template <int IMG, int S, int V>
+__global__ __launch_bounds__(256) void k_gather_fuse(const int4* __restrict__ vlist,
+                                                     const int* __restrict__ vcode,
+                                                     const int* __restrict__ count,
+                                                     const void* __restrict__ img, int64_t s0,
+                                                     int64_t s1, int64_t s2, int w, int ch_first,
+                                                     LayerDev L, int lpp_log2, int topk)
+{
+    gather_blocks<IMG, S, V>(vlist, vcode, count, img, s0, s1, s2, w, ch_first, L, lpp_log2, topk, blockIdx.x,
+                             gridDim.x);
+}
+
+// Variants of a gather job: image type (u8, f32) x storage (FP32, BF16, FP8)
+// x channels per lane (the storage's vector width, or one; top-k inputs take
+// one).
+constexpr int kind_of(int img_dtype, int storage, bool vec)
+{
+    return (img_dtype == MEM_U8 ? 0 : 6) + (storage == MEM_F32 ? 0 : storage == MEM_BF16 ? 2 : 4) + (vec ? 0 : 1);
+}
+
+template <int IMG, int S, int V>
+__device__ __forceinline__ void run_job(const GatherJob& J, int64_t blk)
+{
+    gather_blocks<IMG, S, V>(J.vlist, J.vcode, J.count, J.img, J.s0, J.s1, J.s2, J.w, J.ch_first, J.L, J.lpp_log2,
+                             J.topk, blk, J.blocks);
+}
+
+// Bit of storage type S in the set of storage types a fused launch holds.
+constexpr int storage_bit(int storage)
+{
+    return storage == MEM_F32 ? 1 : storage == MEM_BF16 ? 2 : 4;
+}
+
+// Several jobs in one launch: workgroup b runs the job whose range of
+// workgroups holds b.  Jobs write different layers, so the order in which
+// their workgroups run does not matter.  SM is the set of the jobs' storage
+// types (storage_bit), so that a launch carries the registers of those
+// variants only.
+template <int SM>
+__global__ __launch_bounds__(256) void k_gather_multi(GatherJobs js)
+{
+    int j = 0;
+    for (int k = 1; k < js.n; k++)
+        if ((int)blockIdx.x >= js.j[k].block0) j = k;
+    const GatherJob& J = js.j[j];
+    const int64_t blk = (int64_t)blockIdx.x - J.block0;
+#define MEM_JOB(IMG, S, V)                                                                  \
+    case kind_of(IMG, S, V > 1):                                                            \
+        if constexpr ((SM & storage_bit(S)) != 0) run_job<IMG, S, V>(J, blk);               \
+        break;
+    switch (J.kind) {
+        MEM_JOB(MEM_U8, MEM_F32, 4)
+        MEM_JOB(MEM_U8, MEM_F32, 1)
+        MEM_JOB(MEM_U8, MEM_BF16, 8)
+        MEM_JOB(MEM_U8, MEM_BF16, 1)
+        MEM_JOB(MEM_U8, MEM_FP8_E4M3, 8)
+        MEM_JOB(MEM_U8, MEM_FP8_E4M3, 1)
+        MEM_JOB(MEM_F32, MEM_F32, 4)
+        MEM_JOB(MEM_F32, MEM_F32, 1)
+        MEM_JOB(MEM_F32, MEM_BF16, 8)
+        MEM_JOB(MEM_F32, MEM_BF16, 1)
+        MEM_JOB(MEM_F32, MEM_FP8_E4M3, 8)
+        MEM_JOB(MEM_F32, MEM_FP8_E4M3, 1)
+    default:
+        break;
+    }
+#undef MEM_JOB
 }
 
 __global__ void k_zero_int(int* p, int n)
@@ -227,25 +304,77 @@ void launch_project(hipStream_t s, const Grid& g, const CameraSet& cs, const flo
                           cs, h, tm, vlist, vcode, cap, vcount, d, stats);
 }
 
+GatherJob gather_job(const int4* vlist, const int* vcode, const int* count, int max_pairs, const void* img,
+                     int img_dtype, int64_t s0, int64_t s1, int64_t s2, int w, int ch_first, const LayerDev& L,
+                     int topk, bool one_channel)
+{
+    GatherJob J{};
+    J.vlist = vlist;
+    J.vcode = vcode;
+    J.count = count;
+    J.img = img;
+    J.s0 = s0;
+    J.s1 = s1;
+    J.s2 = s2;
+    J.L = L;
+    J.w = w;
+    J.ch_first = ch_first;
+    J.topk = topk;
+    const int V = topk || one_channel ? 1 : gather_vec_width(L.storage, L.C, img_dtype, img, s0, s1, s2, ch_first, L);
+    J.kind = kind_of(img_dtype, L.storage, V > 1);
+    int lpp_log2 = 0;
+    while (topk == 0 && (1 << lpp_log2) * V < L.C && lpp_log2 < 6) lpp_log2++;
+    J.lpp_log2 = lpp_log2;
+    const int ppw = 64 >> lpp_log2;
+    const int64_t waves = ((int64_t)max_pairs + ppw - 1) / ppw;
+    int64_t blocks = (waves + 3) / 4;
+    if (blocks > 2048) blocks = 2048;
+    if (blocks < 1) blocks = 1;
+    J.blocks = (int)blocks;
+    J.block0 = 0;
+    return J;
+}
+
+void launch_gather_multi(hipStream_t s, GatherJobs& js, LaunchEv ev)
+{
+    // the jobs with the most lanes per pair (the longest rows) first, and at
+    // most 1024 workgroups each (512-4096 and the call order measured slower)
+    for (int a = 1; a < js.n; a++)
+        for (int b = a; b > 0 && js.j[b].lpp_log2 > js.j[b - 1].lpp_log2; b--) std::swap(js.j[b], js.j[b - 1]);
+    int total = 0;
+    for (int k = 0; k < js.n; k++) {
+        js.j[k].blocks = std::min(js.j[k].blocks, 1024);
+        js.j[k].block0 = total;
+        total += js.j[k].blocks;
+    }
+    int sm = 0;
+    for (int k = 0; k < js.n; k++) sm |= storage_bit(js.j[k].L.storage);
+    const dim3 gr((unsigned)total), bl(256);
+    switch (sm) {
+    case 1: hipExtLaunchKernelGGL(k_gather_multi<1>, gr, bl, 0, s, ev.start, ev.stop, 0, js); break;
+    case 2: hipExtLaunchKernelGGL(k_gather_multi<2>, gr, bl, 0, s, ev.start, ev.stop, 0, js); break;
+    case 3: hipExtLaunchKernelGGL(k_gather_multi<3>, gr, bl, 0, s, ev.start, ev.stop, 0, js); break;
+    case 4: hipExtLaunchKernelGGL(k_gather_multi<4>, gr, bl, 0, s, ev.start, ev.stop, 0, js); break;
+    case 5: hipExtLaunchKernelGGL(k_gather_multi<5>, gr, bl, 0, s, ev.start, ev.stop, 0, js); break;
+    case 6: hipExtLaunchKernelGGL(k_gather_multi<6>, gr, bl, 0, s, ev.start, ev.stop, 0, js); break;
+    default: hipExtLaunchKernelGGL(k_gather_multi<7>, gr, bl, 0, s, ev.start, ev.stop, 0, js); break;
+    }
+}
+
 void launch_gather_fuse(hipStream_t s, const int4* vlist, const int* vcode, const int* count, int max_pairs,
                         const void* img, int img_dtype, int64_t s0, int64_t s1, int64_t s2, int w,
                         int ch_first, const LayerDev& L, int topk, bool one_channel, LaunchEv ev)
 {
-    const int V = topk || one_channel ? 1 : gather_vec_width(L.storage, L.C, img_dtype, img, s0, s1, s2, ch_first, L);
-    int lpp_log2 = 0;
-    while (topk == 0 && (1 << lpp_log2) * V < L.C && lpp_log2 < 6) lpp_log2++;
-    const int ppw = 64 >> lpp_log2;
-    int64_t waves = ((int64_t)max_pairs + ppw - 1) / ppw;
-    int64_t blocks = (waves + 3) / 4;
-    if (blocks > 2048) blocks = 2048;
-    if (blocks < 1) blocks = 1;
-    dim3 gr((unsigned)blocks), bl(256);
+    const GatherJob J =
+        gather_job(vlist, vcode, count, max_pairs, img, img_dtype, s0, s1, s2, w, ch_first, L, topk, one_channel);
+    const bool vec = J.kind % 2 == 0;
+    dim3 gr((unsigned)J.blocks), bl(256);
 #define MEM_GF(IMG, S, V) \
     hipExtLaunchKernelGGL((k_gather_fuse<IMG, S, V>), gr, bl, 0, s, ev.start, ev.stop, 0, vlist, vcode, count, img, \
-                          s0, s1, s2, w, ch_first, L, lpp_log2, topk)
+                          s0, s1, s2, w, ch_first, L, J.lpp_log2, topk)
 #define MEM_GF2(IMG, S, VV) \
     do {                    \
-        if (V > 1)          \
+        if (vec)            \
             MEM_GF(IMG, S, VV); \
         else                \
             MEM_GF(IMG, S, 1);  \

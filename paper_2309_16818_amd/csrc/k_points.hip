@@ -93,6 +93,35 @@ __global__ __launch_bounds__(kWG) void k_ingest(Grid g, const float* __restrict_
     block_stats(stats, ids, vals);
 }
 
+// k_ingest over several clouds in one launch (grid row y = cloud): each
+// cloud bins into its own sums and ray lists, so the clouds' workgroups
+// are independent; a workgroup past its cloud's points leaves at once.
+__global__ __launch_bounds__(kWG) void k_ingest_clouds(Grid g, IngestClouds cl, float c0, float c1, float mr2,
+                                                       PointBinds pb, unsigned long long* __restrict__ stats)
+{
+    __shared__ int s_march[kMarchLds];
+    __shared__ int s_key[kSlots];
+    __shared__ int s_cnt[kSlots];
+    __shared__ float s_w[kSlots];
+    __shared__ float s_s[kSlots];
+    __shared__ float2 s_first[kSlots];
+    const IngestLds lds{s_key, s_cnt, s_w, s_s, s_first, nullptr, kSlotsLog2};
+
+    const IngestCloud& C = cl.c[blockIdx.y];
+    const int64_t begin = (int64_t)blockIdx.x * kChunk;
+    if (begin >= C.n) return;  // the whole workgroup
+    const int64_t end = begin + kChunk < C.n ? begin + kChunk : C.n;
+    const Accum acc{C.cnt, C.wsum, C.ssum, C.stash, nullptr, nullptr, g.W * g.H};
+    PointCounts pc;
+    ingest_range<kChunk / kWG>(g, C.xyz, begin, end, nullptr, C.T, c0, c1, mr2, pb, acc, lds, pc, true, C.mb,
+                               s_march);
+    const int ids[8] = {ST_ACCEPTED,  ST_NONFINITE, ST_RANGE,     ST_OUTSIDE,
+                        ST_POINTS_IN, ST_FLUSHES,   ST_RAY_STEPS, ST_SEGMENTS};
+    int vals[8] = {pc.acc,     pc.nonfinite, pc.range,     pc.outside, pc.acc + pc.nonfinite + pc.range + pc.outside,
+                   pc.flushed, pc.ray_steps, pc.ray_segs};
+    block_stats(stats, ids, vals);
+}
+
 // The clearing march in two kernels.  k_ray_prep (one lane per point)
 // transforms the point, stores the ray's record (its cell, the reciprocal
 // of its major extent and its height difference)
@@ -336,6 +365,17 @@ void launch_ingest(hipStream_t s, const Grid& g, const float* xyz, int64_t n, co
     const size_t lds = pb.lds_ch ? sizeof(float) * kSlots * pb.Cb : 0;
     hipExtLaunchKernelGGL(k_ingest, dim3(blocks_for(n, kChunk)), dim3(kWG), (uint32_t)lds, s, ev.start, ev.stop, 0, g,
                           xyz, n, ch, T, c0, c1, mr2, pb, acc, march ? *march : MarchBufs{}, march ? 1 : 0, stats);
+}
+
+void launch_ingest_clouds(hipStream_t s, const Grid& g, const IngestClouds& cl, float c0, float c1, float mr2,
+                          unsigned long long* stats, LaunchEv ev)
+{
+    int64_t nmax = 0;
+    for (int k = 0; k < cl.n; k++) nmax = std::max(nmax, cl.c[k].n);
+    if (cl.n < 1 || nmax <= 0) return;
+    PointBinds pb{};
+    hipExtLaunchKernelGGL(k_ingest_clouds, dim3(blocks_for(nmax, kChunk), (unsigned)cl.n), dim3(kWG), 0, s, ev.start,
+                          ev.stop, 0, g, cl, c0, c1, mr2, pb, stats);
 }
 
 void march_pass(float mr2, float res, int64_t n, int64_t* pts, int64_t* full_per_ray)

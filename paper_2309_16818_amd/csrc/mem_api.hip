@@ -79,6 +79,17 @@ size_t elem_size(int storage)
 
 }  // namespace
 
+// Sums, counts and ray lists of one more cloud of a mem_input_pointclouds
+// call (the map's own serve its first cloud); zero between calls.
+struct CloudSet {
+    int* cnt = nullptr;
+    int* clr = nullptr;
+    float* wsum = nullptr;
+    float* ssum = nullptr;
+    float2* stash = nullptr;
+    MarchBufs march;
+};
+
 struct mem_map {
     int W = 0, H = 0;
     float res = 0, inv_res = 0;
@@ -108,6 +119,7 @@ struct mem_map {
     bool acc_clean = false;     // accumulators and march counts are zero (the last cloud's finalize cleared them)
     bool hl_fresh = false;      // hl holds the heights in logical order
     MarchBufs march;            // clearing march: rays and segment lists (grown on first use)
+    std::vector<CloudSet> csets; // further per-cloud sums and lists of mem_input_pointclouds (first use)
     float* hl = nullptr;        // heights in logical order, for the clearing march
     DriftDev* drift = nullptr;  // the last cloud's drift compensation
     char* drift_part = nullptr; // its per-workgroup partial sums
@@ -281,6 +293,17 @@ void free_map(mem_map* m)
     (void)hipFree(m->march.full);
     (void)hipFree(m->march.part);
     (void)hipFree(m->march.counts);
+    for (CloudSet& c : m->csets) {
+        (void)hipFree(c.cnt);
+        (void)hipFree(c.clr);
+        (void)hipFree(c.wsum);
+        (void)hipFree(c.ssum);
+        (void)hipFree(c.stash);
+        (void)hipFree(c.march.rec);
+        (void)hipFree(c.march.full);
+        (void)hipFree(c.march.part);
+        (void)hipFree(c.march.counts);
+    }
     (void)hipFree(m->hl);
     (void)hipFree(m->drift);
     (void)hipFree(m->drift_part);
@@ -631,6 +654,159 @@ mem_status mem_input_pointcloud(mem_map* m, const float* xyz, int64_t n, const f
     return check_launch(m, "mem_input_pointcloud");
 }
 
+// Ray lists with room for passes of `pts` points (grown with a stream
+// synchronisation, as the map's own); counts zeroed when (re)allocated.
+static mem_status grow_march(mem_map* m, MarchBufs* mb, int64_t pts, int64_t fpr, hipStream_t s)
+{
+    if (!mb->counts) {
+        if (mem_status st = dev_alloc(m, &mb->counts, kSegLists * kSegSubs)) return st;
+        launch_zero_int(s, mb->counts, kSegLists * kSegSubs);
+    }
+    if (pts <= mb->cap_pts) return MEM_OK;
+    HIP_TRY(m, hipStreamSynchronize(s));
+    (void)hipFree(mb->rec);
+    (void)hipFree(mb->full);
+    (void)hipFree(mb->part);
+    mb->rec = nullptr;
+    mb->full = nullptr;
+    mb->part = nullptr;
+    mb->cap_pts = 0;
+    const MarchSizes z = march_sizes(pts, fpr);
+    if (mem_status st = dev_alloc(m, &mb->rec, pts)) return st;
+    if (mem_status st = dev_alloc(m, &mb->full, kSegSubs * z.full_sub)) return st;
+    if (mem_status st = dev_alloc(m, &mb->part, 4 * kSegSubs * z.part_sub)) return st;
+    mb->cap_pts = pts;
+    mb->full_sub = z.full_sub;
+    mb->part_sub = z.part_sub;
+    return MEM_OK;
+}
+
+static mem_status check_cloud(const mem_map* m, const mem_cloud& c, int k)
+{
+    if (c.n < 0) return fail(MEM_E_ARG, "cloud %d: n must be >= 0", k);
+    if (c.n > 0 && !c.xyz) return fail(MEM_E_ARG, "cloud %d: xyz is NULL", k);
+    if (c.c < 0 || (c.c > 0 && c.n > 0 && !c.ch)) return fail(MEM_E_ARG, "cloud %d: channels given without data", k);
+    if (c.n_bind < 0 || c.n_bind > kMaxBind || (c.n_bind > 0 && !c.bind))
+        return fail(MEM_E_ARG, "cloud %d: n_bind must be 0..%d with a binding array", k, kMaxBind);
+    if (mem_status st = check_pose(m, c.T_map_sensor, "T_map_sensor")) return st;
+    for (int b = 0; b < c.n_bind; b++) {
+        const Layer* L = nullptr;
+        if (mem_status st = resolve_layer(m, c.bind[b].layer, &L)) return st;
+        char what[48];
+        snprintf(what, sizeof what, "cloud %d binding %d", k, b);
+        if (mem_status st = check_binding(c.bind[b], L, c.c, what)) return st;
+    }
+    return MEM_OK;
+}
+
+mem_status mem_input_pointclouds(mem_map* m, const mem_cloud* clouds, int32_t n_clouds, void* stream)
+{
+    if (mem_status st = usable(m)) return st;
+    if (n_clouds < 1 || n_clouds > kMaxClouds || !clouds)
+        return fail(MEM_E_ARG, "n_clouds must be 1..%d with a cloud array", kMaxClouds);
+    for (int k = 0; k < n_clouds; k++)
+        if (mem_status st = check_cloud(m, clouds[k], k)) return st;
+    // the clouds' ingest in one launch where its conditions hold
+    bool one_launch = n_clouds > 1 && m->clear_min > 0 && !m->drift_on && !m->overlap_on;
+    int64_t pmax = 0, fpr = 0;
+    for (int k = 0; k < n_clouds && one_launch; k++) {
+        int64_t pts = 0;
+        march_pass(m->mr2, m->res, clouds[k].n, &pts, &fpr);
+        one_launch = clouds[k].n_bind == 0 && clouds[k].n > 0 && pts == clouds[k].n;
+        pmax = std::max(pmax, pts);
+    }
+    if (!one_launch) {
+        for (int k = 0; k < n_clouds; k++) {
+            const mem_cloud& c = clouds[k];
+            if (mem_status st = mem_input_pointcloud(m, c.xyz, c.n, c.ch, c.c, c.bind, c.n_bind, c.T_map_sensor,
+                                                     stream))
+                return st;
+        }
+        return MEM_OK;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int K = n_clouds;
+    const int64_t HW = m->cells();
+    while ((int)m->csets.size() < K - 1) {
+        CloudSet c;
+        mem_status st = MEM_OK;
+        (void)((st = dev_alloc(m, &c.cnt, HW)) || (st = dev_alloc(m, &c.clr, HW)) ||
+               (st = dev_alloc(m, &c.wsum, HW)) || (st = dev_alloc(m, &c.ssum, HW)) ||
+               (st = dev_alloc(m, &c.stash, HW)));
+        if (st == MEM_OK) {
+            launch_zero_int(s, c.cnt, (int)HW);
+            launch_zero_int(s, c.clr, (int)HW);
+            launch_zero_int(s, (int*)c.wsum, (int)HW);
+            launch_zero_int(s, (int*)c.ssum, (int)HW);
+            launch_zero_int(s, (int*)c.stash, (int)(2 * HW));
+        }
+        m->csets.push_back(c);  // freed with the map, also when incomplete
+        if (st) return st;
+    }
+    if (mem_status st = grow_march(m, &m->march, pmax, fpr, s)) return st;
+    for (int k = 0; k < K - 1; k++)
+        if (mem_status st = grow_march(m, &m->csets[k].march, pmax, fpr, s)) return st;
+    Grid g = m->grid();
+    if (!m->acc_clean || !m->hl_fresh) {
+        timed_ext(m, s, "zero_accum", [&](LaunchEv ev) {
+            launch_zero_accum(s, g, m->cnt, m->wsum, m->ssum, m->clr, m->chsum, m->chsum_planes, m->march.counts,
+                              m->h, m->hl, m->drift, ev);
+        });
+        m->hl_fresh = true;
+    }
+    m->acc_clean = false;
+    // cloud k (1-based) counts into cnt[k], clr[k]; cnt[0], clr[0] hold the
+    // last call's counts, zeroed by the first cloud's finalize, and each
+    // finalize zeroes the counts of the cloud before it
+    std::vector<int*> cnt(K + 1), clr(K + 1);
+    cnt[0] = m->cnt_last;
+    clr[0] = m->clr_last;
+    cnt[1] = m->cnt;
+    clr[1] = m->clr;
+    for (int k = 2; k <= K; k++) {
+        cnt[k] = m->csets[k - 2].cnt;
+        clr[k] = m->csets[k - 2].clr;
+    }
+    auto march_of = [&](int k) -> MarchBufs& { return k == 1 ? m->march : m->csets[k - 2].march; };
+    IngestClouds cl{};
+    cl.n = K;
+    for (int k = 1; k <= K; k++) {
+        IngestCloud& c = cl.c[k - 1];
+        c.xyz = clouds[k - 1].xyz;
+        c.n = clouds[k - 1].n;
+        memcpy(c.T.m, clouds[k - 1].T_map_sensor, sizeof(c.T.m));
+        c.cnt = cnt[k];
+        c.wsum = k == 1 ? m->wsum : m->csets[k - 2].wsum;
+        c.ssum = k == 1 ? m->ssum : m->csets[k - 2].ssum;
+        c.stash = k == 1 ? m->stash : m->csets[k - 2].stash;
+        c.mb = march_of(k);
+    }
+    timed_ext(m, s, "ingest", [&](LaunchEv ev) { launch_ingest_clouds(s, g, cl, m->c0, m->c1, m->mr2, m->stats, ev); });
+    const PointBinds pb{};
+    for (int k = 1; k <= K; k++) {
+        const IngestCloud& c = cl.c[k - 1];
+        timed_ext(m, s, "clear_march", [&](LaunchEv ev) {
+            launch_clear_march(s, g, c.xyz, c.n, c.T, m->mr2, m->clear_margin, m->hl, clr[k], c.mb, true, m->stats,
+                               ev);
+        });
+        timed_ext(m, s, "finalize", [&](LaunchEv ev) {
+            launch_finalize(s, g, cnt[k], c.wsum, c.ssum, c.stash, clr[k], m->clear_min, m->h, m->v, nullptr, pb,
+                            m->stats, true, cnt[k - 1], clr[k - 1], m->hl, c.mb.counts, m->drift, ev);
+        });
+    }
+    m->cnt = cnt[0];
+    m->clr = clr[0];
+    m->cnt_last = cnt[K];
+    m->clr_last = clr[K];
+    for (int k = 0; k < K - 1; k++) {
+        m->csets[k].cnt = cnt[k + 1];
+        m->csets[k].clr = clr[k + 1];
+    }
+    m->tmax_stale = true;
+    m->acc_clean = true;
+    return check_launch(m, "mem_input_pointclouds");
+}
+
 mem_status mem_set_drift_compensation(mem_map* m, int32_t enable, float kappa, int32_t min_points)
 {
     if (mem_status st = usable(m)) return st;
@@ -850,6 +1026,24 @@ static mem_status input_poses(mem_map* m, const mem_image* images, const int32_t
     timed_ext(m, s, "project", [&](LaunchEv ev) {
         launch_project(s, g, cs, m->h, tm, cap, vc, vc_next, vlist, vcode, nullptr, m->stats, ev);
     });
+    // The gathers in call order, grouped into launches: a binding joins the
+    // open group unless the group already writes its layer (bindings of
+    // different layers commute, those of one layer keep their order).
+    GatherJobs js{};
+    int group_layers[kMaxGatherJobs];
+    auto flush = [&] {
+        if (js.n == 0) return;
+        timed_ext(m, s, "gather_fuse", [&](LaunchEv ev) {
+            if (js.n == 1) {
+                const GatherJob& J = js.j[0];
+                launch_gather_fuse(s, J.vlist, J.vcode, J.count, cap, J.img, J.kind >= 6 ? MEM_F32 : MEM_U8, J.s0,
+                                   J.s1, J.s2, J.w, J.ch_first, J.L, J.topk, J.kind % 2 != 0, ev);
+            } else {
+                launch_gather_multi(s, js, ev);
+            }
+        });
+        js.n = 0;
+    };
     first = 0;
     for (int p = 0; p < n_poses; p++) {
         for (int k = 0; k < counts[p]; k++) {
@@ -857,17 +1051,19 @@ static mem_status input_poses(mem_map* m, const mem_image* images, const int32_t
             for (int b = 0; b < im.n_bind; b++) {
                 const Layer* L = nullptr;
                 resolve_layer(m, im.bind[b].layer, &L);
-                LayerDev d = L->dev();
-                timed_ext(m, s, "gather_fuse", [&](LaunchEv ev) {
-                    launch_gather_fuse(s, vlist + (int64_t)p * cap,
-                                       vcode + ((int64_t)p * kMaxImages + k) * cap, vc + p, cap, im.data,
-                                       im.dtype, im.strides[0], im.strides[1], im.strides[2], im.w,
-                                       im.bind[b].ch_first, d, im.bind[b].topk, m->gather_v1 != 0, ev);
-                });
+                bool taken = js.n == kMaxGatherJobs;
+                for (int q = 0; q < js.n; q++) taken = taken || group_layers[q] == im.bind[b].layer;
+                if (taken) flush();
+                group_layers[js.n] = im.bind[b].layer;
+                js.j[js.n++] = gather_job(vlist + (int64_t)p * cap, vcode + ((int64_t)p * kMaxImages + k) * cap,
+                                          vc + p, cap, im.data, im.dtype, im.strides[0], im.strides[1],
+                                          im.strides[2], im.w, im.bind[b].ch_first, L->dev(), im.bind[b].topk,
+                                          m->gather_v1 != 0);
             }
         }
         first += counts[p];
     }
+    flush();
     return check_launch(m, "mem_input_images");
 }
 

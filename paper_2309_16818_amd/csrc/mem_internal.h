@@ -194,6 +194,26 @@ struct MarchBufs {
     int* counts = nullptr;  // kSegLists * kSegSubs, list-major
     int64_t cap_pts = 0, full_sub = 0, part_sub = 0;
 };
+// Clouds binned by one launch (launch_ingest_clouds): each with its own
+// sums and ray lists (a single clearing pass: n <= mb.cap_pts), no bound
+// channels.
+struct IngestCloud {
+    const float* xyz;
+    int64_t n;
+    Pose T;
+    int* cnt;  // the cloud's sums (as for launch_ingest)
+    float* wsum;
+    float* ssum;
+    float2* stash;
+    MarchBufs mb;
+};
+constexpr int kMaxClouds = 8;
+struct IngestClouds {
+    IngestCloud c[kMaxClouds];
+    int n;
+};
+void launch_ingest_clouds(hipStream_t s, const Grid& g, const IngestClouds& cl, float c0, float c1, float mr2,
+                          unsigned long long* stats, LaunchEv ev = {});
 // Points per pass for a cloud of n points (at most kMarchPass, and few
 // enough that the full list holds every segment) and the full segments a
 // ray within the map's range can have.
@@ -256,6 +276,32 @@ void launch_gather_fuse(hipStream_t s, const int4* vlist, const int* vcode, cons
                         const void* img, int img_dtype, int64_t s0, int64_t s1, int64_t s2, int w,
                         int ch_first, const LayerDev& L, int topk = 0, bool one_channel = false,
                         LaunchEv ev = {});
+// One image binding's gather (launch_gather_fuse's arguments) as a job of a
+// fused launch: gather_job fills in its variant and lane count.
+struct GatherJob {
+    const int4* vlist;
+    const int* vcode;
+    const int* count;
+    const void* img;
+    int64_t s0, s1, s2;
+    LayerDev L;
+    int w, ch_first, topk;
+    int lpp_log2;  // lanes per visible pair: 2^lpp_log2
+    int kind;      // image type x storage type x (vector, one channel, top-k)
+    int blocks;    // workgroups of the job
+    int block0;    // its first workgroup in the fused grid
+};
+constexpr int kMaxGatherJobs = 8;
+struct GatherJobs {
+    GatherJob j[kMaxGatherJobs];
+    int n;
+};
+GatherJob gather_job(const int4* vlist, const int* vcode, const int* count, int max_pairs, const void* img,
+                     int img_dtype, int64_t s0, int64_t s1, int64_t s2, int w, int ch_first, const LayerDev& L,
+                     int topk, bool one_channel);
+// Runs jobs.j[0 .. n) as one launch, each on its own workgroups.  The jobs
+// must write different layers: their order inside the launch is not defined.
+void launch_gather_multi(hipStream_t s, GatherJobs& jobs, LaunchEv ev = {});
 
 // ---- batches of maps ----
 

@@ -30,7 +30,7 @@ STAT_FIELDS = ("points_in", "points_accepted", "dropped_nonfinite", "dropped_ran
 # Exported symbols of include/mem.h.
 SYMBOLS = ("mem_create", "mem_destroy", "mem_move", "mem_input_pointcloud", "mem_input_image",
            "mem_input_images", "mem_get_layer", "mem_set_layer", "mem_normals", "mem_set_drift_compensation", "mem_get_drift",
-           "mem_set_overlap_clearance", "mem_pca", "mem_pca_noalloc", "mem_input_image_poses",
+           "mem_set_overlap_clearance", "mem_pca", "mem_pca_noalloc", "mem_input_image_poses", "mem_input_pointclouds",
            "mem_get_center", "mem_debug_point_cells", "mem_debug_gather_width",
            "mem_debug_cell_pixels", "mem_get_stats", "mem_reset_stats", "mem_profile_enable",
            "mem_profile_read", "mem_last_error")
@@ -57,6 +57,11 @@ class mem_image(C.Structure):
     _fields_ = [("data", C.c_void_p), ("dtype", C.c_int32), ("h", C.c_int32), ("w", C.c_int32),
                 ("c", C.c_int32), ("strides", C.c_int64 * 3), ("K", C.c_float * 4),
                 ("bind", C.POINTER(mem_binding)), ("n_bind", C.c_int32)]
+
+
+class mem_cloud(C.Structure):
+    _fields_ = [("xyz", C.c_void_p), ("n", C.c_int64), ("ch", C.c_void_p), ("c", C.c_int32),
+                ("bind", C.POINTER(mem_binding)), ("n_bind", C.c_int32), ("T_map_sensor", C.c_float * 12)]
 
 
 class mem_stats(C.Structure):
@@ -93,6 +98,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "mem_input_image": [P, P, I32, I32, I32, I32, P, P, P, C.POINTER(mem_binding), I32, P],
         "mem_input_images": [P, C.POINTER(mem_image), I32, P, P],
         "mem_input_image_poses": [P, C.POINTER(mem_image), C.POINTER(I32), I32, P, P],
+        "mem_input_pointclouds": [P, C.POINTER(mem_cloud), I32, P],
         "mem_get_layer": [P, I32, I32, P, P],
         "mem_set_layer": [P, I32, I32, P, P],
         "mem_normals": [P, P, P],
@@ -264,6 +270,27 @@ class Map:
         b, nb = _bindings(bind)
         _check(load().mem_input_pointcloud(self._h, _dev_ptr(xyz, "xyz"), n, chp, c, b, nb,
                                            _pose(T), _stream(stream)))
+
+    def input_pointclouds(self, clouds, stream=None):
+        """clouds: sequence of (xyz, T) or (xyz, T, ch, bind), each as for
+        input_pointcloud; equals input_pointcloud for each in order."""
+        arr = (mem_cloud * max(1, len(clouds)))()
+        keep = []
+        for k, cl in enumerate(clouds):
+            xyz, T = cl[0], cl[1]
+            ch = cl[2] if len(cl) > 2 else None
+            bind = cl[3] if len(cl) > 3 else ()
+            if xyz.dtype != torch.float32 or xyz.dim() != 2 or xyz.shape[1] != 3 or not xyz.is_contiguous():
+                raise ValueError("xyz must be a contiguous float32 [n, 3] tensor")
+            c, chp = 0, None
+            if ch is not None:
+                if ch.dtype != torch.float32 or ch.dim() != 2 or ch.shape[0] != xyz.shape[0] or not ch.is_contiguous():
+                    raise ValueError("ch must be a contiguous float32 [n, c] tensor")
+                c, chp = ch.shape[1], _dev_ptr(ch, "ch")
+            b, nb = _bindings(bind)
+            keep.append(b)
+            arr[k] = mem_cloud(_dev_ptr(xyz, "xyz"), xyz.shape[0], chp, c, b, nb, _pose(T))
+        _check(load().mem_input_pointclouds(self._h, arr, len(clouds), _stream(stream)))
 
     def input_image(self, img: torch.Tensor, K, T, bind=(), stream=None):
         if img.dim() != 3:
