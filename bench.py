@@ -27,6 +27,8 @@ multi-modal layers), copy (a plain 256 MiB copy for counter scaling).
 from __future__ import annotations
 
 import argparse
+import contextlib
+import gc
 import json
 import math
 import os
@@ -83,6 +85,20 @@ def traffic_bytes(kernel):
     if not t or t["sha"] != source_sha(KERNEL_SOURCES.get(kernel, ())):
         return None
     return t["bytes_per_launch"]
+
+
+@contextlib.contextmanager
+def no_gc():
+    """Python's cyclic collector off inside a timed region (collected just
+    before): a collection of the generated frames' objects would otherwise
+    stall the host, and with it the GPU, for tens of milliseconds inside
+    whichever frame it falls."""
+    gc.collect()
+    gc.disable()
+    try:
+        yield
+    finally:
+        gc.enable()
 
 
 def parse():
@@ -858,12 +874,13 @@ def time_drift(dframes, warmup, torch, kappa=3.0, min_points=100):
             m.profile_read()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in dframes[warmup:]]
         offsets = []
-        for k, f in enumerate(dframes[warmup:]):
-            ev[k][0].record()
-            run_frame(m, f)
-            ev[k][1].record()
-            if profile:
-                offsets.append(m.drift())
+        with no_gc():
+            for k, f in enumerate(dframes[warmup:]):
+                ev[k][0].record()
+                run_frame(m, f)
+                ev[k][1].record()
+                if profile:
+                    offsets.append(m.drift())
         torch.cuda.synchronize()
         out = (np.array([a.elapsed_time(b) for a, b in ev]), m.stats(), m.profile_read() if profile else None, offsets)
         m.close()
@@ -894,11 +911,12 @@ def time_overlap(dframes, warmup, torch, range_xy=4.0, range_z=2.0):
             m.profile_enable(True)
             m.profile_read()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in dframes[warmup:]]
-        for k, f in enumerate(dframes[warmup:]):
-            ev[k][0].record()
-            run_frame(m, f)
-            ev[k][1].record()
-        torch.cuda.synchronize()
+        with no_gc():
+            for k, f in enumerate(dframes[warmup:]):
+                ev[k][0].record()
+                run_frame(m, f)
+                ev[k][1].record()
+            torch.cuda.synchronize()
         out = (np.array([a.elapsed_time(b) for a, b in ev]), m.profile_read() if profile else None)
         m.close()
         return out
@@ -1049,19 +1067,20 @@ def main():
     # timed pass: frame-level events only (per-launch events would add host
     # work between the launches)
     m = make_map()
-    for f in dframes[:args.warmup]:
-        run_frame(m, f)
-    torch.cuda.synchronize()
-    m.reset_stats()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k, f in enumerate(dframes[args.warmup:]):
-        ev[k][0].record()
-        run_frame(m, f)
-        ev[k][1].record()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    with no_gc():
+        for f in dframes[:args.warmup]:
+            run_frame(m, f)
+        torch.cuda.synchronize()
+        m.reset_stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k, f in enumerate(dframes[args.warmup:]):
+            ev[k][0].record()
+            run_frame(m, f)
+            ev[k][1].record()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
     st = m.stats()
     post = {"normals": time_normals(m, torch), "normals_4096": time_normals_large(torch),
             "pca": time_pca(m, torch), "class_image": time_topk(m, dframes[-1], torch)}
@@ -1069,6 +1088,7 @@ def main():
     post["drift"] = time_drift(dframes, args.warmup, torch)
     post["overlap_clearance"] = time_overlap(dframes, args.warmup, torch)
     lat = np.array([a.elapsed_time(b) for a, b in ev])
+    print("# frame latencies (ms): " + " ".join(f"{x:.3f}" for x in lat), file=sys.stderr, flush=True)
     wall_ms = (t1 - t0) * 1e3 / args.steps
     pts_s = st["points_accepted"] / ((t1 - t0))
     # profiled pass over the same frames: HIP events around every launch
@@ -1080,9 +1100,10 @@ def main():
         torch.cuda.synchronize()
         m.profile_enable(True)
         m.profile_read()  # clears totals
-        for f in dframes[args.warmup:]:
-            run_frame(m, f)
-        kern = m.profile_read()
+        with no_gc():
+            for f in dframes[args.warmup:]:
+                run_frame(m, f)
+            kern = m.profile_read()
         m.profile_enable(False)
         m.close()
 
