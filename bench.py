@@ -55,14 +55,14 @@ WALK_VALU_PER_CELL = {"clear_march": 13, "project": 57}
 
 # HBM traffic of kernels from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of the
 # full-rate workload, scaled by the same counters for the calibration copy
-# (a 1 GiB copy reads FETCH_SIZE 524303 KiB: factor 1.99994; writes
-# WRITE_SIZE 1048676 KiB: factor 0.99991; profiles/point_path_traffic.md),
+# (a 1 GiB copy reads FETCH_SIZE 524304 KiB: factor 1.99994; writes
+# WRITE_SIZE 1048682 KiB: factor 0.99990; profiles/point_path_traffic.md),
 # bytes per launch, valid while the kernel's sources hash to `sha`.
 TRAFFIC = {
-    "clear_march": {"bytes_per_launch": 4458056, "sha": "4764a1f55d856783"},  # k_ray_walk
-    "ingest": {"bytes_per_launch": 5627987, "sha": "4764a1f55d856783"},
-    "finalize": {"bytes_per_launch": 2214547, "sha": "4764a1f55d856783"},
-    "gather_fuse": {"bytes_per_launch": 2251170, "sha": "7b8ca984d9a524cc"},  # mean over the frame's images
+    "clear_march": {"bytes_per_launch": 4463906, "sha": "06140b38034809c5"},  # k_ray_walk
+    "ingest": {"bytes_per_launch": 59246044, "sha": "06140b38034809c5"},  # k_ingest_clouds: a frame's five clouds
+    "finalize": {"bytes_per_launch": 2220339, "sha": "06140b38034809c5"},
+    "gather_fuse": {"bytes_per_launch": 13917708, "sha": "7a20ad5fc0d45595"},  # k_gather_multi: a pose's three images
 }
 
 
