@@ -197,18 +197,19 @@ def batch_leg(n_maps, steps, warmup, plain_steps, seed=3):
     s0 = all_steps[0]
     tuning = B.tune(s0["robot_xy"], s0["xyz"], s0["offsets"], s0["T"], images=imgs[0], K=s0["K"], T_cam=s0["T_cam"])
     print(f"# tuned: {tuning}", file=sys.stderr, flush=True)
-    for k in range(warmup):
-        bstep(B, k)
-    torch.cuda.synchronize()
-    B.reset_stats()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-    t1 = time.perf_counter()
-    for j in range(steps):
-        ev[j][0].record()
-        bstep(B, warmup + j)
-        ev[j][1].record()
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
+    with no_gc():
+        for k in range(warmup):
+            bstep(B, k)
+        torch.cuda.synchronize()
+        B.reset_stats()
+        t1 = time.perf_counter()
+        for j in range(steps):
+            ev[j][0].record()
+            bstep(B, warmup + j)
+            ev[j][1].record()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
     st = B.stats()
     lat = np.array([a.elapsed_time(b) for a, b in ev])
     batched_pts = st["points_accepted"] / (t2 - t1)
@@ -222,9 +223,10 @@ def batch_leg(n_maps, steps, warmup, plain_steps, seed=3):
     torch.cuda.synchronize()
     P.profile_enable(True)
     P.profile_read()
-    for j in range(steps):
-        bstep(P, warmup + j)
-    kern = P.profile_read()
+    with no_gc():
+        for j in range(steps):
+            bstep(P, warmup + j)
+        kern = P.profile_read()
     P.profile_enable(False)
     P.close()
     stages = {}

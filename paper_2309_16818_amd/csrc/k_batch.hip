@@ -53,18 +53,31 @@ __device__ __forceinline__ int next_item(int* qctr, int q, int n, int* s_item)
     return *s_item;
 }
 
-// Map of point-chunk item `it` (binary search over the per-map prefix) and
-// the item's point range.
-__device__ __forceinline__ int chunk_item(const BatchDev& d, int it, int64_t& begin, int64_t& end)
+// The per-map prefix of point-chunk items copied into LDS (s_cs, kChunkLds
+// ints) when it fits, so that an item's map is found by a search in LDS
+// rather than a chain of dependent global loads; else the global table.
+// Every thread of the workgroup calls it; it ends with a barrier.
+constexpr int kChunkLds = 1088;
+__device__ __forceinline__ const int* stage_chunk_start(const BatchDev& d, int* s_cs)
 {
-    int lo = 0, hi = d.n_maps;  // chunk_start[lo] <= it < chunk_start[hi]
+    if (d.n_maps + 1 > kChunkLds) return d.chunk_start;
+    for (int k = threadIdx.x; k <= d.n_maps; k += blockDim.x) s_cs[k] = d.chunk_start[k];
+    __syncthreads();
+    return s_cs;
+}
+
+// Map of point-chunk item `it` (binary search over the per-map prefix cs)
+// and the item's point range.
+__device__ __forceinline__ int chunk_item(const BatchDev& d, const int* cs, int it, int64_t& begin, int64_t& end)
+{
+    int lo = 0, hi = d.n_maps;  // cs[lo] <= it < cs[hi]
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (d.chunk_start[mid] <= it) lo = mid;
+        if (cs[mid] <= it) lo = mid;
         else hi = mid;
     }
     const BatchMap& m = d.maps[lo];
-    begin = m.pt_begin + (int64_t)(it - d.chunk_start[lo]) * d.chunk;
+    begin = m.pt_begin + (int64_t)(it - cs[lo]) * d.chunk;
     end = begin + d.chunk < m.pt_end ? begin + d.chunk : m.pt_end;
     return lo;
 }
@@ -131,12 +144,14 @@ __device__ __forceinline__ int bin_ntiles(const BatchMap& m, int itile_h)
 __global__ __launch_bounds__(kBatchWG) void k_b_bin(BatchDev d, const float* __restrict__ xyz, float mr2)
 {
     __shared__ int s_hist[kBinTiles];
+    __shared__ int s_cs[kChunkLds];
+    const int* cs = stage_chunk_start(d, s_cs);
     PointCounts pc;
     int points_in = 0;
     const int n = d.n_items[1];
     for (int it = first_static(n); it >= 0; it = next_static(it, n)) {
         int64_t b0, b1;
-        const BatchMap& m = d.maps[chunk_item(d, it, b0, b1)];
+        const BatchMap& m = d.maps[chunk_item(d, cs, it, b0, b1)];
         const int ntiles = bin_ntiles(m, d.itile_h);
         const bool lds = ntiles <= kBinTiles;
         if (lds)
@@ -220,10 +235,12 @@ __global__ __launch_bounds__(kBatchWG) void k_b_bin_scatter(BatchDev d, const fl
                                                             float c1, float mr2)
 {
     __shared__ int s_hist[kBinTiles];
+    __shared__ int s_cs[kChunkLds];
+    const int* cs = stage_chunk_start(d, s_cs);
     const int n = d.n_items[1];
     for (int it = first_static(n); it >= 0; it = next_static(it, n)) {
         int64_t b0, b1;
-        const BatchMap& m = d.maps[chunk_item(d, it, b0, b1)];
+        const BatchMap& m = d.maps[chunk_item(d, cs, it, b0, b1)];
         const int ntiles = bin_ntiles(m, d.itile_h);
         const bool lds = ntiles <= kBinTiles;
         if (lds)
@@ -373,12 +390,14 @@ __global__ __launch_bounds__(kBatchWG) void k_b_march(BatchDev d, const float* _
     __shared__ int s_steps[256];
     __shared__ float4 s_pt[256];
     __shared__ int2 s_cell[256];
+    __shared__ int s_cs[kChunkLds];
+    const int* cs = stage_chunk_start(d, s_cs);
     const int t = threadIdx.x;
     int visited = 0, all_steps = 0;
     const int n = d.n_items[1];
     for (int it = next_item(d.qctr, 2, n, &s_item); it >= 0; it = next_item(d.qctr, 2, n, &s_item)) {
         int64_t b0, b1;
-        const BatchMap& m = d.maps[chunk_item(d, it, b0, b1)];
+        const BatchMap& m = d.maps[chunk_item(d, cs, it, b0, b1)];
         Grid gl = m.g;  // the walks read the logical-order height copy
         gl.rx = 0;
         gl.ry = 0;
