@@ -25,7 +25,7 @@ namespace memk {
 
 namespace {
 
-constexpr int kWG = 1024;             // threads per ingest workgroup (one point each)
+constexpr int kWG = 512;              // threads per ingest workgroup (two points each; 256 and 1024 measured slower)
 constexpr int kChunk = 1024;             // points per ingest workgroup
 constexpr int kSlotsLog2 = 11;
 constexpr int kSlots = 1 << kSlotsLog2;  // LDS hash slots (2 x points)
