@@ -243,8 +243,9 @@ typedef struct mem_cloud {
  * points of all clouds are binned in one launch into per-cloud sums and ray
  * lists, and the clouds' clearing walks and height updates then follow in
  * order; otherwise the clouds run one call each.  The first such call of k
- * clouds allocates k - 1 further sets of sums and ray lists (32 bytes per
- * cell and 24 bytes per point of capacity each), kept until destroy.
+ * clouds allocates k - 1 further sets of sums and ray lists, kept until
+ * destroy: each 24 bytes per cell and, per point of the largest cloud,
+ * 48 bytes plus 8 bytes per 64-cell segment of a ray at max_range.
  * Height updates add float sums in an order that is not fixed, so results
  * equal the one-call-each results up to rounding (the decisions and counts
  * exactly where no sum is at a threshold).  Every cloud is checked before
