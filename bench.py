@@ -1008,6 +1008,18 @@ def calibration(torch, copy_bytes=1 << 30, atomic_words=1 << 24):
             atom[f"{dname}_{pname}"] = round(atomic_words / (ms * 1e-3) / 1e9, 2)
         del buf
     out["atomics_gops"] = atom
+    # scattered loads from a 1 MiB table (the size of the 500 x 500 height
+    # copy the clearing walk reads), the walk's one load per cell and lane
+    # at its launch shape: 1280 workgroups of 256 lanes, 64 loads per lane
+    tab = torch.ones(1 << 18, device="cuda")
+    res = torch.empty(1280 * 256, device="cuda")
+    g = {}
+    for name, runs in (("scatter_1mib", False), ("runs_1mib", True)):
+        ms = timeit(lambda: mem.calib_gather(tab, res, 64, runs=runs, stream=s), 20)
+        g[name] = round(res.numel() * 64 / (ms * 1e-3) / 1e9, 1)
+        g[name + "_checked"] = bool((res == 64).all().item())
+    out["gather_gloads"] = g
+    del tab, res
     return out
 
 
@@ -1146,6 +1158,15 @@ def main():
     cal = calibration(torch)
     out["calibration"] = cal
     out["rooflines"] = kernel_rooflines(kernels, st, cal)
+    if roof and roof["kernel"] == "clear_march" and "gather_gloads" in cal:
+        # one 4-byte load of the heights' logical copy per ray cell, against
+        # the measured rate of scattered loads from a cache-resident table
+        # between uncorrelated loads and per-lane runs of consecutive words
+        lo, hi = cal["gather_gloads"]["scatter_1mib"], cal["gather_gloads"]["runs_1mib"]
+        roof["loads"] = {"achieved_gloads": roof["achieved"], "peak_gloads": hi,
+                         "frac": round(roof["achieved"] / hi, 4), "scattered_gloads": lo,
+                         "peak_is": "measured 4-byte loads from a 1 MiB table in per-lane runs of consecutive "
+                                    "words, 8 in flight per lane (scattered loads: scattered_gloads)"}
     if args.legs:
         out["batched"] = batch_leg(args.leg_maps, 10, 2, 1)
         print(f"# batched leg: {out['batched']['value']:.4g} points/s", file=sys.stderr, flush=True)

@@ -16,6 +16,10 @@
 //                                                    flush of a point ingest
 //                  shared   addr(i) = i mod n_addr   few addresses, all lanes
 //                                                    contend
+//   k_gather     4-byte loads from a small (cache-resident) table, eight in
+//                flight per lane, scattered or in per-lane runs of
+//                consecutive words: the load rates that bracket a walk over
+//                the heights, one cell per lane and load.
 #include <cstdint>
 #include <cstdio>
 #include <type_traits>
@@ -75,6 +79,32 @@ __global__ __launch_bounds__(256) void k_atomic(T* __restrict__ buf, int64_t n_o
         unsafeAtomicAdd(buf + a, static_cast<T>(1));
     else
         atomicAdd(buf + a, static_cast<T>(1));
+}
+
+// Lane i loads per_lane words of the table (2^bits words), eight at a time
+// (their addresses computed before any is loaded), and writes the sum of
+// what it loaded to out[i]: words scatter(i * per_lane + j) (runs = 0), or
+// the run of consecutive words from scatter(i) on, wrapping (runs = 1).
+__global__ __launch_bounds__(256) void k_gather(const float* __restrict__ buf, int bits, float* __restrict__ out,
+                                                int64_t n_lanes, int per_lane, int runs)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_lanes) return;
+    float acc = 0.0f;
+    const uint32_t base = (uint32_t)(i * per_lane);
+    const uint32_t start = scatter((uint32_t)i, bits), mask = (1u << bits) - 1u;
+    for (int j = 0; j < per_lane; j += 8) {
+        uint32_t a[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++)
+            a[u] = runs ? (start + (uint32_t)(j + u)) & mask : scatter(base + (uint32_t)(j + u), bits);
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) v[u] = buf[a[u]];
+#pragma unroll
+        for (int u = 0; u < 8; u++) acc += v[u];
+    }
+    out[i] = acc;
 }
 
 thread_local char g_err[256];
@@ -142,4 +172,23 @@ int mem_calib_atomic(void* buf, int32_t dtype, int32_t pattern, int64_t n_ops, i
     return 0;
 }
 
+int mem_calib_gather(const float* buf, int64_t n_words, float* out, int64_t n_lanes, int32_t per_lane, int32_t runs,
+                     void* stream)
+{
+    if (runs != 0 && runs != 1) return calib_fail(-1, "runs must be 0 or 1");
+    if (!buf || !out) return calib_fail(-1, "NULL buffer");
+    if (n_words < 1 || n_words > (1ll << 30) || (n_words & (n_words - 1)) != 0)
+        return calib_fail(-1, "n_words must be a power of two up to 2^30");
+    if (n_lanes < 0 || n_lanes > 0x7fffffffll * 256) return calib_fail(-1, "n_lanes out of range");
+    if (per_lane < 8 || per_lane % 8 != 0 || per_lane > (1 << 20))
+        return calib_fail(-1, "per_lane must be a positive multiple of 8 up to 2^20");
+    int bits = 0;
+    while ((1ll << bits) < n_words) bits++;
+    if (n_lanes == 0) return 0;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)((n_lanes + 255) / 256)), dim3(256), 0, (hipStream_t)stream, buf, bits,
+                       out, n_lanes, per_lane, runs);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return calib_fail(-3, hipGetErrorString(e));
+    return 0;
+}
 }  // extern "C"

@@ -126,6 +126,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     L.mem_calib_copy.restype = C.c_int
     L.mem_calib_atomic.argtypes = [P, I32, I32, I64, I64, P]
     L.mem_calib_atomic.restype = C.c_int
+    L.mem_calib_gather.argtypes = [P, I64, P, I64, I32, I32, P]
+    L.mem_calib_gather.restype = C.c_int
     L.mem_calib_last_error.argtypes = []
     L.mem_calib_last_error.restype = C.c_char_p
     _lib = L
@@ -133,7 +135,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
 
 
 # Calibration kernels of include/mem_calib.h (the measured peaks).
-CALIB_SYMBOLS = ("mem_calib_copy", "mem_calib_atomic", "mem_calib_last_error")
+CALIB_SYMBOLS = ("mem_calib_copy", "mem_calib_atomic", "mem_calib_gather", "mem_calib_last_error")
 MEM_CALIB_I32, MEM_CALIB_F32 = 0, 1
 MEM_CALIB_UNIQUE, MEM_CALIB_SCATTER, MEM_CALIB_SHARED = 0, 1, 2
 
@@ -154,6 +156,17 @@ def calib_atomic(buf: torch.Tensor, pattern: int, n_ops: int, n_addr: int | None
     if n_addr > buf.numel():
         raise ValueError("n_addr exceeds the buffer")
     if load().mem_calib_atomic(_dev_ptr(buf, "buf"), dt, pattern, n_ops, n_addr, _stream(stream)) != 0:
+        raise MemError(MEM_E_ARG, load().mem_calib_last_error().decode())
+
+
+def calib_gather(buf: torch.Tensor, out: torch.Tensor, per_lane: int, runs: bool = False, stream=None):
+    """mem_calib_gather: out.numel() lanes of per_lane loads from buf
+    (float32, a power-of-two number of words), scattered or in per-lane runs
+    of consecutive words; out receives each lane's sum."""
+    if buf.dtype != torch.float32 or out.dtype != torch.float32:
+        raise ValueError("buf and out must be float32")
+    if load().mem_calib_gather(_dev_ptr(buf, "buf"), buf.numel(), _dev_ptr(out, "out"), out.numel(), per_lane,
+                               1 if runs else 0, _stream(stream)) != 0:
         raise MemError(MEM_E_ARG, load().mem_calib_last_error().decode())
 
 

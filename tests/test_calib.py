@@ -40,3 +40,32 @@ def test_atomic_patterns_add_once_per_operation(dtype):
     mem.calib_atomic(buf, mem.MEM_CALIB_SHARED, 64 * 4096, 64)
     torch.cuda.synchronize()
     assert (buf[:64] == 4096).all() and not buf[64:].any()
+
+
+def test_gather_loads_every_word_of_its_range_once():
+    """With n_lanes x per_lane = n_words the loads visit every word once (the
+    scatter bijection); with a table of ones every lane sums per_lane."""
+    bits = 16
+    n = 1 << bits
+    tab = (torch.arange(n, device="cuda") % 7).float()
+    out = torch.full((n // 64,), -1.0, device="cuda")
+    mem.calib_gather(tab, out, 64)
+    torch.cuda.synchronize()
+    assert float(out.double().sum().item()) == float((torch.arange(n) % 7).sum().item())
+    ones = torch.ones(1 << 18, device="cuda")
+    out = torch.zeros(3000, device="cuda")
+    mem.calib_gather(ones, out, 40)
+    torch.cuda.synchronize()
+    assert (out == 40).all()
+    out.zero_()
+    mem.calib_gather(ones, out, 40, runs=True)
+    torch.cuda.synchronize()
+    assert (out == 40).all()
+    out = torch.full((n // 64,), -1.0, device="cuda")
+    mem.calib_gather(tab, out, 64, runs=True)  # runs wrap around the table
+    torch.cuda.synchronize()
+    assert (out >= 0).all()
+    with pytest.raises(mem.MemError):
+        mem.calib_gather(ones[:1000], out, 40)  # not a power of two
+    with pytest.raises(mem.MemError):
+        mem.calib_gather(ones, out, 12)  # not a multiple of 8
