@@ -35,6 +35,7 @@ struct BLayer {
     void* val = nullptr;
     float* var = nullptr;
     float* scale = nullptr;
+    bool rcp = false;  // the scales allow the reciprocal divide
     LayerDev dev(int64_t off = 0) const
     {
         LayerDev d;
@@ -42,7 +43,7 @@ struct BLayer {
         d.val = (char*)val + off * C * esz;
         d.var = var ? var + off : nullptr;
         d.scale = scale;
-        d.rscale = scale_block_rd(scale, C);
+        d.rscale = rcp ? scale_block_rcp(scale, C) : nullptr;
         d.C = C;
         d.rule = rule;
         d.storage = storage;
@@ -588,7 +589,7 @@ mem_status mem_batch_create(const mem_batch_params* p, void* stream, mem_batch**
         std::vector<float> sc(d.channels, 1.0f / 448.0f);
         if (d.ch_scale)
             for (int q = 0; q < d.channels; q++) sc[q] = d.ch_scale[q] / 448.0f;
-        const std::vector<float> blk = scale_block_host(sc);
+        const std::vector<float> blk = scale_block_host(sc, &b->layers[l].rcp);
         if (hipMalloc((void**)&b->layers[l].scale, sizeof(float) * blk.size()) != hipSuccess ||
             hipMemcpy(b->layers[l].scale, blk.data(), sizeof(float) * blk.size(), hipMemcpyHostToDevice) != hipSuccess) {
             free_batch(b);

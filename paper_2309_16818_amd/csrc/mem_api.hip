@@ -56,13 +56,14 @@ struct Layer {
     void* val = nullptr;
     float* var = nullptr;
     float* scale = nullptr;
+    bool rcp = false;  // the scales allow the reciprocal divide
     LayerDev dev() const
     {
         LayerDev d;
         d.val = val;
         d.var = var;
         d.scale = scale;
-        d.rscale = scale_block_rd(scale, C);
+        d.rscale = rcp ? scale_block_rcp(scale, C) : nullptr;
         d.C = C;
         d.rule = rule;
         d.storage = storage;
@@ -432,7 +433,7 @@ mem_status mem_create(const mem_params* p, void* stream, mem_map** out)
         std::vector<float> sc(d.channels, 1.0f / 448.0f);
         if (d.ch_scale)
             for (int q = 0; q < d.channels; q++) sc[q] = d.ch_scale[q] / 448.0f;
-        const std::vector<float> blk = scale_block_host(sc);
+        const std::vector<float> blk = scale_block_host(sc, &M.rcp);
         hipError_t e = hipMemcpy(M.scale, blk.data(), sizeof(float) * blk.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             free_map(m);

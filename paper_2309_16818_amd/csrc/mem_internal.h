@@ -78,17 +78,24 @@ struct Pose {
 
 // One user layer as the kernels see it.
 // A layer's FP8 scales in one device block: C binary32 scales, then, from
-// a 16-byte aligned offset, their reciprocals rounded to binary64.
-inline size_t scale_block_floats(int C) { return (size_t)((C + 3) & ~3) + 2 * (size_t)C; }
-inline double* scale_block_rd(float* scale, int C) { return scale ? (double*)(scale + ((C + 3) & ~3)) : nullptr; }
-inline std::vector<float> scale_block_host(const std::vector<float>& sc)
+// a 16-byte aligned offset, their reciprocals rounded to binary32.
+inline size_t scale_block_floats(int C) { return 2 * (size_t)((C + 3) & ~3); }
+inline float* scale_block_rcp(float* scale, int C) { return scale ? scale + ((C + 3) & ~3) : nullptr; }
+// Scales for which the vector gather divides through the reciprocal
+// (div_rcp): over this range the corrected product gives the E4M3 code of
+// the correctly rounded quotient.  A layer with a scale outside it leaves
+// the reciprocals unused and takes the one-channel gather, which divides.
+inline bool scale_rcp_ok(float s) { return s >= 0x1p-60f && s <= 0x1p60f; }
+// The block of scales sc; *rcp_ok tells whether every scale is in range.
+inline std::vector<float> scale_block_host(const std::vector<float>& sc, bool* rcp_ok)
 {
     const int C = (int)sc.size();
     std::vector<float> blk(scale_block_floats(C), 0.0f);
+    *rcp_ok = true;
     for (int q = 0; q < C; q++) {
         blk[q] = sc[q];
-        const double rd = 1.0 / (double)sc[q];
-        memcpy(&blk[((C + 3) & ~3) + 2 * q], &rd, sizeof rd);
+        blk[((C + 3) & ~3) + q] = (float)(1.0 / (double)sc[q]);  // correctly rounded: 53 >= 2 * 24 + 2
+        *rcp_ok = *rcp_ok && scale_rcp_ok(sc[q]);
     }
     return blk;
 }
@@ -97,7 +104,7 @@ struct LayerDev {
     void* val;
     float* var;
     float* scale;   // FP8: per-channel amax/448 (device)
-    double* rscale; // FP8: 1 / scale rounded to binary64 (device)
+    float* rscale;  // FP8: 1 / scale rounded to binary32 (device), or null (scale_rcp_ok)
     int C, rule, storage;
     float param;
 };

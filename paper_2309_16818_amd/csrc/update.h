@@ -670,27 +670,27 @@ __device__ __forceinline__ uint32_t word_elem(const uint32_t (&w)[NW], int k)
     return (w[k / per] >> (8 * B * (k % per))) & ((1u << (8 * B)) - 1u);
 }
 
-// The FP8 scales of the V channels from q and their binary64 reciprocals;
+// The FP8 scales of the V channels from q and their binary32 reciprocals;
 // 1 for other storage types.
 template <int S, int V>
 struct ChanScales {
     float sc[V];
-    double rd[V];
+    float rc[V];
     __device__ __forceinline__ void load(const LayerDev& L, int q)
     {
 #pragma unroll
         for (int k = 0; k < V; k++) {
             sc[k] = 1.0f;
-            rd[k] = 1.0;
+            rc[k] = 1.0f;
         }
         if constexpr (S == MEM_FP8_E4M3) {
-            uint32_t ws[V], wd[2 * V];
+            uint32_t ws[V], wr[V];
             load_words(L.scale + q, ws);
-            load_words(L.rscale + q, wd);
+            load_words(L.rscale + q, wr);
 #pragma unroll
             for (int k = 0; k < V; k++) {
                 sc[k] = __uint_as_float(ws[k]);
-                rd[k] = __hiloint2double((int)wd[2 * k + 1], (int)wd[2 * k]);
+                rc[k] = __uint_as_float(wr[k]);
             }
         }
     }
@@ -742,10 +742,11 @@ __device__ __forceinline__ void gather_pair_vec_rule(int2 pr, const void* __rest
             if constexpr (S == MEM_F32) out[i] = __float_as_uint(nv[i]);
             else if constexpr (S == MEM_BF16)
                 out[i] = (uint32_t)f32_to_bf16(nv[2 * i]) | ((uint32_t)f32_to_bf16(nv[2 * i + 1]) << 16);
-            else  // v / sc[k] through the binary64 reciprocal: the correctly rounded quotient
-                out[i] = f32x4_to_e4m3(div_rd(nv[4 * i], cs.rd[4 * i]), div_rd(nv[4 * i + 1], cs.rd[4 * i + 1]),
-                                       div_rd(nv[4 * i + 2], cs.rd[4 * i + 2]),
-                                       div_rd(nv[4 * i + 3], cs.rd[4 * i + 3]));
+            else  // v / sc[k] through the reciprocal, corrected: the correctly rounded quotient
+                out[i] = f32x4_to_e4m3(div_rcp(nv[4 * i], cs.sc[4 * i], cs.rc[4 * i]),
+                                       div_rcp(nv[4 * i + 1], cs.sc[4 * i + 1], cs.rc[4 * i + 1]),
+                                       div_rcp(nv[4 * i + 2], cs.sc[4 * i + 2], cs.rc[4 * i + 2]),
+                                       div_rcp(nv[4 * i + 3], cs.sc[4 * i + 3], cs.rc[4 * i + 3]));
         }
         store_words(row_p, out);
     }

@@ -119,6 +119,29 @@ def test_vector_gather_writes_the_one_channel_bits(storage, C):
     channel (20 channels in BF16 / FP8, 200 in FP8)."""
     rng = np.random.default_rng(40 + C + 7 * storage)
     scales = list(rng.uniform(0.2, 3.0, C).astype(np.float32)) if storage == mem.MEM_FP8_E4M3 else None
+    _gather_bits_equal(rng, storage, C, scales, 3.0)
+
+
+@pytest.mark.parametrize("C", [64, 384])
+@pytest.mark.parametrize("spread", ["wide", "outside"])
+def test_fp8_vector_gather_bits_on_scales_of_every_range(C, spread):
+    """The vector gather divides by an FP8 scale through its binary32
+    reciprocal and one correction step, which gives the correctly rounded
+    quotient for scales from 2^-60 to 2^60; the one-channel gather divides.
+    Scales whose exponents spread over 2^-55 .. 2^55 (quotients that flush
+    to zero, saturate, and everything between) give the same bits on both;
+    so does a layer with one scale outside the range ("outside": 2^-70),
+    which takes the one-channel gather."""
+    rng = np.random.default_rng(70 + C + (spread == "outside"))
+    amax = 448.0 * np.exp2(rng.uniform(-55, 55, C)) * rng.uniform(1.0, 2.0, C)
+    if spread == "outside":
+        amax[C // 2] = 448.0 * 2.0 ** -70
+    _gather_bits_equal(rng, mem.MEM_FP8_E4M3, C, list(amax.astype(np.float32)), 3.0)
+
+
+def _gather_bits_equal(rng, storage, C, scales, gain):
+    """Two maps fed the same four images, one forced to one channel per lane,
+    hold the same bits in both layers and views."""
     maps = []
     for width in (0, 1):
         m = mem.Map(mem.MapParams(48, 48, 0.05, layers=[mem.Layer(C, mem.MEM_GAUSS, 1.0, storage, scales),
@@ -134,7 +157,7 @@ def test_vector_gather_writes_the_one_channel_bits(storage, C):
         if it % 2:
             img = torch.tensor(rng.integers(0, 256, (72, 96, 2 * C)), dtype=torch.uint8, device="cuda")
         else:
-            img = to_dev(synth.feature_image(rng, 72, 96, 2 * C) * 3.0)
+            img = to_dev(synth.feature_image(rng, 72, 96, 2 * C) * gain)
         R = synth.camera_rotation(rng.uniform(0, 2 * np.pi), math.radians(40)).astype(np.float32)
         T = np.zeros((3, 4), np.float32)
         T[:, :3] = R
