@@ -589,8 +589,7 @@ void launch_batch_step(hipStream_t s, const BatchDev& d, const BatchLaunch& bl, 
         const int V = ib[b].topk ? 1
                                  : gather_vec_width(Lb.storage, Lb.C, img_dtype, images, (int64_t)cam_w * cam_c,
                                                     cam_c, 1, ib[b].ch_first, Lb);
-        int lpp_log2 = 0;
-        while (ib[b].topk == 0 && (1 << lpp_log2) * V < Lb.C && lpp_log2 < 6) lpp_log2++;
+        const int lpp_log2 = gather_lanes_log2(Lb.C, V, ib[b].topk != 0);
         // one gather pass per binding, each with its own queue (4 + b)
 #define MEM_BG(IMG, S, VV)                                                                            \
     hipLaunchKernelGGL((k_b_gather<IMG, S, VV>), dim3(bl.grid), dim3(kBatchWG), 0, s, d, 4 + b, images, \

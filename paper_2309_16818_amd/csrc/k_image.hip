@@ -322,8 +322,7 @@ GatherJob gather_job(const int4* vlist, const int* vcode, const int* count, int 
     J.topk = topk;
     const int V = topk || one_channel ? 1 : gather_vec_width(L.storage, L.C, img_dtype, img, s0, s1, s2, ch_first, L);
     J.kind = kind_of(img_dtype, L.storage, V > 1);
-    int lpp_log2 = 0;
-    while (topk == 0 && (1 << lpp_log2) * V < L.C && lpp_log2 < 6) lpp_log2++;
+    const int lpp_log2 = gather_lanes_log2(L.C, V, topk != 0);
     J.lpp_log2 = lpp_log2;
     const int ppw = 64 >> lpp_log2;
     const int64_t waves = ((int64_t)max_pairs + ppw - 1) / ppw;

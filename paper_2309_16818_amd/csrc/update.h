@@ -791,6 +791,26 @@ inline int gather_vec_width(int storage, int C, int img_dtype, const void* img, 
     return ok ? V : 1;
 }
 
+// log2 of the lanes that share one (cell, image) pair: enough for the
+// pair's groups of V channels in one pass (at most 64 lanes), or 32 or 16
+// lanes over several passes where that leaves fewer lanes idle (ties keep
+// the wider group, with fewer passes).  384 channels in groups of 8 take 16
+// lanes over three passes rather than 64 lanes with 16 idle.  Which lane
+// takes an element does not change its arithmetic.  Top-k inputs take one
+// lane per pair.
+inline int gather_lanes_log2(int C, int V, bool topk)
+{
+    if (topk) return 0;
+    const int G = (C + V - 1) / V;
+    auto slots = [G](int lg) { return ((G + (1 << lg) - 1) >> lg) << lg; };
+    int l = 0;
+    while ((1 << l) < G && l < 6) l++;
+    int best = l;
+    for (int lg = l - 1; lg >= 4; lg--)
+        if (slots(lg) < slots(best)) best = lg;
+    return best;
+}
+
 // An empty cell: no height, never observed layers, Dirichlet alpha_0.
 __device__ __forceinline__ void reset_cell(int st, float* __restrict__ h, float* __restrict__ v,
                                            int* __restrict__ cnt, int* __restrict__ clr,
