@@ -56,13 +56,13 @@ WALK_VALU_PER_CELL = {"clear_march": 13, "project": 57}
 # HBM traffic of kernels from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of the
 # full-rate workload, scaled by the same counters for the calibration copy
 # (a 1 GiB copy reads FETCH_SIZE 524304 KiB: factor 1.99994; writes
-# WRITE_SIZE 1048688 KiB: factor 0.99989; profiles/point_path_traffic.md),
+# WRITE_SIZE 1048678 KiB: factor 0.99990; profiles/point_path_traffic.md),
 # bytes per launch, valid while the kernel's sources hash to `sha`.
 TRAFFIC = {
-    "clear_march": {"bytes_per_launch": 4465948, "sha": "b95f8f5044066711"},  # k_ray_walk
-    "ingest": {"bytes_per_launch": 59298264, "sha": "b95f8f5044066711"},  # k_ingest_clouds: a frame's five clouds
-    "finalize": {"bytes_per_launch": 2228574, "sha": "b95f8f5044066711"},
-    "gather_fuse": {"bytes_per_launch": 13917281, "sha": "b91d26f726381108"},  # k_gather_multi: a pose's three images
+    "clear_march": {"bytes_per_launch": 4465640, "sha": "36bfd6464aacc4c9"},  # k_ray_walk
+    "ingest": {"bytes_per_launch": 59297722, "sha": "36bfd6464aacc4c9"},  # k_ingest_clouds: a frame's five clouds
+    "finalize": {"bytes_per_launch": 2228579, "sha": "36bfd6464aacc4c9"},
+    "gather_fuse": {"bytes_per_launch": 13916372, "sha": "349adda5ba2f2b5e"},  # k_gather_multi: a pose's three images
 }
 
 
